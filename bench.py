@@ -1,0 +1,172 @@
+"""Benchmark of the R-MJP expansion on one MI355X.
+
+One step = one full solve rho(0) exp(A t) of the large two-species workload:
+a 1000 x 1000 grid (N = 10^6 states, 4,995,001 generator entries), rates
+(k1, g1, k2, g2) = (200, 1, 0.5, 0.5), rho(0) at (0, 0), t = 1, L1 truncation
+budget 1e-9 (K and L from the Poisson tails), FP32 products with FP64 weights.
+The operator and rho(0) are resident in HBM before timing starts.
+
+Prints ONE JSON line (rank 0, N = 1):
+  value      solves/s of the timed variant (default: CSR operator)
+  roofline   algorithmic bytes of one solve / solve time (HIP events on the
+             library's stream), against the 8 TB/s HBM3E peak
+  cpu_baseline  the FP64 oracle on the host on the same workload
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "expv solves/s & HBM GB/s at L1≤1e-6 vs FP64; DA-MCMC ESS/s vs plain"
+HBM_PEAK_GBS = 8000.0
+THETA = [200.0, 1.0, 0.5, 0.5]
+S1 = S2 = 1000
+T_SOLVE = 1.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(kind: str, n: int, nnz: int, K: int, L: int) -> float:
+    """Bytes one solve must move: per jump the operator and the vector once
+    (CSR: values 4 B + column 4 B per entry, row pointer 4 B, x in 4 B,
+    y out 4 B per row; stencil: x in + y out), plus the Kahan pair read and
+    written on each accumulated jump (16 B per row)."""
+    per_jump = (8 * nnz + 12 * n) if kind == "csr" else 8 * n
+    return K * per_jump + (K - L + 1) * 16 * n
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--kind", choices=["csr", "stencil"], default="csr")
+    ap.add_argument("--variant", type=int, default=0, help="0 auto, 1 stepwise, 2 persistent")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--no-extra", action="store_true", help="skip the secondary measurements")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    from paper_2312_05647_amd import mjp
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n = S1 * S2
+    model = mjp.make_model(mjp.MJP_MODEL_CASCADE2, THETA, [S1, S2])
+    opts = mjp.mjp_opts_default(variant=args.variant)
+    rp, ci, va = mjp.mjp_model_csr(model)
+    nnz = len(ci)
+
+    def make_plan(kind):
+        return mjp.mjp_plan_create_csr(rp, ci, va, opts) if kind == "csr" else mjp.mjp_plan_create_stencil(model, opts)
+
+    rho0 = torch.zeros(n, dtype=torch.float32, device=dev)
+    rho0[0] = 1.0
+    out = torch.empty((1, n), dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def time_solves(plan, steps, warmup):
+        info = mjp.mjp_expv(plan, rho0, [T_SOLVE], out, info=True)[0]   # also a warm-up
+        for _ in range(warmup):
+            mjp.mjp_expv(plan, rho0, [T_SOLVE], out, stream=stream)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        for _ in range(steps):
+            mjp.mjp_expv(plan, rho0, [T_SOLVE], out, stream=stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return info, ev0.elapsed_time(ev1) / 1e3 / steps, wall
+
+    log(f"[bench] plan {args.kind} N={n} nnz={nnz}")
+    plan = make_plan(args.kind)
+    info, dev_s, wall = time_solves(plan, args.steps, args.warmup)
+    got = out[0].double().cpu().numpy()
+    mjp.mjp_plan_destroy(plan)
+    K, L = info["K"], info["L"]
+    ab = algorithmic_bytes(args.kind, n, nnz, K, L)
+    achieved = ab / dev_s / 1e9
+    log(f"[bench] {args.kind}: {dev_s * 1e3:.3f} ms/solve (device events), wall {wall / args.steps * 1e3:.3f} ms, "
+        f"K={K} L={L}, {achieved:.0f} GB/s algorithmic")
+
+    result = {
+        "metric": METRIC,
+        "value": 1.0 / (wall / args.steps),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"two-species cascade {S1}x{S2} (N=1e6, nnz={nnz}), rates {THETA}, rho0=delta(0,0), "
+                               f"t={T_SOLVE}, tol=1e-9, {args.kind.upper()} FP32 operator",
+                   "operator": args.kind, "variant": args.variant, "K": K, "L": L,
+                   "omega": info["omega"], "global_batch": 1, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "one solve (all K jumps, weighted accumulation, lumping)",
+                     "algorithmic_bytes_per_solve": ab, "ms_per_solve_device": dev_s * 1e3},
+    }
+
+    if not args.no_extra:
+        other = "stencil" if args.kind == "csr" else "csr"
+        plan = make_plan(other)
+        info2, dev2, wall2 = time_solves(plan, max(3, args.steps // 2), 1)
+        mjp.mjp_plan_destroy(plan)
+        ab2 = algorithmic_bytes(other, n, nnz, info2["K"], info2["L"])
+        result[f"{other}_variant"] = {"solves_per_s": 1.0 / (wall2 / max(3, args.steps // 2)),
+                                      "ms_per_solve_device": dev2 * 1e3,
+                                      "algorithmic_GBps": ab2 / dev2 / 1e9}
+        log(f"[bench] {other}: {dev2 * 1e3:.3f} ms/solve")
+
+    if not args.no_cpu:
+        import oracle
+        oracle.build(force=False)
+        A = oracle.model_generator(1, THETA, [S1, S2])
+        r0 = np.zeros(n)
+        r0[0] = 1.0
+        eps_r = opts.tol / 4
+        log(f"[bench] oracle on {oracle.num_threads()} threads")
+        t0 = time.perf_counter()
+        solves = 0
+        ref = None
+        while True:
+            ref, oinfo = oracle.expv(A, r0, T_SOLVE, eps_right=eps_r)
+            solves += 1
+            if time.perf_counter() - t0 > 10.0 or solves >= 3:
+                break
+        cpu_s = (time.perf_counter() - t0) / solves
+        result["cpu_baseline"] = {"value": 1.0 / cpu_s, "unit": "solves/s", "cores": oracle.num_threads(),
+                                  "kind": "oracle",
+                                  "sample": f"{solves} full FP64 solve(s) of the same workload (K={oinfo['K']}, "
+                                            f"right tail {eps_r:g}), OpenMP over rows"}
+        l1 = float(np.abs(got - ref).sum())
+        result["parity"] = {"l1_vs_fp64_oracle": l1, "linf": float(np.abs(got - ref).max()), "bar": 1e-6}
+        log(f"[bench] oracle {cpu_s:.2f} s/solve; GPU L1 vs oracle {l1:.3e}")
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

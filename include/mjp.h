@@ -1,0 +1,292 @@
+/*
+ * mjp.h -- C ABI of libmjp: the R-MJP (restricted Markov-jump-process)
+ * expansion of rho(0) exp(A_theta t) on one MI355X (gfx950).
+ *
+ * Method (Pessoa, Schweiger, Presse, "Avoiding matrix exponentials for large
+ * transition rate matrices", arXiv 2312.05647):
+ *   A_theta   generator (Eq. A_def): a_nm = rate n->m (n != m),
+ *             a_nn = -(total rate out of n); row = from-state.
+ *   Omega     omega_factor * max_n |a_nn|, omega_factor > 1 (Eq. B_def; the
+ *             paper uses 1.1).
+ *   B         I + A/Omega, a stochastic matrix (Eq. B_def).
+ *   rho(t)    = sum_k rho(0) B^k Poisson(k | Omega t)   (Eq. ME_uniform),
+ *             truncated after K products, the dropped weight placed on
+ *             rho(0) B^K (Algorithm 2; Sec. 2.2.3, Eq. R-MJP_expansion).
+ *   loglik    sum_i log rho(T^i)_{s^i} over snapshot observations
+ *             (Sec. 2.1.2).
+ * The surrogate entry points (an MLP over log-parameters trained on exact
+ * log-likelihoods, used for delayed-acceptance sampling) are an addition to
+ * the paper's method; they are documented where declared.
+ *
+ * Conventions for every entry point:
+ *   - Every function returns mjp_status; nothing throws across the ABI.
+ *     On failure mjp_last_error() returns a thread-local message.
+ *   - Arguments named *_d are device pointers (memory on the GPU that was
+ *     current when the plan or surrogate was created); *_h are host pointers.
+ *     All buffers are owned by the caller unless stated otherwise.
+ *   - All argument checks run on the host before any GPU work is enqueued, so
+ *     an invalid call never launches a kernel.
+ *   - Calls are asynchronous on the given stream (a hipStream_t passed as
+ *     mjp_stream_t; NULL = the null stream) unless an info_h pointer is
+ *     given, which makes the call wait for its own work to finish.
+ *   - A plan or surrogate must not be used by two streams at the same time.
+ *     Handles are opaque and freed by their *_destroy function.
+ *   - Scratch memory (ping-pong vectors, compensation terms, weight tables)
+ *     is owned by the plan and grows on demand with hipMalloc.
+ */
+#ifndef MJP_H
+#define MJP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* A hipStream_t. */
+typedef void* mjp_stream_t;
+
+typedef enum {
+    MJP_OK = 0,
+    MJP_E_INVALID_ARG = 1,    /* null pointer, size <= 0, t < 0 or not finite, bad option, ... */
+    MJP_E_NOT_GENERATOR = 2,  /* negative off-diagonal rate, or a row sum that breaks the truncation rule */
+    MJP_E_K_LIMIT = 3,        /* the jump count K needed for (t, tol) exceeds opts.k_cap */
+    MJP_E_WORKSPACE = 4,      /* a size exceeds what the chosen kernel supports */
+    MJP_E_DEVICE = 5,         /* a HIP runtime call failed (no GPU, out of memory, launch error) */
+    MJP_E_NUMERIC = 6,        /* (synchronous calls only) NaN/Inf or a negative entry was detected */
+    MJP_E_UNSUPPORTED = 7     /* a valid request this build does not implement */
+} mjp_status;
+
+/* ---------------------------------------------------------------- options */
+
+enum { MJP_K_TOL = 0,      /* K, L from the Poisson tails: eps_right = eps_left = tol/4 */
+       MJP_K_PAPER = 1 };  /* K = floor(W + 6 sqrt W) + 1, L = 0: the loop bound of
+                              Algorithm 2 (while k <= W + 6 sqrt W, increment first) */
+
+enum { MJP_CONSERVATIVE = 0, /* transitions that would leave the state space are dropped,
+                                so rows of A sum to 0 and rows of B to 1 (Eq. B_def) */
+       MJP_LEAKY = 1 };      /* the exit rate still counts them (the m_theta of the
+                                birth-death example, Sec. 3.1.1); mass leaks */
+
+enum { MJP_VARIANT_AUTO = 0,       /* the plan picks the launch strategy */
+       MJP_VARIANT_STEPWISE = 1,   /* one kernel per jump, launched in a loop */
+       MJP_VARIANT_PERSISTENT = 2  /* all K jumps in one cooperative launch */ };
+
+typedef struct {
+    double  omega_factor;  /* Omega = omega_factor * max|a_nn|; must be > 1 (Eq. B_def: 1.1) */
+    double  tol;           /* L1 truncation budget of the series, 0 < tol < 1.  With lumping the
+                              L1 distance to rho(0)exp(At) from truncation is at most
+                              2 (eps_left + eps_right) = tol. */
+    int32_t k_rule;        /* MJP_K_TOL | MJP_K_PAPER */
+    int32_t truncation;    /* MJP_CONSERVATIVE | MJP_LEAKY */
+    int32_t renorm_every;  /* 0 = off; m > 0: every m jumps rescale rho to the initial mass
+                              (valid only for conservative truncation; rejected otherwise) */
+    int32_t lump;          /* 1 = add (1 - sum_{L..K} w_k) rho(0)B^K (last line of Algorithm 2) */
+    int64_t k_cap;         /* largest K accepted; larger -> MJP_E_K_LIMIT */
+    int32_t variant;       /* MJP_VARIANT_* */
+    int32_t reserved[7];   /* must be zero */
+} mjp_opts;
+
+/* Fill *o with the defaults: omega_factor 1.1, tol 1e-9, MJP_K_TOL,
+ * MJP_CONSERVATIVE, renorm_every 32, lump 1, k_cap 10^7, MJP_VARIANT_AUTO. */
+void mjp_opts_default(mjp_opts* o);
+
+/* ----------------------------------------------------------- result info */
+
+enum { MJP_FLAG_NAN = 1,           /* a NaN/Inf appeared in rho(0) or in the iterate */
+       MJP_FLAG_NEG = 2,           /* rho(0) had a negative entry */
+       MJP_FLAG_UNDERFLOW_OBS = 4, /* an observed state had probability <= 0 in FP32 */
+       MJP_FLAG_OUT_OF_GRID = 8,   /* an observation lies outside the state space */
+       MJP_FLAG_K_LIMIT = 16 };    /* (log-likelihood) an item needed K > k_cap; its value is -inf */
+
+typedef struct {
+    double  omega;          /* Omega */
+    double  W;              /* Omega * t */
+    double  eps_left;       /* sum_{k<L} w_k (FP64) */
+    double  eps_right;      /* sum_{k>K} w_k (FP64) */
+    double  residual;       /* 1 - sum_{k=L..K} w_k, lumped onto rho(0)B^K when opts.lump */
+    double  mass_in;        /* sum of rho(0) (FP64 sum on the GPU) */
+    double  mass_out;       /* sum of the result (FP64 sum on the GPU) */
+    int32_t K;              /* number of products rho <- rho B */
+    int32_t L;              /* first accumulated jump index */
+    int32_t flags;          /* MJP_FLAG_* */
+    int32_t reserved;
+} mjp_info;
+
+/* ------------------------------------------------------------ operators */
+
+/* Generator A in CSR form, on the host, FP64.  Row = from-state.  Column
+ * indices strictly increasing within a row; the diagonal entry may be absent
+ * only in a row with no off-diagonal entries. */
+typedef struct {
+    int32_t        n;        /* number of states N >= 1 */
+    int32_t        nnz;      /* row_ptr[n] */
+    const int32_t* row_ptr;  /* [n+1], row_ptr[0] = 0, non-decreasing */
+    const int32_t* col_idx;  /* [nnz], 0 <= col < n */
+    const double*  val;      /* [nnz], a_nm */
+} mjp_csr;
+
+/* Built-in reaction networks whose generator is computed on the fly.
+ *   MJP_MODEL_BD: immigration-death (Eq. BD_def), theta = {beta, gamma},
+ *     dims = {N, 1}, state n = count; n -> n+1 at beta, n -> n-1 at gamma n.
+ *   MJP_MODEL_CASCADE2: two species on an S1 x S2 grid, theta = {k1, g1, k2, g2},
+ *     dims = {S1, S2}, state n = n1 + S1 n2 (first coordinate fastest, as the
+ *     paper linearises multi-index states, Sec. 3.1.2);
+ *     (n1,n2) -> (n1+1,n2) at k1, -> (n1-1,n2) at g1 n1, -> (n1,n2+1) at k2 n1,
+ *     -> (n1,n2-1) at g2 n2. */
+enum { MJP_MODEL_BD = 0, MJP_MODEL_CASCADE2 = 1 };
+
+typedef struct {
+    int32_t model;     /* MJP_MODEL_* */
+    int32_t dims[2];
+    double  theta[8];  /* rates, >= 0 and finite; unused entries ignored */
+} mjp_model;
+
+/* Number of states and stored entries of a model's generator under the given
+ * truncation (host only, no GPU needed). */
+mjp_status mjp_model_csr_size(const mjp_model* m, int32_t truncation, int32_t* n_h, int32_t* nnz_h);
+
+/* Write the model's generator (Eq. A_def) into caller-allocated host CSR
+ * arrays sized by mjp_model_csr_size (host only, no GPU needed).  Zero rates
+ * are not stored. */
+mjp_status mjp_model_csr(const mjp_model* m, int32_t truncation, int32_t* row_ptr_h,
+                         int32_t* col_idx_h, double* val_h);
+
+typedef struct mjp_plan mjp_plan;
+
+/* Build a plan from a generator in CSR (Eq. A_def): checks it is a generator
+ * (off-diagonals >= 0; row sums 0 within 1e-12 max|a_nn| under
+ * MJP_CONSERVATIVE, <= that under MJP_LEAKY), computes Omega (Eq. B_def),
+ * forms B^T in FP32 on the GPU in a sliced-ELL layout, and under
+ * MJP_CONSERVATIVE sets each diagonal b_nn to 1 minus the FP64 sum of that
+ * row's FP32 off-diagonals so every FP32 row of B sums to 1 to within one
+ * rounding.  Copies what it needs; the caller's arrays may be freed after. */
+mjp_status mjp_plan_create_csr(const mjp_csr* A, const mjp_opts* opts, mjp_plan** out);
+
+/* Build a plan for a built-in model: no matrix is stored, the kernels
+ * compute each entry of B from theta when they need it. */
+mjp_status mjp_plan_create_stencil(const mjp_model* m, const mjp_opts* opts, mjp_plan** out);
+
+/* Free a plan and its device memory.  NULL is accepted. */
+void mjp_plan_destroy(mjp_plan* p);
+
+/* Number of states of a plan (0 for NULL). */
+int32_t mjp_plan_n(const mjp_plan* p);
+
+/* ------------------------------------------------------------- solvers */
+
+/* rho(t_j) for n_t times in one sweep of jumps (Algorithm 2 per time, all
+ * times sharing the iterates rho(0)B^k).
+ *   rho0_d   [N] FP32 on the device, entries >= 0 (the map is linear, so any
+ *            total mass is allowed).
+ *   t_h      [n_t] times on the host, finite and >= 0, any order.
+ *   out_d    [n_t x N] FP32 on the device; row j is rho(t_h[j]).  Must not
+ *            overlap rho0_d.
+ *   info_h   [n_t] or NULL.  Non-NULL makes the call synchronous and returns
+ *            MJP_E_NUMERIC if a NaN/Inf or negative entry was detected.
+ * t = 0 and Omega = 0 (all rates zero) return rho0 unchanged.
+ * Precision: the products run in FP32; the weighted series is accumulated
+ * with Kahan compensation in FP32; the Poisson weights are FP64. */
+mjp_status mjp_expv(mjp_plan* p, const float* rho0_d, int32_t n_t, const double* t_h,
+                    float* out_d, mjp_info* info_h, mjp_stream_t stream);
+
+/* B independent solves, item b: plans[b], rho0_d[b], n_t[b] times t_h[b],
+ * outputs out_d[b] ([n_t[b] x N_b]).  info_h, if not NULL, holds
+ * sum_b n_t[b] entries in item order and makes the call synchronous.
+ * Plans may repeat (the same operator with several initial vectors). */
+mjp_status mjp_expv_batched(int32_t B, mjp_plan* const* plans, const float* const* rho0_d,
+                            const int32_t* n_t, const double* const* t_h, float* const* out_d,
+                            mjp_info* info_h, mjp_stream_t stream);
+
+/* Snapshot observations shared by every item of a log-likelihood batch
+ * (Sec. 2.1.2): each observation is one system observed at one collection
+ * time.  States are given as grid coordinates so items with different grid
+ * sizes can share them; for MJP_MODEL_BD x2 must be 0. */
+typedef struct {
+    int32_t        n_t;      /* number of collection times */
+    const double*  T_h;      /* [n_t] collection times, host, >= 0 */
+    int32_t        n_obs;    /* number of (time, state) records */
+    const int32_t* obs_h;    /* [n_obs x 4] host: (time index, x1, x2, count >= 1) */
+    int32_t        x0[2];    /* initial state: rho(0) is a point mass there */
+} mjp_obs;
+
+/* Log-likelihoods of B parameter draws of one built-in model:
+ *   loglik_d[b] = sum_i count_i log rho_b(T_{j_i})_{(x1_i, x2_i)}
+ * where rho_b solves the model with theta_d[b*4 .. b*4+3] on the grid
+ * dims_d[b*2], dims_d[b*2+1] (conservative truncation).  All items run in one
+ * persistent launch ordered longest-first; each item keeps its whole state
+ * vector in the LDS of one workgroup, so S1*S2 <= mjp_loglik_max_states().
+ * Only observed states are accumulated.  An observation outside an item's
+ * grid, or with FP32 probability 0, gives -inf for that item (and a flag).
+ *   theta_d  [B x 4] FP64 device (BD uses the first 2 of each 4)
+ *   dims_d   [B x 2] int32 device
+ *   loglik_d [B] FP64 device
+ *   info_d   [B] device or NULL (omega, W of the last time, K, L of the last
+ *            time, flags, mass_out = final mass of the iterate)
+ * Asynchronous; safe to capture in a hipGraph. */
+mjp_status mjp_loglik(int32_t model, int32_t B, const double* theta_d, const int32_t* dims_d,
+                      const mjp_obs* obs, const mjp_opts* opts, double* loglik_d,
+                      mjp_info* info_d, mjp_stream_t stream);
+
+/* Largest S1*S2 a log-likelihood item may have (LDS capacity of one CU). */
+int32_t mjp_loglik_max_states(void);
+
+/* ------------------------------------------------ surrogate (not in paper) */
+
+typedef struct mjp_surrogate mjp_surrogate;
+
+typedef struct {
+    int32_t in_dim;   /* inputs (standardised log-parameters), 1..16 */
+    int32_t width;    /* hidden width, multiple of 64, <= 512 */
+    int32_t depth;    /* number of hidden layers (Linear+GELU), 1..8 */
+} mjp_mlp_cfg;
+
+typedef struct {
+    int32_t epochs;
+    int32_t batch;        /* minibatch, multiple of 64 */
+    float   lr;           /* Adam step size */
+    float   beta1, beta2, eps_adam;
+    float   weight_decay; /* decoupled, 0 = off */
+    uint64_t seed;        /* minibatch shuffling */
+} mjp_train_cfg;
+
+/* Create an MLP in->width->...->width->1 with exact (erf) GELU between the
+ * Linear layers, FP32 master weights initialised from seed, BF16 copies used by
+ * the matrix-core kernels. */
+mjp_status mjp_surrogate_create(const mjp_mlp_cfg* cfg, uint64_t seed, mjp_surrogate** out);
+void       mjp_surrogate_destroy(mjp_surrogate* s);
+
+/* Mean-squared-error training with Adam on x_d [n x in_dim] FP32 and targets
+ * y_d [n] FP32 (device).  loss_h [epochs] receives the mean training loss of
+ * each epoch (the call is synchronous when loss_h is not NULL). */
+mjp_status mjp_surrogate_train(mjp_surrogate* s, const float* x_d, const float* y_d, int32_t n,
+                               const mjp_train_cfg* cfg, float* loss_h, mjp_stream_t stream);
+
+/* y_d[i] = MLP(x_d[i]) for n inputs (device FP32). */
+mjp_status mjp_surrogate_infer(const mjp_surrogate* s, const float* x_d, int32_t n, float* y_d,
+                               mjp_stream_t stream);
+
+/* Copy the FP32 master parameters to/from host memory: layer l weight
+ * [out x in] row-major then bias [out], layers in order.  Count = params_h
+ * size, checked against mjp_surrogate_num_params. */
+int64_t    mjp_surrogate_num_params(const mjp_surrogate* s);
+mjp_status mjp_surrogate_get_params(const mjp_surrogate* s, float* params_h, int64_t count);
+mjp_status mjp_surrogate_set_params(mjp_surrogate* s, const float* params_h, int64_t count);
+
+/* Save / load the configuration and FP32 master parameters (little-endian
+ * binary, magic "MJPS"). */
+mjp_status mjp_surrogate_save(const mjp_surrogate* s, const char* path);
+mjp_status mjp_surrogate_load(const char* path, mjp_surrogate** out);
+
+/* ---------------------------------------------------------------- misc */
+
+/* Message describing the last failure on this thread ("" if none). */
+const char* mjp_last_error(void);
+
+/* Library version string. */
+const char* mjp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MJP_H */

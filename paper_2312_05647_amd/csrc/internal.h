@@ -1,0 +1,98 @@
+// Internal declarations shared by the libmjp translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "mjp.h"
+
+namespace mjp {
+
+// ---------------------------------------------------------------- errors
+mjp_status fail(mjp_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+void clear_error();
+
+#define MJP_HIP(expr)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return ::mjp::fail(MJP_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+#define MJP_CHECK(cond, status, ...)                 \
+    do {                                             \
+        if (!(cond)) return ::mjp::fail(status, __VA_ARGS__); \
+    } while (0)
+
+// ------------------------------------------------------ device buffers
+// A growable device allocation owned by a plan (or surrogate).
+struct DevBuf {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    mjp_status reserve(size_t want);  // grows (never shrinks); contents not kept
+    void release();
+    template <class T> T* as() const { return static_cast<T*>(ptr); }
+};
+
+// --------------------------------------------------- Poisson window (FP64)
+// Jump window of one collection time: the series keeps k = L..K.
+struct Window {
+    double t = 0, W = 0;
+    double eps_left = 0, eps_right = 0, residual = 0;
+    int64_t K = 0, L = 0;
+};
+// Chooses K and L for W = Omega t under opts (tolerance rule or the paper's
+// loop bound); residual = eps_left + eps_right.
+Window poisson_window(double W, const mjp_opts& o);
+
+// ------------------------------------------------------------- plans
+enum PlanKind { PLAN_CSR = 0, PLAN_STENCIL = 1 };
+
+// FP32 coefficients of a built-in model's B = I + A/Omega, one per reaction
+// channel (the diagonal is formed from them in the kernels).
+struct StencilCoef {
+    float c[4];     // BD: {beta/O, gamma/O, 0, 0}; cascade2: {k1/O, g1/O, k2/O, g2/O}
+    int32_t S1, S2; // BD: {N, 1}
+    int32_t model;
+    int32_t leaky;
+};
+
+constexpr int kSlice = 64;  // rows per sliced-ELL slice (= one wavefront)
+
+}  // namespace mjp
+
+struct mjp_plan {
+    int kind = mjp::PLAN_CSR;
+    int device = 0;
+    int32_t n = 0;
+    mjp_opts opts{};
+    double m_theta = 0.0;  // max |a_nn|
+    double omega = 0.0;    // opts.omega_factor * m_theta
+
+    // CSR plans: B^T in sliced ELL (slice = 64 consecutive output rows,
+    // entry j of row r at slice_off[r/64] + 64*j + r%64).
+    int32_t n_slices = 0;
+    int64_t sell_entries = 0;
+    int64_t nnz = 0;
+    int32_t max_width = 0;
+    mjp::DevBuf slice_off;  // int32[n_slices+1]
+    mjp::DevBuf col;        // int32[sell_entries]
+    mjp::DevBuf val;        // float[sell_entries]
+
+    // stencil plans
+    mjp_model model{};
+    mjp::StencilCoef coef{};
+
+    // workspace
+    mjp::DevBuf rho[2];     // float[N] ping-pong iterate
+    mjp::DevBuf comp;       // float[n_t * N] Kahan compensation terms
+    mjp::DevBuf wtab;       // double weights, per time k = L..K
+    mjp::DevBuf tinfo;      // per-time device parameters
+    mjp::DevBuf partials;   // float per-block partial sums
+    mjp::DevBuf scal;       // device scalars (masses, scale, flags)
+    mjp::DevBuf sync;       // persistent-kernel barrier words
+    std::vector<char> host_stage;
+};

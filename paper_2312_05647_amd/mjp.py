@@ -1,0 +1,306 @@
+"""Thin ctypes binding of libmjp (include/mjp.h): argument marshalling only.
+
+Every function here has the name of the C entry point it calls.  Device
+buffers are passed as torch CUDA tensors (their data pointers); the current
+torch stream is used unless a stream is given.  Nothing in this module
+computes any part of the method: if libmjp.so is missing or fails to load,
+every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmjp.so")
+
+MJP_OK, MJP_E_INVALID_ARG, MJP_E_NOT_GENERATOR, MJP_E_K_LIMIT, MJP_E_WORKSPACE, MJP_E_DEVICE, \
+    MJP_E_NUMERIC, MJP_E_UNSUPPORTED = range(8)
+STATUS_NAMES = ["MJP_OK", "MJP_E_INVALID_ARG", "MJP_E_NOT_GENERATOR", "MJP_E_K_LIMIT", "MJP_E_WORKSPACE",
+                "MJP_E_DEVICE", "MJP_E_NUMERIC", "MJP_E_UNSUPPORTED"]
+MJP_K_TOL, MJP_K_PAPER = 0, 1
+MJP_CONSERVATIVE, MJP_LEAKY = 0, 1
+MJP_VARIANT_AUTO, MJP_VARIANT_STEPWISE, MJP_VARIANT_PERSISTENT = 0, 1, 2
+MJP_MODEL_BD, MJP_MODEL_CASCADE2 = 0, 1
+MJP_FLAG_NAN, MJP_FLAG_NEG, MJP_FLAG_UNDERFLOW_OBS, MJP_FLAG_OUT_OF_GRID, MJP_FLAG_K_LIMIT = 1, 2, 4, 8, 16
+
+
+class MjpError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        self.status = status
+        super().__init__(f"{STATUS_NAMES[status] if 0 <= status < 8 else status}: {msg}")
+
+
+class mjp_opts(ctypes.Structure):
+    _fields_ = [("omega_factor", ctypes.c_double), ("tol", ctypes.c_double), ("k_rule", ctypes.c_int32),
+                ("truncation", ctypes.c_int32), ("renorm_every", ctypes.c_int32), ("lump", ctypes.c_int32),
+                ("k_cap", ctypes.c_int64), ("variant", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+
+
+class mjp_info(ctypes.Structure):
+    _fields_ = [("omega", ctypes.c_double), ("W", ctypes.c_double), ("eps_left", ctypes.c_double),
+                ("eps_right", ctypes.c_double), ("residual", ctypes.c_double), ("mass_in", ctypes.c_double),
+                ("mass_out", ctypes.c_double), ("K", ctypes.c_int32), ("L", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+class mjp_csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int32), ("row_ptr", ctypes.c_void_p),
+                ("col_idx", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
+class mjp_model(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_int32), ("dims", ctypes.c_int32 * 2), ("theta", ctypes.c_double * 8)]
+
+
+class mjp_obs(ctypes.Structure):
+    _fields_ = [("n_t", ctypes.c_int32), ("T_h", ctypes.c_void_p), ("n_obs", ctypes.c_int32),
+                ("obs_h", ctypes.c_void_p), ("x0", ctypes.c_int32 * 2)]
+
+
+class mjp_mlp_cfg(ctypes.Structure):
+    _fields_ = [("in_dim", ctypes.c_int32), ("width", ctypes.c_int32), ("depth", ctypes.c_int32)]
+
+
+class mjp_train_cfg(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps_adam", ctypes.c_float),
+                ("weight_decay", ctypes.c_float), ("seed", ctypes.c_uint64)]
+
+
+_lib = None
+
+# (name, restype, argtypes) of every exported function
+_P = ctypes.c_void_p
+_SIGS = [
+    ("mjp_opts_default", None, [_P]),
+    ("mjp_model_csr_size", ctypes.c_int, [_P, ctypes.c_int32, _P, _P]),
+    ("mjp_model_csr", ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P]),
+    ("mjp_plan_create_csr", ctypes.c_int, [_P, _P, _P]),
+    ("mjp_plan_create_stencil", ctypes.c_int, [_P, _P, _P]),
+    ("mjp_plan_destroy", None, [_P]),
+    ("mjp_plan_n", ctypes.c_int32, [_P]),
+    ("mjp_expv", ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, _P, _P]),
+    ("mjp_expv_batched", ctypes.c_int, [ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P]),
+    ("mjp_loglik", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P]),
+    ("mjp_loglik_max_states", ctypes.c_int32, []),
+    ("mjp_surrogate_create", ctypes.c_int, [_P, ctypes.c_uint64, _P]),
+    ("mjp_surrogate_destroy", None, [_P]),
+    ("mjp_surrogate_train", ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P, _P, _P]),
+    ("mjp_surrogate_infer", ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P]),
+    ("mjp_surrogate_num_params", ctypes.c_int64, [_P]),
+    ("mjp_surrogate_get_params", ctypes.c_int, [_P, _P, ctypes.c_int64]),
+    ("mjp_surrogate_set_params", ctypes.c_int, [_P, _P, ctypes.c_int64]),
+    ("mjp_surrogate_save", ctypes.c_int, [_P, ctypes.c_char_p]),
+    ("mjp_surrogate_load", ctypes.c_int, [ctypes.c_char_p, _P]),
+    ("mjp_last_error", ctypes.c_char_p, []),
+    ("mjp_version", ctypes.c_char_p, []),
+]
+
+
+def lib():
+    """Load libmjp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2312_05647_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in _SIGS:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != MJP_OK:
+        raise MjpError(status, lib().mjp_last_error().decode())
+
+
+def _ptr(x) -> int:
+    """Data pointer of a torch tensor or numpy array (None -> NULL)."""
+    if x is None:
+        return None
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data
+    return x.data_ptr()
+
+
+def _stream(stream):
+    if stream is not None:
+        return stream if isinstance(stream, int) else stream.cuda_stream
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+# ---------------------------------------------------------------- options
+
+def mjp_opts_default(**over) -> mjp_opts:
+    o = mjp_opts()
+    lib().mjp_opts_default(ctypes.byref(o))
+    for k, v in over.items():
+        setattr(o, k, v)
+    return o
+
+
+def make_model(model: int, theta, dims) -> mjp_model:
+    m = mjp_model()
+    m.model = model
+    d = list(dims) + [1] * (2 - len(dims))
+    m.dims[0], m.dims[1] = int(d[0]), int(d[1])
+    for i, v in enumerate(theta):
+        m.theta[i] = float(v)
+    return m
+
+
+def mjp_model_csr(model: mjp_model, truncation: int = MJP_CONSERVATIVE):
+    """Host CSR (row_ptr int32, col int32, val float64) of a built-in model."""
+    n = ctypes.c_int32()
+    nnz = ctypes.c_int32()
+    _check(lib().mjp_model_csr_size(ctypes.byref(model), truncation, ctypes.byref(n), ctypes.byref(nnz)))
+    rp = np.zeros(n.value + 1, np.int32)
+    ci = np.zeros(nnz.value, np.int32)
+    va = np.zeros(nnz.value, np.float64)
+    _check(lib().mjp_model_csr(ctypes.byref(model), truncation, _ptr(rp), _ptr(ci), _ptr(va)))
+    return rp, ci, va
+
+
+# ---------------------------------------------------------------- plans
+
+def mjp_plan_create_csr(row_ptr, col, val, opts: mjp_opts | None = None) -> int:
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    val = np.ascontiguousarray(val, dtype=np.float64)
+    A = mjp_csr(len(row_ptr) - 1, len(col), _ptr(row_ptr), _ptr(col), _ptr(val))
+    opts = opts or mjp_opts_default()
+    h = ctypes.c_void_p()
+    _check(lib().mjp_plan_create_csr(ctypes.byref(A), ctypes.byref(opts), ctypes.byref(h)))
+    return h.value
+
+
+def mjp_plan_create_stencil(model: mjp_model, opts: mjp_opts | None = None) -> int:
+    opts = opts or mjp_opts_default()
+    h = ctypes.c_void_p()
+    _check(lib().mjp_plan_create_stencil(ctypes.byref(model), ctypes.byref(opts), ctypes.byref(h)))
+    return h.value
+
+
+def mjp_plan_destroy(plan: int) -> None:
+    lib().mjp_plan_destroy(plan)
+
+
+def mjp_plan_n(plan: int) -> int:
+    return int(lib().mjp_plan_n(plan))
+
+
+# -------------------------------------------------------------- solvers
+
+def mjp_expv(plan: int, rho0, times, out, info: bool = False, stream=None):
+    """out[j] = rho(times[j]); rho0 [N] and out [n_t, N] are float32 CUDA
+    tensors.  Returns a list of info dicts when info=True (synchronous)."""
+    t = np.ascontiguousarray(times, dtype=np.float64).reshape(-1)
+    inf = (mjp_info * len(t))() if info else None
+    _check(lib().mjp_expv(plan, _ptr(rho0), len(t), _ptr(t), _ptr(out),
+                          ctypes.cast(inf, ctypes.c_void_p) if info else None, _stream(stream)))
+    return [i.as_dict() for i in inf] if info else None
+
+
+def mjp_expv_batched(plans, rho0s, times_list, outs, info: bool = False, stream=None):
+    B = len(plans)
+    P = (ctypes.c_void_p * B)(*plans)
+    R = (ctypes.c_void_p * B)(*[_ptr(r) for r in rho0s])
+    O = (ctypes.c_void_p * B)(*[_ptr(o) for o in outs])
+    ts = [np.ascontiguousarray(t, dtype=np.float64).reshape(-1) for t in times_list]
+    NT = (ctypes.c_int32 * B)(*[len(t) for t in ts])
+    TP = (ctypes.c_void_p * B)(*[_ptr(t) for t in ts])
+    total = sum(len(t) for t in ts)
+    inf = (mjp_info * total)() if info else None
+    _check(lib().mjp_expv_batched(B, P, R, NT, TP, O, ctypes.cast(inf, ctypes.c_void_p) if info else None,
+                                  _stream(stream)))
+    return [i.as_dict() for i in inf] if info else None
+
+
+def make_obs(T, obs, x0=(0, 0)):
+    """Keeps the host arrays alive alongside the struct."""
+    T = np.ascontiguousarray(T, dtype=np.float64)
+    obs = np.ascontiguousarray(obs, dtype=np.int32).reshape(-1, 4)
+    o = mjp_obs(len(T), _ptr(T), obs.shape[0], _ptr(obs), (ctypes.c_int32 * 2)(*x0))
+    o._keep = (T, obs)
+    return o
+
+
+def mjp_loglik(model: int, theta, dims, obs: mjp_obs, out, opts: mjp_opts | None = None, info=None,
+               stream=None) -> None:
+    """theta [B, 4] float64, dims [B, 2] int32, out [B] float64: CUDA tensors;
+    info: optional CUDA uint8 tensor of B * sizeof(mjp_info) bytes."""
+    opts = opts or mjp_opts_default()
+    B = int(out.shape[0])
+    _check(lib().mjp_loglik(model, B, _ptr(theta), _ptr(dims), ctypes.byref(obs), ctypes.byref(opts), _ptr(out),
+                            _ptr(info), _stream(stream)))
+
+
+def mjp_loglik_max_states() -> int:
+    return int(lib().mjp_loglik_max_states())
+
+
+# ------------------------------------------------------------ surrogate
+
+def mjp_surrogate_create(in_dim=4, width=256, depth=3, seed=0) -> int:
+    cfg = mjp_mlp_cfg(in_dim, width, depth)
+    h = ctypes.c_void_p()
+    _check(lib().mjp_surrogate_create(ctypes.byref(cfg), seed, ctypes.byref(h)))
+    return h.value
+
+
+def mjp_surrogate_destroy(s: int) -> None:
+    lib().mjp_surrogate_destroy(s)
+
+
+def mjp_surrogate_train(s: int, x, y, cfg: mjp_train_cfg, losses: bool = True, stream=None):
+    n = int(y.shape[0])
+    buf = np.zeros(cfg.epochs, np.float32) if losses else None
+    _check(lib().mjp_surrogate_train(s, _ptr(x), _ptr(y), n, ctypes.byref(cfg), _ptr(buf), _stream(stream)))
+    return buf
+
+
+def mjp_surrogate_infer(s: int, x, y, stream=None) -> None:
+    _check(lib().mjp_surrogate_infer(s, _ptr(x), int(x.shape[0]), _ptr(y), _stream(stream)))
+
+
+def mjp_surrogate_num_params(s: int) -> int:
+    return int(lib().mjp_surrogate_num_params(s))
+
+
+def mjp_surrogate_get_params(s: int) -> np.ndarray:
+    buf = np.zeros(mjp_surrogate_num_params(s), np.float32)
+    _check(lib().mjp_surrogate_get_params(s, _ptr(buf), buf.size))
+    return buf
+
+
+def mjp_surrogate_set_params(s: int, params) -> None:
+    buf = np.ascontiguousarray(params, dtype=np.float32)
+    _check(lib().mjp_surrogate_set_params(s, _ptr(buf), buf.size))
+
+
+def mjp_surrogate_save(s: int, path: str) -> None:
+    _check(lib().mjp_surrogate_save(s, path.encode()))
+
+
+def mjp_surrogate_load(path: str) -> int:
+    h = ctypes.c_void_p()
+    _check(lib().mjp_surrogate_load(path.encode(), ctypes.byref(h)))
+    return h.value
+
+
+def mjp_last_error() -> str:
+    return lib().mjp_last_error().decode()
+
+
+def mjp_version() -> str:
+    return lib().mjp_version().decode()

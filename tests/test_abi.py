@@ -1,0 +1,155 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/mjp.h declares, builds model generators identical to the oracle's
+independent ones, and rejects invalid calls on the host before any launch."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2312_05647_amd import mjp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "mjp.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = set(re.findall(r"\b(mjp_[a-z0-9_]+)\s*\(", src))
+    return sorted(names)
+
+
+def test_every_declared_symbol_is_exported():
+    L = mjp.lib()
+    names = declared_functions()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(L, name), name
+    bound = {n for n, _, _ in mjp._SIGS}
+    assert set(names) == bound, set(names) ^ bound
+
+
+def test_version_and_defaults():
+    assert "gfx950" in mjp.mjp_version()
+    o = mjp.mjp_opts_default()
+    assert o.omega_factor == 1.1 and o.tol == 1e-9 and o.lump == 1
+    assert o.k_rule == mjp.MJP_K_TOL and o.truncation == mjp.MJP_CONSERVATIVE
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Every ctypes struct of the binding has the size and field offsets the
+    C compiler gives the header's struct."""
+    import subprocess
+    structs = {"mjp_opts": mjp.mjp_opts, "mjp_info": mjp.mjp_info, "mjp_csr": mjp.mjp_csr,
+               "mjp_model": mjp.mjp_model, "mjp_obs": mjp.mjp_obs, "mjp_mlp_cfg": mjp.mjp_mlp_cfg,
+               "mjp_train_cfg": mjp.mjp_train_cfg}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mjp.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        for f, _ in cls._fields_:
+            lines.append(f'printf("{name}.{f} %zu\\n", offsetof({name}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines())
+    for name, cls in structs.items():
+        assert int(got[name]) == ctypes.sizeof(cls), name
+        for f, _ in cls._fields_:
+            assert int(got[f"{name}.{f}"]) == getattr(cls, f).offset, (name, f)
+
+
+@pytest.mark.parametrize("leaky", [0, 1])
+@pytest.mark.parametrize("case", [(0, [500.0, 1.0], [1000]), (0, [3.0, 0.0], [9]), (1, [200.0, 1.0, 0.5, 0.5], [30, 20]),
+                                  (1, [5.0, 0.7, 0.0, 2.0], [7, 5]), (1, [1.0, 2.0, 3.0, 4.0], [1, 6])])
+def test_model_csr_matches_oracle(orc, case, leaky):
+    model, theta, dims = case
+    rp, ci, va = mjp.mjp_model_csr(mjp.make_model(model, theta, dims), leaky)
+    ref = orc.model_generator(model, theta, dims, leaky=bool(leaky))
+    assert np.array_equal(rp.astype(np.int64), ref.row_ptr)
+    assert np.array_equal(ci, ref.col)
+    assert np.allclose(va, ref.val, rtol=1e-15, atol=0)
+
+
+def _csr(rp, ci, va):
+    return (np.asarray(rp, np.int32), np.asarray(ci, np.int32), np.asarray(va, np.float64))
+
+
+GOOD = _csr([0, 2, 4], [0, 1, 0, 1], [-1.0, 1.0, 2.0, -2.0])
+
+
+def status_of(fn, *a, **k):
+    try:
+        fn(*a, **k)
+    except mjp.MjpError as e:
+        return e.status
+    return mjp.MJP_OK
+
+
+@pytest.mark.parametrize("bad,expect", [
+    (_csr([0, 2, 4], [0, 1, 0, 1], [-1.0, -1.0, 2.0, -2.0]), mjp.MJP_E_NOT_GENERATOR),   # negative rate
+    (_csr([0, 2, 4], [0, 1, 0, 1], [-1.5, 1.0, 2.0, -2.0]), mjp.MJP_E_NOT_GENERATOR),    # row sum != 0
+    (_csr([0, 2, 4], [1, 0, 0, 1], [1.0, -1.0, 2.0, -2.0]), mjp.MJP_E_INVALID_ARG),      # unsorted
+    (_csr([0, 2, 4], [0, 2, 0, 1], [-1.0, 1.0, 2.0, -2.0]), mjp.MJP_E_INVALID_ARG),      # column out of range
+    (_csr([0, 3, 4], [0, 1, 0, 1], [-1.0, 1.0, 2.0, -2.0]), mjp.MJP_E_INVALID_ARG),      # row_ptr end != nnz
+    (_csr([0, 2, 4], [0, 1, 0, 1], [-1.0, np.nan, 2.0, -2.0]), mjp.MJP_E_INVALID_ARG),   # non-finite
+    (_csr([0], [], []), mjp.MJP_E_INVALID_ARG),                                          # n = 0
+])
+def test_csr_validation(bad, expect):
+    assert status_of(mjp.mjp_plan_create_csr, *bad) == expect
+
+
+def test_leaky_rows_may_lose_but_not_gain_mass():
+    gain = _csr([0, 2, 4], [0, 1, 0, 1], [-0.5, 1.0, 2.0, -2.0])
+    assert status_of(mjp.mjp_plan_create_csr, *gain, mjp.mjp_opts_default(truncation=mjp.MJP_LEAKY, renorm_every=0)) \
+        == mjp.MJP_E_NOT_GENERATOR
+
+
+@pytest.mark.parametrize("over", [dict(omega_factor=1.0), dict(omega_factor=float("nan")), dict(tol=0.0),
+                                  dict(tol=1.0), dict(k_rule=5), dict(truncation=3), dict(renorm_every=-1),
+                                  dict(truncation=1, renorm_every=8), dict(lump=2), dict(k_cap=0),
+                                  dict(variant=9)])
+def test_option_validation(over):
+    o = mjp.mjp_opts_default(**over)
+    assert status_of(mjp.mjp_plan_create_csr, *GOOD, o) == mjp.MJP_E_INVALID_ARG
+    m = mjp.make_model(mjp.MJP_MODEL_BD, [1.0, 1.0], [5])
+    assert status_of(mjp.mjp_plan_create_stencil, m, o) == mjp.MJP_E_INVALID_ARG
+
+
+def test_reserved_option_fields_must_be_zero():
+    o = mjp.mjp_opts_default()
+    o.reserved[3] = 1
+    assert status_of(mjp.mjp_plan_create_csr, *GOOD, o) == mjp.MJP_E_INVALID_ARG
+
+
+@pytest.mark.parametrize("model,theta,dims", [(7, [1.0], [3]), (0, [-1.0, 1.0], [5]), (0, [1.0, 1.0], [0]),
+                                              (0, [1.0, 1.0], [5, 2]), (1, [1.0, 1.0, np.inf, 1.0], [4, 4]),
+                                              (1, [1.0] * 4, [0, 4])])
+def test_model_validation(model, theta, dims):
+    m = mjp.make_model(model, theta, dims)
+    assert status_of(mjp.mjp_plan_create_stencil, m) == mjp.MJP_E_INVALID_ARG
+    assert status_of(mjp.mjp_model_csr, m) == mjp.MJP_E_INVALID_ARG
+
+
+def test_null_arguments_rejected_on_host():
+    L = mjp.lib()
+    assert L.mjp_plan_create_csr(None, None, None) == mjp.MJP_E_INVALID_ARG
+    assert L.mjp_plan_create_stencil(None, None, None) == mjp.MJP_E_INVALID_ARG
+    t = np.array([1.0])
+    assert L.mjp_expv(None, None, 1, t.ctypes.data, None, None, None) == mjp.MJP_E_INVALID_ARG
+    assert L.mjp_expv_batched(-1, None, None, None, None, None, None, None) == mjp.MJP_E_INVALID_ARG
+    assert L.mjp_expv_batched(0, None, None, None, None, None, None, None) == mjp.MJP_OK
+    assert mjp.mjp_last_error() == ""
+    L.mjp_plan_destroy(None)   # accepted
+    assert L.mjp_plan_n(None) == 0
+
+
+def test_no_device_reports_device_error():
+    """A valid operator on a machine without a GPU fails with MJP_E_DEVICE
+    (the host checks all passed first)."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    assert status_of(mjp.mjp_plan_create_csr, *GOOD) == mjp.MJP_E_DEVICE

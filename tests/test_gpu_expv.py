@@ -1,0 +1,303 @@
+"""GPU parity of mjp_expv against the FP64 oracle, through the C ABI.
+
+Bar (FP32 products, FP64 weights): L1 distance <= 1e-6 per result vector, and
+entrywise relative error <= 1e-4 wherever the oracle's probability exceeds
+1e-7 (all terms are non-negative, so FP32 rounding stays relative; tiny
+entries are dominated by the allowed left/right truncation of 2.5e-10 each).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2312_05647_amd import mjp, synth
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+L1_BAR = 1e-6
+REL_BAR = 1e-4
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def gpu_expv(plan, rho0, times, info=True):
+    n = mjp.mjp_plan_n(plan)
+    r0 = torch.as_tensor(np.asarray(rho0, np.float32), device="cuda")
+    out = torch.empty((len(times), n), dtype=torch.float32, device="cuda")
+    inf = mjp.mjp_expv(plan, r0, times, out, info=info)
+    torch.cuda.synchronize()
+    return out.cpu().double().numpy(), inf
+
+
+def check_close(got, ref, what=""):
+    l1 = np.abs(got - ref).sum()
+    big = ref > 1e-7
+    rel = (np.abs(got - ref)[big] / ref[big]).max() if big.any() else 0.0
+    assert l1 <= L1_BAR, f"{what}: L1 {l1:.3e}"
+    assert rel <= REL_BAR, f"{what}: entrywise rel {rel:.3e}"
+    assert (got >= 0).all(), f"{what}: negative entry"
+    return l1
+
+
+def csr_plan_from_model(model, theta, dims, **opts):
+    m = mjp.make_model(model, theta, dims)
+    rp, ci, va = mjp.mjp_model_csr(m, opts.get("truncation", 0))
+    return mjp.mjp_plan_create_csr(rp, ci, va, mjp.mjp_opts_default(**opts))
+
+
+def stencil_plan(model, theta, dims, **opts):
+    return mjp.mjp_plan_create_stencil(mjp.make_model(model, theta, dims), mjp.mjp_opts_default(**opts))
+
+
+@pytest.fixture(scope="module")
+def bd_small(orc):
+    """Immigration-death, N = 1000, lambda = 500, mu = 1, t = 1, from 0."""
+    A = orc.model_generator(0, [500.0, 1.0], [1000])
+    ref, info = orc.expv(A, synth.delta(1000), 1.0)
+    return ref, info
+
+
+@pytest.mark.parametrize("kind", ["csr", "stencil"])
+def test_birth_death_small_workload(orc, bd_small, kind):
+    say(f"[gpu] birth-death N=1000 t=1 via {kind}")
+    ref, oinfo = bd_small
+    plan = (csr_plan_from_model if kind == "csr" else stencil_plan)(0, [500.0, 1.0], [1000])
+    try:
+        got, inf = gpu_expv(plan, synth.delta(1000), [1.0])
+    finally:
+        mjp.mjp_plan_destroy(plan)
+    check_close(got[0], ref, kind)
+    from scipy.stats import poisson
+    exact = poisson.pmf(np.arange(1000), 500.0 * (1 - math.exp(-1.0)))
+    assert np.abs(got[0] - exact).sum() <= L1_BAR
+    i = inf[0]
+    assert abs(i["omega"] - oinfo["omega"]) < 1e-9 * oinfo["omega"]
+    assert i["L"] > 0 and i["K"] > i["W"]
+    assert i["eps_left"] <= 2.5e-10 and i["eps_right"] <= 2.5e-10
+    assert abs(i["mass_in"] - 1) < 1e-7 and abs(i["mass_out"] - 1) < 1e-6 and i["flags"] == 0
+
+
+@pytest.fixture(scope="module")
+def cascade_300(orc):
+    theta = [200.0, 1.0, 0.5, 0.5]
+    A = orc.model_generator(1, theta, [300, 300])
+    times = synth.log_spaced_times(16, 0.1, 10.0)
+    say("[oracle] cascade 300x300, 16 times")
+    ref = orc.expv_times(A, synth.delta(90000), times)
+    return theta, times, ref
+
+
+@pytest.mark.parametrize("kind", ["csr", "stencil"])
+def test_cascade_16_times(cascade_300, kind):
+    theta, times, ref = cascade_300
+    say(f"[gpu] cascade 300x300, 16 log-spaced times via {kind}")
+    plan = (csr_plan_from_model if kind == "csr" else stencil_plan)(1, theta, [300, 300])
+    try:
+        got, inf = gpu_expv(plan, synth.delta(90000), times)
+    finally:
+        mjp.mjp_plan_destroy(plan)
+    worst = 0.0
+    for j in range(len(times)):
+        worst = max(worst, check_close(got[j], ref[j], f"{kind} t={times[j]:.3f}"))
+        assert inf[j]["flags"] == 0
+    say(f"    worst L1 over times: {worst:.3e}")
+
+
+@pytest.mark.parametrize("n,seed", [(1, 1), (2, 2), (63, 3), (64, 4), (65, 5), (257, 6), (1000, 7), (4097, 8)])
+def test_random_generators_ragged_sizes(orc, n, seed):
+    """Random sparse generators at sizes around the 64-row slice and the
+    256-row block: ragged tails of both."""
+    say(f"[gpu] random generator n={n} seed={seed}")
+    if n == 1:
+        rp, ci, va = np.array([0, 1]), np.array([0]), np.array([0.0])
+    else:
+        rp, ci, va = synth.with_generator_diagonal(*synth.random_rate_graph(n, seed, degree=4, scale=3.0))
+    A = orc.CSR.from_arrays(rp, ci, va)
+    rho0 = synth.random_prob(n, seed + 50)
+    times = [0.0, 0.05, 0.7, 2.3]
+    ref = orc.expv_times(A, rho0, times)
+    plan = mjp.mjp_plan_create_csr(rp, ci, va)
+    try:
+        got, inf = gpu_expv(plan, rho0, times)
+    finally:
+        mjp.mjp_plan_destroy(plan)
+    for j, t in enumerate(times):
+        check_close(got[j], ref[j], f"n={n} t={t}")
+    assert np.array_equal(got[0], np.asarray(rho0, np.float32).astype(np.float64))  # t = 0 returns rho0
+
+
+def test_unsorted_and_repeated_times(orc):
+    A = orc.model_generator(1, [20.0, 1.0, 0.5, 0.5], [40, 30])
+    rho0 = synth.delta(1200)
+    times = [3.0, 0.5, 3.0, 0.0, 1e-9, 7.5]
+    ref = orc.expv_times(A, rho0, times)
+    say("[gpu] unsorted/repeated times")
+    plan = stencil_plan(1, [20.0, 1.0, 0.5, 0.5], [40, 30])
+    try:
+        got, inf = gpu_expv(plan, rho0, times)
+    finally:
+        mjp.mjp_plan_destroy(plan)
+    for j in range(len(times)):
+        check_close(got[j], ref[j], f"t={times[j]}")
+    assert np.array_equal(got[0], got[2])
+    assert inf[4]["K"] <= 1
+
+
+def test_zero_rates_return_rho0():
+    say("[gpu] zero rates")
+    plan = stencil_plan(1, [0.0, 0.0, 0.0, 0.0], [5, 4])
+    rho0 = synth.random_prob(20, 3)
+    try:
+        got, inf = gpu_expv(plan, rho0, [0.0, 2.0])
+    finally:
+        mjp.mjp_plan_destroy(plan)
+    r32 = np.asarray(rho0, np.float32).astype(np.float64)
+    assert np.array_equal(got[0], r32) and np.array_equal(got[1], r32)
+    assert inf[1]["omega"] == 0 and inf[1]["K"] == 0
+
+
+@pytest.mark.parametrize("kind", ["csr", "stencil"])
+def test_paper_rule_equal_K(orc, kind):
+    """Paper cutoff K = floor(W + 6 sqrt W) + 1, accumulated from k = 0, on
+    both sides: the GPU and the oracle run the same number of products."""
+    say(f"[gpu] paper cutoff via {kind}")
+    A = orc.model_generator(0, [60.0, 2.0], [150])
+    rho0 = synth.delta(150, 3)
+    ref, oi = orc.expv(A, rho0, 0.3, k_rule=orc.K_PAPER)
+    mk = csr_plan_from_model if kind == "csr" else stencil_plan
+    plan = mk(0, [60.0, 2.0], [150], k_rule=mjp.MJP_K_PAPER)
+    try:
+        got, inf = gpu_expv(plan, rho0, [0.3])
+    finally:
+        mjp.mjp_plan_destroy(plan)
+    assert inf[0]["K"] == oi["K"] and inf[0]["L"] == 0
+    check_close(got[0], ref, "paper rule")
+
+
+def test_without_lumping_mass_is_window_weight(orc):
+    say("[gpu] lump off")
+    plan = stencil_plan(1, [30.0, 1.0, 0.5, 0.5], [60, 50], lump=0, tol=1e-4)
+    try:
+        got, inf = gpu_expv(plan, synth.delta(3000), [1.5])
+    finally:
+        mjp.mjp_plan_destroy(plan)
+    i = inf[0]
+    assert i["residual"] > 1e-6
+    assert abs(got[0].sum() - (1 - i["residual"])) < 2e-7
+    assert abs(i["mass_out"] - (1 - i["residual"])) < 2e-7
+
+
+@pytest.mark.parametrize("factor", [1.5, 2.0])
+def test_omega_factor(orc, factor):
+    say(f"[gpu] omega factor {factor}")
+    A = orc.model_generator(1, [15.0, 1.0, 0.6, 0.4], [35, 40])
+    rho0 = synth.random_prob(1400, 9)
+    ref, _ = orc.expv(A, rho0, 1.2, omega_factor=factor)
+    plan = stencil_plan(1, [15.0, 1.0, 0.6, 0.4], [35, 40], omega_factor=factor)
+    try:
+        got, inf = gpu_expv(plan, rho0, [1.2])
+    finally:
+        mjp.mjp_plan_destroy(plan)
+    check_close(got[0], ref, f"factor {factor}")
+
+
+@pytest.mark.parametrize("renorm", [0, 1, 7])
+def test_renorm_interval(orc, renorm):
+    say(f"[gpu] renorm_every={renorm}")
+    A = orc.model_generator(1, [40.0, 1.0, 0.5, 0.5], [80, 70])
+    rho0 = synth.delta(5600)
+    ref, _ = orc.expv(A, rho0, 4.0)
+    plan = stencil_plan(1, [40.0, 1.0, 0.5, 0.5], [80, 70], renorm_every=renorm)
+    try:
+        got, _ = gpu_expv(plan, rho0, [4.0])
+    finally:
+        mjp.mjp_plan_destroy(plan)
+    check_close(got[0], ref, f"renorm {renorm}")
+
+
+def test_leaky_truncation(orc):
+    """Leaky reading (exit rate counts births off the grid): mass leaks; the
+    oracle's leaky generator is the reference."""
+    say("[gpu] leaky truncation")
+    A = orc.model_generator(0, [30.0, 1.0], [40], leaky=True)
+    ref, _ = orc.expv(A, synth.delta(40), 2.0)
+    for kind in ("csr", "stencil"):
+        mk = csr_plan_from_model if kind == "csr" else stencil_plan
+        plan = mk(0, [30.0, 1.0], [40], truncation=mjp.MJP_LEAKY, renorm_every=0)
+        try:
+            got, _ = gpu_expv(plan, synth.delta(40), [2.0])
+        finally:
+            mjp.mjp_plan_destroy(plan)
+        assert ref.sum() < 0.999
+        check_close(got[0], ref, f"leaky {kind}")
+
+
+def test_bitwise_deterministic():
+    say("[gpu] determinism")
+    plan = csr_plan_from_model(1, [200.0, 1.0, 0.5, 0.5], [120, 150])
+    try:
+        a, _ = gpu_expv(plan, synth.delta(18000), [0.3, 2.0], info=False)
+        b, _ = gpu_expv(plan, synth.delta(18000), [0.3, 2.0], info=False)
+    finally:
+        mjp.mjp_plan_destroy(plan)
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("bad,flag", [(np.nan, mjp.MJP_FLAG_NAN), (-0.25, mjp.MJP_FLAG_NEG)])
+def test_bad_rho0_flags(bad, flag):
+    say(f"[gpu] rho0 with {bad}")
+    plan = stencil_plan(0, [5.0, 1.0], [30])
+    rho0 = synth.random_prob(30, 4)
+    rho0[7] = bad
+    r0 = torch.as_tensor(rho0.astype(np.float32), device="cuda")
+    out = torch.empty((1, 30), dtype=torch.float32, device="cuda")
+    try:
+        with pytest.raises(mjp.MjpError) as e:
+            mjp.mjp_expv(plan, r0, [1.0], out, info=True)
+        assert e.value.status == mjp.MJP_E_NUMERIC
+        # asynchronous form does not fail, it only computes
+        mjp.mjp_expv(plan, r0, [1.0], out, info=False)
+        torch.cuda.synchronize()
+    finally:
+        mjp.mjp_plan_destroy(plan)
+
+
+def test_k_cap():
+    plan = stencil_plan(0, [500.0, 1.0], [1000], k_cap=100)
+    r0 = torch.zeros(1000, device="cuda")
+    out = torch.empty((1, 1000), device="cuda")
+    try:
+        with pytest.raises(mjp.MjpError) as e:
+            mjp.mjp_expv(plan, r0, [1.0], out)
+        assert e.value.status == mjp.MJP_E_K_LIMIT
+    finally:
+        mjp.mjp_plan_destroy(plan)
+
+
+def test_batched_matches_single(orc):
+    say("[gpu] expv_batched")
+    plans = [stencil_plan(0, [50.0, 1.0], [200]), stencil_plan(1, [10.0, 1.0, 0.5, 0.5], [30, 30]),
+             csr_plan_from_model(1, [5.0, 1.0, 2.0, 1.0], [20, 41])]
+    rho0s = [synth.delta(200), synth.random_prob(900, 1), synth.random_prob(820, 2)]
+    times = [[0.5, 2.0], [1.0], [0.2, 0.9, 3.0]]
+    try:
+        r = [torch.as_tensor(x.astype(np.float32), device="cuda") for x in rho0s]
+        outs = [torch.empty((len(t), mjp.mjp_plan_n(p)), device="cuda") for p, t in zip(plans, times)]
+        inf = mjp.mjp_expv_batched(plans, r, times, outs, info=True)
+        torch.cuda.synchronize()
+        assert len(inf) == 6
+        refs = [orc.expv_times(orc.model_generator(0, [50.0, 1.0], [200]), rho0s[0], times[0]),
+                orc.expv_times(orc.model_generator(1, [10.0, 1.0, 0.5, 0.5], [30, 30]), rho0s[1], times[1]),
+                orc.expv_times(orc.model_generator(1, [5.0, 1.0, 2.0, 1.0], [20, 41]), rho0s[2], times[2])]
+        for o, ref in zip(outs, refs):
+            o = o.cpu().double().numpy()
+            for j in range(len(ref)):
+                check_close(o[j], ref[j], "batched")
+    finally:
+        for p in plans:
+            mjp.mjp_plan_destroy(p)
