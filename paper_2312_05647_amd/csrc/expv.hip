@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "sweep.h"
 
 namespace mjp {
 
@@ -26,16 +27,6 @@ mjp_status check_opts(const mjp_opts* o);
 
 constexpr int kBlock = 256;
 constexpr int kMaxFused = 6;     // active times accumulated inside a step kernel
-constexpr int kMaxTimes = 48;    // times handled by one sweep
-
-// Per collection time, passed by value.
-struct TimeParam {
-    double W;       // Omega t
-    double lastw;   // weight applied at k == K: w_K (+ residual when lumping)
-    int32_t L, K;   // accumulated window
-    int32_t woff;   // offset of w_L in the weight table
-    int32_t out;    // row of the output array
-};
 
 struct TimeSet {
     int32_t n;
@@ -43,13 +34,6 @@ struct TimeSet {
     int32_t slot[kMaxFused];  // compensation-buffer row of each active time
 };
 
-struct AllTimes {
-    int32_t n;
-    TimeParam tp[kMaxTimes];
-};
-
-// scalar slots in plan->scal (doubles)
-enum { S_MASS0 = 0, S_MASSK = 1, S_FLAGS = 2, S_SCALE = 3, S_COUNT = 8 };
 
 // ------------------------------------------------------------- helpers
 
@@ -354,82 +338,101 @@ static mjp_status run_sweep(mjp_plan* p, const float* rho0, const std::vector<Sw
         hipLaunchKernelGGL(k_weights, dim3(gx, nt), dim3(256), 0, st, at, wtab);
     }
 
-    // compensation rows are handed out to times while their window is open
-    std::vector<int> slot_of(nt, -1);
-    std::vector<int> free_slots;
-    for (int i = max_open - 1; i >= 0; --i) free_slots.push_back(i);
-
-    auto active_at = [&](int k, std::vector<int>& act) {
-        act.clear();
-        for (int j = 0; j < nt; ++j)
-            if (at.tp[j].L <= k && k <= at.tp[j].K) act.push_back(j);
-    };
-    std::vector<int> act;
-    // Launch the accumulations of jump k for the active times: the first
-    // kMaxFused inside the step kernel (through ts), the rest separately.
-    auto make_sets = [&](int k, TimeSet& fused, std::vector<TimeSet>& extra) -> mjp_status {
-        active_at(k, act);
-        fused.n = 0;
-        extra.clear();
-        for (int j : act) {
-            if (slot_of[j] < 0) {
-                if (free_slots.empty()) return fail(MJP_E_WORKSPACE, "internal: compensation rows exhausted");
-                slot_of[j] = free_slots.back();
-                free_slots.pop_back();
-            }
-            TimeSet* dst = &fused;
-            if (fused.n == kMaxFused) {
-                if (extra.empty() || extra.back().n == kMaxFused) extra.push_back(TimeSet{});
-                dst = &extra.back();
-            }
-            dst->tp[dst->n] = at.tp[j];
-            dst->slot[dst->n] = slot_of[j];
-            dst->n++;
+    PersistCfg cfg;
+    if (p->opts.variant != MJP_VARIANT_STEPWISE && persistent_fits(p, max_open, cfg)) {
+        // colour the windows (sorted by start) onto the register slots
+        std::vector<int> slot(nt, -1);
+        std::vector<int32_t> busy_until;  // last jump of each slot's current window
+        for (int j = 0; j < nt; ++j) {
+            int q = -1;
+            for (size_t i = 0; i < busy_until.size(); ++i)
+                if (busy_until[i] < at.tp[j].L) { q = (int)i; break; }
+            if (q < 0) { q = (int)busy_until.size(); busy_until.push_back(0); }
+            busy_until[(size_t)q] = at.tp[j].K;
+            slot[(size_t)j] = q;
         }
-        return MJP_OK;
-    };
-    auto release_done = [&](int k) {
-        for (int j : act)
-            if (at.tp[j].K == k) {
-                free_slots.push_back(slot_of[j]);
-                slot_of[j] = -2;
+        if ((s = launch_persistent(p, cfg, rho0, at, slot, out, st))) return s;
+    } else {
+        if (p->opts.variant == MJP_VARIANT_PERSISTENT)
+            return fail(MJP_E_UNSUPPORTED, "the persistent kernel cannot hold this operator (width %d, %d open windows)",
+                        p->max_width, max_open);
+        // compensation rows are handed out to times while their window is open
+        std::vector<int> slot_of(nt, -1);
+        std::vector<int> free_slots;
+        for (int i = max_open - 1; i >= 0; --i) free_slots.push_back(i);
+
+        auto active_at = [&](int k, std::vector<int>& act) {
+            act.clear();
+            for (int j = 0; j < nt; ++j)
+                if (at.tp[j].L <= k && k <= at.tp[j].K) act.push_back(j);
+        };
+        std::vector<int> act;
+        // Launch the accumulations of jump k for the active times: the first
+        // kMaxFused inside the step kernel (through ts), the rest separately.
+        auto make_sets = [&](int k, TimeSet& fused, std::vector<TimeSet>& extra) -> mjp_status {
+            active_at(k, act);
+            fused.n = 0;
+            extra.clear();
+            for (int j : act) {
+                if (slot_of[j] < 0) {
+                    if (free_slots.empty()) return fail(MJP_E_WORKSPACE, "internal: compensation rows exhausted");
+                    slot_of[j] = free_slots.back();
+                    free_slots.pop_back();
+                }
+                TimeSet* dst = &fused;
+                if (fused.n == kMaxFused) {
+                    if (extra.empty() || extra.back().n == kMaxFused) extra.push_back(TimeSet{});
+                    dst = &extra.back();
+                }
+                dst->tp[dst->n] = at.tp[j];
+                dst->slot[dst->n] = slot_of[j];
+                dst->n++;
             }
-    };
+            return MJP_OK;
+        };
+        auto release_done = [&](int k) {
+            for (int j : act)
+                if (at.tp[j].K == k) {
+                    free_slots.push_back(slot_of[j]);
+                    slot_of[j] = -2;
+                }
+        };
 
-    TimeSet fused{};
-    std::vector<TimeSet> extra;
-    if ((s = make_sets(0, fused, extra))) return s;
-    hipLaunchKernelGGL(k_first, dim3(nblk), dim3(kBlock), 0, st, rho0, n, fused, wtab, out, comp, partials, flags);
-    for (const TimeSet& e : extra)
-        hipLaunchKernelGGL(k_accumulate, dim3(nblk), dim3(kBlock), 0, st, rho0, n, 0, e, wtab, out, comp);
-    release_done(0);
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, partials, (int)nblk, scal, 0);
-
-    const int m = p->opts.renorm_every;
-    const float* x = rho0;
-    for (int k = 1; k <= Kmax; ++k) {
-        float* y = p->rho[k & 1].as<float>();
-        if ((s = make_sets(k, fused, extra))) return s;
-        const double* scale = (m > 0 && (k - 1) > 0 && (k - 1) % m == 0) ? scal + S_SCALE : nullptr;
-        if (p->kind == PLAN_CSR) {
-            SellArgs a{p->slice_off.as<int32_t>(), p->col.as<int32_t>(), p->val.as<float>(), x, y, scale, n};
-            if (fused.n)
-                hipLaunchKernelGGL(k_sell_step<true>, dim3(nblk), dim3(kBlock), 0, st, a, k, fused, wtab, out, comp, partials);
-            else
-                hipLaunchKernelGGL(k_sell_step<false>, dim3(nblk), dim3(kBlock), 0, st, a, k, fused, wtab, out, comp, partials);
-        } else {
-            StencilArgs a{p->coef, x, y, scale, n};
-            if (fused.n)
-                hipLaunchKernelGGL(k_stencil_step<true>, dim3(nblk), dim3(kBlock), 0, st, a, k, fused, wtab, out, comp, partials);
-            else
-                hipLaunchKernelGGL(k_stencil_step<false>, dim3(nblk), dim3(kBlock), 0, st, a, k, fused, wtab, out, comp, partials);
-        }
+        TimeSet fused{};
+        std::vector<TimeSet> extra;
+        if ((s = make_sets(0, fused, extra))) return s;
+        hipLaunchKernelGGL(k_first, dim3(nblk), dim3(kBlock), 0, st, rho0, n, fused, wtab, out, comp, partials, flags);
         for (const TimeSet& e : extra)
-            hipLaunchKernelGGL(k_accumulate, dim3(nblk), dim3(kBlock), 0, st, y, n, k, e, wtab, out, comp);
-        release_done(k);
-        if (m > 0 && k % m == 0 && k < Kmax)
-            hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, partials, (int)nblk, scal, 1);
-        x = y;
+            hipLaunchKernelGGL(k_accumulate, dim3(nblk), dim3(kBlock), 0, st, rho0, n, 0, e, wtab, out, comp);
+        release_done(0);
+        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, partials, (int)nblk, scal, 0);
+
+        const int m = p->opts.renorm_every;
+        const float* x = rho0;
+        for (int k = 1; k <= Kmax; ++k) {
+            float* y = p->rho[k & 1].as<float>();
+            if ((s = make_sets(k, fused, extra))) return s;
+            const double* scale = (m > 0 && (k - 1) > 0 && (k - 1) % m == 0) ? scal + S_SCALE : nullptr;
+            if (p->kind == PLAN_CSR) {
+                SellArgs a{p->slice_off.as<int32_t>(), p->col.as<int32_t>(), p->val.as<float>(), x, y, scale, n};
+                if (fused.n)
+                    hipLaunchKernelGGL(k_sell_step<true>, dim3(nblk), dim3(kBlock), 0, st, a, k, fused, wtab, out, comp, partials);
+                else
+                    hipLaunchKernelGGL(k_sell_step<false>, dim3(nblk), dim3(kBlock), 0, st, a, k, fused, wtab, out, comp, partials);
+            } else {
+                StencilArgs a{p->coef, x, y, scale, n};
+                if (fused.n)
+                    hipLaunchKernelGGL(k_stencil_step<true>, dim3(nblk), dim3(kBlock), 0, st, a, k, fused, wtab, out, comp, partials);
+                else
+                    hipLaunchKernelGGL(k_stencil_step<false>, dim3(nblk), dim3(kBlock), 0, st, a, k, fused, wtab, out, comp, partials);
+            }
+            for (const TimeSet& e : extra)
+                hipLaunchKernelGGL(k_accumulate, dim3(nblk), dim3(kBlock), 0, st, y, n, k, e, wtab, out, comp);
+            release_done(k);
+            if (m > 0 && k % m == 0 && k < Kmax)
+                hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, partials, (int)nblk, scal, 1);
+            x = y;
+        }
     }
     MJP_HIP(hipGetLastError());
     if (out_mass) {
@@ -510,8 +513,10 @@ extern "C" mjp_status mjp_expv(mjp_plan* p, const float* rho0_d, int32_t n_t, co
                 inf.mass_out = mass[j];
                 inf.K = (int32_t)chunk[j].win.K;
                 inf.L = (int32_t)chunk[j].win.L;
-                inf.flags = (int32_t)flags;
+                inf.flags = (int32_t)(flags & ~kFlagBarrierTimeout);
             }
+            if (flags & kFlagBarrierTimeout)
+                return fail(MJP_E_DEVICE, "a grid barrier of the persistent kernel timed out");
             if (flags & (MJP_FLAG_NAN | MJP_FLAG_NEG))
                 return fail(MJP_E_NUMERIC, "numeric flags 0x%x (NaN/Inf or negative entry)", flags);
         }

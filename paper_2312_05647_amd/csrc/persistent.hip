@@ -1,0 +1,385 @@
+// Persistent R-MJP sweep: all K jumps, the weighted accumulation and the
+// lumping in ONE cooperative launch.
+//
+// Layout: workgroup g (after an XCD-aware renumbering so each XCD owns a
+// contiguous band of rows) owns WAVES*R consecutive 64-row slices; lane l of
+// wave w holds rows slice*64 + l of its R slices.  For a CSR plan each
+// thread loads its rows' entries of B^T (column, value) into registers once,
+// so the operator is read from memory once per solve instead of once per jump.
+// For a stencil plan each thread keeps its rows' five coefficients in
+// registers.  The Kahan pairs (s, c) of the open collection windows live in
+// registers too.  Per jump only the iterate moves: each thread gathers x at
+// its columns (L2/MALL) and writes its rows of y.
+//
+// Jumps are separated by a grid barrier: a monotone arrival counter updated
+// with an agent-scope release and polled with agent-scope acquire loads
+// (the acquire/release pair makes the y written before the barrier visible
+// to every XCD after it).  Every poll loop is bounded: on timeout the
+// workgroup raises a flag and leaves the loop, so the kernel always ends.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "internal.h"
+#include "sweep.h"
+
+namespace mjp {
+
+constexpr int kPWaves = 8;            // waves per workgroup
+constexpr int kPThreads = 64 * kPWaves;
+constexpr int kPSlots = 4;            // open collection windows held in registers
+
+struct PersistArgs {
+    const int32_t* __restrict__ slice_off;
+    const int32_t* __restrict__ col;
+    const float* __restrict__ val;
+    StencilCoef cf;
+    const float* __restrict__ rho0;
+    float* __restrict__ buf0;
+    float* __restrict__ buf1;
+    float* __restrict__ out;
+    const double* __restrict__ wtab;
+    double* __restrict__ pmass;   // [3][G] FP64 partial masses (initial, renorm double buffer)
+    unsigned* __restrict__ bar;   // [1] arrival counter, zero at launch
+    unsigned* __restrict__ flags;
+    double* __restrict__ mass_out;  // [2]: initial mass, last measured mass
+    uint64_t timeout_ticks;         // per-barrier wait limit in wall-clock ticks
+    int64_t n;
+    int32_t n_slices;
+    int32_t Kmax;
+    int32_t renorm_every;
+    int32_t G;
+    AllTimes at;
+    int32_t slot[kMaxTimes];
+};
+
+__device__ __forceinline__ int logical_block(int G) {
+    // workgroups are dispatched round-robin over the 8 XCDs; renumber so
+    // that XCD x runs logical blocks [x*G/8, (x+1)*G/8)
+    const int b = blockIdx.x;
+    return (b & 7) * (G >> 3) + (b >> 3);
+}
+
+// Returns false if the sweep was aborted (a barrier timed out somewhere);
+// every workgroup then leaves the kernel.  The wait is bounded by a
+// wall-clock deadline (s_memrealtime ticks), not by a poll count.
+__device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned target, unsigned* flags,
+                                             uint64_t timeout_ticks) {
+    __shared__ int aborted;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        aborted = 0;
+        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t t0 = wall_clock64();
+        while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(2);
+            if (__hip_atomic_load(flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kFlagBarrierTimeout) {
+                aborted = 1;
+                break;
+            }
+            if (wall_clock64() - t0 > timeout_ticks) {
+                __hip_atomic_fetch_or(flags, kFlagBarrierTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                aborted = 1;
+                break;
+            }
+        }
+    }
+    __syncthreads();
+    return aborted == 0;
+}
+
+__device__ __forceinline__ double block_sum_f64(double v, double* red) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < kPWaves; ++i) s += red[i];
+    __syncthreads();
+    return s;  // valid in thread 0
+}
+
+// Sum of the G partials in a fixed order (identical in every workgroup).
+__device__ __forceinline__ double sum_partials(const double* p, int G, double* red) {
+    double v = 0.0;
+    for (int i = threadIdx.x; i < G; i += kPThreads)
+        v += __hip_atomic_load(p + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    double s = block_sum_f64(v, red);
+    if (threadIdx.x == 0) red[kPWaves] = s;
+    __syncthreads();
+    s = red[kPWaves];
+    __syncthreads();
+    return s;
+}
+
+template <int R, int W, bool CSR>
+__global__ __launch_bounds__(kPThreads) void k_persistent(PersistArgs a) {
+    __shared__ double red[kPWaves + 1];
+    const int G = a.G;
+    const int g = logical_block(G);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int slice0 = (g * kPWaves + wave) * R;
+    const int64_t n = a.n;
+
+    int32_t row[R];
+    bool live[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        row[i] = (slice0 + i) * 64 + lane;
+        live[i] = row[i] < n;
+    }
+
+    // ---- operator into registers
+    int32_t cidx[R][W];
+    float cval[R][W];
+    if (CSR) {
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const int s = slice0 + i;
+            int beg = 0, w = 0;
+            if (s < a.n_slices) {
+                beg = a.slice_off[s];
+                w = (a.slice_off[s + 1] - beg) >> 6;
+            }
+#pragma unroll
+            for (int j = 0; j < W; ++j) {
+                if (live[i] && j < w) {
+                    cidx[i][j] = a.col[beg + j * 64 + lane];
+                    cval[i][j] = a.val[beg + j * 64 + lane];
+                } else {
+                    cidx[i][j] = live[i] ? (int32_t)row[i] : 0;
+                    cval[i][j] = 0.f;
+                }
+            }
+        }
+    } else {
+        // stencil: neighbour offsets and coefficients of each row (W == 5:
+        // self, -1, +1, -S1, +S1); absent neighbours get weight 0
+        const StencilCoef cf = a.cf;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const int64_t m = live[i] ? (int64_t)row[i] : 0;
+            int32_t i1, i2, S1 = cf.S1, S2 = cf.S2;
+            if (cf.model == MJP_MODEL_BD) { i1 = (int32_t)m; i2 = 0; S2 = 1; }
+            else { i2 = (int32_t)(m / S1); i1 = (int32_t)(m - (int64_t)i2 * S1); }
+            const float f1 = (float)i1, f2 = (float)i2;
+            float b1, d1, b2, d2;
+            b1 = cf.c[0]; d1 = cf.c[1];
+            b2 = cf.model == MJP_MODEL_BD ? 0.f : cf.c[2];
+            d2 = cf.model == MJP_MODEL_BD ? 0.f : cf.c[3];
+            const float o_b1 = (i1 + 1 < S1 || cf.leaky) ? b1 : 0.f;
+            const float o_d1 = d1 * f1;
+            const float o_b2 = (i2 + 1 < S2 || cf.leaky) ? b2 * f1 : 0.f;
+            const float o_d2 = d2 * f2;
+            float diag = (float)(1.0 - (((double)o_b1 + (double)o_d1) + ((double)o_b2 + (double)o_d2)));
+            int32_t cc[5] = {(int32_t)m, (int32_t)m, (int32_t)m, (int32_t)m, (int32_t)m};
+            float vv[5] = {diag, 0.f, 0.f, 0.f, 0.f};
+            if (i1 > 0) { cc[1] = (int32_t)m - 1; vv[1] = b1; }
+            if (i1 + 1 < S1) { cc[2] = (int32_t)m + 1; vv[2] = d1 * (f1 + 1.f); }
+            if (i2 > 0) { cc[3] = (int32_t)m - S1; vv[3] = b2 * f1; }
+            if (i2 + 1 < S2) { cc[4] = (int32_t)m + S1; vv[4] = d2 * (f2 + 1.f); }
+#pragma unroll
+            for (int j = 0; j < W; ++j) {
+                cidx[i][j] = j < 5 ? cc[j] : (int32_t)m;
+                cval[i][j] = (j < 5 && live[i]) ? vv[j] : 0.f;
+            }
+        }
+    }
+
+    // ---- k = 0
+    float sacc[kPSlots][R], cacc[kPSlots][R];
+#pragma unroll
+    for (int q = 0; q < kPSlots; ++q)
+#pragma unroll
+        for (int i = 0; i < R; ++i) { sacc[q][i] = 0.f; cacc[q][i] = 0.f; }
+
+    float yv[R];
+    double mloc = 0.0;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        yv[i] = live[i] ? a.rho0[row[i]] : 0.f;
+        if (live[i]) {
+            if (!(yv[i] >= 0.f)) atomicOr(a.flags, (yv[i] != yv[i]) ? (unsigned)MJP_FLAG_NAN : (unsigned)MJP_FLAG_NEG);
+            else if (isinf(yv[i])) atomicOr(a.flags, (unsigned)MJP_FLAG_NAN);
+        }
+        mloc += (double)yv[i];
+    }
+
+    auto accumulate = [&](int k) {
+        for (int j = 0; j < a.at.n; ++j) {
+            const TimeParam& tp = a.at.tp[j];
+            if (k < tp.L || k > tp.K) continue;
+            const int q = a.slot[j];
+            const float w = (k == tp.K) ? (float)tp.lastw : (float)a.wtab[tp.woff + (k - tp.L)];
+#pragma unroll
+            for (int qq = 0; qq < kPSlots; ++qq) {
+                if (qq != q) continue;
+#pragma unroll
+                for (int i = 0; i < R; ++i) {
+                    if (k == tp.L) {
+                        sacc[qq][i] = w * yv[i];
+                        cacc[qq][i] = 0.f;
+                    } else {
+                        const float yk = fmaf(w, yv[i], -cacc[qq][i]);
+                        const float t = sacc[qq][i] + yk;
+                        cacc[qq][i] = (t - sacc[qq][i]) - yk;
+                        sacc[qq][i] = t;
+                    }
+                    if (k == tp.K && live[i]) a.out[(int64_t)tp.out * n + row[i]] = sacc[qq][i] - cacc[qq][i];
+                }
+            }
+        }
+    };
+    accumulate(0);
+
+    // initial mass, reduced once all partials are in
+    {
+        const double s = block_sum_f64(mloc, red);
+        if (threadIdx.x == 0) __hip_atomic_store(a.pmass + g, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    unsigned epoch = 1;
+    if (!grid_barrier(a.bar, epoch * (unsigned)G, a.flags, a.timeout_ticks)) return;
+    const double mass0 = sum_partials(a.pmass, G, red);
+    double scale = 1.0;
+    double last_mass = mass0;
+
+    const int m = a.renorm_every;
+    for (int k = 1; k <= a.Kmax; ++k) {
+        const float* __restrict__ x = (k == 1) ? a.rho0 : ((k & 1) ? a.buf0 : a.buf1);
+        float* __restrict__ y = (k & 1) ? a.buf1 : a.buf0;
+        const float fs = (float)scale;
+        double part = 0.0;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            float acc = 0.f;
+#pragma unroll
+            for (int j = 0; j < W; ++j) acc = fmaf(cval[i][j], x[cidx[i][j]], acc);
+            yv[i] = fs * acc;
+            if (live[i]) y[row[i]] = yv[i];
+            part += (double)yv[i];
+        }
+        accumulate(k);
+        const bool renorm = m > 0 && (k % m == 0) && k < a.Kmax;
+        double* pm = a.pmass + (size_t)G * (1 + ((k / (m > 0 ? m : 1)) & 1));
+        if (renorm) {
+            const double s = block_sum_f64(part, red);
+            if (threadIdx.x == 0) __hip_atomic_store(pm + g, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (k == a.Kmax) break;
+        ++epoch;
+        if (!grid_barrier(a.bar, epoch * (unsigned)G, a.flags, a.timeout_ticks)) return;
+        if (renorm) {
+            last_mass = sum_partials(pm, G, red);
+            scale = (last_mass > 0.0 && mass0 > 0.0) ? mass0 / last_mass : 1.0;
+        } else {
+            scale = 1.0;
+        }
+    }
+    if (g == 0 && threadIdx.x == 0) {
+        a.mass_out[0] = mass0;
+        a.mass_out[1] = last_mass;
+    }
+}
+
+using PersistFn = void (*)(PersistArgs);
+
+template <bool CSR>
+static PersistFn pick(int R, int W) {
+#define MJP_CASE(r, w) if (R == r && W == w) return k_persistent<r, w, CSR>;
+    if (CSR) {
+        MJP_CASE(1, 3) MJP_CASE(2, 3) MJP_CASE(4, 3) MJP_CASE(8, 3)
+        MJP_CASE(1, 5) MJP_CASE(2, 5) MJP_CASE(4, 5) MJP_CASE(8, 5)
+        MJP_CASE(1, 8) MJP_CASE(2, 8) MJP_CASE(4, 8)
+    } else {
+        MJP_CASE(1, 5) MJP_CASE(2, 5) MJP_CASE(4, 5) MJP_CASE(8, 5)
+    }
+#undef MJP_CASE
+    return nullptr;
+}
+
+__global__ void k_zero_u32(unsigned* p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+// Decide whether the persistent kernel can run this sweep; fills cfg.
+bool persistent_fits(const mjp_plan* p, int max_open, PersistCfg& cfg) {
+    if (max_open > kPSlots) return false;
+    int W = 5;
+    if (p->kind == PLAN_CSR) {
+        if (p->max_width <= 3) W = 3;
+        else if (p->max_width <= 5) W = 5;
+        else if (p->max_width <= 8) W = 8;
+        else return false;
+    }
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return false;
+    int coop = 0;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return false;
+    const int64_t slices = (p->n + 63) / 64;
+    for (int R : {1, 2, 4, 8}) {
+        PersistFn f = p->kind == PLAN_CSR ? pick<true>(R, W) : pick<false>(R, W);
+        if (!f) continue;
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(f), kPThreads, 0) !=
+                hipSuccess || per_cu < 1)
+            continue;
+        const int64_t need = (slices + (int64_t)kPWaves * R - 1) / ((int64_t)kPWaves * R);
+        int64_t G = (need + 7) / 8 * 8;
+        if (G > (int64_t)ncu * per_cu) continue;  // does not fit co-resident: try more rows per thread
+        cfg.R = R;
+        cfg.W = W;
+        cfg.G = (int)G;
+        cfg.fn = reinterpret_cast<const void*>(f);
+        return true;
+    }
+    return false;
+}
+
+mjp_status launch_persistent(mjp_plan* p, const PersistCfg& cfg, const float* rho0, const AllTimes& at,
+                             const std::vector<int>& slot, float* out, hipStream_t st) {
+    const int64_t n = p->n;
+    mjp_status s;
+    if ((s = p->rho[0].reserve(sizeof(float) * n)) || (s = p->rho[1].reserve(sizeof(float) * n)) ||
+        (s = p->sync.reserve(sizeof(double) * (3 * (size_t)cfg.G + 4) + 64)))
+        return s;
+    double* pmass = p->sync.as<double>();
+    unsigned* bar = reinterpret_cast<unsigned*>(pmass + 3 * (size_t)cfg.G + 2);
+    double* mass_out = p->scal.as<double>() + S_MASS0;  // [S_MASS0], [S_MASSK]
+    PersistArgs a{};
+    a.slice_off = p->slice_off.as<int32_t>();
+    a.col = p->col.as<int32_t>();
+    a.val = p->val.as<float>();
+    a.cf = p->coef;
+    a.rho0 = rho0;
+    a.buf0 = p->rho[0].as<float>();
+    a.buf1 = p->rho[1].as<float>();
+    a.out = out;
+    a.wtab = p->wtab.as<double>();
+    a.pmass = pmass;
+    a.bar = bar;
+    a.flags = reinterpret_cast<unsigned*>(p->scal.as<double>() + S_FLAGS);
+    a.mass_out = mass_out;
+    a.n = n;
+    a.n_slices = (int32_t)((n + 63) / 64);
+    a.Kmax = 0;
+    for (int j = 0; j < at.n; ++j) a.Kmax = std::max(a.Kmax, at.tp[j].K);
+    a.renorm_every = p->opts.renorm_every;
+    a.G = cfg.G;
+    {
+        int khz = 0;
+        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, p->device) != hipSuccess || khz <= 0)
+            khz = 100000;
+        a.timeout_ticks = (uint64_t)khz * 1000ull * 2ull;  // 2 s for one barrier
+    }
+    a.at = at;
+    for (int j = 0; j < at.n; ++j) a.slot[j] = slot[(size_t)j];
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, bar, 1);
+    void* args[] = {&a};
+    MJP_HIP(hipLaunchCooperativeKernel(cfg.fn, dim3(cfg.G), dim3(kPThreads), args, 0, st));
+    return MJP_OK;
+}
+
+}  // namespace mjp

@@ -364,8 +364,10 @@ mjp_status mjp_plan_create_csr(const mjp_csr* A, const mjp_opts* opts, mjp_plan*
     }
 
     // B = I + A/Omega in FP32, pull form (row m of B^T lists b_nm over n).
-    // Conservative: b_nn = 1 - (FP64 sum of the row's FP32 off-diagonals), so
-    // each FP32 row of B sums to 1 up to the rounding of b_nn.
+    // b_nn = (exact row sum of B) - (FP64 sum of the row's FP32 off-diagonals),
+    // so each FP32 row of B has the row sum of the exact B up to the rounding
+    // of b_nn: 1 under conservative truncation, 1 - (leaked rate)/Omega under
+    // the leaky reading.
     const double omega = p->omega > 0.0 ? p->omega : 1.0;
     std::vector<int32_t> cnt((size_t)n + 1, 0);
     std::vector<float> bdiag((size_t)n);
@@ -377,7 +379,14 @@ mjp_status mjp_plan_create_csr(const mjp_csr* A, const mjp_opts* opts, mjp_plan*
             off += (double)(float)(A->val[i] / omega);
             cnt[(size_t)c]++;
         }
-        bdiag[(size_t)r] = leaky ? (float)(1.0 + diag[(size_t)r] / omega) : (float)(1.0 - off);
+        double target = 1.0;
+        if (leaky) {
+            double exact_off = 0.0;
+            for (int32_t i = A->row_ptr[r]; i < A->row_ptr[r + 1]; ++i)
+                if (A->col_idx[i] != r) exact_off += A->val[i];
+            target = 1.0 + (exact_off + diag[(size_t)r]) / omega;
+        }
+        bdiag[(size_t)r] = (float)(target - off);
         cnt[(size_t)r]++;  // the diagonal is always present in B
     }
     const int32_t n_slices = (n + kSlice - 1) / kSlice;

@@ -62,11 +62,15 @@ def bd_small(orc):
     return ref, info
 
 
+VARIANTS = [mjp.MJP_VARIANT_STEPWISE, mjp.MJP_VARIANT_PERSISTENT]
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("kind", ["csr", "stencil"])
-def test_birth_death_small_workload(orc, bd_small, kind):
-    say(f"[gpu] birth-death N=1000 t=1 via {kind}")
+def test_birth_death_small_workload(orc, bd_small, kind, variant):
+    say(f"[gpu] birth-death N=1000 t=1 via {kind}, variant {variant}")
     ref, oinfo = bd_small
-    plan = (csr_plan_from_model if kind == "csr" else stencil_plan)(0, [500.0, 1.0], [1000])
+    plan = (csr_plan_from_model if kind == "csr" else stencil_plan)(0, [500.0, 1.0], [1000], variant=variant)
     try:
         got, inf = gpu_expv(plan, synth.delta(1000), [1.0])
     finally:
@@ -92,11 +96,12 @@ def cascade_300(orc):
     return theta, times, ref
 
 
+@pytest.mark.parametrize("variant", [mjp.MJP_VARIANT_AUTO, mjp.MJP_VARIANT_STEPWISE])
 @pytest.mark.parametrize("kind", ["csr", "stencil"])
-def test_cascade_16_times(cascade_300, kind):
+def test_cascade_16_times(cascade_300, kind, variant):
     theta, times, ref = cascade_300
-    say(f"[gpu] cascade 300x300, 16 log-spaced times via {kind}")
-    plan = (csr_plan_from_model if kind == "csr" else stencil_plan)(1, theta, [300, 300])
+    say(f"[gpu] cascade 300x300, 16 log-spaced times via {kind}, variant {variant}")
+    plan = (csr_plan_from_model if kind == "csr" else stencil_plan)(1, theta, [300, 300], variant=variant)
     try:
         got, inf = gpu_expv(plan, synth.delta(90000), times)
     finally:
@@ -108,11 +113,13 @@ def test_cascade_16_times(cascade_300, kind):
     say(f"    worst L1 over times: {worst:.3e}")
 
 
-@pytest.mark.parametrize("n,seed", [(1, 1), (2, 2), (63, 3), (64, 4), (65, 5), (257, 6), (1000, 7), (4097, 8)])
-def test_random_generators_ragged_sizes(orc, n, seed):
-    """Random sparse generators at sizes around the 64-row slice and the
-    256-row block: ragged tails of both."""
-    say(f"[gpu] random generator n={n} seed={seed}")
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("n,seed", [(1, 1), (2, 2), (63, 3), (64, 4), (65, 5), (257, 6), (1000, 7), (4097, 8),
+                                    (33000, 10)])
+def test_random_generators_ragged_sizes(orc, n, seed, variant):
+    """Random sparse generators at sizes around the 64-row slice, the
+    256-row block and the 512-row persistent workgroup: ragged tails."""
+    say(f"[gpu] random generator n={n} seed={seed} variant {variant}")
     if n == 1:
         rp, ci, va = np.array([0, 1]), np.array([0]), np.array([0.0])
     else:
@@ -121,7 +128,7 @@ def test_random_generators_ragged_sizes(orc, n, seed):
     rho0 = synth.random_prob(n, seed + 50)
     times = [0.0, 0.05, 0.7, 2.3]
     ref = orc.expv_times(A, rho0, times)
-    plan = mjp.mjp_plan_create_csr(rp, ci, va)
+    plan = mjp.mjp_plan_create_csr(rp, ci, va, mjp.mjp_opts_default(variant=variant))
     try:
         got, inf = gpu_expv(plan, rho0, times)
     finally:
@@ -237,9 +244,10 @@ def test_leaky_truncation(orc):
         check_close(got[0], ref, f"leaky {kind}")
 
 
-def test_bitwise_deterministic():
-    say("[gpu] determinism")
-    plan = csr_plan_from_model(1, [200.0, 1.0, 0.5, 0.5], [120, 150])
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_bitwise_deterministic(variant):
+    say(f"[gpu] determinism, variant {variant}")
+    plan = csr_plan_from_model(1, [200.0, 1.0, 0.5, 0.5], [120, 150], variant=variant)
     try:
         a, _ = gpu_expv(plan, synth.delta(18000), [0.3, 2.0], info=False)
         b, _ = gpu_expv(plan, synth.delta(18000), [0.3, 2.0], info=False)
@@ -301,3 +309,18 @@ def test_batched_matches_single(orc):
     finally:
         for p in plans:
             mjp.mjp_plan_destroy(p)
+
+
+def test_persistent_refuses_wide_operator():
+    """A generator with rows wider than the register budget is refused by the
+    persistent variant (and solved by the stepwise one under AUTO)."""
+    rp, ci, va = synth.with_generator_diagonal(*synth.random_rate_graph(24, 5, dense=True, scale=1.0))
+    plan = mjp.mjp_plan_create_csr(rp, ci, va, mjp.mjp_opts_default(variant=mjp.MJP_VARIANT_PERSISTENT))
+    r0 = torch.full((24,), 1.0 / 24, device="cuda")
+    out = torch.empty((1, 24), device="cuda")
+    try:
+        with pytest.raises(mjp.MjpError) as e:
+            mjp.mjp_expv(plan, r0, [0.5], out)
+        assert e.value.status == mjp.MJP_E_UNSUPPORTED
+    finally:
+        mjp.mjp_plan_destroy(plan)

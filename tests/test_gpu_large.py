@@ -42,7 +42,7 @@ def run(plan):
 
 
 @pytest.mark.parametrize("kind", ["csr", "stencil"])
-@pytest.mark.parametrize("variant", [mjp.MJP_VARIANT_AUTO, mjp.MJP_VARIANT_STEPWISE])
+@pytest.mark.parametrize("variant", [mjp.MJP_VARIANT_PERSISTENT, mjp.MJP_VARIANT_STEPWISE])
 def test_full_size_parity(ref, kind, variant):
     say(f"[gpu] cascade {S}x{S} t=1 via {kind}, variant {variant}")
     m = mjp.make_model(1, THETA, [S, S])
