@@ -78,6 +78,7 @@ struct mjp_plan {
     int64_t sell_entries = 0;
     int64_t nnz = 0;
     int32_t max_width = 0;
+    std::vector<int32_t> slice_cmin, slice_cmax;  // column span of each slice (host)
     mjp::DevBuf slice_off;  // int32[n_slices+1]
     mjp::DevBuf col;        // int32[sell_entries]
     mjp::DevBuf val;        // float[sell_entries]
@@ -93,6 +94,8 @@ struct mjp_plan {
     mjp::DevBuf tinfo;      // per-time device parameters
     mjp::DevBuf partials;   // float per-block partial sums
     mjp::DevBuf scal;       // device scalars (masses, scale, flags)
-    mjp::DevBuf sync;       // persistent-kernel barrier words
+    mjp::DevBuf sync;       // persistent-kernel barrier words, flags, partials
+    mjp::DevBuf wait;       // persistent kernel: per-workgroup neighbour interval
+    int wait_key[3] = {0, 0, 0};  // (G, R, valid) the wait table was built for
     std::vector<char> host_stage;
 };

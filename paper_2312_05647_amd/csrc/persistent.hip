@@ -40,7 +40,9 @@ struct PersistArgs {
     float* __restrict__ out;
     const double* __restrict__ wtab;
     double* __restrict__ pmass;   // [3][G] FP64 partial masses (initial, renorm double buffer)
-    unsigned* __restrict__ bar;   // [1] arrival counter, zero at launch
+    unsigned* __restrict__ bar;   // [kBarWords] barrier words, zero at launch
+    unsigned* __restrict__ wflag; // [G * 32] per-workgroup epoch flags (one 128-byte line each), zero at launch
+    const int32_t* __restrict__ wait;  // [G][2] neighbour interval [lo, hi] or null (global barriers only)
     unsigned* __restrict__ flags;
     double* __restrict__ mass_out;  // [2]: initial mass, last measured mass
     uint64_t timeout_ticks;         // per-barrier wait limit in wall-clock ticks
@@ -60,19 +62,45 @@ __device__ __forceinline__ int logical_block(int G) {
     return (b & 7) * (G >> 3) + (b >> 3);
 }
 
-// Returns false if the sweep was aborted (a barrier timed out somewhere);
-// every workgroup then leaves the kernel.  The wait is bounded by a
-// wall-clock deadline (s_memrealtime ticks), not by a poll count.
-__device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned target, unsigned* flags,
+// Barrier words (unsigned), each on its own 256-byte line:
+//   [x*64]      arrival counter of XCD group x (x < 8)
+//   [8*64]      arrival counter of the group leaders
+//   [(9+x)*64]  release epoch as seen by group x
+constexpr int kBarWords = 17 * 64;
+
+// Two-level grid barrier.  Each workgroup arrives on its XCD group's
+// counter (release fence + relaxed add); the last arrival of a group
+// arrives on the top counter; the last of those publishes the epoch to the
+// eight group words, which each group polls with relaxed loads before one
+// acquire fence.  Every hand-off re-fences (acquire then release), so each
+// arrival's writes happen-before every reader's acquire.  Spreading the
+// arrivals over 8 counters removes most of the contention of a single
+// counter hit by every workgroup.  Returns false if the sweep was aborted
+// (a wait exceeded its wall-clock deadline somewhere); every workgroup
+// then leaves the kernel.
+__device__ __forceinline__ bool grid_barrier(unsigned* w, unsigned epoch, int g, int G, unsigned* flags,
                                              uint64_t timeout_ticks) {
     __shared__ int aborted;
     __syncthreads();
     if (threadIdx.x == 0) {
         aborted = 0;
-        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        const int per = G >> 3, grp = g / per;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const unsigned old = __hip_atomic_fetch_add(&w[grp * 64], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (old == epoch * (unsigned)per - 1u) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            const unsigned o2 = __hip_atomic_fetch_add(&w[8 * 64], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (o2 == epoch * 8u - 1u) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                for (int x = 0; x < 8; ++x)
+                    __hip_atomic_store(&w[(9 + x) * 64], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
         const uint64_t t0 = wall_clock64();
-        while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            __builtin_amdgcn_s_sleep(2);
+        while (__hip_atomic_load(&w[(9 + grp) * 64], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
+            __builtin_amdgcn_s_sleep(1);
             if (__hip_atomic_load(flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kFlagBarrierTimeout) {
                 aborted = 1;
                 break;
@@ -83,6 +111,50 @@ __device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned target, uns
                 break;
             }
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+    return aborted == 0;
+}
+
+// Neighbour synchronisation after jump k: publish "my rows of step k are
+// written" (release fence + relaxed store of k to my flag line), then wait
+// until every workgroup in my interval [lo, hi] has published k.  The
+// interval covers the workgroups whose rows I read (their y of step k must
+// be visible before I compute step k+1) and those that read my rows (they
+// must have finished reading the buffer I overwrite at step k+1).  Lanes of
+// wave 0 poll one flag each, then the wave issues one acquire fence.
+__device__ __forceinline__ bool neighbour_sync(unsigned* wflag, const int32_t* wait, unsigned k, int g,
+                                               unsigned* flags, uint64_t timeout_ticks) {
+    __shared__ int aborted;
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    if (threadIdx.x < 64) {
+        if (lane == 0) {
+            aborted = 0;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __hip_atomic_store(&wflag[g * 32], k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        const int lo = wait[2 * g], hi = wait[2 * g + 1];
+        const int h = lo + lane;
+        bool bad = false;
+        if (h <= hi && h != g) {
+            const uint64_t t0 = wall_clock64();
+            while (__hip_atomic_load(&wflag[h * 32], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < k) {
+                __builtin_amdgcn_s_sleep(1);
+                if (__hip_atomic_load(flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kFlagBarrierTimeout) {
+                    bad = true;
+                    break;
+                }
+                if (wall_clock64() - t0 > timeout_ticks) {
+                    __hip_atomic_fetch_or(flags, kFlagBarrierTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    bad = true;
+                    break;
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (bad) aborted = 1;
     }
     __syncthreads();
     return aborted == 0;
@@ -239,7 +311,7 @@ __global__ __launch_bounds__(kPThreads) void k_persistent(PersistArgs a) {
         if (threadIdx.x == 0) __hip_atomic_store(a.pmass + g, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     unsigned epoch = 1;
-    if (!grid_barrier(a.bar, epoch * (unsigned)G, a.flags, a.timeout_ticks)) return;
+    if (!grid_barrier(a.bar, epoch, g, G, a.flags, a.timeout_ticks)) return;
     const double mass0 = sum_partials(a.pmass, G, red);
     double scale = 1.0;
     double last_mass = mass0;
@@ -267,8 +339,14 @@ __global__ __launch_bounds__(kPThreads) void k_persistent(PersistArgs a) {
             if (threadIdx.x == 0) __hip_atomic_store(pm + g, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         if (k == a.Kmax) break;
-        ++epoch;
-        if (!grid_barrier(a.bar, epoch * (unsigned)G, a.flags, a.timeout_ticks)) return;
+        if (renorm || !a.wait) {
+            ++epoch;
+            if (!grid_barrier(a.bar, epoch, g, G, a.flags, a.timeout_ticks)) return;
+            if (a.wait && threadIdx.x == 0)  // keep the flags current for later neighbour waits
+                __hip_atomic_store(&a.wflag[g * 32], (unsigned)k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            if (!neighbour_sync(a.wflag, a.wait, (unsigned)k, g, a.flags, a.timeout_ticks)) return;
+        }
         if (renorm) {
             last_mass = sum_partials(pm, G, red);
             scale = (last_mass > 0.0 && mass0 > 0.0) ? mass0 / last_mass : 1.0;
@@ -287,10 +365,12 @@ using PersistFn = void (*)(PersistArgs);
 template <bool CSR>
 static PersistFn pick(int R, int W) {
 #define MJP_CASE(r, w) if (R == r && W == w) return k_persistent<r, w, CSR>;
-    if (CSR) {
+    if constexpr (CSR) {
         MJP_CASE(1, 3) MJP_CASE(2, 3) MJP_CASE(4, 3) MJP_CASE(8, 3)
         MJP_CASE(1, 5) MJP_CASE(2, 5) MJP_CASE(4, 5) MJP_CASE(8, 5)
         MJP_CASE(1, 8) MJP_CASE(2, 8) MJP_CASE(4, 8)
+        MJP_CASE(1, 12) MJP_CASE(2, 12) MJP_CASE(4, 12)
+        MJP_CASE(1, 16) MJP_CASE(2, 16)
     } else {
         MJP_CASE(1, 5) MJP_CASE(2, 5) MJP_CASE(4, 5) MJP_CASE(8, 5)
     }
@@ -311,6 +391,8 @@ bool persistent_fits(const mjp_plan* p, int max_open, PersistCfg& cfg) {
         if (p->max_width <= 3) W = 3;
         else if (p->max_width <= 5) W = 5;
         else if (p->max_width <= 8) W = 8;
+        else if (p->max_width <= 12) W = 12;
+        else if (p->max_width <= 16) W = 16;
         else return false;
     }
     int dev = 0, ncu = 0;
@@ -338,15 +420,80 @@ bool persistent_fits(const mjp_plan* p, int max_open, PersistCfg& cfg) {
     return false;
 }
 
+// Per-workgroup neighbour interval for the persistent sweep: the hull of
+// the workgroups owning the columns my rows read and of the workgroups that
+// read my rows.  Built once per (plan, G, R) and kept on the device.  If some
+// interval spans more than 64 workgroups the sweep uses global barriers only.
+static mjp_status build_wait_table(mjp_plan* p, const PersistCfg& cfg, const int32_t*& out) {
+    out = nullptr;
+    if (p->wait_key[2] == 1 && p->wait_key[0] == cfg.G && p->wait_key[1] == cfg.R) {
+        out = p->wait.as<int32_t>();
+        return MJP_OK;
+    }
+    if (p->wait_key[2] == 2 && p->wait_key[0] == cfg.G && p->wait_key[1] == cfg.R) return MJP_OK;
+    const int G = cfg.G;
+    const int64_t rows_per = (int64_t)kPWaves * cfg.R * 64;
+    const int64_t n = p->n;
+    std::vector<int32_t> lo(G), hi(G);
+    for (int g = 0; g < G; ++g) {
+        const int64_t r0 = (int64_t)g * rows_per, r1 = std::min(n, r0 + rows_per);
+        if (r0 >= n) { lo[g] = hi[g] = g; continue; }
+        int64_t cmin, cmax;
+        if (p->kind == PLAN_CSR) {
+            cmin = INT64_MAX;
+            cmax = -1;
+            for (int64_t sl = r0 / 64; sl <= (r1 - 1) / 64; ++sl) {
+                cmin = std::min<int64_t>(cmin, p->slice_cmin[(size_t)sl]);
+                cmax = std::max<int64_t>(cmax, p->slice_cmax[(size_t)sl]);
+            }
+        } else {
+            const int64_t reach = p->coef.model == MJP_MODEL_BD ? 1 : p->coef.S1;
+            cmin = std::max<int64_t>(0, r0 - reach);
+            cmax = std::min<int64_t>(n - 1, r1 - 1 + reach);
+        }
+        lo[g] = (int32_t)std::min<int64_t>(g, cmin / rows_per);
+        hi[g] = (int32_t)std::max<int64_t>(g, cmax / rows_per);
+    }
+    // add the readers of each workgroup's rows
+    std::vector<int32_t> wlo(lo), whi(hi);
+    for (int g = 0; g < G; ++g)
+        for (int h = lo[g]; h <= hi[g]; ++h) {
+            wlo[h] = std::min(wlo[h], g);
+            whi[h] = std::max(whi[h], g);
+        }
+    bool ok = true;
+    for (int g = 0; g < G && ok; ++g) ok = whi[g] - wlo[g] + 1 <= 64;
+    p->wait_key[0] = G;
+    p->wait_key[1] = cfg.R;
+    if (!ok) {
+        p->wait_key[2] = 2;
+        return MJP_OK;
+    }
+    std::vector<int32_t> tab(2 * (size_t)G);
+    for (int g = 0; g < G; ++g) {
+        tab[2 * (size_t)g] = wlo[g];
+        tab[2 * (size_t)g + 1] = whi[g];
+    }
+    mjp_status s = p->wait.reserve(sizeof(int32_t) * tab.size());
+    if (s) return s;
+    MJP_HIP(hipMemcpy(p->wait.ptr, tab.data(), sizeof(int32_t) * tab.size(), hipMemcpyHostToDevice));
+    p->wait_key[2] = 1;
+    out = p->wait.as<int32_t>();
+    return MJP_OK;
+}
+
 mjp_status launch_persistent(mjp_plan* p, const PersistCfg& cfg, const float* rho0, const AllTimes& at,
                              const std::vector<int>& slot, float* out, hipStream_t st) {
     const int64_t n = p->n;
     mjp_status s;
     if ((s = p->rho[0].reserve(sizeof(float) * n)) || (s = p->rho[1].reserve(sizeof(float) * n)) ||
-        (s = p->sync.reserve(sizeof(double) * (3 * (size_t)cfg.G + 4) + 64)))
+        (s = p->sync.reserve(sizeof(unsigned) * (kBarWords + 32 * (size_t)cfg.G) + sizeof(double) * 3 * (size_t)cfg.G)))
         return s;
-    double* pmass = p->sync.as<double>();
-    unsigned* bar = reinterpret_cast<unsigned*>(pmass + 3 * (size_t)cfg.G + 2);
+    unsigned* bar = p->sync.as<unsigned>();
+    unsigned* wflag = bar + kBarWords;
+    double* pmass = reinterpret_cast<double*>(wflag + 32 * (size_t)cfg.G);
+    const int32_t* wait = nullptr;
+    if ((s = build_wait_table(p, cfg, wait))) return s;
     double* mass_out = p->scal.as<double>() + S_MASS0;  // [S_MASS0], [S_MASSK]
     PersistArgs a{};
     a.slice_off = p->slice_off.as<int32_t>();
@@ -360,6 +507,8 @@ mjp_status launch_persistent(mjp_plan* p, const PersistCfg& cfg, const float* rh
     a.wtab = p->wtab.as<double>();
     a.pmass = pmass;
     a.bar = bar;
+    a.wflag = wflag;
+    a.wait = wait;
     a.flags = reinterpret_cast<unsigned*>(p->scal.as<double>() + S_FLAGS);
     a.mass_out = mass_out;
     a.n = n;
@@ -376,7 +525,8 @@ mjp_status launch_persistent(mjp_plan* p, const PersistCfg& cfg, const float* rh
     }
     a.at = at;
     for (int j = 0; j < at.n; ++j) a.slot[j] = slot[(size_t)j];
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, bar, 1);
+    const int nzero = kBarWords + 32 * cfg.G;
+    hipLaunchKernelGGL(k_zero_u32, dim3((nzero + 255) / 256), dim3(256), 0, st, bar, nzero);
     void* args[] = {&a};
     MJP_HIP(hipLaunchCooperativeKernel(cfg.fn, dim3(cfg.G), dim3(kPThreads), args, 0, st));
     return MJP_OK;

@@ -292,6 +292,7 @@ void mjp_plan_destroy(mjp_plan* p) {
     p->val.release();
     for (auto& b : p->rho) b.release();
     p->comp.release();
+    p->wait.release();
     p->wtab.release();
     p->tinfo.release();
     p->partials.release();
@@ -429,6 +430,13 @@ mjp_status mjp_plan_create_csr(const mjp_csr* A, const mjp_opts* opts, mjp_plan*
         }
         if (!diag_done) put(r, r, bdiag[(size_t)r]);
     }
+    p->slice_cmin.assign((size_t)n_slices, INT32_MAX);
+    p->slice_cmax.assign((size_t)n_slices, -1);
+    for (int32_t s = 0; s < n_slices; ++s)
+        for (int64_t e = slice_off[(size_t)s]; e < slice_off[(size_t)s + 1]; ++e) {
+            p->slice_cmin[(size_t)s] = std::min(p->slice_cmin[(size_t)s], hcol[(size_t)e]);
+            p->slice_cmax[(size_t)s] = std::max(p->slice_cmax[(size_t)s], hcol[(size_t)e]);
+        }
     p->n_slices = n_slices;
     p->sell_entries = total;
     p->max_width = max_w;

@@ -113,7 +113,7 @@ def test_cascade_16_times(cascade_300, kind, variant):
     say(f"    worst L1 over times: {worst:.3e}")
 
 
-@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("variant", VARIANTS + [mjp.MJP_VARIANT_AUTO])
 @pytest.mark.parametrize("n,seed", [(1, 1), (2, 2), (63, 3), (64, 4), (65, 5), (257, 6), (1000, 7), (4097, 8),
                                     (33000, 10)])
 def test_random_generators_ragged_sizes(orc, n, seed, variant):
@@ -129,7 +129,14 @@ def test_random_generators_ragged_sizes(orc, n, seed, variant):
     times = [0.0, 0.05, 0.7, 2.3]
     ref = orc.expv_times(A, rho0, times)
     plan = mjp.mjp_plan_create_csr(rp, ci, va, mjp.mjp_opts_default(variant=variant))
+    pull_width = int(np.bincount(np.asarray(ci), minlength=n).max())  # incoming entries + diagonal
     try:
+        if variant == mjp.MJP_VARIANT_PERSISTENT and pull_width > 16:
+            # more incoming entries per state than the register budget holds
+            with pytest.raises(mjp.MjpError) as e:
+                gpu_expv(plan, rho0, times)
+            assert e.value.status == mjp.MJP_E_UNSUPPORTED
+            return
         got, inf = gpu_expv(plan, rho0, times)
     finally:
         mjp.mjp_plan_destroy(plan)
