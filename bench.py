@@ -46,6 +46,46 @@ def algorithmic_bytes(kind: str, n: int, nnz: int, K: int, L: int) -> float:
     return K * per_jump + (K - L + 1) * 16 * n
 
 
+def bench_loglik(torch, mjp, reps: int = 3):
+    """Batched log-likelihoods: 4096 draws log-uniform over a decade around
+    (50, 1, 0.5, 0.5), 20 collection times 0.5..10 with 50 snapshots each,
+    per-draw grids of 50..200 per side, one persistent launch per batch."""
+    import ctypes
+    from paper_2312_05647_amd import synth
+    theta_star = [50.0, 1.0, 0.5, 0.5]
+    T = synth.even_times(20, 0.5)
+    data = synth.gillespie_cascade2(theta_star, T, 50, seed=synth.SEED_DATA)
+    recs = synth.cascade_records(data)
+    theta = synth.theta_draws(4096, theta_star, seed=synth.SEED_THETA)
+    dims = synth.grid_dims(theta, (int(data[:, 1].max()), int(data[:, 2].max())))
+    B = len(theta)
+    th = torch.as_tensor(theta, device="cuda")
+    dm = torch.as_tensor(dims, device="cuda")
+    out = torch.empty(B, dtype=torch.float64, device="cuda")
+    info = torch.zeros(B * ctypes.sizeof(mjp.mjp_info), dtype=torch.uint8, device="cuda")
+    obs = mjp.make_obs(T, recs, (0, 0))
+    stream = torch.cuda.current_stream()
+    mjp.mjp_loglik(1, th, dm, obs, out, info=info, stream=stream)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(reps):
+        mjp.mjp_loglik(1, th, dm, obs, out, stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    sec = ev0.elapsed_time(ev1) / 1e3 / reps
+    raw = info.cpu().numpy().tobytes()
+    sz = ctypes.sizeof(mjp.mjp_info)
+    K = np.array([mjp.mjp_info.from_buffer_copy(raw[i * sz:(i + 1) * sz]).K for i in range(B)], np.float64)
+    cells = float(np.sum((K + 1) * dims[:, 0] * dims[:, 1]))
+    log(f"[bench] loglik batch: {sec * 1e3:.1f} ms for {B} draws, {B / sec:.0f} loglik/s")
+    return {"workload": "4096 cascade draws, grids 50..200 per side, 20 times x 50 snapshots",
+            "loglik_per_s": B / sec, "ms_per_batch": sec * 1e3,
+            "cell_updates_per_s": cells / sec,
+            "lds_equiv_GBps": 8 * cells / sec / 1e9,
+            "finite_fraction": float(np.isfinite(out.cpu().numpy()).mean())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -139,6 +179,9 @@ def main():
                                       "ms_per_solve_device": dev2 * 1e3,
                                       "algorithmic_GBps": ab2 / dev2 / 1e9}
         log(f"[bench] {other}: {dev2 * 1e3:.3f} ms/solve")
+
+    if not args.no_extra:
+        result["loglik_batch"] = bench_loglik(torch, mjp)
 
     if not args.no_cpu:
         import oracle

@@ -1,0 +1,533 @@
+// Batched snapshot log-likelihoods (Sec. 2.1.2):
+//   loglik[b] = sum_i count_i log rho_b(T_{j_i})_{s_i}
+// for B parameter draws of a built-in model, each on its own grid, in one
+// persistent launch.
+//
+//   k_ll_prep   one thread per (item, time): Omega from theta and the grid,
+//               then the jump window [L, K] of W = Omega T by walking out from
+//               the Poisson mode with the ratio recurrence (FP64); K is the
+//               first jump whose geometric bound on the right tail is below
+//               tol/4, L the last whose bound on the left tail is; the window
+//               weight sum gives the residual lumped at K (Algorithm 2).
+//   k_ll_order  one block: items sorted by cost K_max * N, longest first.
+//   k_ll_main   one workgroup per CU pulls items from an atomic queue.  The
+//               whole state vector of an item sits in LDS; each thread owns
+//               cells m = tid + i*1024; a jump is "compute the new values of
+//               my cells into registers, barrier, write back, barrier".  Only observed states are
+//               accumulated (Kahan, FP32), one observation record per thread;
+//               the per-time weights are formed in FP64 log space by one
+//               thread per time.  The final sum of count * log p is FP64.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "internal.h"
+
+namespace mjp {
+
+mjp_status check_opts(const mjp_opts* o);
+
+constexpr int kLLThreads = 1024;
+constexpr int kLLMaxStates = 40000;            // 160,000 B of LDS
+constexpr int kLLCellsPerThread = (kLLMaxStates + kLLThreads - 1) / kLLThreads;  // 40
+constexpr int kLLMaxTimes = 64;
+constexpr int kLLRecPerThread = 4;
+constexpr int kLLMaxRecords = kLLThreads * kLLRecPerThread;
+constexpr int kLLMaxSort = 16384;
+constexpr int kLLExtraLds = 3584;             // weights, window table, reduction scratch
+
+struct LLWin {     // per (item, time)
+    double W;
+    double lastw;  // w_K + residual (lumping) or w_K
+    int32_t L, K;
+};
+
+struct LLRecord {  // per observation record
+    int32_t t, x1, x2, count;
+};
+
+struct LLArgs {
+    const double* __restrict__ theta;   // [B][4]
+    const int32_t* __restrict__ dims;   // [B][2]
+    const double* __restrict__ T;       // [n_t]
+    const LLRecord* __restrict__ rec;   // [n_rec]
+    LLWin* __restrict__ win;            // [B][n_t]
+    float* __restrict__ cost;           // [B]
+    int32_t* __restrict__ order;        // [B]
+    unsigned* __restrict__ queue;       // [1]
+    double* __restrict__ loglik;        // [B]
+    mjp_info* __restrict__ info;        // [B] or null
+    int32_t B, n_t, n_rec, model, x0_1, x0_2;
+    double omega_factor, tol;
+    int32_t k_rule, lump, renorm_every;
+    int64_t k_cap;
+};
+
+__device__ double ll_max_exit(int model, const double* th, int S1, int S2) {
+    double best = 0.0;
+    if (model == MJP_MODEL_BD) {
+        for (int n = max(0, S1 - 2); n < S1; ++n)
+            best = fmax(best, ((n + 1 < S1) ? th[0] : 0.0) + th[1] * n);
+    } else {
+        for (int n2 = max(0, S2 - 2); n2 < S2; ++n2)
+            for (int n1 = max(0, S1 - 2); n1 < S1; ++n1)
+                best = fmax(best, ((n1 + 1 < S1) ? th[0] : 0.0) + th[1] * n1 + ((n2 + 1 < S2) ? th[2] * n1 : 0.0) +
+                                      th[3] * n2);
+    }
+    return best;
+}
+
+__global__ void k_ll_prep(LLArgs a) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx == 0) *a.queue = 0u;
+    if (idx >= a.B * a.n_t) return;
+    const int b = idx / a.n_t, j = idx - b * a.n_t;
+    const double* th = a.theta + 4 * (int64_t)b;
+    const int S1 = a.dims[2 * b], S2 = a.model == MJP_MODEL_BD ? 1 : a.dims[2 * b + 1];
+    bool bad_theta = false;
+    for (int i = 0; i < (a.model == MJP_MODEL_BD ? 2 : 4); ++i) bad_theta |= !(th[i] >= 0.0) || isinf(th[i]);
+    const double omega = bad_theta ? 0.0 : a.omega_factor * ll_max_exit(a.model, th, S1, S2);
+    const double W = bad_theta ? NAN : omega * a.T[j];
+    LLWin w;
+    w.W = W;
+    if (W == 0.0) {
+        w.L = w.K = 0;
+        w.lastw = 1.0;
+    } else if (!(W > 0.0) || !(W < 1e9) || W > (double)a.k_cap) {
+        // non-finite or enormous rates: K >= floor(W) already exceeds the cap
+        w.L = 0;
+        w.K = -1;
+        w.lastw = 0.0;
+        w.W = isfinite(W) ? W : 0.0;
+    } else {
+        const double eps = a.tol / 4.0;
+        const double mode = floor(W);
+        const double wm = exp(-W + mode * log(W) - lgamma(mode + 1.0));
+        // right end
+        double k = mode, wk = wm, sum = wm;
+        int64_t K;
+        if (a.k_rule == MJP_K_PAPER) {
+            K = (int64_t)floor(W + 6.0 * sqrt(W)) + 1;
+            while (k < (double)K) { wk = wk * W / (k + 1.0); k += 1.0; sum += wk; }
+        } else {
+            const double kstop = (double)a.k_cap + 1.0;  // bounded walk: past the cap the item is rejected
+            while (k < kstop) {
+                const double wn = wk * W / (k + 1.0);
+                const double q = W / (k + 2.0);
+                if (wn / (1.0 - q) <= eps) break;
+                wk = wn;
+                k += 1.0;
+                sum += wk;
+            }
+            K = (int64_t)k;
+        }
+        const double wK = wk;
+        // left end
+        int64_t L;
+        k = mode;
+        wk = wm;
+        if (a.k_rule == MJP_K_PAPER) {
+            while (k > 0.0) { wk = wk * k / W; k -= 1.0; sum += wk; }
+            L = 0;
+        } else {
+            while (k > 0.0) {
+                const double wp = wk * k / W;
+                const double q = (k - 1.0) / W;
+                if (wp / (1.0 - q) <= eps) break;
+                wk = wp;
+                k -= 1.0;
+                sum += wk;
+            }
+            L = (int64_t)k;
+        }
+        const double resid = 1.0 - sum;
+        w.K = (int32_t)min<int64_t>(K, (int64_t)INT32_MAX / 2);
+        w.L = (int32_t)L;
+        w.lastw = wK + (a.lump ? resid : 0.0);
+        if (K > a.k_cap) w.K = -1;  // marks the item as over the cap
+    }
+    a.win[(int64_t)b * a.n_t + j] = w;
+}
+
+// cost of each item (max K over its times times its states), then a
+// longest-first ordering of the items
+__global__ void k_ll_order(LLArgs a) {
+    extern __shared__ unsigned long long keys[];
+    const int B = a.B;
+    int P = 1;
+    while (P < B) P <<= 1;
+    const bool sort = P <= kLLMaxSort;
+    for (int b = threadIdx.x; b < (sort ? P : B); b += blockDim.x) {
+        unsigned long long key = 0ull;
+        if (b < B) {
+            int32_t kmax = 0;
+            for (int j = 0; j < a.n_t; ++j) kmax = max(kmax, a.win[(int64_t)b * a.n_t + j].K);
+            const int S1 = a.dims[2 * b], S2 = a.model == MJP_MODEL_BD ? 1 : a.dims[2 * b + 1];
+            const float c = (float)(kmax + 1) * (float)S1 * (float)S2;
+            a.cost[b] = c;
+            // descending cost: invert the (non-negative) float bits
+            key = ((unsigned long long)(~__float_as_uint(c)) << 32) | (unsigned)b;
+        } else {
+            key = ~0ull;
+        }
+        if (sort) keys[b] = key;
+        else a.order[b] = b;
+    }
+    if (!sort) return;
+    __syncthreads();
+    for (int size = 2; size <= P; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = threadIdx.x; i < P; i += blockDim.x) {
+                const int jx = i ^ stride;
+                if (jx > i) {
+                    const bool up = (i & size) == 0;
+                    const unsigned long long u = keys[i], v = keys[jx];
+                    if ((u > v) == up) { keys[i] = v; keys[jx] = u; }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int b = threadIdx.x; b < B; b += blockDim.x) a.order[b] = (int32_t)(keys[b] & 0xffffffffu);
+}
+
+__device__ __forceinline__ double ll_block_sum(double v, double* scratch) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) scratch[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int i = 0; i < kLLThreads / 64; ++i) s += scratch[i];  // same order in every thread
+    __syncthreads();
+    return s;
+}
+
+__global__ __launch_bounds__(kLLThreads) void k_ll_main(LLArgs a) {
+    extern __shared__ char lds[];
+    float* rho = reinterpret_cast<float*>(lds);                                   // [kLLMaxStates]
+    double* wbuf = reinterpret_cast<double*>(lds + sizeof(float) * kLLMaxStates);  // [2][kLLMaxTimes]
+    double* scratch = wbuf + 2 * kLLMaxTimes;                                      // [16]
+    LLWin* win = reinterpret_cast<LLWin*>(scratch + 16);                           // [kLLMaxTimes]
+    __shared__ int item_sh;
+    __shared__ unsigned flag_sh;
+    const int tid = threadIdx.x;
+
+    while (true) {
+        if (tid == 0) item_sh = (int)atomicAdd(a.queue, 1u);
+        __syncthreads();
+        const int slot = item_sh;
+        __syncthreads();
+        if (slot >= a.B) break;
+        const int b = a.order[slot];
+        const double* th = a.theta + 4 * (int64_t)b;
+        const int S1 = a.dims[2 * b];
+        const int S2 = a.model == MJP_MODEL_BD ? 1 : a.dims[2 * b + 1];
+        if (tid < a.n_t) win[tid] = a.win[(int64_t)b * a.n_t + tid];
+        if (tid == 0) flag_sh = 0u;
+        __syncthreads();
+        unsigned flags = 0;
+        int32_t Kmax = 0, Lmin = INT32_MAX;
+        bool over = false;
+        for (int j = 0; j < a.n_t; ++j) {
+            const int Kj = win[j].K;
+            if (Kj < 0) over = true;
+            Kmax = max(Kmax, Kj);
+            Lmin = min(Lmin, win[j].L);
+        }
+        const int64_t N64 = (int64_t)S1 * S2;
+        double omega = a.omega_factor * ll_max_exit(a.model, th, S1, S2);
+        if (over || S1 < 1 || S2 < 1 || N64 > kLLMaxStates) {
+            if (tid == 0) {
+                a.loglik[b] = -INFINITY;
+                if (a.info) {
+                    mjp_info inf{};
+                    inf.omega = omega;
+                    inf.flags = over ? MJP_FLAG_K_LIMIT : MJP_FLAG_OUT_OF_GRID;
+                    a.info[b] = inf;
+                }
+            }
+            continue;
+        }
+        const int N = (int)N64;
+        const double om = omega > 0.0 ? omega : 1.0;
+        const float b1 = (float)(th[0] / om), d1 = (float)(th[1] / om);
+        const float b2 = a.model == MJP_MODEL_BD ? 0.f : (float)(th[2] / om);
+        const float d2 = a.model == MJP_MODEL_BD ? 0.f : (float)(th[3] / om);
+
+        // owned cells, their coordinates advance by 1024 = q*S1 + r per step
+        const int q1024 = kLLThreads / S1, r1024 = kLLThreads - q1024 * S1;
+        // rho(0) = point mass at x0 (if on the grid)
+        const int x0 = (a.x0_1 < S1 && a.x0_2 < S2) ? a.x0_1 + S1 * a.x0_2 : -1;
+        for (int m = tid; m < N; m += kLLThreads) rho[m] = (m == x0) ? 1.f : 0.f;
+
+        // observation records of this thread
+        int rm[kLLRecPerThread], rt[kLLRecPerThread];
+        float rs[kLLRecPerThread], rc[kLLRecPerThread];
+#pragma unroll
+        for (int u = 0; u < kLLRecPerThread; ++u) {
+            const int r = tid + u * kLLThreads;
+            rm[u] = -2;
+            rt[u] = 0;
+            rs[u] = 0.f;
+            rc[u] = 0.f;
+            if (r < a.n_rec) {
+                const LLRecord R = a.rec[r];
+                rt[u] = R.t;
+                rm[u] = (R.x1 < S1 && R.x2 < S2) ? R.x1 + S1 * R.x2 : -1;
+                if (rm[u] < 0) flags |= MJP_FLAG_OUT_OF_GRID;
+            }
+        }
+        if (tid < a.n_t) wbuf[tid] = 0.0;
+        __syncthreads();
+        if (x0 < 0) flags |= MJP_FLAG_OUT_OF_GRID;
+
+        const int i1_0 = tid % S1, i2_0 = tid / S1;
+        double scale = 1.0;
+        const int m_renorm = a.renorm_every;
+        double lw = 0.0, logW = 0.0;
+        if (tid < a.n_t) {
+            const double W = win[tid].W;
+            logW = W > 0.0 ? log(W) : 0.0;
+            lw = W > 0.0 ? -W : 0.0;  // log w_0
+        }
+        for (int k = 0; k <= Kmax; ++k) {
+            // weight of jump k for each time (FP64 log space, running form)
+            if (tid < a.n_t) {
+                if (k > 0) lw += logW - log((double)k);
+                const double W = win[tid].W;
+                wbuf[(k & 1) * kLLMaxTimes + tid] = W > 0.0 ? exp(lw) : (k == 0 ? 1.0 : 0.0);
+            }
+            if (k > 0) {
+                float nv[kLLCellsPerThread];
+                int i1 = i1_0, i2 = i2_0, mb = tid;
+                // opaque to the optimiser: stops it hoisting 40 cells' worth of
+                // addresses and predicates out of the jump loop (which spills)
+                asm volatile("" : "+v"(i1), "+v"(i2), "+v"(mb));
+                const float fs = (float)scale;
+                float part = 0.f;
+#pragma unroll
+                for (int c = 0; c < kLLCellsPerThread; ++c) {
+                    const int m = mb + c * kLLThreads;
+                    float y = 0.f;
+                    if (m < N) {
+                        const float f1 = (float)i1, f2 = (float)i2;
+                        // diagonal of B: 1 minus the FP64 sum of this state's FP32
+                        // exit coefficients (the same numbers its neighbours pull)
+                        const float o_b1 = (i1 + 1 < S1) ? b1 : 0.f;
+                        const float o_b2 = (i2 + 1 < S2) ? b2 * f1 : 0.f;
+                        const float diag =
+                            (float)(1.0 - (((double)o_b1 + (double)(d1 * f1)) + ((double)o_b2 + (double)(d2 * f2))));
+                        y = diag * rho[m];
+                        if (i1 > 0) y = fmaf(b1, rho[m - 1], y);
+                        if (i1 + 1 < S1) y = fmaf(d1 * (f1 + 1.f), rho[m + 1], y);
+                        if (i2 > 0) y = fmaf(b2 * f1, rho[m - S1], y);
+                        if (i2 + 1 < S2) y = fmaf(d2 * (f2 + 1.f), rho[m + S1], y);
+                        y *= fs;
+                    }
+                    nv[c] = y;
+                    part += y;
+                    i1 += r1024;
+                    i2 += q1024;
+                    if (i1 >= S1) { i1 -= S1; i2 += 1; }
+                }
+                __syncthreads();
+#pragma unroll
+                for (int c = 0; c < kLLCellsPerThread; ++c) {
+                    const int m = tid + c * kLLThreads;
+                    if (m < N) rho[m] = nv[c];
+                }
+                if (m_renorm > 0 && k % m_renorm == 0 && k < Kmax) {
+                    const double tot = ll_block_sum((double)part, scratch);  // includes the barrier
+                    scale = tot > 0.0 ? 1.0 / tot : 1.0;  // rho(0) has unit mass
+                } else {
+                    scale = 1.0;
+                    __syncthreads();
+                }
+            } else {
+                __syncthreads();
+            }
+            // accumulate observed states
+#pragma unroll
+            for (int u = 0; u < kLLRecPerThread; ++u) {
+                if (rm[u] < 0) continue;
+                const LLWin& w = win[rt[u]];
+                if (k < w.L || k > w.K) continue;
+                const float wt = (k == w.K) ? (float)w.lastw : (float)wbuf[(k & 1) * kLLMaxTimes + rt[u]];
+                const float v = rho[rm[u]];
+                if (k == w.L) {
+                    rs[u] = wt * v;
+                    rc[u] = 0.f;
+                } else {
+                    const float yk = fmaf(wt, v, -rc[u]);
+                    const float t = rs[u] + yk;
+                    rc[u] = (t - rs[u]) - yk;
+                    rs[u] = t;
+                }
+            }
+        }
+        // log-likelihood: FP64 sum of count * log p over the records
+        double ll = 0.0;
+        bool neg_inf = false;
+#pragma unroll
+        for (int u = 0; u < kLLRecPerThread; ++u) {
+            const int r = tid + u * kLLThreads;
+            if (r >= a.n_rec) continue;
+            if (rm[u] < 0) { neg_inf = true; continue; }
+            const float p = rs[u] - rc[u];
+            if (!(p > 0.f)) {
+                neg_inf = true;
+                flags |= MJP_FLAG_UNDERFLOW_OBS;
+                continue;
+            }
+            ll += (double)a.rec[r].count * log((double)p);
+        }
+        if (flags) atomicOr(&flag_sh, flags);
+        const double tot = ll_block_sum(ll, scratch);
+        const double ninf = ll_block_sum(neg_inf ? 1.0 : 0.0, scratch);
+        double mass = 0.0;
+        {
+            float part = 0.f;
+            for (int m = tid; m < N; m += kLLThreads) part += rho[m];
+            mass = ll_block_sum((double)part, scratch);
+        }
+        if (tid == 0) {
+            a.loglik[b] = ninf > 0.0 ? -INFINITY : tot;
+            if (a.info) {
+                mjp_info inf{};
+                inf.omega = omega;
+                inf.W = win[a.n_t - 1].W;
+                inf.mass_in = x0 >= 0 ? 1.0 : 0.0;
+                inf.mass_out = mass;
+                inf.K = Kmax;
+                inf.L = Lmin;
+                inf.flags = (int32_t)flag_sh;
+                a.info[b] = inf;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- host
+
+struct LLContext {
+    std::mutex mu;
+    int device = -1;
+    DevBuf rec, T, win, cost, order, queue;
+    std::vector<LLRecord> rec_host;
+    std::vector<double> T_host;
+    bool attr_set = false;
+};
+
+static LLContext& ctx_for(int dev) {
+    static LLContext ctxs[64];
+    return ctxs[dev & 63];
+}
+
+}  // namespace mjp
+
+using namespace mjp;
+
+extern "C" int32_t mjp_loglik_max_states(void) { return kLLMaxStates; }
+
+extern "C" mjp_status mjp_loglik(int32_t model, int32_t B, const double* theta_d, const int32_t* dims_d,
+                                 const mjp_obs* obs, const mjp_opts* opts, double* loglik_d, mjp_info* info_d,
+                                 mjp_stream_t stream) {
+    clear_error();
+    MJP_CHECK(model == MJP_MODEL_BD || model == MJP_MODEL_CASCADE2, MJP_E_INVALID_ARG, "unknown model %d", model);
+    MJP_CHECK(B >= 0, MJP_E_INVALID_ARG, "B must be >= 0");
+    mjp_status st = check_opts(opts);
+    if (st) return st;
+    MJP_CHECK(opts->truncation == MJP_CONSERVATIVE, MJP_E_UNSUPPORTED, "log-likelihoods use conservative truncation");
+    MJP_CHECK(obs, MJP_E_INVALID_ARG, "obs is NULL");
+    MJP_CHECK(obs->n_t >= 1 && obs->n_t <= kLLMaxTimes, MJP_E_INVALID_ARG, "n_t must be in [1, %d]", kLLMaxTimes);
+    MJP_CHECK(obs->T_h && (obs->n_obs == 0 || obs->obs_h), MJP_E_INVALID_ARG, "null observation arrays");
+    MJP_CHECK(obs->n_obs >= 0 && obs->n_obs <= kLLMaxRecords, MJP_E_INVALID_ARG, "n_obs must be in [0, %d]",
+              kLLMaxRecords);
+    MJP_CHECK(obs->x0[0] >= 0 && obs->x0[1] >= 0 && (model != MJP_MODEL_BD || obs->x0[1] == 0), MJP_E_INVALID_ARG,
+              "bad initial state");
+    for (int j = 0; j < obs->n_t; ++j)
+        MJP_CHECK(std::isfinite(obs->T_h[j]) && obs->T_h[j] >= 0.0, MJP_E_INVALID_ARG, "T[%d] must be finite, >= 0", j);
+    std::vector<LLRecord> recs((size_t)obs->n_obs);
+    for (int i = 0; i < obs->n_obs; ++i) {
+        const int32_t* r = obs->obs_h + 4 * (size_t)i;
+        MJP_CHECK(r[0] >= 0 && r[0] < obs->n_t, MJP_E_INVALID_ARG, "record %d: time index out of range", i);
+        MJP_CHECK(r[1] >= 0 && r[2] >= 0, MJP_E_INVALID_ARG, "record %d: negative state", i);
+        MJP_CHECK(model != MJP_MODEL_BD || r[2] == 0, MJP_E_INVALID_ARG, "record %d: x2 must be 0 for BD", i);
+        MJP_CHECK(r[3] >= 1, MJP_E_INVALID_ARG, "record %d: count must be >= 1", i);
+        recs[(size_t)i] = {r[0], r[1], r[2], r[3]};
+    }
+    if (B == 0) return MJP_OK;
+    MJP_CHECK(theta_d && dims_d && loglik_d, MJP_E_INVALID_ARG, "null device array");
+
+    int dev = 0;
+    MJP_HIP(hipGetDevice(&dev));
+    LLContext& C = ctx_for(dev);
+    std::lock_guard<std::mutex> lock(C.mu);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    // observation tables are uploaded only when they change, so repeated
+    // calls with the same data enqueue kernels only (graph-capturable)
+    const bool same_rec = C.device == dev && C.rec_host.size() == recs.size() &&
+                          (recs.empty() || std::memcmp(C.rec_host.data(), recs.data(), sizeof(LLRecord) * recs.size()) == 0);
+    const bool same_T = C.device == dev && C.T_host.size() == (size_t)obs->n_t &&
+                        std::memcmp(C.T_host.data(), obs->T_h, sizeof(double) * obs->n_t) == 0;
+    if (!same_rec) {
+        if ((st = C.rec.reserve(sizeof(LLRecord) * std::max<size_t>(recs.size(), 1)))) return st;
+        if (!recs.empty()) MJP_HIP(hipMemcpy(C.rec.ptr, recs.data(), sizeof(LLRecord) * recs.size(), hipMemcpyHostToDevice));
+        C.rec_host = recs;
+    }
+    if (!same_T) {
+        if ((st = C.T.reserve(sizeof(double) * obs->n_t))) return st;
+        MJP_HIP(hipMemcpy(C.T.ptr, obs->T_h, sizeof(double) * obs->n_t, hipMemcpyHostToDevice));
+        C.T_host.assign(obs->T_h, obs->T_h + obs->n_t);
+    }
+    C.device = dev;
+    if ((st = C.win.reserve(sizeof(LLWin) * (size_t)B * obs->n_t)) || (st = C.cost.reserve(sizeof(float) * B)) ||
+        (st = C.order.reserve(sizeof(int32_t) * B)) || (st = C.queue.reserve(64)))
+        return st;
+    const size_t lds = sizeof(float) * kLLMaxStates + kLLExtraLds;
+    if (!C.attr_set) {
+        MJP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_ll_main), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)lds));
+        MJP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_ll_order), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)(sizeof(unsigned long long) * kLLMaxSort)));
+        C.attr_set = true;
+    }
+    LLArgs a{};
+    a.theta = theta_d;
+    a.dims = dims_d;
+    a.T = C.T.as<double>();
+    a.rec = C.rec.as<LLRecord>();
+    a.win = C.win.as<LLWin>();
+    a.cost = C.cost.as<float>();
+    a.order = C.order.as<int32_t>();
+    a.queue = C.queue.as<unsigned>();
+    a.loglik = loglik_d;
+    a.info = info_d;
+    a.B = B;
+    a.n_t = obs->n_t;
+    a.n_rec = obs->n_obs;
+    a.model = model;
+    a.x0_1 = obs->x0[0];
+    a.x0_2 = obs->x0[1];
+    a.omega_factor = opts->omega_factor;
+    a.tol = opts->tol;
+    a.k_rule = opts->k_rule;
+    a.lump = opts->lump;
+    a.renorm_every = opts->truncation == MJP_CONSERVATIVE ? opts->renorm_every : 0;
+    a.k_cap = opts->k_cap;
+    const int nthr = B * obs->n_t;
+    hipLaunchKernelGGL(k_ll_prep, dim3((nthr + 255) / 256), dim3(256), 0, s, a);
+    int P = 1;
+    while (P < B) P <<= 1;
+    const size_t sort_lds = P <= kLLMaxSort ? sizeof(unsigned long long) * P : 0;
+    hipLaunchKernelGGL(k_ll_order, dim3(1), dim3(1024), sort_lds, s, a);
+    int ncu = 0;
+    MJP_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    const int grid = std::min(B, ncu);
+    hipLaunchKernelGGL(k_ll_main, dim3(grid), dim3(kLLThreads), lds, s, a);
+    MJP_HIP(hipGetLastError());
+    return MJP_OK;
+}

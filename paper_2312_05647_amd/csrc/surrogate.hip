@@ -30,9 +30,6 @@ mjp_status mjp_surrogate_load(const char*, mjp_surrogate** out) {
     if (out) *out = nullptr;
     return fail(MJP_E_UNSUPPORTED, "surrogate not built yet");
 }
-mjp_status mjp_loglik(int32_t, int32_t, const double*, const int32_t*, const mjp_obs*, const mjp_opts*, double*,
-                      mjp_info*, mjp_stream_t) {
-    return fail(MJP_E_UNSUPPORTED, "loglik not built yet");
-}
-int32_t mjp_loglik_max_states(void) { return 0; }
+
+
 }

@@ -189,3 +189,31 @@ def tally(pairs: np.ndarray) -> np.ndarray:
     column appended; rows sorted lexicographically."""
     uniq, counts = np.unique(pairs, axis=0, return_counts=True)
     return np.concatenate([uniq, counts[:, None]], axis=1).astype(np.int64)
+
+
+# ------------------------------------------------------------ grid sizing ---
+
+def grid_dims(theta, max_counts, lo: int = 50, hi: int = 200, t_max: float = 10.0) -> np.ndarray:
+    """Per-draw grid sides (S1, S2) for the two-species cascade.
+
+    Each side is the larger of twice the largest observed count of that
+    species (the data-driven cutoff of Sec. 3.1.1) and mean + 8 standard
+    deviations of the stationary law under the draw's rates, clamped to
+    [lo, hi].  theta: (B, 4) array of (k1, g1, k2, g2).  The stationary
+    moments of this affine network are upper bounds of the moments at
+    t <= t_max from an empty start."""
+    th = np.atleast_2d(np.asarray(theta, np.float64))
+    k1, g1, k2, g2 = th[:, 0], th[:, 1], th[:, 2], th[:, 3]
+    m1 = k1 / g1
+    c11 = m1
+    m2 = k2 * m1 / g2
+    c12 = k2 * c11 / (g1 + g2)
+    c22 = (k2 * m1 + g2 * m2 + 2 * k2 * c12) / (2 * g2)
+    s1 = np.maximum(2 * max_counts[0], np.ceil(m1 + 8 * np.sqrt(c11)))
+    s2 = np.maximum(2 * max_counts[1], np.ceil(m2 + 8 * np.sqrt(c22)))
+    return np.stack([np.clip(s1, lo, hi), np.clip(s2, lo, hi)], axis=1).astype(np.int32)
+
+
+def cascade_records(data: np.ndarray) -> np.ndarray:
+    """(time idx, n1, n2) snapshot rows -> (time idx, x1, x2, count) records."""
+    return tally(data)

@@ -153,3 +153,34 @@ def test_no_device_reports_device_error():
     if torch.cuda.is_available():
         pytest.skip("a GPU is present")
     assert status_of(mjp.mjp_plan_create_csr, *GOOD) == mjp.MJP_E_DEVICE
+
+
+def _ll_status(model=1, B=1, T=(1.0,), recs=((0, 1, 1, 1),), x0=(0, 0), **opts):
+    obs = mjp.make_obs(np.asarray(T, float), np.asarray(recs, np.int32).reshape(-1, 4), x0)
+    L = mjp.lib()
+    o = mjp.mjp_opts_default(**opts)
+    dummy = np.zeros(8)
+    return L.mjp_loglik(model, B, dummy.ctypes.data, dummy.ctypes.data, ctypes.byref(obs), ctypes.byref(o),
+                        dummy.ctypes.data, None, None)
+
+
+@pytest.mark.parametrize("kw,expect", [
+    (dict(model=5), mjp.MJP_E_INVALID_ARG),
+    (dict(B=-1), mjp.MJP_E_INVALID_ARG),
+    (dict(T=()), mjp.MJP_E_INVALID_ARG),
+    (dict(T=(1.0, -2.0)), mjp.MJP_E_INVALID_ARG),
+    (dict(recs=((3, 1, 1, 1),)), mjp.MJP_E_INVALID_ARG),       # time index out of range
+    (dict(recs=((0, 1, 1, 0),)), mjp.MJP_E_INVALID_ARG),       # count 0
+    (dict(recs=((0, -1, 1, 1),)), mjp.MJP_E_INVALID_ARG),      # negative state
+    (dict(model=0, recs=((0, 1, 1, 1),)), mjp.MJP_E_INVALID_ARG),  # BD with x2 != 0
+    (dict(x0=(-1, 0)), mjp.MJP_E_INVALID_ARG),
+    (dict(truncation=mjp.MJP_LEAKY, renorm_every=0), mjp.MJP_E_UNSUPPORTED),
+    (dict(tol=2.0), mjp.MJP_E_INVALID_ARG),
+    (dict(B=0), mjp.MJP_OK),
+])
+def test_loglik_validation(kw, expect):
+    assert _ll_status(**kw) == expect
+
+
+def test_loglik_capacity():
+    assert mjp.mjp_loglik_max_states() == 40000
