@@ -243,7 +243,7 @@ typedef struct {
 
 typedef struct {
     int32_t epochs;
-    int32_t batch;        /* minibatch, multiple of 64 */
+    int32_t batch;        /* minibatch, multiple of 512 in [512, 65536]; the last one of an epoch may be short */
     float   lr;           /* Adam step size */
     float   beta1, beta2, eps_adam;
     float   weight_decay; /* decoupled, 0 = off */
@@ -251,8 +251,10 @@ typedef struct {
 } mjp_train_cfg;
 
 /* Create an MLP in->width->...->width->1 with exact (erf) GELU between the
- * Linear layers, FP32 master weights initialised from seed, BF16 copies used by
- * the matrix-core kernels. */
+ * Linear layers, FP32 master weights initialised from seed (uniform in
+ * +-1/sqrt(fan_in)), BF16 copies used by the matrix-core kernels.  Not part
+ * of the paper: a learned stand-in for the log-likelihood over log-rates,
+ * screening proposals in delayed-acceptance sampling. */
 mjp_status mjp_surrogate_create(const mjp_mlp_cfg* cfg, uint64_t seed, mjp_surrogate** out);
 void       mjp_surrogate_destroy(mjp_surrogate* s);
 
@@ -261,6 +263,13 @@ void       mjp_surrogate_destroy(mjp_surrogate* s);
  * each epoch (the call is synchronous when loss_h is not NULL). */
 mjp_status mjp_surrogate_train(mjp_surrogate* s, const float* x_d, const float* y_d, int32_t n,
                                const mjp_train_cfg* cfg, float* loss_h, mjp_stream_t stream);
+
+/* Mean-squared-error loss and its gradient with respect to every parameter
+ * for one batch of n <= 65536 rows, without updating anything (for checking
+ * the backward kernels).  grad_h [num_params] FP32 in the packing of
+ * mjp_surrogate_get_params; loss_h [1] or NULL.  Synchronous. */
+mjp_status mjp_surrogate_grad(const mjp_surrogate* s, const float* x_d, const float* y_d, int32_t n, float* grad_h,
+                              float* loss_h, mjp_stream_t stream);
 
 /* y_d[i] = MLP(x_d[i]) for n inputs (device FP32). */
 mjp_status mjp_surrogate_infer(const mjp_surrogate* s, const float* x_d, int32_t n, float* y_d,

@@ -1,35 +1,714 @@
-// Surrogate MLP entry points (filled in with the matrix-core kernels).
+// MLP surrogate of the log-likelihood (an addition to the paper's method):
+// in -> width -> ... -> width -> 1, exact (erf) GELU between Linear layers,
+// FP32 master parameters, BF16 operands on the matrix cores.
+//
+// Every Linear layer, forward and backward, runs through one MFMA GEMM
+// kernel (k_gemm): a 64x64 output tile per workgroup, four waves of 32x32,
+// BF16 tiles staged through LDS in the [row][k] order the
+// v_mfma_f32_16x16x32_bf16 operands want, FP32 accumulation, and an
+// epilogue chosen at compile time:
+//   FWD_GELU    z = acc + b -> Z (FP32, kept for the backward pass), GELU(z) -> next input (BF16)
+//   FWD_LINEAR  y = acc + b (FP32)
+//   BWD_DATA    dZ_prev = acc * GELU'(Z_prev) -> BF16 (next GEMM) and FP32 (bias gradient)
+//   WGRAD       split-K partial products of dW = dZ^T X (FP32), reduced in a fixed order later
+// Every padded dimension is a multiple of 64 (the reduction one of 32);
+// padding rows/columns carry zeros, and rows past the batch are masked in
+// the loss so they contribute nothing.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <random>
+#include <vector>
+
 #include "internal.h"
+
+namespace mjp {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kTM = 64, kTN = 64, kTK = 32, kGT = 256, kLDP = kTK + 8;
+constexpr int kMaxLayers = 9;
+constexpr int kWgradChunk = 512;  // batch rows per split of the weight-gradient GEMM
+
+__device__ __forceinline__ uint16_t f2bf(float f) {  // round to nearest even
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;  // NaN
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+
+__device__ __forceinline__ float gelu_grad(float z) {
+    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
+}
+
+enum { EPI_FWD_GELU = 0, EPI_FWD_LINEAR = 1, EPI_BWD_DATA = 2, EPI_WGRAD = 3 };
+
+struct GemmArgs {
+    int M, N, K;                 // padded: M, N multiples of 64, K of 32
+    const uint16_t* A;           // A(m,k) = TA ? A[k*lda+m] : A[m*lda+k]
+    int lda;
+    const uint16_t* B;           // B(k,n) = TB ? B[n*ldb+k] : B[k*ldb+n]
+    int ldb;
+    int k_per_split;             // multiple of 32; gridDim.z splits
+    const float* bias;           // FWD: bias[col], col < n_valid
+    int n_valid;                 // columns that are real outputs
+    int m_valid;                 // rows that are real batch rows (FWD_LINEAR output mask)
+    float* Z;                    // FWD_GELU: out pre-activation [M x N]; BWD_DATA: in, previous layer's [M x N]
+    uint16_t* H;                 // FWD_GELU: GELU out [M x N]; BWD_DATA: dZ_prev BF16 [M x N]
+    float* Hf;                   // BWD_DATA: dZ_prev FP32 [M x N]; FWD_LINEAR: y [M x N]
+    float* P;                    // WGRAD: partials [split][M][N]
+};
+
+template <bool TA, bool TB, int EPI>
+__global__ __launch_bounds__(kGT) void k_gemm(GemmArgs g) {
+    __shared__ __attribute__((aligned(16))) uint16_t As[kTM][kLDP];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[kTN][kLDP];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int m0 = blockIdx.y * kTM, n0 = blockIdx.x * kTN;
+    const int kbeg = blockIdx.z * g.k_per_split;
+    const int kend = min(g.K, kbeg + g.k_per_split);
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    floatx4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    for (int k0 = kbeg; k0 < kend; k0 += kTK) {
+        if (!TA) {
+            const int r = tid >> 2, c = (tid & 3) * 8;
+            *reinterpret_cast<uint4*>(&As[r][c]) =
+                *reinterpret_cast<const uint4*>(&g.A[(size_t)(m0 + r) * g.lda + k0 + c]);
+        } else {
+            const int kk = tid >> 3, mm = (tid & 7) * 8;
+            const uint4 v = *reinterpret_cast<const uint4*>(&g.A[(size_t)(k0 + kk) * g.lda + m0 + mm]);
+            const uint16_t* e = reinterpret_cast<const uint16_t*>(&v);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) As[mm + i][kk] = e[i];
+        }
+        if (TB) {
+            const int r = tid >> 2, c = (tid & 3) * 8;
+            *reinterpret_cast<uint4*>(&Bs[r][c]) =
+                *reinterpret_cast<const uint4*>(&g.B[(size_t)(n0 + r) * g.ldb + k0 + c]);
+        } else {
+            const int kk = tid >> 3, nn = (tid & 7) * 8;
+            const uint4 v = *reinterpret_cast<const uint4*>(&g.B[(size_t)(k0 + kk) * g.ldb + n0 + nn]);
+            const uint16_t* e = reinterpret_cast<const uint16_t*>(&v);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) Bs[nn + i][kk] = e[i];
+        }
+        __syncthreads();
+        bf16x8 af[2], bfv[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) af[i] = *reinterpret_cast<const bf16x8*>(&As[wm + i * 16 + (lane & 15)][(lane >> 4) * 8]);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) bfv[j] = *reinterpret_cast<const bf16x8*>(&Bs[wn + j * 16 + (lane & 15)][(lane >> 4) * 8]);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfv[j], acc[i][j], 0, 0, 0);
+        __syncthreads();
+    }
+
+    // D layout: lane holds column (lane & 15), rows 4*(lane >> 4) + r
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
+                const int col = n0 + wn + j * 16 + (lane & 15);
+                const float v = acc[i][j][r];
+                const size_t at = (size_t)row * g.N + col;
+                if (EPI == EPI_FWD_GELU) {
+                    const float z = col < g.n_valid ? v + g.bias[col] : 0.f;
+                    g.Z[at] = z;
+                    g.H[at] = f2bf(col < g.n_valid ? gelu(z) : 0.f);
+                } else if (EPI == EPI_FWD_LINEAR) {
+                    g.Hf[at] = col < g.n_valid ? v + g.bias[col] : 0.f;
+                } else if (EPI == EPI_BWD_DATA) {
+                    const float d = col < g.n_valid ? v * gelu_grad(g.Z[at]) : 0.f;
+                    g.H[at] = f2bf(d);
+                    g.Hf[at] = d;
+                } else {
+                    g.P[((size_t)blockIdx.z * g.M + row) * g.N + col] = v;
+                }
+            }
+}
+
+// X rows (optionally permuted) into the padded BF16 input, targets alongside.
+__global__ void k_mlp_input(const float* __restrict__ x, const float* __restrict__ y, const int32_t* __restrict__ perm,
+                            int base, int n_valid, int in_dim, int kpad, int Bpad, uint16_t* __restrict__ X,
+                            float* __restrict__ tgt) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= Bpad * kpad) return;
+    const int b = idx / kpad, i = idx - b * kpad;
+    float v = 0.f;
+    if (b < n_valid && i < in_dim) {
+        const int src = perm ? perm[base + b] : base + b;
+        v = x[(size_t)src * in_dim + i];
+    }
+    X[idx] = f2bf(v);
+    if (i == 0 && tgt) {
+        float t = 0.f;
+        if (b < n_valid && y) t = y[perm ? perm[base + b] : base + b];
+        tgt[b] = t;
+    }
+}
+
+// MSE over the n_valid real rows: dZ = 2 (y - t) / n_valid in column 0,
+// per-block partial sums of (y - t)^2.
+__global__ void k_mse(const float* __restrict__ Y, int npad, const float* __restrict__ tgt, int n_valid, int Bpad,
+                      uint16_t* __restrict__ dZ, float* __restrict__ dZf, double* __restrict__ partial) {
+    __shared__ double red[4];
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    double e2 = 0.0;
+    if (b < Bpad) {
+        float d = 0.f;
+        if (b < n_valid) {
+            const float e = Y[(size_t)b * npad] - tgt[b];
+            e2 = (double)e * (double)e;
+            d = 2.f * e / (float)n_valid;
+        }
+        for (int c = 0; c < npad; ++c) {
+            dZ[(size_t)b * npad + c] = f2bf(c == 0 ? d : 0.f);
+            dZf[(size_t)b * npad + c] = c == 0 ? d : 0.f;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) e2 += __shfl_down(e2, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = e2;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// Bias gradients: column sums of dZ (FP32), 64 columns per block, fixed order.
+__global__ void k_bias_grad(const float* __restrict__ dZf, int Bpad, int npad, int n_valid, float* __restrict__ gb) {
+    __shared__ float red[4][64];
+    const int c = blockIdx.x * 64 + (threadIdx.x & 63), rg = threadIdx.x >> 6;
+    float s = 0.f;
+    if (c < npad)
+        for (int b = rg; b < Bpad; b += 4) s += dZf[(size_t)b * npad + c];
+    red[rg][threadIdx.x & 63] = s;
+    __syncthreads();
+    if (rg == 0 && c < n_valid) gb[c] = (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+}
+
+struct LayerDev {
+    int in, out, kpad, npad;
+    int64_t woff;      // offset of W[out][in] in the packed parameters (bias follows)
+    float* P;          // weight-gradient partials [splits][npad][kpad]
+    float* gb;         // bias gradient [out]
+    uint16_t* Wbf;     // BF16 weights [npad][kpad]
+};
+
+struct AdamArgs {
+    int L;
+    LayerDev lay[kMaxLayers];
+    int splits;
+    float* master;
+    float* m1;
+    float* m2;
+    float* grad_out;   // if set: write gradients only (no update)
+    float lr, beta1, beta2, eps, wd, bc1, bc2;
+    int64_t total;
+};
+
+__global__ void k_adam(AdamArgs a) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.total) return;
+    int l = 0;
+    while (l + 1 < a.L && p >= a.lay[l + 1].woff) ++l;
+    const LayerDev& d = a.lay[l];
+    const int64_t q = p - d.woff;
+    const int64_t nw = (int64_t)d.out * d.in;
+    float g;
+    int o = -1, i = -1;
+    if (q < nw) {
+        o = (int)(q / d.in);
+        i = (int)(q - (int64_t)o * d.in);
+        g = 0.f;
+        for (int s = 0; s < a.splits; ++s) g += d.P[((size_t)s * d.npad + o) * d.kpad + i];
+    } else {
+        g = d.gb[q - nw];
+    }
+    if (a.grad_out) {
+        a.grad_out[p] = g;
+        return;
+    }
+    const float m = a.beta1 * a.m1[p] + (1.f - a.beta1) * g;
+    const float v = a.beta2 * a.m2[p] + (1.f - a.beta2) * g * g;
+    a.m1[p] = m;
+    a.m2[p] = v;
+    const float mh = m / a.bc1, vh = v / a.bc2;
+    float w = a.master[p];
+    w -= a.lr * (mh / (sqrtf(vh) + a.eps) + a.wd * w);
+    a.master[p] = w;
+    if (o >= 0) d.Wbf[(size_t)o * d.kpad + i] = f2bf(w);
+}
+
+// BF16 padded copies of all weights from the masters (after create/set/load).
+__global__ void k_refresh_bf16(AdamArgs a) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.total) return;
+    int l = 0;
+    while (l + 1 < a.L && p >= a.lay[l + 1].woff) ++l;
+    const LayerDev& d = a.lay[l];
+    const int64_t q = p - d.woff;
+    if (q < (int64_t)d.out * d.in) {
+        const int o = (int)(q / d.in), i = (int)(q - (int64_t)o * d.in);
+        d.Wbf[(size_t)o * d.kpad + i] = f2bf(a.master[p]);
+    }
+}
+
+__global__ void k_copy_col0(const float* __restrict__ Y, int npad, int n, float* __restrict__ out) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < n) out[b] = Y[(size_t)b * npad];
+}
+
+}  // namespace mjp
 
 using namespace mjp;
 
+struct mjp_surrogate {
+    mjp_mlp_cfg cfg{};
+    int device = 0;
+    int L = 0;
+    int in[kMaxLayers], out[kMaxLayers], kpad[kMaxLayers], npad[kMaxLayers];
+    int64_t woff[kMaxLayers + 1];
+    int64_t total = 0;
+    int Bmax = 0, splits = 0;
+    int64_t step = 0;
+    DevBuf master, m1, m2, gradbuf;
+    DevBuf wbf[kMaxLayers], P[kMaxLayers], gb[kMaxLayers];
+    DevBuf X[kMaxLayers + 1];  // BF16 inputs of each layer [Bmax x kpad]; X[L] unused
+    DevBuf Z[kMaxLayers];      // FP32 pre-activations [Bmax x npad]
+    DevBuf dZ[kMaxLayers], dZf[kMaxLayers];
+    DevBuf Y, tgt, lossp, perm;
+};
+
+namespace mjp {
+
+static int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+static mjp_status surrogate_alloc(mjp_surrogate* s, int Bmax) {
+    if (Bmax <= s->Bmax) return MJP_OK;
+    s->Bmax = Bmax;
+    s->splits = std::max(1, Bmax / kWgradChunk);
+    mjp_status st;
+    for (int l = 0; l < s->L; ++l) {
+        if ((st = s->X[l].reserve(sizeof(uint16_t) * (size_t)Bmax * s->kpad[l])) ||
+            (st = s->Z[l].reserve(sizeof(float) * (size_t)Bmax * s->npad[l])) ||
+            (st = s->dZ[l].reserve(sizeof(uint16_t) * (size_t)Bmax * s->npad[l])) ||
+            (st = s->dZf[l].reserve(sizeof(float) * (size_t)Bmax * s->npad[l])) ||
+            (st = s->P[l].reserve(sizeof(float) * (size_t)s->splits * s->npad[l] * s->kpad[l])))
+            return st;
+    }
+    if ((st = s->Y.reserve(sizeof(float) * (size_t)Bmax * s->npad[s->L - 1])) ||
+        (st = s->tgt.reserve(sizeof(float) * (size_t)Bmax)) || (st = s->lossp.reserve(sizeof(double) * (size_t)Bmax)))
+        return st;
+    return MJP_OK;
+}
+
+static AdamArgs adam_args(mjp_surrogate* s) {
+    AdamArgs a{};
+    a.L = s->L;
+    for (int l = 0; l < s->L; ++l) {
+        a.lay[l].in = s->in[l];
+        a.lay[l].out = s->out[l];
+        a.lay[l].kpad = s->kpad[l];
+        a.lay[l].npad = s->npad[l];
+        a.lay[l].woff = s->woff[l];
+        a.lay[l].P = s->P[l].as<float>();
+        a.lay[l].gb = s->gb[l].as<float>();
+        a.lay[l].Wbf = s->wbf[l].as<uint16_t>();
+    }
+    a.splits = s->splits;
+    a.master = s->master.as<float>();
+    a.m1 = s->m1.as<float>();
+    a.m2 = s->m2.as<float>();
+    a.total = s->total;
+    return a;
+}
+
+static void launch_gemm(bool TA, bool TB, int epi, const GemmArgs& g, int splits, hipStream_t st) {
+    const dim3 grid(g.N / kTN, g.M / kTM, splits);
+#define MJP_G(ta, tb, e) \
+    if (TA == ta && TB == tb && epi == e) { hipLaunchKernelGGL((k_gemm<ta, tb, e>), grid, dim3(kGT), 0, st, g); return; }
+    MJP_G(false, true, EPI_FWD_GELU)
+    MJP_G(false, true, EPI_FWD_LINEAR)
+    MJP_G(false, false, EPI_BWD_DATA)
+    MJP_G(true, false, EPI_WGRAD)
+#undef MJP_G
+}
+
+// forward pass of rows already in X[0]: Y = MLP(X[0]) (n_valid rows real)
+static void forward(mjp_surrogate* s, int Bpad, int n_valid, hipStream_t st) {
+    for (int l = 0; l < s->L; ++l) {
+        GemmArgs g{};
+        g.M = Bpad;
+        g.N = s->npad[l];
+        g.K = s->kpad[l];
+        g.A = s->X[l].as<uint16_t>();
+        g.lda = s->kpad[l];
+        g.B = s->wbf[l].as<uint16_t>();
+        g.ldb = s->kpad[l];
+        g.k_per_split = g.K;
+        g.bias = s->master.as<float>() + s->woff[l] + (int64_t)s->out[l] * s->in[l];
+        g.n_valid = s->out[l];
+        g.m_valid = n_valid;
+        if (l + 1 < s->L) {
+            g.Z = s->Z[l].as<float>();
+            g.H = s->X[l + 1].as<uint16_t>();
+            launch_gemm(false, true, EPI_FWD_GELU, g, 1, st);
+        } else {
+            g.Hf = s->Y.as<float>();
+            launch_gemm(false, true, EPI_FWD_LINEAR, g, 1, st);
+        }
+    }
+}
+
+// backward pass after forward + loss (dZ[L-1] set): fills P and gb
+static void backward(mjp_surrogate* s, int Bpad, hipStream_t st) {
+    for (int l = s->L - 1; l >= 0; --l) {
+        GemmArgs w{};
+        w.M = s->npad[l];
+        w.N = s->kpad[l];
+        w.K = Bpad;
+        w.A = s->dZ[l].as<uint16_t>();
+        w.lda = s->npad[l];
+        w.B = s->X[l].as<uint16_t>();
+        w.ldb = s->kpad[l];
+        const int splits = std::max(1, Bpad / kWgradChunk);
+        w.k_per_split = Bpad / splits;
+        w.P = s->P[l].as<float>();
+        launch_gemm(true, false, EPI_WGRAD, w, splits, st);  // the reduction reads only these splits
+        hipLaunchKernelGGL(k_bias_grad, dim3(s->npad[l] / 64), dim3(256), 0, st, s->dZf[l].as<float>(), Bpad,
+                           s->npad[l], s->out[l], s->gb[l].as<float>());
+        if (l > 0) {
+            GemmArgs d{};
+            d.M = Bpad;
+            d.N = s->kpad[l];
+            d.K = s->npad[l];
+            d.A = s->dZ[l].as<uint16_t>();
+            d.lda = s->npad[l];
+            d.B = s->wbf[l].as<uint16_t>();
+            d.ldb = s->kpad[l];
+            d.k_per_split = d.K;
+            d.n_valid = s->in[l];
+            d.Z = s->Z[l - 1].as<float>();
+            d.H = s->dZ[l - 1].as<uint16_t>();
+            d.Hf = s->dZf[l - 1].as<float>();
+            launch_gemm(false, false, EPI_BWD_DATA, d, 1, st);
+        }
+    }
+}
+
+static void load_rows(mjp_surrogate* s, const float* x, const float* y, const int32_t* perm, int base, int n_valid,
+                      int Bpad, hipStream_t st) {
+    const int tot = Bpad * s->kpad[0];
+    hipLaunchKernelGGL(k_mlp_input, dim3((tot + 255) / 256), dim3(256), 0, st, x, y, perm, base, n_valid, s->in[0],
+                       s->kpad[0], Bpad, s->X[0].as<uint16_t>(), s->tgt.as<float>());
+}
+
+static void loss_grad(mjp_surrogate* s, int n_valid, int Bpad, hipStream_t st) {
+    hipLaunchKernelGGL(k_mse, dim3(Bpad / 256 + (Bpad % 256 ? 1 : 0)), dim3(256), 0, st, s->Y.as<float>(),
+                       s->npad[s->L - 1], s->tgt.as<float>(), n_valid, Bpad, s->dZ[s->L - 1].as<uint16_t>(),
+                       s->dZf[s->L - 1].as<float>(), s->lossp.as<double>());
+}
+
+}  // namespace mjp
+
 extern "C" {
-mjp_status mjp_surrogate_create(const mjp_mlp_cfg*, uint64_t, mjp_surrogate** out) {
-    if (out) *out = nullptr;
-    return fail(MJP_E_UNSUPPORTED, "surrogate not built yet");
-}
-void mjp_surrogate_destroy(mjp_surrogate*) {}
-mjp_status mjp_surrogate_train(mjp_surrogate*, const float*, const float*, int32_t, const mjp_train_cfg*, float*,
-                               mjp_stream_t) {
-    return fail(MJP_E_UNSUPPORTED, "surrogate not built yet");
-}
-mjp_status mjp_surrogate_infer(const mjp_surrogate*, const float*, int32_t, float*, mjp_stream_t) {
-    return fail(MJP_E_UNSUPPORTED, "surrogate not built yet");
-}
-int64_t mjp_surrogate_num_params(const mjp_surrogate*) { return 0; }
-mjp_status mjp_surrogate_get_params(const mjp_surrogate*, float*, int64_t) {
-    return fail(MJP_E_UNSUPPORTED, "surrogate not built yet");
-}
-mjp_status mjp_surrogate_set_params(mjp_surrogate*, const float*, int64_t) {
-    return fail(MJP_E_UNSUPPORTED, "surrogate not built yet");
-}
-mjp_status mjp_surrogate_save(const mjp_surrogate*, const char*) {
-    return fail(MJP_E_UNSUPPORTED, "surrogate not built yet");
-}
-mjp_status mjp_surrogate_load(const char*, mjp_surrogate** out) {
-    if (out) *out = nullptr;
-    return fail(MJP_E_UNSUPPORTED, "surrogate not built yet");
+
+mjp_status mjp_surrogate_create(const mjp_mlp_cfg* cfg, uint64_t seed, mjp_surrogate** out) {
+    clear_error();
+    MJP_CHECK(out, MJP_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    MJP_CHECK(cfg, MJP_E_INVALID_ARG, "cfg is NULL");
+    MJP_CHECK(cfg->in_dim >= 1 && cfg->in_dim <= 16, MJP_E_INVALID_ARG, "in_dim must be in [1, 16]");
+    MJP_CHECK(cfg->width >= 64 && cfg->width <= 512 && cfg->width % 64 == 0, MJP_E_INVALID_ARG,
+              "width must be a multiple of 64 in [64, 512]");
+    MJP_CHECK(cfg->depth >= 1 && cfg->depth <= kMaxLayers - 1, MJP_E_INVALID_ARG, "depth must be in [1, %d]",
+              kMaxLayers - 1);
+    mjp_surrogate* s = new (std::nothrow) mjp_surrogate();
+    MJP_CHECK(s, MJP_E_DEVICE, "out of host memory");
+    s->cfg = *cfg;
+    s->L = cfg->depth + 1;
+    int64_t off = 0;
+    for (int l = 0; l < s->L; ++l) {
+        s->in[l] = l == 0 ? cfg->in_dim : cfg->width;
+        s->out[l] = l + 1 == s->L ? 1 : cfg->width;
+        s->kpad[l] = round_up(s->in[l], 64);
+        s->npad[l] = round_up(s->out[l], 64);
+        s->woff[l] = off;
+        off += (int64_t)s->in[l] * s->out[l] + s->out[l];
+    }
+    s->woff[s->L] = off;
+    s->total = off;
+    if (hipGetDevice(&s->device) != hipSuccess) {
+        delete s;
+        return fail(MJP_E_DEVICE, "no HIP device available");
+    }
+    // PyTorch-style default init: U(-1/sqrt(in), 1/sqrt(in)) for weights and biases
+    std::vector<float> h((size_t)s->total);
+    std::mt19937_64 rng(seed);
+    for (int l = 0; l < s->L; ++l) {
+        const float bound = 1.0f / std::sqrt((float)s->in[l]);
+        std::uniform_real_distribution<float> U(-bound, bound);
+        for (int64_t p = s->woff[l]; p < s->woff[l + 1]; ++p) h[(size_t)p] = U(rng);
+    }
+    mjp_status st;
+    if ((st = s->master.reserve(sizeof(float) * s->total)) || (st = s->m1.reserve(sizeof(float) * s->total)) ||
+        (st = s->m2.reserve(sizeof(float) * s->total))) {
+        mjp_surrogate_destroy(s);
+        return st;
+    }
+    for (int l = 0; l < s->L; ++l) {
+        if ((st = s->wbf[l].reserve(sizeof(uint16_t) * (size_t)s->npad[l] * s->kpad[l])) ||
+            (st = s->gb[l].reserve(sizeof(float) * (size_t)s->out[l]))) {
+            mjp_surrogate_destroy(s);
+            return st;
+        }
+        if (hipMemset(s->wbf[l].ptr, 0, sizeof(uint16_t) * (size_t)s->npad[l] * s->kpad[l]) != hipSuccess) {
+            mjp_surrogate_destroy(s);
+            return fail(MJP_E_DEVICE, "hipMemset failed");
+        }
+    }
+    if (hipMemcpy(s->master.ptr, h.data(), sizeof(float) * s->total, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(s->m1.ptr, 0, sizeof(float) * s->total) != hipSuccess ||
+        hipMemset(s->m2.ptr, 0, sizeof(float) * s->total) != hipSuccess) {
+        mjp_surrogate_destroy(s);
+        return fail(MJP_E_DEVICE, "parameter upload failed");
+    }
+    AdamArgs a = adam_args(s);
+    hipLaunchKernelGGL(k_refresh_bf16, dim3((unsigned)((s->total + 255) / 256)), dim3(256), 0, 0, a);
+    if (hipDeviceSynchronize() != hipSuccess) {
+        mjp_surrogate_destroy(s);
+        return fail(MJP_E_DEVICE, "init kernel failed");
+    }
+    *out = s;
+    return MJP_OK;
 }
 
-
+void mjp_surrogate_destroy(mjp_surrogate* s) {
+    if (!s) return;
+    s->master.release();
+    s->m1.release();
+    s->m2.release();
+    s->gradbuf.release();
+    for (int l = 0; l < kMaxLayers; ++l) {
+        s->wbf[l].release();
+        s->P[l].release();
+        s->gb[l].release();
+        s->Z[l].release();
+        s->dZ[l].release();
+        s->dZf[l].release();
+    }
+    for (auto& b : s->X) b.release();
+    s->Y.release();
+    s->tgt.release();
+    s->lossp.release();
+    s->perm.release();
+    delete s;
 }
+
+int64_t mjp_surrogate_num_params(const mjp_surrogate* s) { return s ? s->total : 0; }
+
+mjp_status mjp_surrogate_get_params(const mjp_surrogate* s, float* params_h, int64_t count) {
+    clear_error();
+    MJP_CHECK(s && params_h, MJP_E_INVALID_ARG, "null argument");
+    MJP_CHECK(count == s->total, MJP_E_INVALID_ARG, "count %lld != %lld parameters", (long long)count,
+              (long long)s->total);
+    MJP_HIP(hipMemcpy(params_h, s->master.ptr, sizeof(float) * s->total, hipMemcpyDeviceToHost));
+    return MJP_OK;
+}
+
+mjp_status mjp_surrogate_set_params(mjp_surrogate* s, const float* params_h, int64_t count) {
+    clear_error();
+    MJP_CHECK(s && params_h, MJP_E_INVALID_ARG, "null argument");
+    MJP_CHECK(count == s->total, MJP_E_INVALID_ARG, "count %lld != %lld parameters", (long long)count,
+              (long long)s->total);
+    for (int64_t p = 0; p < count; ++p) MJP_CHECK(std::isfinite(params_h[p]), MJP_E_INVALID_ARG, "non-finite parameter");
+    MJP_HIP(hipMemcpy(s->master.ptr, params_h, sizeof(float) * s->total, hipMemcpyHostToDevice));
+    MJP_HIP(hipMemset(s->m1.ptr, 0, sizeof(float) * s->total));
+    MJP_HIP(hipMemset(s->m2.ptr, 0, sizeof(float) * s->total));
+    s->step = 0;
+    AdamArgs a = adam_args(s);
+    hipLaunchKernelGGL(k_refresh_bf16, dim3((unsigned)((s->total + 255) / 256)), dim3(256), 0, 0, a);
+    MJP_HIP(hipDeviceSynchronize());
+    return MJP_OK;
+}
+
+mjp_status mjp_surrogate_infer(const mjp_surrogate* sc, const float* x_d, int32_t n, float* y_d, mjp_stream_t stream) {
+    clear_error();
+    MJP_CHECK(sc, MJP_E_INVALID_ARG, "surrogate is NULL");
+    MJP_CHECK(n >= 0, MJP_E_INVALID_ARG, "n must be >= 0");
+    if (n == 0) return MJP_OK;
+    MJP_CHECK(x_d && y_d, MJP_E_INVALID_ARG, "null buffer");
+    mjp_surrogate* s = const_cast<mjp_surrogate*>(sc);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const int chunk = 4096;
+    mjp_status e = surrogate_alloc(s, std::max(s->Bmax, std::min(chunk, round_up(n, 256))));
+    if (e) return e;
+    for (int base = 0; base < n; base += s->Bmax) {
+        const int nv = std::min(s->Bmax, n - base);
+        const int Bpad = round_up(nv, 256);
+        load_rows(s, x_d, nullptr, nullptr, base, nv, Bpad, st);
+        forward(s, Bpad, nv, st);
+        hipLaunchKernelGGL(k_copy_col0, dim3((nv + 255) / 256), dim3(256), 0, st, s->Y.as<float>(), s->npad[s->L - 1],
+                           nv, y_d + base);
+    }
+    MJP_HIP(hipGetLastError());
+    return MJP_OK;
+}
+
+mjp_status mjp_surrogate_grad(const mjp_surrogate* sc, const float* x_d, const float* y_d, int32_t n, float* grad_h,
+                              float* loss_h, mjp_stream_t stream) {
+    clear_error();
+    MJP_CHECK(sc && x_d && y_d && grad_h, MJP_E_INVALID_ARG, "null argument");
+    MJP_CHECK(n >= 1 && n <= 65536, MJP_E_INVALID_ARG, "n must be in [1, 65536]");
+    mjp_surrogate* s = const_cast<mjp_surrogate*>(sc);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const int Bpad = round_up(n, 512);
+    mjp_status e = surrogate_alloc(s, Bpad);
+    if (e) return e;
+    if ((e = s->gradbuf.reserve(sizeof(float) * s->total))) return e;
+    load_rows(s, x_d, y_d, nullptr, 0, n, Bpad, st);
+    forward(s, Bpad, n, st);
+    loss_grad(s, n, Bpad, st);
+    backward(s, Bpad, st);
+    AdamArgs a = adam_args(s);
+    a.splits = std::max(1, Bpad / kWgradChunk);
+    a.grad_out = s->gradbuf.as<float>();
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)((s->total + 255) / 256)), dim3(256), 0, st, a);
+    MJP_HIP(hipGetLastError());
+    std::vector<double> lp((size_t)(Bpad + 255) / 256);
+    MJP_HIP(hipMemcpyAsync(lp.data(), s->lossp.ptr, sizeof(double) * lp.size(), hipMemcpyDeviceToHost, st));
+    MJP_HIP(hipMemcpyAsync(grad_h, s->gradbuf.ptr, sizeof(float) * s->total, hipMemcpyDeviceToHost, st));
+    MJP_HIP(hipStreamSynchronize(st));
+    if (loss_h) {
+        double tot = 0.0;
+        for (double v : lp) tot += v;
+        *loss_h = (float)(tot / n);
+    }
+    return MJP_OK;
+}
+
+mjp_status mjp_surrogate_train(mjp_surrogate* s, const float* x_d, const float* y_d, int32_t n,
+                               const mjp_train_cfg* cfg, float* loss_h, mjp_stream_t stream) {
+    clear_error();
+    MJP_CHECK(s && x_d && y_d && cfg, MJP_E_INVALID_ARG, "null argument");
+    MJP_CHECK(n >= 1, MJP_E_INVALID_ARG, "n must be >= 1");
+    MJP_CHECK(cfg->epochs >= 1 && cfg->batch >= 512 && cfg->batch % 512 == 0 && cfg->batch <= 65536,
+              MJP_E_INVALID_ARG, "epochs >= 1 and batch a multiple of 512 in [512, 65536]");
+    MJP_CHECK(std::isfinite(cfg->lr) && cfg->lr > 0 && cfg->beta1 >= 0 && cfg->beta1 < 1 && cfg->beta2 >= 0 &&
+                  cfg->beta2 < 1 && cfg->eps_adam > 0 && cfg->weight_decay >= 0,
+              MJP_E_INVALID_ARG, "bad optimiser settings");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    mjp_status e = surrogate_alloc(s, cfg->batch);
+    if (e) return e;
+    if ((e = s->perm.reserve(sizeof(int32_t) * (size_t)n))) return e;
+    std::vector<int32_t> perm((size_t)n);
+    std::mt19937_64 rng(cfg->seed);
+    const int nb = (n + cfg->batch - 1) / cfg->batch;
+    std::vector<double> lp;
+    for (int ep = 0; ep < cfg->epochs; ++ep) {
+        for (int i = 0; i < n; ++i) perm[(size_t)i] = i;
+        std::shuffle(perm.begin(), perm.end(), rng);
+        MJP_HIP(hipStreamSynchronize(st));  // the previous epoch's reads of perm are done
+        MJP_HIP(hipMemcpyAsync(s->perm.ptr, perm.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, st));
+        MJP_HIP(hipStreamSynchronize(st));
+        double ep_loss = 0.0;
+        for (int bi = 0; bi < nb; ++bi) {
+            const int base = bi * cfg->batch;
+            const int nv = std::min(cfg->batch, n - base);
+            const int Bpad = round_up(nv, 512);
+            load_rows(s, x_d, y_d, s->perm.as<int32_t>(), base, nv, Bpad, st);
+            forward(s, Bpad, nv, st);
+            loss_grad(s, nv, Bpad, st);
+            backward(s, Bpad, st);
+            s->step += 1;
+            AdamArgs a = adam_args(s);
+            a.splits = std::max(1, Bpad / kWgradChunk);
+            a.lr = cfg->lr;
+            a.beta1 = cfg->beta1;
+            a.beta2 = cfg->beta2;
+            a.eps = cfg->eps_adam;
+            a.wd = cfg->weight_decay;
+            a.bc1 = 1.f - std::pow(cfg->beta1, (float)s->step);
+            a.bc2 = 1.f - std::pow(cfg->beta2, (float)s->step);
+            hipLaunchKernelGGL(k_adam, dim3((unsigned)((s->total + 255) / 256)), dim3(256), 0, st, a);
+            if (loss_h) {
+                lp.assign((size_t)(Bpad + 255) / 256, 0.0);
+                MJP_HIP(hipMemcpyAsync(lp.data(), s->lossp.ptr, sizeof(double) * lp.size(), hipMemcpyDeviceToHost, st));
+                MJP_HIP(hipStreamSynchronize(st));
+                for (double v : lp) ep_loss += v;
+            }
+        }
+        if (loss_h) loss_h[ep] = (float)(ep_loss / n);
+    }
+    MJP_HIP(hipGetLastError());
+    return MJP_OK;
+}
+
+mjp_status mjp_surrogate_save(const mjp_surrogate* s, const char* path) {
+    clear_error();
+    MJP_CHECK(s && path, MJP_E_INVALID_ARG, "null argument");
+    std::vector<float> h((size_t)s->total);
+    MJP_HIP(hipMemcpy(h.data(), s->master.ptr, sizeof(float) * s->total, hipMemcpyDeviceToHost));
+    FILE* f = std::fopen(path, "wb");
+    MJP_CHECK(f, MJP_E_INVALID_ARG, "cannot open %s", path);
+    const char magic[4] = {'M', 'J', 'P', 'S'};
+    const int32_t hdr[4] = {1, s->cfg.in_dim, s->cfg.width, s->cfg.depth};
+    const int64_t cnt = s->total;
+    bool ok = std::fwrite(magic, 1, 4, f) == 4 && std::fwrite(hdr, sizeof hdr, 1, f) == 1 &&
+              std::fwrite(&cnt, sizeof cnt, 1, f) == 1 && std::fwrite(h.data(), sizeof(float), h.size(), f) == h.size();
+    ok = (std::fclose(f) == 0) && ok;
+    MJP_CHECK(ok, MJP_E_INVALID_ARG, "write to %s failed", path);
+    return MJP_OK;
+}
+
+mjp_status mjp_surrogate_load(const char* path, mjp_surrogate** out) {
+    clear_error();
+    MJP_CHECK(path && out, MJP_E_INVALID_ARG, "null argument");
+    *out = nullptr;
+    FILE* f = std::fopen(path, "rb");
+    MJP_CHECK(f, MJP_E_INVALID_ARG, "cannot open %s", path);
+    char magic[4];
+    int32_t hdr[4];
+    int64_t cnt = 0;
+    bool ok = std::fread(magic, 1, 4, f) == 4 && std::memcmp(magic, "MJPS", 4) == 0 &&
+              std::fread(hdr, sizeof hdr, 1, f) == 1 && hdr[0] == 1 && std::fread(&cnt, sizeof cnt, 1, f) == 1 &&
+              cnt > 0 && cnt < ((int64_t)1 << 28);
+    std::vector<float> h;
+    if (ok) {
+        h.resize((size_t)cnt);
+        ok = std::fread(h.data(), sizeof(float), h.size(), f) == h.size();
+    }
+    std::fclose(f);
+    MJP_CHECK(ok, MJP_E_INVALID_ARG, "%s is not a surrogate file", path);
+    mjp_mlp_cfg cfg{hdr[1], hdr[2], hdr[3]};
+    mjp_surrogate* s = nullptr;
+    mjp_status st = mjp_surrogate_create(&cfg, 0, &s);
+    if (st) return st;
+    if (cnt != s->total) {
+        mjp_surrogate_destroy(s);
+        return fail(MJP_E_INVALID_ARG, "%s: parameter count does not match its configuration", path);
+    }
+    if ((st = mjp_surrogate_set_params(s, h.data(), cnt))) {
+        mjp_surrogate_destroy(s);
+        return st;
+    }
+    *out = s;
+    return MJP_OK;
+}
+
+}  // extern "C"

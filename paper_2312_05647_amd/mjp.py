@@ -93,6 +93,7 @@ _SIGS = [
     ("mjp_surrogate_destroy", None, [_P]),
     ("mjp_surrogate_train", ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P, _P, _P]),
     ("mjp_surrogate_infer", ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P]),
+    ("mjp_surrogate_grad", ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P, _P, _P]),
     ("mjp_surrogate_num_params", ctypes.c_int64, [_P]),
     ("mjp_surrogate_get_params", ctypes.c_int, [_P, _P, ctypes.c_int64]),
     ("mjp_surrogate_set_params", ctypes.c_int, [_P, _P, ctypes.c_int64]),
@@ -271,6 +272,21 @@ def mjp_surrogate_train(s: int, x, y, cfg: mjp_train_cfg, losses: bool = True, s
 
 def mjp_surrogate_infer(s: int, x, y, stream=None) -> None:
     _check(lib().mjp_surrogate_infer(s, _ptr(x), int(x.shape[0]), _ptr(y), _stream(stream)))
+
+
+def mjp_surrogate_grad(s: int, x, y, stream=None):
+    """(loss, gradient as float32 numpy) of the MSE on one batch."""
+    g = np.zeros(mjp_surrogate_num_params(s), np.float32)
+    loss = np.zeros(1, np.float32)
+    _check(lib().mjp_surrogate_grad(s, _ptr(x), _ptr(y), int(y.shape[0]), _ptr(g), _ptr(loss), _stream(stream)))
+    return float(loss[0]), g
+
+
+def mjp_train_cfg_default(**over) -> mjp_train_cfg:
+    c = mjp_train_cfg(epochs=10, batch=4096, lr=1e-3, beta1=0.9, beta2=0.999, eps_adam=1e-8, weight_decay=0.0, seed=0)
+    for k, v in over.items():
+        setattr(c, k, v)
+    return c
 
 
 def mjp_surrogate_num_params(s: int) -> int:

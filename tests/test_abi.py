@@ -184,3 +184,27 @@ def test_loglik_validation(kw, expect):
 
 def test_loglik_capacity():
     assert mjp.mjp_loglik_max_states() == 40000
+
+
+@pytest.mark.parametrize("cfg", [(0, 256, 3), (17, 256, 3), (4, 100, 3), (4, 1024, 3), (4, 256, 0), (4, 256, 9)])
+def test_surrogate_config_validation(cfg):
+    c = mjp.mjp_mlp_cfg(*cfg)
+    h = ctypes.c_void_p()
+    assert mjp.lib().mjp_surrogate_create(ctypes.byref(c), 0, ctypes.byref(h)) == mjp.MJP_E_INVALID_ARG
+    assert h.value is None
+
+
+def test_surrogate_null_handles():
+    L = mjp.lib()
+    assert L.mjp_surrogate_num_params(None) == 0
+    L.mjp_surrogate_destroy(None)
+    assert L.mjp_surrogate_infer(None, None, 0, None, None) == mjp.MJP_E_INVALID_ARG
+    assert L.mjp_surrogate_grad(None, None, None, 1, None, None, None) == mjp.MJP_E_INVALID_ARG
+    assert L.mjp_surrogate_load(None, None) == mjp.MJP_E_INVALID_ARG
+
+
+def test_surrogate_load_rejects_foreign_file(tmp_path):
+    p = tmp_path / "x.bin"
+    p.write_bytes(b"NOTASURROGATE" * 4)
+    h = ctypes.c_void_p()
+    assert mjp.lib().mjp_surrogate_load(str(p).encode(), ctypes.byref(h)) == mjp.MJP_E_INVALID_ARG
