@@ -86,6 +86,61 @@ def bench_loglik(torch, mjp, reps: int = 3):
             "finite_fraction": float(np.isfinite(out.cpu().numpy()).mean())}
 
 
+def bench_da(torch, mjp, chains: int = 512, steps: int = 200, n_train: int = 16384):
+    """Delayed-acceptance vs plain Metropolis-Hastings on the cascade
+    posterior: data = 20 times 0.5..10 x 50 snapshots from rates
+    (50, 1, 0.5, 0.5), fixed grid from the data (twice the largest count or
+    the stationary mean + 8 sd), both samplers with the same chains, start
+    points and adapted proposal covariance."""
+    from paper_2312_05647_amd import sampler, synth
+    theta_star = np.array([50.0, 1.0, 0.5, 0.5])
+    T = synth.even_times(20, 0.5)
+    data = synth.gillespie_cascade2(theta_star, T, 50, seed=synth.SEED_DATA)
+    recs = synth.cascade_records(data)
+    dims = synth.grid_dims(theta_star[None, :], (int(data[:, 1].max()), int(data[:, 2].max())))[0]
+    post = sampler.Posterior(mjp.MJP_MODEL_CASCADE2, T, recs, dims)
+    gen = torch.Generator(device="cuda").manual_seed(synth.SEED_MCMC)
+    psi0 = torch.log(torch.as_tensor(np.tile(theta_star, (chains, 1)), device="cuda"))
+    t0 = time.perf_counter()
+    Z, psi = sampler.adapt_covariance(post, psi0, gen, rounds=4, steps=30)
+    t_adapt = time.perf_counter() - t0
+    pilot_m = psi.mean(0).cpu().numpy()
+    g = synth.rng(synth.SEED_MLP)
+    pts = g.multivariate_normal(pilot_m, 9.0 * Z / (2.38 / 4) ** 2, size=n_train)
+    t0 = time.perf_counter()
+    ll = torch.cat([post.loglik(torch.as_tensor(pts[i:i + 4096], device="cuda"))
+                    for i in range(0, n_train, 4096)]).cpu().numpy()
+    t_data = time.perf_counter() - t0
+    ok = np.isfinite(ll)
+    screen, losses, t_train = sampler.train_surrogate(pts[ok], ll[ok], epochs=60, batch=1024, seed=synth.SEED_MLP)
+    res = {}
+    try:
+        for name, run in (("plain_mh", lambda: sampler.run_mh(post, psi, Z, steps, gen)),
+                          ("delayed_acceptance", lambda: sampler.run_da(post, screen, psi, Z, steps, gen))):
+            smp, st = run()
+            e = sampler.ess(smp)
+            flat = smp.reshape(-1, smp.shape[2])
+            res[name] = {"ess_min": float(e.min()), "ess_per_s": float(e.min() / st.seconds),
+                         "seconds": st.seconds, "exact_evals": st.exact_evals,
+                         "accept_rate": st.accepted / (steps * chains),
+                         "stage1_accept_rate": (st.stage1_accepted / (steps * chains)) if name != "plain_mh" else None,
+                         "mean_log_theta": flat.mean(0).tolist(), "var_log_theta": flat.var(0).tolist(),
+                         "mcse_mean": np.sqrt(flat.var(0) / e).tolist()}
+            log(f"[bench] {name}: ESS/s {res[name]['ess_per_s']:.1f}, {st.seconds:.2f} s, exact {st.exact_evals}")
+    finally:
+        mjp.mjp_surrogate_destroy(screen.h)
+    mh, da = res["plain_mh"], res["delayed_acceptance"]
+    z = np.abs(np.array(mh["mean_log_theta"]) - np.array(da["mean_log_theta"])) / np.hypot(mh["mcse_mean"], da["mcse_mean"])
+    return {"workload": f"cascade posterior, grid {int(dims[0])}x{int(dims[1])}, {len(recs)} records, "
+                        f"{chains} chains x {steps} steps per sampler, surrogate 4-256-256-256-1 on {int(ok.sum())} exact evaluations",
+            "ess_per_s_ratio_da_over_mh": da["ess_per_s"] / mh["ess_per_s"],
+            "mean_diff_in_mcse_max": float(z.max()),
+            "adapt_s": t_adapt, "train_data_s": t_data, "train_s": t_train,
+            "train_loss_first_last": [float(losses[0]), float(losses[-1])],
+            "ess_per_s_da_incl_training": da["ess_min"] / (da["seconds"] + t_data + t_train),
+            **res}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -182,6 +237,7 @@ def main():
 
     if not args.no_extra:
         result["loglik_batch"] = bench_loglik(torch, mjp)
+        result["da_mcmc"] = bench_da(torch, mjp)
 
     if not args.no_cpu:
         import oracle
