@@ -46,6 +46,22 @@ def algorithmic_bytes(kind: str, n: int, nnz: int, K: int, L: int) -> float:
     return K * per_jump + (K - L + 1) * 16 * n
 
 
+def measured_traffic(kind: str):
+    """HBM bytes per launch of the solve kernel from the committed counter
+    record (profiles/), used only while the kernel source is unchanged since
+    the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_expv_{kind}_N1e6.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = os.path.join(ROOT, "paper_2312_05647_amd", "csrc", "persistent.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if rec.get("persistent_hip_sha256") != sha:
+        return None
+    return {"bytes_per_launch": rec["hbm_bytes_per_launch"], "source": os.path.relpath(path, ROOT)}
+
+
 def bench_loglik(torch, mjp, reps: int = 3):
     """Batched log-likelihoods: 4096 draws log-uniform over a decade around
     (50, 1, 0.5, 0.5), 20 collection times 0.5..10 with 50 snapshots each,
@@ -150,6 +166,10 @@ def main():
     ap.add_argument("--variant", type=int, default=0, help="0 auto, 1 stepwise, 2 persistent")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the secondary measurements")
+    ap.add_argument("--part", choices=["all", "loglik", "da"], default="all",
+                    help="run only one secondary leg (for profiling)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (reference for the byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -157,6 +177,21 @@ def main():
 
     import torch
     from paper_2312_05647_amd import mjp
+
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4, "copies": 3}))
+        return
+    if args.part == "loglik":
+        print(json.dumps({"loglik_batch": bench_loglik(torch, mjp)}))
+        return
+    if args.part == "da":
+        print(json.dumps({"da_mcmc": bench_da(torch, mjp)}))
+        return
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -201,6 +236,7 @@ def main():
     log(f"[bench] {args.kind}: {dev_s * 1e3:.3f} ms/solve (device events), wall {wall / args.steps * 1e3:.3f} ms, "
         f"K={K} L={L}, {achieved:.0f} GB/s algorithmic")
 
+    traffic = measured_traffic(args.kind)
     result = {
         "metric": METRIC,
         "value": 1.0 / (wall / args.steps),
@@ -219,7 +255,9 @@ def main():
                    "operator": args.kind, "variant": args.variant, "K": K, "L": L,
                    "omega": info["omega"], "global_batch": 1, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic["bytes_per_launch"] if traffic else None,
+                     "traffic_source": traffic["source"] if traffic else "no counter record for the current kernel source",
                      "kernel": "one solve (all K jumps, weighted accumulation, lumping)",
                      "algorithmic_bytes_per_solve": ab, "ms_per_solve_device": dev_s * 1e3},
     }
