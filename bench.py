@@ -102,12 +102,14 @@ def bench_loglik(torch, mjp, reps: int = 3):
             "finite_fraction": float(np.isfinite(out.cpu().numpy()).mean())}
 
 
-def bench_da(torch, mjp, chains: int = 512, steps: int = 200, n_train: int = 16384):
+def bench_da(torch, mjp, chains: int = 2048, steps: int = 100, burn: int = 20, n_train: int = 16384):
     """Delayed-acceptance vs plain Metropolis-Hastings on the cascade
     posterior: data = 20 times 0.5..10 x 50 snapshots from rates
     (50, 1, 0.5, 0.5), fixed grid from the data (twice the largest count or
-    the stationary mean + 8 sd), both samplers with the same chains, start
-    points and adapted proposal covariance."""
+    the stationary mean + 8 sd).  The proposal covariance is adapted on 256
+    chains (SI scheme) and frozen at the 2.38^2/d random-walk scaling; both
+    samplers then start from the same burnt-in states of `chains` chains and
+    use the same covariance."""
     from paper_2312_05647_amd import sampler, synth
     theta_star = np.array([50.0, 1.0, 0.5, 0.5])
     T = synth.even_times(20, 0.5)
@@ -116,13 +118,18 @@ def bench_da(torch, mjp, chains: int = 512, steps: int = 200, n_train: int = 163
     dims = synth.grid_dims(theta_star[None, :], (int(data[:, 1].max()), int(data[:, 2].max())))[0]
     post = sampler.Posterior(mjp.MJP_MODEL_CASCADE2, T, recs, dims)
     gen = torch.Generator(device="cuda").manual_seed(synth.SEED_MCMC)
-    psi0 = torch.log(torch.as_tensor(np.tile(theta_star, (chains, 1)), device="cuda"))
+    psi0 = torch.log(torch.as_tensor(np.tile(theta_star, (256, 1)), device="cuda"))
     t0 = time.perf_counter()
-    Z, psi = sampler.adapt_covariance(post, psi0, gen, rounds=4, steps=30)
+    Z, psi = sampler.adapt_covariance(post, psi0, gen, rounds=4, steps=30, final_scale="optimal")
+    psi = psi.repeat(chains // 256, 1)
+    _, _ = sampler.run_mh(post, psi, Z, 1, gen)  # warm the batch size
+    smp, _ = sampler.run_mh(post, psi, Z, burn, gen)
+    psi = torch.as_tensor(smp[-1], device="cuda")
     t_adapt = time.perf_counter() - t0
     pilot_m = psi.mean(0).cpu().numpy()
+    cov = np.cov(smp.reshape(-1, 4).T)
     g = synth.rng(synth.SEED_MLP)
-    pts = g.multivariate_normal(pilot_m, 9.0 * Z / (2.38 / 4) ** 2, size=n_train)
+    pts = g.multivariate_normal(pilot_m, 9.0 * cov, size=n_train)
     t0 = time.perf_counter()
     ll = torch.cat([post.loglik(torch.as_tensor(pts[i:i + 4096], device="cuda"))
                     for i in range(0, n_train, 4096)]).cpu().numpy()

@@ -223,7 +223,11 @@ typedef struct {
  *   loglik_d [B] FP64 device
  *   info_d   [B] device or NULL (omega, W of the last time, K, L of the last
  *            time, flags, mass_out = final mass of the iterate)
- * Asynchronous; safe to capture in a hipGraph. */
+ * Asynchronous.  The first call with new observations uploads them
+ * (synchronously) and a larger B grows per-device work buffers; a call after
+ * one with the same observations and at least this B only enqueues kernels,
+ * so it may be captured in a hipGraph.  A later call that grows the buffers
+ * invalidates such a graph. */
 mjp_status mjp_loglik(int32_t model, int32_t B, const double* theta_d, const int32_t* dims_d,
                       const mjp_obs* obs, const mjp_opts* opts, double* loglik_d,
                       mjp_info* info_d, mjp_stream_t stream);

@@ -197,19 +197,26 @@ def run_da(post: Posterior, screen, psi0, Z, steps: int, gen, draws=None):
 
 
 def adapt_covariance(post: Posterior, psi0, gen, rounds: int = 6, steps: int = 40, z0: float = 1e-4,
-                     eps: float = 1e-12):
+                     eps: float = 1e-12, final_scale: str = "si"):
     """SI adaptive scheme: Z = (2.38 / eta)^2 [cov(recent samples) + eps I],
     the covariance pooled over all chains' last `steps` samples, `rounds`
-    times.  Returns (Z, last states)."""
+    times.  final_scale "si" returns that Z; "optimal" returns the same
+    pooled covariance scaled by 2.38^2 / eta (the random-walk scaling of
+    Gelman, Roberts and Gilks), which the SI's constant is 1/eta of.
+    Returns (Z, last states)."""
     import torch
     C, d = psi0.shape
     Z = z0 * np.eye(d)
     psi = psi0
+    cov = None
     for _ in range(rounds):
         s, st = run_mh(post, psi, Z, steps, gen)
         flat = s.reshape(-1, d)
-        Z = (2.38 / d) ** 2 * (np.cov(flat.T) + eps * np.eye(d))
+        cov = np.cov(flat.T) + eps * np.eye(d)
+        Z = (2.38 / d) ** 2 * cov
         psi = torch.as_tensor(s[-1], device="cuda")
+    if final_scale == "optimal":
+        Z = 2.38 ** 2 / d * cov
     return Z, psi
 
 

@@ -176,3 +176,30 @@ def test_full_batch_sampled_items(orc, full_case):
         if pmin < 1e-12:
             continue
         assert abs(got[b] - ll) <= tol, (b, got[b], ll, tol)
+
+
+def test_graph_capture_replay(small_case):
+    """mjp_loglik enqueues kernels only (after its first call uploads the
+    observation tables), so it can be captured in a graph and replayed; every
+    replay, with eager work and synchronisation between replays, must equal
+    the eager result."""
+    theta, dims, T, recs = small_case
+    eager = run_loglik(1, theta, dims, T, recs)
+    B = len(theta)
+    th = torch.as_tensor(theta, device="cuda")
+    dm = torch.as_tensor(np.asarray(dims, np.int32), device="cuda")
+    out = torch.zeros(B, dtype=torch.float64, device="cuda")
+    obs = mjp.make_obs(T, recs, (0, 0))
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        mjp.mjp_loglik(1, th, dm, obs, out)   # same shapes: no growth inside the capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        mjp.mjp_loglik(1, th, dm, obs, out, stream=s)
+    for rep in range(4):
+        out.zero_()
+        _ = (th * 2).sum()               # unrelated eager work between replays
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), eager), rep
