@@ -70,7 +70,14 @@ enum { MJP_CONSERVATIVE = 0, /* transitions that would leave the state space are
 
 enum { MJP_VARIANT_AUTO = 0,       /* the plan picks the launch strategy */
        MJP_VARIANT_STEPWISE = 1,   /* one kernel per jump, launched in a loop */
-       MJP_VARIANT_PERSISTENT = 2  /* all K jumps in one cooperative launch */ };
+       MJP_VARIANT_PERSISTENT = 2, /* all K jumps in one cooperative launch; the
+                                      iterate moves between XCDs through
+                                      device-scope loads and stores */
+       MJP_VARIANT_PERSISTENT_FENCED = 3 /* the same launch, synchronised with
+                                      agent-scope release/acquire fences (L2
+                                      write-back and invalidate per workgroup
+                                      and jump): slower, bit-identical; kept
+                                      as the reference protocol */ };
 
 typedef struct {
     double  omega_factor;  /* Omega = omega_factor * max|a_nn|; must be > 1 (Eq. B_def: 1.1) */

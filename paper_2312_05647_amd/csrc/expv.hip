@@ -339,7 +339,8 @@ static mjp_status run_sweep(mjp_plan* p, const float* rho0, const std::vector<Sw
     }
 
     PersistCfg cfg;
-    if (p->opts.variant != MJP_VARIANT_STEPWISE && persistent_fits(p, max_open, cfg)) {
+    const bool coh = p->opts.variant != MJP_VARIANT_PERSISTENT_FENCED;
+    if (p->opts.variant != MJP_VARIANT_STEPWISE && persistent_fits(p, max_open, coh, cfg)) {
         // colour the windows (sorted by start) onto the register slots
         std::vector<int> slot(nt, -1);
         std::vector<int32_t> busy_until;  // last jump of each slot's current window
@@ -353,7 +354,7 @@ static mjp_status run_sweep(mjp_plan* p, const float* rho0, const std::vector<Sw
         }
         if ((s = launch_persistent(p, cfg, rho0, at, slot, out, st))) return s;
     } else {
-        if (p->opts.variant == MJP_VARIANT_PERSISTENT)
+        if (p->opts.variant == MJP_VARIANT_PERSISTENT || p->opts.variant == MJP_VARIANT_PERSISTENT_FENCED)
             return fail(MJP_E_UNSUPPORTED, "the persistent kernel cannot hold this operator (width %d, %d open windows)",
                         p->max_width, max_open);
         // compensation rows are handed out to times while their window is open

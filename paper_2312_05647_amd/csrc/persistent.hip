@@ -9,13 +9,33 @@
 // For a stencil plan each thread keeps its rows' five coefficients in
 // registers.  The Kahan pairs (s, c) of the open collection windows live in
 // registers too.  Per jump only the iterate moves: each thread gathers x at
-// its columns (L2/MALL) and writes its rows of y.
+// its columns and writes its rows of y.
 //
-// Jumps are separated by a grid barrier: a monotone arrival counter updated
-// with an agent-scope release and polled with agent-scope acquire loads
-// (the acquire/release pair makes the y written before the barrier visible
-// to every XCD after it).  Every poll loop is bounded: on timeout the
-// workgroup raises a flag and leaves the loop, so the kernel always ends.
+// Jumps are separated by neighbour synchronisation (per-workgroup epoch
+// flags) or, every renorm_every jumps and for operators without a narrow
+// interval, a two-level grid barrier.  Every poll loop is bounded: on
+// timeout the workgroup raises a flag and leaves the loop, so the kernel
+// always ends.
+//
+// Two memory protocols make y of jump k visible to every XCD before jump k+1
+// reads it:
+//  * COH (default): the iterate is read and written only with device-scope
+//    (agent) relaxed atomic loads and stores, which the hardware performs at
+//    the device coherence point (the sc1 cache policy), never leaving a
+//    dirty or stale copy in an XCD's L2.  Each wave waits for its own
+//    stores to complete (s_waitcnt vmcnt(0)) before the workgroup publishes
+//    its flag; a reader issues its loads only after it has seen the flag.
+//    This keeps exactly the two hardware facts that the compiler's own
+//    agent-scope release/acquire mapping rests on (a device-scope store is
+//    visible device-wide once its counter has drained; a device-scope load
+//    reads the coherent value), and drops the per-workgroup L2 write-back
+//    and invalidate, which only plain (non-atomic) accesses need.  Those two
+//    cache operations, issued by all ~32 workgroups of an XCD every jump,
+//    cost more than the jump's data movement.
+//  * fenced: plain loads and stores of the iterate, published with the
+//    compiler's agent-scope release fence and consumed after an agent-scope
+//    acquire fence (L2 write-back / invalidate).  Kept as the reference
+//    protocol; both protocols give bit-identical results.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -62,6 +82,36 @@ __device__ __forceinline__ int logical_block(int G) {
     return (b & 7) * (G >> 3) + (b >> 3);
 }
 
+// Iterate accesses under either protocol.
+template <bool COH>
+__device__ __forceinline__ float ld_iter(const float* p) {
+    if constexpr (COH) return __hip_atomic_load(const_cast<float*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else return *p;
+}
+template <bool COH>
+__device__ __forceinline__ void st_iter(float* p, float v) {
+    if constexpr (COH) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else *p = v;
+}
+
+// Publishing side of a synchronisation point.  COH: every wave waits until
+// its own loads and stores have completed (device-scope stores are then
+// visible to every XCD, and the loads of the buffer about to be overwritten
+// have returned).  Fenced: the release fence is issued by the publishing
+// thread after the workgroup barrier.
+template <bool COH>
+__device__ __forceinline__ void drain_wave() {
+    if constexpr (COH) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+template <bool COH>
+__device__ __forceinline__ void release_agent() {
+    if constexpr (!COH) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+}
+template <bool COH>
+__device__ __forceinline__ void acquire_agent() {
+    if constexpr (!COH) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
 // Barrier words (unsigned), each on its own 256-byte line:
 //   [x*64]      arrival counter of XCD group x (x < 8)
 //   [8*64]      arrival counter of the group leaders
@@ -69,31 +119,34 @@ __device__ __forceinline__ int logical_block(int G) {
 constexpr int kBarWords = 17 * 64;
 
 // Two-level grid barrier.  Each workgroup arrives on its XCD group's
-// counter (release fence + relaxed add); the last arrival of a group
-// arrives on the top counter; the last of those publishes the epoch to the
-// eight group words, which each group polls with relaxed loads before one
-// acquire fence.  Every hand-off re-fences (acquire then release), so each
-// arrival's writes happen-before every reader's acquire.  Spreading the
-// arrivals over 8 counters removes most of the contention of a single
-// counter hit by every workgroup.  Returns false if the sweep was aborted
-// (a wait exceeded its wall-clock deadline somewhere); every workgroup
-// then leaves the kernel.
+// counter (relaxed add after the publishing step); the last arrival of a
+// group arrives on the top counter; the last of those publishes the epoch to
+// the eight group words, which each group polls with relaxed loads.  In the
+// fenced protocol every hand-off re-fences (acquire then release), so each
+// arrival's writes happen-before every reader's acquire; in the COH protocol
+// every arrival's device-scope writes were complete before it arrived, so
+// the hand-offs need no fences.  Spreading the arrivals over 8 counters
+// removes most of the contention of a single counter hit by every
+// workgroup.  Returns false if the sweep was aborted (a wait exceeded its
+// wall-clock deadline somewhere); every workgroup then leaves the kernel.
+template <bool COH>
 __device__ __forceinline__ bool grid_barrier(unsigned* w, unsigned epoch, int g, int G, unsigned* flags,
                                              uint64_t timeout_ticks) {
     __shared__ int aborted;
+    drain_wave<COH>();
     __syncthreads();
     if (threadIdx.x == 0) {
         aborted = 0;
         const int per = G >> 3, grp = g / per;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        release_agent<COH>();
         const unsigned old = __hip_atomic_fetch_add(&w[grp * 64], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (old == epoch * (unsigned)per - 1u) {
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            acquire_agent<COH>();
+            release_agent<COH>();
             const unsigned o2 = __hip_atomic_fetch_add(&w[8 * 64], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (o2 == epoch * 8u - 1u) {
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                acquire_agent<COH>();
+                release_agent<COH>();
                 for (int x = 0; x < 8; ++x)
                     __hip_atomic_store(&w[(9 + x) * 64], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
@@ -111,28 +164,31 @@ __device__ __forceinline__ bool grid_barrier(unsigned* w, unsigned epoch, int g,
                 break;
             }
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        acquire_agent<COH>();
     }
     __syncthreads();
     return aborted == 0;
 }
 
 // Neighbour synchronisation after jump k: publish "my rows of step k are
-// written" (release fence + relaxed store of k to my flag line), then wait
+// written" (publishing step + relaxed store of k to my flag line), then wait
 // until every workgroup in my interval [lo, hi] has published k.  The
 // interval covers the workgroups whose rows I read (their y of step k must
 // be visible before I compute step k+1) and those that read my rows (they
 // must have finished reading the buffer I overwrite at step k+1).  Lanes of
-// wave 0 poll one flag each, then the wave issues one acquire fence.
+// wave 0 poll one flag each; in the fenced protocol the wave then issues one
+// acquire fence.
+template <bool COH>
 __device__ __forceinline__ bool neighbour_sync(unsigned* wflag, const int32_t* wait, unsigned k, int g,
                                                unsigned* flags, uint64_t timeout_ticks) {
     __shared__ int aborted;
+    drain_wave<COH>();
     __syncthreads();
     const int lane = threadIdx.x & 63;
     if (threadIdx.x < 64) {
         if (lane == 0) {
             aborted = 0;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            release_agent<COH>();
             __hip_atomic_store(&wflag[g * 32], k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         const int lo = wait[2 * g], hi = wait[2 * g + 1];
@@ -153,7 +209,7 @@ __device__ __forceinline__ bool neighbour_sync(unsigned* wflag, const int32_t* w
                 }
             }
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        acquire_agent<COH>();
         if (bad) aborted = 1;
     }
     __syncthreads();
@@ -185,7 +241,7 @@ __device__ __forceinline__ double sum_partials(const double* p, int G, double* r
     return s;
 }
 
-template <int R, int W, bool CSR>
+template <int R, int W, bool CSR, bool COH>
 __global__ __launch_bounds__(kPThreads) void k_persistent(PersistArgs a) {
     __shared__ double red[kPWaves + 1];
     const int G = a.G;
@@ -311,7 +367,7 @@ __global__ __launch_bounds__(kPThreads) void k_persistent(PersistArgs a) {
         if (threadIdx.x == 0) __hip_atomic_store(a.pmass + g, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     unsigned epoch = 1;
-    if (!grid_barrier(a.bar, epoch, g, G, a.flags, a.timeout_ticks)) return;
+    if (!grid_barrier<COH>(a.bar, epoch, g, G, a.flags, a.timeout_ticks)) return;
     const double mass0 = sum_partials(a.pmass, G, red);
     double scale = 1.0;
     double last_mass = mass0;
@@ -322,15 +378,24 @@ __global__ __launch_bounds__(kPThreads) void k_persistent(PersistArgs a) {
         float* __restrict__ y = (k & 1) ? a.buf1 : a.buf0;
         const float fs = (float)scale;
         double part = 0.0;
+        // all R*W gathers first, in one basic block, so they are in flight
+        // together; the predicated stores come after every load was issued
+        float xv[R][W];
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+#pragma unroll
+            for (int j = 0; j < W; ++j) xv[i][j] = ld_iter<COH>(x + cidx[i][j]);
 #pragma unroll
         for (int i = 0; i < R; ++i) {
             float acc = 0.f;
 #pragma unroll
-            for (int j = 0; j < W; ++j) acc = fmaf(cval[i][j], x[cidx[i][j]], acc);
+            for (int j = 0; j < W; ++j) acc = fmaf(cval[i][j], xv[i][j], acc);
             yv[i] = fs * acc;
-            if (live[i]) y[row[i]] = yv[i];
             part += (double)yv[i];
         }
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+            if (live[i]) st_iter<COH>(y + row[i], yv[i]);
         accumulate(k);
         const bool renorm = m > 0 && (k % m == 0) && k < a.Kmax;
         double* pm = a.pmass + (size_t)G * (1 + ((k / (m > 0 ? m : 1)) & 1));
@@ -341,11 +406,11 @@ __global__ __launch_bounds__(kPThreads) void k_persistent(PersistArgs a) {
         if (k == a.Kmax) break;
         if (renorm || !a.wait) {
             ++epoch;
-            if (!grid_barrier(a.bar, epoch, g, G, a.flags, a.timeout_ticks)) return;
+            if (!grid_barrier<COH>(a.bar, epoch, g, G, a.flags, a.timeout_ticks)) return;
             if (a.wait && threadIdx.x == 0)  // keep the flags current for later neighbour waits
                 __hip_atomic_store(&a.wflag[g * 32], (unsigned)k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
-            if (!neighbour_sync(a.wflag, a.wait, (unsigned)k, g, a.flags, a.timeout_ticks)) return;
+            if (!neighbour_sync<COH>(a.wflag, a.wait, (unsigned)k, g, a.flags, a.timeout_ticks)) return;
         }
         if (renorm) {
             last_mass = sum_partials(pm, G, red);
@@ -362,9 +427,9 @@ __global__ __launch_bounds__(kPThreads) void k_persistent(PersistArgs a) {
 
 using PersistFn = void (*)(PersistArgs);
 
-template <bool CSR>
+template <bool CSR, bool COH>
 static PersistFn pick(int R, int W) {
-#define MJP_CASE(r, w) if (R == r && W == w) return k_persistent<r, w, CSR>;
+#define MJP_CASE(r, w) if (R == r && W == w) return k_persistent<r, w, CSR, COH>;
     if constexpr (CSR) {
         MJP_CASE(1, 3) MJP_CASE(2, 3) MJP_CASE(4, 3) MJP_CASE(8, 3)
         MJP_CASE(1, 5) MJP_CASE(2, 5) MJP_CASE(4, 5) MJP_CASE(8, 5)
@@ -384,7 +449,7 @@ __global__ void k_zero_u32(unsigned* p, int n) {
 }
 
 // Decide whether the persistent kernel can run this sweep; fills cfg.
-bool persistent_fits(const mjp_plan* p, int max_open, PersistCfg& cfg) {
+bool persistent_fits(const mjp_plan* p, int max_open, bool coh, PersistCfg& cfg) {
     if (max_open > kPSlots) return false;
     int W = 5;
     if (p->kind == PLAN_CSR) {
@@ -402,7 +467,8 @@ bool persistent_fits(const mjp_plan* p, int max_open, PersistCfg& cfg) {
     if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return false;
     const int64_t slices = (p->n + 63) / 64;
     for (int R : {1, 2, 4, 8}) {
-        PersistFn f = p->kind == PLAN_CSR ? pick<true>(R, W) : pick<false>(R, W);
+        PersistFn f = p->kind == PLAN_CSR ? (coh ? pick<true, true>(R, W) : pick<true, false>(R, W))
+                                          : (coh ? pick<false, true>(R, W) : pick<false, false>(R, W));
         if (!f) continue;
         int per_cu = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(f), kPThreads, 0) !=
@@ -414,6 +480,7 @@ bool persistent_fits(const mjp_plan* p, int max_open, PersistCfg& cfg) {
         cfg.R = R;
         cfg.W = W;
         cfg.G = (int)G;
+        cfg.coh = coh;
         cfg.fn = reinterpret_cast<const void*>(f);
         return true;
     }

@@ -62,7 +62,8 @@ def bd_small(orc):
     return ref, info
 
 
-VARIANTS = [mjp.MJP_VARIANT_STEPWISE, mjp.MJP_VARIANT_PERSISTENT]
+VARIANTS = [mjp.MJP_VARIANT_STEPWISE, mjp.MJP_VARIANT_PERSISTENT, mjp.MJP_VARIANT_PERSISTENT_FENCED]
+PERSISTENT = (mjp.MJP_VARIANT_PERSISTENT, mjp.MJP_VARIANT_PERSISTENT_FENCED)
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
@@ -131,7 +132,7 @@ def test_random_generators_ragged_sizes(orc, n, seed, variant):
     plan = mjp.mjp_plan_create_csr(rp, ci, va, mjp.mjp_opts_default(variant=variant))
     pull_width = int(np.bincount(np.asarray(ci), minlength=n).max())  # incoming entries + diagonal
     try:
-        if variant == mjp.MJP_VARIANT_PERSISTENT and pull_width > 16:
+        if variant in PERSISTENT and pull_width > 16:
             # more incoming entries per state than the register budget holds
             with pytest.raises(mjp.MjpError) as e:
                 gpu_expv(plan, rho0, times)
@@ -331,3 +332,48 @@ def test_persistent_refuses_wide_operator():
         assert e.value.status == mjp.MJP_E_UNSUPPORTED
     finally:
         mjp.mjp_plan_destroy(plan)
+
+
+def _protocol_case(name):
+    """(plan factory, rho0, times) for the protocol comparison."""
+    if name == "cascade-csr-90000":
+        return (lambda **o: csr_plan_from_model(1, [60.0, 1.0, 0.7, 0.4], [300, 300], **o),
+                synth.delta(90000), [0.05, 2.0, 2.1, 2.2, 2.3])  # up to 4 windows open together
+    if name == "cascade-stencil-90000":
+        return (lambda **o: stencil_plan(1, [60.0, 1.0, 0.7, 0.4], [300, 300], **o),
+                synth.random_prob(90000, 3), [0.4, 2.5])
+    if name == "bd-stencil-1000":
+        return (lambda **o: stencil_plan(0, [500.0, 1.0], [1000], **o), synth.delta(1000), [1.0])
+    if name == "random-csr-33000":
+        rp, ci, va = synth.with_generator_diagonal(*synth.random_rate_graph(33000, 10, degree=4, scale=3.0))
+        return (lambda **o: mjp.mjp_plan_create_csr(rp, ci, va, mjp.mjp_opts_default(**o)),
+                synth.random_prob(33000, 60), [0.05, 0.7, 2.3])
+    if name == "banded-csr-200001":
+        # a ragged size (not a multiple of the 4096-row workgroup) with narrow
+        # neighbour intervals: the flags path, not the global barrier
+        m = mjp.make_model(1, [30.0, 1.0, 1.0, 0.5], [401, 499])
+        rp, ci, va = mjp.mjp_model_csr(m)
+        return (lambda **o: mjp.mjp_plan_create_csr(rp, ci, va, mjp.mjp_opts_default(**o)),
+                synth.random_prob(401 * 499, 61), [0.3, 1.1])
+    raise KeyError(name)
+
+
+@pytest.mark.parametrize("renorm", [32, 0, 1])
+@pytest.mark.parametrize("case", ["cascade-csr-90000", "cascade-stencil-90000", "bd-stencil-1000",
+                                  "random-csr-33000", "banded-csr-200001"])
+def test_protocols_bit_identical(case, renorm):
+    """The persistent kernel's two memory protocols (device-scope iterate
+    accesses vs agent-scope fences) do the same arithmetic in the same order,
+    so their results must agree bit for bit; a stale read of the iterate in
+    either would change the bits.  renorm 0 runs on neighbour flags only,
+    renorm 1 on a grid barrier every jump."""
+    make, rho0, times = _protocol_case(case)
+    say(f"[gpu] protocols {case} renorm_every={renorm}")
+    res = []
+    for variant in PERSISTENT:
+        plan = make(variant=variant, renorm_every=renorm)
+        try:
+            res.append(gpu_expv(plan, rho0, times, info=False)[0])
+        finally:
+            mjp.mjp_plan_destroy(plan)
+    assert np.array_equal(res[0], res[1])

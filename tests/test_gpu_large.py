@@ -42,7 +42,8 @@ def run(plan):
 
 
 @pytest.mark.parametrize("kind", ["csr", "stencil"])
-@pytest.mark.parametrize("variant", [mjp.MJP_VARIANT_PERSISTENT, mjp.MJP_VARIANT_STEPWISE])
+@pytest.mark.parametrize("variant", [mjp.MJP_VARIANT_PERSISTENT, mjp.MJP_VARIANT_PERSISTENT_FENCED,
+                                     mjp.MJP_VARIANT_STEPWISE])
 def test_full_size_parity(ref, kind, variant):
     say(f"[gpu] cascade {S}x{S} t=1 via {kind}, variant {variant}")
     m = mjp.make_model(1, THETA, [S, S])
@@ -69,3 +70,21 @@ def test_full_size_parity(ref, kind, variant):
     marg = got.reshape(S, S).sum(axis=0)
     exact = poisson.pmf(np.arange(S), THETA[0] * (1 - math.exp(-1.0)))
     assert np.abs(marg - exact).sum() <= 1e-6
+
+
+@pytest.mark.parametrize("kind", ["csr", "stencil"])
+def test_full_size_protocols_bit_identical(kind):
+    """Device-scope and fenced protocols of the persistent kernel agree bit
+    for bit at full size (256 workgroups, every XCD)."""
+    say(f"[gpu] cascade {S}x{S} protocols via {kind}")
+    m = mjp.make_model(1, THETA, [S, S])
+    res = []
+    for variant in (mjp.MJP_VARIANT_PERSISTENT, mjp.MJP_VARIANT_PERSISTENT_FENCED):
+        opts = mjp.mjp_opts_default(variant=variant)
+        plan = mjp.mjp_plan_create_csr(*mjp.mjp_model_csr(m), opts) if kind == "csr" else \
+            mjp.mjp_plan_create_stencil(m, opts)
+        try:
+            res.append(run(plan)[0])
+        finally:
+            mjp.mjp_plan_destroy(plan)
+    assert np.array_equal(res[0], res[1])
