@@ -82,16 +82,27 @@ __device__ __forceinline__ int logical_block(int G) {
     return (b & 7) * (G >> 3) + (b >> 3);
 }
 
-// Iterate accesses under either protocol.
+// Iterate accesses under either protocol: raw buffer loads and stores at a
+// 32-bit byte offset from a uniform descriptor (one offset register per
+// gather instead of a 64-bit address pair).  The descriptor's range is the
+// vector's n*4 bytes, so an access past the end reads 0 or is dropped.  COH
+// sets the device-scope cache policy (the SC1 bit of the instruction's
+// cache-policy operand on this architecture family), which is what the
+// compiler emits for an agent-scope relaxed atomic load or store.
+constexpr int kCpolSC1 = 16;
+constexpr int kRsrcWord3 = 0x00020000;  // raw 32-bit buffer, no swizzle
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t iter_rsrc(const float* p, int64_t n) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(p), 0, (int)(uint32_t)(4 * n), kRsrcWord3);
+}
+// (the b32 builtins move 32-bit integers: the float travels as its bits)
 template <bool COH>
-__device__ __forceinline__ float ld_iter(const float* p) {
-    if constexpr (COH) return __hip_atomic_load(const_cast<float*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    else return *p;
+__device__ __forceinline__ float ld_iter(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, COH ? kCpolSC1 : 0));
 }
 template <bool COH>
-__device__ __forceinline__ void st_iter(float* p, float v) {
-    if constexpr (COH) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    else *p = v;
+__device__ __forceinline__ void st_iter(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, COH ? kCpolSC1 : 0);
 }
 
 // Publishing side of a synchronisation point.  COH: every wave waits until
@@ -179,7 +190,7 @@ __device__ __forceinline__ bool grid_barrier(unsigned* w, unsigned epoch, int g,
 // wave 0 poll one flag each; in the fenced protocol the wave then issues one
 // acquire fence.
 template <bool COH>
-__device__ __forceinline__ bool neighbour_sync(unsigned* wflag, const int32_t* wait, unsigned k, int g,
+__device__ __forceinline__ bool neighbour_sync(unsigned* wflag, int lo, int hi, unsigned k, int g,
                                                unsigned* flags, uint64_t timeout_ticks) {
     __shared__ int aborted;
     drain_wave<COH>();
@@ -191,7 +202,6 @@ __device__ __forceinline__ bool neighbour_sync(unsigned* wflag, const int32_t* w
             release_agent<COH>();
             __hip_atomic_store(&wflag[g * 32], k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        const int lo = wait[2 * g], hi = wait[2 * g + 1];
         const int h = lo + lane;
         bool bad = false;
         if (h <= hi && h != g) {
@@ -250,16 +260,16 @@ __global__ __launch_bounds__(kPThreads) void k_persistent(PersistArgs a) {
     const int slice0 = (g * kPWaves + wave) * R;
     const int64_t n = a.n;
 
-    int32_t row[R];
-    bool live[R];
-#pragma unroll
-    for (int i = 0; i < R; ++i) {
-        row[i] = (slice0 + i) * 64 + lane;
-        live[i] = row[i] < n;
-    }
+    // rows of this thread: row0 + 64 i, i < R (computed where used, which
+    // keeps R registers free for the operator)
+    const int32_t row0 = slice0 * 64 + lane;
+    auto row = [&](int i) { return row0 + 64 * i; };
+    auto live = [&](int i) { return (int64_t)(row0 + 64 * i) < n; };
 
     // ---- operator into registers
-    int32_t cidx[R][W];
+    // column of each entry, held as a 32-bit byte offset into the iterate so
+    // each gather is a 32-bit register offset on a uniform base (n < 2^30)
+    uint32_t coff[R][W];
     float cval[R][W];
     if (CSR) {
 #pragma unroll
@@ -272,11 +282,11 @@ __global__ __launch_bounds__(kPThreads) void k_persistent(PersistArgs a) {
             }
 #pragma unroll
             for (int j = 0; j < W; ++j) {
-                if (live[i] && j < w) {
-                    cidx[i][j] = a.col[beg + j * 64 + lane];
+                if (live(i) && j < w) {
+                    coff[i][j] = 4u * (uint32_t)a.col[beg + j * 64 + lane];
                     cval[i][j] = a.val[beg + j * 64 + lane];
                 } else {
-                    cidx[i][j] = live[i] ? (int32_t)row[i] : 0;
+                    coff[i][j] = live(i) ? 4u * (uint32_t)row(i) : 0u;
                     cval[i][j] = 0.f;
                 }
             }
@@ -287,7 +297,7 @@ __global__ __launch_bounds__(kPThreads) void k_persistent(PersistArgs a) {
         const StencilCoef cf = a.cf;
 #pragma unroll
         for (int i = 0; i < R; ++i) {
-            const int64_t m = live[i] ? (int64_t)row[i] : 0;
+            const int64_t m = live(i) ? (int64_t)row(i) : 0;
             int32_t i1, i2, S1 = cf.S1, S2 = cf.S2;
             if (cf.model == MJP_MODEL_BD) { i1 = (int32_t)m; i2 = 0; S2 = 1; }
             else { i2 = (int32_t)(m / S1); i1 = (int32_t)(m - (int64_t)i2 * S1); }
@@ -309,8 +319,8 @@ __global__ __launch_bounds__(kPThreads) void k_persistent(PersistArgs a) {
             if (i2 + 1 < S2) { cc[4] = (int32_t)m + S1; vv[4] = d2 * (f2 + 1.f); }
 #pragma unroll
             for (int j = 0; j < W; ++j) {
-                cidx[i][j] = j < 5 ? cc[j] : (int32_t)m;
-                cval[i][j] = (j < 5 && live[i]) ? vv[j] : 0.f;
+                coff[i][j] = 4u * (uint32_t)(j < 5 ? cc[j] : (int32_t)m);
+                cval[i][j] = (j < 5 && live(i)) ? vv[j] : 0.f;
             }
         }
     }
@@ -326,39 +336,60 @@ __global__ __launch_bounds__(kPThreads) void k_persistent(PersistArgs a) {
     double mloc = 0.0;
 #pragma unroll
     for (int i = 0; i < R; ++i) {
-        yv[i] = live[i] ? a.rho0[row[i]] : 0.f;
-        if (live[i]) {
+        yv[i] = live(i) ? a.rho0[row(i)] : 0.f;
+        if (live(i)) {
             if (!(yv[i] >= 0.f)) atomicOr(a.flags, (yv[i] != yv[i]) ? (unsigned)MJP_FLAG_NAN : (unsigned)MJP_FLAG_NEG);
             else if (isinf(yv[i])) atomicOr(a.flags, (unsigned)MJP_FLAG_NAN);
         }
         mloc += (double)yv[i];
     }
 
-    auto accumulate = [&](int k) {
+    // Per-slot parameters of jump k (uniform): the time whose window holds k
+    // in slot q (or -1) and its table weight.  fetch() runs at the top of a
+    // jump, so the weight loads are in flight together with the gathers;
+    // accumulate() consumes them after the new iterate is formed.
+    int jq[kPSlots];
+    double wraw[kPSlots];
+    auto fetch = [&](int k) {
+#pragma unroll
+        for (int qq = 0; qq < kPSlots; ++qq) jq[qq] = -1;
         for (int j = 0; j < a.at.n; ++j) {
             const TimeParam& tp = a.at.tp[j];
             if (k < tp.L || k > tp.K) continue;
-            const int q = a.slot[j];
-            const float w = (k == tp.K) ? (float)tp.lastw : (float)a.wtab[tp.woff + (k - tp.L)];
 #pragma unroll
-            for (int qq = 0; qq < kPSlots; ++qq) {
-                if (qq != q) continue;
+            for (int qq = 0; qq < kPSlots; ++qq)
+                if (qq == a.slot[j]) jq[qq] = j;
+        }
 #pragma unroll
-                for (int i = 0; i < R; ++i) {
-                    if (k == tp.L) {
-                        sacc[qq][i] = w * yv[i];
-                        cacc[qq][i] = 0.f;
-                    } else {
-                        const float yk = fmaf(w, yv[i], -cacc[qq][i]);
-                        const float t = sacc[qq][i] + yk;
-                        cacc[qq][i] = (t - sacc[qq][i]) - yk;
-                        sacc[qq][i] = t;
-                    }
-                    if (k == tp.K && live[i]) a.out[(int64_t)tp.out * n + row[i]] = sacc[qq][i] - cacc[qq][i];
+        for (int qq = 0; qq < kPSlots; ++qq) {
+            const int j = jq[qq];
+            const int idx = j < 0 ? 0 : a.at.tp[j].woff + (k - a.at.tp[j].L);  // in [woff, woff + K - L]
+            wraw[qq] = a.wtab[idx];
+        }
+    };
+    auto accumulate = [&](int k) {
+#pragma unroll
+        for (int qq = 0; qq < kPSlots; ++qq) {
+            const int j = jq[qq];
+            if (j < 0) continue;
+            const TimeParam& tp = a.at.tp[j];
+            const float w = (k == tp.K) ? (float)tp.lastw : (float)wraw[qq];
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                if (k == tp.L) {
+                    sacc[qq][i] = w * yv[i];
+                    cacc[qq][i] = 0.f;
+                } else {
+                    const float yk = fmaf(w, yv[i], -cacc[qq][i]);
+                    const float t = sacc[qq][i] + yk;
+                    cacc[qq][i] = (t - sacc[qq][i]) - yk;
+                    sacc[qq][i] = t;
                 }
+                if (k == tp.K && live(i)) a.out[(int64_t)tp.out * n + row(i)] = sacc[qq][i] - cacc[qq][i];
             }
         }
     };
+    fetch(0);
     accumulate(0);
 
     // initial mass, reduced once all partials are in
@@ -373,18 +404,23 @@ __global__ __launch_bounds__(kPThreads) void k_persistent(PersistArgs a) {
     double last_mass = mass0;
 
     const int m = a.renorm_every;
+    // this workgroup's neighbour interval, read once
+    const int wlo = a.wait ? a.wait[2 * g] : g, whi = a.wait ? a.wait[2 * g + 1] : g;
+    const __amdgpu_buffer_rsrc_t r_rho0 = iter_rsrc(a.rho0, n), r_buf0 = iter_rsrc(a.buf0, n),
+                                 r_buf1 = iter_rsrc(a.buf1, n);
     for (int k = 1; k <= a.Kmax; ++k) {
-        const float* __restrict__ x = (k == 1) ? a.rho0 : ((k & 1) ? a.buf0 : a.buf1);
-        float* __restrict__ y = (k & 1) ? a.buf1 : a.buf0;
+        const __amdgpu_buffer_rsrc_t x = (k == 1) ? r_rho0 : ((k & 1) ? r_buf0 : r_buf1);
+        const __amdgpu_buffer_rsrc_t y = (k & 1) ? r_buf1 : r_buf0;
         const float fs = (float)scale;
         double part = 0.0;
+        fetch(k);
         // all R*W gathers first, in one basic block, so they are in flight
         // together; the predicated stores come after every load was issued
         float xv[R][W];
 #pragma unroll
         for (int i = 0; i < R; ++i)
 #pragma unroll
-            for (int j = 0; j < W; ++j) xv[i][j] = ld_iter<COH>(x + cidx[i][j]);
+            for (int j = 0; j < W; ++j) xv[i][j] = ld_iter<COH>(x, coff[i][j]);
 #pragma unroll
         for (int i = 0; i < R; ++i) {
             float acc = 0.f;
@@ -394,8 +430,7 @@ __global__ __launch_bounds__(kPThreads) void k_persistent(PersistArgs a) {
             part += (double)yv[i];
         }
 #pragma unroll
-        for (int i = 0; i < R; ++i)
-            if (live[i]) st_iter<COH>(y + row[i], yv[i]);
+        for (int i = 0; i < R; ++i) st_iter<COH>(y, 4u * (uint32_t)row(i), yv[i]);  // rows >= n fall outside the range
         accumulate(k);
         const bool renorm = m > 0 && (k % m == 0) && k < a.Kmax;
         double* pm = a.pmass + (size_t)G * (1 + ((k / (m > 0 ? m : 1)) & 1));
@@ -410,7 +445,7 @@ __global__ __launch_bounds__(kPThreads) void k_persistent(PersistArgs a) {
             if (a.wait && threadIdx.x == 0)  // keep the flags current for later neighbour waits
                 __hip_atomic_store(&a.wflag[g * 32], (unsigned)k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
-            if (!neighbour_sync<COH>(a.wflag, a.wait, (unsigned)k, g, a.flags, a.timeout_ticks)) return;
+            if (!neighbour_sync<COH>(a.wflag, wlo, whi, (unsigned)k, g, a.flags, a.timeout_ticks)) return;
         }
         if (renorm) {
             last_mass = sum_partials(pm, G, red);
@@ -451,6 +486,7 @@ __global__ void k_zero_u32(unsigned* p, int n) {
 // Decide whether the persistent kernel can run this sweep; fills cfg.
 bool persistent_fits(const mjp_plan* p, int max_open, bool coh, PersistCfg& cfg) {
     if (max_open > kPSlots) return false;
+    if (p->n >= ((int64_t)1 << 30)) return false;  // byte offsets of the iterate must fit 32 bits
     int W = 5;
     if (p->kind == PLAN_CSR) {
         if (p->max_width <= 3) W = 3;
