@@ -96,6 +96,7 @@ struct mjp_plan {
     mjp::DevBuf scal;       // device scalars (masses, scale, flags)
     mjp::DevBuf sync;       // persistent-kernel barrier words, flags, partials
     mjp::DevBuf wait;       // persistent kernel: per-workgroup neighbour interval
-    int wait_key[3] = {0, 0, 0};  // (G, R, valid) the wait table was built for
+    mjp::DevBuf sflag;      // persistent kernel: per-slice local / exported bits
+    int wait_key[3] = {0, 0, 0};  // (G, R, valid) the two tables were built for
     std::vector<char> host_stage;
 };

@@ -48,6 +48,7 @@ namespace mjp {
 constexpr int kPWaves = 8;            // waves per workgroup
 constexpr int kPThreads = 64 * kPWaves;
 constexpr int kPSlots = 4;            // open collection windows held in registers
+constexpr uint8_t kSliceLocal = 1;   // per-slice table bit (see build_sweep_tables)
 
 struct PersistArgs {
     const int32_t* __restrict__ slice_off;
@@ -63,6 +64,7 @@ struct PersistArgs {
     unsigned* __restrict__ bar;   // [kBarWords] barrier words, zero at launch
     unsigned* __restrict__ wflag; // [G * 32] per-workgroup epoch flags (one 128-byte line each), zero at launch
     const int32_t* __restrict__ wait;  // [G][2] neighbour interval [lo, hi] or null (global barriers only)
+    const uint8_t* __restrict__ sflag; // [n_slices] kSliceLocal or 0
     unsigned* __restrict__ flags;
     double* __restrict__ mass_out;  // [2]: initial mass, last measured mass
     uint64_t timeout_ticks;         // per-barrier wait limit in wall-clock ticks
@@ -325,6 +327,31 @@ __global__ __launch_bounds__(kPThreads) void k_persistent(PersistArgs a) {
         }
     }
 
+    // ---- this workgroup's rows of the iterate, double-buffered in LDS
+    // Workgroup g owns rows [r0, r0 + kPWaves*R*64).  Slice i of a wave is
+    // "local" when every column of every entry of its 64 rows is one of those
+    // rows; a local slice gathers from the LDS copy (written by this
+    // workgroup, visible after its own barrier), any other slice from the
+    // iterate in global memory.  Every slice stores its rows to both.  The
+    // bit is uniform per slice and fixed for the whole sweep (host-built
+    // table).
+    constexpr int kRowsWG = kPWaves * R * 64;
+    __shared__ float ybuf[2][kRowsWG];
+    const uint32_t lbase = 4u * (uint32_t)(g * kRowsWG);
+    uint32_t lmask = 0;  // bit i: slice i is local
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        if (!live(i)) {
+#pragma unroll
+            for (int j = 0; j < W; ++j) coff[i][j] = lbase;  // padding lanes read a local row, weight 0
+        }
+        const int sl = slice0 + i;
+        const uint8_t f = sl < a.n_slices ? a.sflag[sl] : kSliceLocal;
+        if (f & kSliceLocal) lmask |= 1u << i;
+    }
+    lmask = __builtin_amdgcn_readfirstlane(lmask);
+    const int lrow0 = wave * R * 64 + lane;  // this thread's row i sits at lrow0 + 64 i
+
     // ---- k = 0
     float sacc[kPSlots][R], cacc[kPSlots][R];
 #pragma unroll
@@ -342,6 +369,7 @@ __global__ __launch_bounds__(kPThreads) void k_persistent(PersistArgs a) {
             else if (isinf(yv[i])) atomicOr(a.flags, (unsigned)MJP_FLAG_NAN);
         }
         mloc += (double)yv[i];
+        ybuf[0][lrow0 + 64 * i] = yv[i];
     }
 
     // Per-slot parameters of jump k (uniform): the time whose window holds k
@@ -416,11 +444,19 @@ __global__ __launch_bounds__(kPThreads) void k_persistent(PersistArgs a) {
         fetch(k);
         // all R*W gathers first, in one basic block, so they are in flight
         // together; the predicated stores come after every load was issued
+        const char* __restrict__ xl = reinterpret_cast<const char*>(ybuf[(k - 1) & 1]) - lbase;
+        float* __restrict__ yl = ybuf[k & 1];
         float xv[R][W];
 #pragma unroll
-        for (int i = 0; i < R; ++i)
+        for (int i = 0; i < R; ++i) {
+            if ((lmask >> i) & 1u) {
 #pragma unroll
-            for (int j = 0; j < W; ++j) xv[i][j] = ld_iter<COH>(x, coff[i][j]);
+                for (int j = 0; j < W; ++j) xv[i][j] = *reinterpret_cast<const float*>(xl + coff[i][j]);
+            } else {
+#pragma unroll
+                for (int j = 0; j < W; ++j) xv[i][j] = ld_iter<COH>(x, coff[i][j]);
+            }
+        }
 #pragma unroll
         for (int i = 0; i < R; ++i) {
             float acc = 0.f;
@@ -430,7 +466,10 @@ __global__ __launch_bounds__(kPThreads) void k_persistent(PersistArgs a) {
             part += (double)yv[i];
         }
 #pragma unroll
-        for (int i = 0; i < R; ++i) st_iter<COH>(y, 4u * (uint32_t)row(i), yv[i]);  // rows >= n fall outside the range
+        for (int i = 0; i < R; ++i) {
+            yl[lrow0 + 64 * i] = yv[i];
+            st_iter<COH>(y, 4u * (uint32_t)row(i), yv[i]);  // rows >= n fall outside the range
+        }
         accumulate(k);
         const bool renorm = m > 0 && (k % m == 0) && k < a.Kmax;
         double* pm = a.pmass + (size_t)G * (1 + ((k / (m > 0 ? m : 1)) & 1));
@@ -523,36 +562,60 @@ bool persistent_fits(const mjp_plan* p, int max_open, bool coh, PersistCfg& cfg)
     return false;
 }
 
-// Per-workgroup neighbour interval for the persistent sweep: the hull of
-// the workgroups owning the columns my rows read and of the workgroups that
-// read my rows.  Built once per (plan, G, R) and kept on the device.  If some
-// interval spans more than 64 workgroups the sweep uses global barriers only.
-static mjp_status build_wait_table(mjp_plan* p, const PersistCfg& cfg, const int32_t*& out) {
-    out = nullptr;
-    if (p->wait_key[2] == 1 && p->wait_key[0] == cfg.G && p->wait_key[1] == cfg.R) {
-        out = p->wait.as<int32_t>();
+// Tables of the persistent sweep, built once per (plan, G, R) and kept on
+// the device:
+//  * per-workgroup neighbour interval: the hull of the workgroups owning the
+//    columns my rows read and of the workgroups that read my rows.  If some
+//    interval spans more than 64 workgroups the sweep uses global barriers
+//    only (wait = null).
+//  * per-slice bit kSliceLocal: every column the slice reads belongs to its
+//    own workgroup (it gathers from the workgroup's LDS copy), decided from
+//    the slice's column hull.
+static mjp_status build_sweep_tables(mjp_plan* p, const PersistCfg& cfg, const int32_t*& wait_out,
+                                     const uint8_t*& sflag_out) {
+    wait_out = nullptr;
+    sflag_out = nullptr;
+    const bool cached = p->wait_key[2] != 0 && p->wait_key[0] == cfg.G && p->wait_key[1] == cfg.R;
+    if (cached) {
+        if (p->wait_key[2] == 1) wait_out = p->wait.as<int32_t>();
+        sflag_out = p->sflag.as<uint8_t>();
         return MJP_OK;
     }
-    if (p->wait_key[2] == 2 && p->wait_key[0] == cfg.G && p->wait_key[1] == cfg.R) return MJP_OK;
     const int G = cfg.G;
     const int64_t rows_per = (int64_t)kPWaves * cfg.R * 64;
+    const int64_t slices_per = rows_per / 64;
     const int64_t n = p->n;
+    const int64_t n_slices = (n + 63) / 64;
+    // column hull of each slice
+    std::vector<int64_t> smin((size_t)n_slices), smax((size_t)n_slices);
+    for (int64_t sl = 0; sl < n_slices; ++sl) {
+        if (p->kind == PLAN_CSR) {
+            smin[(size_t)sl] = p->slice_cmin[(size_t)sl];
+            smax[(size_t)sl] = p->slice_cmax[(size_t)sl];
+        } else {
+            const int64_t reach = p->coef.model == MJP_MODEL_BD ? 1 : p->coef.S1;
+            smin[(size_t)sl] = std::max<int64_t>(0, sl * 64 - reach);
+            smax[(size_t)sl] = std::min<int64_t>(n - 1, sl * 64 + 63 + reach);
+        }
+    }
+    // per-slice bits
+    std::vector<uint8_t> flag((size_t)n_slices, 0);
+    for (int64_t sl = 0; sl < n_slices; ++sl) {
+        const int64_t r0 = (sl / slices_per) * rows_per;
+        if (smin[(size_t)sl] >= r0 && smax[(size_t)sl] < r0 + rows_per) flag[(size_t)sl] = kSliceLocal;
+    }
+    mjp_status s = p->sflag.reserve(flag.size());
+    if (s) return s;
+    MJP_HIP(hipMemcpy(p->sflag.ptr, flag.data(), flag.size(), hipMemcpyHostToDevice));
+
     std::vector<int32_t> lo(G), hi(G);
     for (int g = 0; g < G; ++g) {
         const int64_t r0 = (int64_t)g * rows_per, r1 = std::min(n, r0 + rows_per);
         if (r0 >= n) { lo[g] = hi[g] = g; continue; }
-        int64_t cmin, cmax;
-        if (p->kind == PLAN_CSR) {
-            cmin = INT64_MAX;
-            cmax = -1;
-            for (int64_t sl = r0 / 64; sl <= (r1 - 1) / 64; ++sl) {
-                cmin = std::min<int64_t>(cmin, p->slice_cmin[(size_t)sl]);
-                cmax = std::max<int64_t>(cmax, p->slice_cmax[(size_t)sl]);
-            }
-        } else {
-            const int64_t reach = p->coef.model == MJP_MODEL_BD ? 1 : p->coef.S1;
-            cmin = std::max<int64_t>(0, r0 - reach);
-            cmax = std::min<int64_t>(n - 1, r1 - 1 + reach);
+        int64_t cmin = INT64_MAX, cmax = -1;
+        for (int64_t sl = r0 / 64; sl <= (r1 - 1) / 64; ++sl) {
+            cmin = std::min(cmin, smin[(size_t)sl]);
+            cmax = std::max(cmax, smax[(size_t)sl]);
         }
         lo[g] = (int32_t)std::min<int64_t>(g, cmin / rows_per);
         hi[g] = (int32_t)std::max<int64_t>(g, cmax / rows_per);
@@ -568,6 +631,7 @@ static mjp_status build_wait_table(mjp_plan* p, const PersistCfg& cfg, const int
     for (int g = 0; g < G && ok; ++g) ok = whi[g] - wlo[g] + 1 <= 64;
     p->wait_key[0] = G;
     p->wait_key[1] = cfg.R;
+    sflag_out = p->sflag.as<uint8_t>();
     if (!ok) {
         p->wait_key[2] = 2;
         return MJP_OK;
@@ -577,11 +641,10 @@ static mjp_status build_wait_table(mjp_plan* p, const PersistCfg& cfg, const int
         tab[2 * (size_t)g] = wlo[g];
         tab[2 * (size_t)g + 1] = whi[g];
     }
-    mjp_status s = p->wait.reserve(sizeof(int32_t) * tab.size());
-    if (s) return s;
+    if ((s = p->wait.reserve(sizeof(int32_t) * tab.size()))) return s;
     MJP_HIP(hipMemcpy(p->wait.ptr, tab.data(), sizeof(int32_t) * tab.size(), hipMemcpyHostToDevice));
     p->wait_key[2] = 1;
-    out = p->wait.as<int32_t>();
+    wait_out = p->wait.as<int32_t>();
     return MJP_OK;
 }
 
@@ -596,7 +659,8 @@ mjp_status launch_persistent(mjp_plan* p, const PersistCfg& cfg, const float* rh
     unsigned* wflag = bar + kBarWords;
     double* pmass = reinterpret_cast<double*>(wflag + 32 * (size_t)cfg.G);
     const int32_t* wait = nullptr;
-    if ((s = build_wait_table(p, cfg, wait))) return s;
+    const uint8_t* sflag = nullptr;
+    if ((s = build_sweep_tables(p, cfg, wait, sflag))) return s;
     double* mass_out = p->scal.as<double>() + S_MASS0;  // [S_MASS0], [S_MASSK]
     PersistArgs a{};
     a.slice_off = p->slice_off.as<int32_t>();
@@ -612,6 +676,7 @@ mjp_status launch_persistent(mjp_plan* p, const PersistCfg& cfg, const float* rh
     a.bar = bar;
     a.wflag = wflag;
     a.wait = wait;
+    a.sflag = sflag;
     a.flags = reinterpret_cast<unsigned*>(p->scal.as<double>() + S_FLAGS);
     a.mass_out = mass_out;
     a.n = n;
