@@ -62,6 +62,66 @@ def measured_traffic(kind: str):
     return {"bytes_per_launch": rec["hbm_bytes_per_launch"], "source": os.path.relpath(path, ROOT)}
 
 
+def bench_small(torch, mjp, reps: int = 20):
+    """The two smaller expv workloads.
+    C1: immigration-death on states 0..999, lambda = 500, mu = 1, t = 1,
+        rho(0) at 0 (latency-bound: one short sweep of ~1900 jumps); its
+        result is compared with the closed form Poisson(500 (1 - e^-1)).
+    C2: cascade 300 x 300 (N = 90,000), rates (200, 1, 0.5, 0.5), rho(0) at
+        (0, 0), 16 log-spaced times 0.1..10 in one sweep with 16 full-vector
+        outputs (K up to ~9400); its bytes are served from cache (the vector
+        pair is 0.7 MB)."""
+    from scipy.stats import poisson
+    from paper_2312_05647_amd import synth
+    res = {}
+    stream = torch.cuda.current_stream()
+
+    def run(plan, r0, times, out):
+        inf = mjp.mjp_expv(plan, r0, times, out, info=True)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(reps):
+            mjp.mjp_expv(plan, r0, times, out, stream=stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        return inf, ev0.elapsed_time(ev1) / 1e3 / reps
+
+    m1 = mjp.make_model(mjp.MJP_MODEL_BD, [500.0, 1.0], [1000])
+    rp, ci, va = mjp.mjp_model_csr(m1)
+    plan = mjp.mjp_plan_create_csr(rp, ci, va, mjp.mjp_opts_default())
+    r0 = torch.zeros(1000, device="cuda")
+    r0[0] = 1.0
+    out = torch.empty((1, 1000), device="cuda")
+    try:
+        inf, sec = run(plan, r0, [1.0], out)
+    finally:
+        mjp.mjp_plan_destroy(plan)
+    exact = poisson.pmf(np.arange(1000), 500.0 * (1 - math.exp(-1.0)))
+    res["C1_birth_death_N1000"] = {"us_per_solve": sec * 1e6, "jumps_per_s": inf[0]["K"] / sec, "K": inf[0]["K"],
+                                   "l1_vs_closed_form": float(np.abs(out[0].double().cpu().numpy() - exact).sum())}
+    log(f"[bench] C1: {sec * 1e6:.1f} us/solve, K={inf[0]['K']}")
+
+    m2 = mjp.make_model(mjp.MJP_MODEL_CASCADE2, [200.0, 1.0, 0.5, 0.5], [300, 300])
+    rp, ci, va = mjp.mjp_model_csr(m2)
+    plan = mjp.mjp_plan_create_csr(rp, ci, va, mjp.mjp_opts_default())
+    times = list(synth.log_spaced_times(16, 0.1, 10.0))
+    r0 = torch.zeros(90000, device="cuda")
+    r0[0] = 1.0
+    out = torch.empty((16, 90000), device="cuda")
+    try:
+        inf, sec = run(plan, r0, times, out)
+    finally:
+        mjp.mjp_plan_destroy(plan)
+    Kmax = max(i["K"] for i in inf)
+    acc = sum(i["K"] - i["L"] + 1 for i in inf)
+    ab = Kmax * (8 * len(ci) + 12 * 90000) + acc * 16 * 90000
+    res["C2_cascade_300x300_16_times"] = {"ms_per_sweep": sec * 1e3, "K_max": Kmax, "jumps_per_s": Kmax / sec,
+                                          "algorithmic_GBps_cache_served": ab / sec / 1e9}
+    log(f"[bench] C2: {sec * 1e3:.2f} ms per 16-time sweep, K_max={Kmax}")
+    return res
+
+
 def bench_loglik(torch, mjp, reps: int = 3):
     """Batched log-likelihoods: 4096 draws log-uniform over a decade around
     (50, 1, 0.5, 0.5), 20 collection times 0.5..10 with 50 snapshots each,
@@ -173,7 +233,7 @@ def main():
     ap.add_argument("--variant", type=int, default=0, help="0 auto, 1 stepwise, 2 persistent")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the secondary measurements")
-    ap.add_argument("--part", choices=["all", "loglik", "da"], default="all",
+    ap.add_argument("--part", choices=["all", "loglik", "da", "small"], default="all",
                     help="run only one secondary leg (for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the byte counters)")
@@ -198,6 +258,9 @@ def main():
         return
     if args.part == "da":
         print(json.dumps({"da_mcmc": bench_da(torch, mjp)}))
+        return
+    if args.part == "small":
+        print(json.dumps({"small_configs": bench_small(torch, mjp)}))
         return
 
     dev = torch.device("cuda:0")
@@ -281,6 +344,7 @@ def main():
         log(f"[bench] {other}: {dev2 * 1e3:.3f} ms/solve")
 
     if not args.no_extra:
+        result["small_configs"] = bench_small(torch, mjp)
         result["loglik_batch"] = bench_loglik(torch, mjp)
         result["da_mcmc"] = bench_da(torch, mjp)
 

@@ -148,6 +148,7 @@ __device__ __forceinline__ bool grid_barrier(unsigned* w, unsigned epoch, int g,
     __shared__ int aborted;
     drain_wave<COH>();
     __syncthreads();
+    if (G == 1) return true;  // a single workgroup: its own barrier is the grid barrier
     if (threadIdx.x == 0) {
         aborted = 0;
         const int per = G >> 3, grp = g / per;
@@ -372,12 +373,16 @@ __global__ __launch_bounds__(kPThreads) void k_persistent(PersistArgs a) {
         ybuf[0][lrow0 + 64 * i] = yv[i];
     }
 
-    // Per-slot parameters of jump k (uniform): the time whose window holds k
-    // in slot q (or -1) and its table weight.  fetch() runs at the top of a
-    // jump, so the weight loads are in flight together with the gathers;
-    // accumulate() consumes them after the new iterate is formed.
+    // Per-slot parameters of jump k (uniform): jq[q] is the time whose
+    // window holds k in slot q (or -1); fetch() finds them from the kernel
+    // arguments only.  The Poisson weights are held 64 jumps at a time: lane
+    // l of wvec[q] is the weight of jump wbase + l for the time occupying
+    // slot q then (0 if none), refilled every 64 jumps with one vector load
+    // per lane, so a jump reads its weight from a register (v_readlane at a
+    // uniform index) and never waits on memory for it.
     int jq[kPSlots];
-    double wraw[kPSlots];
+    float wvec[kPSlots];
+    int wbase = 0;
     auto fetch = [&](int k) {
 #pragma unroll
         for (int qq = 0; qq < kPSlots; ++qq) jq[qq] = -1;
@@ -388,11 +393,19 @@ __global__ __launch_bounds__(kPThreads) void k_persistent(PersistArgs a) {
             for (int qq = 0; qq < kPSlots; ++qq)
                 if (qq == a.slot[j]) jq[qq] = j;
         }
+        if ((k & 63) == 0) {
+            wbase = k;
+            const int kk = k + lane;
 #pragma unroll
-        for (int qq = 0; qq < kPSlots; ++qq) {
-            const int j = jq[qq];
-            const int idx = j < 0 ? 0 : a.at.tp[j].woff + (k - a.at.tp[j].L);  // in [woff, woff + K - L]
-            wraw[qq] = a.wtab[idx];
+            for (int qq = 0; qq < kPSlots; ++qq) wvec[qq] = 0.f;
+            for (int j = 0; j < a.at.n; ++j) {
+                const TimeParam& tp = a.at.tp[j];
+                if (kk < tp.L || kk > tp.K) continue;
+                const float w = (kk == tp.K) ? (float)tp.lastw : (float)a.wtab[tp.woff + (kk - tp.L)];
+#pragma unroll
+                for (int qq = 0; qq < kPSlots; ++qq)
+                    if (qq == a.slot[j]) wvec[qq] = w;
+            }
         }
     };
     auto accumulate = [&](int k) {
@@ -401,7 +414,8 @@ __global__ __launch_bounds__(kPThreads) void k_persistent(PersistArgs a) {
             const int j = jq[qq];
             if (j < 0) continue;
             const TimeParam& tp = a.at.tp[j];
-            const float w = (k == tp.K) ? (float)tp.lastw : (float)wraw[qq];
+            const float w = __builtin_bit_cast(
+                float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, wvec[qq]), k - wbase));
 #pragma unroll
             for (int i = 0; i < R; ++i) {
                 if (k == tp.L) {
@@ -468,7 +482,8 @@ __global__ __launch_bounds__(kPThreads) void k_persistent(PersistArgs a) {
 #pragma unroll
         for (int i = 0; i < R; ++i) {
             yl[lrow0 + 64 * i] = yv[i];
-            st_iter<COH>(y, 4u * (uint32_t)row(i), yv[i]);  // rows >= n fall outside the range
+            // rows >= n fall outside the range; a single workgroup reads only its LDS copy
+            if (G > 1) st_iter<COH>(y, 4u * (uint32_t)row(i), yv[i]);
         }
         accumulate(k);
         const bool renorm = m > 0 && (k % m == 0) && k < a.Kmax;
@@ -483,6 +498,8 @@ __global__ __launch_bounds__(kPThreads) void k_persistent(PersistArgs a) {
             if (!grid_barrier<COH>(a.bar, epoch, g, G, a.flags, a.timeout_ticks)) return;
             if (a.wait && threadIdx.x == 0)  // keep the flags current for later neighbour waits
                 __hip_atomic_store(&a.wflag[g * 32], (unsigned)k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else if (G == 1) {
+            __syncthreads();  // one workgroup: the LDS double buffer needs only its own barrier
         } else {
             if (!neighbour_sync<COH>(a.wflag, wlo, whi, (unsigned)k, g, a.flags, a.timeout_ticks)) return;
         }
@@ -541,9 +558,24 @@ bool persistent_fits(const mjp_plan* p, int max_open, bool coh, PersistCfg& cfg)
     int coop = 0;
     if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return false;
     const int64_t slices = (p->n + 63) / 64;
+    auto fn_for = [&](int R) {
+        return p->kind == PLAN_CSR ? (coh ? pick<true, true>(R, W) : pick<true, false>(R, W))
+                                   : (coh ? pick<false, true>(R, W) : pick<false, false>(R, W));
+    };
+    // a vector that one workgroup can hold runs in a single workgroup: every
+    // gather is local (LDS) and a jump costs two workgroup barriers
     for (int R : {1, 2, 4, 8}) {
-        PersistFn f = p->kind == PLAN_CSR ? (coh ? pick<true, true>(R, W) : pick<true, false>(R, W))
-                                          : (coh ? pick<false, true>(R, W) : pick<false, false>(R, W));
+        PersistFn f = fn_for(R);
+        if (!f || slices > (int64_t)kPWaves * R) continue;
+        cfg.R = R;
+        cfg.W = W;
+        cfg.G = 1;
+        cfg.coh = coh;
+        cfg.fn = reinterpret_cast<const void*>(f);
+        return true;
+    }
+    for (int R : {1, 2, 4, 8}) {
+        PersistFn f = fn_for(R);
         if (!f) continue;
         int per_cu = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(f), kPThreads, 0) !=
