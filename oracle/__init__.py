@@ -20,6 +20,8 @@ What each function follows (Pessoa, Schweiger, Presse, arXiv 2312.05647):
 * ``mlp_*`` / ``adam_*`` -- an FP64 reference of the surrogate network, used
   to check the GPU training kernels' gradients (the surrogate itself is not in
   the paper).
+* ``oracle.krylov`` -- the Krylov-subspace propagator (Method #5, Algorithm
+  ArnoldiKrylov, Eq. Krylov_expansion) in numpy FP64.
 
 Parity status: every function above is pinned by ``tests/test_oracle_*.py``
 against closed forms, library routines (``scipy.stats.poisson``,
