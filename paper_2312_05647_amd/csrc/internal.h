@@ -62,6 +62,9 @@ struct StencilCoef {
 
 constexpr int kSlice = 64;  // rows per sliced-ELL slice (= one wavefront)
 
+// Generator checks shared by every CSR entry point (see runtime.hip).
+mjp_status check_generator_csr(const mjp_csr* A, int leaky, double* m_theta, std::vector<double>* diag);
+
 }  // namespace mjp
 
 struct mjp_plan {

@@ -1,0 +1,565 @@
+// Krylov-subspace propagator (Method #5, Sec. 2.3: Algorithm ArnoldiKrylov
+// and Eq. Krylov_expansion) on the GPU, in FP64.
+//
+// One step over [t, t + dt] from rho:
+//   q_1 = rho / ||rho||;  for i = 2..kappa: q_i = q_{i-1} A orthogonalised
+//   against q_1..q_{i-1} (h_{j,i-1}), h_{i,i-1} = ||q_i||, q_i /= h_{i,i-1};
+//   rho(t + dt) = ||rho|| sum_i [exp(H dt)]_{i,1} q_i,
+// with dt = dt_factor * kappa / max|a_nn| (the paper uses dt_factor = 2),
+// shortened before each requested time so the propagation lands on it.
+//
+// Layout and kernels:
+//  * A^T in sliced ELL (64-row slices, column-major inside a slice, FP64
+//    values): the product q A is a pull over the output rows.
+//  * The basis is stored unnormalised, Qraw[i] with q_i = scale[i] Qraw[i],
+//    so normalising never needs a pass of its own.
+//  * One Arnoldi iteration = three streaming kernels, each ending in a
+//    deterministic reduction done by the last block to arrive (release fence
+//    + ticket, acquire fence, fixed summation order):
+//      spmv_dot:  w = q_{i-1} A;  first projections <q_j, w>;  ||w||^2
+//      orth_dot:  w -= sum_j h1_j q_j;  second projections (reorthogonalisation)
+//      orth_norm: w -= sum_j h2_j q_j;  ||w||  -> h_{i,i-1}, scale[i]
+//    h_{j,i-1} = h1_j + h2_j.  This is classical Gram-Schmidt with one
+//    reorthogonalisation, equal to the paper's modified Gram-Schmidt in exact
+//    arithmetic and as accurate in FP64; it reads each basis vector in one
+//    coalesced pass instead of i dependent passes.
+//  * The kappa x kappa exponential is formed by one workgroup in LDS: Taylor
+//    polynomial of degree 12 (Horner) on H dt / 2^s with ||.||_1 <= 1/4,
+//    then s squarings.
+//  * The combination writes rho (and the output vector when the step lands
+//    on a requested time) and its squared norm for the next step.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "internal.h"
+
+namespace mjp {
+
+constexpr int kKB = 256;          // threads per block of the streaming kernels
+constexpr int kKMax = 32;         // largest basis
+constexpr int kTaylor = 12;       // Taylor degree of the small exponential
+constexpr double kBreakRel = 1e-12;
+
+// scalar slots (FP64) of the device scalar block
+constexpr int S_BETA = 0;
+constexpr int S_WN2 = 1;
+constexpr int S_SCALE = 8;                  // [kKMax]
+constexpr int S_H1 = S_SCALE + kKMax;       // [kKMax]
+constexpr int S_H2 = S_H1 + kKMax;          // [kKMax]
+constexpr int S_C = S_H2 + kKMax;           // [kKMax]
+constexpr int S_COUNT = S_C + kKMax;
+
+struct KryOp {
+    const int32_t* __restrict__ slice_off;
+    const int32_t* __restrict__ col;
+    const double* __restrict__ val;
+};
+
+// Sum of M per-thread values over the block; result for value m in red[m]
+// (valid after the call for all threads).  Fixed order: wave shuffles, then
+// the waves in index order.
+template <int M>
+__device__ __forceinline__ void block_sums(double (&v)[M], double* red) {
+    constexpr int kWaves = kKB / 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        double x = v[m];
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+        if (lane == 0) red[m * kWaves + wave] = x;
+    }
+    __syncthreads();
+    for (int m = threadIdx.x; m < M; m += kKB) {
+        double s = 0.0;
+        for (int w = 0; w < kWaves; ++w) s += red[m * kWaves + w];
+        red[m * kWaves] = s;
+    }
+    __syncthreads();
+}
+
+// Last-block reduction of partials part[m * nblk + b] for m < count.  Each
+// block has written its partials; returns true in the block that arrives
+// last, which then holds the sums in sums[m].  The ticket is reset there.
+__device__ __forceinline__ bool last_block(unsigned* ticket) {
+    __shared__ int is_last;
+    __threadfence();  // publish this block's partials (agent-scope release)
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned t = atomicAdd(ticket, 1u);
+        is_last = (t == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (is_last) __threadfence();  // acquire the other blocks' partials
+    return is_last;
+}
+
+__device__ __forceinline__ void sum_partials(const double* part, int nblk, int count, double* sums) {
+    // each wave sums whole rows of partials in block order; rows spread over waves
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int m = wave; m < count; m += kKB / 64) {
+        double s = 0.0;
+        for (int b = lane; b < nblk; b += 64) s += part[(size_t)m * nblk + b];
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+        if (lane == 0) sums[m] = s;
+    }
+    __syncthreads();
+}
+
+// ---- kernels
+
+// rho -> Qraw[0], ||rho||^2; last block: beta and scale[0].
+__global__ __launch_bounds__(kKB) void k_kry_start(const double* __restrict__ rho, double* __restrict__ q0, int64_t n,
+                                                   double* __restrict__ part, unsigned* __restrict__ ticket,
+                                                   double* __restrict__ sc) {
+    __shared__ double red[kKB / 64 * 1];
+    const int64_t r = (int64_t)blockIdx.x * kKB + threadIdx.x;
+    double v[1] = {0.0};
+    if (r < n) {
+        const double x = rho[r];
+        q0[r] = x;
+        v[0] = x * x;
+    }
+    block_sums<1>(v, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+    if (!last_block(ticket)) return;
+    __shared__ double sums[1];
+    sum_partials(part, gridDim.x, 1, sums);
+    if (threadIdx.x == 0) {
+        const double beta = sqrt(sums[0]);
+        sc[S_BETA] = beta;
+        sc[S_SCALE + 0] = beta > 0.0 ? 1.0 / beta : 0.0;
+        *ticket = 0u;
+    }
+}
+
+// w = q_{i-1} A (row i of Qraw), first projections <Qraw_j, w> (j < i) and ||w||^2.
+template <int I>
+__global__ __launch_bounds__(kKB) void k_kry_spmv_dot(KryOp op, double* __restrict__ Q, int64_t n,
+                                                      double* __restrict__ part, unsigned* __restrict__ ticket,
+                                                      double* __restrict__ sc) {
+    __shared__ double red[(I + 1) * (kKB / 64)];
+    const int64_t r = (int64_t)blockIdx.x * kKB + threadIdx.x;
+    const int nblk = gridDim.x;
+    double v[I + 1];
+#pragma unroll
+    for (int m = 0; m <= I; ++m) v[m] = 0.0;
+    if (r < n) {
+        const double* __restrict__ x = Q + (size_t)(I - 1) * n;
+        const int64_t s = r >> 6;
+        const int lane = (int)(r & 63);
+        const int32_t b = op.slice_off[s], e = op.slice_off[s + 1];
+        double acc = 0.0;
+        for (int32_t k = b + lane; k < e; k += 64) acc += op.val[k] * x[op.col[k]];
+        const double w = sc[S_SCALE + I - 1] * acc;
+        Q[(size_t)I * n + r] = w;
+#pragma unroll
+        for (int j = 0; j < I; ++j) v[j] = Q[(size_t)j * n + r] * w;
+        v[I] = w * w;
+    }
+    block_sums<I + 1>(v, red);
+    if (threadIdx.x <= I) part[(size_t)threadIdx.x * nblk + blockIdx.x] = red[threadIdx.x * (kKB / 64)];
+    if (!last_block(ticket)) return;
+    __shared__ double sums[I + 1];
+    sum_partials(part, nblk, I + 1, sums);
+    if (threadIdx.x < I) sc[S_H1 + threadIdx.x] = sc[S_SCALE + threadIdx.x] * sums[threadIdx.x];
+    if (threadIdx.x == 0) {
+        sc[S_WN2] = sums[I];
+        *ticket = 0u;
+    }
+}
+
+// w -= sum_j h1_j q_j; second projections.  Writes H[j][I-1] = h1_j + h2_j.
+template <int I>
+__global__ __launch_bounds__(kKB) void k_kry_orth_dot(double* __restrict__ Q, int64_t n, int kappa,
+                                                      double* __restrict__ H, double* __restrict__ part,
+                                                      unsigned* __restrict__ ticket, double* __restrict__ sc) {
+    __shared__ double red[I * (kKB / 64)];
+    __shared__ double coef[I];
+    if (threadIdx.x < I) coef[threadIdx.x] = sc[S_H1 + threadIdx.x] * sc[S_SCALE + threadIdx.x];
+    __syncthreads();
+    const int64_t r = (int64_t)blockIdx.x * kKB + threadIdx.x;
+    const int nblk = gridDim.x;
+    double v[I];
+#pragma unroll
+    for (int m = 0; m < I; ++m) v[m] = 0.0;
+    if (r < n) {
+        double qj[I];
+#pragma unroll
+        for (int j = 0; j < I; ++j) qj[j] = Q[(size_t)j * n + r];
+        double w = Q[(size_t)I * n + r];
+#pragma unroll
+        for (int j = 0; j < I; ++j) w -= coef[j] * qj[j];
+        Q[(size_t)I * n + r] = w;
+#pragma unroll
+        for (int j = 0; j < I; ++j) v[j] = qj[j] * w;
+    }
+    block_sums<I>(v, red);
+    if (threadIdx.x < I) part[(size_t)threadIdx.x * nblk + blockIdx.x] = red[threadIdx.x * (kKB / 64)];
+    if (!last_block(ticket)) return;
+    __shared__ double sums[I];
+    sum_partials(part, nblk, I, sums);
+    if (threadIdx.x < I) {
+        const double h2 = sc[S_SCALE + threadIdx.x] * sums[threadIdx.x];
+        sc[S_H2 + threadIdx.x] = h2;
+        H[threadIdx.x * kappa + (I - 1)] = sc[S_H1 + threadIdx.x] + h2;
+    }
+    if (threadIdx.x == 0) *ticket = 0u;
+}
+
+// w -= sum_j h2_j q_j; ||w|| -> H[I][I-1], scale[I] (0 after a breakdown).
+template <int I>
+__global__ __launch_bounds__(kKB) void k_kry_orth_norm(double* __restrict__ Q, int64_t n, int kappa,
+                                                       double* __restrict__ H, double* __restrict__ part,
+                                                       unsigned* __restrict__ ticket, double* __restrict__ sc) {
+    __shared__ double red[kKB / 64];
+    __shared__ double coef[I];
+    if (threadIdx.x < I) coef[threadIdx.x] = sc[S_H2 + threadIdx.x] * sc[S_SCALE + threadIdx.x];
+    __syncthreads();
+    const int64_t r = (int64_t)blockIdx.x * kKB + threadIdx.x;
+    double v[1] = {0.0};
+    if (r < n) {
+        double w = Q[(size_t)I * n + r];
+#pragma unroll
+        for (int j = 0; j < I; ++j) w -= coef[j] * Q[(size_t)j * n + r];
+        Q[(size_t)I * n + r] = w;
+        v[0] = w * w;
+    }
+    block_sums<1>(v, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+    if (!last_block(ticket)) return;
+    __shared__ double sums[1];
+    sum_partials(part, gridDim.x, 1, sums);
+    if (threadIdx.x == 0) {
+        const double h = sqrt(sums[0]);
+        const bool brk = !(h > kBreakRel * sqrt(sc[S_WN2]));
+        H[I * kappa + (I - 1)] = brk ? 0.0 : h;
+        sc[S_SCALE + I] = brk ? 0.0 : 1.0 / h;
+        *ticket = 0u;
+    }
+}
+
+// E = exp(H dt) for the kappa x kappa Hessenberg H (one workgroup, LDS);
+// c_i = beta * E[i][0] * scale[i] (the coefficient of Qraw[i]).  Clears H
+// for the next step.
+__global__ __launch_bounds__(kKB) void k_kry_expm(double* __restrict__ H, int kappa, double dt,
+                                                  double* __restrict__ sc) {
+    __shared__ double M[kKMax * kKMax], T[kKMax * kKMax], U[kKMax * kKMax];
+    __shared__ double colsum[kKMax];
+    __shared__ int s_sq;
+    const int kk = kappa * kappa;
+    for (int e = threadIdx.x; e < kk; e += kKB) M[e] = H[e] * dt;
+    __syncthreads();
+    // ||M||_1 -> number of squarings so that ||M / 2^s||_1 <= 1/4
+    for (int c = threadIdx.x; c < kappa; c += kKB) {
+        double s = 0.0;
+        for (int r = 0; r < kappa; ++r) s += fabs(M[r * kappa + c]);
+        colsum[c] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double nrm = 0.0;
+        for (int c = 0; c < kappa; ++c) nrm = fmax(nrm, colsum[c]);
+        int s = 0;
+        while (nrm > 0.25 && s < 1000) { nrm *= 0.5; ++s; }
+        s_sq = s;
+    }
+    __syncthreads();
+    const int s = s_sq;
+    const double sc2 = ldexp(1.0, -s);
+    for (int e = threadIdx.x; e < kk; e += kKB) {
+        M[e] *= sc2;
+        T[e] = ((e / kappa) == (e % kappa)) ? 1.0 : 0.0;  // Horner start: I
+    }
+    __syncthreads();
+    // Horner: T = I + M T / k for k = p .. 1
+    for (int k = kTaylor; k >= 1; --k) {
+        const double inv = 1.0 / (double)k;
+        for (int e = threadIdx.x; e < kk; e += kKB) {
+            const int r = e / kappa, c = e % kappa;
+            double acc = 0.0;
+            for (int q = 0; q < kappa; ++q) acc += M[r * kappa + q] * T[q * kappa + c];
+            U[e] = (r == c ? 1.0 : 0.0) + acc * inv;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < kk; e += kKB) T[e] = U[e];
+        __syncthreads();
+    }
+    for (int q2 = 0; q2 < s; ++q2) {
+        for (int e = threadIdx.x; e < kk; e += kKB) {
+            const int r = e / kappa, c = e % kappa;
+            double acc = 0.0;
+            for (int q = 0; q < kappa; ++q) acc += T[r * kappa + q] * T[q * kappa + c];
+            U[e] = acc;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < kk; e += kKB) T[e] = U[e];
+        __syncthreads();
+    }
+    const double beta = sc[S_BETA];
+    for (int i = threadIdx.x; i < kappa; i += kKB) sc[S_C + i] = beta * T[i * kappa + 0] * sc[S_SCALE + i];
+    for (int e = threadIdx.x; e < kk; e += kKB) H[e] = 0.0;
+}
+
+// rho = sum_i c_i Qraw[i] -> Qraw[0] (next start) and out (if given);
+// ||rho||^2 -> beta, scale[0] of the next step.
+__global__ __launch_bounds__(kKB) void k_kry_combine(double* __restrict__ Q, int64_t n, int kappa,
+                                                     double* __restrict__ out, double* __restrict__ part,
+                                                     unsigned* __restrict__ ticket, double* __restrict__ sc) {
+    __shared__ double red[kKB / 64];
+    __shared__ double c[kKMax];
+    if (threadIdx.x < kappa) c[threadIdx.x] = sc[S_C + threadIdx.x];
+    __syncthreads();
+    const int64_t r = (int64_t)blockIdx.x * kKB + threadIdx.x;
+    double v[1] = {0.0};
+    if (r < n) {
+        double x = 0.0;
+        for (int i = 0; i < kappa; ++i) x += c[i] * Q[(size_t)i * n + r];
+        Q[r] = x;
+        if (out) out[r] = x;
+        v[0] = x * x;
+    }
+    block_sums<1>(v, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+    if (!last_block(ticket)) return;
+    __shared__ double sums[1];
+    sum_partials(part, gridDim.x, 1, sums);
+    if (threadIdx.x == 0) {
+        const double beta = sqrt(sums[0]);
+        sc[S_BETA] = beta;
+        sc[S_SCALE + 0] = beta > 0.0 ? 1.0 / beta : 0.0;
+        *ticket = 0u;
+    }
+}
+
+__global__ void k_kry_copy(const double* __restrict__ a, double* __restrict__ b, int64_t n) {
+    const int64_t r = (int64_t)blockIdx.x * kKB + threadIdx.x;
+    if (r < n) b[r] = a[r];
+}
+
+__global__ void k_kry_zero(double* __restrict__ p, int64_t n) {
+    const int64_t r = (int64_t)blockIdx.x * kKB + threadIdx.x;
+    if (r < n) p[r] = 0.0;
+}
+
+__global__ void k_kry_zero_u32(unsigned* __restrict__ p, int n) {
+    const int r = blockIdx.x * kKB + threadIdx.x;
+    if (r < n) p[r] = 0u;
+}
+
+// per-iteration launch tables (I = 1 .. kKMax - 1)
+using SpmvFn = void (*)(KryOp, double*, int64_t, double*, unsigned*, double*);
+using OrthFn = void (*)(double*, int64_t, int, double*, double*, unsigned*, double*);
+
+template <int... Is>
+struct Tables {
+    static constexpr SpmvFn spmv[sizeof...(Is)] = {k_kry_spmv_dot<Is + 1>...};
+    static constexpr OrthFn dot[sizeof...(Is)] = {k_kry_orth_dot<Is + 1>...};
+    static constexpr OrthFn norm[sizeof...(Is)] = {k_kry_orth_norm<Is + 1>...};
+};
+template <int N, int... Is>
+struct MakeTables : MakeTables<N - 1, N - 1, Is...> {};
+template <int... Is>
+struct MakeTables<0, Is...> {
+    using type = Tables<Is...>;
+};
+using KryTables = MakeTables<kKMax - 1>::type;
+
+}  // namespace mjp
+
+using namespace mjp;
+
+struct mjp_krylov {
+    int device = 0;
+    int64_t n = 0;
+    int32_t kappa = 20;
+    double dt_factor = 2.0;
+    double m_theta = 0.0;
+    int32_t n_slices = 0;
+    DevBuf slice_off, col, val;  // A^T sliced ELL
+    DevBuf Q;                    // kappa x n FP64, unnormalised basis
+    DevBuf H;                    // kappa x kappa FP64
+    DevBuf part;                 // (kKMax + 1) x nblk FP64 partials
+    DevBuf sc;                   // S_COUNT FP64 scalars
+    DevBuf ticket;               // one unsigned per kernel kind
+};
+
+extern "C" {
+
+void mjp_krylov_opts_default(mjp_krylov_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->kappa = 20;
+    o->dt_factor = 2.0;
+}
+
+mjp_status mjp_krylov_create(const mjp_csr* A, const mjp_krylov_opts* opts, mjp_krylov** out) {
+    clear_error();
+    MJP_CHECK(out, MJP_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    MJP_CHECK(opts, MJP_E_INVALID_ARG, "opts is NULL");
+    MJP_CHECK(opts->kappa >= 2 && opts->kappa <= kKMax, MJP_E_INVALID_ARG, "kappa must be in [2, %d]", kKMax);
+    MJP_CHECK(std::isfinite(opts->dt_factor) && opts->dt_factor > 0.0, MJP_E_INVALID_ARG,
+              "dt_factor must be finite and > 0");
+    double m_theta = 0.0;
+    std::vector<double> diag;
+    mjp_status st = check_generator_csr(A, 0, &m_theta, &diag);
+    if (st) return st;
+    const int32_t n = A->n;
+    // A^T in pull form: output row m collects (source n, a_nm) for all n
+    std::vector<int32_t> cnt((size_t)n, 0);
+    for (int32_t r = 0; r < n; ++r)
+        for (int32_t i = A->row_ptr[r]; i < A->row_ptr[r + 1]; ++i) cnt[(size_t)A->col_idx[i]]++;
+    const int32_t n_slices = (n + kSlice - 1) / kSlice;
+    std::vector<int32_t> slice_off((size_t)n_slices + 1, 0);
+    for (int32_t s = 0; s < n_slices; ++s) {
+        int32_t w = 0;
+        for (int32_t r = s * kSlice; r < std::min(n, (s + 1) * kSlice); ++r) w = std::max(w, cnt[(size_t)r]);
+        const int64_t next = (int64_t)slice_off[(size_t)s] + (int64_t)w * kSlice;
+        MJP_CHECK(next <= INT32_MAX, MJP_E_WORKSPACE, "operator too large");
+        slice_off[(size_t)s + 1] = (int32_t)next;
+    }
+    const size_t total = (size_t)slice_off[(size_t)n_slices];
+    std::vector<int32_t> hcol(total);
+    std::vector<double> hval(total, 0.0);
+    for (int32_t s = 0; s < n_slices; ++s) {  // padding: own row, value 0
+        const int32_t w = (slice_off[(size_t)s + 1] - slice_off[(size_t)s]) / kSlice;
+        for (int32_t j = 0; j < w; ++j)
+            for (int32_t l = 0; l < kSlice; ++l)
+                hcol[(size_t)slice_off[(size_t)s] + (size_t)j * kSlice + l] = std::min(n - 1, s * kSlice + l);
+    }
+    std::vector<int32_t> fill((size_t)n, 0);
+    for (int32_t r = 0; r < n; ++r)
+        for (int32_t i = A->row_ptr[r]; i < A->row_ptr[r + 1]; ++i) {
+            const int32_t m = A->col_idx[i];
+            const int32_t s = m / kSlice, l = m % kSlice;
+            const size_t at = (size_t)slice_off[(size_t)s] + (size_t)fill[(size_t)m] * kSlice + l;
+            hcol[at] = r;
+            hval[at] = A->val[i];
+            fill[(size_t)m]++;
+        }
+
+    mjp_krylov* k = new (std::nothrow) mjp_krylov();
+    MJP_CHECK(k, MJP_E_DEVICE, "out of host memory");
+    auto bail = [&](mjp_status s) {
+        mjp_krylov_destroy(k);
+        return s;
+    };
+    if (hipGetDevice(&k->device) != hipSuccess) return bail(fail(MJP_E_DEVICE, "no HIP device available"));
+    k->n = n;
+    k->kappa = opts->kappa;
+    k->dt_factor = opts->dt_factor;
+    k->m_theta = m_theta;
+    k->n_slices = n_slices;
+    const int64_t nblk = (n + kKB - 1) / kKB;
+    if ((st = k->slice_off.reserve(sizeof(int32_t) * slice_off.size())) ||
+        (st = k->col.reserve(sizeof(int32_t) * std::max<size_t>(total, 1))) ||
+        (st = k->val.reserve(sizeof(double) * std::max<size_t>(total, 1))) ||
+        (st = k->Q.reserve(sizeof(double) * (size_t)k->kappa * (size_t)n)) ||
+        (st = k->H.reserve(sizeof(double) * kKMax * kKMax)) ||
+        (st = k->part.reserve(sizeof(double) * (kKMax + 1) * (size_t)nblk)) ||
+        (st = k->sc.reserve(sizeof(double) * S_COUNT)) || (st = k->ticket.reserve(sizeof(unsigned) * 64)))
+        return bail(st);
+    auto up = [&](DevBuf& b, const void* h, size_t bytes) -> mjp_status {
+        if (bytes) MJP_HIP(hipMemcpy(b.ptr, h, bytes, hipMemcpyHostToDevice));
+        return MJP_OK;
+    };
+    if ((st = up(k->slice_off, slice_off.data(), sizeof(int32_t) * slice_off.size())) ||
+        (st = up(k->col, hcol.data(), sizeof(int32_t) * total)) ||
+        (st = up(k->val, hval.data(), sizeof(double) * total)))
+        return bail(st);
+    std::vector<double> zeros(kKMax * kKMax, 0.0);
+    std::vector<unsigned> z32(64, 0u);
+    if ((st = up(k->H, zeros.data(), sizeof(double) * kKMax * kKMax)) ||
+        (st = up(k->ticket, z32.data(), sizeof(unsigned) * 64)))
+        return bail(st);
+    *out = k;
+    return MJP_OK;
+}
+
+void mjp_krylov_destroy(mjp_krylov* k) {
+    if (!k) return;
+    int prev = 0;
+    const bool restore = hipGetDevice(&prev) == hipSuccess;
+    if (restore) (void)hipSetDevice(k->device);
+    k->slice_off.release();
+    k->col.release();
+    k->val.release();
+    k->Q.release();
+    k->H.release();
+    k->part.release();
+    k->sc.release();
+    k->ticket.release();
+    if (restore) (void)hipSetDevice(prev);
+    delete k;
+}
+
+int32_t mjp_krylov_n(const mjp_krylov* k) { return k ? (int32_t)k->n : 0; }
+
+mjp_status mjp_krylov_expv(mjp_krylov* k, const double* rho0_d, int32_t n_t, const double* t_h, double* out_d,
+                           mjp_krylov_info* info_h, mjp_stream_t stream) {
+    clear_error();
+    MJP_CHECK(k, MJP_E_INVALID_ARG, "handle is NULL");
+    MJP_CHECK(n_t >= 1, MJP_E_INVALID_ARG, "n_t must be >= 1");
+    MJP_CHECK(t_h && rho0_d && out_d, MJP_E_INVALID_ARG, "null argument");
+    for (int j = 0; j < n_t; ++j)
+        MJP_CHECK(std::isfinite(t_h[j]) && t_h[j] >= 0.0, MJP_E_INVALID_ARG, "t[%d] must be finite and >= 0", j);
+    int dev = 0;
+    MJP_HIP(hipGetDevice(&dev));
+    MJP_CHECK(dev == k->device, MJP_E_INVALID_ARG, "handle belongs to device %d, current device is %d", k->device, dev);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const int64_t n = k->n;
+    const int kappa = k->kappa;
+    const unsigned nblk = (unsigned)((n + kKB - 1) / kKB);
+    double* Q = k->Q.as<double>();
+    double* H = k->H.as<double>();
+    double* part = k->part.as<double>();
+    double* sc = k->sc.as<double>();
+    unsigned* tk = k->ticket.as<unsigned>();
+    KryOp op{k->slice_off.as<int32_t>(), k->col.as<int32_t>(), k->val.as<double>()};
+
+    std::vector<int> order((size_t)n_t);
+    for (int j = 0; j < n_t; ++j) order[(size_t)j] = j;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return t_h[a] < t_h[b]; });
+    const double dt = k->m_theta > 0.0 ? k->dt_factor * kappa / k->m_theta : INFINITY;
+
+    hipLaunchKernelGGL(k_kry_start, dim3(nblk), dim3(kKB), 0, st, rho0_d, Q, n, part, tk + 0, sc);
+    double tau = 0.0;
+    int64_t steps = 0;
+    for (int idx : order) {
+        const double t = t_h[idx];
+        double* outj = out_d + (size_t)idx * n;
+        if (!(t - tau > 0.0) || k->m_theta == 0.0) {  // already there (t = 0, repeated time, or A = 0)
+            hipLaunchKernelGGL(k_kry_copy, dim3(nblk), dim3(kKB), 0, st, Q, outj, n);
+            continue;
+        }
+        while (t - tau > 0.0) {
+            const double h = std::min(dt, t - tau);
+            const bool lands = h == t - tau;
+            for (int i = 1; i < kappa; ++i) {
+                hipLaunchKernelGGL(KryTables::spmv[i - 1], dim3(nblk), dim3(kKB), 0, st, op, Q, n, part, tk + 1, sc);
+                hipLaunchKernelGGL(KryTables::dot[i - 1], dim3(nblk), dim3(kKB), 0, st, Q, n, kappa, H, part, tk + 2,
+                                   sc);
+                hipLaunchKernelGGL(KryTables::norm[i - 1], dim3(nblk), dim3(kKB), 0, st, Q, n, kappa, H, part, tk + 3,
+                                   sc);
+            }
+            hipLaunchKernelGGL(k_kry_expm, dim3(1), dim3(kKB), 0, st, H, kappa, h, sc);
+            hipLaunchKernelGGL(k_kry_combine, dim3(nblk), dim3(kKB), 0, st, Q, n, kappa, lands ? outj : nullptr, part,
+                               tk + 4, sc);
+            tau = lands ? t : tau + h;
+            ++steps;
+        }
+    }
+    MJP_HIP(hipGetLastError());
+    if (info_h) {
+        std::memset(info_h, 0, sizeof(*info_h));
+        info_h->m_theta = k->m_theta;
+        info_h->dt = dt;
+        info_h->steps = steps;
+        info_h->kappa = kappa;
+    }
+    return MJP_OK;
+}
+
+}  // extern "C"

@@ -293,6 +293,7 @@ void mjp_plan_destroy(mjp_plan* p) {
     for (auto& b : p->rho) b.release();
     p->comp.release();
     p->wait.release();
+    p->sflag.release();
     p->wtab.release();
     p->tinfo.release();
     p->partials.release();
@@ -302,13 +303,14 @@ void mjp_plan_destroy(mjp_plan* p) {
     delete p;
 }
 
-mjp_status mjp_plan_create_csr(const mjp_csr* A, const mjp_opts* opts, mjp_plan** out) {
-    clear_error();
-    MJP_CHECK(out, MJP_E_INVALID_ARG, "out is NULL");
-    *out = nullptr;
+}  // extern "C"
+
+namespace mjp {
+// Structure, sign and row-sum checks of a generator in CSR form (Eq. A_def:
+// non-negative off-diagonal rates, rows summing to 0, or to <= 0 when
+// leaky).  Returns m_theta = max |a_nn| and the diagonal.
+mjp_status check_generator_csr(const mjp_csr* A, int leaky, double* m_theta_out, std::vector<double>* diag_out) {
     MJP_CHECK(A, MJP_E_INVALID_ARG, "A is NULL");
-    mjp_status st = check_opts(opts);
-    if (st) return st;
     const int32_t n = A->n;
     MJP_CHECK(n >= 1, MJP_E_INVALID_ARG, "n must be >= 1 (got %d)", n);
     MJP_CHECK(A->nnz >= 0, MJP_E_INVALID_ARG, "nnz must be >= 0");
@@ -316,11 +318,9 @@ mjp_status mjp_plan_create_csr(const mjp_csr* A, const mjp_opts* opts, mjp_plan*
               "null CSR array");
     MJP_CHECK(A->row_ptr[0] == 0 && A->row_ptr[n] == A->nnz, MJP_E_INVALID_ARG,
               "row_ptr must start at 0 and end at nnz");
-    const int leaky = opts->truncation == MJP_LEAKY;
-
-    // validation pass: structure, signs, and the exit rates
     double m_theta = 0.0;
-    std::vector<double> diag((size_t)n, 0.0);
+    std::vector<double>& diag = *diag_out;
+    diag.assign((size_t)n, 0.0);
     for (int32_t r = 0; r < n; ++r) {
         const int32_t b = A->row_ptr[r], e = A->row_ptr[r + 1];
         MJP_CHECK(b <= e, MJP_E_INVALID_ARG, "row_ptr decreases at row %d", r);
@@ -350,6 +350,25 @@ mjp_status mjp_plan_create_csr(const mjp_csr* A, const mjp_opts* opts, mjp_plan*
             MJP_CHECK(std::fabs(rowsum) <= slack, MJP_E_NOT_GENERATOR,
                       "row %d sums to %g, not 0 (conservative truncation)", r, rowsum);
     }
+    *m_theta_out = m_theta;
+    return MJP_OK;
+}
+}  // namespace mjp
+
+extern "C" {
+
+mjp_status mjp_plan_create_csr(const mjp_csr* A, const mjp_opts* opts, mjp_plan** out) {
+    clear_error();
+    MJP_CHECK(out, MJP_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    MJP_CHECK(A, MJP_E_INVALID_ARG, "A is NULL");
+    mjp_status st = check_opts(opts);
+    if (st) return st;
+    const int leaky = opts->truncation == MJP_LEAKY;
+    double m_theta = 0.0;
+    std::vector<double> diag;
+    if ((st = check_generator_csr(A, leaky, &m_theta, &diag))) return st;
+    const int32_t n = A->n;
 
     mjp_plan* p = new (std::nothrow) mjp_plan();
     MJP_CHECK(p, MJP_E_DEVICE, "out of host memory");

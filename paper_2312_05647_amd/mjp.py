@@ -73,6 +73,19 @@ class mjp_train_cfg(ctypes.Structure):
                 ("weight_decay", ctypes.c_float), ("seed", ctypes.c_uint64)]
 
 
+class mjp_krylov_opts(ctypes.Structure):
+    _fields_ = [("kappa", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("dt_factor", ctypes.c_double),
+                ("reserved", ctypes.c_int32 * 6)]
+
+
+class mjp_krylov_info(ctypes.Structure):
+    _fields_ = [("m_theta", ctypes.c_double), ("dt", ctypes.c_double), ("steps", ctypes.c_int64),
+                ("kappa", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
 _lib = None
 
 # (name, restype, argtypes) of every exported function
@@ -99,6 +112,11 @@ _SIGS = [
     ("mjp_surrogate_set_params", ctypes.c_int, [_P, _P, ctypes.c_int64]),
     ("mjp_surrogate_save", ctypes.c_int, [_P, ctypes.c_char_p]),
     ("mjp_surrogate_load", ctypes.c_int, [ctypes.c_char_p, _P]),
+    ("mjp_krylov_opts_default", None, [_P]),
+    ("mjp_krylov_create", ctypes.c_int, [_P, _P, _P]),
+    ("mjp_krylov_destroy", None, [_P]),
+    ("mjp_krylov_n", ctypes.c_int32, [_P]),
+    ("mjp_krylov_expv", ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, _P, _P]),
     ("mjp_last_error", ctypes.c_char_p, []),
     ("mjp_version", ctypes.c_char_p, []),
 ]
@@ -225,6 +243,44 @@ def mjp_expv_batched(plans, rho0s, times_list, outs, info: bool = False, stream=
     _check(lib().mjp_expv_batched(B, P, R, NT, TP, O, ctypes.cast(inf, ctypes.c_void_p) if info else None,
                                   _stream(stream)))
     return [i.as_dict() for i in inf] if info else None
+
+
+# ------------------------------------------------------- Krylov (Method #5)
+
+def mjp_krylov_opts_default(**kw) -> mjp_krylov_opts:
+    o = mjp_krylov_opts()
+    lib().mjp_krylov_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def mjp_krylov_create(row_ptr, col, val, opts: mjp_krylov_opts | None = None) -> int:
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    val = np.ascontiguousarray(val, dtype=np.float64)
+    A = mjp_csr(len(row_ptr) - 1, len(col), _ptr(row_ptr), _ptr(col), _ptr(val))
+    opts = opts or mjp_krylov_opts_default()
+    h = ctypes.c_void_p()
+    _check(lib().mjp_krylov_create(ctypes.byref(A), ctypes.byref(opts), ctypes.byref(h)))
+    return h.value
+
+
+def mjp_krylov_destroy(k: int) -> None:
+    lib().mjp_krylov_destroy(k)
+
+
+def mjp_krylov_n(k: int) -> int:
+    return int(lib().mjp_krylov_n(k))
+
+
+def mjp_krylov_expv(k: int, rho0, times, out, stream=None) -> dict:
+    """out[j] = rho(times[j]); rho0 [N] and out [n_t, N] are float64 CUDA
+    tensors.  Returns the info dict (step count) filled on the host."""
+    t = np.ascontiguousarray(times, dtype=np.float64).reshape(-1)
+    inf = mjp_krylov_info()
+    _check(lib().mjp_krylov_expv(k, _ptr(rho0), len(t), _ptr(t), _ptr(out), ctypes.byref(inf), _stream(stream)))
+    return inf.as_dict()
 
 
 def make_obs(T, obs, x0=(0, 0)):

@@ -43,7 +43,8 @@ def test_struct_layouts_match_header(tmp_path):
     import subprocess
     structs = {"mjp_opts": mjp.mjp_opts, "mjp_info": mjp.mjp_info, "mjp_csr": mjp.mjp_csr,
                "mjp_model": mjp.mjp_model, "mjp_obs": mjp.mjp_obs, "mjp_mlp_cfg": mjp.mjp_mlp_cfg,
-               "mjp_train_cfg": mjp.mjp_train_cfg}
+               "mjp_train_cfg": mjp.mjp_train_cfg, "mjp_krylov_opts": mjp.mjp_krylov_opts,
+               "mjp_krylov_info": mjp.mjp_krylov_info}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mjp.h"', "int main(void) {"]
     for name, cls in structs.items():
         lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
@@ -208,3 +209,33 @@ def test_surrogate_load_rejects_foreign_file(tmp_path):
     p.write_bytes(b"NOTASURROGATE" * 4)
     h = ctypes.c_void_p()
     assert mjp.lib().mjp_surrogate_load(str(p).encode(), ctypes.byref(h)) == mjp.MJP_E_INVALID_ARG
+
+
+@pytest.mark.parametrize("kw,expect", [
+    (dict(kappa=1), mjp.MJP_E_INVALID_ARG),
+    (dict(kappa=33), mjp.MJP_E_INVALID_ARG),
+    (dict(dt_factor=0.0), mjp.MJP_E_INVALID_ARG),
+    (dict(dt_factor=float("nan")), mjp.MJP_E_INVALID_ARG),
+])
+def test_krylov_option_validation(kw, expect):
+    assert status_of(mjp.mjp_krylov_create, *GOOD, mjp.mjp_krylov_opts_default(**kw)) == expect
+
+
+def test_krylov_operator_validation():
+    bad = _csr([0, 2, 4], [0, 1, 0, 1], [-1.0, 1.0, -2.0, 2.0])  # negative off-diagonal rate
+    assert status_of(mjp.mjp_krylov_create, *bad) == mjp.MJP_E_NOT_GENERATOR
+    off = _csr([0, 2, 4], [0, 1, 0, 1], [-1.0, 1.5, 2.0, -2.0])  # row 0 sums to 0.5
+    assert status_of(mjp.mjp_krylov_create, *off) == mjp.MJP_E_NOT_GENERATOR
+    L = mjp.lib()
+    assert L.mjp_krylov_expv(None, None, 1, None, None, None, None) == mjp.MJP_E_INVALID_ARG
+    assert L.mjp_krylov_n(None) == 0
+    L.mjp_krylov_destroy(None)
+    o = mjp.mjp_krylov_opts_default()
+    assert o.kappa == 20 and o.dt_factor == 2.0
+
+
+def test_krylov_no_device_reports_device_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    assert status_of(mjp.mjp_krylov_create, *GOOD) == mjp.MJP_E_DEVICE
