@@ -122,6 +122,46 @@ def bench_small(torch, mjp, reps: int = 20):
     return res
 
 
+def krylov_bytes_per_step(kappa: int, n: int, nnz: int) -> float:
+    """Bytes the Krylov step streams: per Arnoldi iteration i = 1..kappa-1 the
+    product (12 B per stored entry of A^T, the gathered and written vectors)
+    and three passes that read the i earlier basis vectors (projections,
+    reorthogonalisation, norm) and read/write the new one; then the
+    combination reads kappa vectors and writes one."""
+    per_i = sum(12 * nnz + 8 * n * (3 * i + 6) for i in range(1, kappa))
+    return per_i + 8 * n * (kappa + 1)
+
+
+def bench_krylov(torch, mjp, rp, ci, va, n, reps: int = 3):
+    """Krylov propagator (Method #5) on the same N = 10^6 solve, FP64: the
+    paper's step (dt_factor 2) and a converged one (dt_factor 0.5)."""
+    res = {}
+    r0 = torch.zeros(n, dtype=torch.float64, device="cuda")
+    r0[0] = 1.0
+    out = torch.empty((1, n), dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    for f in (2.0, 0.5):
+        h = mjp.mjp_krylov_create(rp, ci, va, mjp.mjp_krylov_opts_default(dt_factor=f))
+        try:
+            info = mjp.mjp_krylov_expv(h, r0, [T_SOLVE], out, stream=stream)
+            torch.cuda.synchronize()
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record(stream)
+            for _ in range(reps):
+                mjp.mjp_krylov_expv(h, r0, [T_SOLVE], out, stream=stream)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+        finally:
+            mjp.mjp_krylov_destroy(h)
+        sec = ev0.elapsed_time(ev1) / 1e3 / reps
+        ab = info["steps"] * krylov_bytes_per_step(info["kappa"], n, len(ci))
+        res[f"dt_factor_{f:g}"] = {"ms_per_solve": sec * 1e3, "steps": info["steps"], "kappa": info["kappa"],
+                                   "streamed_GBps": ab / sec / 1e9, "frac_of_hbm_peak": ab / sec / 1e9 / HBM_PEAK_GBS,
+                                   "result": out[0].cpu().numpy()}
+        log(f"[bench] krylov f={f}: {sec * 1e3:.2f} ms/solve, {info['steps']} steps, {ab / sec / 1e9:.0f} GB/s")
+    return res
+
+
 def bench_loglik(torch, mjp, reps: int = 3):
     """Batched log-likelihoods: 4096 draws log-uniform over a decade around
     (50, 1, 0.5, 0.5), 20 collection times 0.5..10 with 50 snapshots each,
@@ -233,7 +273,7 @@ def main():
     ap.add_argument("--variant", type=int, default=0, help="0 auto, 1 stepwise, 2 persistent")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the secondary measurements")
-    ap.add_argument("--part", choices=["all", "loglik", "da", "small"], default="all",
+    ap.add_argument("--part", choices=["all", "loglik", "da", "small", "krylov"], default="all",
                     help="run only one secondary leg (for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the byte counters)")
@@ -261,6 +301,12 @@ def main():
         return
     if args.part == "small":
         print(json.dumps({"small_configs": bench_small(torch, mjp)}))
+        return
+    if args.part == "krylov":
+        rp, ci, va = mjp.mjp_model_csr(mjp.make_model(mjp.MJP_MODEL_CASCADE2, THETA, [S1, S2]))
+        kr = bench_krylov(torch, mjp, rp, ci, va, S1 * S2)
+        print(json.dumps({"krylov_method5": {k: {kk: vv for kk, vv in v.items() if kk != "result"}
+                                             for k, v in kr.items()}}))
         return
 
     dev = torch.device("cuda:0")
@@ -343,7 +389,12 @@ def main():
                                       "algorithmic_GBps": ab2 / dev2 / 1e9}
         log(f"[bench] {other}: {dev2 * 1e3:.3f} ms/solve")
 
+    kry = None
     if not args.no_extra:
+        kry = bench_krylov(torch, mjp, rp, ci, va, n)
+        result["krylov_method5"] = {k: {kk: vv for kk, vv in v.items() if kk != "result"} for k, v in kry.items()}
+        for k, v in kry.items():  # accuracy against the FP32 R-MJP result (its own L1 vs FP64 is ~3e-7)
+            result["krylov_method5"][k]["l1_vs_rmjp_gpu"] = float(np.abs(v["result"] - got).sum())
         result["small_configs"] = bench_small(torch, mjp)
         result["loglik_batch"] = bench_loglik(torch, mjp)
         result["da_mcmc"] = bench_da(torch, mjp)
@@ -371,6 +422,9 @@ def main():
                                             f"right tail {eps_r:g}), OpenMP over rows"}
         l1 = float(np.abs(got - ref).sum())
         result["parity"] = {"l1_vs_fp64_oracle": l1, "linf": float(np.abs(got - ref).max()), "bar": 1e-6}
+        if kry:
+            for k, v in kry.items():
+                result["krylov_method5"][k]["l1_vs_fp64_oracle"] = float(np.abs(v["result"] - ref).sum())
         log(f"[bench] oracle {cpu_s:.2f} s/solve; GPU L1 vs oracle {l1:.3e}")
 
     print(json.dumps(result), flush=True)

@@ -14,8 +14,8 @@
 //  * The basis is stored unnormalised, Qraw[i] with q_i = scale[i] Qraw[i],
 //    so normalising never needs a pass of its own.
 //  * One Arnoldi iteration = three streaming kernels, each ending in a
-//    deterministic reduction done by the last block to arrive (release fence
-//    + ticket, acquire fence, fixed summation order):
+//    deterministic reduction done by the last block to arrive (device-scope
+//    partials and ticket, fixed summation order):
 //      spmv_dot:  w = q_{i-1} A;  first projections <q_j, w>;  ||w||^2
 //      orth_dot:  w -= sum_j h1_j q_j;  second projections (reorthogonalisation)
 //      orth_norm: w -= sum_j h2_j q_j;  ||w||  -> h_{i,i-1}, scale[i]
@@ -40,6 +40,7 @@ namespace mjp {
 constexpr int kKB = 256;          // threads per block of the streaming kernels
 constexpr int kKMax = 32;         // largest basis
 constexpr int kTaylor = 12;       // Taylor degree of the small exponential
+constexpr int kMaxBlocks = 1024;  // grid of the streaming kernels (4 per CU)
 constexpr double kBreakRel = 1e-12;
 
 // scalar slots (FP64) of the device scalar block
@@ -79,112 +80,162 @@ __device__ __forceinline__ void block_sums(double (&v)[M], double* red) {
     __syncthreads();
 }
 
-// Last-block reduction of partials part[m * nblk + b] for m < count.  Each
-// block has written its partials; returns true in the block that arrives
-// last, which then holds the sums in sums[m].  The ticket is reset there.
-__device__ __forceinline__ bool last_block(unsigned* ticket) {
+// Partials cross blocks through device-scope (agent) stores and loads,
+// which the hardware performs at the device coherence point; a block's
+// partial stores have completed (s_waitcnt vmcnt(0)) before its ticket
+// increment, so the block that takes the last ticket reads them all.  No
+// agent-scope fence is needed (one per block would write back and
+// invalidate the L2 thousands of times per kernel).  The reduction is a
+// two-level tree: the last block of each group of kGroup blocks sums the
+// group's partials, the last group to finish sums the group results.
+constexpr int kGroup = 64;
+constexpr int kCpolSC1 = 16;            // device-scope cache policy of a buffer access
+constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, 32-bit elements, no swizzle
+
+__device__ __forceinline__ void put_partial(double* p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// true in the block taking the last of `arrivals` tickets (the ticket is
+// reset there)
+__device__ __forceinline__ bool arrive_last(unsigned* ticket, unsigned arrivals) {
     __shared__ int is_last;
-    __threadfence();  // publish this block's partials (agent-scope release)
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's partial stores are complete
     __syncthreads();
     if (threadIdx.x == 0) {
-        const unsigned t = atomicAdd(ticket, 1u);
-        is_last = (t == gridDim.x - 1);
+        const unsigned t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        is_last = (t == arrivals - 1);
+        if (is_last) __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
-    if (is_last) __threadfence();  // acquire the other blocks' partials
     return is_last;
 }
 
-__device__ __forceinline__ void sum_partials(const double* part, int nblk, int count, double* sums) {
-    // each wave sums whole rows of partials in block order; rows spread over waves
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int m = wave; m < count; m += kKB / 64) {
+// sums[m] = sum_{b < len} p[m * stride + b] for m < count (count <= 64):
+// eight threads per row, each reading every eighth value in batches of
+// eight device-scope loads, then a fixed tree over the eight threads.
+__device__ __forceinline__ void sum_rows(const double* p, size_t stride, int len, int count, double* sums) {
+    const int sub = threadIdx.x & 7, slot = threadIdx.x >> 3;  // 32 rows per round
+    for (int m0 = 0; m0 < count; m0 += kKB / 8) {
+        const int m = m0 + slot;
         double s = 0.0;
-        for (int b = lane; b < nblk; b += 64) s += part[(size_t)m * nblk + b];
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-        if (lane == 0) sums[m] = s;
+        if (m < count) {
+            const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<double*>(p + (size_t)m * stride), 0, len * 8, kRsrcWord3);
+            for (int b0 = sub; b0 < len; b0 += 64) {
+                double x[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u)  // past len the descriptor returns 0
+                    x[u] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
+                                                          r, (uint32_t)(b0 + 8 * u) * 8u, 0, kCpolSC1));
+#pragma unroll
+                for (int u = 0; u < 8; ++u) s += x[u];
+            }
+        }
+        for (int off = 4; off > 0; off >>= 1) s += __shfl_down(s, off, 8);
+        if (sub == 0 && m < count) sums[m] = s;
     }
     __syncthreads();
+}
+
+// Block partials (count values, already in red[m * waves]) -> the tree.
+// Returns true in the one block that ends holding the totals in sums[].
+struct Tree {
+    double* part;    // [count][nblk]
+    double* part2;   // [count][ngroups]
+    unsigned* tk;    // [1 + ngroups]: top ticket, then one per group
+};
+__device__ __forceinline__ bool tree_sum(const Tree& t, const double* red, int count, double* sums) {
+    const int nblk = gridDim.x, blk = blockIdx.x;
+    const int ngroups = (nblk + kGroup - 1) / kGroup, grp = blk / kGroup;
+    if (threadIdx.x < count) put_partial(t.part + (size_t)threadIdx.x * nblk + blk, red[threadIdx.x * (kKB / 64)]);
+    const int gsize = min(kGroup, nblk - grp * kGroup);
+    if (!arrive_last(t.tk + 1 + grp, (unsigned)gsize)) return false;
+    sum_rows(t.part + (size_t)grp * kGroup, (size_t)nblk, gsize, count, sums);
+    if (threadIdx.x < count) put_partial(t.part2 + (size_t)threadIdx.x * ngroups + grp, sums[threadIdx.x]);
+    if (!arrive_last(t.tk, (unsigned)ngroups)) return false;
+    sum_rows(t.part2, (size_t)ngroups, ngroups, count, sums);
+    return true;
 }
 
 // ---- kernels
 
 // rho -> Qraw[0], ||rho||^2; last block: beta and scale[0].
 __global__ __launch_bounds__(kKB) void k_kry_start(const double* __restrict__ rho, double* __restrict__ q0, int64_t n,
-                                                   double* __restrict__ part, unsigned* __restrict__ ticket,
-                                                   double* __restrict__ sc) {
+                                                   Tree tree, double* __restrict__ sc) {
     __shared__ double red[kKB / 64 * 1];
-    const int64_t r = (int64_t)blockIdx.x * kKB + threadIdx.x;
     double v[1] = {0.0};
-    if (r < n) {
+    for (int64_t r = (int64_t)blockIdx.x * kKB + threadIdx.x; r < n; r += (int64_t)gridDim.x * kKB) {
         const double x = rho[r];
         q0[r] = x;
-        v[0] = x * x;
+        v[0] += x * x;
     }
     block_sums<1>(v, red);
-    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
-    if (!last_block(ticket)) return;
     __shared__ double sums[1];
-    sum_partials(part, gridDim.x, 1, sums);
+    if (!tree_sum(tree, red, 1, sums)) return;
     if (threadIdx.x == 0) {
         const double beta = sqrt(sums[0]);
         sc[S_BETA] = beta;
         sc[S_SCALE + 0] = beta > 0.0 ? 1.0 / beta : 0.0;
-        *ticket = 0u;
     }
 }
 
 // w = q_{i-1} A (row i of Qraw), first projections <Qraw_j, w> (j < i) and ||w||^2.
 template <int I>
-__global__ __launch_bounds__(kKB) void k_kry_spmv_dot(KryOp op, double* __restrict__ Q, int64_t n,
-                                                      double* __restrict__ part, unsigned* __restrict__ ticket,
+__global__ __launch_bounds__(kKB) void k_kry_spmv_dot(KryOp op, double* __restrict__ Q, int64_t n, Tree tree,
                                                       double* __restrict__ sc) {
     __shared__ double red[(I + 1) * (kKB / 64)];
-    const int64_t r = (int64_t)blockIdx.x * kKB + threadIdx.x;
-    const int nblk = gridDim.x;
     double v[I + 1];
 #pragma unroll
     for (int m = 0; m <= I; ++m) v[m] = 0.0;
-    if (r < n) {
-        const double* __restrict__ x = Q + (size_t)(I - 1) * n;
+    const double* __restrict__ x = Q + (size_t)(I - 1) * n;
+    const double xs = sc[S_SCALE + I - 1];
+    for (int64_t r = (int64_t)blockIdx.x * kKB + threadIdx.x; r < n; r += (int64_t)gridDim.x * kKB) {
         const int64_t s = r >> 6;
         const int lane = (int)(r & 63);
-        const int32_t b = op.slice_off[s], e = op.slice_off[s + 1];
+        const int32_t b = op.slice_off[s] + lane;
+        const int wdt = (op.slice_off[s + 1] - op.slice_off[s]) >> 6;
         double acc = 0.0;
-        for (int32_t k = b + lane; k < e; k += 64) acc += op.val[k] * x[op.col[k]];
-        const double w = sc[S_SCALE + I - 1] * acc;
+        int j = 0;
+        for (; j + 4 <= wdt; j += 4) {  // four entries' indices and values, then their gathers
+            int32_t c[4];
+            double a[4], g[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                c[u] = op.col[b + (j + u) * 64];
+                a[u] = op.val[b + (j + u) * 64];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) g[u] = x[c[u]];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc += a[u] * g[u];
+        }
+        for (; j < wdt; ++j) acc += op.val[b + j * 64] * x[op.col[b + j * 64]];
+        const double w = xs * acc;
         Q[(size_t)I * n + r] = w;
 #pragma unroll
-        for (int j = 0; j < I; ++j) v[j] = Q[(size_t)j * n + r] * w;
-        v[I] = w * w;
+        for (int jj = 0; jj < I; ++jj) v[jj] += Q[(size_t)jj * n + r] * w;
+        v[I] += w * w;
     }
     block_sums<I + 1>(v, red);
-    if (threadIdx.x <= I) part[(size_t)threadIdx.x * nblk + blockIdx.x] = red[threadIdx.x * (kKB / 64)];
-    if (!last_block(ticket)) return;
     __shared__ double sums[I + 1];
-    sum_partials(part, nblk, I + 1, sums);
+    if (!tree_sum(tree, red, I + 1, sums)) return;
     if (threadIdx.x < I) sc[S_H1 + threadIdx.x] = sc[S_SCALE + threadIdx.x] * sums[threadIdx.x];
-    if (threadIdx.x == 0) {
-        sc[S_WN2] = sums[I];
-        *ticket = 0u;
-    }
+    if (threadIdx.x == 0) sc[S_WN2] = sums[I];
 }
 
 // w -= sum_j h1_j q_j; second projections.  Writes H[j][I-1] = h1_j + h2_j.
 template <int I>
 __global__ __launch_bounds__(kKB) void k_kry_orth_dot(double* __restrict__ Q, int64_t n, int kappa,
-                                                      double* __restrict__ H, double* __restrict__ part,
-                                                      unsigned* __restrict__ ticket, double* __restrict__ sc) {
+                                                      double* __restrict__ H, Tree tree, double* __restrict__ sc) {
     __shared__ double red[I * (kKB / 64)];
     __shared__ double coef[I];
     if (threadIdx.x < I) coef[threadIdx.x] = sc[S_H1 + threadIdx.x] * sc[S_SCALE + threadIdx.x];
     __syncthreads();
-    const int64_t r = (int64_t)blockIdx.x * kKB + threadIdx.x;
-    const int nblk = gridDim.x;
     double v[I];
 #pragma unroll
     for (int m = 0; m < I; ++m) v[m] = 0.0;
-    if (r < n) {
+    for (int64_t r = (int64_t)blockIdx.x * kKB + threadIdx.x; r < n; r += (int64_t)gridDim.x * kKB) {
         double qj[I];
 #pragma unroll
         for (int j = 0; j < I; ++j) qj[j] = Q[(size_t)j * n + r];
@@ -193,50 +244,42 @@ __global__ __launch_bounds__(kKB) void k_kry_orth_dot(double* __restrict__ Q, in
         for (int j = 0; j < I; ++j) w -= coef[j] * qj[j];
         Q[(size_t)I * n + r] = w;
 #pragma unroll
-        for (int j = 0; j < I; ++j) v[j] = qj[j] * w;
+        for (int j = 0; j < I; ++j) v[j] += qj[j] * w;
     }
     block_sums<I>(v, red);
-    if (threadIdx.x < I) part[(size_t)threadIdx.x * nblk + blockIdx.x] = red[threadIdx.x * (kKB / 64)];
-    if (!last_block(ticket)) return;
     __shared__ double sums[I];
-    sum_partials(part, nblk, I, sums);
+    if (!tree_sum(tree, red, I, sums)) return;
     if (threadIdx.x < I) {
         const double h2 = sc[S_SCALE + threadIdx.x] * sums[threadIdx.x];
         sc[S_H2 + threadIdx.x] = h2;
         H[threadIdx.x * kappa + (I - 1)] = sc[S_H1 + threadIdx.x] + h2;
     }
-    if (threadIdx.x == 0) *ticket = 0u;
 }
 
 // w -= sum_j h2_j q_j; ||w|| -> H[I][I-1], scale[I] (0 after a breakdown).
 template <int I>
 __global__ __launch_bounds__(kKB) void k_kry_orth_norm(double* __restrict__ Q, int64_t n, int kappa,
-                                                       double* __restrict__ H, double* __restrict__ part,
-                                                       unsigned* __restrict__ ticket, double* __restrict__ sc) {
+                                                       double* __restrict__ H, Tree tree, double* __restrict__ sc) {
     __shared__ double red[kKB / 64];
     __shared__ double coef[I];
     if (threadIdx.x < I) coef[threadIdx.x] = sc[S_H2 + threadIdx.x] * sc[S_SCALE + threadIdx.x];
     __syncthreads();
-    const int64_t r = (int64_t)blockIdx.x * kKB + threadIdx.x;
     double v[1] = {0.0};
-    if (r < n) {
+    for (int64_t r = (int64_t)blockIdx.x * kKB + threadIdx.x; r < n; r += (int64_t)gridDim.x * kKB) {
         double w = Q[(size_t)I * n + r];
 #pragma unroll
         for (int j = 0; j < I; ++j) w -= coef[j] * Q[(size_t)j * n + r];
         Q[(size_t)I * n + r] = w;
-        v[0] = w * w;
+        v[0] += w * w;
     }
     block_sums<1>(v, red);
-    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
-    if (!last_block(ticket)) return;
     __shared__ double sums[1];
-    sum_partials(part, gridDim.x, 1, sums);
+    if (!tree_sum(tree, red, 1, sums)) return;
     if (threadIdx.x == 0) {
         const double h = sqrt(sums[0]);
         const bool brk = !(h > kBreakRel * sqrt(sc[S_WN2]));
         H[I * kappa + (I - 1)] = brk ? 0.0 : h;
         sc[S_SCALE + I] = brk ? 0.0 : 1.0 / h;
-        *ticket = 0u;
     }
 }
 
@@ -305,52 +348,36 @@ __global__ __launch_bounds__(kKB) void k_kry_expm(double* __restrict__ H, int ka
 // rho = sum_i c_i Qraw[i] -> Qraw[0] (next start) and out (if given);
 // ||rho||^2 -> beta, scale[0] of the next step.
 __global__ __launch_bounds__(kKB) void k_kry_combine(double* __restrict__ Q, int64_t n, int kappa,
-                                                     double* __restrict__ out, double* __restrict__ part,
-                                                     unsigned* __restrict__ ticket, double* __restrict__ sc) {
+                                                     double* __restrict__ out, Tree tree, double* __restrict__ sc) {
     __shared__ double red[kKB / 64];
     __shared__ double c[kKMax];
     if (threadIdx.x < kappa) c[threadIdx.x] = sc[S_C + threadIdx.x];
     __syncthreads();
-    const int64_t r = (int64_t)blockIdx.x * kKB + threadIdx.x;
     double v[1] = {0.0};
-    if (r < n) {
+    for (int64_t r = (int64_t)blockIdx.x * kKB + threadIdx.x; r < n; r += (int64_t)gridDim.x * kKB) {
         double x = 0.0;
         for (int i = 0; i < kappa; ++i) x += c[i] * Q[(size_t)i * n + r];
         Q[r] = x;
         if (out) out[r] = x;
-        v[0] = x * x;
+        v[0] += x * x;
     }
     block_sums<1>(v, red);
-    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
-    if (!last_block(ticket)) return;
     __shared__ double sums[1];
-    sum_partials(part, gridDim.x, 1, sums);
+    if (!tree_sum(tree, red, 1, sums)) return;
     if (threadIdx.x == 0) {
         const double beta = sqrt(sums[0]);
         sc[S_BETA] = beta;
         sc[S_SCALE + 0] = beta > 0.0 ? 1.0 / beta : 0.0;
-        *ticket = 0u;
     }
 }
 
 __global__ void k_kry_copy(const double* __restrict__ a, double* __restrict__ b, int64_t n) {
-    const int64_t r = (int64_t)blockIdx.x * kKB + threadIdx.x;
-    if (r < n) b[r] = a[r];
-}
-
-__global__ void k_kry_zero(double* __restrict__ p, int64_t n) {
-    const int64_t r = (int64_t)blockIdx.x * kKB + threadIdx.x;
-    if (r < n) p[r] = 0.0;
-}
-
-__global__ void k_kry_zero_u32(unsigned* __restrict__ p, int n) {
-    const int r = blockIdx.x * kKB + threadIdx.x;
-    if (r < n) p[r] = 0u;
+    for (int64_t r = (int64_t)blockIdx.x * kKB + threadIdx.x; r < n; r += (int64_t)gridDim.x * kKB) b[r] = a[r];
 }
 
 // per-iteration launch tables (I = 1 .. kKMax - 1)
-using SpmvFn = void (*)(KryOp, double*, int64_t, double*, unsigned*, double*);
-using OrthFn = void (*)(double*, int64_t, int, double*, double*, unsigned*, double*);
+using SpmvFn = void (*)(KryOp, double*, int64_t, Tree, double*);
+using OrthFn = void (*)(double*, int64_t, int, double*, Tree, double*);
 
 template <int... Is>
 struct Tables {
@@ -380,9 +407,10 @@ struct mjp_krylov {
     DevBuf slice_off, col, val;  // A^T sliced ELL
     DevBuf Q;                    // kappa x n FP64, unnormalised basis
     DevBuf H;                    // kappa x kappa FP64
-    DevBuf part;                 // (kKMax + 1) x nblk FP64 partials
+    DevBuf part;                 // (kKMax + 1) x nblk FP64 block partials
+    DevBuf part2;                // (kKMax + 1) x ngroups FP64 group partials
     DevBuf sc;                   // S_COUNT FP64 scalars
-    DevBuf ticket;               // one unsigned per kernel kind
+    DevBuf ticket;               // 1 + ngroups arrival counters (zero between kernels)
 };
 
 extern "C" {
@@ -453,13 +481,16 @@ mjp_status mjp_krylov_create(const mjp_csr* A, const mjp_krylov_opts* opts, mjp_
     k->m_theta = m_theta;
     k->n_slices = n_slices;
     const int64_t nblk = (n + kKB - 1) / kKB;
+    const int64_t ngroups = (nblk + kGroup - 1) / kGroup;
     if ((st = k->slice_off.reserve(sizeof(int32_t) * slice_off.size())) ||
         (st = k->col.reserve(sizeof(int32_t) * std::max<size_t>(total, 1))) ||
         (st = k->val.reserve(sizeof(double) * std::max<size_t>(total, 1))) ||
         (st = k->Q.reserve(sizeof(double) * (size_t)k->kappa * (size_t)n)) ||
         (st = k->H.reserve(sizeof(double) * kKMax * kKMax)) ||
         (st = k->part.reserve(sizeof(double) * (kKMax + 1) * (size_t)nblk)) ||
-        (st = k->sc.reserve(sizeof(double) * S_COUNT)) || (st = k->ticket.reserve(sizeof(unsigned) * 64)))
+        (st = k->part2.reserve(sizeof(double) * (kKMax + 1) * (size_t)ngroups)) ||
+        (st = k->sc.reserve(sizeof(double) * S_COUNT)) ||
+        (st = k->ticket.reserve(sizeof(unsigned) * (size_t)(1 + ngroups))))
         return bail(st);
     auto up = [&](DevBuf& b, const void* h, size_t bytes) -> mjp_status {
         if (bytes) MJP_HIP(hipMemcpy(b.ptr, h, bytes, hipMemcpyHostToDevice));
@@ -470,9 +501,9 @@ mjp_status mjp_krylov_create(const mjp_csr* A, const mjp_krylov_opts* opts, mjp_
         (st = up(k->val, hval.data(), sizeof(double) * total)))
         return bail(st);
     std::vector<double> zeros(kKMax * kKMax, 0.0);
-    std::vector<unsigned> z32(64, 0u);
+    std::vector<unsigned> z32((size_t)(1 + ngroups), 0u);
     if ((st = up(k->H, zeros.data(), sizeof(double) * kKMax * kKMax)) ||
-        (st = up(k->ticket, z32.data(), sizeof(unsigned) * 64)))
+        (st = up(k->ticket, z32.data(), sizeof(unsigned) * z32.size())))
         return bail(st);
     *out = k;
     return MJP_OK;
@@ -489,6 +520,7 @@ void mjp_krylov_destroy(mjp_krylov* k) {
     k->Q.release();
     k->H.release();
     k->part.release();
+    k->part2.release();
     k->sc.release();
     k->ticket.release();
     if (restore) (void)hipSetDevice(prev);
@@ -511,12 +543,13 @@ mjp_status mjp_krylov_expv(mjp_krylov* k, const double* rho0_d, int32_t n_t, con
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const int64_t n = k->n;
     const int kappa = k->kappa;
-    const unsigned nblk = (unsigned)((n + kKB - 1) / kKB);
+    // grid-stride launches: at most kMaxBlocks blocks, so each block reduces
+    // once over several rows per thread
+    const unsigned nblk = (unsigned)std::min<int64_t>((n + kKB - 1) / kKB, kMaxBlocks);
     double* Q = k->Q.as<double>();
     double* H = k->H.as<double>();
-    double* part = k->part.as<double>();
+    const Tree tree{k->part.as<double>(), k->part2.as<double>(), k->ticket.as<unsigned>()};
     double* sc = k->sc.as<double>();
-    unsigned* tk = k->ticket.as<unsigned>();
     KryOp op{k->slice_off.as<int32_t>(), k->col.as<int32_t>(), k->val.as<double>()};
 
     std::vector<int> order((size_t)n_t);
@@ -524,7 +557,7 @@ mjp_status mjp_krylov_expv(mjp_krylov* k, const double* rho0_d, int32_t n_t, con
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return t_h[a] < t_h[b]; });
     const double dt = k->m_theta > 0.0 ? k->dt_factor * kappa / k->m_theta : INFINITY;
 
-    hipLaunchKernelGGL(k_kry_start, dim3(nblk), dim3(kKB), 0, st, rho0_d, Q, n, part, tk + 0, sc);
+    hipLaunchKernelGGL(k_kry_start, dim3(nblk), dim3(kKB), 0, st, rho0_d, Q, n, tree, sc);
     double tau = 0.0;
     int64_t steps = 0;
     for (int idx : order) {
@@ -538,15 +571,13 @@ mjp_status mjp_krylov_expv(mjp_krylov* k, const double* rho0_d, int32_t n_t, con
             const double h = std::min(dt, t - tau);
             const bool lands = h == t - tau;
             for (int i = 1; i < kappa; ++i) {
-                hipLaunchKernelGGL(KryTables::spmv[i - 1], dim3(nblk), dim3(kKB), 0, st, op, Q, n, part, tk + 1, sc);
-                hipLaunchKernelGGL(KryTables::dot[i - 1], dim3(nblk), dim3(kKB), 0, st, Q, n, kappa, H, part, tk + 2,
-                                   sc);
-                hipLaunchKernelGGL(KryTables::norm[i - 1], dim3(nblk), dim3(kKB), 0, st, Q, n, kappa, H, part, tk + 3,
-                                   sc);
+                hipLaunchKernelGGL(KryTables::spmv[i - 1], dim3(nblk), dim3(kKB), 0, st, op, Q, n, tree, sc);
+                hipLaunchKernelGGL(KryTables::dot[i - 1], dim3(nblk), dim3(kKB), 0, st, Q, n, kappa, H, tree, sc);
+                hipLaunchKernelGGL(KryTables::norm[i - 1], dim3(nblk), dim3(kKB), 0, st, Q, n, kappa, H, tree, sc);
             }
             hipLaunchKernelGGL(k_kry_expm, dim3(1), dim3(kKB), 0, st, H, kappa, h, sc);
-            hipLaunchKernelGGL(k_kry_combine, dim3(nblk), dim3(kKB), 0, st, Q, n, kappa, lands ? outj : nullptr, part,
-                               tk + 4, sc);
+            hipLaunchKernelGGL(k_kry_combine, dim3(nblk), dim3(kKB), 0, st, Q, n, kappa, lands ? outj : nullptr, tree,
+                               sc);
             tau = lands ? t : tau + h;
             ++steps;
         }

@@ -121,7 +121,8 @@ def test_full_size_converged_vs_exact(orc):
     l1 = np.abs(got[0] - ref).sum()
     say(f"    steps {info['steps']}  L1 vs exact {l1:.3e}")
     assert l1 <= 1e-9
-    got2, info2 = gpu_krylov(rp, ci, va, synth.delta(10 ** 6), [1.0])
+    got2, info2 = gpu_krylov(rp, ci, va, synth.delta(10 ** 6), [1.0, 0.0])
+    assert np.array_equal(got2[1], synth.delta(10 ** 6))  # t = 0 copies rho(0) through every row
     assert abs(got2[0].sum() - 1.0) < 1e-10
     l1p = np.abs(got2[0] - ref).sum()
     say(f"    paper step: steps {info2['steps']}  L1 vs exact {l1p:.3e}")
