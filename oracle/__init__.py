@@ -42,6 +42,8 @@ _LIB_PATH = os.path.join(_HERE, "_mjp_oracle.so")
 
 MODEL_BD = 0
 MODEL_CASCADE2 = 1
+MODEL_TWOSTATE = 2
+MODEL_AUTOREG = 3
 K_TOL = 0
 K_PAPER = 1
 
@@ -209,3 +211,18 @@ def loglik(A: CSR, rho0, T, obs, omega_factor: float = 1.1, k_rule: int = K_TOL,
     if rc != 0:
         raise ValueError("oracle loglik: bad input")
     return float(out[0])
+
+
+def loglik_marginal(A: CSR, rho0, T, groups, **kw) -> float:
+    """Snapshot log-likelihood when part of the state is not observed (the
+    gene state of the two-state and autoregulatory models, Secs. 3.1.2-3.1.3):
+    sum_i c_i log sum_{s in S_i} rho(T_{j_i})_s.  groups is a list of
+    (time index, list of state indices, count); independent solves per time."""
+    rho = expv_times(A, rho0, T, **kw)
+    total = 0.0
+    for j, states, c in groups:
+        p = float(np.sum(rho[int(j), np.asarray(states, dtype=np.int64)]))
+        if not p > 0.0:
+            return -np.inf
+        total += c * np.log(p)
+    return total

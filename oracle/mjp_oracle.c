@@ -46,7 +46,7 @@
 #include <omp.h>
 #endif
 
-enum { ORC_BD = 0, ORC_CASCADE2 = 1 };
+enum { ORC_BD = 0, ORC_CASCADE2 = 1, ORC_TWOSTATE = 2, ORC_AUTOREG = 3 };
 enum { ORC_K_TOL = 0, ORC_K_PAPER = 1 };
 
 int orc_num_threads(void) {
@@ -77,7 +77,45 @@ int orc_model_size(int model, const int32_t* dims, int64_t* n_states, int64_t* n
         *nnz_max = 5 * *n_states;
         return 0;
     }
+    if (model == ORC_TWOSTATE) {
+        if (dims[0] < 1) return -1;
+        *n_states = 2 * (int64_t)dims[0];
+        *nnz_max = 5 * *n_states;
+        return 0;
+    }
+    if (model == ORC_AUTOREG) {
+        if (dims[0] < 1 || dims[1] < 1) return -1;
+        *n_states = 2 * (int64_t)dims[0] * dims[1];
+        *nnz_max = 7 * *n_states;
+        return 0;
+    }
     return -1;
+}
+
+/* One row of a generator from a list of (target, rate) moves out of state
+ * n: rates into states off the grid (target < 0) are dropped, or counted in
+ * the exit rate only when leaky; zero rates are not stored; entries are
+ * emitted in increasing column order with the diagonal -(sum of exits). */
+typedef struct { int64_t to; double rate; } orc_move;
+
+static int64_t emit_row(int64_t n, orc_move* mv, int nm, int leaky, int64_t e, int32_t* col, double* val) {
+    double out = 0.0;
+    for (int i = 0; i < nm; ++i)
+        if (mv[i].rate != 0.0 && (mv[i].to >= 0 || leaky)) out += mv[i].rate;
+    /* insertion sort of the kept moves by target, with the diagonal */
+    orc_move kept[8];
+    int nk = 0;
+    for (int i = 0; i < nm; ++i)
+        if (mv[i].rate != 0.0 && mv[i].to >= 0) kept[nk++] = mv[i];
+    kept[nk].to = n;
+    kept[nk].rate = -out;
+    ++nk;
+    for (int i = 1; i < nk; ++i)
+        for (int j = i; j > 0 && kept[j - 1].to > kept[j].to; --j) {
+            orc_move t = kept[j]; kept[j] = kept[j - 1]; kept[j - 1] = t;
+        }
+    for (int i = 0; i < nk; ++i) { col[e] = (int32_t)kept[i].to; val[e] = kept[i].rate; ++e; }
+    return e;
 }
 
 /*
@@ -138,6 +176,58 @@ int64_t orc_model_generator(int model, const double* theta, const int32_t* dims,
             }
         }
         row_ptr[(int64_t)S1 * S2] = e;
+        return e;
+    }
+    if (model == ORC_TWOSTATE) {
+        /* Two-state birth-death (Sec. 3.1.2, Eq. 2S_chem): theta = (beta, gamma,
+         * lambda_act, lambda_ina); state n = n_R + s N_R with s = 0 active,
+         * s = 1 inactive.  Active: n_R -> n_R+1 at beta.  Both: n_R -> n_R-1 at
+         * gamma n_R.  Active -> inactive at lambda_ina, inactive -> active at
+         * lambda_act (the text's labels; births never wrap into the other gene
+         * state). */
+        const double beta = theta[0], gamma = theta[1], lact = theta[2], lina = theta[3];
+        const int32_t NR = dims[0];
+        for (int32_t s = 0; s < 2; ++s)
+            for (int32_t r = 0; r < NR; ++r) {
+                const int64_t n = r + (int64_t)s * NR;
+                row_ptr[n] = e;
+                orc_move mv[4];
+                int nm = 0;
+                if (s == 0) { mv[nm].to = (r + 1 < NR) ? n + 1 : -1; mv[nm].rate = beta; ++nm; }
+                if (r >= 1) { mv[nm].to = n - 1; mv[nm].rate = gamma * (double)r; ++nm; }
+                if (s == 0) { mv[nm].to = n + NR; mv[nm].rate = lina; ++nm; }
+                else { mv[nm].to = n - NR; mv[nm].rate = lact; ++nm; }
+                e = emit_row(n, mv, nm, leaky, e, col, val);
+            }
+        row_ptr[2 * (int64_t)NR] = e;
+        return e;
+    }
+    if (model == ORC_AUTOREG) {
+        /* Autoregulatory gene network (Sec. 3.1.3, Eq. STS_chem): theta =
+         * (beta_R, beta_P, gamma_R, gamma_P, lambda_act, lambda_ina); state
+         * n = n_R + n_P N_R + s N_R N_P (s = 0 active, 1 inactive), N = 2 N_R N_P.
+         * Active: R born at beta_R.  Any: P born at beta_P n_R; R dies at
+         * gamma_R n_R; P dies at gamma_P n_P.  Active + P -> inactive at
+         * lambda_ina n_P (one P bound); inactive -> active + P at lambda_act. */
+        const double bR = theta[0], bP = theta[1], gR = theta[2], gP = theta[3], lact = theta[4], lina = theta[5];
+        const int32_t NR = dims[0], NP = dims[1];
+        const int64_t plane = (int64_t)NR * NP;
+        for (int32_t s = 0; s < 2; ++s)
+            for (int32_t p = 0; p < NP; ++p)
+                for (int32_t r = 0; r < NR; ++r) {
+                    const int64_t n = r + (int64_t)p * NR + s * plane;
+                    row_ptr[n] = e;
+                    orc_move mv[6];
+                    int nm = 0;
+                    if (s == 0) { mv[nm].to = (r + 1 < NR) ? n + 1 : -1; mv[nm].rate = bR; ++nm; }
+                    mv[nm].to = (p + 1 < NP) ? n + NR : -1; mv[nm].rate = bP * (double)r; ++nm;
+                    if (r >= 1) { mv[nm].to = n - 1; mv[nm].rate = gR * (double)r; ++nm; }
+                    if (p >= 1) { mv[nm].to = n - NR; mv[nm].rate = gP * (double)p; ++nm; }
+                    if (s == 0 && p >= 1) { mv[nm].to = n + plane - NR; mv[nm].rate = lina * (double)p; ++nm; }
+                    if (s == 1) { mv[nm].to = (p + 1 < NP) ? n - plane + NR : -1; mv[nm].rate = lact; ++nm; }
+                    e = emit_row(n, mv, nm, leaky, e, col, val);
+                }
+        row_ptr[2 * plane] = e;
         return e;
     }
     return -1;
