@@ -140,8 +140,21 @@ typedef struct {
  *     dims = {S1, S2}, state n = n1 + S1 n2 (first coordinate fastest, as the
  *     paper linearises multi-index states, Sec. 3.1.2);
  *     (n1,n2) -> (n1+1,n2) at k1, -> (n1-1,n2) at g1 n1, -> (n1,n2+1) at k2 n1,
- *     -> (n1,n2-1) at g2 n2. */
-enum { MJP_MODEL_BD = 0, MJP_MODEL_CASCADE2 = 1 };
+ *     -> (n1,n2-1) at g2 n2.
+ *   MJP_MODEL_TWOSTATE: two-state birth-death (Sec. 3.1.2, Eq. 2S_chem),
+ *     theta = {beta, gamma, lambda_act, lambda_ina}, dims = {N_R, 1}, state
+ *     n = n_R + g N_R (g = 0 active, 1 inactive; N = 2 N_R); active births at
+ *     beta, deaths at gamma n_R, active -> inactive at lambda_ina, inactive ->
+ *     active at lambda_act.
+ *   MJP_MODEL_AUTOREG: autoregulatory gene network (Sec. 3.1.3, Eq. STS_chem),
+ *     theta = {beta_R, beta_P, gamma_R, gamma_P, lambda_act, lambda_ina},
+ *     dims = {N_R, N_P}, state n = n_R + n_P N_R + g N_R N_P (N = 2 N_R N_P);
+ *     active R births at beta_R, P births at beta_P n_R, deaths at gamma_R n_R
+ *     and gamma_P n_P, active + P -> inactive at lambda_ina n_P, inactive ->
+ *     active + P at lambda_act.
+ * Stencil plans (mjp_plan_create_stencil) cover BD and CASCADE2; the other
+ * two are run through mjp_model_csr and a CSR plan. */
+enum { MJP_MODEL_BD = 0, MJP_MODEL_CASCADE2 = 1, MJP_MODEL_TWOSTATE = 2, MJP_MODEL_AUTOREG = 3 };
 
 typedef struct {
     int32_t model;     /* MJP_MODEL_* */
@@ -213,11 +226,16 @@ typedef struct {
     int32_t        n_t;      /* number of collection times */
     const double*  T_h;      /* [n_t] collection times, host, >= 0 */
     int32_t        n_obs;    /* number of (time, state) records */
-    const int32_t* obs_h;    /* [n_obs x 4] host: (time index, x1, x2, count >= 1) */
-    int32_t        x0[2];    /* initial state: rho(0) is a point mass there */
+    const int32_t* obs_h;    /* [n_obs x 4] host: (time index, x1, x2, count >= 1); the
+                                observed counts: (n, 0) BD, (n1, n2) cascade, (n_R, 0)
+                                two-state, (n_R, n_P) autoregulatory */
+    int32_t        x0[2];    /* initial state, a point mass: (n, 0), (n1, n2), (n_R, gene
+                                state 0/1) two-state, (n_R, n_P) autoregulatory (active) */
 } mjp_obs;
 
-/* Log-likelihoods of B parameter draws of one built-in model:
+/* Log-likelihoods of B parameter draws of one built-in model (any of the
+ * four; for the two gene-state models the gene state is not observed and a
+ * record's probability is the sum over it, Secs. 3.1.2-3.1.3):
  *   loglik_d[b] = sum_i count_i log rho_b(T_{j_i})_{(x1_i, x2_i)}
  * where rho_b solves the model with theta_d[b*4 .. b*4+3] on the grid
  * dims_d[b*2], dims_d[b*2+1] (conservative truncation).  All items run in one
@@ -225,8 +243,9 @@ typedef struct {
  * vector in the LDS of one workgroup, so S1*S2 <= mjp_loglik_max_states().
  * Only observed states are accumulated.  An observation outside an item's
  * grid, or with FP32 probability 0, gives -inf for that item (and a flag).
- *   theta_d  [B x 4] FP64 device (BD uses the first 2 of each 4)
- *   dims_d   [B x 2] int32 device
+ *   theta_d  [B x P] FP64 device, P = 6 for MJP_MODEL_AUTOREG and 4 otherwise
+ *            (BD uses the first 2 of each 4)
+ *   dims_d   [B x 2] int32 device: {N, 1}, {S1, S2}, {N_R, 1} or {N_R, N_P}
  *   loglik_d [B] FP64 device
  *   info_d   [B] device or NULL (omega, W of the last time, K, L of the last
  *            time, flags, mass_out = final mass of the iterate)

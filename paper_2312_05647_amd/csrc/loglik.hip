@@ -10,7 +10,8 @@
 //               tol/4, L the last whose bound on the left tail is; the window
 //               weight sum gives the residual lumped at K (Algorithm 2).
 //   k_ll_order  one block: items sorted by cost K_max * N, longest first.
-//   k_ll_main   one workgroup per CU pulls items from an atomic queue.  The
+//   k_ll_main   (one instance per model) one workgroup per CU pulls items
+//               from an atomic queue.  The
 //               whole state vector of an item sits in LDS; each thread owns
 //               cells m = tid + i*1024; a jump is "compute the new values of
 //               my cells into registers, barrier, write back, barrier".  Only observed states are
@@ -65,16 +66,48 @@ struct LLArgs {
     int64_t k_cap;
 };
 
-__device__ double ll_max_exit(int model, const double* th, int S1, int S2) {
+// theta stride and parameter count of a model's draws
+__host__ __device__ inline int ll_stride(int model) { return model == MJP_MODEL_AUTOREG ? 6 : 4; }
+__host__ __device__ inline int ll_params(int model) {
+    return model == MJP_MODEL_BD ? 2 : (model == MJP_MODEL_AUTOREG ? 6 : 4);
+}
+// grid of an item as (S1, S2): BD {N, 1}; cascade {S1, S2}; two-state
+// {N_R, 2} (second coordinate = gene state); autoregulatory {N_R, 2 N_P}
+// (second coordinate = n_P + N_P g)
+__device__ inline void ll_grid(int model, const int32_t* d, int& S1, int& S2) {
+    S1 = d[0];
+    S2 = model == MJP_MODEL_BD ? 1 : (model == MJP_MODEL_TWOSTATE ? 2 : (model == MJP_MODEL_AUTOREG ? 2 * d[1] : d[1]));
+}
+
+// max_n |a_nn| under conservative truncation; exits grow with every count
+// except for births blocked at a cap, so the last two values of each count
+// hold the maximum
+__device__ double ll_max_exit(int model, const double* th, const int32_t* d) {
     double best = 0.0;
     if (model == MJP_MODEL_BD) {
+        const int S1 = d[0];
         for (int n = max(0, S1 - 2); n < S1; ++n)
             best = fmax(best, ((n + 1 < S1) ? th[0] : 0.0) + th[1] * n);
-    } else {
+    } else if (model == MJP_MODEL_CASCADE2) {
+        const int S1 = d[0], S2 = d[1];
         for (int n2 = max(0, S2 - 2); n2 < S2; ++n2)
             for (int n1 = max(0, S1 - 2); n1 < S1; ++n1)
                 best = fmax(best, ((n1 + 1 < S1) ? th[0] : 0.0) + th[1] * n1 + ((n2 + 1 < S2) ? th[2] * n1 : 0.0) +
                                       th[3] * n2);
+    } else if (model == MJP_MODEL_TWOSTATE) {
+        const int NR = d[0];
+        for (int r = max(0, NR - 2); r < NR; ++r) {
+            best = fmax(best, ((r + 1 < NR) ? th[0] : 0.0) + th[1] * r + th[3]);  // active
+            best = fmax(best, th[1] * r + th[2]);                                 // inactive
+        }
+    } else {
+        const int NR = d[0], NP = d[1];
+        for (int p = max(0, NP - 2); p < NP; ++p)
+            for (int r = max(0, NR - 2); r < NR; ++r) {
+                const double common = ((p + 1 < NP) ? th[1] * r : 0.0) + th[2] * r + th[3] * p;
+                best = fmax(best, common + ((r + 1 < NR) ? th[0] : 0.0) + th[5] * p);  // active
+                best = fmax(best, common + ((p + 1 < NP) ? th[4] : 0.0));              // inactive
+            }
     }
     return best;
 }
@@ -84,11 +117,10 @@ __global__ void k_ll_prep(LLArgs a) {
     if (idx == 0) *a.queue = 0u;
     if (idx >= a.B * a.n_t) return;
     const int b = idx / a.n_t, j = idx - b * a.n_t;
-    const double* th = a.theta + 4 * (int64_t)b;
-    const int S1 = a.dims[2 * b], S2 = a.model == MJP_MODEL_BD ? 1 : a.dims[2 * b + 1];
+    const double* th = a.theta + ll_stride(a.model) * (int64_t)b;
     bool bad_theta = false;
-    for (int i = 0; i < (a.model == MJP_MODEL_BD ? 2 : 4); ++i) bad_theta |= !(th[i] >= 0.0) || isinf(th[i]);
-    const double omega = bad_theta ? 0.0 : a.omega_factor * ll_max_exit(a.model, th, S1, S2);
+    for (int i = 0; i < ll_params(a.model); ++i) bad_theta |= !(th[i] >= 0.0) || isinf(th[i]);
+    const double omega = bad_theta ? 0.0 : a.omega_factor * ll_max_exit(a.model, th, a.dims + 2 * b);
     const double W = bad_theta ? NAN : omega * a.T[j];
     LLWin w;
     w.W = W;
@@ -164,7 +196,8 @@ __global__ void k_ll_order(LLArgs a) {
         if (b < B) {
             int32_t kmax = 0;
             for (int j = 0; j < a.n_t; ++j) kmax = max(kmax, a.win[(int64_t)b * a.n_t + j].K);
-            const int S1 = a.dims[2 * b], S2 = a.model == MJP_MODEL_BD ? 1 : a.dims[2 * b + 1];
+            int S1, S2;
+            ll_grid(a.model, a.dims + 2 * b, S1, S2);
             const float c = (float)(kmax + 1) * (float)S1 * (float)S2;
             a.cost[b] = c;
             // descending cost: invert the (non-negative) float bits
@@ -205,6 +238,67 @@ __device__ __forceinline__ double ll_block_sum(double v, double* scratch) {
     return s;
 }
 
+// Rates of an item divided by Omega (FP32), and the number of P levels of
+// the autoregulatory model.
+struct LLCoef {
+    float c[6];
+    int NP;
+};
+
+// New value of cell m = i1 + S1 i2 after one jump (pull form y_m = sum_n
+// rho_n b_nm).  The diagonal of B is 1 minus the FP64 sum of the state's
+// FP32 exit coefficients, the same numbers its neighbours pull.
+template <int MODEL>
+__device__ __forceinline__ float ll_cell(const float* rho, int m, int i1, int i2, int S1, int S2, const LLCoef& k) {
+    const float f1 = (float)i1;
+    if constexpr (MODEL == MJP_MODEL_BD || MODEL == MJP_MODEL_CASCADE2) {
+        const float b1 = k.c[0], d1 = k.c[1], b2 = k.c[2], d2 = k.c[3];
+        const float f2 = (float)i2;
+        const float o_b1 = (i1 + 1 < S1) ? b1 : 0.f;
+        const float o_b2 = (i2 + 1 < S2) ? b2 * f1 : 0.f;
+        const float diag = (float)(1.0 - (((double)o_b1 + (double)(d1 * f1)) + ((double)o_b2 + (double)(d2 * f2))));
+        float y = diag * rho[m];
+        if (i1 > 0) y = fmaf(b1, rho[m - 1], y);
+        if (i1 + 1 < S1) y = fmaf(d1 * (f1 + 1.f), rho[m + 1], y);
+        if (i2 > 0) y = fmaf(b2 * f1, rho[m - S1], y);
+        if (i2 + 1 < S2) y = fmaf(d2 * (f2 + 1.f), rho[m + S1], y);
+        return y;
+    } else if constexpr (MODEL == MJP_MODEL_TWOSTATE) {
+        // i1 = n_R, i2 = gene state (0 active); c = beta, gamma, l_act, l_ina
+        const float be = k.c[0], ga = k.c[1], la = k.c[2], li = k.c[3];
+        const bool act = i2 == 0;
+        const float o_b = (act && i1 + 1 < S1) ? be : 0.f;
+        const float o_s = act ? li : la;
+        const float diag = (float)(1.0 - (((double)o_b + (double)(ga * f1)) + (double)o_s));
+        float y = diag * rho[m];
+        if (act && i1 > 0) y = fmaf(be, rho[m - 1], y);
+        if (i1 + 1 < S1) y = fmaf(ga * (f1 + 1.f), rho[m + 1], y);
+        y = act ? fmaf(la, rho[m + S1], y) : fmaf(li, rho[m - S1], y);
+        return y;
+    } else {
+        // i1 = n_R, i2 = n_P + NP g; c = beta_R, beta_P, gamma_R, gamma_P, l_act, l_ina
+        const int NP = k.NP;
+        const bool act = i2 < NP;
+        const int p = act ? i2 : i2 - NP;
+        const int plane = S1 * NP;
+        const float fp = (float)p;
+        const float o_bR = (act && i1 + 1 < S1) ? k.c[0] : 0.f;
+        const float o_bP = (p + 1 < NP) ? k.c[1] * f1 : 0.f;
+        const float o_sw = act ? k.c[5] * fp : ((p + 1 < NP) ? k.c[4] : 0.f);
+        const float diag = (float)(1.0 - ((((double)o_bR + (double)o_bP) + ((double)(k.c[2] * f1) + (double)(k.c[3] * fp))) +
+                                          (double)o_sw));
+        float y = diag * rho[m];
+        if (act && i1 > 0) y = fmaf(k.c[0], rho[m - 1], y);               // R birth from n_R - 1
+        if (p > 0) y = fmaf(k.c[1] * f1, rho[m - S1], y);                 // P birth from n_P - 1
+        if (i1 + 1 < S1) y = fmaf(k.c[2] * (f1 + 1.f), rho[m + 1], y);    // R death from n_R + 1
+        if (p + 1 < NP) y = fmaf(k.c[3] * (fp + 1.f), rho[m + S1], y);    // P death from n_P + 1
+        if (!act && p + 1 < NP) y = fmaf(k.c[5] * (fp + 1.f), rho[m - plane + S1], y);  // binding
+        if (act && p > 0) y = fmaf(k.c[4], rho[m + plane - S1], y);       // unbinding
+        return y;
+    }
+}
+
+template <int MODEL>
 __global__ __launch_bounds__(kLLThreads) void k_ll_main(LLArgs a) {
     extern __shared__ char lds[];
     float* rho = reinterpret_cast<float*>(lds);                                   // [kLLMaxStates]
@@ -222,9 +316,9 @@ __global__ __launch_bounds__(kLLThreads) void k_ll_main(LLArgs a) {
         __syncthreads();
         if (slot >= a.B) break;
         const int b = a.order[slot];
-        const double* th = a.theta + 4 * (int64_t)b;
-        const int S1 = a.dims[2 * b];
-        const int S2 = a.model == MJP_MODEL_BD ? 1 : a.dims[2 * b + 1];
+        const double* th = a.theta + ll_stride(MODEL) * (int64_t)b;
+        int S1, S2;
+        ll_grid(MODEL, a.dims + 2 * b, S1, S2);
         if (tid < a.n_t) win[tid] = a.win[(int64_t)b * a.n_t + tid];
         if (tid == 0) flag_sh = 0u;
         __syncthreads();
@@ -238,7 +332,7 @@ __global__ __launch_bounds__(kLLThreads) void k_ll_main(LLArgs a) {
             Lmin = min(Lmin, win[j].L);
         }
         const int64_t N64 = (int64_t)S1 * S2;
-        double omega = a.omega_factor * ll_max_exit(a.model, th, S1, S2);
+        double omega = a.omega_factor * ll_max_exit(MODEL, th, a.dims + 2 * b);
         if (over || S1 < 1 || S2 < 1 || N64 > kLLMaxStates) {
             if (tid == 0) {
                 a.loglik[b] = -INFINITY;
@@ -253,17 +347,25 @@ __global__ __launch_bounds__(kLLThreads) void k_ll_main(LLArgs a) {
         }
         const int N = (int)N64;
         const double om = omega > 0.0 ? omega : 1.0;
-        const float b1 = (float)(th[0] / om), d1 = (float)(th[1] / om);
-        const float b2 = a.model == MJP_MODEL_BD ? 0.f : (float)(th[2] / om);
-        const float d2 = a.model == MJP_MODEL_BD ? 0.f : (float)(th[3] / om);
+        LLCoef kc;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) kc.c[i] = i < ll_params(MODEL) ? (float)(th[i] / om) : 0.f;
+        kc.NP = MODEL == MJP_MODEL_AUTOREG ? a.dims[2 * b + 1] : 1;
 
         // owned cells, their coordinates advance by 1024 = q*S1 + r per step
         const int q1024 = kLLThreads / S1, r1024 = kLLThreads - q1024 * S1;
-        // rho(0) = point mass at x0 (if on the grid)
-        const int x0 = (a.x0_1 < S1 && a.x0_2 < S2) ? a.x0_1 + S1 * a.x0_2 : -1;
+        // rho(0) = point mass at x0 (if on the grid); for the two-state model
+        // x0 = (n_R, gene state), for the autoregulatory one (n_R, n_P), active
+        const int x0lim2 = MODEL == MJP_MODEL_AUTOREG ? kc.NP : S2;
+        const int x0 = (a.x0_1 < S1 && a.x0_2 < x0lim2) ? a.x0_1 + S1 * a.x0_2 : -1;
         for (int m = tid; m < N; m += kLLThreads) rho[m] = (m == x0) ? 1.f : 0.f;
 
         // observation records of this thread
+        // an observed state; for the two gene-state models it is observed
+        // without the gene state, so the record sums cells rm and rm + hid
+        constexpr bool kHidden = MODEL == MJP_MODEL_TWOSTATE || MODEL == MJP_MODEL_AUTOREG;
+        const int hid = MODEL == MJP_MODEL_TWOSTATE ? S1 : S1 * kc.NP;
+        const int lim2 = MODEL == MJP_MODEL_TWOSTATE ? 1 : (MODEL == MJP_MODEL_AUTOREG ? kc.NP : S2);
         int rm[kLLRecPerThread], rt[kLLRecPerThread];
         float rs[kLLRecPerThread], rc[kLLRecPerThread];
 #pragma unroll
@@ -276,7 +378,7 @@ __global__ __launch_bounds__(kLLThreads) void k_ll_main(LLArgs a) {
             if (r < a.n_rec) {
                 const LLRecord R = a.rec[r];
                 rt[u] = R.t;
-                rm[u] = (R.x1 < S1 && R.x2 < S2) ? R.x1 + S1 * R.x2 : -1;
+                rm[u] = (R.x1 < S1 && R.x2 < lim2) ? R.x1 + S1 * R.x2 : -1;
                 if (rm[u] < 0) flags |= MJP_FLAG_OUT_OF_GRID;
             }
         }
@@ -312,21 +414,7 @@ __global__ __launch_bounds__(kLLThreads) void k_ll_main(LLArgs a) {
                 for (int c = 0; c < kLLCellsPerThread; ++c) {
                     const int m = mb + c * kLLThreads;
                     float y = 0.f;
-                    if (m < N) {
-                        const float f1 = (float)i1, f2 = (float)i2;
-                        // diagonal of B: 1 minus the FP64 sum of this state's FP32
-                        // exit coefficients (the same numbers its neighbours pull)
-                        const float o_b1 = (i1 + 1 < S1) ? b1 : 0.f;
-                        const float o_b2 = (i2 + 1 < S2) ? b2 * f1 : 0.f;
-                        const float diag =
-                            (float)(1.0 - (((double)o_b1 + (double)(d1 * f1)) + ((double)o_b2 + (double)(d2 * f2))));
-                        y = diag * rho[m];
-                        if (i1 > 0) y = fmaf(b1, rho[m - 1], y);
-                        if (i1 + 1 < S1) y = fmaf(d1 * (f1 + 1.f), rho[m + 1], y);
-                        if (i2 > 0) y = fmaf(b2 * f1, rho[m - S1], y);
-                        if (i2 + 1 < S2) y = fmaf(d2 * (f2 + 1.f), rho[m + S1], y);
-                        y *= fs;
-                    }
+                    if (m < N) y = fs * ll_cell<MODEL>(rho, m, i1, i2, S1, S2, kc);
                     nv[c] = y;
                     part += y;
                     i1 += r1024;
@@ -356,7 +444,7 @@ __global__ __launch_bounds__(kLLThreads) void k_ll_main(LLArgs a) {
                 const LLWin& w = win[rt[u]];
                 if (k < w.L || k > w.K) continue;
                 const float wt = (k == w.K) ? (float)w.lastw : (float)wbuf[(k & 1) * kLLMaxTimes + rt[u]];
-                const float v = rho[rm[u]];
+                const float v = kHidden ? rho[rm[u]] + rho[rm[u] + hid] : rho[rm[u]];
                 if (k == w.L) {
                     rs[u] = wt * v;
                     rc[u] = 0.f;
@@ -436,7 +524,7 @@ extern "C" mjp_status mjp_loglik(int32_t model, int32_t B, const double* theta_d
                                  const mjp_obs* obs, const mjp_opts* opts, double* loglik_d, mjp_info* info_d,
                                  mjp_stream_t stream) {
     clear_error();
-    MJP_CHECK(model == MJP_MODEL_BD || model == MJP_MODEL_CASCADE2, MJP_E_INVALID_ARG, "unknown model %d", model);
+    MJP_CHECK(model >= MJP_MODEL_BD && model <= MJP_MODEL_AUTOREG, MJP_E_INVALID_ARG, "unknown model %d", model);
     MJP_CHECK(B >= 0, MJP_E_INVALID_ARG, "B must be >= 0");
     mjp_status st = check_opts(opts);
     if (st) return st;
@@ -446,8 +534,9 @@ extern "C" mjp_status mjp_loglik(int32_t model, int32_t B, const double* theta_d
     MJP_CHECK(obs->T_h && (obs->n_obs == 0 || obs->obs_h), MJP_E_INVALID_ARG, "null observation arrays");
     MJP_CHECK(obs->n_obs >= 0 && obs->n_obs <= kLLMaxRecords, MJP_E_INVALID_ARG, "n_obs must be in [0, %d]",
               kLLMaxRecords);
-    MJP_CHECK(obs->x0[0] >= 0 && obs->x0[1] >= 0 && (model != MJP_MODEL_BD || obs->x0[1] == 0), MJP_E_INVALID_ARG,
-              "bad initial state");
+    MJP_CHECK(obs->x0[0] >= 0 && obs->x0[1] >= 0 && (model != MJP_MODEL_BD || obs->x0[1] == 0) &&
+                  (model != MJP_MODEL_TWOSTATE || obs->x0[1] <= 1),
+              MJP_E_INVALID_ARG, "bad initial state");
     for (int j = 0; j < obs->n_t; ++j)
         MJP_CHECK(std::isfinite(obs->T_h[j]) && obs->T_h[j] >= 0.0, MJP_E_INVALID_ARG, "T[%d] must be finite, >= 0", j);
     std::vector<LLRecord> recs((size_t)obs->n_obs);
@@ -455,7 +544,8 @@ extern "C" mjp_status mjp_loglik(int32_t model, int32_t B, const double* theta_d
         const int32_t* r = obs->obs_h + 4 * (size_t)i;
         MJP_CHECK(r[0] >= 0 && r[0] < obs->n_t, MJP_E_INVALID_ARG, "record %d: time index out of range", i);
         MJP_CHECK(r[1] >= 0 && r[2] >= 0, MJP_E_INVALID_ARG, "record %d: negative state", i);
-        MJP_CHECK(model != MJP_MODEL_BD || r[2] == 0, MJP_E_INVALID_ARG, "record %d: x2 must be 0 for BD", i);
+        MJP_CHECK((model != MJP_MODEL_BD && model != MJP_MODEL_TWOSTATE) || r[2] == 0, MJP_E_INVALID_ARG,
+                  "record %d: x2 must be 0 for a one-count model", i);
         MJP_CHECK(r[3] >= 1, MJP_E_INVALID_ARG, "record %d: count must be >= 1", i);
         recs[(size_t)i] = {r[0], r[1], r[2], r[3]};
     }
@@ -488,9 +578,13 @@ extern "C" mjp_status mjp_loglik(int32_t model, int32_t B, const double* theta_d
         (st = C.order.reserve(sizeof(int32_t) * B)) || (st = C.queue.reserve(64)))
         return st;
     const size_t lds = sizeof(float) * kLLMaxStates + kLLExtraLds;
+    using MainFn = void (*)(LLArgs);
+    const MainFn mains[4] = {k_ll_main<MJP_MODEL_BD>, k_ll_main<MJP_MODEL_CASCADE2>, k_ll_main<MJP_MODEL_TWOSTATE>,
+                             k_ll_main<MJP_MODEL_AUTOREG>};
     if (!C.attr_set) {
-        MJP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_ll_main), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)lds));
+        for (MainFn f : mains)
+            MJP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(f), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)lds));
         MJP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_ll_order), hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)(sizeof(unsigned long long) * kLLMaxSort)));
         C.attr_set = true;
@@ -527,7 +621,7 @@ extern "C" mjp_status mjp_loglik(int32_t model, int32_t B, const double* theta_d
     int ncu = 0;
     MJP_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     const int grid = std::min(B, ncu);
-    hipLaunchKernelGGL(k_ll_main, dim3(grid), dim3(kLLThreads), lds, s, a);
+    hipLaunchKernelGGL(mains[model], dim3(grid), dim3(kLLThreads), lds, s, a);
     MJP_HIP(hipGetLastError());
     return MJP_OK;
 }

@@ -156,6 +156,14 @@ mjp_status check_model(const mjp_model* m) {
         MJP_CHECK(m->dims[0] >= 1 && m->dims[1] >= 1, MJP_E_INVALID_ARG, "cascade needs dims >= 1");
         MJP_CHECK((int64_t)m->dims[0] * m->dims[1] <= INT32_MAX / 8, MJP_E_INVALID_ARG, "grid too large");
         np = 4;
+    } else if (m->model == MJP_MODEL_TWOSTATE) {
+        MJP_CHECK(m->dims[0] >= 1 && m->dims[1] == 1, MJP_E_INVALID_ARG, "two-state model needs dims = {N_R >= 1, 1}");
+        MJP_CHECK(2 * (int64_t)m->dims[0] <= INT32_MAX / 8, MJP_E_INVALID_ARG, "grid too large");
+        np = 4;
+    } else if (m->model == MJP_MODEL_AUTOREG) {
+        MJP_CHECK(m->dims[0] >= 1 && m->dims[1] >= 1, MJP_E_INVALID_ARG, "autoregulatory model needs dims >= 1");
+        MJP_CHECK(2 * (int64_t)m->dims[0] * m->dims[1] <= INT32_MAX / 8, MJP_E_INVALID_ARG, "grid too large");
+        np = 6;
     } else {
         return fail(MJP_E_INVALID_ARG, "unknown model %d", m->model);
     }
@@ -166,8 +174,75 @@ mjp_status check_model(const mjp_model* m) {
 }
 
 // Exit rate of every state of a built-in model (the -a_nn of Eq. A_def).
+int64_t model_states(const mjp_model* m) {
+    switch (m->model) {
+        case MJP_MODEL_TWOSTATE: return 2 * (int64_t)m->dims[0];
+        case MJP_MODEL_AUTOREG: return 2 * (int64_t)m->dims[0] * m->dims[1];
+        default: return (int64_t)m->dims[0] * m->dims[1];
+    }
+}
+
+// Moves out of state s of a built-in model: target (-1 when it leaves the
+// grid) and rate, from the model's reactions.  Returns the number of moves.
+//   two-state birth-death (Sec. 3.1.2, Eq. 2S_chem), theta = {beta, gamma,
+//     lambda_act, lambda_ina}, s = n_R + g N_R (g = 0 active): active births
+//     at beta, deaths at gamma n_R, active -> inactive at lambda_ina,
+//     inactive -> active at lambda_act (the text's labels; a birth never
+//     crosses into the other gene state);
+//   autoregulatory network (Sec. 3.1.3, Eq. STS_chem), theta = {beta_R,
+//     beta_P, gamma_R, gamma_P, lambda_act, lambda_ina}, s = n_R + n_P N_R +
+//     g N_R N_P: active R births at beta_R, P births at beta_P n_R, deaths at
+//     gamma_R n_R and gamma_P n_P, active + P -> inactive at lambda_ina n_P,
+//     inactive -> active + P at lambda_act.
+struct Move { int64_t to; double rate; };
+static int model_moves(const mjp_model* m, int64_t s, Move* mv) {
+    int k = 0;
+    const double* th = m->theta;
+    if (m->model == MJP_MODEL_BD) {
+        const int64_t N = m->dims[0];
+        mv[k++] = {s + 1 < N ? s + 1 : -1, th[0]};
+        if (s >= 1) mv[k++] = {s - 1, th[1] * (double)s};
+    } else if (m->model == MJP_MODEL_CASCADE2) {
+        const int64_t S1 = m->dims[0], S2 = m->dims[1];
+        const int64_t x = s % S1, y = s / S1;
+        mv[k++] = {x + 1 < S1 ? s + 1 : -1, th[0]};
+        if (x >= 1) mv[k++] = {s - 1, th[1] * (double)x};
+        mv[k++] = {y + 1 < S2 ? s + S1 : -1, th[2] * (double)x};
+        if (y >= 1) mv[k++] = {s - S1, th[3] * (double)y};
+    } else if (m->model == MJP_MODEL_TWOSTATE) {
+        const int64_t NR = m->dims[0];
+        const int64_t r = s % NR, g = s / NR;
+        if (g == 0) mv[k++] = {r + 1 < NR ? s + 1 : -1, th[0]};
+        if (r >= 1) mv[k++] = {s - 1, th[1] * (double)r};
+        if (g == 0) mv[k++] = {s + NR, th[3]};
+        else mv[k++] = {s - NR, th[2]};
+    } else {  // MJP_MODEL_AUTOREG
+        const int64_t NR = m->dims[0], NP = m->dims[1], plane = NR * NP;
+        const int64_t r = s % NR, p = (s / NR) % NP, g = s / plane;
+        if (g == 0) mv[k++] = {r + 1 < NR ? s + 1 : -1, th[0]};
+        mv[k++] = {p + 1 < NP ? s + NR : -1, th[1] * (double)r};
+        if (r >= 1) mv[k++] = {s - 1, th[2] * (double)r};
+        if (p >= 1) mv[k++] = {s - NR, th[3] * (double)p};
+        if (g == 0 && p >= 1) mv[k++] = {s + plane - NR, th[5] * (double)p};
+        if (g == 1) mv[k++] = {p + 1 < NP ? s - plane + NR : -1, th[4]};
+    }
+    return k;
+}
+
 double model_max_exit(const mjp_model* m, int leaky) {
     double best = 0.0;
+    if (m->model == MJP_MODEL_TWOSTATE || m->model == MJP_MODEL_AUTOREG) {
+        const int64_t n = model_states(m);
+        Move mv[8];
+        for (int64_t s = 0; s < n; ++s) {
+            double e = 0.0;
+            const int k = model_moves(m, s, mv);
+            for (int i = 0; i < k; ++i)
+                if (mv[i].to >= 0 || leaky) e += mv[i].rate;
+            best = std::max(best, e);
+        }
+        return best;
+    }
     if (m->model == MJP_MODEL_BD) {
         const int32_t N = m->dims[0];
         const double beta = m->theta[0], gamma = m->theta[1];
@@ -207,6 +282,14 @@ mjp_status mjp_model_csr_size(const mjp_model* m, int32_t truncation, int32_t* n
         nnz = N;
         if (m->theta[0] != 0.0) nnz += N - 1;          // births n -> n+1
         if (m->theta[1] != 0.0) nnz += N - 1;          // deaths n -> n-1, n >= 1
+    } else if (m->model == MJP_MODEL_TWOSTATE || m->model == MJP_MODEL_AUTOREG) {
+        n = model_states(m);
+        nnz = n;
+        Move mv[8];
+        for (int64_t s = 0; s < n; ++s) {
+            const int k = model_moves(m, s, mv);
+            for (int i = 0; i < k; ++i) nnz += (mv[i].to >= 0 && mv[i].rate != 0.0) ? 1 : 0;
+        }
     } else {
         const int64_t S1 = m->dims[0], S2 = m->dims[1];
         n = S1 * S2;
@@ -232,7 +315,29 @@ mjp_status mjp_model_csr(const mjp_model* m, int32_t truncation, int32_t* row_pt
     int32_t e = 0;
     // one row = one from-state; entries in increasing column order
     struct Ent { int32_t c; double v; };
-    if (m->model == MJP_MODEL_BD) {
+    if (m->model == MJP_MODEL_TWOSTATE || m->model == MJP_MODEL_AUTOREG) {
+        Move mv[8];
+        for (int32_t s = 0; s < n; ++s) {
+            row_ptr[s] = e;
+            Ent ent[9];
+            int ne = 0;
+            double exit = 0.0;
+            const int k = model_moves(m, s, mv);
+            for (int i = 0; i < k; ++i) {
+                if (mv[i].rate == 0.0) continue;
+                if (mv[i].to >= 0) {
+                    ent[ne++] = {(int32_t)mv[i].to, mv[i].rate};
+                    exit += mv[i].rate;
+                } else if (leaky) {
+                    exit += mv[i].rate;
+                }
+            }
+            ent[ne++] = {s, -exit};
+            std::sort(ent, ent + ne, [](const Ent& a, const Ent& b) { return a.c < b.c; });
+            for (int i = 0; i < ne; ++i) { col_idx[e] = ent[i].c; val[e] = ent[i].v; ++e; }
+        }
+        row_ptr[n] = e;
+    } else if (m->model == MJP_MODEL_BD) {
         const int32_t N = m->dims[0];
         const double beta = m->theta[0], gamma = m->theta[1];
         for (int32_t s = 0; s < N; ++s) {
@@ -486,6 +591,8 @@ mjp_status mjp_plan_create_stencil(const mjp_model* m, const mjp_opts* opts, mjp
     mjp_status st = check_model(m);
     if (st) return st;
     if ((st = check_opts(opts))) return st;
+    MJP_CHECK(m->model == MJP_MODEL_BD || m->model == MJP_MODEL_CASCADE2, MJP_E_UNSUPPORTED,
+              "stencil plans cover the birth-death and cascade models; build the others with mjp_model_csr");
     mjp_plan* p = new (std::nothrow) mjp_plan();
     MJP_CHECK(p, MJP_E_DEVICE, "out of host memory");
     p->kind = PLAN_STENCIL;

@@ -23,7 +23,7 @@ STATUS_NAMES = ["MJP_OK", "MJP_E_INVALID_ARG", "MJP_E_NOT_GENERATOR", "MJP_E_K_L
 MJP_K_TOL, MJP_K_PAPER = 0, 1
 MJP_CONSERVATIVE, MJP_LEAKY = 0, 1
 MJP_VARIANT_AUTO, MJP_VARIANT_STEPWISE, MJP_VARIANT_PERSISTENT, MJP_VARIANT_PERSISTENT_FENCED = 0, 1, 2, 3
-MJP_MODEL_BD, MJP_MODEL_CASCADE2 = 0, 1
+MJP_MODEL_BD, MJP_MODEL_CASCADE2, MJP_MODEL_TWOSTATE, MJP_MODEL_AUTOREG = 0, 1, 2, 3
 MJP_FLAG_NAN, MJP_FLAG_NEG, MJP_FLAG_UNDERFLOW_OBS, MJP_FLAG_OUT_OF_GRID, MJP_FLAG_K_LIMIT = 1, 2, 4, 8, 16
 
 

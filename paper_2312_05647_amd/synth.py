@@ -184,6 +184,53 @@ def gillespie_cascade2(theta, times, n_per_time: int, seed: int = SEED_DATA):
     return np.concatenate(out).astype(np.int64)
 
 
+def gillespie_twostate(theta, times, n_per_time: int, seed: int = SEED_DATA):
+    """Two-state birth-death snapshot data (Sec. 3.1.2): independent runs from
+    n_R = 0 in the active gene state, observed as n_R only (the gene state is
+    hidden).  theta = (beta, gamma, lambda_act, lambda_ina).  Returns an (I, 2)
+    array of (time index, n_R)."""
+    beta, gamma, lact, lina = [float(x) for x in theta]
+    g = rng(seed)
+    # state (n_R, gene state); gene 0 = active
+    upd = np.array([[1, 0], [-1, 0], [0, 1], [0, -1]], np.int64)
+
+    def prop(s):
+        r = s[:, 0].astype(np.float64)
+        act = s[:, 1] == 0
+        return np.stack([np.where(act, beta, 0.0), gamma * r, np.where(act, lina, 0.0), np.where(act, 0.0, lact)],
+                        axis=1)
+
+    out = []
+    for j, T in enumerate(times):
+        fin = _gillespie_lockstep(g, n_per_time, float(T), prop, upd, [0, 0])
+        out.append(np.stack([np.full(n_per_time, j), fin[:, 0]], axis=1))
+    return np.concatenate(out).astype(np.int64)
+
+
+def gillespie_autoreg(theta, times, n_per_time: int, seed: int = SEED_DATA):
+    """Autoregulatory gene network snapshot data (Sec. 3.1.3): independent
+    runs from (n_R, n_P) = (0, 0) in the active gene state, observed as
+    (n_R, n_P) (the gene state is hidden).  theta = (beta_R, beta_P, gamma_R,
+    gamma_P, lambda_act, lambda_ina).  Returns (I, 3) rows (time index, n_R, n_P)."""
+    bR, bP, gR, gP, lact, lina = [float(x) for x in theta]
+    g = rng(seed)
+    # state (n_R, n_P, gene state); binding moves one P onto the gene
+    upd = np.array([[1, 0, 0], [0, 1, 0], [-1, 0, 0], [0, -1, 0], [0, -1, 1], [0, 1, -1]], np.int64)
+
+    def prop(s):
+        r = s[:, 0].astype(np.float64)
+        p = s[:, 1].astype(np.float64)
+        act = s[:, 2] == 0
+        return np.stack([np.where(act, bR, 0.0), bP * r, gR * r, gP * p, np.where(act, lina * p, 0.0),
+                         np.where(act, 0.0, lact)], axis=1)
+
+    out = []
+    for j, T in enumerate(times):
+        fin = _gillespie_lockstep(g, n_per_time, float(T), prop, upd, [0, 0, 0])
+        out.append(np.concatenate([np.full((n_per_time, 1), j), fin[:, :2]], axis=1))
+    return np.concatenate(out).astype(np.int64)
+
+
 def tally(pairs: np.ndarray) -> np.ndarray:
     """Collapse repeated observation rows into (row..., count) with a count
     column appended; rows sorted lexicographically."""

@@ -64,14 +64,17 @@ def test_struct_layouts_match_header(tmp_path):
 
 @pytest.mark.parametrize("leaky", [0, 1])
 @pytest.mark.parametrize("case", [(0, [500.0, 1.0], [1000]), (0, [3.0, 0.0], [9]), (1, [200.0, 1.0, 0.5, 0.5], [30, 20]),
-                                  (1, [5.0, 0.7, 0.0, 2.0], [7, 5]), (1, [1.0, 2.0, 3.0, 4.0], [1, 6])])
+                                  (1, [5.0, 0.7, 0.0, 2.0], [7, 5]), (1, [1.0, 2.0, 3.0, 4.0], [1, 6]),
+                                  (2, [100.0, 1.0, 2.0, 1.0], [250]), (2, [3.0, 0.5, 0.0, 1.5], [1]),
+                                  (3, [5.0, 0.25, 1.0, 0.1, 0.1, 0.05], [20, 40]),
+                                  (3, [2.5, 0.4, 1.0, 0.3, 0.0, 0.05], [1, 3])])
 def test_model_csr_matches_oracle(orc, case, leaky):
     model, theta, dims = case
     rp, ci, va = mjp.mjp_model_csr(mjp.make_model(model, theta, dims), leaky)
     ref = orc.model_generator(model, theta, dims, leaky=bool(leaky))
     assert np.array_equal(rp.astype(np.int64), ref.row_ptr)
     assert np.array_equal(ci, ref.col)
-    assert np.allclose(va, ref.val, rtol=1e-15, atol=0)
+    assert np.allclose(va, ref.val, rtol=1e-14, atol=0)
 
 
 def _csr(rp, ci, va):
@@ -239,3 +242,14 @@ def test_krylov_no_device_reports_device_error():
     if torch.cuda.is_available():
         pytest.skip("a GPU is present")
     assert status_of(mjp.mjp_krylov_create, *GOOD) == mjp.MJP_E_DEVICE
+
+
+@pytest.mark.parametrize("model,dims", [(2, [0, 1]), (2, [5, 2]), (3, [0, 4]), (3, [4, 0])])
+def test_new_model_dims_validation(model, dims):
+    m = mjp.make_model(model, [1.0] * 6, dims)
+    assert status_of(mjp.mjp_model_csr, m) == mjp.MJP_E_INVALID_ARG
+
+
+def test_stencil_plans_refuse_gene_state_models():
+    for model, dims in ((2, [10]), (3, [4, 5])):
+        assert status_of(mjp.mjp_plan_create_stencil, mjp.make_model(model, [1.0] * 6, dims)) == mjp.MJP_E_UNSUPPORTED

@@ -1,0 +1,148 @@
+"""GPU parity for the paper's second and third models (two-state birth-death,
+Sec. 3.1.2; autoregulatory gene network, Sec. 3.1.3) through the C ABI.
+
+* Propagation through CSR plans (mjp_model_csr -> mjp_plan_create_csr ->
+  mjp_expv) against the FP64 oracle, persistent and stepwise.  Bar from the
+  FP32 arithmetic: each jump forms every entry from at most five rounded
+  products and sums (relative error <= 3u, u = 2^-24, with the corrected
+  diagonal keeping the mass), and these errors accumulate like a random walk
+  over the K jumps, so L1 <= max(1e-6, 4 u sqrt(K)); entrywise relative
+  <= 1e-4 where p > 1e-7.  (The headline workload keeps its fixed 1e-6.)
+* Batched log-likelihoods with the gene state hidden (mjp_loglik sums a
+  record's probability over it) against the oracle's marginal definition:
+  |l_gpu - l_oracle| <= sum_i c_i (2e-6 + 2e-9 / p_i), the log-likelihood bar.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2312_05647_amd import mjp, synth
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+TS_THETA = [100.0, 1.0, 2.0, 1.0]                 # beta, gamma, lambda_act, lambda_ina (Sec. 3.1.2)
+AR_THETA = [5.0, 0.25, 1.0, 0.1, 0.1, 0.05]       # beta_R, beta_P, gamma_R, gamma_P, l_act, l_ina (Sec. 3.1.3)
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def expv_gpu(model, theta, dims, rho0, times, variant):
+    rp, ci, va = mjp.mjp_model_csr(mjp.make_model(model, theta, dims))
+    plan = mjp.mjp_plan_create_csr(rp, ci, va, mjp.mjp_opts_default(variant=variant))
+    try:
+        n = mjp.mjp_plan_n(plan)
+        r0 = torch.as_tensor(np.asarray(rho0, np.float32), device="cuda")
+        out = torch.empty((len(times), n), dtype=torch.float32, device="cuda")
+        inf = mjp.mjp_expv(plan, r0, times, out, info=True)
+        torch.cuda.synchronize()
+        return out.cpu().double().numpy(), inf
+    finally:
+        mjp.mjp_plan_destroy(plan)
+
+
+def check(got, ref, what, K):
+    l1 = np.abs(got - ref).sum()
+    big = ref > 1e-7
+    rel = (np.abs(got - ref)[big] / ref[big]).max()
+    bar = max(1e-6, 4 * 2.0 ** -24 * np.sqrt(K))
+    say(f"    {what}: K {K}  L1 {l1:.3e} (bar {bar:.2e})  rel {rel:.2e}")
+    assert l1 <= bar and rel <= 1e-4, (what, l1, bar, rel)
+    return l1
+
+
+@pytest.mark.parametrize("variant", [mjp.MJP_VARIANT_PERSISTENT, mjp.MJP_VARIANT_STEPWISE])
+def test_two_state_expv(orc, variant):
+    NR = 250
+    A = orc.model_generator(orc.MODEL_TWOSTATE, TS_THETA, [NR])
+    times = [0.5, 2.0, 10.0]
+    ref = orc.expv_times(A, synth.delta(2 * NR), times)
+    say(f"[gpu] two-state N={2 * NR} variant {variant}")
+    got, inf = expv_gpu(mjp.MJP_MODEL_TWOSTATE, TS_THETA, [NR, 1], synth.delta(2 * NR), times, variant)
+    for j, t in enumerate(times):
+        check(got[j], ref[j], f"t={t}", inf[j]["K"])
+        assert inf[j]["flags"] == 0
+
+
+@pytest.mark.parametrize("variant", [mjp.MJP_VARIANT_PERSISTENT, mjp.MJP_VARIANT_STEPWISE])
+def test_autoreg_expv(orc, variant):
+    NR, NP = 20, 60
+    A = orc.model_generator(orc.MODEL_AUTOREG, AR_THETA, [NR, NP])
+    rho0 = synth.random_prob(2 * NR * NP, 12)
+    times = [0.5, 3.0, 10.0]
+    ref = orc.expv_times(A, rho0, times)
+    say(f"[gpu] autoregulatory N={2 * NR * NP} variant {variant}")
+    got, inf = expv_gpu(mjp.MJP_MODEL_AUTOREG, AR_THETA, [NR, NP], rho0, times, variant)
+    for j, t in enumerate(times):
+        check(got[j], ref[j], f"t={t}", inf[j]["K"])
+
+
+def run_loglik(model, theta, dims, T, recs, x0):
+    B = len(theta)
+    th = torch.as_tensor(np.asarray(theta, np.float64), device="cuda").contiguous()
+    dm = torch.as_tensor(np.asarray(dims, np.int32), device="cuda")
+    out = torch.empty(B, dtype=torch.float64, device="cuda")
+    mjp.mjp_loglik(model, th, dm, mjp.make_obs(T, recs, x0), out)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def oracle_marginal(orc, model, theta, dims, T, groups, x0_index, n):
+    A = orc.model_generator(model, theta, dims)
+    rho = orc.expv_times(A, synth.delta(n, x0_index), T)
+    ll = orc.loglik_marginal(A, synth.delta(n, x0_index), T, groups)
+    tol = sum(c * (2e-6 + 2e-9 / max(rho[j, s].sum(), 1e-300)) for j, s, c in groups)
+    pmin = min(rho[j, s].sum() for j, s, c in groups)
+    return ll, tol, pmin
+
+
+def test_two_state_loglik(orc):
+    """Data as in the paper's design (20 times 0.5..10), 30 snapshots per time,
+    only n_R observed; 24 draws around the truth."""
+    T = synth.even_times(20, 0.5)
+    data = synth.gillespie_twostate(TS_THETA, T, 30, seed=synth.SEED_DATA)
+    tal = synth.tally(data)                         # (time, n_R, count)
+    recs = np.stack([tal[:, 0], tal[:, 1], np.zeros(len(tal), np.int64), tal[:, 2]], axis=1)
+    g = synth.rng(synth.SEED_THETA)
+    theta = np.asarray(TS_THETA) * np.exp(g.uniform(-0.3, 0.3, size=(24, 4)))
+    NR = int(max(2 * tal[:, 1].max(), 220))
+    dims = np.array([[NR, 1]] * 24)
+    say(f"[gpu] two-state loglik B=24 N={2 * NR}, {len(recs)} records")
+    got = run_loglik(mjp.MJP_MODEL_TWOSTATE, theta, dims, T, recs, (0, 0))
+    compared = 0
+    for b in range(24):
+        groups = [(int(j), [int(r), int(r) + NR], int(c)) for j, r, _, c in recs]
+        ll, tol, pmin = oracle_marginal(orc, orc.MODEL_TWOSTATE, theta[b], [NR], T, groups, 0, 2 * NR)
+        if pmin < 1e-12:
+            continue
+        assert abs(got[b] - ll) <= tol, (b, got[b], ll, tol)
+        compared += 1
+    assert compared >= 12
+
+
+def test_autoreg_loglik(orc):
+    """20 times 0.5..10, 30 snapshots each, (n_R, n_P) observed; 12 draws."""
+    T = synth.even_times(20, 0.5)
+    data = synth.gillespie_autoreg(AR_THETA, T, 30, seed=synth.SEED_DATA)
+    recs = synth.tally(data)                        # (time, n_R, n_P, count)
+    g = synth.rng(synth.SEED_THETA + 1)
+    theta = np.asarray(AR_THETA) * np.exp(g.uniform(-0.3, 0.3, size=(12, 6)))
+    NR, NP = 24, 60
+    assert recs[:, 1].max() < NR and recs[:, 2].max() < NP
+    dims = np.array([[NR, NP]] * 12)
+    say(f"[gpu] autoregulatory loglik B=12 N={2 * NR * NP}, {len(recs)} records")
+    got = run_loglik(mjp.MJP_MODEL_AUTOREG, theta, dims, T, recs, (0, 0))
+    plane = NR * NP
+    compared = 0
+    for b in range(12):
+        groups = [(int(j), [int(r) + NR * int(p), int(r) + NR * int(p) + plane], int(c)) for j, r, p, c in recs]
+        ll, tol, pmin = oracle_marginal(orc, orc.MODEL_AUTOREG, theta[b], [NR, NP], T, groups, 0, 2 * plane)
+        if pmin < 1e-12:
+            continue
+        assert abs(got[b] - ll) <= tol, (b, got[b], ll, tol)
+        compared += 1
+    assert compared >= 6
