@@ -22,6 +22,8 @@ What each function follows (Pessoa, Schweiger, Presse, arXiv 2312.05647):
   the paper).
 * ``oracle.krylov`` -- the Krylov-subspace propagator (Method #5, Algorithm
   ArnoldiKrylov, Eq. Krylov_expansion) in numpy FP64.
+* ``oracle.rk4`` -- the fourth-order Runge-Kutta propagator (Method #4, Eqs.
+  RKstep / RKintermediate) with time-dependent rates, numpy FP64.
 
 Parity status: every function above is pinned by ``tests/test_oracle_*.py``
 against closed forms, library routines (``scipy.stats.poisson``,
