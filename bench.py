@@ -162,6 +162,42 @@ def bench_krylov(torch, mjp, rp, ci, va, n, reps: int = 3):
     return res
 
 
+def rk4_bytes_per_step(n: int, nnz: int) -> float:
+    """Bytes the RK4 step streams: four products, each reading every stored
+    entry of the merged A^T once (8 B rate, 4 B source, 1 B channel) and the
+    stage input once; the stages also read x and read/write the weighted sum
+    (first stage: write only) and write the next stage input (last: the new
+    x): 24 + 40 + 40 + 32 = 136 B per state."""
+    return 4 * (13 * nnz + 8 * n) + 8 * n * (3 + 5 + 5 + 4)
+
+
+def bench_rk4(torch, mjp, rp, ci, va, n, reps: int = 3):
+    """Runge-Kutta propagator (Method #4) on the same N = 10^6 solve, FP64,
+    with the paper's step bound (dt_factor 1)."""
+    r0 = torch.zeros(n, dtype=torch.float64, device="cuda")
+    r0[0] = 1.0
+    out = torch.empty((1, n), dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    h = mjp.mjp_rk4_create([(rp, ci, va)], mjp.mjp_rk4_opts_default(dt_factor=1.0))
+    try:
+        info = mjp.mjp_rk4_expv(h, r0, [T_SOLVE], out, stream=stream)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(reps):
+            mjp.mjp_rk4_expv(h, r0, [T_SOLVE], out, stream=stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+    finally:
+        mjp.mjp_rk4_destroy(h)
+    sec = ev0.elapsed_time(ev1) / 1e3 / reps
+    ab = info["steps"] * rk4_bytes_per_step(n, len(ci))
+    log(f"[bench] rk4 f=1: {sec * 1e3:.2f} ms/solve, {info['steps']} steps, {ab / sec / 1e9:.0f} GB/s")
+    return {"ms_per_solve": sec * 1e3, "steps": info["steps"], "dt_factor": 1.0,
+            "streamed_GBps": ab / sec / 1e9, "frac_of_hbm_peak": ab / sec / 1e9 / HBM_PEAK_GBS,
+            "result": out[0].cpu().numpy()}
+
+
 def bench_loglik(torch, mjp, reps: int = 3):
     """Batched log-likelihoods: 4096 draws log-uniform over a decade around
     (50, 1, 0.5, 0.5), 20 collection times 0.5..10 with 50 snapshots each,
@@ -273,7 +309,7 @@ def main():
     ap.add_argument("--variant", type=int, default=0, help="0 auto, 1 stepwise, 2 persistent")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the secondary measurements")
-    ap.add_argument("--part", choices=["all", "loglik", "da", "small", "krylov"], default="all",
+    ap.add_argument("--part", choices=["all", "loglik", "da", "small", "krylov", "rk4"], default="all",
                     help="run only one secondary leg (for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the byte counters)")
@@ -307,6 +343,12 @@ def main():
         kr = bench_krylov(torch, mjp, rp, ci, va, S1 * S2)
         print(json.dumps({"krylov_method5": {k: {kk: vv for kk, vv in v.items() if kk != "result"}
                                              for k, v in kr.items()}}))
+        return
+
+    if args.part == "rk4":
+        rp, ci, va = mjp.mjp_model_csr(mjp.make_model(mjp.MJP_MODEL_CASCADE2, THETA, [S1, S2]))
+        r = bench_rk4(torch, mjp, rp, ci, va, S1 * S2)
+        print(json.dumps({"rk4_method4": {k: v for k, v in r.items() if k != "result"}}))
         return
 
     dev = torch.device("cuda:0")
@@ -395,6 +437,9 @@ def main():
         result["krylov_method5"] = {k: {kk: vv for kk, vv in v.items() if kk != "result"} for k, v in kry.items()}
         for k, v in kry.items():  # accuracy against the FP32 R-MJP result (its own L1 vs FP64 is ~3e-7)
             result["krylov_method5"][k]["l1_vs_rmjp_gpu"] = float(np.abs(v["result"] - got).sum())
+        rk = bench_rk4(torch, mjp, rp, ci, va, n)
+        result["rk4_method4"] = {k: v for k, v in rk.items() if k != "result"}
+        result["rk4_method4"]["l1_vs_rmjp_gpu"] = float(np.abs(rk["result"] - got).sum())
         result["small_configs"] = bench_small(torch, mjp)
         result["loglik_batch"] = bench_loglik(torch, mjp)
         result["da_mcmc"] = bench_da(torch, mjp)

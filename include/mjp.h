@@ -364,6 +364,56 @@ int32_t    mjp_krylov_n(const mjp_krylov* k);
 mjp_status mjp_krylov_expv(mjp_krylov* k, const double* rho0_d, int32_t n_t, const double* t_h, double* out_d,
                            mjp_krylov_info* info_h, mjp_stream_t stream);
 
+/* ----------------------------- Runge-Kutta propagator (Method #4) */
+
+/* rho(0) propagated by the classical fourth-order Runge-Kutta step
+ * (Sec. 2.3, Eqs. RKstep and RKintermediate), in FP64, with rates that may
+ * change in time: A(t) = sum_c g_c(t) A_c over 1..8 channels.  Each channel
+ * A_c is a generator (checked like mjp_plan_create_csr, conservative rows)
+ * and g_c(t) >= 0 is piecewise linear through the knots set with
+ * mjp_rk4_set_schedule, constant outside them (default: g_c = 1).  Step
+ * dt = dt_factor / m with m = max over the knots of max_n |a_nn(t)|
+ * (dt_factor 1 is the paper's stability bound); the last step before each
+ * requested time is shortened to land on it.  Error O(dt^4). */
+typedef struct mjp_rk4 mjp_rk4;
+
+typedef struct {
+    double  dt_factor;   /* > 0 (the paper's bound: 1) */
+    int32_t reserved[6];
+} mjp_rk4_opts;
+
+typedef struct {
+    double  m;           /* max over the schedule of max |a_nn(t)| */
+    double  dt;          /* full step length (inf when m = 0) */
+    int64_t steps;       /* steps taken over all requested times */
+    int32_t reserved[6];
+} mjp_rk4_info;
+
+/* Defaults: dt_factor 1. */
+void mjp_rk4_opts_default(mjp_rk4_opts* o);
+
+/* Merges the channels' A_c^T into one FP64 sliced-ELL operator (entry:
+ * source state, rate, channel) on the current device; every channel has the
+ * same n.  MJP_E_INVALID_ARG on n_channels outside 1..8 or mismatched sizes,
+ * MJP_E_NOT_GENERATOR as for a CSR plan.  The handle owns its device memory
+ * (operator + five N-vectors) until mjp_rk4_destroy. */
+mjp_status mjp_rk4_create(int32_t n_channels, const mjp_csr* channels, const mjp_rk4_opts* opts, mjp_rk4** out);
+void       mjp_rk4_destroy(mjp_rk4* k);
+int32_t    mjp_rk4_n(const mjp_rk4* k);
+
+/* g_c(t) through (t_knots[i], g_knots[i]), i < n_knots (host arrays, copied):
+ * times strictly increasing and finite, values finite and >= 0. */
+mjp_status mjp_rk4_set_schedule(mjp_rk4* k, int32_t channel, int32_t n_knots, const double* t_knots,
+                                const double* g_knots);
+
+/* out_d[j*N .. j*N+N-1] = rho(t_h[j]) for j < n_t (times in any order, >= 0;
+ * one propagation through the sorted times).  rho0_d and out_d are FP64
+ * device vectors owned by the caller; rho0_d is only read.  Asynchronous on
+ * `stream`; info_h (host, may be NULL) gets m, dt and the step count.  A
+ * handle must not be used on two streams at once. */
+mjp_status mjp_rk4_expv(mjp_rk4* k, const double* rho0_d, int32_t n_t, const double* t_h, double* out_d,
+                        mjp_rk4_info* info_h, mjp_stream_t stream);
+
 /* ---------------------------------------------------------------- misc */
 
 /* Message describing the last failure on this thread ("" if none). */

@@ -86,6 +86,18 @@ class mjp_krylov_info(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
 
 
+class mjp_rk4_opts(ctypes.Structure):
+    _fields_ = [("dt_factor", ctypes.c_double), ("reserved", ctypes.c_int32 * 6)]
+
+
+class mjp_rk4_info(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_double), ("dt", ctypes.c_double), ("steps", ctypes.c_int64),
+                ("reserved", ctypes.c_int32 * 6)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
 _lib = None
 
 # (name, restype, argtypes) of every exported function
@@ -117,6 +129,12 @@ _SIGS = [
     ("mjp_krylov_destroy", None, [_P]),
     ("mjp_krylov_n", ctypes.c_int32, [_P]),
     ("mjp_krylov_expv", ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, _P, _P]),
+    ("mjp_rk4_opts_default", None, [_P]),
+    ("mjp_rk4_create", ctypes.c_int, [ctypes.c_int32, _P, _P, _P]),
+    ("mjp_rk4_destroy", None, [_P]),
+    ("mjp_rk4_n", ctypes.c_int32, [_P]),
+    ("mjp_rk4_set_schedule", ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P, _P]),
+    ("mjp_rk4_expv", ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, _P, _P]),
     ("mjp_last_error", ctypes.c_char_p, []),
     ("mjp_version", ctypes.c_char_p, []),
 ]
@@ -280,6 +298,53 @@ def mjp_krylov_expv(k: int, rho0, times, out, stream=None) -> dict:
     t = np.ascontiguousarray(times, dtype=np.float64).reshape(-1)
     inf = mjp_krylov_info()
     _check(lib().mjp_krylov_expv(k, _ptr(rho0), len(t), _ptr(t), _ptr(out), ctypes.byref(inf), _stream(stream)))
+    return inf.as_dict()
+
+
+# -------------------------------------------------- Runge-Kutta (Method #4)
+
+def mjp_rk4_opts_default(**kw) -> mjp_rk4_opts:
+    o = mjp_rk4_opts()
+    lib().mjp_rk4_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def mjp_rk4_create(channels, opts: mjp_rk4_opts | None = None) -> int:
+    """channels: list of host CSR triples (row_ptr, col, val), one per A_c."""
+    keep = [(np.ascontiguousarray(rp, dtype=np.int32), np.ascontiguousarray(ci, dtype=np.int32),
+             np.ascontiguousarray(va, dtype=np.float64)) for rp, ci, va in channels]
+    arr = (mjp_csr * len(keep))(*[mjp_csr(len(rp) - 1, len(ci), _ptr(rp), _ptr(ci), _ptr(va))
+                                   for rp, ci, va in keep])
+    opts = opts or mjp_rk4_opts_default()
+    h = ctypes.c_void_p()
+    _check(lib().mjp_rk4_create(len(keep), arr, ctypes.byref(opts), ctypes.byref(h)))
+    return h.value
+
+
+def mjp_rk4_set_schedule(k: int, channel: int, t_knots, g_knots) -> None:
+    t = np.ascontiguousarray(t_knots, dtype=np.float64).reshape(-1)
+    g = np.ascontiguousarray(g_knots, dtype=np.float64).reshape(-1)
+    if len(t) != len(g):
+        raise ValueError("t_knots and g_knots differ in length")
+    _check(lib().mjp_rk4_set_schedule(k, channel, len(t), _ptr(t), _ptr(g)))
+
+
+def mjp_rk4_destroy(k: int) -> None:
+    lib().mjp_rk4_destroy(k)
+
+
+def mjp_rk4_n(k: int) -> int:
+    return int(lib().mjp_rk4_n(k))
+
+
+def mjp_rk4_expv(k: int, rho0, times, out, stream=None) -> dict:
+    """out[j] = rho(times[j]); rho0 [N] and out [n_t, N] are float64 CUDA
+    tensors.  Returns the info dict (m, dt, steps) filled on the host."""
+    t = np.ascontiguousarray(times, dtype=np.float64).reshape(-1)
+    inf = mjp_rk4_info()
+    _check(lib().mjp_rk4_expv(k, _ptr(rho0), len(t), _ptr(t), _ptr(out), ctypes.byref(inf), _stream(stream)))
     return inf.as_dict()
 
 

@@ -44,7 +44,8 @@ def test_struct_layouts_match_header(tmp_path):
     structs = {"mjp_opts": mjp.mjp_opts, "mjp_info": mjp.mjp_info, "mjp_csr": mjp.mjp_csr,
                "mjp_model": mjp.mjp_model, "mjp_obs": mjp.mjp_obs, "mjp_mlp_cfg": mjp.mjp_mlp_cfg,
                "mjp_train_cfg": mjp.mjp_train_cfg, "mjp_krylov_opts": mjp.mjp_krylov_opts,
-               "mjp_krylov_info": mjp.mjp_krylov_info}
+               "mjp_krylov_info": mjp.mjp_krylov_info,
+               "mjp_rk4_opts": mjp.mjp_rk4_opts, "mjp_rk4_info": mjp.mjp_rk4_info}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mjp.h"', "int main(void) {"]
     for name, cls in structs.items():
         lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
@@ -242,6 +243,35 @@ def test_krylov_no_device_reports_device_error():
     if torch.cuda.is_available():
         pytest.skip("a GPU is present")
     assert status_of(mjp.mjp_krylov_create, *GOOD) == mjp.MJP_E_DEVICE
+
+
+@pytest.mark.parametrize("channels,kw,expect", [
+    ([], {}, mjp.MJP_E_INVALID_ARG),                                   # no channel
+    ([GOOD] * 9, {}, mjp.MJP_E_INVALID_ARG),                           # more than 8
+    ([GOOD, _csr([0, 1], [0], [0.0])], {}, mjp.MJP_E_INVALID_ARG),      # sizes differ
+    ([GOOD], dict(dt_factor=0.0), mjp.MJP_E_INVALID_ARG),
+    ([GOOD], dict(dt_factor=float("inf")), mjp.MJP_E_INVALID_ARG),
+    ([GOOD, _csr([0, 2, 4], [0, 1, 0, 1], [-1.0, 1.0, -2.0, 2.0])], {}, mjp.MJP_E_NOT_GENERATOR),
+    ([_csr([0, 2, 4], [0, 1, 0, 1], [-1.0, 1.5, 2.0, -2.0])], {}, mjp.MJP_E_NOT_GENERATOR),
+])
+def test_rk4_create_validation(channels, kw, expect):
+    assert status_of(mjp.mjp_rk4_create, channels, mjp.mjp_rk4_opts_default(**kw)) == expect
+
+
+def test_rk4_null_handles_and_defaults():
+    L = mjp.lib()
+    assert L.mjp_rk4_expv(None, None, 1, None, None, None, None) == mjp.MJP_E_INVALID_ARG
+    assert L.mjp_rk4_set_schedule(None, 0, 1, None, None) == mjp.MJP_E_INVALID_ARG
+    assert L.mjp_rk4_n(None) == 0
+    L.mjp_rk4_destroy(None)
+    assert mjp.mjp_rk4_opts_default().dt_factor == 1.0
+
+
+def test_rk4_no_device_reports_device_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    assert status_of(mjp.mjp_rk4_create, [GOOD, GOOD]) == mjp.MJP_E_DEVICE
 
 
 @pytest.mark.parametrize("model,dims", [(2, [0, 1]), (2, [5, 2]), (3, [0, 4]), (3, [4, 0])])
