@@ -164,11 +164,12 @@ def bench_krylov(torch, mjp, rp, ci, va, n, reps: int = 3):
 
 def rk4_bytes_per_step(n: int, nnz: int) -> float:
     """Bytes the RK4 step streams: four products, each reading every stored
-    entry of the merged A^T once (8 B rate, 4 B source, 1 B channel) and the
-    stage input once; the stages also read x and read/write the weighted sum
-    (first stage: write only) and write the next stage input (last: the new
-    x): 24 + 40 + 40 + 32 = 136 B per state."""
-    return 4 * (13 * nnz + 8 * n) + 8 * n * (3 + 5 + 5 + 4)
+    entry of the merged A^T once (8 B rate, 4 B source, 1 B channel); per
+    state, stage 1 reads x and writes the next input and the weighted sum
+    (24 B), stages 2 and 3 read their input and x, write the next input and
+    read/write the sum (40 B each), stage 4 reads its input, x and the sum
+    and writes the new x (32 B): 136 B per state."""
+    return 4 * 13 * nnz + 136 * n
 
 
 def bench_rk4(torch, mjp, rp, ci, va, n, reps: int = 3):
