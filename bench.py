@@ -231,12 +231,31 @@ def bench_loglik(torch, mjp, reps: int = 3):
     sz = ctypes.sizeof(mjp.mjp_info)
     K = np.array([mjp.mjp_info.from_buffer_copy(raw[i * sz:(i + 1) * sz]).K for i in range(B)], np.float64)
     cells = float(np.sum((K + 1) * dims[:, 0] * dims[:, 1]))
-    log(f"[bench] loglik batch: {sec * 1e3:.1f} ms for {B} draws, {B / sec:.0f} loglik/s")
+    default_shapes = mjp.mjp_loglik_get_shapes(1, len(recs))
+    log(f"[bench] loglik batch: {sec * 1e3:.1f} ms for {B} draws, {B / sec:.0f} loglik/s (default shapes)")
+    # autotuner: time every eligible launch shape per size class on this batch
+    rep = mjp.mjp_loglik_tune(1, th, dm, obs, out, reps=1, stream=stream)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(reps):
+        mjp.mjp_loglik(1, th, dm, obs, out, stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    sec_t = ev0.elapsed_time(ev1) / 1e3 / reps
+    shapes = mjp.mjp_loglik_shapes()
+    log(f"[bench] loglik batch tuned: {sec_t * 1e3:.1f} ms, shapes {rep['chosen']} (items per class {rep['items']})")
     return {"workload": "4096 cascade draws, grids 50..200 per side, 20 times x 50 snapshots",
-            "loglik_per_s": B / sec, "ms_per_batch": sec * 1e3,
-            "cell_updates_per_s": cells / sec,
-            "lds_equiv_GBps": 8 * cells / sec / 1e9,
-            "finite_fraction": float(np.isfinite(out.cpu().numpy()).mean())}
+            "loglik_per_s": B / sec_t, "ms_per_batch": sec_t * 1e3,
+            "cell_updates_per_s": cells / sec_t,
+            "lds_equiv_GBps": 8 * cells / sec_t / 1e9,
+            "finite_fraction": float(np.isfinite(out.cpu().numpy()).mean()),
+            "ms_per_batch_default_shapes": sec * 1e3,
+            "tuner": {"items_per_class": rep["items"],
+                      "default": [f"{shapes[i]['threads']}x{shapes[i]['cells']}" for i in default_shapes],
+                      "chosen": [f"{shapes[i]['threads']}x{shapes[i]['cells']}" for i in rep["chosen"]],
+                      "ms_per_class_shape": {f"class{c}": {f"{shapes[i]['threads']}x{shapes[i]['cells']}": v
+                                                           for i, v in enumerate(rep["ms"][c][:len(shapes)]) if v >= 0}
+                                             for c in range(mjp.MJP_LL_CLASSES) if rep["items"][c] > 0}}}
 
 
 def bench_da(torch, mjp, chains: int = 2048, steps: int = 100, burn: int = 20, n_train: int = 16384):

@@ -238,9 +238,12 @@ typedef struct {
  * record's probability is the sum over it, Secs. 3.1.2-3.1.3):
  *   loglik_d[b] = sum_i count_i log rho_b(T_{j_i})_{(x1_i, x2_i)}
  * where rho_b solves the model with theta_d[b*4 .. b*4+3] on the grid
- * dims_d[b*2], dims_d[b*2+1] (conservative truncation).  All items run in one
- * persistent launch ordered longest-first; each item keeps its whole state
- * vector in the LDS of one workgroup, so S1*S2 <= mjp_loglik_max_states().
+ * dims_d[b*2], dims_d[b*2+1] (conservative truncation).  Items are grouped
+ * by size class (states <= mjp_loglik_class_limit(c), c < MJP_LL_CLASSES)
+ * and each class runs in one persistent launch, longest item first, with the
+ * class's launch shape (a default, or set by mjp_loglik_tune /
+ * mjp_loglik_set_shapes); each item keeps its whole state vector in the LDS
+ * of one workgroup, so S1*S2 <= mjp_loglik_max_states().
  * Only observed states are accumulated.  An observation outside an item's
  * grid, or with FP32 probability 0, gives -inf for that item (and a flag).
  *   theta_d  [B x P] FP64 device, P = 6 for MJP_MODEL_AUTOREG and 4 otherwise
@@ -260,6 +263,54 @@ mjp_status mjp_loglik(int32_t model, int32_t B, const double* theta_d, const int
 
 /* Largest S1*S2 a log-likelihood item may have (LDS capacity of one CU). */
 int32_t mjp_loglik_max_states(void);
+
+/* Launch shapes of the batched log-likelihood (not in the paper: how the
+ * batch maps onto the chip).  A shape is T threads per workgroup, each
+ * owning C cells of the item's state vector; it holds up to
+ * max_states = min(T*C, mjp_loglik_max_states()) states in lds_bytes of LDS,
+ * so smaller shapes let several workgroups share a CU, and a shape with T
+ * threads takes at most 4*T observation records.  Size class c holds the
+ * items with mjp_loglik_class_limit(c-1) < S1*S2 <= mjp_loglik_class_limit(c);
+ * a shape may run class c if max_states >= mjp_loglik_class_limit(c). */
+#define MJP_LL_CLASSES 4
+#define MJP_LL_MAX_SHAPES 16
+
+typedef struct {
+    int32_t threads, cells, max_states, lds_bytes;
+    int32_t reserved[4];
+} mjp_ll_shape;
+
+typedef struct {
+    int32_t items[MJP_LL_CLASSES];                    /* items of the batch per class */
+    int32_t chosen[MJP_LL_CLASSES];                   /* shape now used per class */
+    float   ms[MJP_LL_CLASSES][MJP_LL_MAX_SHAPES];    /* fastest of reps runs of (class,
+                                                         shape) in ms; -1 = not timed */
+} mjp_ll_tune_report;
+
+int32_t    mjp_loglik_num_shapes(void);
+/* MJP_E_INVALID_ARG for id outside [0, mjp_loglik_num_shapes()). */
+mjp_status mjp_loglik_shape(int32_t id, mjp_ll_shape* out_h);
+/* Largest S1*S2 of class cls (0 for cls outside [0, MJP_LL_CLASSES)). */
+int32_t    mjp_loglik_class_limit(int32_t cls);
+
+/* Shapes per class for a model on the current device: ids_h[MJP_LL_CLASSES],
+ * -1 = the default.  MJP_E_INVALID_ARG if a shape cannot hold its class.
+ * A call whose records exceed a chosen shape's 4*T uses the default. */
+mjp_status mjp_loglik_set_shapes(int32_t model, const int32_t* ids_h);
+/* The shapes a call with n_rec records would use now (defaults resolved). */
+mjp_status mjp_loglik_get_shapes(int32_t model, int32_t n_rec, int32_t* ids_h);
+
+/* Autotuner: runs the batch of mjp_loglik (same arguments) once per
+ * eligible shape and size class (after one warm-up run each, reps timed
+ * runs, HIP events on `stream`), keeps the fastest shape per class for this
+ * model on the current device, and reruns the chosen shapes, so loglik_d and
+ * info_d hold what mjp_loglik now returns.  Synchronous; do not call it
+ * while a graph is being captured.  report_h (host, may be NULL) gets the
+ * class sizes, the timings and the choice.  Results of different shapes
+ * differ only in the rounding of the mass renormalisation's block sums. */
+mjp_status mjp_loglik_tune(int32_t model, int32_t B, const double* theta_d, const int32_t* dims_d,
+                           const mjp_obs* obs, const mjp_opts* opts, double* loglik_d, mjp_info* info_d,
+                           int32_t reps, mjp_ll_tune_report* report_h, mjp_stream_t stream);
 
 /* ------------------------------------------------ surrogate (not in paper) */
 

@@ -9,19 +9,27 @@
 //               first jump whose geometric bound on the right tail is below
 //               tol/4, L the last whose bound on the left tail is; the window
 //               weight sum gives the residual lumped at K (Algorithm 2).
-//   k_ll_order  one block: items sorted by cost K_max * N, longest first.
-//   k_ll_main   (one instance per model) one workgroup per CU pulls items
-//               from an atomic queue.  The
-//               whole state vector of an item sits in LDS; each thread owns
-//               cells m = tid + i*1024; a jump is "compute the new values of
-//               my cells into registers, barrier, write back, barrier".  Only observed states are
+//   k_ll_order  one block: items grouped by size class (states <= 5120,
+//               10240, 20480, 40000), longest first (cost K_max * N) inside
+//               a class; writes the class offsets.
+//   k_ll_main   one launch per size class, each instance a (model, shape):
+//               shape = T threads x C cells per thread, with exactly the LDS
+//               of T*C states, so small shapes let several workgroups share a
+//               CU.  Workgroups pull the class's items from an atomic queue.
+//               The whole state vector of an item sits in LDS; each thread
+//               owns cells m = tid + i*T; a jump is "compute the new values of
+//               my cells into registers, barrier, write back, barrier".  The
+//               shape per class is a default or the one mjp_loglik_tune
+//               measured fastest on the caller's batch.  Only observed states are
 //               accumulated (Kahan, FP32), one observation record per thread;
 //               the per-time weights are formed in FP64 log space by one
 //               thread per time.  The final sum of count * log p is FP64.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <mutex>
+#include <utility>
 #include <vector>
 
 #include "internal.h"
@@ -30,14 +38,27 @@ namespace mjp {
 
 mjp_status check_opts(const mjp_opts* o);
 
-constexpr int kLLThreads = 1024;
 constexpr int kLLMaxStates = 40000;            // 160,000 B of LDS
-constexpr int kLLCellsPerThread = (kLLMaxStates + kLLThreads - 1) / kLLThreads;  // 40
 constexpr int kLLMaxTimes = 64;
 constexpr int kLLRecPerThread = 4;
-constexpr int kLLMaxRecords = kLLThreads * kLLRecPerThread;
+constexpr int kLLMaxRecords = 1024 * kLLRecPerThread;
 constexpr int kLLMaxSort = 16384;
 constexpr int kLLExtraLds = 3584;             // weights, window table, reduction scratch
+
+// size classes of items (states S1*S2) and the launch shapes
+constexpr int kLLClasses = MJP_LL_CLASSES;
+constexpr int kLLClassCap[kLLClasses] = {5120, 10240, 20480, kLLMaxStates};
+__host__ __device__ inline int ll_class(int64_t n) { return n <= 5120 ? 0 : (n <= 10240 ? 1 : (n <= 20480 ? 2 : 3)); }
+
+struct LLShape {
+    int T, C;  // threads per workgroup, cells per thread
+};
+constexpr LLShape kLLShapes[] = {{1024, 40}, {512, 80}, {1024, 20}, {512, 40}, {256, 80}, {1024, 10}, {512, 20},
+                                 {256, 40},  {1024, 5}, {512, 10},  {256, 20}, {768, 53}, {768, 27}};
+constexpr int kLLNumShapes = (int)(sizeof(kLLShapes) / sizeof(kLLShapes[0]));
+static_assert(kLLNumShapes <= MJP_LL_MAX_SHAPES, "shape table larger than the report");
+constexpr int kLLDefaultShape[kLLClasses] = {8, 5, 2, 0};  // T = 1024, tightest C
+constexpr int ll_cap(int T, int C) { return T * C < kLLMaxStates ? T * C : kLLMaxStates; }
 
 struct LLWin {     // per (item, time)
     double W;
@@ -57,7 +78,8 @@ struct LLArgs {
     LLWin* __restrict__ win;            // [B][n_t]
     float* __restrict__ cost;           // [B]
     int32_t* __restrict__ order;        // [B]
-    unsigned* __restrict__ queue;       // [1]
+    unsigned* __restrict__ queue;       // [kLLClasses]
+    int32_t* __restrict__ cls_off;      // [kLLClasses + 1] class ranges of order[]
     double* __restrict__ loglik;        // [B]
     mjp_info* __restrict__ info;        // [B] or null
     int32_t B, n_t, n_rec, model, x0_1, x0_2;
@@ -114,7 +136,7 @@ __device__ double ll_max_exit(int model, const double* th, const int32_t* d) {
 
 __global__ void k_ll_prep(LLArgs a) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx == 0) *a.queue = 0u;
+    if (idx < kLLClasses) a.queue[idx] = 0u;
     if (idx >= a.B * a.n_t) return;
     const int b = idx / a.n_t, j = idx - b * a.n_t;
     const double* th = a.theta + ll_stride(a.model) * (int64_t)b;
@@ -183,33 +205,55 @@ __global__ void k_ll_prep(LLArgs a) {
     a.win[(int64_t)b * a.n_t + j] = w;
 }
 
-// cost of each item (max K over its times times its states), then a
-// longest-first ordering of the items
+// cost of each item (max K over its times times its states), its size
+// class, then the items grouped by class (ascending) and longest-first inside
+// a class; cls_off[c] .. cls_off[c+1] is class c's range of order[]
 __global__ void k_ll_order(LLArgs a) {
     extern __shared__ unsigned long long keys[];
+    __shared__ int cnt[kLLClasses], cur[kLLClasses];
     const int B = a.B;
     int P = 1;
     while (P < B) P <<= 1;
     const bool sort = P <= kLLMaxSort;
+    if (threadIdx.x < kLLClasses) cnt[threadIdx.x] = 0;
+    __syncthreads();
     for (int b = threadIdx.x; b < (sort ? P : B); b += blockDim.x) {
-        unsigned long long key = 0ull;
+        unsigned long long key = ~0ull;
         if (b < B) {
             int32_t kmax = 0;
             for (int j = 0; j < a.n_t; ++j) kmax = max(kmax, a.win[(int64_t)b * a.n_t + j].K);
             int S1, S2;
             ll_grid(a.model, a.dims + 2 * b, S1, S2);
-            const float c = (float)(kmax + 1) * (float)S1 * (float)S2;
+            const int cls = ll_class((int64_t)S1 * S2);
+            atomicAdd(&cnt[cls], 1);
+            const float c = fmaxf((float)(kmax + 1) * (float)S1 * (float)S2, 0.f);
             a.cost[b] = c;
-            // descending cost: invert the (non-negative) float bits
-            key = ((unsigned long long)(~__float_as_uint(c)) << 32) | (unsigned)b;
-        } else {
-            key = ~0ull;
+            // class, then descending cost (inverted bits of a non-negative
+            // float, sign bit dropped), then the item
+            key = ((unsigned long long)cls << 62) | ((unsigned long long)(~__float_as_uint(c) & 0x7fffffffu) << 31) |
+                  (unsigned)b;
         }
         if (sort) keys[b] = key;
-        else a.order[b] = b;
     }
-    if (!sort) return;
     __syncthreads();
+    if (threadIdx.x == 0) {
+        int at = 0;
+        for (int c = 0; c < kLLClasses; ++c) {
+            a.cls_off[c] = at;
+            cur[c] = at;
+            at += cnt[c];
+        }
+        a.cls_off[kLLClasses] = at;
+    }
+    __syncthreads();
+    if (!sort) {  // too many items to sort in LDS: grouped by class only
+        for (int b = threadIdx.x; b < B; b += blockDim.x) {
+            int S1, S2;
+            ll_grid(a.model, a.dims + 2 * b, S1, S2);
+            a.order[atomicAdd(&cur[ll_class((int64_t)S1 * S2)], 1)] = b;
+        }
+        return;
+    }
     for (int size = 2; size <= P; size <<= 1) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
             for (int i = threadIdx.x; i < P; i += blockDim.x) {
@@ -223,9 +267,10 @@ __global__ void k_ll_order(LLArgs a) {
             __syncthreads();
         }
     }
-    for (int b = threadIdx.x; b < B; b += blockDim.x) a.order[b] = (int32_t)(keys[b] & 0xffffffffu);
+    for (int b = threadIdx.x; b < B; b += blockDim.x) a.order[b] = (int32_t)(keys[b] & 0x7fffffffu);
 }
 
+template <int T>
 __device__ __forceinline__ double ll_block_sum(double v, double* scratch) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -233,7 +278,7 @@ __device__ __forceinline__ double ll_block_sum(double v, double* scratch) {
     if (lane == 0) scratch[wid] = v;
     __syncthreads();
     double s = 0.0;
-    for (int i = 0; i < kLLThreads / 64; ++i) s += scratch[i];  // same order in every thread
+    for (int i = 0; i < T / 64; ++i) s += scratch[i];  // same order in every thread
     __syncthreads();
     return s;
 }
@@ -298,23 +343,25 @@ __device__ __forceinline__ float ll_cell(const float* rho, int m, int i1, int i2
     }
 }
 
-template <int MODEL>
-__global__ __launch_bounds__(kLLThreads) void k_ll_main(LLArgs a) {
+template <int MODEL, int T, int C>
+__global__ __launch_bounds__(T) void k_ll_main(LLArgs a, int cls) {
+    constexpr int CAP = ll_cap(T, C);  // states this shape holds (a multiple of 2)
     extern __shared__ char lds[];
-    float* rho = reinterpret_cast<float*>(lds);                                   // [kLLMaxStates]
-    double* wbuf = reinterpret_cast<double*>(lds + sizeof(float) * kLLMaxStates);  // [2][kLLMaxTimes]
+    float* rho = reinterpret_cast<float*>(lds);                          // [CAP]
+    double* wbuf = reinterpret_cast<double*>(lds + sizeof(float) * CAP);  // [2][kLLMaxTimes]
     double* scratch = wbuf + 2 * kLLMaxTimes;                                      // [16]
     LLWin* win = reinterpret_cast<LLWin*>(scratch + 16);                           // [kLLMaxTimes]
     __shared__ int item_sh;
     __shared__ unsigned flag_sh;
     const int tid = threadIdx.x;
 
+    const int first = a.cls_off[cls], last = a.cls_off[cls + 1];
     while (true) {
-        if (tid == 0) item_sh = (int)atomicAdd(a.queue, 1u);
+        if (tid == 0) item_sh = first + (int)atomicAdd(a.queue + cls, 1u);
         __syncthreads();
         const int slot = item_sh;
         __syncthreads();
-        if (slot >= a.B) break;
+        if (slot >= last) break;
         const int b = a.order[slot];
         const double* th = a.theta + ll_stride(MODEL) * (int64_t)b;
         int S1, S2;
@@ -333,7 +380,7 @@ __global__ __launch_bounds__(kLLThreads) void k_ll_main(LLArgs a) {
         }
         const int64_t N64 = (int64_t)S1 * S2;
         double omega = a.omega_factor * ll_max_exit(MODEL, th, a.dims + 2 * b);
-        if (over || S1 < 1 || S2 < 1 || N64 > kLLMaxStates) {
+        if (over || S1 < 1 || S2 < 1 || N64 > CAP) {
             if (tid == 0) {
                 a.loglik[b] = -INFINITY;
                 if (a.info) {
@@ -352,13 +399,13 @@ __global__ __launch_bounds__(kLLThreads) void k_ll_main(LLArgs a) {
         for (int i = 0; i < 6; ++i) kc.c[i] = i < ll_params(MODEL) ? (float)(th[i] / om) : 0.f;
         kc.NP = MODEL == MJP_MODEL_AUTOREG ? a.dims[2 * b + 1] : 1;
 
-        // owned cells, their coordinates advance by 1024 = q*S1 + r per step
-        const int q1024 = kLLThreads / S1, r1024 = kLLThreads - q1024 * S1;
+        // owned cells, their coordinates advance by T = q*S1 + r per step
+        const int qT = T / S1, rT = T - qT * S1;
         // rho(0) = point mass at x0 (if on the grid); for the two-state model
         // x0 = (n_R, gene state), for the autoregulatory one (n_R, n_P), active
         const int x0lim2 = MODEL == MJP_MODEL_AUTOREG ? kc.NP : S2;
         const int x0 = (a.x0_1 < S1 && a.x0_2 < x0lim2) ? a.x0_1 + S1 * a.x0_2 : -1;
-        for (int m = tid; m < N; m += kLLThreads) rho[m] = (m == x0) ? 1.f : 0.f;
+        for (int m = tid; m < N; m += T) rho[m] = (m == x0) ? 1.f : 0.f;
 
         // observation records of this thread
         // an observed state; for the two gene-state models it is observed
@@ -370,7 +417,7 @@ __global__ __launch_bounds__(kLLThreads) void k_ll_main(LLArgs a) {
         float rs[kLLRecPerThread], rc[kLLRecPerThread];
 #pragma unroll
         for (int u = 0; u < kLLRecPerThread; ++u) {
-            const int r = tid + u * kLLThreads;
+            const int r = tid + u * T;
             rm[u] = -2;
             rt[u] = 0;
             rs[u] = 0.f;
@@ -403,32 +450,32 @@ __global__ __launch_bounds__(kLLThreads) void k_ll_main(LLArgs a) {
                 wbuf[(k & 1) * kLLMaxTimes + tid] = W > 0.0 ? exp(lw) : (k == 0 ? 1.0 : 0.0);
             }
             if (k > 0) {
-                float nv[kLLCellsPerThread];
+                float nv[C];
                 int i1 = i1_0, i2 = i2_0, mb = tid;
-                // opaque to the optimiser: stops it hoisting 40 cells' worth of
+                // opaque to the optimiser: stops it hoisting C cells' worth of
                 // addresses and predicates out of the jump loop (which spills)
                 asm volatile("" : "+v"(i1), "+v"(i2), "+v"(mb));
                 const float fs = (float)scale;
                 float part = 0.f;
 #pragma unroll
-                for (int c = 0; c < kLLCellsPerThread; ++c) {
-                    const int m = mb + c * kLLThreads;
+                for (int c = 0; c < C; ++c) {
+                    const int m = mb + c * T;
                     float y = 0.f;
                     if (m < N) y = fs * ll_cell<MODEL>(rho, m, i1, i2, S1, S2, kc);
                     nv[c] = y;
                     part += y;
-                    i1 += r1024;
-                    i2 += q1024;
+                    i1 += rT;
+                    i2 += qT;
                     if (i1 >= S1) { i1 -= S1; i2 += 1; }
                 }
                 __syncthreads();
 #pragma unroll
-                for (int c = 0; c < kLLCellsPerThread; ++c) {
-                    const int m = tid + c * kLLThreads;
+                for (int c = 0; c < C; ++c) {
+                    const int m = tid + c * T;
                     if (m < N) rho[m] = nv[c];
                 }
                 if (m_renorm > 0 && k % m_renorm == 0 && k < Kmax) {
-                    const double tot = ll_block_sum((double)part, scratch);  // includes the barrier
+                    const double tot = ll_block_sum<T>((double)part, scratch);  // includes the barrier
                     scale = tot > 0.0 ? 1.0 / tot : 1.0;  // rho(0) has unit mass
                 } else {
                     scale = 1.0;
@@ -461,7 +508,7 @@ __global__ __launch_bounds__(kLLThreads) void k_ll_main(LLArgs a) {
         bool neg_inf = false;
 #pragma unroll
         for (int u = 0; u < kLLRecPerThread; ++u) {
-            const int r = tid + u * kLLThreads;
+            const int r = tid + u * T;
             if (r >= a.n_rec) continue;
             if (rm[u] < 0) { neg_inf = true; continue; }
             const float p = rs[u] - rc[u];
@@ -473,13 +520,13 @@ __global__ __launch_bounds__(kLLThreads) void k_ll_main(LLArgs a) {
             ll += (double)a.rec[r].count * log((double)p);
         }
         if (flags) atomicOr(&flag_sh, flags);
-        const double tot = ll_block_sum(ll, scratch);
-        const double ninf = ll_block_sum(neg_inf ? 1.0 : 0.0, scratch);
+        const double tot = ll_block_sum<T>(ll, scratch);
+        const double ninf = ll_block_sum<T>(neg_inf ? 1.0 : 0.0, scratch);
         double mass = 0.0;
         {
             float part = 0.f;
-            for (int m = tid; m < N; m += kLLThreads) part += rho[m];
-            mass = ll_block_sum((double)part, scratch);
+            for (int m = tid; m < N; m += T) part += rho[m];
+            mass = ll_block_sum<T>((double)part, scratch);
         }
         if (tid == 0) {
             a.loglik[b] = ninf > 0.0 ? -INFINITY : tot;
@@ -500,13 +547,42 @@ __global__ __launch_bounds__(kLLThreads) void k_ll_main(LLArgs a) {
 
 // ---------------------------------------------------------------- host
 
+using MainFn = void (*)(LLArgs, int);
+
+template <int MODEL, size_t... S>
+constexpr std::array<MainFn, kLLNumShapes> ll_row(std::index_sequence<S...>) {
+    return {{&k_ll_main<MODEL, kLLShapes[S].T, kLLShapes[S].C>...}};
+}
+// kernel of (model, shape)
+static const std::array<MainFn, kLLNumShapes> kLLMains[4] = {
+    ll_row<MJP_MODEL_BD>(std::make_index_sequence<kLLNumShapes>{}),
+    ll_row<MJP_MODEL_CASCADE2>(std::make_index_sequence<kLLNumShapes>{}),
+    ll_row<MJP_MODEL_TWOSTATE>(std::make_index_sequence<kLLNumShapes>{}),
+    ll_row<MJP_MODEL_AUTOREG>(std::make_index_sequence<kLLNumShapes>{})};
+
+inline size_t ll_lds(int shape) {
+    return sizeof(float) * (size_t)ll_cap(kLLShapes[shape].T, kLLShapes[shape].C) + kLLExtraLds;
+}
+// a shape may run class c with n_rec records if it holds the class's largest
+// item and has a record slot per record
+inline bool ll_eligible(int shape, int cls, int n_rec) {
+    return ll_cap(kLLShapes[shape].T, kLLShapes[shape].C) >= kLLClassCap[cls] &&
+           n_rec <= kLLRecPerThread * kLLShapes[shape].T;
+}
+
 struct LLContext {
     std::mutex mu;
     int device = -1;
-    DevBuf rec, T, win, cost, order, queue;
+    DevBuf rec, T, win, cost, order, queue, cls_off;
     std::vector<LLRecord> rec_host;
     std::vector<double> T_host;
     bool attr_set = false;
+    int occ[4][kLLNumShapes] = {};  // resident workgroups per CU (0 = not queried)
+    int shape[4][kLLClasses];       // chosen shape per (model, class); -1 = default
+    LLContext() {
+        for (auto& m : shape)
+            for (int& c : m) c = -1;
+    }
 };
 
 static LLContext& ctx_for(int dev) {
@@ -518,12 +594,87 @@ static LLContext& ctx_for(int dev) {
 
 using namespace mjp;
 
+namespace mjp {
+
+// per-call buffers, kernel attributes and the argument block
+static mjp_status ll_setup(LLContext& C, int model, int B, const mjp_obs* obs, const mjp_opts* opts,
+                           const double* theta_d, const int32_t* dims_d, double* loglik_d, mjp_info* info_d,
+                           LLArgs& a) {
+    mjp_status st;
+    if ((st = C.win.reserve(sizeof(LLWin) * (size_t)B * obs->n_t)) || (st = C.cost.reserve(sizeof(float) * B)) ||
+        (st = C.order.reserve(sizeof(int32_t) * B)) || (st = C.queue.reserve(64)) ||
+        (st = C.cls_off.reserve(sizeof(int32_t) * (kLLClasses + 1))))
+        return st;
+    if (!C.attr_set) {
+        for (int m = 0; m < 4; ++m)
+            for (int sid = 0; sid < kLLNumShapes; ++sid) {
+                MJP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kLLMains[m][sid]),
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)ll_lds(sid)));
+                int nb = 0;
+                MJP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kLLMains[m][sid], kLLShapes[sid].T,
+                                                                     ll_lds(sid)));
+                C.occ[m][sid] = std::max(nb, 1);
+            }
+        MJP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_ll_order), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)(sizeof(unsigned long long) * kLLMaxSort)));
+        C.attr_set = true;
+    }
+    a = LLArgs{};
+    a.theta = theta_d;
+    a.dims = dims_d;
+    a.T = C.T.as<double>();
+    a.rec = C.rec.as<LLRecord>();
+    a.win = C.win.as<LLWin>();
+    a.cost = C.cost.as<float>();
+    a.order = C.order.as<int32_t>();
+    a.queue = C.queue.as<unsigned>();
+    a.cls_off = C.cls_off.as<int32_t>();
+    a.loglik = loglik_d;
+    a.info = info_d;
+    a.B = B;
+    a.n_t = obs->n_t;
+    a.n_rec = obs->n_obs;
+    a.model = model;
+    a.x0_1 = obs->x0[0];
+    a.x0_2 = obs->x0[1];
+    a.omega_factor = opts->omega_factor;
+    a.tol = opts->tol;
+    a.k_rule = opts->k_rule;
+    a.lump = opts->lump;
+    a.renorm_every = opts->truncation == MJP_CONSERVATIVE ? opts->renorm_every : 0;
+    a.k_cap = opts->k_cap;
+    return MJP_OK;
+}
+
+// windows, costs, classes and the order (also zeroes the class queues)
+static void ll_prepare(const LLArgs& a, hipStream_t s) {
+    const int nthr = a.B * a.n_t;
+    hipLaunchKernelGGL(k_ll_prep, dim3((nthr + 255) / 256), dim3(256), 0, s, a);
+    int P = 1;
+    while (P < a.B) P <<= 1;
+    const size_t sort_lds = P <= kLLMaxSort ? sizeof(unsigned long long) * P : 0;
+    hipLaunchKernelGGL(k_ll_order, dim3(1), dim3(1024), sort_lds, s, a);
+}
+
+// the items of class c with shape sid: as many workgroups as fit on the chip
+static void ll_launch(const LLContext& C, const LLArgs& a, int cls, int sid, hipStream_t s) {
+    int ncu = 0;
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, C.device);
+    const int grid = std::max(1, std::min(a.B, std::max(ncu, 1) * C.occ[a.model][sid]));
+    hipLaunchKernelGGL(kLLMains[a.model][sid], dim3(grid), dim3(kLLShapes[sid].T), ll_lds(sid), s, a, cls);
+}
+
+__global__ void k_ll_queue_reset(unsigned* q, int cls) { q[cls] = 0u; }
+
+}  // namespace mjp
+
 extern "C" int32_t mjp_loglik_max_states(void) { return kLLMaxStates; }
 
-extern "C" mjp_status mjp_loglik(int32_t model, int32_t B, const double* theta_d, const int32_t* dims_d,
-                                 const mjp_obs* obs, const mjp_opts* opts, double* loglik_d, mjp_info* info_d,
-                                 mjp_stream_t stream) {
-    clear_error();
+namespace mjp {
+
+// host checks of a log-likelihood call; the records in kernel form
+static mjp_status ll_check(int32_t model, int32_t B, const mjp_obs* obs, const mjp_opts* opts,
+                           std::vector<LLRecord>& recs) {
     MJP_CHECK(model >= MJP_MODEL_BD && model <= MJP_MODEL_AUTOREG, MJP_E_INVALID_ARG, "unknown model %d", model);
     MJP_CHECK(B >= 0, MJP_E_INVALID_ARG, "B must be >= 0");
     mjp_status st = check_opts(opts);
@@ -539,7 +690,7 @@ extern "C" mjp_status mjp_loglik(int32_t model, int32_t B, const double* theta_d
               MJP_E_INVALID_ARG, "bad initial state");
     for (int j = 0; j < obs->n_t; ++j)
         MJP_CHECK(std::isfinite(obs->T_h[j]) && obs->T_h[j] >= 0.0, MJP_E_INVALID_ARG, "T[%d] must be finite, >= 0", j);
-    std::vector<LLRecord> recs((size_t)obs->n_obs);
+    recs.resize((size_t)obs->n_obs);
     for (int i = 0; i < obs->n_obs; ++i) {
         const int32_t* r = obs->obs_h + 4 * (size_t)i;
         MJP_CHECK(r[0] >= 0 && r[0] < obs->n_t, MJP_E_INVALID_ARG, "record %d: time index out of range", i);
@@ -549,16 +700,13 @@ extern "C" mjp_status mjp_loglik(int32_t model, int32_t B, const double* theta_d
         MJP_CHECK(r[3] >= 1, MJP_E_INVALID_ARG, "record %d: count must be >= 1", i);
         recs[(size_t)i] = {r[0], r[1], r[2], r[3]};
     }
-    if (B == 0) return MJP_OK;
-    MJP_CHECK(theta_d && dims_d && loglik_d, MJP_E_INVALID_ARG, "null device array");
+    return MJP_OK;
+}
 
-    int dev = 0;
-    MJP_HIP(hipGetDevice(&dev));
-    LLContext& C = ctx_for(dev);
-    std::lock_guard<std::mutex> lock(C.mu);
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    // observation tables are uploaded only when they change, so repeated
-    // calls with the same data enqueue kernels only (graph-capturable)
+// observation tables are uploaded only when they change, so repeated calls
+// with the same data enqueue kernels only (graph-capturable)
+static mjp_status ll_upload(LLContext& C, int dev, const std::vector<LLRecord>& recs, const mjp_obs* obs) {
+    mjp_status st;
     const bool same_rec = C.device == dev && C.rec_host.size() == recs.size() &&
                           (recs.empty() || std::memcmp(C.rec_host.data(), recs.data(), sizeof(LLRecord) * recs.size()) == 0);
     const bool same_T = C.device == dev && C.T_host.size() == (size_t)obs->n_t &&
@@ -574,54 +722,163 @@ extern "C" mjp_status mjp_loglik(int32_t model, int32_t B, const double* theta_d
         C.T_host.assign(obs->T_h, obs->T_h + obs->n_t);
     }
     C.device = dev;
-    if ((st = C.win.reserve(sizeof(LLWin) * (size_t)B * obs->n_t)) || (st = C.cost.reserve(sizeof(float) * B)) ||
-        (st = C.order.reserve(sizeof(int32_t) * B)) || (st = C.queue.reserve(64)))
+    return MJP_OK;
+}
+
+inline int ll_effective(const LLContext& C, int model, int cls, int n_rec) {
+    const int sid = C.shape[model][cls];
+    return (sid < 0 || !ll_eligible(sid, cls, n_rec)) ? kLLDefaultShape[cls] : sid;
+}
+
+}  // namespace mjp
+
+extern "C" mjp_status mjp_loglik(int32_t model, int32_t B, const double* theta_d, const int32_t* dims_d,
+                                 const mjp_obs* obs, const mjp_opts* opts, double* loglik_d, mjp_info* info_d,
+                                 mjp_stream_t stream) {
+    clear_error();
+    std::vector<LLRecord> recs;
+    mjp_status st = ll_check(model, B, obs, opts, recs);
+    if (st) return st;
+    if (B == 0) return MJP_OK;
+    MJP_CHECK(theta_d && dims_d && loglik_d, MJP_E_INVALID_ARG, "null device array");
+    int dev = 0;
+    MJP_HIP(hipGetDevice(&dev));
+    LLContext& C = ctx_for(dev);
+    std::lock_guard<std::mutex> lock(C.mu);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    LLArgs a;
+    if ((st = ll_upload(C, dev, recs, obs)) || (st = ll_setup(C, model, B, obs, opts, theta_d, dims_d, loglik_d, info_d, a)))
         return st;
-    const size_t lds = sizeof(float) * kLLMaxStates + kLLExtraLds;
-    using MainFn = void (*)(LLArgs);
-    const MainFn mains[4] = {k_ll_main<MJP_MODEL_BD>, k_ll_main<MJP_MODEL_CASCADE2>, k_ll_main<MJP_MODEL_TWOSTATE>,
-                             k_ll_main<MJP_MODEL_AUTOREG>};
-    if (!C.attr_set) {
-        for (MainFn f : mains)
-            MJP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(f), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        (int)lds));
-        MJP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_ll_order), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)(sizeof(unsigned long long) * kLLMaxSort)));
-        C.attr_set = true;
-    }
-    LLArgs a{};
-    a.theta = theta_d;
-    a.dims = dims_d;
-    a.T = C.T.as<double>();
-    a.rec = C.rec.as<LLRecord>();
-    a.win = C.win.as<LLWin>();
-    a.cost = C.cost.as<float>();
-    a.order = C.order.as<int32_t>();
-    a.queue = C.queue.as<unsigned>();
-    a.loglik = loglik_d;
-    a.info = info_d;
-    a.B = B;
-    a.n_t = obs->n_t;
-    a.n_rec = obs->n_obs;
-    a.model = model;
-    a.x0_1 = obs->x0[0];
-    a.x0_2 = obs->x0[1];
-    a.omega_factor = opts->omega_factor;
-    a.tol = opts->tol;
-    a.k_rule = opts->k_rule;
-    a.lump = opts->lump;
-    a.renorm_every = opts->truncation == MJP_CONSERVATIVE ? opts->renorm_every : 0;
-    a.k_cap = opts->k_cap;
-    const int nthr = B * obs->n_t;
-    hipLaunchKernelGGL(k_ll_prep, dim3((nthr + 255) / 256), dim3(256), 0, s, a);
-    int P = 1;
-    while (P < B) P <<= 1;
-    const size_t sort_lds = P <= kLLMaxSort ? sizeof(unsigned long long) * P : 0;
-    hipLaunchKernelGGL(k_ll_order, dim3(1), dim3(1024), sort_lds, s, a);
-    int ncu = 0;
-    MJP_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    const int grid = std::min(B, ncu);
-    hipLaunchKernelGGL(mains[model], dim3(grid), dim3(kLLThreads), lds, s, a);
+    ll_prepare(a, s);
+    for (int c = 0; c < kLLClasses; ++c) ll_launch(C, a, c, ll_effective(C, model, c, a.n_rec), s);
     MJP_HIP(hipGetLastError());
+    return MJP_OK;
+}
+
+extern "C" int32_t mjp_loglik_num_shapes(void) { return kLLNumShapes; }
+
+extern "C" mjp_status mjp_loglik_shape(int32_t id, mjp_ll_shape* out) {
+    clear_error();
+    MJP_CHECK(out, MJP_E_INVALID_ARG, "out is NULL");
+    MJP_CHECK(id >= 0 && id < kLLNumShapes, MJP_E_INVALID_ARG, "shape %d out of range [0, %d)", id, kLLNumShapes);
+    std::memset(out, 0, sizeof(*out));
+    out->threads = kLLShapes[id].T;
+    out->cells = kLLShapes[id].C;
+    out->max_states = ll_cap(kLLShapes[id].T, kLLShapes[id].C);
+    out->lds_bytes = (int32_t)ll_lds(id);
+    return MJP_OK;
+}
+
+extern "C" int32_t mjp_loglik_class_limit(int32_t cls) {
+    return (cls >= 0 && cls < kLLClasses) ? kLLClassCap[cls] : 0;
+}
+
+extern "C" mjp_status mjp_loglik_set_shapes(int32_t model, const int32_t* ids) {
+    clear_error();
+    MJP_CHECK(model >= MJP_MODEL_BD && model <= MJP_MODEL_AUTOREG, MJP_E_INVALID_ARG, "unknown model %d", model);
+    MJP_CHECK(ids, MJP_E_INVALID_ARG, "ids is NULL");
+    for (int c = 0; c < kLLClasses; ++c) {
+        MJP_CHECK(ids[c] >= -1 && ids[c] < kLLNumShapes, MJP_E_INVALID_ARG, "class %d: shape %d out of range", c, ids[c]);
+        MJP_CHECK(ids[c] < 0 || ll_cap(kLLShapes[ids[c]].T, kLLShapes[ids[c]].C) >= kLLClassCap[c], MJP_E_INVALID_ARG,
+                  "class %d: shape %d holds fewer than %d states", c, ids[c], kLLClassCap[c]);
+    }
+    int dev = 0;
+    MJP_HIP(hipGetDevice(&dev));
+    LLContext& C = ctx_for(dev);
+    std::lock_guard<std::mutex> lock(C.mu);
+    for (int c = 0; c < kLLClasses; ++c) C.shape[model][c] = ids[c];
+    return MJP_OK;
+}
+
+extern "C" mjp_status mjp_loglik_get_shapes(int32_t model, int32_t n_rec, int32_t* ids) {
+    clear_error();
+    MJP_CHECK(model >= MJP_MODEL_BD && model <= MJP_MODEL_AUTOREG, MJP_E_INVALID_ARG, "unknown model %d", model);
+    MJP_CHECK(ids, MJP_E_INVALID_ARG, "ids is NULL");
+    MJP_CHECK(n_rec >= 0 && n_rec <= kLLMaxRecords, MJP_E_INVALID_ARG, "n_rec must be in [0, %d]", kLLMaxRecords);
+    int dev = 0;
+    MJP_HIP(hipGetDevice(&dev));
+    LLContext& C = ctx_for(dev);
+    std::lock_guard<std::mutex> lock(C.mu);
+    for (int c = 0; c < kLLClasses; ++c) ids[c] = ll_effective(C, model, c, n_rec);
+    return MJP_OK;
+}
+
+extern "C" mjp_status mjp_loglik_tune(int32_t model, int32_t B, const double* theta_d, const int32_t* dims_d,
+                                      const mjp_obs* obs, const mjp_opts* opts, double* loglik_d, mjp_info* info_d,
+                                      int32_t reps, mjp_ll_tune_report* report, mjp_stream_t stream) {
+    clear_error();
+    std::vector<LLRecord> recs;
+    mjp_status st = ll_check(model, B, obs, opts, recs);
+    if (st) return st;
+    MJP_CHECK(reps >= 1 && reps <= 100, MJP_E_INVALID_ARG, "reps must be in [1, 100]");
+    MJP_CHECK(B >= 1, MJP_E_INVALID_ARG, "tuning needs B >= 1");
+    MJP_CHECK(theta_d && dims_d && loglik_d, MJP_E_INVALID_ARG, "null device array");
+    int dev = 0;
+    MJP_HIP(hipGetDevice(&dev));
+    LLContext& C = ctx_for(dev);
+    std::lock_guard<std::mutex> lock(C.mu);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    LLArgs a;
+    if ((st = ll_upload(C, dev, recs, obs)) || (st = ll_setup(C, model, B, obs, opts, theta_d, dims_d, loglik_d, info_d, a)))
+        return st;
+    ll_prepare(a, s);
+    int32_t off[kLLClasses + 1];
+    MJP_HIP(hipMemcpyAsync(off, a.cls_off, sizeof(off), hipMemcpyDeviceToHost, s));
+    MJP_HIP(hipStreamSynchronize(s));
+    mjp_ll_tune_report rep;
+    std::memset(&rep, 0, sizeof(rep));
+    for (auto& row : rep.ms)
+        for (float& v : row) v = -1.f;
+    hipEvent_t e0, e1;
+    MJP_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(MJP_E_DEVICE, "hipEventCreate failed");
+    }
+    st = MJP_OK;
+    for (int c = 0; c < kLLClasses && st == MJP_OK; ++c) {
+        rep.items[c] = off[c + 1] - off[c];
+        int best = ll_effective(C, model, c, a.n_rec);
+        if (rep.items[c] > 0) {
+            float best_ms = INFINITY;
+            for (int sid = 0; sid < kLLNumShapes && st == MJP_OK; ++sid) {
+                if (!ll_eligible(sid, c, a.n_rec)) continue;
+                float t_min = INFINITY;
+                for (int r = 0; r <= reps; ++r) {  // run 0 warms up
+                    hipLaunchKernelGGL(k_ll_queue_reset, dim3(1), dim3(1), 0, s, a.queue, c);
+                    if (hipEventRecord(e0, s) != hipSuccess) { st = fail(MJP_E_DEVICE, "hipEventRecord failed"); break; }
+                    ll_launch(C, a, c, sid, s);
+                    float ms = 0.f;
+                    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                        st = fail(MJP_E_DEVICE, "timing class %d shape %d failed: %s", c, sid,
+                                  hipGetErrorString(hipGetLastError()));
+                        break;
+                    }
+                    if (r > 0) t_min = std::min(t_min, ms);
+                }
+                rep.ms[c][sid] = t_min;
+                if (t_min < best_ms) {
+                    best_ms = t_min;
+                    best = sid;
+                }
+            }
+            if (st == MJP_OK) C.shape[model][c] = best;
+        }
+        rep.chosen[c] = best;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st) return st;
+    // the last run of each class was not the chosen shape's: run the chosen
+    // shapes once more so the outputs are the ones mjp_loglik gives
+    for (int c = 0; c < kLLClasses; ++c) {
+        if (rep.items[c] == 0) continue;
+        hipLaunchKernelGGL(k_ll_queue_reset, dim3(1), dim3(1), 0, s, a.queue, c);
+        ll_launch(C, a, c, rep.chosen[c], s);
+    }
+    MJP_HIP(hipGetLastError());
+    MJP_HIP(hipStreamSynchronize(s));
+    if (report) *report = rep;
     return MJP_OK;
 }

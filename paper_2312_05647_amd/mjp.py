@@ -25,6 +25,7 @@ MJP_CONSERVATIVE, MJP_LEAKY = 0, 1
 MJP_VARIANT_AUTO, MJP_VARIANT_STEPWISE, MJP_VARIANT_PERSISTENT, MJP_VARIANT_PERSISTENT_FENCED = 0, 1, 2, 3
 MJP_MODEL_BD, MJP_MODEL_CASCADE2, MJP_MODEL_TWOSTATE, MJP_MODEL_AUTOREG = 0, 1, 2, 3
 MJP_FLAG_NAN, MJP_FLAG_NEG, MJP_FLAG_UNDERFLOW_OBS, MJP_FLAG_OUT_OF_GRID, MJP_FLAG_K_LIMIT = 1, 2, 4, 8, 16
+MJP_LL_CLASSES, MJP_LL_MAX_SHAPES = 4, 16
 
 
 class MjpError(RuntimeError):
@@ -86,6 +87,16 @@ class mjp_krylov_info(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
 
 
+class mjp_ll_shape(ctypes.Structure):
+    _fields_ = [("threads", ctypes.c_int32), ("cells", ctypes.c_int32), ("max_states", ctypes.c_int32),
+                ("lds_bytes", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+
+
+class mjp_ll_tune_report(ctypes.Structure):
+    _fields_ = [("items", ctypes.c_int32 * MJP_LL_CLASSES), ("chosen", ctypes.c_int32 * MJP_LL_CLASSES),
+                ("ms", (ctypes.c_float * MJP_LL_MAX_SHAPES) * MJP_LL_CLASSES)]
+
+
 class mjp_rk4_opts(ctypes.Structure):
     _fields_ = [("dt_factor", ctypes.c_double), ("reserved", ctypes.c_int32 * 6)]
 
@@ -114,6 +125,13 @@ _SIGS = [
     ("mjp_expv_batched", ctypes.c_int, [ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P]),
     ("mjp_loglik", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P]),
     ("mjp_loglik_max_states", ctypes.c_int32, []),
+    ("mjp_loglik_num_shapes", ctypes.c_int32, []),
+    ("mjp_loglik_shape", ctypes.c_int, [ctypes.c_int32, _P]),
+    ("mjp_loglik_class_limit", ctypes.c_int32, [ctypes.c_int32]),
+    ("mjp_loglik_set_shapes", ctypes.c_int, [ctypes.c_int32, _P]),
+    ("mjp_loglik_get_shapes", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _P]),
+    ("mjp_loglik_tune", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P, _P, ctypes.c_int32, _P,
+                                       _P]),
     ("mjp_surrogate_create", ctypes.c_int, [_P, ctypes.c_uint64, _P]),
     ("mjp_surrogate_destroy", None, [_P]),
     ("mjp_surrogate_train", ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P, _P, _P]),
@@ -369,6 +387,46 @@ def mjp_loglik(model: int, theta, dims, obs: mjp_obs, out, opts: mjp_opts | None
 
 def mjp_loglik_max_states() -> int:
     return int(lib().mjp_loglik_max_states())
+
+
+def mjp_loglik_shapes() -> list:
+    """The launch-shape table: one dict per shape id."""
+    out = []
+    for i in range(int(lib().mjp_loglik_num_shapes())):
+        sh = mjp_ll_shape()
+        _check(lib().mjp_loglik_shape(i, ctypes.byref(sh)))
+        out.append({"threads": sh.threads, "cells": sh.cells, "max_states": sh.max_states,
+                    "lds_bytes": sh.lds_bytes})
+    return out
+
+
+def mjp_loglik_class_limits() -> list:
+    return [int(lib().mjp_loglik_class_limit(c)) for c in range(MJP_LL_CLASSES)]
+
+
+def mjp_loglik_set_shapes(model: int, ids) -> None:
+    """Shape id per size class for `model` on the current device (-1 = default)."""
+    a = (ctypes.c_int32 * MJP_LL_CLASSES)(*[int(i) for i in ids])
+    _check(lib().mjp_loglik_set_shapes(model, a))
+
+
+def mjp_loglik_get_shapes(model: int, n_rec: int = 0) -> list:
+    a = (ctypes.c_int32 * MJP_LL_CLASSES)()
+    _check(lib().mjp_loglik_get_shapes(model, n_rec, a))
+    return list(a)
+
+
+def mjp_loglik_tune(model: int, theta, dims, obs: mjp_obs, out, opts: mjp_opts | None = None, info=None,
+                    reps: int = 2, stream=None) -> dict:
+    """Times every eligible shape per size class on this batch, keeps the
+    fastest; `out` (and `info`) then hold the batch's log-likelihoods."""
+    opts = opts or mjp_opts_default()
+    B = int(out.shape[0])
+    rep = mjp_ll_tune_report()
+    _check(lib().mjp_loglik_tune(model, B, _ptr(theta), _ptr(dims), ctypes.byref(obs), ctypes.byref(opts), _ptr(out),
+                                 _ptr(info), reps, ctypes.byref(rep), _stream(stream)))
+    return {"items": list(rep.items), "chosen": list(rep.chosen),
+            "ms": [[float(v) for v in row] for row in rep.ms]}
 
 
 # ------------------------------------------------------------ surrogate

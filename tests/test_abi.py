@@ -45,7 +45,8 @@ def test_struct_layouts_match_header(tmp_path):
                "mjp_model": mjp.mjp_model, "mjp_obs": mjp.mjp_obs, "mjp_mlp_cfg": mjp.mjp_mlp_cfg,
                "mjp_train_cfg": mjp.mjp_train_cfg, "mjp_krylov_opts": mjp.mjp_krylov_opts,
                "mjp_krylov_info": mjp.mjp_krylov_info,
-               "mjp_rk4_opts": mjp.mjp_rk4_opts, "mjp_rk4_info": mjp.mjp_rk4_info}
+               "mjp_rk4_opts": mjp.mjp_rk4_opts, "mjp_rk4_info": mjp.mjp_rk4_info,
+               "mjp_ll_shape": mjp.mjp_ll_shape, "mjp_ll_tune_report": mjp.mjp_ll_tune_report}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mjp.h"', "int main(void) {"]
     for name, cls in structs.items():
         lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
@@ -189,6 +190,43 @@ def test_loglik_validation(kw, expect):
 
 def test_loglik_capacity():
     assert mjp.mjp_loglik_max_states() == 40000
+
+
+def test_loglik_shape_table():
+    """Every shape's capacity is min(T*C, 40000) in at most 160 KB of LDS
+    (plus the weight/window scratch); every size class has its default
+    shape (T = 1024, so every record count fits) and at least two others."""
+    shapes = mjp.mjp_loglik_shapes()
+    limits = mjp.mjp_loglik_class_limits()
+    assert limits == sorted(limits) and limits[-1] == mjp.mjp_loglik_max_states()
+    assert mjp.lib().mjp_loglik_class_limit(-1) == 0 and mjp.lib().mjp_loglik_class_limit(4) == 0
+    for sh in shapes:
+        assert sh["max_states"] == min(sh["threads"] * sh["cells"], 40000)
+        assert sh["threads"] % 64 == 0 and sh["lds_bytes"] <= 4 * 40000 + 4096
+    for lim in limits:
+        fit = [i for i, sh in enumerate(shapes) if sh["max_states"] >= lim]
+        assert len(fit) >= 3 and any(shapes[i]["threads"] == 1024 for i in fit)
+    out = mjp.mjp_ll_shape()
+    assert mjp.lib().mjp_loglik_shape(len(shapes), ctypes.byref(out)) == mjp.MJP_E_INVALID_ARG
+    assert mjp.lib().mjp_loglik_shape(-1, ctypes.byref(out)) == mjp.MJP_E_INVALID_ARG
+
+
+@pytest.mark.parametrize("ids", [[0, 0, 0, 99], [-2, -1, -1, -1], [0, 0, 0, 8]])  # out of range; too small for class 3
+def test_loglik_set_shapes_validation(ids):
+    assert status_of(mjp.mjp_loglik_set_shapes, 1, ids) == mjp.MJP_E_INVALID_ARG
+    assert status_of(mjp.mjp_loglik_set_shapes, 7, [-1] * 4) == mjp.MJP_E_INVALID_ARG
+
+
+def test_loglik_tune_validation():
+    obs = mjp.make_obs(np.asarray([1.0]), np.asarray([[0, 1, 1, 1]], np.int32), (0, 0))
+    o = mjp.mjp_opts_default()
+    d = np.zeros(8)
+    L = mjp.lib()
+    args = (ctypes.byref(obs), ctypes.byref(o), d.ctypes.data, None)
+    assert L.mjp_loglik_tune(1, 1, d.ctypes.data, d.ctypes.data, *args, 0, None, None) == mjp.MJP_E_INVALID_ARG
+    assert L.mjp_loglik_tune(1, 0, d.ctypes.data, d.ctypes.data, *args, 2, None, None) == mjp.MJP_E_INVALID_ARG
+    assert L.mjp_loglik_tune(1, 1, None, d.ctypes.data, *args, 2, None, None) == mjp.MJP_E_INVALID_ARG
+    assert L.mjp_loglik_tune(9, 1, d.ctypes.data, d.ctypes.data, *args, 2, None, None) == mjp.MJP_E_INVALID_ARG
 
 
 @pytest.mark.parametrize("cfg", [(0, 256, 3), (17, 256, 3), (4, 100, 3), (4, 1024, 3), (4, 256, 0), (4, 256, 9)])
