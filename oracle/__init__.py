@@ -24,6 +24,8 @@ What each function follows (Pessoa, Schweiger, Presse, arXiv 2312.05647):
   ArnoldiKrylov, Eq. Krylov_expansion) in numpy FP64.
 * ``oracle.rk4`` -- the fourth-order Runge-Kutta propagator (Method #4, Eqs.
   RKstep / RKintermediate) with time-dependent rates, numpy FP64.
+* ``oracle.jmjp`` -- J-MJP (Method #2): the state probabilities given the
+  jump counts (its Algorithm) and the jump-count conditional, FP64.
 
 Parity status: every function above is pinned by ``tests/test_oracle_*.py``
 against closed forms, library routines (``scipy.stats.poisson``,
