@@ -312,6 +312,28 @@ mjp_status mjp_loglik_tune(int32_t model, int32_t B, const double* theta_d, cons
                            const mjp_obs* obs, const mjp_opts* opts, double* loglik_d, mjp_info* info_d,
                            int32_t reps, mjp_ll_tune_report* report_h, mjp_stream_t stream);
 
+/* J-MJP state probabilities (Method #2, Sec. 2.2.2, the algorithm of the
+ * state probabilities for J-MJP): for each draw b and observation i,
+ *   logphi_d[b*I + i] = log p(s_i | k_i, theta_b) = log (rho(0) B_b^{k_i})_{s_i}
+ * with B_b = I + A_b / Omega_b, Omega_b = omega_factor * max|a_nn| (the same
+ * Omega as mjp_loglik), k_i = k_d[b*I + i] the observation's own number of
+ * virtual jumps, I = obs->n_obs, and s_i the record's state (for the two
+ * gene-state models summed over the hidden gene state).  Every record's
+ * count must be 1 (each observation has its own jump count); the record's
+ * time index is not used here (the caller needs T for the jump-count prior
+ * Poisson(k | Omega_b T)).  One sweep per draw to max_i k_i, the iterate in
+ * LDS as in mjp_loglik (same size classes, default shapes), FP32 jumps and
+ * mass renormalisation, FP64 logs.
+ *   k_d      [B x I] int32 device; a draw with some k_i < 0 or > opts->k_cap
+ *            gets -inf everywhere and MJP_FLAG_K_LIMIT
+ *   logphi_d [B x I] FP64 device; -inf where the FP32 probability is 0 or the
+ *            state is off the draw's grid
+ *   omega_d  [B] FP64 device or NULL: Omega_b
+ * Asynchronous; opts->tol and variant are not used. */
+mjp_status mjp_jump_probs(int32_t model, int32_t B, const double* theta_d, const int32_t* dims_d,
+                          const mjp_obs* obs, const int32_t* k_d, const mjp_opts* opts, double* logphi_d,
+                          double* omega_d, mjp_stream_t stream);
+
 /* ------------------------------------------------ surrogate (not in paper) */
 
 typedef struct mjp_surrogate mjp_surrogate;

@@ -82,6 +82,9 @@ struct LLArgs {
     int32_t* __restrict__ cls_off;      // [kLLClasses + 1] class ranges of order[]
     double* __restrict__ loglik;        // [B]
     mjp_info* __restrict__ info;        // [B] or null
+    const int32_t* __restrict__ kobs;   // jump mode: [B][n_rec] jump count of each observation
+    double* __restrict__ phi;           // jump mode: [B][n_rec] log p(s_i | k_i, theta)
+    double* __restrict__ omega_out;     // jump mode: [B] Omega_theta, or null
     int32_t B, n_t, n_rec, model, x0_1, x0_2;
     double omega_factor, tol;
     int32_t k_rule, lump, renorm_every;
@@ -203,6 +206,28 @@ __global__ void k_ll_prep(LLArgs a) {
         if (K > a.k_cap) w.K = -1;  // marks the item as over the cap
     }
     a.win[(int64_t)b * a.n_t + j] = w;
+}
+
+// Jump mode (J-MJP state probabilities): one window per item whose K is
+// the largest jump count of its observations; an item with a count below 0
+// or above k_cap gets K = -1 (rejected like an item over the cap).
+__global__ void k_jp_prep(LLArgs a) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < kLLClasses) a.queue[b] = 0u;
+    if (b >= a.B) return;
+    int64_t kmax = 0;
+    bool bad = false;
+    for (int r = 0; r < a.n_rec; ++r) {
+        const int32_t k = a.kobs[(int64_t)b * a.n_rec + r];
+        bad |= k < 0 || (int64_t)k > a.k_cap;
+        kmax = max(kmax, (int64_t)k);
+    }
+    LLWin w;
+    w.W = 0.0;
+    w.lastw = 0.0;
+    w.L = 0;
+    w.K = bad ? -1 : (int32_t)kmax;
+    a.win[b] = w;
 }
 
 // cost of each item (max K over its times times its states), its size
@@ -343,7 +368,10 @@ __device__ __forceinline__ float ll_cell(const float* rho, int m, int i1, int i2
     }
 }
 
-template <int MODEL, int T, int C>
+// JUMP: the J-MJP state probabilities (Method #2's algorithm): no weights;
+// observation i records log rho_{k_i} at its state when the sweep reaches its
+// own jump count k_i (one window per item, n_t = 1).
+template <int MODEL, int T, int C, bool JUMP = false>
 __global__ __launch_bounds__(T) void k_ll_main(LLArgs a, int cls) {
     constexpr int CAP = ll_cap(T, C);  // states this shape holds (a multiple of 2)
     extern __shared__ char lds[];
@@ -381,8 +409,12 @@ __global__ __launch_bounds__(T) void k_ll_main(LLArgs a, int cls) {
         const int64_t N64 = (int64_t)S1 * S2;
         double omega = a.omega_factor * ll_max_exit(MODEL, th, a.dims + 2 * b);
         if (over || S1 < 1 || S2 < 1 || N64 > CAP) {
+            if constexpr (JUMP) {
+                for (int r = tid; r < a.n_rec; r += T) a.phi[(int64_t)b * a.n_rec + r] = -INFINITY;
+                if (tid == 0 && a.omega_out) a.omega_out[b] = omega;
+            }
             if (tid == 0) {
-                a.loglik[b] = -INFINITY;
+                if (!JUMP) a.loglik[b] = -INFINITY;
                 if (a.info) {
                     mjp_info inf{};
                     inf.omega = omega;
@@ -424,9 +456,12 @@ __global__ __launch_bounds__(T) void k_ll_main(LLArgs a, int cls) {
             rc[u] = 0.f;
             if (r < a.n_rec) {
                 const LLRecord R = a.rec[r];
-                rt[u] = R.t;
+                rt[u] = JUMP ? a.kobs[(int64_t)b * a.n_rec + r] : R.t;  // jump mode: the jump count
                 rm[u] = (R.x1 < S1 && R.x2 < lim2) ? R.x1 + S1 * R.x2 : -1;
-                if (rm[u] < 0) flags |= MJP_FLAG_OUT_OF_GRID;
+                if (rm[u] < 0) {
+                    flags |= MJP_FLAG_OUT_OF_GRID;
+                    if (JUMP) a.phi[(int64_t)b * a.n_rec + r] = -INFINITY;
+                }
             }
         }
         if (tid < a.n_t) wbuf[tid] = 0.0;
@@ -437,14 +472,14 @@ __global__ __launch_bounds__(T) void k_ll_main(LLArgs a, int cls) {
         double scale = 1.0;
         const int m_renorm = a.renorm_every;
         double lw = 0.0, logW = 0.0;
-        if (tid < a.n_t) {
+        if (!JUMP && tid < a.n_t) {
             const double W = win[tid].W;
             logW = W > 0.0 ? log(W) : 0.0;
             lw = W > 0.0 ? -W : 0.0;  // log w_0
         }
         for (int k = 0; k <= Kmax; ++k) {
             // weight of jump k for each time (FP64 log space, running form)
-            if (tid < a.n_t) {
+            if (!JUMP && tid < a.n_t) {
                 if (k > 0) lw += logW - log((double)k);
                 const double W = win[tid].W;
                 wbuf[(k & 1) * kLLMaxTimes + tid] = W > 0.0 ? exp(lw) : (k == 0 ? 1.0 : 0.0);
@@ -484,6 +519,16 @@ __global__ __launch_bounds__(T) void k_ll_main(LLArgs a, int cls) {
             } else {
                 __syncthreads();
             }
+            if constexpr (JUMP) {  // the observations whose jump count is k
+#pragma unroll
+                for (int u = 0; u < kLLRecPerThread; ++u) {
+                    if (rm[u] < 0 || rt[u] != k) continue;
+                    const float v = kHidden ? rho[rm[u]] + rho[rm[u] + hid] : rho[rm[u]];
+                    if (!(v > 0.f)) flags |= MJP_FLAG_UNDERFLOW_OBS;
+                    a.phi[(int64_t)b * a.n_rec + tid + u * T] = v > 0.f ? log((double)v) : -INFINITY;
+                }
+                continue;
+            }
             // accumulate observed states
 #pragma unroll
             for (int u = 0; u < kLLRecPerThread; ++u) {
@@ -504,24 +549,27 @@ __global__ __launch_bounds__(T) void k_ll_main(LLArgs a, int cls) {
             }
         }
         // log-likelihood: FP64 sum of count * log p over the records
-        double ll = 0.0;
-        bool neg_inf = false;
+        double tot = 0.0, ninf = 0.0;
+        if constexpr (!JUMP) {
+            double ll = 0.0;
+            bool neg_inf = false;
 #pragma unroll
-        for (int u = 0; u < kLLRecPerThread; ++u) {
-            const int r = tid + u * T;
-            if (r >= a.n_rec) continue;
-            if (rm[u] < 0) { neg_inf = true; continue; }
-            const float p = rs[u] - rc[u];
-            if (!(p > 0.f)) {
-                neg_inf = true;
-                flags |= MJP_FLAG_UNDERFLOW_OBS;
-                continue;
+            for (int u = 0; u < kLLRecPerThread; ++u) {
+                const int r = tid + u * T;
+                if (r >= a.n_rec) continue;
+                if (rm[u] < 0) { neg_inf = true; continue; }
+                const float p = rs[u] - rc[u];
+                if (!(p > 0.f)) {
+                    neg_inf = true;
+                    flags |= MJP_FLAG_UNDERFLOW_OBS;
+                    continue;
+                }
+                ll += (double)a.rec[r].count * log((double)p);
             }
-            ll += (double)a.rec[r].count * log((double)p);
+            tot = ll_block_sum<T>(ll, scratch);
+            ninf = ll_block_sum<T>(neg_inf ? 1.0 : 0.0, scratch);
         }
         if (flags) atomicOr(&flag_sh, flags);
-        const double tot = ll_block_sum<T>(ll, scratch);
-        const double ninf = ll_block_sum<T>(neg_inf ? 1.0 : 0.0, scratch);
         double mass = 0.0;
         {
             float part = 0.f;
@@ -529,7 +577,11 @@ __global__ __launch_bounds__(T) void k_ll_main(LLArgs a, int cls) {
             mass = ll_block_sum<T>((double)part, scratch);
         }
         if (tid == 0) {
-            a.loglik[b] = ninf > 0.0 ? -INFINITY : tot;
+            if (JUMP) {
+                if (a.omega_out) a.omega_out[b] = omega;
+            } else {
+                a.loglik[b] = ninf > 0.0 ? -INFINITY : tot;
+            }
             if (a.info) {
                 mjp_info inf{};
                 inf.omega = omega;
@@ -560,6 +612,17 @@ static const std::array<MainFn, kLLNumShapes> kLLMains[4] = {
     ll_row<MJP_MODEL_TWOSTATE>(std::make_index_sequence<kLLNumShapes>{}),
     ll_row<MJP_MODEL_AUTOREG>(std::make_index_sequence<kLLNumShapes>{})};
 
+// jump-mode kernels of (model, class): the default shape of each class
+template <int MODEL, size_t... S>
+constexpr std::array<MainFn, kLLClasses> jp_row(std::index_sequence<S...>) {
+    return {{&k_ll_main<MODEL, kLLShapes[kLLDefaultShape[S]].T, kLLShapes[kLLDefaultShape[S]].C, true>...}};
+}
+static const std::array<MainFn, kLLClasses> kJpMains[4] = {
+    jp_row<MJP_MODEL_BD>(std::make_index_sequence<kLLClasses>{}),
+    jp_row<MJP_MODEL_CASCADE2>(std::make_index_sequence<kLLClasses>{}),
+    jp_row<MJP_MODEL_TWOSTATE>(std::make_index_sequence<kLLClasses>{}),
+    jp_row<MJP_MODEL_AUTOREG>(std::make_index_sequence<kLLClasses>{})};
+
 inline size_t ll_lds(int shape) {
     return sizeof(float) * (size_t)ll_cap(kLLShapes[shape].T, kLLShapes[shape].C) + kLLExtraLds;
 }
@@ -578,6 +641,7 @@ struct LLContext {
     std::vector<double> T_host;
     bool attr_set = false;
     int occ[4][kLLNumShapes] = {};  // resident workgroups per CU (0 = not queried)
+    int occ_jp[4][kLLClasses] = {};  // the same for the jump-mode kernels
     int shape[4][kLLClasses];       // chosen shape per (model, class); -1 = default
     LLContext() {
         for (auto& m : shape)
@@ -614,6 +678,15 @@ static mjp_status ll_setup(LLContext& C, int model, int B, const mjp_obs* obs, c
                 MJP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kLLMains[m][sid], kLLShapes[sid].T,
                                                                      ll_lds(sid)));
                 C.occ[m][sid] = std::max(nb, 1);
+            }
+        for (int m = 0; m < 4; ++m)
+            for (int c = 0; c < kLLClasses; ++c) {
+                const int sid = kLLDefaultShape[c];
+                MJP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kJpMains[m][c]),
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)ll_lds(sid)));
+                int nb = 0;
+                MJP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kJpMains[m][c], kLLShapes[sid].T, ll_lds(sid)));
+                C.occ_jp[m][c] = std::max(nb, 1);
             }
         MJP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_ll_order), hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)(sizeof(unsigned long long) * kLLMaxSort)));
@@ -880,5 +953,45 @@ extern "C" mjp_status mjp_loglik_tune(int32_t model, int32_t B, const double* th
     MJP_HIP(hipGetLastError());
     MJP_HIP(hipStreamSynchronize(s));
     if (report) *report = rep;
+    return MJP_OK;
+}
+
+extern "C" mjp_status mjp_jump_probs(int32_t model, int32_t B, const double* theta_d, const int32_t* dims_d,
+                                     const mjp_obs* obs, const int32_t* k_d, const mjp_opts* opts, double* logphi_d,
+                                     double* omega_d, mjp_stream_t stream) {
+    clear_error();
+    std::vector<LLRecord> recs;
+    mjp_status st = ll_check(model, B, obs, opts, recs);
+    if (st) return st;
+    for (size_t i = 0; i < recs.size(); ++i)
+        MJP_CHECK(recs[i].count == 1, MJP_E_INVALID_ARG, "record %zu: each observation has its own jump count (count 1)",
+                  i);
+    if (B == 0 || recs.empty()) return MJP_OK;
+    MJP_CHECK(theta_d && dims_d && k_d && logphi_d, MJP_E_INVALID_ARG, "null device array");
+    int dev = 0;
+    MJP_HIP(hipGetDevice(&dev));
+    LLContext& C = ctx_for(dev);
+    std::lock_guard<std::mutex> lock(C.mu);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    LLArgs a;
+    if ((st = ll_upload(C, dev, recs, obs)) || (st = ll_setup(C, model, B, obs, opts, theta_d, dims_d, nullptr, nullptr, a)))
+        return st;
+    a.n_t = 1;  // one window per item: [0, max_i k_i]
+    a.kobs = k_d;
+    a.phi = logphi_d;
+    a.omega_out = omega_d;
+    hipLaunchKernelGGL(k_jp_prep, dim3((B + 255) / 256), dim3(256), 0, s, a);
+    int P = 1;
+    while (P < B) P <<= 1;
+    const size_t sort_lds = P <= kLLMaxSort ? sizeof(unsigned long long) * P : 0;
+    hipLaunchKernelGGL(k_ll_order, dim3(1), dim3(1024), sort_lds, s, a);
+    int ncu = 0;
+    MJP_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    for (int c = 0; c < kLLClasses; ++c) {
+        const int sid = kLLDefaultShape[c];
+        const int grid = std::max(1, std::min(B, std::max(ncu, 1) * C.occ_jp[model][c]));
+        hipLaunchKernelGGL(kJpMains[model][c], dim3(grid), dim3(kLLShapes[sid].T), ll_lds(sid), s, a, c);
+    }
+    MJP_HIP(hipGetLastError());
     return MJP_OK;
 }

@@ -132,6 +132,7 @@ _SIGS = [
     ("mjp_loglik_get_shapes", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _P]),
     ("mjp_loglik_tune", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P, _P, ctypes.c_int32, _P,
                                        _P]),
+    ("mjp_jump_probs", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P, _P]),
     ("mjp_surrogate_create", ctypes.c_int, [_P, ctypes.c_uint64, _P]),
     ("mjp_surrogate_destroy", None, [_P]),
     ("mjp_surrogate_train", ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P, _P, _P]),
@@ -383,6 +384,17 @@ def mjp_loglik(model: int, theta, dims, obs: mjp_obs, out, opts: mjp_opts | None
     B = int(out.shape[0])
     _check(lib().mjp_loglik(model, B, _ptr(theta), _ptr(dims), ctypes.byref(obs), ctypes.byref(opts), _ptr(out),
                             _ptr(info), _stream(stream)))
+
+
+def mjp_jump_probs(model: int, theta, dims, obs: mjp_obs, k, logphi, omega=None, opts: mjp_opts | None = None,
+                   stream=None) -> None:
+    """J-MJP state probabilities: logphi[b, i] = log p(s_i | k[b, i], theta[b]).
+    theta [B, P] float64, dims [B, 2] int32, k [B, I] int32, logphi [B, I]
+    float64, omega [B] float64 or None: CUDA tensors; obs records of count 1."""
+    opts = opts or mjp_opts_default()
+    B = int(logphi.shape[0])
+    _check(lib().mjp_jump_probs(model, B, _ptr(theta), _ptr(dims), ctypes.byref(obs), _ptr(k), ctypes.byref(opts),
+                                _ptr(logphi), _ptr(omega), _stream(stream)))
 
 
 def mjp_loglik_max_states() -> int:

@@ -217,6 +217,22 @@ def test_loglik_set_shapes_validation(ids):
     assert status_of(mjp.mjp_loglik_set_shapes, 7, [-1] * 4) == mjp.MJP_E_INVALID_ARG
 
 
+def test_jump_probs_validation():
+    """Host checks of mjp_jump_probs: the mjp_loglik checks, plus records of
+    count 1 only."""
+    L = mjp.lib()
+    o = mjp.mjp_opts_default()
+    d = np.zeros(8)
+    def st(recs, model=0, B=1):
+        obs = mjp.make_obs(np.asarray([1.0]), np.asarray(recs, np.int32).reshape(-1, 4), (0, 0))
+        return L.mjp_jump_probs(model, B, d.ctypes.data, d.ctypes.data, ctypes.byref(obs), d.ctypes.data,
+                                ctypes.byref(o), d.ctypes.data, None, None)
+    assert st([[0, 1, 0, 2]]) == mjp.MJP_E_INVALID_ARG          # count 2
+    assert st([[0, 1, 1, 1]]) == mjp.MJP_E_INVALID_ARG          # BD with x2 != 0
+    assert st([[0, 1, 0, 1]], model=7) == mjp.MJP_E_INVALID_ARG
+    assert st([[0, 1, 0, 1]], B=0) == mjp.MJP_OK
+
+
 def test_loglik_tune_validation():
     obs = mjp.make_obs(np.asarray([1.0]), np.asarray([[0, 1, 1, 1]], np.int32), (0, 0))
     o = mjp.mjp_opts_default()
