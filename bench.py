@@ -199,6 +199,45 @@ def bench_rk4(torch, mjp, rp, ci, va, n, reps: int = 3):
             "result": out[0].cpu().numpy()}
 
 
+def bench_jmjp(torch, mjp, chains: int = 512, steps: int = 300):
+    """J-MJP (Method #2: Gibbs over rates and jump counts) against plain MH
+    on the marginal likelihood (R-MJP) for the birth-death posterior of
+    (log beta, log gamma): data 10 times 0.5..5 x 30 snapshots from
+    (50, 1); both start from the same draws near the posterior and share the
+    random-walk covariance (posterior covariance x 2.38^2/2)."""
+    from paper_2312_05647_amd import jmjp, sampler, synth
+    beta, gamma = 50.0, 1.0
+    T = np.linspace(0.5, 5.0, 10)
+    data = synth.gillespie_bd(beta, gamma, T, 30, seed=synth.SEED_DATA)
+    recs = np.array([[j, n, 0, c] for j, n, c in synth.tally(data)], np.int32)
+    N = max(2 * int(data[:, 1].max()), 120)
+    g = synth.rng(12)
+    center = np.log([beta, gamma])
+    cov = np.diag([0.004, 0.004])
+    psi0 = torch.as_tensor(g.multivariate_normal(center, cov, size=chains), device="cuda")
+    mh_post = sampler.Posterior(mjp.MJP_MODEL_BD, T, recs, (N, 1), n_par=2)
+    gen = torch.Generator(device="cuda").manual_seed(13)
+    # posterior covariance from a short MH pilot, shared by both samplers
+    pilot, _ = sampler.run_mh(mh_post, psi0, cov * 2.38 ** 2 / 2, 200, gen)
+    Z = np.cov(pilot[100:].reshape(-1, 2).T) * 2.38 ** 2 / 2
+    psi1 = torch.as_tensor(pilot[-1], device="cuda")
+    s_mh, st_mh = sampler.run_mh(mh_post, psi1, Z, steps, gen)
+    post = jmjp.JumpPosterior(mjp.MJP_MODEL_BD, T, recs, (N, 1), n_par=2)
+    s_j, st_j = jmjp.run_jmjp(post, psi1, Z, steps, gen)
+    e_mh, e_j = sampler.ess(s_mh), sampler.ess(s_j)
+    res = {"workload": f"birth-death posterior, {post.I} snapshots, {chains} chains x {steps} steps per sampler",
+           "ess_per_s_mh_rmjp": float(e_mh.min() / st_mh.seconds), "ess_per_s_jmjp": float(e_j.min() / st_j.seconds),
+           "ess_per_step_mh_rmjp": float(e_mh.min() / steps), "ess_per_step_jmjp": float(e_j.min() / steps),
+           "seconds_mh": st_mh.seconds, "seconds_jmjp": st_j.seconds,
+           "jmjp_theta_accept": st_j.theta_accepted / (steps * chains), "jmjp_k_accept": st_j.k_accept_rate,
+           "mh_accept": st_mh.accepted / (steps * chains),
+           "posterior_mean_mh": s_mh.reshape(-1, 2).mean(0).tolist(),
+           "posterior_mean_jmjp": s_j.reshape(-1, 2).mean(0).tolist()}
+    log(f"[bench] J-MJP: ESS/s {res['ess_per_s_jmjp']:.1f} vs MH on R-MJP {res['ess_per_s_mh_rmjp']:.1f} "
+        f"(ESS/step {res['ess_per_step_jmjp']:.3f} vs {res['ess_per_step_mh_rmjp']:.3f})")
+    return res
+
+
 def bench_loglik(torch, mjp, reps: int = 3):
     """Batched log-likelihoods: 4096 draws log-uniform over a decade around
     (50, 1, 0.5, 0.5), 20 collection times 0.5..10 with 50 snapshots each,
@@ -329,7 +368,7 @@ def main():
     ap.add_argument("--variant", type=int, default=0, help="0 auto, 1 stepwise, 2 persistent")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the secondary measurements")
-    ap.add_argument("--part", choices=["all", "loglik", "da", "small", "krylov", "rk4"], default="all",
+    ap.add_argument("--part", choices=["all", "loglik", "da", "small", "krylov", "rk4", "jmjp"], default="all",
                     help="run only one secondary leg (for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the byte counters)")
@@ -365,6 +404,9 @@ def main():
                                              for k, v in kr.items()}}))
         return
 
+    if args.part == "jmjp":
+        print(json.dumps({"jmjp_method2": bench_jmjp(torch, mjp)}))
+        return
     if args.part == "rk4":
         rp, ci, va = mjp.mjp_model_csr(mjp.make_model(mjp.MJP_MODEL_CASCADE2, THETA, [S1, S2]))
         r = bench_rk4(torch, mjp, rp, ci, va, S1 * S2)
@@ -463,6 +505,7 @@ def main():
         result["small_configs"] = bench_small(torch, mjp)
         result["loglik_batch"] = bench_loglik(torch, mjp)
         result["da_mcmc"] = bench_da(torch, mjp)
+        result["jmjp_method2"] = bench_jmjp(torch, mjp)
 
     if not args.no_cpu:
         import oracle
