@@ -72,12 +72,22 @@ enum { MJP_VARIANT_AUTO = 0,       /* the plan picks the launch strategy */
        MJP_VARIANT_STEPWISE = 1,   /* one kernel per jump, launched in a loop */
        MJP_VARIANT_PERSISTENT = 2, /* all K jumps in one cooperative launch; the
                                       iterate moves between XCDs through
-                                      device-scope loads and stores */
-       MJP_VARIANT_PERSISTENT_FENCED = 3 /* the same launch, synchronised with
-                                      agent-scope release/acquire fences (L2
-                                      write-back and invalidate per workgroup
-                                      and jump): slower, bit-identical; kept
-                                      as the reference protocol */ };
+                                      device-scope loads and stores; where the
+                                      operator's reach is short (at most 2048
+                                      rows of halo per 4096-row block, width
+                                      <= 5) and renorm_every is even, each
+                                      workgroup computes two jumps per
+                                      synchronisation, recomputing its
+                                      neighbours' boundary rows
+                                      (bit-identical) */
+       MJP_VARIANT_PERSISTENT_FENCED = 3, /* one jump per synchronisation,
+                                      synchronised with agent-scope
+                                      release/acquire fences (L2 write-back and
+                                      invalidate per workgroup and jump):
+                                      slower, bit-identical; kept as the
+                                      reference protocol */
+       MJP_VARIANT_PERSISTENT_ONEJUMP = 4 /* one jump per synchronisation,
+                                      device-scope protocol: bit-identical */ };
 
 typedef struct {
     double  omega_factor;  /* Omega = omega_factor * max|a_nn|; must be > 1 (Eq. B_def: 1.1) */
@@ -117,8 +127,13 @@ typedef struct {
     int32_t K;              /* number of products rho <- rho B */
     int32_t L;              /* first accumulated jump index */
     int32_t flags;          /* MJP_FLAG_* */
-    int32_t reserved;
+    int32_t path;           /* mjp_expv: the sweep that ran (MJP_PATH_*); 0 elsewhere */
 } mjp_info;
+
+enum { MJP_PATH_STEPWISE = 1,            /* one launch per jump */
+       MJP_PATH_PERSISTENT = 2,          /* one launch, one jump per synchronisation */
+       MJP_PATH_PERSISTENT_FENCED = 3,   /* the same, fenced protocol */
+       MJP_PATH_PERSISTENT_TWOJUMP = 4 };/* one launch, two jumps per synchronisation */
 
 /* ------------------------------------------------------------ operators */
 

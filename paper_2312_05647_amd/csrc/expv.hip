@@ -339,8 +339,13 @@ static mjp_status run_sweep(mjp_plan* p, const float* rho0, const std::vector<Sw
     }
 
     PersistCfg cfg;
-    const bool coh = p->opts.variant != MJP_VARIANT_PERSISTENT_FENCED;
-    if (p->opts.variant != MJP_VARIANT_STEPWISE && persistent_fits(p, max_open, coh, cfg)) {
+    const int var = p->opts.variant;
+    const bool coh = var != MJP_VARIANT_PERSISTENT_FENCED;
+    // two jumps per synchronisation where the operator's reach allows it,
+    // else one
+    bool fits = (var == MJP_VARIANT_AUTO || var == MJP_VARIANT_PERSISTENT) && persistent2_fits(p, max_open, cfg);
+    if (!fits && var != MJP_VARIANT_STEPWISE) fits = persistent_fits(p, max_open, coh, cfg);
+    if (fits) {
         // colour the windows (sorted by start) onto the register slots
         std::vector<int> slot(nt, -1);
         std::vector<int32_t> busy_until;  // last jump of each slot's current window
@@ -352,11 +357,14 @@ static mjp_status run_sweep(mjp_plan* p, const float* rho0, const std::vector<Sw
             busy_until[(size_t)q] = at.tp[j].K;
             slot[(size_t)j] = q;
         }
+        p->last_path = cfg.jumps == 2 ? MJP_PATH_PERSISTENT_TWOJUMP
+                                      : (coh ? MJP_PATH_PERSISTENT : MJP_PATH_PERSISTENT_FENCED);
         if ((s = launch_persistent(p, cfg, rho0, at, slot, out, st))) return s;
     } else {
-        if (p->opts.variant == MJP_VARIANT_PERSISTENT || p->opts.variant == MJP_VARIANT_PERSISTENT_FENCED)
+        if (var == MJP_VARIANT_PERSISTENT || var == MJP_VARIANT_PERSISTENT_FENCED || var == MJP_VARIANT_PERSISTENT_ONEJUMP)
             return fail(MJP_E_UNSUPPORTED, "the persistent kernel cannot hold this operator (width %d, %d open windows)",
                         p->max_width, max_open);
+        p->last_path = MJP_PATH_STEPWISE;
         // compensation rows are handed out to times while their window is open
         std::vector<int> slot_of(nt, -1);
         std::vector<int> free_slots;
@@ -515,6 +523,7 @@ extern "C" mjp_status mjp_expv(mjp_plan* p, const float* rho0_d, int32_t n_t, co
                 inf.K = (int32_t)chunk[j].win.K;
                 inf.L = (int32_t)chunk[j].win.L;
                 inf.flags = (int32_t)(flags & ~kFlagBarrierTimeout);
+                inf.path = p->last_path;
             }
             if (flags & kFlagBarrierTimeout)
                 return fail(MJP_E_DEVICE, "a grid barrier of the persistent kernel timed out");

@@ -101,5 +101,8 @@ struct mjp_plan {
     mjp::DevBuf wait;       // persistent kernel: per-workgroup neighbour interval
     mjp::DevBuf sflag;      // persistent kernel: per-slice local / exported bits
     int wait_key[3] = {0, 0, 0};  // (G, R, valid) the two tables were built for
+    mjp::DevBuf p2tab;      // two-jump persistent kernel: per-workgroup regions and neighbour interval
+    int p2_key[2] = {0, 0};       // (G, state) the table was built for: 1 fits, 2 does not
+    int last_path = 0;            // MJP_PATH_* of the last sweep
     std::vector<char> host_stage;
 };

@@ -65,6 +65,7 @@ struct PersistArgs {
     unsigned* __restrict__ wflag; // [G * 32] per-workgroup epoch flags (one 128-byte line each), zero at launch
     const int32_t* __restrict__ wait;  // [G][2] neighbour interval [lo, hi] or null (global barriers only)
     const uint8_t* __restrict__ sflag; // [n_slices] kSliceLocal or 0
+    const int32_t* __restrict__ p2;    // two-jump kernel: [G][kP2Tab] regions and neighbour interval
     unsigned* __restrict__ flags;
     double* __restrict__ mass_out;  // [2]: initial mass, last measured mass
     uint64_t timeout_ticks;         // per-barrier wait limit in wall-clock ticks
@@ -516,6 +517,323 @@ __global__ __launch_bounds__(kPThreads) void k_persistent(PersistArgs a) {
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// Two jumps per synchronisation (communication-avoiding form of the same
+// sweep).  Workgroup g owns rows [r0, r1) (kP2Rows of them, R = 8 per
+// thread as above).  E1 = [e1lo, e1hi) is the hull of the columns its rows
+// read, E2 = [e2lo, e2hi) the hull of the columns E1's rows read.  A round
+// advances the iterate from x_k to x_{k+2}:
+//   A  read x_k on E2 outside the own rows from the global iterate (one
+//      coalesced pass; the own rows are already in LDS),
+//   B  x_{k+1} on all of E1 from that LDS copy: own rows with the operator
+//      in registers, the halo rows E1 \ own with their entries kept in LDS
+//      (copied once from the operator in the same order as the owner's
+//      registers, so the owner and the neighbours form bit-identical values),
+//   C  x_{k+2} on the own rows from x_{k+1} in LDS; stored to LDS and to the
+//      global iterate, then one synchronisation (neighbour flags, or a grid
+//      barrier at a renormalisation point, which must fall on an even jump).
+// Every jump's values equal the one-jump kernel's bit for bit: halo rows are
+// recomputed from the same inputs with the same operations.  Global
+// accesses of the iterate use the device-scope protocol.
+constexpr int kP2R = 8;                          // own rows per thread
+constexpr int kP2Rows = kPWaves * kP2R * 64;     // own rows of a workgroup
+constexpr int kP2Halo = 2048;                    // rows of E1 outside the own rows, at most
+constexpr int kP2HR = kP2Halo / kPThreads;       // halo rows per thread
+constexpr int kP2X2 = kP2Rows + 2 * kP2Halo;     // rows of E2, at most
+constexpr int kP2X1 = kP2Rows + kP2Halo;         // rows of E1, at most
+constexpr int kP2Tab = 8;                        // {r0, r1, e1lo, e1hi, e2lo, e2hi, wlo, whi}
+
+template <int W>
+constexpr size_t p2_lds_bytes() {
+    return sizeof(float) * (kP2X2 + kP2X1) + (sizeof(int16_t) + sizeof(float)) * (size_t)kP2Halo * W;
+}
+
+// Entries of pull row m (column, value) in the order the one-jump kernel
+// keeps them in registers; absent entries read row m with weight 0.
+template <int W, bool CSR>
+__device__ __forceinline__ void row_entries(const PersistArgs& a, int64_t m, int32_t (&cc)[W], float (&vv)[W]) {
+    if constexpr (CSR) {
+        const int s = (int)(m >> 6), l = (int)(m & 63);
+        int beg = 0, w = 0;
+        if (s < a.n_slices) {
+            beg = a.slice_off[s];
+            w = (a.slice_off[s + 1] - beg) >> 6;
+        }
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+            if (j < w) {
+                cc[j] = a.col[beg + j * 64 + l];
+                vv[j] = a.val[beg + j * 64 + l];
+            } else {
+                cc[j] = (int32_t)m;
+                vv[j] = 0.f;
+            }
+        }
+    } else {
+        const StencilCoef cf = a.cf;
+        int32_t i1, i2, S1 = cf.S1, S2 = cf.S2;
+        if (cf.model == MJP_MODEL_BD) { i1 = (int32_t)m; i2 = 0; S2 = 1; }
+        else { i2 = (int32_t)(m / S1); i1 = (int32_t)(m - (int64_t)i2 * S1); }
+        const float f1 = (float)i1, f2 = (float)i2;
+        const float b1 = cf.c[0], d1 = cf.c[1];
+        const float b2 = cf.model == MJP_MODEL_BD ? 0.f : cf.c[2];
+        const float d2 = cf.model == MJP_MODEL_BD ? 0.f : cf.c[3];
+        const float o_b1 = (i1 + 1 < S1 || cf.leaky) ? b1 : 0.f;
+        const float o_d1 = d1 * f1;
+        const float o_b2 = (i2 + 1 < S2 || cf.leaky) ? b2 * f1 : 0.f;
+        const float o_d2 = d2 * f2;
+        const float diag = (float)(1.0 - (((double)o_b1 + (double)o_d1) + ((double)o_b2 + (double)o_d2)));
+        int32_t c5[5] = {(int32_t)m, (int32_t)m, (int32_t)m, (int32_t)m, (int32_t)m};
+        float v5[5] = {diag, 0.f, 0.f, 0.f, 0.f};
+        if (i1 > 0) { c5[1] = (int32_t)m - 1; v5[1] = b1; }
+        if (i1 + 1 < S1) { c5[2] = (int32_t)m + 1; v5[2] = d1 * (f1 + 1.f); }
+        if (i2 > 0) { c5[3] = (int32_t)m - S1; v5[3] = b2 * f1; }
+        if (i2 + 1 < S2) { c5[4] = (int32_t)m + S1; v5[4] = d2 * (f2 + 1.f); }
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+            cc[j] = j < 5 ? c5[j] : (int32_t)m;
+            vv[j] = j < 5 ? v5[j] : 0.f;
+        }
+    }
+}
+
+template <int W, bool CSR>
+__global__ __launch_bounds__(kPThreads) void k_persistent2(PersistArgs a) {
+    constexpr int R = kP2R;
+    extern __shared__ __align__(16) char p2lds[];
+    float* X2 = reinterpret_cast<float*>(p2lds);                  // x_k on E2
+    float* X1 = X2 + kP2X2;                                       // x_{k+1} on E1
+    int16_t* hcol = reinterpret_cast<int16_t*>(X1 + kP2X1);       // halo entries: column - e2lo
+    float* hval = reinterpret_cast<float*>(hcol + kP2Halo * W);   // halo entries: value
+    __shared__ double red[kPWaves + 1];
+    const int G = a.G;
+    const int g = logical_block(G);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t n = a.n;
+    const int32_t* tb = a.p2 + kP2Tab * g;
+    const int r0 = tb[0], r1 = tb[1], e1lo = tb[2], e1hi = tb[3], e2lo = tb[4], e2hi = tb[5];
+    const int wlo = tb[6], whi = tb[7];
+    const int nlo = r0 - e1lo, nh = nlo + (e1hi - r1);        // halo rows of E1: below, in total
+    const int nl2 = r0 - e2lo, nt2 = nl2 + (e2hi - r1);       // rows of E2 outside the own rows
+    const int32_t row0 = ((g * kPWaves + wave) * R) * 64 + lane;
+    auto row = [&](int i) { return row0 + 64 * i; };
+    auto live = [&](int i) { return (int64_t)(row0 + 64 * i) < n; };
+
+    // own rows' operator in registers (byte offsets of absolute columns)
+    uint32_t coff[R][W];
+    float cval[R][W];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        int32_t cc[W];
+        float vv[W];
+        row_entries<W, CSR>(a, live(i) ? (int64_t)row(i) : 0, cc, vv);
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+            coff[i][j] = live(i) ? 4u * (uint32_t)cc[j] : 4u * (uint32_t)e1lo;
+            cval[i][j] = live(i) ? vv[j] : 0.f;
+        }
+    }
+    // halo rows' entries in LDS
+    for (int h = tid; h < nh; h += kPThreads) {
+        const int m = h < nlo ? e1lo + h : r1 + (h - nlo);
+        int32_t cc[W];
+        float vv[W];
+        row_entries<W, CSR>(a, m, cc, vv);
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+            hcol[h * W + j] = (int16_t)(cc[j] - e2lo);
+            hval[h * W + j] = vv[j];
+        }
+    }
+
+    // ---- k = 0
+    float sacc[kPSlots][R], cacc[kPSlots][R];
+#pragma unroll
+    for (int q = 0; q < kPSlots; ++q)
+#pragma unroll
+        for (int i = 0; i < R; ++i) { sacc[q][i] = 0.f; cacc[q][i] = 0.f; }
+    float yv[R];
+    double mloc = 0.0;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        yv[i] = live(i) ? a.rho0[row(i)] : 0.f;
+        if (live(i)) {
+            if (!(yv[i] >= 0.f)) atomicOr(a.flags, (yv[i] != yv[i]) ? (unsigned)MJP_FLAG_NAN : (unsigned)MJP_FLAG_NEG);
+            else if (isinf(yv[i])) atomicOr(a.flags, (unsigned)MJP_FLAG_NAN);
+            X2[row(i) - e2lo] = yv[i];
+        }
+        mloc += (double)yv[i];
+    }
+    int jq[kPSlots];
+    float wvec[kPSlots];
+    int wbase = 0;
+    auto fetch = [&](int k) {
+#pragma unroll
+        for (int qq = 0; qq < kPSlots; ++qq) jq[qq] = -1;
+        for (int j = 0; j < a.at.n; ++j) {
+            const TimeParam& tp = a.at.tp[j];
+            if (k < tp.L || k > tp.K) continue;
+#pragma unroll
+            for (int qq = 0; qq < kPSlots; ++qq)
+                if (qq == a.slot[j]) jq[qq] = j;
+        }
+        if ((k & 63) == 0) {
+            wbase = k;
+            const int kk = k + lane;
+#pragma unroll
+            for (int qq = 0; qq < kPSlots; ++qq) wvec[qq] = 0.f;
+            for (int j = 0; j < a.at.n; ++j) {
+                const TimeParam& tp = a.at.tp[j];
+                if (kk < tp.L || kk > tp.K) continue;
+                const float w = (kk == tp.K) ? (float)tp.lastw : (float)a.wtab[tp.woff + (kk - tp.L)];
+#pragma unroll
+                for (int qq = 0; qq < kPSlots; ++qq)
+                    if (qq == a.slot[j]) wvec[qq] = w;
+            }
+        }
+    };
+    auto accumulate = [&](int k) {
+#pragma unroll
+        for (int qq = 0; qq < kPSlots; ++qq) {
+            const int j = jq[qq];
+            if (j < 0) continue;
+            const TimeParam& tp = a.at.tp[j];
+            const float w = __builtin_bit_cast(
+                float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, wvec[qq]), k - wbase));
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                if (k == tp.L) {
+                    sacc[qq][i] = w * yv[i];
+                    cacc[qq][i] = 0.f;
+                } else {
+                    const float yk = fmaf(w, yv[i], -cacc[qq][i]);
+                    const float t = sacc[qq][i] + yk;
+                    cacc[qq][i] = (t - sacc[qq][i]) - yk;
+                    sacc[qq][i] = t;
+                }
+                if (k == tp.K && live(i)) a.out[(int64_t)tp.out * n + row(i)] = sacc[qq][i] - cacc[qq][i];
+            }
+        }
+    };
+    fetch(0);
+    accumulate(0);
+    {
+        const double s = block_sum_f64(mloc, red);
+        if (tid == 0) __hip_atomic_store(a.pmass + g, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    unsigned epoch = 1;
+    if (!grid_barrier<true>(a.bar, epoch, g, G, a.flags, a.timeout_ticks)) return;
+    const double mass0 = sum_partials(a.pmass, G, red);
+    double scale = 1.0;
+    double last_mass = mass0;
+    const int m = a.renorm_every;  // even or 0
+    const __amdgpu_buffer_rsrc_t r_rho0 = iter_rsrc(a.rho0, n), r_buf0 = iter_rsrc(a.buf0, n),
+                                 r_buf1 = iter_rsrc(a.buf1, n);
+    const char* __restrict__ x2b = reinterpret_cast<const char*>(X2) - 4 * (int64_t)e2lo;
+    const char* __restrict__ x1b = reinterpret_cast<const char*>(X1) - 4 * (int64_t)e1lo;
+    for (int k = 0; k < a.Kmax; k += 2) {
+        const int q = k >> 1;
+        const __amdgpu_buffer_rsrc_t src = (q == 0) ? r_rho0 : ((q & 1) ? r_buf0 : r_buf1);
+        const __amdgpu_buffer_rsrc_t dst = ((q + 1) & 1) ? r_buf0 : r_buf1;
+        // A: x_k on E2 outside the own rows (loads past the vector's end read 0)
+        {
+            constexpr int kU = kP2X2 / kPThreads - kP2R;  // passes covering E2 \ own
+            float t[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int i = tid + u * kPThreads;
+                const int rr = i < nl2 ? e2lo + i : r1 + (i - nl2);
+                t[u] = ld_iter<true>(src, 4u * (uint32_t)rr);
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int i = tid + u * kPThreads;
+                if (i < nt2) X2[i < nl2 ? i : (r1 - e2lo) + (i - nl2)] = t[u];
+            }
+        }
+        __syncthreads();
+        // B: x_{k+1} on E1
+        fetch(k + 1);
+        {
+            const float fs = (float)scale;
+            float xv[R][W];
+#pragma unroll
+            for (int i = 0; i < R; ++i)
+#pragma unroll
+                for (int j = 0; j < W; ++j) xv[i][j] = *reinterpret_cast<const float*>(x2b + coff[i][j]);
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                float acc = 0.f;
+#pragma unroll
+                for (int j = 0; j < W; ++j) acc = fmaf(cval[i][j], xv[i][j], acc);
+                yv[i] = fs * acc;
+            }
+#pragma unroll
+            for (int u = 0; u < kP2HR; ++u) {
+                const int h = tid + u * kPThreads;
+                if (h < nh) {
+                    float acc = 0.f;
+#pragma unroll
+                    for (int j = 0; j < W; ++j) acc = fmaf(hval[h * W + j], X2[hcol[h * W + j]], acc);
+                    X1[h < nlo ? h : (r1 - e1lo) + (h - nlo)] = fs * acc;
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < R; ++i)
+                if (live(i)) X1[row(i) - e1lo] = yv[i];
+        }
+        accumulate(k + 1);
+        if (k + 1 == a.Kmax) break;
+        __syncthreads();
+        // C: x_{k+2} on the own rows
+        fetch(k + 2);
+        double part = 0.0;
+        {
+            float xv[R][W];
+#pragma unroll
+            for (int i = 0; i < R; ++i)
+#pragma unroll
+                for (int j = 0; j < W; ++j) xv[i][j] = *reinterpret_cast<const float*>(x1b + coff[i][j]);
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                float acc = 0.f;
+#pragma unroll
+                for (int j = 0; j < W; ++j) acc = fmaf(cval[i][j], xv[i][j], acc);
+                yv[i] = 1.0f * acc;
+                part += (double)yv[i];
+            }
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                if (live(i)) X2[row(i) - e2lo] = yv[i];
+                st_iter<true>(dst, 4u * (uint32_t)row(i), yv[i]);  // rows >= n fall outside the range
+            }
+        }
+        accumulate(k + 2);
+        const bool renorm = m > 0 && ((k + 2) % m == 0) && k + 2 < a.Kmax;
+        double* pm = a.pmass + (size_t)G * (1 + (((k + 2) / (m > 0 ? m : 1)) & 1));
+        if (renorm) {
+            const double s = block_sum_f64(part, red);
+            if (tid == 0) __hip_atomic_store(pm + g, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (k + 2 == a.Kmax) break;
+        if (renorm) {
+            ++epoch;
+            if (!grid_barrier<true>(a.bar, epoch, g, G, a.flags, a.timeout_ticks)) return;
+            if (tid == 0) __hip_atomic_store(&a.wflag[g * 32], (unsigned)(k + 2), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            last_mass = sum_partials(pm, G, red);
+            scale = (last_mass > 0.0 && mass0 > 0.0) ? mass0 / last_mass : 1.0;
+        } else {
+            if (!neighbour_sync<true>(a.wflag, wlo, whi, (unsigned)(k + 2), g, a.flags, a.timeout_ticks)) return;
+            scale = 1.0;
+        }
+    }
+    if (g == 0 && tid == 0) {
+        a.mass_out[0] = mass0;
+        a.mass_out[1] = last_mass;
+    }
+}
+
 using PersistFn = void (*)(PersistArgs);
 
 template <bool CSR, bool COH>
@@ -592,6 +910,140 @@ bool persistent_fits(const mjp_plan* p, int max_open, bool coh, PersistCfg& cfg)
         return true;
     }
     return false;
+}
+
+// ---- the two-jump kernel: table and fit
+template <bool CSR>
+static PersistFn pick2(int W) {
+    if constexpr (CSR) {
+        if (W == 3) return k_persistent2<3, true>;
+        if (W == 5) return k_persistent2<5, true>;
+    } else {
+        if (W == 5) return k_persistent2<5, false>;
+    }
+    return nullptr;
+}
+
+static size_t p2_lds_for(int W) { return W == 3 ? p2_lds_bytes<3>() : p2_lds_bytes<5>(); }
+
+// Per workgroup {r0, r1, e1lo, e1hi, e2lo, e2hi, wlo, whi} from the slices'
+// column hulls (conservative); false if some region exceeds the LDS
+// buffers or a neighbour interval spans more than 64 workgroups.
+static bool build_p2_table(const mjp_plan* p, int G, std::vector<int32_t>& tab) {
+    const int64_t n = p->n, n_slices = (n + 63) / 64;
+    auto hull = [&](int64_t sl, int64_t& lo, int64_t& hi) {
+        if (p->kind == PLAN_CSR) {
+            lo = p->slice_cmin[(size_t)sl];
+            hi = p->slice_cmax[(size_t)sl];
+        } else {
+            const int64_t reach = p->coef.model == MJP_MODEL_BD ? 1 : p->coef.S1;
+            lo = std::max<int64_t>(0, sl * 64 - reach);
+            hi = std::min<int64_t>(n - 1, sl * 64 + 63 + reach);
+        }
+    };
+    // hull of the columns read by rows [a, b)
+    auto cols = [&](int64_t a, int64_t b, int64_t& lo, int64_t& hi) {
+        lo = a;
+        hi = b - 1;
+        for (int64_t sl = a / 64; sl <= (b - 1) / 64; ++sl) {
+            int64_t l, h;
+            hull(sl, l, h);
+            lo = std::min(lo, l);
+            hi = std::max(hi, h);
+        }
+    };
+    tab.assign((size_t)kP2Tab * G, 0);
+    std::vector<int32_t> lo(G), hi(G);
+    for (int g = 0; g < G; ++g) {
+        int32_t* t = tab.data() + (size_t)kP2Tab * g;
+        const int64_t r0 = std::min<int64_t>(n, (int64_t)g * kP2Rows), r1 = std::min<int64_t>(n, r0 + kP2Rows);
+        t[0] = (int32_t)r0;
+        t[1] = (int32_t)r1;
+        lo[g] = hi[g] = g;
+        if (r0 >= r1) {
+            for (int c = 2; c < 6; ++c) t[c] = (int32_t)r0;
+            continue;
+        }
+        int64_t e1lo, e1hi, e2lo, e2hi;
+        cols(r0, r1, e1lo, e1hi);
+        cols(e1lo, e1hi + 1, e2lo, e2hi);
+        e1hi += 1;
+        e2hi += 1;
+        if ((r0 - e1lo) + (e1hi - r1) > kP2Halo) return false;
+        if ((r0 - e2lo) + (e2hi - r1) > 2 * kP2Halo) return false;
+        t[2] = (int32_t)e1lo;
+        t[3] = (int32_t)e1hi;
+        t[4] = (int32_t)e2lo;
+        t[5] = (int32_t)e2hi;
+        lo[g] = (int32_t)(e2lo / kP2Rows);
+        hi[g] = (int32_t)((e2hi - 1) / kP2Rows);
+    }
+    // wait for the owners of my E2 and for the workgroups whose E2 holds my rows
+    std::vector<int32_t> wlo(lo), whi(hi);
+    for (int g = 0; g < G; ++g)
+        for (int h = lo[g]; h <= hi[g]; ++h) {
+            wlo[h] = std::min(wlo[h], g);
+            whi[h] = std::max(whi[h], g);
+        }
+    for (int g = 0; g < G; ++g) {
+        if (whi[g] - wlo[g] + 1 > 64) return false;
+        tab[(size_t)kP2Tab * g + 6] = wlo[g];
+        tab[(size_t)kP2Tab * g + 7] = whi[g];
+    }
+    return true;
+}
+
+bool persistent2_fits(mjp_plan* p, int max_open, PersistCfg& cfg) {
+    if (max_open > kPSlots) return false;
+    if (p->n >= ((int64_t)1 << 30)) return false;
+    if (p->opts.renorm_every % 2 != 0) return false;  // renormalisation points must end a round
+    int W = 5;
+    if (p->kind == PLAN_CSR) {
+        if (p->max_width <= 3) W = 3;
+        else if (p->max_width <= 5) W = 5;
+        else return false;
+    }
+    int dev = 0, ncu = 0, coop = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return false;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return false;
+    const int64_t need = (p->n + kP2Rows - 1) / kP2Rows;
+    const int64_t G = (need + 7) / 8 * 8;
+    if (G < ncu / 2) return false;  // too few workgroups to use the chip: the one-jump kernel spreads wider
+    PersistFn f = p->kind == PLAN_CSR ? pick2<true>(W) : pick2<false>(W);
+    if (!f) return false;
+    const size_t lds = p2_lds_for(W);
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(f), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+        hipSuccess)
+        return false;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(f), kPThreads, lds) !=
+            hipSuccess || per_cu < 1 || G > (int64_t)ncu * per_cu)
+        return false;
+    if (p->p2_key[0] != (int)G || p->p2_key[1] == 0) {
+        std::vector<int32_t> tab;
+        const bool ok = build_p2_table(p, (int)G, tab);
+        p->p2_key[0] = (int)G;
+        p->p2_key[1] = ok ? 1 : 2;
+        if (ok) {
+            if (p->p2tab.reserve(sizeof(int32_t) * tab.size()) != MJP_OK) {
+                p->p2_key[1] = 0;
+                return false;
+            }
+            if (hipMemcpy(p->p2tab.ptr, tab.data(), sizeof(int32_t) * tab.size(), hipMemcpyHostToDevice) != hipSuccess) {
+                p->p2_key[1] = 0;
+                return false;
+            }
+        }
+    }
+    if (p->p2_key[1] != 1) return false;
+    cfg.R = kP2R;
+    cfg.W = W;
+    cfg.G = (int)G;
+    cfg.coh = true;
+    cfg.jumps = 2;
+    cfg.fn = reinterpret_cast<const void*>(f);
+    return true;
 }
 
 // Tables of the persistent sweep, built once per (plan, G, R) and kept on
@@ -692,7 +1144,7 @@ mjp_status launch_persistent(mjp_plan* p, const PersistCfg& cfg, const float* rh
     double* pmass = reinterpret_cast<double*>(wflag + 32 * (size_t)cfg.G);
     const int32_t* wait = nullptr;
     const uint8_t* sflag = nullptr;
-    if ((s = build_sweep_tables(p, cfg, wait, sflag))) return s;
+    if (cfg.jumps == 1 && (s = build_sweep_tables(p, cfg, wait, sflag))) return s;
     double* mass_out = p->scal.as<double>() + S_MASS0;  // [S_MASS0], [S_MASSK]
     PersistArgs a{};
     a.slice_off = p->slice_off.as<int32_t>();
@@ -709,6 +1161,7 @@ mjp_status launch_persistent(mjp_plan* p, const PersistCfg& cfg, const float* rh
     a.wflag = wflag;
     a.wait = wait;
     a.sflag = sflag;
+    a.p2 = cfg.jumps == 2 ? p->p2tab.as<int32_t>() : nullptr;
     a.flags = reinterpret_cast<unsigned*>(p->scal.as<double>() + S_FLAGS);
     a.mass_out = mass_out;
     a.n = n;
@@ -728,7 +1181,8 @@ mjp_status launch_persistent(mjp_plan* p, const PersistCfg& cfg, const float* rh
     const int nzero = kBarWords + 32 * cfg.G;
     hipLaunchKernelGGL(k_zero_u32, dim3((nzero + 255) / 256), dim3(256), 0, st, bar, nzero);
     void* args[] = {&a};
-    MJP_HIP(hipLaunchCooperativeKernel(cfg.fn, dim3(cfg.G), dim3(kPThreads), args, 0, st));
+    const size_t lds = cfg.jumps == 2 ? p2_lds_for(cfg.W) : 0;
+    MJP_HIP(hipLaunchCooperativeKernel(cfg.fn, dim3(cfg.G), dim3(kPThreads), args, lds, st));
     return MJP_OK;
 }
 

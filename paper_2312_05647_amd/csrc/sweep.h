@@ -32,10 +32,13 @@ constexpr unsigned kFlagBarrierTimeout = 0x80000000u;
 struct PersistCfg {
     int R = 0, W = 0, G = 0;
     bool coh = true;  // device-scope iterate accesses (true) or the fenced protocol
+    int jumps = 1;    // jumps per synchronisation (2: the two-jump kernel)
     const void* fn = nullptr;
 };
 
 bool persistent_fits(const mjp_plan* p, int max_open, bool coh, PersistCfg& cfg);
+// the two-jump kernel (device-scope protocol only); builds its tables
+bool persistent2_fits(mjp_plan* p, int max_open, PersistCfg& cfg);
 mjp_status launch_persistent(mjp_plan* p, const PersistCfg& cfg, const float* rho0, const AllTimes& at,
                              const std::vector<int>& slot, float* out, hipStream_t st);
 

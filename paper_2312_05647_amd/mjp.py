@@ -23,6 +23,8 @@ STATUS_NAMES = ["MJP_OK", "MJP_E_INVALID_ARG", "MJP_E_NOT_GENERATOR", "MJP_E_K_L
 MJP_K_TOL, MJP_K_PAPER = 0, 1
 MJP_CONSERVATIVE, MJP_LEAKY = 0, 1
 MJP_VARIANT_AUTO, MJP_VARIANT_STEPWISE, MJP_VARIANT_PERSISTENT, MJP_VARIANT_PERSISTENT_FENCED = 0, 1, 2, 3
+MJP_VARIANT_PERSISTENT_ONEJUMP = 4
+MJP_PATH_STEPWISE, MJP_PATH_PERSISTENT, MJP_PATH_PERSISTENT_FENCED, MJP_PATH_PERSISTENT_TWOJUMP = 1, 2, 3, 4
 MJP_MODEL_BD, MJP_MODEL_CASCADE2, MJP_MODEL_TWOSTATE, MJP_MODEL_AUTOREG = 0, 1, 2, 3
 MJP_FLAG_NAN, MJP_FLAG_NEG, MJP_FLAG_UNDERFLOW_OBS, MJP_FLAG_OUT_OF_GRID, MJP_FLAG_K_LIMIT = 1, 2, 4, 8, 16
 MJP_LL_CLASSES, MJP_LL_MAX_SHAPES = 4, 16
@@ -44,10 +46,10 @@ class mjp_info(ctypes.Structure):
     _fields_ = [("omega", ctypes.c_double), ("W", ctypes.c_double), ("eps_left", ctypes.c_double),
                 ("eps_right", ctypes.c_double), ("residual", ctypes.c_double), ("mass_in", ctypes.c_double),
                 ("mass_out", ctypes.c_double), ("K", ctypes.c_int32), ("L", ctypes.c_int32),
-                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("path", ctypes.c_int32)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class mjp_csr(ctypes.Structure):
