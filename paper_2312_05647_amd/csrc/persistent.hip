@@ -528,8 +528,10 @@ __global__ __launch_bounds__(kPThreads) void k_persistent(PersistArgs a) {
 //      coalesced pass; the own rows are already in LDS),
 //   B  x_{k+1} on all of E1 from that LDS copy: own rows with the operator
 //      in registers, the halo rows E1 \ own with their entries kept in LDS
-//      (copied once from the operator in the same order as the owner's
-//      registers, so the owner and the neighbours form bit-identical values),
+//      as (byte offset into the E2 copy, value) pairs, copied once from the
+//      operator in the same order as the owner's registers, so the owner and
+//      the neighbours form bit-identical values; a thread reads all entries
+//      of its halo rows, then all their gathers, then does the arithmetic,
 //   C  x_{k+2} on the own rows from x_{k+1} in LDS; stored to LDS and to the
 //      global iterate, then one synchronisation (neighbour flags, or a grid
 //      barrier at a renormalisation point, which must fall on an even jump).
@@ -543,10 +545,11 @@ constexpr int kP2HR = kP2Halo / kPThreads;       // halo rows per thread
 constexpr int kP2X2 = kP2Rows + 2 * kP2Halo;     // rows of E2, at most
 constexpr int kP2X1 = kP2Rows + kP2Halo;         // rows of E1, at most
 constexpr int kP2Tab = 8;                        // {r0, r1, e1lo, e1hi, e2lo, e2hi, wlo, whi}
+constexpr int kP2Slots = 2;                      // open windows held in registers (the one-jump kernel: 4)
 
 template <int W>
 constexpr size_t p2_lds_bytes() {
-    return sizeof(float) * (kP2X2 + kP2X1) + (sizeof(int16_t) + sizeof(float)) * (size_t)kP2Halo * W;
+    return sizeof(float) * (kP2X2 + kP2X1) + sizeof(uint2) * (size_t)kP2Halo * W;
 }
 
 // Entries of pull row m (column, value) in the order the one-jump kernel
@@ -604,8 +607,7 @@ __global__ __launch_bounds__(kPThreads) void k_persistent2(PersistArgs a) {
     extern __shared__ __align__(16) char p2lds[];
     float* X2 = reinterpret_cast<float*>(p2lds);                  // x_k on E2
     float* X1 = X2 + kP2X2;                                       // x_{k+1} on E1
-    int16_t* hcol = reinterpret_cast<int16_t*>(X1 + kP2X1);       // halo entries: column - e2lo
-    float* hval = reinterpret_cast<float*>(hcol + kP2Halo * W);   // halo entries: value
+    uint2* hent = reinterpret_cast<uint2*>(X1 + kP2X1);           // halo entries: (4 (column - e2lo), value bits)
     __shared__ double red[kPWaves + 1];
     const int G = a.G;
     const int g = logical_block(G);
@@ -641,16 +643,14 @@ __global__ __launch_bounds__(kPThreads) void k_persistent2(PersistArgs a) {
         float vv[W];
         row_entries<W, CSR>(a, m, cc, vv);
 #pragma unroll
-        for (int j = 0; j < W; ++j) {
-            hcol[h * W + j] = (int16_t)(cc[j] - e2lo);
-            hval[h * W + j] = vv[j];
-        }
+        for (int j = 0; j < W; ++j)
+            hent[h * W + j] = make_uint2(4u * (uint32_t)(cc[j] - e2lo), __builtin_bit_cast(uint32_t, vv[j]));
     }
 
     // ---- k = 0
-    float sacc[kPSlots][R], cacc[kPSlots][R];
+    float sacc[kP2Slots][R], cacc[kP2Slots][R];
 #pragma unroll
-    for (int q = 0; q < kPSlots; ++q)
+    for (int q = 0; q < kP2Slots; ++q)
 #pragma unroll
         for (int i = 0; i < R; ++i) { sacc[q][i] = 0.f; cacc[q][i] = 0.f; }
     float yv[R];
@@ -665,37 +665,37 @@ __global__ __launch_bounds__(kPThreads) void k_persistent2(PersistArgs a) {
         }
         mloc += (double)yv[i];
     }
-    int jq[kPSlots];
-    float wvec[kPSlots];
+    int jq[kP2Slots];
+    float wvec[kP2Slots];
     int wbase = 0;
     auto fetch = [&](int k) {
 #pragma unroll
-        for (int qq = 0; qq < kPSlots; ++qq) jq[qq] = -1;
+        for (int qq = 0; qq < kP2Slots; ++qq) jq[qq] = -1;
         for (int j = 0; j < a.at.n; ++j) {
             const TimeParam& tp = a.at.tp[j];
             if (k < tp.L || k > tp.K) continue;
 #pragma unroll
-            for (int qq = 0; qq < kPSlots; ++qq)
+            for (int qq = 0; qq < kP2Slots; ++qq)
                 if (qq == a.slot[j]) jq[qq] = j;
         }
         if ((k & 63) == 0) {
             wbase = k;
             const int kk = k + lane;
 #pragma unroll
-            for (int qq = 0; qq < kPSlots; ++qq) wvec[qq] = 0.f;
+            for (int qq = 0; qq < kP2Slots; ++qq) wvec[qq] = 0.f;
             for (int j = 0; j < a.at.n; ++j) {
                 const TimeParam& tp = a.at.tp[j];
                 if (kk < tp.L || kk > tp.K) continue;
                 const float w = (kk == tp.K) ? (float)tp.lastw : (float)a.wtab[tp.woff + (kk - tp.L)];
 #pragma unroll
-                for (int qq = 0; qq < kPSlots; ++qq)
+                for (int qq = 0; qq < kP2Slots; ++qq)
                     if (qq == a.slot[j]) wvec[qq] = w;
             }
         }
     };
     auto accumulate = [&](int k) {
 #pragma unroll
-        for (int qq = 0; qq < kPSlots; ++qq) {
+        for (int qq = 0; qq < kP2Slots; ++qq) {
             const int j = jq[qq];
             if (j < 0) continue;
             const TimeParam& tp = a.at.tp[j];
@@ -769,14 +769,31 @@ __global__ __launch_bounds__(kPThreads) void k_persistent2(PersistArgs a) {
                 for (int j = 0; j < W; ++j) acc = fmaf(cval[i][j], xv[i][j], acc);
                 yv[i] = fs * acc;
             }
+            if (nh > 0) {
+                constexpr int kB = 2;  // halo rows per batch (registers)
 #pragma unroll
-            for (int u = 0; u < kP2HR; ++u) {
-                const int h = tid + u * kPThreads;
-                if (h < nh) {
-                    float acc = 0.f;
+                for (int u0 = 0; u0 < kP2HR; u0 += kB) {
+                    uint2 e[kB][W];
+                    float hx[kB][W];
 #pragma unroll
-                    for (int j = 0; j < W; ++j) acc = fmaf(hval[h * W + j], X2[hcol[h * W + j]], acc);
-                    X1[h < nlo ? h : (r1 - e1lo) + (h - nlo)] = fs * acc;
+                    for (int u = 0; u < kB; ++u) {
+                        const int h = min(tid + (u0 + u) * kPThreads, nh - 1);
+#pragma unroll
+                        for (int j = 0; j < W; ++j) e[u][j] = hent[h * W + j];
+                    }
+#pragma unroll
+                    for (int u = 0; u < kB; ++u)
+#pragma unroll
+                        for (int j = 0; j < W; ++j)
+                            hx[u][j] = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(X2) + e[u][j].x);
+#pragma unroll
+                    for (int u = 0; u < kB; ++u) {
+                        const int h = tid + (u0 + u) * kPThreads;
+                        float acc = 0.f;
+#pragma unroll
+                        for (int j = 0; j < W; ++j) acc = fmaf(__builtin_bit_cast(float, e[u][j].y), hx[u][j], acc);
+                        if (h < nh) X1[h < nlo ? h : (r1 - e1lo) + (h - nlo)] = fs * acc;
+                    }
                 }
             }
 #pragma unroll
@@ -994,7 +1011,7 @@ static bool build_p2_table(const mjp_plan* p, int G, std::vector<int32_t>& tab) 
 }
 
 bool persistent2_fits(mjp_plan* p, int max_open, PersistCfg& cfg) {
-    if (max_open > kPSlots) return false;
+    if (max_open > kP2Slots) return false;
     if (p->n >= ((int64_t)1 << 30)) return false;
     if (p->opts.renorm_every % 2 != 0) return false;  // renormalisation points must end a round
     int W = 5;

@@ -380,33 +380,39 @@ def test_protocols_bit_identical(case, renorm):
 
 
 def _twojump_case(name):
-    if name == "cascade-csr-560000":
-        m = mjp.make_model(1, [30.0, 1.0, 1.0, 0.5], [700, 800])
-        rp, ci, va = mjp.mjp_model_csr(m)
+    """(plan factory, rho0, times, whether the two-jump kernel can hold it)."""
+    cas = mjp.make_model(1, [30.0, 1.0, 1.0, 0.5], [700, 800])
+    rp, ci, va = mjp.mjp_model_csr(cas)
+    if name == "cascade-csr-560000":          # two windows open together
         return (lambda **o: mjp.mjp_plan_create_csr(rp, ci, va, mjp.mjp_opts_default(**o)),
-                synth.delta(560000), [0.05, 0.3, 0.31, 0.32])
+                synth.delta(560000), [0.05, 0.3, 0.31], True)
+    if name == "cascade-csr-560000-3open":    # three: more than the two-jump kernel keeps
+        return (lambda **o: mjp.mjp_plan_create_csr(rp, ci, va, mjp.mjp_opts_default(**o)),
+                synth.delta(560000), [0.3, 0.31, 0.32], False)
     if name == "cascade-stencil-600000-odd":
         m = mjp.make_model(1, [30.0, 1.0, 0.7, 0.4], [600, 1000])
         return (lambda **o: mjp.mjp_plan_create_stencil(m, mjp.mjp_opts_default(**o)),
-                synth.random_prob(600000, 71), [0.2])
+                synth.random_prob(600000, 71), [0.2], True)
     if name == "bd-stencil-700001":
         m = mjp.make_model(0, [50000.0, 0.01], [700001])
         return (lambda **o: mjp.mjp_plan_create_stencil(m, mjp.mjp_opts_default(**o)),
-                synth.delta(700001), [0.01, 0.013])
+                synth.delta(700001), [0.01, 0.013], True)
     raise KeyError(name)
 
 
 @pytest.mark.parametrize("renorm", [32, 0, 2, 1])
-@pytest.mark.parametrize("case", ["cascade-csr-560000", "cascade-stencil-600000-odd", "bd-stencil-700001"])
+@pytest.mark.parametrize("case", ["cascade-csr-560000", "cascade-csr-560000-3open", "cascade-stencil-600000-odd",
+                                  "bd-stencil-700001"])
 def test_twojump_bit_identical(case, renorm):
     """Two jumps per synchronisation (neighbours' boundary rows recomputed
     from the same inputs with the same operations) against the one-jump
     kernel and the fenced protocol, bit for bit, on operators large enough
     for the two-jump kernel (>= 128 workgroups of 4096 rows; ragged sizes;
-    odd and even jump counts; several windows open together).  An odd
-    renorm_every cannot end a two-jump round: the sweep falls back to one
-    jump per synchronisation."""
-    make, rho0, times = _twojump_case(case)
+    odd and even jump counts; two windows open together).  An odd
+    renorm_every cannot end a two-jump round, and more than two open windows
+    exceed its registers: those sweeps fall back to one jump per
+    synchronisation."""
+    make, rho0, times, fits = _twojump_case(case)
     say(f"[gpu] two-jump {case} renorm_every={renorm}")
     res, paths = [], []
     for variant in (mjp.MJP_VARIANT_PERSISTENT, mjp.MJP_VARIANT_PERSISTENT_ONEJUMP,
@@ -419,7 +425,7 @@ def test_twojump_bit_identical(case, renorm):
         res.append(out)
         paths.append(inf[0]["path"])
         say(f"    variant {variant}: path {inf[0]['path']}, K {[i['K'] for i in inf]}")
-    want = mjp.MJP_PATH_PERSISTENT_TWOJUMP if renorm % 2 == 0 else mjp.MJP_PATH_PERSISTENT
+    want = mjp.MJP_PATH_PERSISTENT_TWOJUMP if fits and renorm % 2 == 0 else mjp.MJP_PATH_PERSISTENT
     assert paths == [want, mjp.MJP_PATH_PERSISTENT, mjp.MJP_PATH_PERSISTENT_FENCED]
     for r in res[1:]:
         assert np.array_equal(res[0], r)
