@@ -37,10 +37,10 @@
 
 namespace mjp {
 
-constexpr int kKB = 256;          // threads per block of the streaming kernels
+constexpr int kKB = 512;          // threads per block of the streaming kernels
 constexpr int kKMax = 32;         // largest basis
 constexpr int kTaylor = 12;       // Taylor degree of the small exponential
-constexpr int kMaxBlocks = 1024;  // grid of the streaming kernels (4 per CU)
+constexpr int kMaxBlocks = 256;   // grid of the streaming kernels (1 per CU)
 constexpr double kBreakRel = 1e-12;
 
 // scalar slots (FP64) of the device scalar block

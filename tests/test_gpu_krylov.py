@@ -5,8 +5,11 @@ the C ABI.
   same steps; they differ only in rounding order (classical Gram-Schmidt with
   reorthogonalisation and a Taylor exponential on the GPU, modified
   Gram-Schmidt and scipy's Pade exponential in the oracle), so the bar is
-  L1 <= 1e-10 per output vector (FP64 rounding over <= a few hundred steps
-  of kappa^2 operations stays below 1e-12 on these sizes).
+  L1 <= 1e-10 per output vector at dt_factor <= 1 (the oracle's own result
+  moves by ~1e-14 when every rate moves by one ulp).  At the paper's step
+  (dt_factor 2) the step is ill-conditioned: one-ulp rate perturbations move
+  the oracle's own result by up to ~2e-10, so there the bar is ten times
+  that sensitivity, measured per case with the oracle.
 * On invariant subspaces the step is exact: compared with the dense
   exponential.
 * At full size (N = 10^6) with dt_factor = 0.5, where the method converges
@@ -27,6 +30,34 @@ pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
 
 BAR = 1e-10
+
+
+def rounding_sensitivity(orc, rp, ci, va, rho0, times, trials=2, **opts):
+    """Largest L1 change of the oracle's own result when every rate moves by
+    one ulp (diagonal recomputed so rows stay conservative).  At the paper's
+    step (dt_factor 2, large ||H dt||) the step is ill-conditioned: this
+    reaches ~2e-10 on the birth-death workload, so two correct FP64
+    implementations that round differently can differ by that much; at
+    dt_factor <= 1 it is ~1e-14."""
+    base, _ = krylov.krylov_expv(orc.CSR.from_arrays(rp, ci, va), rho0, times, **opts)
+    g = np.random.default_rng(0)
+    rp64 = np.asarray(rp, np.int64)
+    worst = 0.0
+    for _ in range(trials):
+        v2 = np.asarray(va, np.float64) * (1 + g.choice([-1.0, 1.0], size=len(va)) * 2.0 ** -53)
+        for r in range(len(rp64) - 1):
+            idx = np.arange(rp64[r], rp64[r + 1])
+            d = idx[np.asarray(ci)[idx] == r]
+            off = idx[np.asarray(ci)[idx] != r]
+            v2[d] = -v2[off].sum()
+        got, _ = krylov.krylov_expv(orc.CSR.from_arrays(rp, ci, v2), rho0, times, **opts)
+        worst = max(worst, float(np.abs(got - base).sum(axis=1).max()))
+    return worst
+
+
+def paper_step_bar(orc, rp, ci, va, rho0, times, **opts):
+    """BAR, or ten times the oracle's own one-ulp sensitivity if larger."""
+    return max(BAR, 10.0 * rounding_sensitivity(orc, rp, ci, va, rho0, times, **opts))
 
 
 def say(*a):
@@ -59,8 +90,9 @@ def test_birth_death_vs_oracle(orc, f):
     ref, rinfo = krylov.krylov_expv(A, synth.delta(1000), [1.0], dt_factor=f)
     assert info["steps"] == rinfo["steps"]
     l1 = np.abs(got - ref).sum()
-    say(f"    steps {info['steps']}  L1 vs oracle {l1:.3e}")
-    assert l1 <= BAR
+    bar = paper_step_bar(orc, rp, ci, va, synth.delta(1000), [1.0], dt_factor=f) if f > 1.0 else BAR
+    say(f"    steps {info['steps']}  L1 vs oracle {l1:.3e} (bar {bar:.2e})")
+    assert l1 <= bar
 
 
 def test_cascade_several_times_vs_oracle(orc):
@@ -71,8 +103,11 @@ def test_cascade_several_times_vs_oracle(orc):
     say("[gpu] krylov cascade 40x30, 5 times")
     got, info = gpu_krylov(rp, ci, va, rho0, times)
     ref, _ = krylov.krylov_expv(A, rho0, times)
+    bar = paper_step_bar(orc, rp, ci, va, rho0, times)   # the default step is the paper's (dt_factor 2)
     for j in range(len(times)):
-        assert np.abs(got[j] - ref[j]).sum() <= BAR, (j, times[j])
+        l1 = np.abs(got[j] - ref[j]).sum()
+        say(f"    t={times[j]}: L1 vs oracle {l1:.3e} (bar {bar:.2e})")
+        assert l1 <= bar, (j, times[j])
     assert np.array_equal(got[1], rho0)
 
 
