@@ -189,16 +189,31 @@ __global__ void k_mse(const float* __restrict__ Y, int npad, const float* __rest
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
-// Bias gradients: column sums of dZ (FP32), 64 columns per block, fixed order.
-__global__ void k_bias_grad(const float* __restrict__ dZf, int Bpad, int npad, int n_valid, float* __restrict__ gb) {
+// Bias gradients: column sums of dZ (FP32) in a fixed order, in two stages
+// so the whole chip works on them: blocks of 64 columns x kBgRows rows write
+// one partial per (chunk, column), then each column adds its chunks in order.
+constexpr int kBgRows = 32;  // rows per partial (divides every padded batch)
+
+__global__ void k_bias_part(const float* __restrict__ dZf, int npad, float* __restrict__ part) {
     __shared__ float red[4][64];
     const int c = blockIdx.x * 64 + (threadIdx.x & 63), rg = threadIdx.x >> 6;
+    const int b0 = blockIdx.y * kBgRows;
     float s = 0.f;
-    if (c < npad)
-        for (int b = rg; b < Bpad; b += 4) s += dZf[(size_t)b * npad + c];
+#pragma unroll
+    for (int b = rg; b < kBgRows; b += 4) s += dZf[(size_t)(b0 + b) * npad + c];
     red[rg][threadIdx.x & 63] = s;
     __syncthreads();
-    if (rg == 0 && c < n_valid) gb[c] = (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+    if (rg == 0)
+        part[(size_t)blockIdx.y * npad + c] = (red[0][threadIdx.x] + red[1][threadIdx.x]) +
+                                              (red[2][threadIdx.x] + red[3][threadIdx.x]);
+}
+
+__global__ void k_bias_sum(const float* __restrict__ part, int nchunk, int npad, int n_valid, float* __restrict__ gb) {
+    const int c = blockIdx.x * 64 + threadIdx.x;
+    if (c >= n_valid) return;
+    float s = 0.f;
+    for (int k = 0; k < nchunk; ++k) s += part[(size_t)k * npad + c];
+    gb[c] = s;
 }
 
 struct LayerDev {
@@ -292,6 +307,7 @@ struct mjp_surrogate {
     DevBuf Z[kMaxLayers];      // FP32 pre-activations [Bmax x npad]
     DevBuf dZ[kMaxLayers], dZf[kMaxLayers];
     DevBuf Y, tgt, lossp, perm;
+    DevBuf bpart;              // bias-gradient partials [Bmax / kBgRows][max npad]
 };
 
 namespace mjp {
@@ -311,6 +327,9 @@ static mjp_status surrogate_alloc(mjp_surrogate* s, int Bmax) {
             (st = s->P[l].reserve(sizeof(float) * (size_t)s->splits * s->npad[l] * s->kpad[l])))
             return st;
     }
+    int np_max = 0;
+    for (int l = 0; l < s->L; ++l) np_max = std::max(np_max, s->npad[l]);
+    if ((st = s->bpart.reserve(sizeof(float) * (size_t)(Bmax / kBgRows + 1) * np_max))) return st;
     if ((st = s->Y.reserve(sizeof(float) * (size_t)Bmax * s->npad[s->L - 1])) ||
         (st = s->tgt.reserve(sizeof(float) * (size_t)Bmax)) || (st = s->lossp.reserve(sizeof(double) * (size_t)Bmax)))
         return st;
@@ -390,7 +409,9 @@ static void backward(mjp_surrogate* s, int Bpad, hipStream_t st) {
         w.k_per_split = Bpad / splits;
         w.P = s->P[l].as<float>();
         launch_gemm(true, false, EPI_WGRAD, w, splits, st);  // the reduction reads only these splits
-        hipLaunchKernelGGL(k_bias_grad, dim3(s->npad[l] / 64), dim3(256), 0, st, s->dZf[l].as<float>(), Bpad,
+        hipLaunchKernelGGL(k_bias_part, dim3(s->npad[l] / 64, Bpad / kBgRows), dim3(256), 0, st,
+                           s->dZf[l].as<float>(), s->npad[l], s->bpart.as<float>());
+        hipLaunchKernelGGL(k_bias_sum, dim3(s->npad[l] / 64), dim3(64), 0, st, s->bpart.as<float>(), Bpad / kBgRows,
                            s->npad[l], s->out[l], s->gb[l].as<float>());
         if (l > 0) {
             GemmArgs d{};
@@ -517,6 +538,7 @@ void mjp_surrogate_destroy(mjp_surrogate* s) {
     s->tgt.release();
     s->lossp.release();
     s->perm.release();
+    s->bpart.release();
     delete s;
 }
 
