@@ -37,6 +37,7 @@
 //    acquire fence (L2 write-back / invalidate).  Kept as the reference
 //    protocol; both protocols give bit-identical results.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <vector>
 
@@ -375,24 +376,40 @@ __global__ __launch_bounds__(kPThreads) void k_persistent(PersistArgs a) {
     }
 
     // Per-slot parameters of jump k (uniform): jq[q] is the time whose
-    // window holds k in slot q (or -1); fetch() finds them from the kernel
-    // arguments only.  The Poisson weights are held 64 jumps at a time: lane
+    // window holds k in slot q (or -1), jL/jK/jO its window and output row.
+    // They change only where a window opens or closes, so fetch() rescans
+    // the kernel arguments only when k reaches knext, the first such jump
+    // after the last scan.  The Poisson weights are held 64 jumps at a time: lane
     // l of wvec[q] is the weight of jump wbase + l for the time occupying
     // slot q then (0 if none), refilled every 64 jumps with one vector load
     // per lane, so a jump reads its weight from a register (v_readlane at a
     // uniform index) and never waits on memory for it.
-    int jq[kPSlots];
+    int jq[kPSlots], jL[kPSlots], jK[kPSlots], jO[kPSlots];
+    int knext = 0;
     float wvec[kPSlots];
     int wbase = 0;
     auto fetch = [&](int k) {
+        if (k >= knext) {
+            knext = INT_MAX;
 #pragma unroll
-        for (int qq = 0; qq < kPSlots; ++qq) jq[qq] = -1;
-        for (int j = 0; j < a.at.n; ++j) {
-            const TimeParam& tp = a.at.tp[j];
-            if (k < tp.L || k > tp.K) continue;
+            for (int qq = 0; qq < kPSlots; ++qq) {
+                jq[qq] = -1;
+                jL[qq] = jK[qq] = jO[qq] = 0;
+            }
+            for (int j = 0; j < a.at.n; ++j) {
+                const TimeParam& tp = a.at.tp[j];
+                const int L = tp.L, K = tp.K;
+                if (k < L) {
+                    knext = min(knext, L);
+                    continue;
+                }
+                if (k > K) continue;
+                knext = min(knext, K + 1);
+                const int o = tp.out, sj = a.slot[j];
 #pragma unroll
-            for (int qq = 0; qq < kPSlots; ++qq)
-                if (qq == a.slot[j]) jq[qq] = j;
+                for (int qq = 0; qq < kPSlots; ++qq)
+                    if (qq == sj) { jq[qq] = j; jL[qq] = L; jK[qq] = K; jO[qq] = o; }
+            }
         }
         if ((k & 63) == 0) {
             wbase = k;
@@ -412,14 +429,12 @@ __global__ __launch_bounds__(kPThreads) void k_persistent(PersistArgs a) {
     auto accumulate = [&](int k) {
 #pragma unroll
         for (int qq = 0; qq < kPSlots; ++qq) {
-            const int j = jq[qq];
-            if (j < 0) continue;
-            const TimeParam& tp = a.at.tp[j];
+            if (jq[qq] < 0) continue;
             const float w = __builtin_bit_cast(
                 float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, wvec[qq]), k - wbase));
 #pragma unroll
             for (int i = 0; i < R; ++i) {
-                if (k == tp.L) {
+                if (k == jL[qq]) {
                     sacc[qq][i] = w * yv[i];
                     cacc[qq][i] = 0.f;
                 } else {
@@ -428,7 +443,7 @@ __global__ __launch_bounds__(kPThreads) void k_persistent(PersistArgs a) {
                     cacc[qq][i] = (t - sacc[qq][i]) - yk;
                     sacc[qq][i] = t;
                 }
-                if (k == tp.K && live(i)) a.out[(int64_t)tp.out * n + row(i)] = sacc[qq][i] - cacc[qq][i];
+                if (k == jK[qq] && live(i)) a.out[(int64_t)jO[qq] * n + row(i)] = sacc[qq][i] - cacc[qq][i];
             }
         }
     };
@@ -447,6 +462,10 @@ __global__ __launch_bounds__(kPThreads) void k_persistent(PersistArgs a) {
     double last_mass = mass0;
 
     const int m = a.renorm_every;
+    // renormalisation every m jumps (m = 0: never): rc counts down to the
+    // next one, rpar is the parity of the renormalisations so far (selects
+    // which of the two partial-mass arrays it writes)
+    int rc = m, rpar = 0;
     // this workgroup's neighbour interval, read once
     const int wlo = a.wait ? a.wait[2 * g] : g, whi = a.wait ? a.wait[2 * g + 1] : g;
     const __amdgpu_buffer_rsrc_t r_rho0 = iter_rsrc(a.rho0, n), r_buf0 = iter_rsrc(a.buf0, n),
@@ -487,8 +506,13 @@ __global__ __launch_bounds__(kPThreads) void k_persistent(PersistArgs a) {
             if (G > 1) st_iter<COH>(y, 4u * (uint32_t)row(i), yv[i]);
         }
         accumulate(k);
-        const bool renorm = m > 0 && (k % m == 0) && k < a.Kmax;
-        double* pm = a.pmass + (size_t)G * (1 + ((k / (m > 0 ? m : 1)) & 1));
+        bool renorm = false;
+        if (m > 0 && --rc == 0) {
+            rc = m;
+            rpar ^= 1;
+            renorm = k < a.Kmax;
+        }
+        double* pm = a.pmass + (size_t)G * (1 + rpar);
         if (renorm) {
             const double s = block_sum_f64(part, red);
             if (threadIdx.x == 0) __hip_atomic_store(pm + g, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -665,18 +689,32 @@ __global__ __launch_bounds__(kPThreads) void k_persistent2(PersistArgs a) {
         }
         mloc += (double)yv[i];
     }
-    int jq[kP2Slots];
+    int jq[kP2Slots], jL[kP2Slots], jK[kP2Slots], jO[kP2Slots];  // as in the one-jump kernel
+    int knext = 0;
     float wvec[kP2Slots];
     int wbase = 0;
     auto fetch = [&](int k) {
+        if (k >= knext) {
+            knext = INT_MAX;
 #pragma unroll
-        for (int qq = 0; qq < kP2Slots; ++qq) jq[qq] = -1;
-        for (int j = 0; j < a.at.n; ++j) {
-            const TimeParam& tp = a.at.tp[j];
-            if (k < tp.L || k > tp.K) continue;
+            for (int qq = 0; qq < kP2Slots; ++qq) {
+                jq[qq] = -1;
+                jL[qq] = jK[qq] = jO[qq] = 0;
+            }
+            for (int j = 0; j < a.at.n; ++j) {
+                const TimeParam& tp = a.at.tp[j];
+                const int L = tp.L, K = tp.K;
+                if (k < L) {
+                    knext = min(knext, L);
+                    continue;
+                }
+                if (k > K) continue;
+                knext = min(knext, K + 1);
+                const int o = tp.out, sj = a.slot[j];
 #pragma unroll
-            for (int qq = 0; qq < kP2Slots; ++qq)
-                if (qq == a.slot[j]) jq[qq] = j;
+                for (int qq = 0; qq < kP2Slots; ++qq)
+                    if (qq == sj) { jq[qq] = j; jL[qq] = L; jK[qq] = K; jO[qq] = o; }
+            }
         }
         if ((k & 63) == 0) {
             wbase = k;
@@ -696,14 +734,12 @@ __global__ __launch_bounds__(kPThreads) void k_persistent2(PersistArgs a) {
     auto accumulate = [&](int k) {
 #pragma unroll
         for (int qq = 0; qq < kP2Slots; ++qq) {
-            const int j = jq[qq];
-            if (j < 0) continue;
-            const TimeParam& tp = a.at.tp[j];
+            if (jq[qq] < 0) continue;
             const float w = __builtin_bit_cast(
                 float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, wvec[qq]), k - wbase));
 #pragma unroll
             for (int i = 0; i < R; ++i) {
-                if (k == tp.L) {
+                if (k == jL[qq]) {
                     sacc[qq][i] = w * yv[i];
                     cacc[qq][i] = 0.f;
                 } else {
@@ -712,7 +748,7 @@ __global__ __launch_bounds__(kPThreads) void k_persistent2(PersistArgs a) {
                     cacc[qq][i] = (t - sacc[qq][i]) - yk;
                     sacc[qq][i] = t;
                 }
-                if (k == tp.K && live(i)) a.out[(int64_t)tp.out * n + row(i)] = sacc[qq][i] - cacc[qq][i];
+                if (k == jK[qq] && live(i)) a.out[(int64_t)jO[qq] * n + row(i)] = sacc[qq][i] - cacc[qq][i];
             }
         }
     };
@@ -728,6 +764,7 @@ __global__ __launch_bounds__(kPThreads) void k_persistent2(PersistArgs a) {
     double scale = 1.0;
     double last_mass = mass0;
     const int m = a.renorm_every;  // even or 0
+    int rc = m, rpar = 0;          // countdown to the next renormalisation, parity of those done
     const __amdgpu_buffer_rsrc_t r_rho0 = iter_rsrc(a.rho0, n), r_buf0 = iter_rsrc(a.buf0, n),
                                  r_buf1 = iter_rsrc(a.buf1, n);
     const char* __restrict__ x2b = reinterpret_cast<const char*>(X2) - 4 * (int64_t)e2lo;
@@ -827,8 +864,13 @@ __global__ __launch_bounds__(kPThreads) void k_persistent2(PersistArgs a) {
             }
         }
         accumulate(k + 2);
-        const bool renorm = m > 0 && ((k + 2) % m == 0) && k + 2 < a.Kmax;
-        double* pm = a.pmass + (size_t)G * (1 + (((k + 2) / (m > 0 ? m : 1)) & 1));
+        bool renorm = false;
+        if (m > 0 && (rc -= 2) == 0) {
+            rc = m;
+            rpar ^= 1;
+            renorm = k + 2 < a.Kmax;
+        }
+        double* pm = a.pmass + (size_t)G * (1 + rpar);
         if (renorm) {
             const double s = block_sum_f64(part, red);
             if (tid == 0) __hip_atomic_store(pm + g, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
