@@ -4,12 +4,19 @@
 //
 // Every Linear layer, forward and backward, runs through one MFMA GEMM
 // kernel (k_gemm): a 64x64 output tile per workgroup, four waves of 32x32,
-// BF16 tiles staged through LDS in the [row][k] order the
-// v_mfma_f32_16x16x32_bf16 operands want, FP32 accumulation, and an
-// epilogue chosen at compile time:
+// FP32 accumulation.  The reduction runs in chunks of up to 256 (one
+// chunk for the 256-wide layers): each thread issues all sixteen 16-byte
+// loads of a chunk at once, and the chunk is staged whole in LDS in the [row][k] order the
+// v_mfma_f32_16x16x32_bf16 operands want; operands stored [k][row] are
+// transposed in registers in 8x8 blocks on the way.  The layers are 256
+// wide, so a GEMM is a few chunks: the old 32-wide steps with a global
+// round trip each were latency-bound.  The epilogue is chosen at compile
+// time:
 //   FWD_GELU    z = acc + b -> Z (FP32, kept for the backward pass), GELU(z) -> next input (BF16)
 //   FWD_LINEAR  y = acc + b (FP32)
-//   BWD_DATA    dZ_prev = acc * GELU'(Z_prev) -> BF16 (next GEMM) and FP32 (bias gradient)
+//   BWD_DATA    dZ_prev = acc * GELU'(Z_prev) -> BF16 (next GEMM), and the tile's
+//               column sums of dZ_prev in FP32 (one partial of the previous layer's
+//               bias gradient per 64 batch rows, added in a fixed order by k_adam)
 //   WGRAD       split-K partial products of dW = dZ^T X (FP32), reduced in a fixed order later
 // Every padded dimension is a multiple of 64 (the reduction one of 32);
 // padding rows/columns carry zeros, and rows past the batch are masked in
@@ -29,9 +36,12 @@ namespace mjp {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-constexpr int kTM = 64, kTN = 64, kTK = 32, kGT = 256, kLDP = kTK + 8;
+constexpr int kTM = 64, kTN = 64, kGT = 256;
+constexpr int kKC = 256;          // reduction chunk staged in LDS
+constexpr int kLDK = kKC + 8;     // LDS row pitch (bf16): rows 16 B apart in bank space
+constexpr size_t kGemmLds = sizeof(uint16_t) * (size_t)(kTM + kTN) * kLDK;  // 67,584 B
 constexpr int kMaxLayers = 9;
-constexpr int kWgradChunk = 512;  // batch rows per split of the weight-gradient GEMM
+constexpr int kWgradChunk = 256;  // batch rows per split of the weight-gradient GEMM (one chunk)
 
 __device__ __forceinline__ uint16_t f2bf(float f) {  // round to nearest even
     uint32_t u = __float_as_uint(f);
@@ -62,14 +72,76 @@ struct GemmArgs {
     int m_valid;                 // rows that are real batch rows (FWD_LINEAR output mask)
     float* Z;                    // FWD_GELU: out pre-activation [M x N]; BWD_DATA: in, previous layer's [M x N]
     uint16_t* H;                 // FWD_GELU: GELU out [M x N]; BWD_DATA: dZ_prev BF16 [M x N]
-    float* Hf;                   // BWD_DATA: dZ_prev FP32 [M x N]; FWD_LINEAR: y [M x N]
+    float* Hf;                   // FWD_LINEAR: y [M x N]
+    float* bpart;                // BWD_DATA: column sums per 64-row tile [M / 64][N]
     float* P;                    // WGRAD: partials [split][M][N]
 };
 
+// One operand tile (64 rows x a chunk of up to kKC reductions) into
+// registers: eight 16-byte loads per thread, all issued together.
+//   [row][k] storage: slot u covers row (tid >> 5) + 8u, k offset 8 (tid & 31)
+//                     (32 lanes read one row's 512 bytes);
+//   [k][row] storage: the thread owns the 8x8 block of rows rg..rg+7 and
+//                     k offsets kg..kg+7 (slot u = k offset kg + u); lanes
+//                     0-7 of a wave cover eight k rows, so each k row is read
+//                     as one 128-byte segment by eight lanes.
+// Lanes past klen (a partial last chunk) load from offset 0 of the chunk
+// instead (every load is issued, none waits on a branch) and are never
+// stored.
+template <bool KMAJOR>
+__device__ __forceinline__ void tile_load(uint4 (&v)[8], const uint16_t* __restrict__ p, int ld, int r0, int k0,
+                                          int klen, int tid) {
+    if (!KMAJOR) {
+        const int c = (tid & 31) * 8, cc = c < klen ? c : 0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int r = (tid >> 5) + 8 * u;
+            v[u] = *reinterpret_cast<const uint4*>(p + (size_t)(r0 + r) * ld + k0 + cc);
+        }
+    } else {
+        const int lane = tid & 63, rg = (lane >> 3) * 8, kg = ((lane & 7) + 8 * (tid >> 6)) * 8;
+        const int kc = kg < klen ? kg : 0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = *reinterpret_cast<const uint4*>(p + (size_t)(k0 + kc + u) * ld + r0 + rg);
+    }
+}
+
+// The registers of tile_load into LDS rows [row][k] (pitch kLDK); a [k][row]
+// block is transposed first: output row c holds the eight k values of
+// element c of the eight loaded vectors.
+template <bool KMAJOR>
+__device__ __forceinline__ void tile_store(const uint4 (&v)[8], uint16_t* __restrict__ S, int klen, int tid) {
+    if (!KMAJOR) {
+        const int c = (tid & 31) * 8;
+        const bool on = c < klen;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (on) *reinterpret_cast<uint4*>(S + ((tid >> 5) + 8 * u) * kLDK + c) = v[u];
+    } else {
+        const int lane = tid & 63, rg = (lane >> 3) * 8, kg = ((lane & 7) + 8 * (tid >> 6)) * 8;
+        if (kg < klen) {
+            auto word = [&](int u, int w) -> uint32_t {
+                return w == 0 ? v[u].x : (w == 1 ? v[u].y : (w == 2 ? v[u].z : v[u].w));
+            };
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                uint32_t o[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const uint32_t a = word(2 * j, c >> 1), b = word(2 * j + 1, c >> 1);
+                    o[j] = (c & 1) ? ((a >> 16) | (b & 0xffff0000u)) : ((a & 0xffffu) | (b << 16));
+                }
+                *reinterpret_cast<uint4*>(S + (rg + c) * kLDK + kg) = make_uint4(o[0], o[1], o[2], o[3]);
+            }
+        }
+    }
+}
+
 template <bool TA, bool TB, int EPI>
 __global__ __launch_bounds__(kGT) void k_gemm(GemmArgs g) {
-    __shared__ __attribute__((aligned(16))) uint16_t As[kTM][kLDP];
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[kTN][kLDP];
+    extern __shared__ __attribute__((aligned(16))) uint16_t gemm_lds[];
+    uint16_t* As = gemm_lds;               // [kTM][kLDK]
+    uint16_t* Bs = gemm_lds + kTM * kLDK;  // [kTN][kLDK]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int m0 = blockIdx.y * kTM, n0 = blockIdx.x * kTN;
     const int kbeg = blockIdx.z * g.k_per_split;
@@ -81,43 +153,55 @@ __global__ __launch_bounds__(kGT) void k_gemm(GemmArgs g) {
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-    for (int k0 = kbeg; k0 < kend; k0 += kTK) {
-        if (!TA) {
-            const int r = tid >> 2, c = (tid & 3) * 8;
-            *reinterpret_cast<uint4*>(&As[r][c]) =
-                *reinterpret_cast<const uint4*>(&g.A[(size_t)(m0 + r) * g.lda + k0 + c]);
-        } else {
-            const int kk = tid >> 3, mm = (tid & 7) * 8;
-            const uint4 v = *reinterpret_cast<const uint4*>(&g.A[(size_t)(k0 + kk) * g.lda + m0 + mm]);
-            const uint16_t* e = reinterpret_cast<const uint16_t*>(&v);
-#pragma unroll
-            for (int i = 0; i < 8; ++i) As[mm + i][kk] = e[i];
-        }
-        if (TB) {
-            const int r = tid >> 2, c = (tid & 3) * 8;
-            *reinterpret_cast<uint4*>(&Bs[r][c]) =
-                *reinterpret_cast<const uint4*>(&g.B[(size_t)(n0 + r) * g.ldb + k0 + c]);
-        } else {
-            const int kk = tid >> 3, nn = (tid & 7) * 8;
-            const uint4 v = *reinterpret_cast<const uint4*>(&g.B[(size_t)(k0 + kk) * g.ldb + n0 + nn]);
-            const uint16_t* e = reinterpret_cast<const uint16_t*>(&v);
-#pragma unroll
-            for (int i = 0; i < 8; ++i) Bs[nn + i][kk] = e[i];
+    for (int k0 = kbeg; k0 < kend; k0 += kKC) {
+        const int cur = min(kKC, kend - k0);
+        {
+            uint4 ra[8], rb[8];
+            tile_load<TA>(ra, g.A, g.lda, m0, k0, cur, tid);
+            tile_load<!TB>(rb, g.B, g.ldb, n0, k0, cur, tid);
+            tile_store<TA>(ra, As, cur, tid);
+            tile_store<!TB>(rb, Bs, cur, tid);
         }
         __syncthreads();
-        bf16x8 af[2], bfv[2];
+        for (int ks = 0; ks < cur; ks += 32) {
+            bf16x8 af[2], bfv[2];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) af[i] = *reinterpret_cast<const bf16x8*>(&As[wm + i * 16 + (lane & 15)][(lane >> 4) * 8]);
+            for (int i = 0; i < 2; ++i)
+                af[i] = *reinterpret_cast<const bf16x8*>(As + (wm + i * 16 + (lane & 15)) * kLDK + ks + (lane >> 4) * 8);
 #pragma unroll
-        for (int j = 0; j < 2; ++j) bfv[j] = *reinterpret_cast<const bf16x8*>(&Bs[wn + j * 16 + (lane & 15)][(lane >> 4) * 8]);
+            for (int j = 0; j < 2; ++j)
+                bfv[j] = *reinterpret_cast<const bf16x8*>(Bs + (wn + j * 16 + (lane & 15)) * kLDK + ks + (lane >> 4) * 8);
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfv[j], acc[i][j], 0, 0, 0);
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfv[j], acc[i][j], 0, 0, 0);
+        }
         __syncthreads();
     }
 
-    // D layout: lane holds column (lane & 15), rows 4*(lane >> 4) + r
+    // D layout: lane holds column (lane & 15), rows 4*(lane >> 4) + r.
+    // Every global operand of the epilogue is loaded before any arithmetic
+    // (the bias of the lane's two columns, or the 16 pre-activations), so
+    // the loads are in flight together.
+    float csum[2] = {0.f, 0.f};  // BWD_DATA: this lane's rows of column j, in a fixed order
+    float bj[2] = {0.f, 0.f};
+    float zin[2][2][4];
+    auto at_of = [&](int i, int j, int r) {
+        return (size_t)(m0 + wm + i * 16 + 4 * (lane >> 4) + r) * g.N + (n0 + wn + j * 16 + (lane & 15));
+    };
+    if (EPI == EPI_FWD_GELU || EPI == EPI_FWD_LINEAR) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) bj[j] = g.bias[min(n0 + wn + j * 16 + (lane & 15), g.n_valid - 1)];
+    }
+    if (EPI == EPI_BWD_DATA) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) zin[i][j][r] = g.Z[at_of(i, j, r)];
+    }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -127,21 +211,37 @@ __global__ __launch_bounds__(kGT) void k_gemm(GemmArgs g) {
                 const int row = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
                 const int col = n0 + wn + j * 16 + (lane & 15);
                 const float v = acc[i][j][r];
-                const size_t at = (size_t)row * g.N + col;
+                const size_t at = at_of(i, j, r);
+                const bool real = col < g.n_valid;
                 if (EPI == EPI_FWD_GELU) {
-                    const float z = col < g.n_valid ? v + g.bias[col] : 0.f;
+                    const float z = real ? v + bj[j] : 0.f;
                     g.Z[at] = z;
-                    g.H[at] = f2bf(col < g.n_valid ? gelu(z) : 0.f);
+                    g.H[at] = f2bf(real ? gelu(z) : 0.f);
                 } else if (EPI == EPI_FWD_LINEAR) {
-                    g.Hf[at] = col < g.n_valid ? v + g.bias[col] : 0.f;
+                    g.Hf[at] = real ? v + bj[j] : 0.f;
                 } else if (EPI == EPI_BWD_DATA) {
-                    const float d = col < g.n_valid ? v * gelu_grad(g.Z[at]) : 0.f;
+                    const float d = real ? v * gelu_grad(zin[i][j][r]) : 0.f;
                     g.H[at] = f2bf(d);
-                    g.Hf[at] = d;
+                    csum[j] += d;
                 } else {
                     g.P[((size_t)blockIdx.z * g.M + row) * g.N + col] = v;
                 }
             }
+    if (EPI == EPI_BWD_DATA) {
+        // column sums over the tile's 64 rows: the four row groups of a wave
+        // (lanes 16 apart), then the two waves sharing the columns, via LDS
+        // (free: the last chunk's barrier has passed)
+        float* red = reinterpret_cast<float*>(gemm_lds);  // [2][64]
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            float t = csum[j];
+            t += __shfl_xor(t, 16, 64);
+            t += __shfl_xor(t, 32, 64);
+            if (lane < 16) red[(wm >> 5) * 64 + wn + j * 16 + lane] = t;
+        }
+        __syncthreads();
+        if (tid < 64) g.bpart[(size_t)blockIdx.y * g.N + n0 + tid] = red[tid] + red[64 + tid];
+    }
 }
 
 // X rows (optionally permuted) into the padded BF16 input, targets alongside.
@@ -164,63 +264,54 @@ __global__ void k_mlp_input(const float* __restrict__ x, const float* __restrict
     }
 }
 
-// MSE over the n_valid real rows: dZ = 2 (y - t) / n_valid in column 0,
-// per-block partial sums of (y - t)^2.
-__global__ void k_mse(const float* __restrict__ Y, int npad, const float* __restrict__ tgt, int n_valid, int Bpad,
-                      uint16_t* __restrict__ dZ, float* __restrict__ dZf, double* __restrict__ partial) {
-    __shared__ double red[4];
+// MSE over the n_valid real rows: dZ = 2 (y - t) / n_valid in column 0 of
+// the last layer's dZ (its other columns stay zero from allocation), and
+// per-block partial sums of (y - t)^2 (FP64) and of dZ's column 0 (FP32:
+// the output bias gradient's partials, added in a fixed order by k_adam).
+constexpr int kMseRows = 256;  // rows per block (divides every padded batch)
+
+__global__ __launch_bounds__(kMseRows) void k_mse(const float* __restrict__ Y, int npad, const float* __restrict__ tgt,
+                                                  int n_valid, int Bpad, uint16_t* __restrict__ dZ,
+                                                  double* __restrict__ loss_part, float* __restrict__ bias_part) {
+    __shared__ double red[kMseRows / 64];
+    __shared__ float redf[kMseRows / 64];
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     double e2 = 0.0;
+    float d = 0.f;
     if (b < Bpad) {
-        float d = 0.f;
         if (b < n_valid) {
             const float e = Y[(size_t)b * npad] - tgt[b];
             e2 = (double)e * (double)e;
             d = 2.f * e / (float)n_valid;
         }
-        for (int c = 0; c < npad; ++c) {
-            dZ[(size_t)b * npad + c] = f2bf(c == 0 ? d : 0.f);
-            dZf[(size_t)b * npad + c] = c == 0 ? d : 0.f;
-        }
+        dZ[(size_t)b * npad] = f2bf(d);
     }
-    for (int off = 32; off > 0; off >>= 1) e2 += __shfl_down(e2, off, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = e2;
+    for (int off = 32; off > 0; off >>= 1) {
+        e2 += __shfl_down(e2, off, 64);
+        d += __shfl_down(d, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[threadIdx.x >> 6] = e2;
+        redf[threadIdx.x >> 6] = d;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+    if (threadIdx.x == 0) {
+        loss_part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+        bias_part[(size_t)blockIdx.x * npad] = (redf[0] + redf[1]) + (redf[2] + redf[3]);
+    }
 }
 
-// Bias gradients: column sums of dZ (FP32) in a fixed order, in two stages
-// so the whole chip works on them: blocks of 64 columns x kBgRows rows write
-// one partial per (chunk, column), then each column adds its chunks in order.
-constexpr int kBgRows = 32;  // rows per partial (divides every padded batch)
-
-__global__ void k_bias_part(const float* __restrict__ dZf, int npad, float* __restrict__ part) {
-    __shared__ float red[4][64];
-    const int c = blockIdx.x * 64 + (threadIdx.x & 63), rg = threadIdx.x >> 6;
-    const int b0 = blockIdx.y * kBgRows;
-    float s = 0.f;
-#pragma unroll
-    for (int b = rg; b < kBgRows; b += 4) s += dZf[(size_t)(b0 + b) * npad + c];
-    red[rg][threadIdx.x & 63] = s;
-    __syncthreads();
-    if (rg == 0)
-        part[(size_t)blockIdx.y * npad + c] = (red[0][threadIdx.x] + red[1][threadIdx.x]) +
-                                              (red[2][threadIdx.x] + red[3][threadIdx.x]);
-}
-
-__global__ void k_bias_sum(const float* __restrict__ part, int nchunk, int npad, int n_valid, float* __restrict__ gb) {
-    const int c = blockIdx.x * 64 + threadIdx.x;
-    if (c >= n_valid) return;
-    float s = 0.f;
-    for (int k = 0; k < nchunk; ++k) s += part[(size_t)k * npad + c];
-    gb[c] = s;
+__global__ void k_zero_u32(uint32_t* __restrict__ p, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
 }
 
 struct LayerDev {
     int in, out, kpad, npad;
     int64_t woff;      // offset of W[out][in] in the packed parameters (bias follows)
     float* P;          // weight-gradient partials [splits][npad][kpad]
-    float* gb;         // bias gradient [out]
+    const float* bp;   // bias-gradient partials [nbp][bps] (column c = output c)
+    int nbp, bps;
     uint16_t* Wbf;     // BF16 weights [npad][kpad]
 };
 
@@ -252,7 +343,9 @@ __global__ void k_adam(AdamArgs a) {
         g = 0.f;
         for (int s = 0; s < a.splits; ++s) g += d.P[((size_t)s * d.npad + o) * d.kpad + i];
     } else {
-        g = d.gb[q - nw];
+        const int c = (int)(q - nw);
+        g = 0.f;
+        for (int k = 0; k < d.nbp; ++k) g += d.bp[(size_t)k * d.bps + c];
     }
     if (a.grad_out) {
         a.grad_out[p] = g;
@@ -302,19 +395,19 @@ struct mjp_surrogate {
     int Bmax = 0, splits = 0;
     int64_t step = 0;
     DevBuf master, m1, m2, gradbuf;
-    DevBuf wbf[kMaxLayers], P[kMaxLayers], gb[kMaxLayers];
+    DevBuf wbf[kMaxLayers], P[kMaxLayers];
     DevBuf X[kMaxLayers + 1];  // BF16 inputs of each layer [Bmax x kpad]; X[L] unused
     DevBuf Z[kMaxLayers];      // FP32 pre-activations [Bmax x npad]
-    DevBuf dZ[kMaxLayers], dZf[kMaxLayers];
+    DevBuf dZ[kMaxLayers];     // BF16 output gradients [Bmax x npad]
+    DevBuf bpart[kMaxLayers];  // bias-gradient partials [Bmax / 64][npad] (last layer: [Bmax / kMseRows][npad])
     DevBuf Y, tgt, lossp, perm;
-    DevBuf bpart;              // bias-gradient partials [Bmax / kBgRows][max npad]
 };
 
 namespace mjp {
 
 static int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
-static mjp_status surrogate_alloc(mjp_surrogate* s, int Bmax) {
+static mjp_status surrogate_alloc(mjp_surrogate* s, int Bmax, hipStream_t st_) {
     if (Bmax <= s->Bmax) return MJP_OK;
     s->Bmax = Bmax;
     s->splits = std::max(1, Bmax / kWgradChunk);
@@ -323,16 +416,19 @@ static mjp_status surrogate_alloc(mjp_surrogate* s, int Bmax) {
         if ((st = s->X[l].reserve(sizeof(uint16_t) * (size_t)Bmax * s->kpad[l])) ||
             (st = s->Z[l].reserve(sizeof(float) * (size_t)Bmax * s->npad[l])) ||
             (st = s->dZ[l].reserve(sizeof(uint16_t) * (size_t)Bmax * s->npad[l])) ||
-            (st = s->dZf[l].reserve(sizeof(float) * (size_t)Bmax * s->npad[l])) ||
+            (st = s->bpart[l].reserve(sizeof(float) * (size_t)(Bmax / 64) * s->npad[l])) ||
             (st = s->P[l].reserve(sizeof(float) * (size_t)s->splits * s->npad[l] * s->kpad[l])))
             return st;
     }
-    int np_max = 0;
-    for (int l = 0; l < s->L; ++l) np_max = std::max(np_max, s->npad[l]);
-    if ((st = s->bpart.reserve(sizeof(float) * (size_t)(Bmax / kBgRows + 1) * np_max))) return st;
     if ((st = s->Y.reserve(sizeof(float) * (size_t)Bmax * s->npad[s->L - 1])) ||
         (st = s->tgt.reserve(sizeof(float) * (size_t)Bmax)) || (st = s->lossp.reserve(sizeof(double) * (size_t)Bmax)))
         return st;
+    // the loss kernel writes only column 0 of the last layer's dZ: the
+    // padding columns are cleared once per allocation
+    const size_t words = (size_t)Bmax * s->npad[s->L - 1] / 2;
+    hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, st_,
+                       s->dZ[s->L - 1].as<uint32_t>(), words);
+    if (hipGetLastError() != hipSuccess) return fail(MJP_E_DEVICE, "clearing the output gradient failed");
     return MJP_OK;
 }
 
@@ -346,7 +442,9 @@ static AdamArgs adam_args(mjp_surrogate* s) {
         a.lay[l].npad = s->npad[l];
         a.lay[l].woff = s->woff[l];
         a.lay[l].P = s->P[l].as<float>();
-        a.lay[l].gb = s->gb[l].as<float>();
+        a.lay[l].bp = s->bpart[l].as<float>();
+        a.lay[l].nbp = 0;
+        a.lay[l].bps = s->npad[l];
         a.lay[l].Wbf = s->wbf[l].as<uint16_t>();
     }
     a.splits = s->splits;
@@ -357,10 +455,26 @@ static AdamArgs adam_args(mjp_surrogate* s) {
     return a;
 }
 
+// The GEMM's LDS chunk is above the default 64 KB limit: raise it once per
+// instantiation (the same four the dispatcher below launches).
+static hipError_t gemm_lds_limits() {
+    const void* fns[] = {reinterpret_cast<const void*>(k_gemm<false, true, EPI_FWD_GELU>),
+                         reinterpret_cast<const void*>(k_gemm<false, true, EPI_FWD_LINEAR>),
+                         reinterpret_cast<const void*>(k_gemm<false, false, EPI_BWD_DATA>),
+                         reinterpret_cast<const void*>(k_gemm<true, false, EPI_WGRAD>)};
+    for (const void* f : fns) {
+        const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kGemmLds);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 static void launch_gemm(bool TA, bool TB, int epi, const GemmArgs& g, int splits, hipStream_t st) {
+    static const hipError_t lds_ok = gemm_lds_limits();  // a failure surfaces as a launch error
+    (void)lds_ok;
     const dim3 grid(g.N / kTN, g.M / kTM, splits);
 #define MJP_G(ta, tb, e) \
-    if (TA == ta && TB == tb && epi == e) { hipLaunchKernelGGL((k_gemm<ta, tb, e>), grid, dim3(kGT), 0, st, g); return; }
+    if (TA == ta && TB == tb && epi == e) { hipLaunchKernelGGL((k_gemm<ta, tb, e>), grid, dim3(kGT), kGemmLds, st, g); return; }
     MJP_G(false, true, EPI_FWD_GELU)
     MJP_G(false, true, EPI_FWD_LINEAR)
     MJP_G(false, false, EPI_BWD_DATA)
@@ -409,10 +523,6 @@ static void backward(mjp_surrogate* s, int Bpad, hipStream_t st) {
         w.k_per_split = Bpad / splits;
         w.P = s->P[l].as<float>();
         launch_gemm(true, false, EPI_WGRAD, w, splits, st);  // the reduction reads only these splits
-        hipLaunchKernelGGL(k_bias_part, dim3(s->npad[l] / 64, Bpad / kBgRows), dim3(256), 0, st,
-                           s->dZf[l].as<float>(), s->npad[l], s->bpart.as<float>());
-        hipLaunchKernelGGL(k_bias_sum, dim3(s->npad[l] / 64), dim3(64), 0, st, s->bpart.as<float>(), Bpad / kBgRows,
-                           s->npad[l], s->out[l], s->gb[l].as<float>());
         if (l > 0) {
             GemmArgs d{};
             d.M = Bpad;
@@ -426,7 +536,7 @@ static void backward(mjp_surrogate* s, int Bpad, hipStream_t st) {
             d.n_valid = s->in[l];
             d.Z = s->Z[l - 1].as<float>();
             d.H = s->dZ[l - 1].as<uint16_t>();
-            d.Hf = s->dZf[l - 1].as<float>();
+            d.bpart = s->bpart[l - 1].as<float>();
             launch_gemm(false, false, EPI_BWD_DATA, d, 1, st);
         }
     }
@@ -439,10 +549,20 @@ static void load_rows(mjp_surrogate* s, const float* x, const float* y, const in
                        s->kpad[0], Bpad, s->X[0].as<uint16_t>(), s->tgt.as<float>());
 }
 
-static void loss_grad(mjp_surrogate* s, int n_valid, int Bpad, hipStream_t st) {
-    hipLaunchKernelGGL(k_mse, dim3(Bpad / 256 + (Bpad % 256 ? 1 : 0)), dim3(256), 0, st, s->Y.as<float>(),
-                       s->npad[s->L - 1], s->tgt.as<float>(), n_valid, Bpad, s->dZ[s->L - 1].as<uint16_t>(),
-                       s->dZf[s->L - 1].as<float>(), s->lossp.as<double>());
+// loss partials go to loss_part[Bpad / kMseRows]
+static void loss_grad(mjp_surrogate* s, int n_valid, int Bpad, double* loss_part, hipStream_t st) {
+    hipLaunchKernelGGL(k_mse, dim3(Bpad / kMseRows), dim3(kMseRows), 0, st, s->Y.as<float>(), s->npad[s->L - 1],
+                       s->tgt.as<float>(), n_valid, Bpad, s->dZ[s->L - 1].as<uint16_t>(), loss_part,
+                       s->bpart[s->L - 1].as<float>());
+}
+
+// Adam arguments of one training step at padded batch Bpad: split-K
+// weight-gradient partials and the bias-gradient partials' counts.
+static AdamArgs step_args(mjp_surrogate* s, int Bpad) {
+    AdamArgs a = adam_args(s);
+    a.splits = std::max(1, Bpad / kWgradChunk);
+    for (int l = 0; l < s->L; ++l) a.lay[l].nbp = l + 1 == s->L ? Bpad / kMseRows : Bpad / 64;
+    return a;
 }
 
 }  // namespace mjp
@@ -493,8 +613,7 @@ mjp_status mjp_surrogate_create(const mjp_mlp_cfg* cfg, uint64_t seed, mjp_surro
         return st;
     }
     for (int l = 0; l < s->L; ++l) {
-        if ((st = s->wbf[l].reserve(sizeof(uint16_t) * (size_t)s->npad[l] * s->kpad[l])) ||
-            (st = s->gb[l].reserve(sizeof(float) * (size_t)s->out[l]))) {
+        if ((st = s->wbf[l].reserve(sizeof(uint16_t) * (size_t)s->npad[l] * s->kpad[l]))) {
             mjp_surrogate_destroy(s);
             return st;
         }
@@ -528,17 +647,15 @@ void mjp_surrogate_destroy(mjp_surrogate* s) {
     for (int l = 0; l < kMaxLayers; ++l) {
         s->wbf[l].release();
         s->P[l].release();
-        s->gb[l].release();
         s->Z[l].release();
         s->dZ[l].release();
-        s->dZf[l].release();
+        s->bpart[l].release();
     }
     for (auto& b : s->X) b.release();
     s->Y.release();
     s->tgt.release();
     s->lossp.release();
     s->perm.release();
-    s->bpart.release();
     delete s;
 }
 
@@ -578,7 +695,7 @@ mjp_status mjp_surrogate_infer(const mjp_surrogate* sc, const float* x_d, int32_
     mjp_surrogate* s = const_cast<mjp_surrogate*>(sc);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const int chunk = 4096;
-    mjp_status e = surrogate_alloc(s, std::max(s->Bmax, std::min(chunk, round_up(n, 256))));
+    mjp_status e = surrogate_alloc(s, std::max(s->Bmax, std::min(chunk, round_up(n, 256))), st);
     if (e) return e;
     for (int base = 0; base < n; base += s->Bmax) {
         const int nv = std::min(s->Bmax, n - base);
@@ -600,19 +717,18 @@ mjp_status mjp_surrogate_grad(const mjp_surrogate* sc, const float* x_d, const f
     mjp_surrogate* s = const_cast<mjp_surrogate*>(sc);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const int Bpad = round_up(n, 512);
-    mjp_status e = surrogate_alloc(s, Bpad);
+    mjp_status e = surrogate_alloc(s, Bpad, st);
     if (e) return e;
     if ((e = s->gradbuf.reserve(sizeof(float) * s->total))) return e;
     load_rows(s, x_d, y_d, nullptr, 0, n, Bpad, st);
     forward(s, Bpad, n, st);
-    loss_grad(s, n, Bpad, st);
+    loss_grad(s, n, Bpad, s->lossp.as<double>(), st);
     backward(s, Bpad, st);
-    AdamArgs a = adam_args(s);
-    a.splits = std::max(1, Bpad / kWgradChunk);
+    AdamArgs a = step_args(s, Bpad);
     a.grad_out = s->gradbuf.as<float>();
     hipLaunchKernelGGL(k_adam, dim3((unsigned)((s->total + 255) / 256)), dim3(256), 0, st, a);
     MJP_HIP(hipGetLastError());
-    std::vector<double> lp((size_t)(Bpad + 255) / 256);
+    std::vector<double> lp((size_t)Bpad / kMseRows);
     MJP_HIP(hipMemcpyAsync(lp.data(), s->lossp.ptr, sizeof(double) * lp.size(), hipMemcpyDeviceToHost, st));
     MJP_HIP(hipMemcpyAsync(grad_h, s->gradbuf.ptr, sizeof(float) * s->total, hipMemcpyDeviceToHost, st));
     MJP_HIP(hipStreamSynchronize(st));
@@ -635,31 +751,55 @@ mjp_status mjp_surrogate_train(mjp_surrogate* s, const float* x_d, const float* 
                   cfg->beta2 < 1 && cfg->eps_adam > 0 && cfg->weight_decay >= 0,
               MJP_E_INVALID_ARG, "bad optimiser settings");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    mjp_status e = surrogate_alloc(s, cfg->batch);
+    mjp_status e = surrogate_alloc(s, cfg->batch, st);
     if (e) return e;
-    if ((e = s->perm.reserve(sizeof(int32_t) * (size_t)n))) return e;
-    std::vector<int32_t> perm((size_t)n);
-    std::mt19937_64 rng(cfg->seed);
+    // The host runs ahead of the device: no step waits for the previous one.
+    // Each epoch's permutation goes to one of two device slots from one of
+    // two pinned host buffers, reused once the epoch two back has finished
+    // (an event per slot); the loss partials of every step stay on the
+    // device and are read once at the end.
     const int nb = (n + cfg->batch - 1) / cfg->batch;
-    std::vector<double> lp;
-    for (int ep = 0; ep < cfg->epochs; ++ep) {
-        for (int i = 0; i < n; ++i) perm[(size_t)i] = i;
-        std::shuffle(perm.begin(), perm.end(), rng);
-        MJP_HIP(hipStreamSynchronize(st));  // the previous epoch's reads of perm are done
-        MJP_HIP(hipMemcpyAsync(s->perm.ptr, perm.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, st));
-        MJP_HIP(hipStreamSynchronize(st));
-        double ep_loss = 0.0;
+    const int lstride = cfg->batch / kMseRows;  // loss partials per step
+    if ((e = s->perm.reserve(sizeof(int32_t) * 2 * (size_t)n))) return e;
+    if (loss_h && (e = s->lossp.reserve(sizeof(double) * (size_t)cfg->epochs * nb * lstride))) return e;
+    int32_t* ph[2] = {nullptr, nullptr};
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    auto cleanup = [&]() {
+        for (int q = 0; q < 2; ++q) {
+            if (ev[q]) (void)hipEventDestroy(ev[q]);
+            if (ph[q]) (void)hipHostFree(ph[q]);
+        }
+    };
+    for (int q = 0; q < 2; ++q) {
+        if (hipHostMalloc(reinterpret_cast<void**>(&ph[q]), sizeof(int32_t) * (size_t)n, hipHostMallocDefault) !=
+                hipSuccess ||
+            hipEventCreateWithFlags(&ev[q], hipEventDisableTiming) != hipSuccess) {
+            cleanup();
+            return fail(MJP_E_DEVICE, "pinned permutation buffers or events could not be created");
+        }
+    }
+    std::mt19937_64 rng(cfg->seed);
+    hipError_t he = hipSuccess;
+    for (int ep = 0; ep < cfg->epochs && he == hipSuccess; ++ep) {
+        const int slot = ep & 1;
+        if (ep >= 2 && (he = hipEventSynchronize(ev[slot])) != hipSuccess) break;  // epoch ep - 2 is done with it
+        int32_t* perm = ph[slot];
+        for (int i = 0; i < n; ++i) perm[i] = i;
+        std::shuffle(perm, perm + n, rng);
+        int32_t* perm_d = s->perm.as<int32_t>() + (size_t)slot * n;
+        if ((he = hipMemcpyAsync(perm_d, perm, sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, st)) != hipSuccess)
+            break;
         for (int bi = 0; bi < nb; ++bi) {
             const int base = bi * cfg->batch;
             const int nv = std::min(cfg->batch, n - base);
             const int Bpad = round_up(nv, 512);
-            load_rows(s, x_d, y_d, s->perm.as<int32_t>(), base, nv, Bpad, st);
+            load_rows(s, x_d, y_d, perm_d, base, nv, Bpad, st);
             forward(s, Bpad, nv, st);
-            loss_grad(s, nv, Bpad, st);
+            double* lp = loss_h ? s->lossp.as<double>() + ((size_t)ep * nb + bi) * lstride : s->lossp.as<double>();
+            loss_grad(s, nv, Bpad, lp, st);
             backward(s, Bpad, st);
             s->step += 1;
-            AdamArgs a = adam_args(s);
-            a.splits = std::max(1, Bpad / kWgradChunk);
+            AdamArgs a = step_args(s, Bpad);
             a.lr = cfg->lr;
             a.beta1 = cfg->beta1;
             a.beta2 = cfg->beta2;
@@ -668,16 +808,26 @@ mjp_status mjp_surrogate_train(mjp_surrogate* s, const float* x_d, const float* 
             a.bc1 = 1.f - std::pow(cfg->beta1, (float)s->step);
             a.bc2 = 1.f - std::pow(cfg->beta2, (float)s->step);
             hipLaunchKernelGGL(k_adam, dim3((unsigned)((s->total + 255) / 256)), dim3(256), 0, st, a);
-            if (loss_h) {
-                lp.assign((size_t)(Bpad + 255) / 256, 0.0);
-                MJP_HIP(hipMemcpyAsync(lp.data(), s->lossp.ptr, sizeof(double) * lp.size(), hipMemcpyDeviceToHost, st));
-                MJP_HIP(hipStreamSynchronize(st));
-                for (double v : lp) ep_loss += v;
-            }
         }
-        if (loss_h) loss_h[ep] = (float)(ep_loss / n);
+        if ((he = hipEventRecord(ev[slot], st)) != hipSuccess) break;
     }
-    MJP_HIP(hipGetLastError());
+    if (he == hipSuccess) he = hipGetLastError();
+    if (he == hipSuccess) he = hipStreamSynchronize(st);
+    cleanup();
+    MJP_CHECK(he == hipSuccess, MJP_E_DEVICE, "training failed: %s", hipGetErrorString(he));
+    if (loss_h) {
+        std::vector<double> lp((size_t)cfg->epochs * nb * lstride);
+        MJP_HIP(hipMemcpy(lp.data(), s->lossp.ptr, sizeof(double) * lp.size(), hipMemcpyDeviceToHost));
+        for (int ep = 0; ep < cfg->epochs; ++ep) {
+            double ep_loss = 0.0;
+            for (int bi = 0; bi < nb; ++bi) {
+                const int nv = std::min(cfg->batch, n - bi * cfg->batch);
+                const int used = round_up(nv, 512) / kMseRows;
+                for (int c = 0; c < used; ++c) ep_loss += lp[((size_t)ep * nb + bi) * lstride + c];
+            }
+            loss_h[ep] = (float)(ep_loss / n);
+        }
+    }
     return MJP_OK;
 }
 
