@@ -512,6 +512,23 @@ __global__ __launch_bounds__(kPThreads) void k_persistent(PersistArgs a) {
             rpar ^= 1;
             renorm = k < a.Kmax;
         }
+        if (G == 1) {
+            // one workgroup: the LDS double buffer needs only its own barrier,
+            // and its block sum is the whole mass (the same value the grid
+            // path's sum over one partial gives)
+            if (k == a.Kmax) break;
+            if (renorm) {
+                const double s = block_sum_f64(part, red);
+                if (threadIdx.x == 0) red[kPWaves] = s;
+                __syncthreads();
+                last_mass = red[kPWaves];
+                scale = (last_mass > 0.0 && mass0 > 0.0) ? mass0 / last_mass : 1.0;
+            } else {
+                __syncthreads();
+                scale = 1.0;
+            }
+            continue;
+        }
         double* pm = a.pmass + (size_t)G * (1 + rpar);
         if (renorm) {
             const double s = block_sum_f64(part, red);
@@ -523,8 +540,6 @@ __global__ __launch_bounds__(kPThreads) void k_persistent(PersistArgs a) {
             if (!grid_barrier<COH>(a.bar, epoch, g, G, a.flags, a.timeout_ticks)) return;
             if (a.wait && threadIdx.x == 0)  // keep the flags current for later neighbour waits
                 __hip_atomic_store(&a.wflag[g * 32], (unsigned)k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else if (G == 1) {
-            __syncthreads();  // one workgroup: the LDS double buffer needs only its own barrier
         } else {
             if (!neighbour_sync<COH>(a.wflag, wlo, whi, (unsigned)k, g, a.flags, a.timeout_ticks)) return;
         }
@@ -631,7 +646,10 @@ __global__ __launch_bounds__(kPThreads) void k_persistent2(PersistArgs a) {
     extern __shared__ __align__(16) char p2lds[];
     float* X2 = reinterpret_cast<float*>(p2lds);                  // x_k on E2
     float* X1 = X2 + kP2X2;                                       // x_{k+1} on E1
-    uint2* hent = reinterpret_cast<uint2*>(X1 + kP2X1);           // halo entries: (4 (column - e2lo), value bits)
+    // halo entries (4 (column - e2lo), value bits), entry j of halo row h at
+    // [j][h]: consecutive lanes (consecutive halo rows) read consecutive
+    // 8-byte words, free of bank conflicts
+    uint2* hent = reinterpret_cast<uint2*>(X1 + kP2X1);
     __shared__ double red[kPWaves + 1];
     const int G = a.G;
     const int g = logical_block(G);
@@ -668,7 +686,7 @@ __global__ __launch_bounds__(kPThreads) void k_persistent2(PersistArgs a) {
         row_entries<W, CSR>(a, m, cc, vv);
 #pragma unroll
         for (int j = 0; j < W; ++j)
-            hent[h * W + j] = make_uint2(4u * (uint32_t)(cc[j] - e2lo), __builtin_bit_cast(uint32_t, vv[j]));
+            hent[j * kP2Halo + h] = make_uint2(4u * (uint32_t)(cc[j] - e2lo), __builtin_bit_cast(uint32_t, vv[j]));
     }
 
     // ---- k = 0
@@ -816,7 +834,7 @@ __global__ __launch_bounds__(kPThreads) void k_persistent2(PersistArgs a) {
                     for (int u = 0; u < kB; ++u) {
                         const int h = min(tid + (u0 + u) * kPThreads, nh - 1);
 #pragma unroll
-                        for (int j = 0; j < W; ++j) e[u][j] = hent[h * W + j];
+                        for (int j = 0; j < W; ++j) e[u][j] = hent[j * kP2Halo + h];
                     }
 #pragma unroll
                     for (int u = 0; u < kB; ++u)
