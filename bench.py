@@ -46,6 +46,9 @@ def algorithmic_bytes(kind: str, n: int, nnz: int, K: int, L: int) -> float:
     return K * per_jump + (K - L + 1) * 16 * n
 
 
+KERNEL_SOURCES = ("persistent.hip", "gridsync.h")
+
+
 def measured_traffic(kind: str):
     """HBM bytes per launch of the solve kernel from the committed counter
     record (profiles/), used only while the kernel source is unchanged since
@@ -55,9 +58,10 @@ def measured_traffic(kind: str):
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = os.path.join(ROOT, "paper_2312_05647_amd", "csrc", "persistent.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if rec.get("persistent_hip_sha256") != sha:
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:  # the kernel and its grid synchronisation
+        h.update(open(os.path.join(ROOT, "paper_2312_05647_amd", "csrc", name), "rb").read())
+    if rec.get("kernel_sources_sha256") != h.hexdigest():
         return None
     return {"bytes_per_launch": rec["hbm_bytes_per_launch"], "source": os.path.relpath(path, ROOT)}
 
@@ -122,26 +126,31 @@ def bench_small(torch, mjp, reps: int = 20):
     return res
 
 
-def krylov_bytes_per_step(kappa: int, n: int, nnz: int) -> float:
+def krylov_bytes_per_step(kappa: int, n: int, nnz: int, fused: bool) -> float:
     """Bytes the Krylov step streams: per Arnoldi iteration i = 1..kappa-1 the
-    product (12 B per stored entry of A^T, the gathered and written vectors)
-    and three passes that read the i earlier basis vectors (projections,
-    reorthogonalisation, norm) and read/write the new one; then the
-    combination reads kappa vectors and writes one."""
-    per_i = sum(12 * nnz + 8 * n * (3 * i + 6) for i in range(1, kappa))
+    product (12 B per stored entry of A^T, the gathered vector) and three
+    passes that read the i earlier basis vectors (projections,
+    reorthogonalisation, norm); the new vector is written by the product and
+    read/written by the two later passes in the per-pass launches (8 B x 6 per
+    state with the gather), but kept in LDS and written once by the fused
+    step (8 B x 2); then the combination reads kappa vectors and writes one."""
+    own = 2 if fused else 6
+    per_i = sum(12 * nnz + 8 * n * (3 * i + own) for i in range(1, kappa))
     return per_i + 8 * n * (kappa + 1)
 
 
 def bench_krylov(torch, mjp, rp, ci, va, n, reps: int = 3):
     """Krylov propagator (Method #5) on the same N = 10^6 solve, FP64: the
-    paper's step (dt_factor 2) and a converged one (dt_factor 0.5)."""
+    paper's step (dt_factor 2) and a converged one (dt_factor 0.5) with the
+    default per-pass launches, and the paper's step as one cooperative
+    launch per step (the fused variant) for comparison."""
     res = {}
     r0 = torch.zeros(n, dtype=torch.float64, device="cuda")
     r0[0] = 1.0
     out = torch.empty((1, n), dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream()
-    for f in (2.0, 0.5):
-        h = mjp.mjp_krylov_create(rp, ci, va, mjp.mjp_krylov_opts_default(dt_factor=f))
+    for f, variant in ((2.0, mjp.MJP_KRYLOV_AUTO), (0.5, mjp.MJP_KRYLOV_AUTO), (2.0, mjp.MJP_KRYLOV_FUSED)):
+        h = mjp.mjp_krylov_create(rp, ci, va, mjp.mjp_krylov_opts_default(dt_factor=f, variant=variant))
         try:
             info = mjp.mjp_krylov_expv(h, r0, [T_SOLVE], out, stream=stream)
             torch.cuda.synchronize()
@@ -154,11 +163,14 @@ def bench_krylov(torch, mjp, rp, ci, va, n, reps: int = 3):
         finally:
             mjp.mjp_krylov_destroy(h)
         sec = ev0.elapsed_time(ev1) / 1e3 / reps
-        ab = info["steps"] * krylov_bytes_per_step(info["kappa"], n, len(ci))
-        res[f"dt_factor_{f:g}"] = {"ms_per_solve": sec * 1e3, "steps": info["steps"], "kappa": info["kappa"],
-                                   "streamed_GBps": ab / sec / 1e9, "frac_of_hbm_peak": ab / sec / 1e9 / HBM_PEAK_GBS,
-                                   "result": out[0].cpu().numpy()}
-        log(f"[bench] krylov f={f}: {sec * 1e3:.2f} ms/solve, {info['steps']} steps, {ab / sec / 1e9:.0f} GB/s")
+        fused = bool(info["fused"])
+        ab = info["steps"] * krylov_bytes_per_step(info["kappa"], n, len(ci), fused)
+        key = f"dt_factor_{f:g}" + ("" if variant == mjp.MJP_KRYLOV_AUTO else "_fused_step")
+        res[key] = {"ms_per_solve": sec * 1e3, "steps": info["steps"], "kappa": info["kappa"],
+                    "fused_step": fused, "streamed_GBps": ab / sec / 1e9,
+                    "frac_of_hbm_peak": ab / sec / 1e9 / HBM_PEAK_GBS, "result": out[0].cpu().numpy()}
+        log(f"[bench] krylov f={f} fused={fused}: {sec * 1e3:.2f} ms/solve, {info['steps']} steps, "
+            f"{ab / sec / 1e9:.0f} GB/s")
     return res
 
 

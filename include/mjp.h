@@ -420,17 +420,31 @@ typedef struct mjp_krylov mjp_krylov;
 
 typedef struct {
     int32_t kappa;       /* basis size, 2..32 (the paper: 20) */
-    int32_t reserved0;
+    int32_t variant;     /* MJP_KRYLOV_AUTO | MJP_KRYLOV_PASSES | MJP_KRYLOV_FUSED */
     double  dt_factor;   /* > 0 (the paper: 2) */
     int32_t reserved[6];
 } mjp_krylov_opts;
+
+/* How a step runs.  PASSES: one launch per pass over the vectors (three per
+ * Arnoldi iteration, the exponential, the combination).  FUSED: the whole
+ * step in one cooperative launch with grid barriers between the passes
+ * (needs cooperative launch, every workgroup co-resident and N <= 8 rows per
+ * thread of the grid, i.e. N <= 1,048,576 on 256 CUs).  AUTO: PASSES -- a
+ * grid-wide sum inside the fused step (block sums, a grid barrier, every
+ * workgroup adding the partials) costs about what the kernel boundary it
+ * replaces does, so the fused step is slower at N = 10^6.  Both compute the
+ * same arithmetic; the sums across workgroups add the same per-workgroup
+ * partials in different fixed orders, so the two agree to rounding, and
+ * each is deterministic. */
+enum { MJP_KRYLOV_AUTO = 0, MJP_KRYLOV_PASSES = 1, MJP_KRYLOV_FUSED = 2 };
 
 typedef struct {
     double  m_theta;     /* max |a_nn| */
     double  dt;          /* full step length */
     int64_t steps;       /* steps taken over all requested times */
     int32_t kappa;
-    int32_t reserved[5];
+    int32_t fused;       /* 1 if the steps ran as one cooperative launch each */
+    int32_t reserved[4];
 } mjp_krylov_info;
 
 /* Defaults: kappa 20, dt_factor 2. */
@@ -438,8 +452,10 @@ void mjp_krylov_opts_default(mjp_krylov_opts* o);
 
 /* Builds A^T (FP64 sliced ELL) and the kappa x N basis workspace on the
  * current device.  A is checked like mjp_plan_create_csr (conservative rows:
- * MJP_E_NOT_GENERATOR on a negative rate or a row sum off 0).  The handle owns
- * all device memory until mjp_krylov_destroy. */
+ * MJP_E_NOT_GENERATOR on a negative rate or a row sum off 0).  A variant
+ * outside the enum is MJP_E_INVALID_ARG; MJP_KRYLOV_FUSED where the fused
+ * step does not fit is MJP_E_UNSUPPORTED.  The handle owns all device memory
+ * until mjp_krylov_destroy. */
 mjp_status mjp_krylov_create(const mjp_csr* A, const mjp_krylov_opts* opts, mjp_krylov** out);
 void       mjp_krylov_destroy(mjp_krylov* k);
 int32_t    mjp_krylov_n(const mjp_krylov* k);
@@ -448,7 +464,10 @@ int32_t    mjp_krylov_n(const mjp_krylov* k);
  * order, >= 0; one propagation through the sorted times).  rho0_d and out_d
  * are FP64 device vectors owned by the caller; rho0_d is only read.
  * Asynchronous on `stream`; info_h (host, may be NULL) gets the step count.
- * A handle must not be used on two streams at once. */
+ * With info_h on the fused path the call waits for the stream and returns
+ * MJP_E_DEVICE if a grid barrier missed its deadline (every workgroup then
+ * left the step; the output is not valid).  A handle must not be used on two
+ * streams at once. */
 mjp_status mjp_krylov_expv(mjp_krylov* k, const double* rho0_d, int32_t n_t, const double* t_h, double* out_d,
                            mjp_krylov_info* info_h, mjp_stream_t stream);
 

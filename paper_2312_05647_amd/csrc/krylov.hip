@@ -33,6 +33,7 @@
 #include <cstring>
 #include <vector>
 
+#include "gridsync.h"
 #include "internal.h"
 
 namespace mjp {
@@ -61,8 +62,8 @@ struct KryOp {
 // Sum of M per-thread values over the block; result for value m in red[m]
 // (valid after the call for all threads).  Fixed order: wave shuffles, then
 // the waves in index order.
-template <int M>
-__device__ __forceinline__ void block_sums(double (&v)[M], double* red) {
+template <int M, class P>
+__device__ __forceinline__ void block_sums(double (&v)[M], P red) {
     constexpr int kWaves = kKB / 64;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -283,14 +284,11 @@ __global__ __launch_bounds__(kKB) void k_kry_orth_norm(double* __restrict__ Q, i
     }
 }
 
-// E = exp(H dt) for the kappa x kappa Hessenberg H (one workgroup, LDS);
-// c_i = beta * E[i][0] * scale[i] (the coefficient of Qraw[i]).  Clears H
-// for the next step.
-__global__ __launch_bounds__(kKB) void k_kry_expm(double* __restrict__ H, int kappa, double dt,
-                                                  double* __restrict__ sc) {
-    __shared__ double M[kKMax * kKMax], T[kKMax * kKMax], U[kKMax * kKMax];
-    __shared__ double colsum[kKMax];
-    __shared__ int s_sq;
+// T = exp(H dt) for the kappa x kappa Hessenberg H (any memory) by the
+// workgroup, in LDS (M, T, U: kKMax^2 each): Taylor degree kTaylor by
+// Horner after scaling ||H dt||_1 to <= 1/4, then the squarings.
+__device__ void expm_lds(const double* H, int kappa, double dt, double* M, double* T, double* U, double* colsum,
+                         int* s_sq) {
     const int kk = kappa * kappa;
     for (int e = threadIdx.x; e < kk; e += kKB) M[e] = H[e] * dt;
     __syncthreads();
@@ -306,10 +304,10 @@ __global__ __launch_bounds__(kKB) void k_kry_expm(double* __restrict__ H, int ka
         for (int c = 0; c < kappa; ++c) nrm = fmax(nrm, colsum[c]);
         int s = 0;
         while (nrm > 0.25 && s < 1000) { nrm *= 0.5; ++s; }
-        s_sq = s;
+        *s_sq = s;
     }
     __syncthreads();
-    const int s = s_sq;
+    const int s = *s_sq;
     const double sc2 = ldexp(1.0, -s);
     for (int e = threadIdx.x; e < kk; e += kKB) {
         M[e] *= sc2;
@@ -340,9 +338,20 @@ __global__ __launch_bounds__(kKB) void k_kry_expm(double* __restrict__ H, int ka
         for (int e = threadIdx.x; e < kk; e += kKB) T[e] = U[e];
         __syncthreads();
     }
+}
+
+// E = exp(H dt) for the kappa x kappa Hessenberg H (one workgroup, LDS);
+// c_i = beta * E[i][0] * scale[i] (the coefficient of Qraw[i]).  Clears H
+// for the next step.
+__global__ __launch_bounds__(kKB) void k_kry_expm(double* __restrict__ H, int kappa, double dt,
+                                                  double* __restrict__ sc) {
+    __shared__ double M[kKMax * kKMax], T[kKMax * kKMax], U[kKMax * kKMax];
+    __shared__ double colsum[kKMax];
+    __shared__ int s_sq;
+    expm_lds(H, kappa, dt, M, T, U, colsum, &s_sq);
     const double beta = sc[S_BETA];
     for (int i = threadIdx.x; i < kappa; i += kKB) sc[S_C + i] = beta * T[i * kappa + 0] * sc[S_SCALE + i];
-    for (int e = threadIdx.x; e < kk; e += kKB) H[e] = 0.0;
+    for (int e = threadIdx.x; e < kappa * kappa; e += kKB) H[e] = 0.0;
 }
 
 // rho = sum_i c_i Qraw[i] -> Qraw[0] (next start) and out (if given);
@@ -373,6 +382,387 @@ __global__ __launch_bounds__(kKB) void k_kry_combine(double* __restrict__ Q, int
 
 __global__ void k_kry_copy(const double* __restrict__ a, double* __restrict__ b, int64_t n) {
     for (int64_t r = (int64_t)blockIdx.x * kKB + threadIdx.x; r < n; r += (int64_t)gridDim.x * kKB) b[r] = a[r];
+}
+
+// ---- fused step: one cooperative launch per Krylov step
+//
+// The same arithmetic as the per-pass kernels above (classical Gram-Schmidt
+// with one reorthogonalisation, the Taylor exponential, the combination),
+// with grid barriers in place of kernel boundaries.  Block b's thread t owns
+// rows r_k = b kKB + t + k G kKB (k < kKR) -- the rows and the order the
+// per-pass kernels' grid-stride loops give it -- and keeps w of its rows in
+// LDS (wl[k kKB + t]) through the three passes of an Arnoldi iteration,
+// storing q_i once.  Every cross-block sum is: block sums (fixed order), one partial per
+// block with a device-scope store, a grid barrier, then every block adds the
+// G partials in the same fixed order, so all blocks hold identical totals
+// and H, the scales and the exponential need no broadcast (each block keeps
+// them in LDS and computes the exponential itself).  The partial buffers
+// alternate between consecutive sums: a block writes sum s+1's partials only
+// after the barrier of sum s, which every block passes only once done
+// reading the partials of sum s-1.  Gathers of q_{i-1} (rows of other
+// blocks, stored in this launch) are device-scope loads of device-scope
+// stores; everything else a thread reads it wrote itself, or an earlier
+// launch did.
+constexpr int kKR = 8;                    // rows per thread held in registers
+constexpr int kKWaves = kKB / 64;
+constexpr int kKPart = kKMax + 1;         // partials per block and sum, at most
+constexpr int kKBarriersPerIter = 3;
+
+struct KryStepArgs {
+    KryOp op;
+    double* Q;               // kappa x n, raw basis (row 0: this step's start)
+    double* out;             // this step lands on a requested time: rho here, else null
+    double* part;            // [2][kKPart][G] block partials
+    unsigned* bar;           // grid-barrier words, zero at the start of the solve
+    unsigned* flags;         // kFlagBarrierTimeout once a barrier's deadline passed
+    double* sc;              // in: S_BETA, S_SCALE + 0 of the start; out: the next step's
+    int64_t n;
+    double dt;
+    uint64_t timeout_ticks;
+    unsigned epoch0;         // grid barriers of the earlier steps of this solve
+    int kappa;
+};
+
+// Device-scope 64-bit accesses through a buffer descriptor (past the range:
+// loads return 0, stores are dropped).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc64(const double* p, int64_t count) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(p), 0, (int)(8 * count), kRsrcWord3);
+}
+__device__ __forceinline__ double ld_coh(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, kCpolSC1));
+}
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void st_coh(__amdgpu_buffer_rsrc_t r, uint32_t off, double v) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, kCpolSC1);
+}
+
+// tot[m] = sum_{b < G} p[m G + b] for m < count (count <= 64, G <= 256, a
+// multiple of 8): eight threads per m, thread `sub` adding partials sub,
+// sub + 8, ... (all its loads issued together), then a fixed tree over the
+// eight.  Every block computes the same values.
+template <class P>
+__device__ __forceinline__ void grid_totals(const double* p, int G, int count, P tot) {
+    const int sub = threadIdx.x & 7, m = threadIdx.x >> 3;
+    double s = 0.0;
+    if (m < count) {
+        const __amdgpu_buffer_rsrc_t r = rsrc64(p + (size_t)m * G, G);
+        double x[32];
+#pragma unroll
+        for (int u = 0; u < 32; ++u) x[u] = ld_coh(r, (uint32_t)(sub + 8 * u) * 8u);
+#pragma unroll
+        for (int u = 0; u < 32; ++u) s += x[u];
+    }
+    for (int off = 4; off > 0; off >>= 1) s += __shfl_down(s, off, 8);
+    if (sub == 0 && m < count) tot[m] = s;
+    __syncthreads();
+}
+
+// Pointers with their address space spelled out: the iteration bodies are
+// separate functions, where a plain pointer would be generic and every
+// access a flat instruction (which waits on both the memory and the LDS
+// counters).
+typedef __attribute__((address_space(3))) double* lds_d;
+typedef __attribute__((address_space(1))) double* glb_d;
+typedef __attribute__((address_space(1))) const int32_t* glb_ci;
+typedef __attribute__((address_space(1))) const double* glb_cd;
+
+struct KryStepCtx {
+    const KryStepArgs* a;
+    glb_d Q;
+    glb_ci slice_off, col;
+    glb_cd val;
+    int64_t n;
+    int G, blk, kappa;
+    unsigned epoch;
+    int pb;                   // partial buffer of the next sum
+    bool ok;                  // false once a barrier was abandoned
+    lds_d red;                // [kKPart][kKWaves]
+    lds_d tot;                // [kKPart]
+    lds_d Hs;                 // [kappa][kappa] (row stride kappa, as expm_lds reads it)
+    lds_d scale;              // [kKMax]: 1 / ||raw q_j|| (0 after a breakdown)
+    lds_d h1;                 // [kKMax]
+    lds_d coef;               // [kKMax]
+    lds_d wl;                 // [kKR][kKB]: this block's rows of the vector being orthogonalised
+    __attribute__((address_space(3))) int32_t* rb;   // [kKR][kKB]: first entry of the row in A^T
+    __attribute__((address_space(3))) int32_t* rw;   // [kKR][kKB]: entries of the row (0 past n)
+};
+
+// rows of a pass handled together (their loads in flight together): about
+// 16 loads per group for the passes that read I basis vectors per row
+template <int I>
+constexpr int kry_group() { return I >= 16 ? 1 : (I >= 8 ? 2 : (I >= 4 ? 4 : 8)); }
+constexpr int kKSpmvGroup = 4;  // rows per group of the product
+
+__device__ __forceinline__ int64_t kry_row(const KryStepCtx& c, int k) {
+    return (int64_t)c.blk * kKB + threadIdx.x + (int64_t)k * c.G * kKB;
+}
+
+// block sums of v[0..M) (fixed order) -> this block's partials -> grid
+// barrier -> identical totals tot[0..M) in every block
+template <int M>
+__device__ __forceinline__ void kry_sum(KryStepCtx& c, double (&v)[M]) {
+    block_sums<M>(v, c.red);
+    double* p = c.a->part + (size_t)c.pb * kKPart * c.G;
+    if (threadIdx.x < M) put_partial(p + (size_t)threadIdx.x * c.G + c.blk, c.red[threadIdx.x * kKWaves]);
+    c.ok = c.ok && grid_barrier<true>(c.a->bar, ++c.epoch, logical_block(c.G), c.G, c.a->flags, c.a->timeout_ticks);
+    if (c.ok) grid_totals(p, c.G, M, c.tot);
+    c.pb ^= 1;
+}
+
+// Arnoldi iteration I: w = q_{I-1} A, two projections onto q_0..q_{I-1},
+// norm; H column I-1, scale[I]; q_I stored (device scope).
+// (one function per I, not inlined: each gets its own register allocation)
+template <int I>
+__device__ __noinline__ void kry_iter(KryStepCtx& c) {
+    const int64_t n = c.n;
+    const glb_d Q = c.Q;
+    // pass 1: product (rows in groups, entry loads then gathers), then the
+    // first projections (rows in groups of kry_group<I>())
+    {
+        const __amdgpu_buffer_rsrc_t xr = rsrc64((const double*)(Q + (size_t)(I - 1) * n), n);
+        const double xs = c.scale[I - 1];
+        for (int k0 = 0; k0 < kKR; k0 += kKSpmvGroup) {
+            int32_t b[kKSpmvGroup], wdt[kKSpmvGroup];
+            int wmax = 0;
+#pragma unroll
+            for (int u = 0; u < kKSpmvGroup; ++u) {
+                b[u] = c.rb[(k0 + u) * kKB + threadIdx.x];
+                wdt[u] = c.rw[(k0 + u) * kKB + threadIdx.x];
+                wmax = max(wmax, wdt[u]);
+            }
+            double acc[kKSpmvGroup];
+#pragma unroll
+            for (int u = 0; u < kKSpmvGroup; ++u) acc[u] = 0.0;
+            // four entries per row at a time; absent entries weigh 0, which
+            // leaves every row's sum as the per-pass kernel forms it
+            for (int j = 0; j < wmax; j += 4) {
+                int32_t cc[kKSpmvGroup][4];
+                double av[kKSpmvGroup][4], g[kKSpmvGroup][4];
+#pragma unroll
+                for (int u = 0; u < kKSpmvGroup; ++u)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const bool on = j + e < wdt[u];
+                        const int at = on ? b[u] + (j + e) * 64 : 0;
+                        cc[u][e] = on ? c.col[at] : 0;
+                        av[u][e] = on ? c.val[at] : 0.0;
+                    }
+#pragma unroll
+                for (int u = 0; u < kKSpmvGroup; ++u)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) g[u][e] = ld_coh(xr, (uint32_t)cc[u][e] * 8u);
+#pragma unroll
+                for (int u = 0; u < kKSpmvGroup; ++u)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) acc[u] += av[u][e] * g[u][e];
+            }
+#pragma unroll
+            for (int u = 0; u < kKSpmvGroup; ++u) c.wl[(k0 + u) * kKB + threadIdx.x] = xs * acc[u];
+        }
+        double v[I + 1];
+#pragma unroll
+        for (int m = 0; m <= I; ++m) v[m] = 0.0;
+        constexpr int RG = kry_group<I>();
+        for (int k0 = 0; k0 < kKR; k0 += RG) {
+            double qj[RG][I], w[RG];
+            bool live[RG];
+#pragma unroll
+            for (int u = 0; u < RG; ++u) {
+                const int64_t r = kry_row(c, k0 + u);
+                live[u] = r < n;
+                const int64_t rr = live[u] ? r : 0;
+#pragma unroll
+                for (int jj = 0; jj < I; ++jj) qj[u][jj] = Q[(size_t)jj * n + rr];
+                w[u] = c.wl[(k0 + u) * kKB + threadIdx.x];
+            }
+#pragma unroll
+            for (int u = 0; u < RG; ++u) {
+                if (!live[u]) continue;
+#pragma unroll
+                for (int jj = 0; jj < I; ++jj) v[jj] += qj[u][jj] * w[u];
+                v[I] += w[u] * w[u];
+            }
+        }
+        kry_sum<I + 1>(c, v);
+        if (!c.ok) return;
+        if (threadIdx.x < I) c.h1[threadIdx.x] = c.scale[threadIdx.x] * c.tot[threadIdx.x];
+        if (threadIdx.x < I) c.coef[threadIdx.x] = c.h1[threadIdx.x] * c.scale[threadIdx.x];
+        __syncthreads();
+    }
+    const double wn2 = c.tot[I];
+    // pass 2: w -= sum_j h1_j q_j, second projections (the coefficients in
+    // registers)
+    {
+        double v[I], cf[I];
+#pragma unroll
+        for (int m = 0; m < I; ++m) {
+            v[m] = 0.0;
+            cf[m] = c.coef[m];
+        }
+        constexpr int RG = kry_group<I>();
+        for (int k0 = 0; k0 < kKR; k0 += RG) {
+            double qj[RG][I], w[RG];
+            bool live[RG];
+#pragma unroll
+            for (int u = 0; u < RG; ++u) {
+                const int64_t r = kry_row(c, k0 + u);
+                live[u] = r < n;
+                const int64_t rr = live[u] ? r : 0;
+#pragma unroll
+                for (int j = 0; j < I; ++j) qj[u][j] = Q[(size_t)j * n + rr];
+                w[u] = c.wl[(k0 + u) * kKB + threadIdx.x];
+            }
+#pragma unroll
+            for (int u = 0; u < RG; ++u) {
+                if (!live[u]) continue;
+                double x = w[u];
+#pragma unroll
+                for (int j = 0; j < I; ++j) x -= cf[j] * qj[u][j];
+                c.wl[(k0 + u) * kKB + threadIdx.x] = x;
+#pragma unroll
+                for (int j = 0; j < I; ++j) v[j] += qj[u][j] * x;
+            }
+        }
+        __syncthreads();  // every thread has read coef before it is overwritten
+        kry_sum<I>(c, v);
+        if (!c.ok) return;
+        if (threadIdx.x < I) {
+            const double h2 = c.scale[threadIdx.x] * c.tot[threadIdx.x];
+            c.Hs[threadIdx.x * c.kappa + (I - 1)] = c.h1[threadIdx.x] + h2;
+            c.coef[threadIdx.x] = h2 * c.scale[threadIdx.x];
+        }
+        __syncthreads();
+    }
+    // pass 3: w -= sum_j h2_j q_j, norm, q_I stored
+    {
+        const __amdgpu_buffer_rsrc_t qr = rsrc64((const double*)(Q + (size_t)I * n), n);
+        double v[1] = {0.0}, cf[I];
+#pragma unroll
+        for (int m = 0; m < I; ++m) cf[m] = c.coef[m];
+        constexpr int RG = kry_group<I>();
+        for (int k0 = 0; k0 < kKR; k0 += RG) {
+            double qj[RG][I], w[RG];
+            int64_t r[RG];
+#pragma unroll
+            for (int u = 0; u < RG; ++u) {
+                r[u] = kry_row(c, k0 + u);
+                const int64_t rr = r[u] < n ? r[u] : 0;
+#pragma unroll
+                for (int j = 0; j < I; ++j) qj[u][j] = Q[(size_t)j * n + rr];
+                w[u] = c.wl[(k0 + u) * kKB + threadIdx.x];
+            }
+#pragma unroll
+            for (int u = 0; u < RG; ++u) {
+                if (r[u] >= n) continue;
+                double x = w[u];
+#pragma unroll
+                for (int j = 0; j < I; ++j) x -= cf[j] * qj[u][j];
+                st_coh(qr, (uint32_t)r[u] * 8u, x);
+                v[0] += x * x;
+            }
+        }
+        __syncthreads();
+        kry_sum<1>(c, v);
+        if (!c.ok) return;
+        if (threadIdx.x == 0) {
+            const double h = sqrt(c.tot[0]);
+            const bool brk = !(h > kBreakRel * sqrt(wn2));
+            c.Hs[I * c.kappa + (I - 1)] = brk ? 0.0 : h;
+            c.scale[I] = brk ? 0.0 : 1.0 / h;
+        }
+        __syncthreads();
+    }
+}
+
+template <int I>
+__device__ __forceinline__ void kry_iter_dispatch(KryStepCtx& c, int i) {
+    if constexpr (I < kKMax) {
+        if (i == I) {
+            kry_iter<I>(c);
+            return;
+        }
+        kry_iter_dispatch<I + 1>(c, i);
+    }
+}
+
+__global__ __launch_bounds__(kKB) void k_kry_step(KryStepArgs a) {
+    __shared__ double red[kKPart * kKWaves], tot[kKPart];
+    __shared__ double Hs[kKMax * kKMax], scale[kKMax], h1[kKMax], coef[kKMax];
+    __shared__ double M[kKMax * kKMax], T[kKMax * kKMax], U[kKMax * kKMax], colsum[kKMax];
+    __shared__ double wl[kKR * kKB];
+    __shared__ int32_t rb[kKR * kKB], rw[kKR * kKB];
+    __shared__ int s_sq;
+    KryStepCtx c;
+    c.a = &a;
+    c.Q = (glb_d)a.Q;
+    c.slice_off = (glb_ci)a.op.slice_off;
+    c.col = (glb_ci)a.op.col;
+    c.val = (glb_cd)a.op.val;
+    c.n = a.n;
+    c.kappa = a.kappa;
+    c.G = gridDim.x;
+    c.blk = blockIdx.x;
+    c.epoch = a.epoch0;
+    c.pb = 0;
+    c.ok = true;
+    c.red = (lds_d)red;
+    c.tot = (lds_d)tot;
+    c.Hs = (lds_d)Hs;
+    c.scale = (lds_d)scale;
+    c.h1 = (lds_d)h1;
+    c.coef = (lds_d)coef;
+    c.wl = (lds_d)wl;
+    c.rb = (__attribute__((address_space(3))) int32_t*)rb;
+    c.rw = (__attribute__((address_space(3))) int32_t*)rw;
+    const int kappa = a.kappa;
+    // each row's entries in A^T (sliced ELL: slice r / 64, lane r % 64), once per launch
+    for (int k = 0; k < kKR; ++k) {
+        const int64_t r = kry_row(c, k);
+        int32_t b = 0, w = 0;
+        if (r < a.n) {
+            const int64_t sl = r >> 6;
+            b = a.op.slice_off[sl] + (int32_t)(r & 63);
+            w = (a.op.slice_off[sl + 1] - a.op.slice_off[sl]) >> 6;
+        }
+        rb[k * kKB + threadIdx.x] = b;
+        rw[k * kKB + threadIdx.x] = w;
+    }
+    for (int e = threadIdx.x; e < kKMax * kKMax; e += kKB) Hs[e] = 0.0;
+    if (threadIdx.x == 0) scale[0] = a.sc[S_SCALE + 0];
+    const double beta = a.sc[S_BETA];
+    __syncthreads();
+    for (int i = 1; i < kappa; ++i) {
+        kry_iter_dispatch<1>(c, i);
+        if (!c.ok) return;
+    }
+    // exp(H dt) (every block, identical) and the combination of its first column
+    expm_lds(Hs, kappa, a.dt, M, T, U, colsum, &s_sq);
+    if (threadIdx.x < kappa) coef[threadIdx.x] = beta * T[threadIdx.x * kappa + 0] * scale[threadIdx.x];
+    __syncthreads();
+    const int64_t n = a.n;
+    double v[1] = {0.0};
+    for (int k = 0; k < kKR; ++k) {
+        const int64_t r = kry_row(c, k);
+        if (r < n) {
+            double x = 0.0;
+            for (int i = 0; i < kappa; ++i) x += coef[i] * a.Q[(size_t)i * n + r];
+            a.Q[r] = x;
+            if (a.out) a.out[r] = x;
+            v[0] += x * x;
+        }
+    }
+    kry_sum<1>(c, v);
+    if (!c.ok) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const double b2 = sqrt(tot[0]);
+        a.sc[S_BETA] = b2;
+        a.sc[S_SCALE + 0] = b2 > 0.0 ? 1.0 / b2 : 0.0;
+    }
+}
+
+__global__ void k_kry_zero(unsigned* __restrict__ p, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0u;
 }
 
 // per-iteration launch tables (I = 1 .. kKMax - 1)
@@ -411,6 +801,12 @@ struct mjp_krylov {
     DevBuf part2;                // (kKMax + 1) x ngroups FP64 group partials
     DevBuf sc;                   // S_COUNT FP64 scalars
     DevBuf ticket;               // 1 + ngroups arrival counters (zero between kernels)
+    // fused step (one cooperative launch per step), when it fits
+    bool fused = false;
+    int G = 0;                   // its workgroups (a multiple of 8)
+    uint64_t timeout_ticks = 0;  // deadline of one grid barrier
+    DevBuf spart;                // [2][kKPart][G] block partials
+    DevBuf sync;                 // kBarWords barrier words, then the flags word
 };
 
 extern "C" {
@@ -430,6 +826,8 @@ mjp_status mjp_krylov_create(const mjp_csr* A, const mjp_krylov_opts* opts, mjp_
     MJP_CHECK(opts->kappa >= 2 && opts->kappa <= kKMax, MJP_E_INVALID_ARG, "kappa must be in [2, %d]", kKMax);
     MJP_CHECK(std::isfinite(opts->dt_factor) && opts->dt_factor > 0.0, MJP_E_INVALID_ARG,
               "dt_factor must be finite and > 0");
+    MJP_CHECK(opts->variant >= MJP_KRYLOV_AUTO && opts->variant <= MJP_KRYLOV_FUSED, MJP_E_INVALID_ARG,
+              "variant must be MJP_KRYLOV_AUTO, _PASSES or _FUSED");
     double m_theta = 0.0;
     std::vector<double> diag;
     mjp_status st = check_generator_csr(A, 0, &m_theta, &diag);
@@ -505,6 +903,33 @@ mjp_status mjp_krylov_create(const mjp_csr* A, const mjp_krylov_opts* opts, mjp_
     if ((st = up(k->H, zeros.data(), sizeof(double) * kKMax * kKMax)) ||
         (st = up(k->ticket, z32.data(), sizeof(unsigned) * z32.size())))
         return bail(st);
+    // the fused step (only when asked for: AUTO takes the per-pass launches,
+    // which measured faster): the grid of the per-pass kernels rounded up to
+    // a multiple of 8 (the barrier's groups), every workgroup co-resident, at
+    // most kKR rows per thread, byte offsets of a vector within 31 bits
+    if (opts->variant == MJP_KRYLOV_FUSED) {
+        int coop = 0, ncu = 0, per_cu = 0, khz = 0;
+        const int64_t pass_blocks = std::min<int64_t>(nblk, kMaxBlocks);
+        const int64_t G = (std::max<int64_t>(pass_blocks, 8) + 7) / 8 * 8;
+        bool fits = hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, k->device) == hipSuccess &&
+                    coop && hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, k->device) == hipSuccess &&
+                    hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_kry_step),
+                                                                 kKB, 0) == hipSuccess &&
+                    per_cu >= 1 && G <= (int64_t)ncu * per_cu && G <= 256 && (int64_t)n <= G * kKB * kKR &&
+                    8 * (int64_t)n < ((int64_t)1 << 31);
+        if (!fits && opts->variant == MJP_KRYLOV_FUSED)
+            return bail(fail(MJP_E_UNSUPPORTED, "the fused Krylov step does not fit this operator or device"));
+        if (fits) {
+            if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, k->device) != hipSuccess || khz <= 0)
+                khz = 100000;
+            k->fused = true;
+            k->G = (int)G;
+            k->timeout_ticks = (uint64_t)khz * 1000ull * 2ull;  // 2 s for one barrier
+            if ((st = k->spart.reserve(sizeof(double) * 2 * kKPart * (size_t)G)) ||
+                (st = k->sync.reserve(sizeof(unsigned) * (kBarWords + 1))))
+                return bail(st);
+        }
+    }
     *out = k;
     return MJP_OK;
 }
@@ -523,6 +948,8 @@ void mjp_krylov_destroy(mjp_krylov* k) {
     k->part2.release();
     k->sc.release();
     k->ticket.release();
+    k->spart.release();
+    k->sync.release();
     if (restore) (void)hipSetDevice(prev);
     delete k;
 }
@@ -558,6 +985,20 @@ mjp_status mjp_krylov_expv(mjp_krylov* k, const double* rho0_d, int32_t n_t, con
     const double dt = k->m_theta > 0.0 ? k->dt_factor * kappa / k->m_theta : INFINITY;
 
     hipLaunchKernelGGL(k_kry_start, dim3(nblk), dim3(kKB), 0, st, rho0_d, Q, n, tree, sc);
+    KryStepArgs fa{};
+    if (k->fused) {
+        fa.op = op;
+        fa.Q = Q;
+        fa.part = k->spart.as<double>();
+        fa.bar = k->sync.as<unsigned>();
+        fa.flags = fa.bar + kBarWords;
+        fa.sc = sc;
+        fa.n = n;
+        fa.timeout_ticks = k->timeout_ticks;
+        fa.kappa = kappa;
+        hipLaunchKernelGGL(k_kry_zero, dim3((kBarWords + 1 + 255) / 256), dim3(256), 0, st, fa.bar, kBarWords + 1);
+    }
+    const unsigned barriers_per_step = kKBarriersPerIter * (unsigned)(kappa - 1) + 1u;
     double tau = 0.0;
     int64_t steps = 0;
     for (int idx : order) {
@@ -570,6 +1011,17 @@ mjp_status mjp_krylov_expv(mjp_krylov* k, const double* rho0_d, int32_t n_t, con
         while (t - tau > 0.0) {
             const double h = std::min(dt, t - tau);
             const bool lands = h == t - tau;
+            if (k->fused) {
+                fa.out = lands ? outj : nullptr;
+                fa.dt = h;
+                fa.epoch0 = (unsigned)steps * barriers_per_step;
+                void* args[] = {&fa};
+                MJP_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_kry_step), dim3(k->G), dim3(kKB),
+                                                   args, 0, st));
+                tau = lands ? t : tau + h;
+                ++steps;
+                continue;
+            }
             for (int i = 1; i < kappa; ++i) {
                 hipLaunchKernelGGL(KryTables::spmv[i - 1], dim3(nblk), dim3(kKB), 0, st, op, Q, n, tree, sc);
                 hipLaunchKernelGGL(KryTables::dot[i - 1], dim3(nblk), dim3(kKB), 0, st, Q, n, kappa, H, tree, sc);
@@ -589,6 +1041,13 @@ mjp_status mjp_krylov_expv(mjp_krylov* k, const double* rho0_d, int32_t n_t, con
         info_h->dt = dt;
         info_h->steps = steps;
         info_h->kappa = kappa;
+        info_h->fused = k->fused ? 1 : 0;
+        if (k->fused && steps > 0) {
+            unsigned flags = 0;
+            MJP_HIP(hipMemcpyAsync(&flags, k->sync.as<unsigned>() + kBarWords, sizeof flags, hipMemcpyDeviceToHost, st));
+            MJP_HIP(hipStreamSynchronize(st));
+            MJP_CHECK(!(flags & kFlagBarrierTimeout), MJP_E_DEVICE, "a grid barrier of the fused Krylov step timed out");
+        }
     }
     return MJP_OK;
 }

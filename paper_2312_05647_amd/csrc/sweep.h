@@ -3,6 +3,7 @@
 
 #include <vector>
 
+#include "gridsync.h"
 #include "internal.h"
 
 namespace mjp {
@@ -26,8 +27,6 @@ struct AllTimes {
 // scalar slots in plan->scal (doubles)
 enum { S_MASS0 = 0, S_MASSK = 1, S_FLAGS = 2, S_SCALE = 3, S_COUNT = 8 };
 
-// bit of the flags word raised when a persistent grid barrier timed out
-constexpr unsigned kFlagBarrierTimeout = 0x80000000u;
 
 struct PersistCfg {
     int R = 0, W = 0, G = 0;

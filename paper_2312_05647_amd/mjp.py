@@ -25,6 +25,7 @@ MJP_CONSERVATIVE, MJP_LEAKY = 0, 1
 MJP_VARIANT_AUTO, MJP_VARIANT_STEPWISE, MJP_VARIANT_PERSISTENT, MJP_VARIANT_PERSISTENT_FENCED = 0, 1, 2, 3
 MJP_VARIANT_PERSISTENT_ONEJUMP = 4
 MJP_PATH_STEPWISE, MJP_PATH_PERSISTENT, MJP_PATH_PERSISTENT_FENCED, MJP_PATH_PERSISTENT_TWOJUMP = 1, 2, 3, 4
+MJP_KRYLOV_AUTO, MJP_KRYLOV_PASSES, MJP_KRYLOV_FUSED = 0, 1, 2
 MJP_MODEL_BD, MJP_MODEL_CASCADE2, MJP_MODEL_TWOSTATE, MJP_MODEL_AUTOREG = 0, 1, 2, 3
 MJP_FLAG_NAN, MJP_FLAG_NEG, MJP_FLAG_UNDERFLOW_OBS, MJP_FLAG_OUT_OF_GRID, MJP_FLAG_K_LIMIT = 1, 2, 4, 8, 16
 MJP_LL_CLASSES, MJP_LL_MAX_SHAPES = 4, 16
@@ -77,13 +78,13 @@ class mjp_train_cfg(ctypes.Structure):
 
 
 class mjp_krylov_opts(ctypes.Structure):
-    _fields_ = [("kappa", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("dt_factor", ctypes.c_double),
+    _fields_ = [("kappa", ctypes.c_int32), ("variant", ctypes.c_int32), ("dt_factor", ctypes.c_double),
                 ("reserved", ctypes.c_int32 * 6)]
 
 
 class mjp_krylov_info(ctypes.Structure):
     _fields_ = [("m_theta", ctypes.c_double), ("dt", ctypes.c_double), ("steps", ctypes.c_int64),
-                ("kappa", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("kappa", ctypes.c_int32), ("fused", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}

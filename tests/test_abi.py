@@ -274,6 +274,8 @@ def test_surrogate_load_rejects_foreign_file(tmp_path):
     (dict(kappa=33), mjp.MJP_E_INVALID_ARG),
     (dict(dt_factor=0.0), mjp.MJP_E_INVALID_ARG),
     (dict(dt_factor=float("nan")), mjp.MJP_E_INVALID_ARG),
+    (dict(variant=3), mjp.MJP_E_INVALID_ARG),
+    (dict(variant=-1), mjp.MJP_E_INVALID_ARG),
 ])
 def test_krylov_option_validation(kw, expect):
     assert status_of(mjp.mjp_krylov_create, *GOOD, mjp.mjp_krylov_opts_default(**kw)) == expect

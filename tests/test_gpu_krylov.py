@@ -15,6 +15,10 @@ the C ABI.
 * At full size (N = 10^6) with dt_factor = 0.5, where the method converges
   (L1 ~1e-11 against the exact propagator in the oracle pins), against the
   exact R-MJP oracle: L1 <= 1e-9.
+* Both step variants (one launch per pass, and the fused step in one
+  cooperative launch) meet these bars; they add the cross-workgroup
+  partials in different orders, so they agree with each other to rounding
+  (relative 1e-12), and each is deterministic.
 """
 import sys
 
@@ -30,6 +34,7 @@ pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
 
 BAR = 1e-10
+VARIANTS = [mjp.MJP_KRYLOV_PASSES, mjp.MJP_KRYLOV_FUSED]
 
 
 def rounding_sensitivity(orc, rp, ci, va, rho0, times, trials=2, **opts):
@@ -81,12 +86,14 @@ def model_csr(model, theta, dims):
     return mjp.mjp_model_csr(mjp.make_model(model, theta, dims))
 
 
+@pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("f", [2.0, 1.0, 0.5])
-def test_birth_death_vs_oracle(orc, f):
+def test_birth_death_vs_oracle(orc, f, variant):
     rp, ci, va = model_csr(0, [500.0, 1.0], [1000])
     A = orc.CSR.from_arrays(rp, ci, va)
-    say(f"[gpu] krylov birth-death N=1000 f={f}")
-    got, info = gpu_krylov(rp, ci, va, synth.delta(1000), [1.0], dt_factor=f)
+    say(f"[gpu] krylov birth-death N=1000 f={f} variant={variant}")
+    got, info = gpu_krylov(rp, ci, va, synth.delta(1000), [1.0], dt_factor=f, variant=variant)
+    assert info["fused"] == (variant == mjp.MJP_KRYLOV_FUSED)
     ref, rinfo = krylov.krylov_expv(A, synth.delta(1000), [1.0], dt_factor=f)
     assert info["steps"] == rinfo["steps"]
     l1 = np.abs(got - ref).sum()
@@ -95,13 +102,14 @@ def test_birth_death_vs_oracle(orc, f):
     assert l1 <= bar
 
 
-def test_cascade_several_times_vs_oracle(orc):
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_cascade_several_times_vs_oracle(orc, variant):
     rp, ci, va = model_csr(1, [20.0, 1.0, 0.5, 0.5], [40, 30])
     A = orc.CSR.from_arrays(rp, ci, va)
     rho0 = synth.random_prob(1200, 4)
     times = [3.0, 0.0, 0.5, 0.5, 7.25]
-    say("[gpu] krylov cascade 40x30, 5 times")
-    got, info = gpu_krylov(rp, ci, va, rho0, times)
+    say(f"[gpu] krylov cascade 40x30, 5 times, variant={variant}")
+    got, info = gpu_krylov(rp, ci, va, rho0, times, variant=variant)
     ref, _ = krylov.krylov_expv(A, rho0, times)
     bar = paper_step_bar(orc, rp, ci, va, rho0, times)   # the default step is the paper's (dt_factor 2)
     for j in range(len(times)):
@@ -111,8 +119,9 @@ def test_cascade_several_times_vs_oracle(orc):
     assert np.array_equal(got[1], rho0)
 
 
+@pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("n,seed", [(1, 1), (2, 2), (63, 3), (65, 5), (257, 6), (1000, 7), (4097, 8), (33000, 10)])
-def test_random_generators_ragged_sizes(orc, n, seed):
+def test_random_generators_ragged_sizes(orc, n, seed, variant):
     if n == 1:
         rp, ci, va = np.array([0, 1]), np.array([0]), np.array([0.0])
     else:
@@ -120,8 +129,8 @@ def test_random_generators_ragged_sizes(orc, n, seed):
     A = orc.CSR.from_arrays(rp, ci, va)
     rho0 = synth.random_prob(n, seed + 50)
     times = [0.05, 0.7]
-    say(f"[gpu] krylov random n={n}")
-    got, info = gpu_krylov(rp, ci, va, rho0, times, kappa=12, dt_factor=1.0)
+    say(f"[gpu] krylov random n={n} variant={variant}")
+    got, info = gpu_krylov(rp, ci, va, rho0, times, kappa=12, dt_factor=1.0, variant=variant)
     ref, _ = krylov.krylov_expv(A, rho0, times, kappa=12, dt_factor=1.0)
     for j in range(len(times)):
         assert np.abs(got[j] - ref[j]).sum() <= BAR * max(1.0, n / 1000), (n, j)
@@ -136,11 +145,53 @@ def test_invariant_subspace_exact(orc):
         assert np.abs(got[j] - rho0 @ sl.expm(A.dense() * t)).max() < 1e-12
 
 
-def test_deterministic():
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_deterministic(variant):
     rp, ci, va = model_csr(1, [60.0, 1.0, 0.7, 0.4], [120, 150])
-    a, _ = gpu_krylov(rp, ci, va, synth.delta(18000), [0.4, 1.5])
-    b, _ = gpu_krylov(rp, ci, va, synth.delta(18000), [0.4, 1.5])
+    a, _ = gpu_krylov(rp, ci, va, synth.delta(18000), [0.4, 1.5], variant=variant)
+    b, _ = gpu_krylov(rp, ci, va, synth.delta(18000), [0.4, 1.5], variant=variant)
     assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("kappa", [2, 20, 32])
+def test_fused_matches_passes(kappa):
+    """The fused step against the per-pass launches on the same operator
+    (several times, so several steps and a shortened last step): equal to
+    rounding; AUTO takes the per-pass launches."""
+    rp, ci, va = model_csr(1, [60.0, 1.0, 0.7, 0.4], [120, 150])
+    rho0 = synth.random_prob(18000, 9)
+    times = [0.4, 1.5, 0.0]
+    say(f"[gpu] krylov fused vs passes, kappa={kappa}")
+    a, ia = gpu_krylov(rp, ci, va, rho0, times, kappa=kappa, variant=mjp.MJP_KRYLOV_PASSES)
+    b, ib = gpu_krylov(rp, ci, va, rho0, times, kappa=kappa, variant=mjp.MJP_KRYLOV_FUSED)
+    c, ic = gpu_krylov(rp, ci, va, rho0, times, kappa=kappa)
+    assert (ia["fused"], ib["fused"], ic["fused"]) == (0, 1, 0)
+    assert ia["steps"] == ib["steps"] > 1
+    assert np.array_equal(a, c)
+    for j in range(len(times)):
+        rel = np.abs(a[j] - b[j]).sum() / np.abs(a[j]).sum()
+        say(f"    t={times[j]}: relative L1 fused vs passes {rel:.2e}")
+        assert rel <= 1e-12, (j, rel)
+
+
+def test_fused_limit():
+    """An operator with more rows than the fused step holds (8 per thread of
+    256 x 512): FUSED is refused, AUTO runs (per-pass launches)."""
+    rp, ci, va = model_csr(1, [20.0, 1.0, 0.5, 0.5], [1030, 1030])
+    with pytest.raises(mjp.MjpError):
+        mjp.mjp_krylov_create(rp, ci, va, mjp.mjp_krylov_opts_default(variant=mjp.MJP_KRYLOV_FUSED))
+    n = 1030 * 1030
+    h = mjp.mjp_krylov_create(rp, ci, va, mjp.mjp_krylov_opts_default(kappa=4))
+    try:
+        r0 = torch.zeros(n, dtype=torch.float64, device="cuda")
+        r0[0] = 1.0
+        out = torch.empty((1, n), dtype=torch.float64, device="cuda")
+        info = mjp.mjp_krylov_expv(h, r0, [0.01], out)
+        torch.cuda.synchronize()
+        assert info["fused"] == 0
+        assert abs(float(out.sum()) - 1.0) < 1e-12
+    finally:
+        mjp.mjp_krylov_destroy(h)
 
 
 def test_full_size_converged_vs_exact(orc):
@@ -151,11 +202,13 @@ def test_full_size_converged_vs_exact(orc):
     A = orc.CSR.from_arrays(rp, ci, va)
     say("[oracle] cascade 1000x1000 t=1 (exact)")
     ref, _ = orc.expv(A, synth.delta(10 ** 6), 1.0, eps_right=1e-14)
-    say("[gpu] krylov cascade 1000x1000 f=0.5")
-    got, info = gpu_krylov(rp, ci, va, synth.delta(10 ** 6), [1.0], dt_factor=0.5)
-    l1 = np.abs(got[0] - ref).sum()
-    say(f"    steps {info['steps']}  L1 vs exact {l1:.3e}")
-    assert l1 <= 1e-9
+    for variant in VARIANTS:
+        say(f"[gpu] krylov cascade 1000x1000 f=0.5 variant={variant}")
+        got, info = gpu_krylov(rp, ci, va, synth.delta(10 ** 6), [1.0], dt_factor=0.5, variant=variant)
+        assert info["fused"] == (variant == mjp.MJP_KRYLOV_FUSED)   # N = 10^6 fits the fused step on 256 CUs
+        l1 = np.abs(got[0] - ref).sum()
+        say(f"    steps {info['steps']}  L1 vs exact {l1:.3e}")
+        assert l1 <= 1e-9
     got2, info2 = gpu_krylov(rp, ci, va, synth.delta(10 ** 6), [1.0, 0.0])
     assert np.array_equal(got2[1], synth.delta(10 ** 6))  # t = 0 copies rho(0) through every row
     assert abs(got2[0].sum() - 1.0) < 1e-10
