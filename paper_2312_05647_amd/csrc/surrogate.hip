@@ -337,15 +337,32 @@ __global__ void k_adam(AdamArgs a) {
     const int64_t nw = (int64_t)d.out * d.in;
     float g;
     int o = -1, i = -1;
+    // the partials are added in index order; eight loads are in flight at a
+    // time (an out-of-range slot loads the group's first partial and adds 0)
     if (q < nw) {
         o = (int)(q / d.in);
         i = (int)(q - (int64_t)o * d.in);
         g = 0.f;
-        for (int s = 0; s < a.splits; ++s) g += d.P[((size_t)s * d.npad + o) * d.kpad + i];
+        for (int s0 = 0; s0 < a.splits; s0 += 8) {
+            float x[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int sl = s0 + u < a.splits ? s0 + u : s0;
+                x[u] = d.P[((size_t)sl * d.npad + o) * d.kpad + i];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) g += s0 + u < a.splits ? x[u] : 0.f;
+        }
     } else {
         const int c = (int)(q - nw);
         g = 0.f;
-        for (int k = 0; k < d.nbp; ++k) g += d.bp[(size_t)k * d.bps + c];
+        for (int k0 = 0; k0 < d.nbp; k0 += 8) {
+            float x[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) x[u] = d.bp[(size_t)(k0 + u < d.nbp ? k0 + u : k0) * d.bps + c];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) g += k0 + u < d.nbp ? x[u] : 0.f;
+        }
     }
     if (a.grad_out) {
         a.grad_out[p] = g;
