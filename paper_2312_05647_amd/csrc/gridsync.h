@@ -14,6 +14,11 @@ namespace mjp {
 // bit of a flags word raised when a grid barrier timed out
 constexpr unsigned kFlagBarrierTimeout = 0x80000000u;
 
+// A waiting wave re-reads what it waits for every spin, but the abort word
+// (another device-scope round trip) and its wall-clock deadline only every
+// kAbortCheckEvery spins, so a spin costs one memory round trip.
+constexpr unsigned kAbortCheckEvery = 16;
+
 __device__ __forceinline__ int logical_block(int G) {
     // workgroups are dispatched round-robin over the 8 XCDs; renumber so
     // that XCD x runs logical blocks [x*G/8, (x+1)*G/8)
@@ -80,8 +85,10 @@ __device__ __forceinline__ bool grid_barrier(unsigned* w, unsigned epoch, int g,
             }
         }
         const uint64_t t0 = wall_clock64();
+        unsigned spins = 0;
         while (__hip_atomic_load(&w[(9 + grp) * 64], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
             __builtin_amdgcn_s_sleep(1);
+            if (++spins % kAbortCheckEvery != 0) continue;
             if (__hip_atomic_load(flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kFlagBarrierTimeout) {
                 aborted = 1;
                 break;

@@ -128,8 +128,10 @@ __device__ __forceinline__ bool neighbour_sync(unsigned* wflag, int lo, int hi, 
         bool bad = false;
         if (h <= hi && h != g) {
             const uint64_t t0 = wall_clock64();
+            unsigned spins = 0;
             while (__hip_atomic_load(&wflag[h * 32], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < k) {
                 __builtin_amdgcn_s_sleep(1);
+                if (++spins % kAbortCheckEvery != 0) continue;
                 if (__hip_atomic_load(flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kFlagBarrierTimeout) {
                     bad = true;
                     break;
