@@ -101,7 +101,11 @@ typedef struct {
     int32_t lump;          /* 1 = add (1 - sum_{L..K} w_k) rho(0)B^K (last line of Algorithm 2) */
     int64_t k_cap;         /* largest K accepted; larger -> MJP_E_K_LIMIT */
     int32_t variant;       /* MJP_VARIANT_* */
-    int32_t reserved[7];   /* must be zero */
+    int32_t barrier_timeout_us; /* deadline of one grid or neighbour wait of the persistent
+                              kernels: 0 = 2 s; > 0 microseconds; < 0: a wait that has
+                              to spin gives up at once (exercises the abort path: every
+                              workgroup leaves, and a call with info_h fails) */
+    int32_t reserved[6];   /* must be zero */
 } mjp_opts;
 
 /* Fill *o with the defaults: omega_factor 1.1, tol 1e-9, MJP_K_TOL,
@@ -218,7 +222,10 @@ int32_t mjp_plan_n(const mjp_plan* p);
  *   out_d    [n_t x N] FP32 on the device; row j is rho(t_h[j]).  Must not
  *            overlap rho0_d.
  *   info_h   [n_t] or NULL.  Non-NULL makes the call synchronous and returns
- *            MJP_E_NUMERIC if a NaN/Inf or negative entry was detected.
+ *            MJP_E_NUMERIC if a NaN/Inf or negative entry was detected, or
+ *            MJP_E_DEVICE if a wait of the persistent kernel missed its
+ *            deadline (opts.barrier_timeout_us; every workgroup then left the
+ *            kernel and out_d is not valid).
  * t = 0 and Omega = 0 (all rates zero) return rho0 unchanged.
  * Precision: the products run in FP32; the weighted series is accumulated
  * with Kahan compensation in FP32; the Poisson weights are FP64. */

@@ -16,7 +16,9 @@ constexpr unsigned kFlagBarrierTimeout = 0x80000000u;
 
 // A waiting wave re-reads what it waits for every spin, but the abort word
 // (another device-scope round trip) and its wall-clock deadline only every
-// kAbortCheckEvery spins, so a spin costs one memory round trip.
+// kAbortCheckEvery spins, so a spin costs one memory round trip.  A deadline
+// of 0 ticks is checked at every spin (a wait that has to spin gives up at
+// once: the host's way to exercise the abort path).
 constexpr unsigned kAbortCheckEvery = 16;
 
 __device__ __forceinline__ int logical_block(int G) {
@@ -88,7 +90,7 @@ __device__ __forceinline__ bool grid_barrier(unsigned* w, unsigned epoch, int g,
         unsigned spins = 0;
         while (__hip_atomic_load(&w[(9 + grp) * 64], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
             __builtin_amdgcn_s_sleep(1);
-            if (++spins % kAbortCheckEvery != 0) continue;
+            if (++spins % kAbortCheckEvery != 0 && timeout_ticks != 0) continue;
             if (__hip_atomic_load(flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kFlagBarrierTimeout) {
                 aborted = 1;
                 break;

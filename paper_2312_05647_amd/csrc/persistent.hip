@@ -131,7 +131,7 @@ __device__ __forceinline__ bool neighbour_sync(unsigned* wflag, int lo, int hi, 
             unsigned spins = 0;
             while (__hip_atomic_load(&wflag[h * 32], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < k) {
                 __builtin_amdgcn_s_sleep(1);
-                if (++spins % kAbortCheckEvery != 0) continue;
+                if (++spins % kAbortCheckEvery != 0 && timeout_ticks != 0) continue;
                 if (__hip_atomic_load(flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kFlagBarrierTimeout) {
                     bad = true;
                     break;
@@ -1170,7 +1170,8 @@ mjp_status launch_persistent(mjp_plan* p, const PersistCfg& cfg, const float* rh
         int khz = 0;
         if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, p->device) != hipSuccess || khz <= 0)
             khz = 100000;
-        a.timeout_ticks = (uint64_t)khz * 1000ull * 2ull;  // 2 s for one barrier
+        const int32_t us = p->opts.barrier_timeout_us;  // 0: 2 s; < 0: give up at the first spin
+        a.timeout_ticks = us == 0 ? (uint64_t)khz * 1000ull * 2ull : (us < 0 ? 0ull : (uint64_t)khz * (uint64_t)us / 1000ull);
     }
     a.at = at;
     for (int j = 0; j < at.n; ++j) a.slot[j] = slot[(size_t)j];

@@ -142,7 +142,7 @@ mjp_status check_opts(const mjp_opts* o) {
     MJP_CHECK(o->k_cap >= 1 && o->k_cap <= (int64_t)1 << 30, MJP_E_INVALID_ARG, "k_cap out of range");
     MJP_CHECK(o->variant >= MJP_VARIANT_AUTO && o->variant <= MJP_VARIANT_PERSISTENT_ONEJUMP, MJP_E_INVALID_ARG,
               "bad variant %d", o->variant);
-    for (int i = 0; i < 7; ++i) MJP_CHECK(o->reserved[i] == 0, MJP_E_INVALID_ARG, "reserved fields must be 0");
+    for (int i = 0; i < 6; ++i) MJP_CHECK(o->reserved[i] == 0, MJP_E_INVALID_ARG, "reserved fields must be 0");
     return MJP_OK;
 }
 

@@ -40,7 +40,8 @@ class MjpError(RuntimeError):
 class mjp_opts(ctypes.Structure):
     _fields_ = [("omega_factor", ctypes.c_double), ("tol", ctypes.c_double), ("k_rule", ctypes.c_int32),
                 ("truncation", ctypes.c_int32), ("renorm_every", ctypes.c_int32), ("lump", ctypes.c_int32),
-                ("k_cap", ctypes.c_int64), ("variant", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+                ("k_cap", ctypes.c_int64), ("variant", ctypes.c_int32), ("barrier_timeout_us", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
 
 
 class mjp_info(ctypes.Structure):

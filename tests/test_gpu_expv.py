@@ -429,3 +429,38 @@ def test_twojump_bit_identical(case, renorm):
     assert paths == [want, mjp.MJP_PATH_PERSISTENT, mjp.MJP_PATH_PERSISTENT_FENCED]
     for r in res[1:]:
         assert np.array_equal(res[0], r)
+
+
+@pytest.mark.parametrize("variant,dims", [(mjp.MJP_VARIANT_PERSISTENT, (300, 300)),
+                                          (mjp.MJP_VARIANT_PERSISTENT_FENCED, (300, 300)),
+                                          (mjp.MJP_VARIANT_AUTO, (1000, 1000))])
+def test_wait_deadline_abort_path(variant, dims):
+    """The abort path of the persistent kernels, forced from the host: with
+    barrier_timeout_us < 0 every grid or neighbour wait that has to spin
+    gives up at once, raises the abort flag, and every workgroup leaves the
+    kernel; the call with info reports MJP_E_DEVICE.  A solve with the
+    default deadline afterwards is bit-identical to one before (nothing is
+    left behind).  Cases: one jump per synchronisation (176 workgroups, both
+    memory protocols) and two jumps (N = 10^6)."""
+    S1, S2 = dims
+    n = S1 * S2
+    rp, ci, va = mjp.mjp_model_csr(mjp.make_model(mjp.MJP_MODEL_CASCADE2, [200.0, 1.0, 0.5, 0.5], [S1, S2]))
+    rho0 = np.zeros(n, np.float32)
+    rho0[0] = 1.0
+
+    def solve(**opts):
+        plan = mjp.mjp_plan_create_csr(rp, ci, va, mjp.mjp_opts_default(variant=variant, **opts))
+        try:
+            return gpu_expv(plan, rho0, [1.0], info=True)
+        finally:
+            mjp.mjp_plan_destroy(plan)
+
+    say(f"[gpu] wait-deadline abort path: variant {variant}, {S1}x{S2}")
+    before, inf = solve()
+    assert inf[0]["path"] in (mjp.MJP_PATH_PERSISTENT, mjp.MJP_PATH_PERSISTENT_FENCED,
+                              mjp.MJP_PATH_PERSISTENT_TWOJUMP)
+    with pytest.raises(mjp.MjpError) as e:
+        solve(barrier_timeout_us=-1)
+    assert e.value.status == mjp.MJP_E_DEVICE and "timed out" in str(e.value)
+    after, _ = solve()
+    assert np.array_equal(before, after)
