@@ -102,9 +102,10 @@ typedef struct {
     int64_t k_cap;         /* largest K accepted; larger -> MJP_E_K_LIMIT */
     int32_t variant;       /* MJP_VARIANT_* */
     int32_t barrier_timeout_us; /* deadline of one grid or neighbour wait of the persistent
-                              kernels: 0 = 2 s; > 0 microseconds; < 0: a wait that has
-                              to spin gives up at once (exercises the abort path: every
-                              workgroup leaves, and a call with info_h fails) */
+                              kernels: 0 = 2 s; > 0 microseconds.  < 0 exercises the
+                              abort path: the two-jump kernel runs in a form whose waits
+                              give up at their first unready read, so every workgroup
+                              leaves and a call with info_h fails (other paths keep 2 s) */
     int32_t reserved[6];   /* must be zero */
 } mjp_opts;
 

@@ -16,9 +16,10 @@ constexpr unsigned kFlagBarrierTimeout = 0x80000000u;
 
 // A waiting wave re-reads what it waits for every spin, but the abort word
 // (another device-scope round trip) and its wall-clock deadline only every
-// kAbortCheckEvery spins, so a spin costs one memory round trip.  A deadline
-// of 0 ticks is checked at every spin (a wait that has to spin gives up at
-// once: the host's way to exercise the abort path).
+// kAbortCheckEvery spins, so a spin costs one memory round trip.
+// FORCE (a separate instantiation, used only when the host asks for it):
+// a wait whose first read finds the word not yet set gives up at once,
+// raising the abort flag -- the host's way to exercise the abort path.
 constexpr unsigned kAbortCheckEvery = 16;
 
 __device__ __forceinline__ int logical_block(int G) {
@@ -63,7 +64,7 @@ constexpr int kBarWords = 17 * 64;
 // removes most of the contention of a single counter hit by every
 // workgroup.  Returns false if the sweep was aborted (a wait exceeded its
 // wall-clock deadline somewhere); every workgroup then leaves the kernel.
-template <bool COH>
+template <bool COH, bool FORCE = false>
 __device__ __forceinline__ bool grid_barrier(unsigned* w, unsigned epoch, int g, int G, unsigned* flags,
                                              uint64_t timeout_ticks) {
     __shared__ int aborted;
@@ -86,19 +87,26 @@ __device__ __forceinline__ bool grid_barrier(unsigned* w, unsigned epoch, int g,
                     __hip_atomic_store(&w[(9 + x) * 64], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
-        const uint64_t t0 = wall_clock64();
-        unsigned spins = 0;
-        while (__hip_atomic_load(&w[(9 + grp) * 64], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
-            __builtin_amdgcn_s_sleep(1);
-            if (++spins % kAbortCheckEvery != 0 && timeout_ticks != 0) continue;
-            if (__hip_atomic_load(flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kFlagBarrierTimeout) {
-                aborted = 1;
-                break;
-            }
-            if (wall_clock64() - t0 > timeout_ticks) {
+        if constexpr (FORCE) {
+            if (__hip_atomic_load(&w[(9 + grp) * 64], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
                 __hip_atomic_fetch_or(flags, kFlagBarrierTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 aborted = 1;
-                break;
+            }
+        } else {
+            const uint64_t t0 = wall_clock64();
+            unsigned spins = 0;
+            while (__hip_atomic_load(&w[(9 + grp) * 64], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins % kAbortCheckEvery != 0) continue;
+                if (__hip_atomic_load(flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kFlagBarrierTimeout) {
+                    aborted = 1;
+                    break;
+                }
+                if (wall_clock64() - t0 > timeout_ticks) {
+                    __hip_atomic_fetch_or(flags, kFlagBarrierTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    aborted = 1;
+                    break;
+                }
             }
         }
         acquire_agent<COH>();
