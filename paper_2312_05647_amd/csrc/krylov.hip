@@ -86,10 +86,10 @@ __device__ __forceinline__ void block_sums(double (&v)[M], P red) {
 // partial stores have completed (s_waitcnt vmcnt(0)) before its ticket
 // increment, so the block that takes the last ticket reads them all.  No
 // agent-scope fence is needed (one per block would write back and
-// invalidate the L2 thousands of times per kernel).  The reduction is a
-// two-level tree: the last block of each group of kGroup blocks sums the
-// group's partials, the last group to finish sums the group results.
-constexpr int kGroup = 64;
+// invalidate the L2 thousands of times per kernel).  The grids have at most
+// kMaxBlocks blocks, so one level suffices: the last block to arrive sums
+// every partial, with all of its loads issued together (a second level of
+// group sums would add a ticket and a round of loads to the kernel's tail).
 constexpr int kCpolSC1 = 16;            // device-scope cache policy of a buffer access
 constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, 32-bit elements, no swizzle
 
@@ -112,50 +112,45 @@ __device__ __forceinline__ bool arrive_last(unsigned* ticket, unsigned arrivals)
     return is_last;
 }
 
-// sums[m] = sum_{b < len} p[m * stride + b] for m < count (count <= 64):
-// eight threads per row, each reading every eighth value in batches of
-// eight device-scope loads, then a fixed tree over the eight threads.
+// sums[m] = sum_{b < len} p[m * stride + b] for m < count: sixteen threads
+// per row, each reading every sixteenth value in batches of sixteen
+// device-scope loads (one batch covers 256 partials), then a fixed tree over
+// the sixteen threads.
 __device__ __forceinline__ void sum_rows(const double* p, size_t stride, int len, int count, double* sums) {
-    const int sub = threadIdx.x & 7, slot = threadIdx.x >> 3;  // 32 rows per round
-    for (int m0 = 0; m0 < count; m0 += kKB / 8) {
+    const int sub = threadIdx.x & 15, slot = threadIdx.x >> 4;  // 32 rows per round
+    for (int m0 = 0; m0 < count; m0 += kKB / 16) {
         const int m = m0 + slot;
         double s = 0.0;
         if (m < count) {
             const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
                 const_cast<double*>(p + (size_t)m * stride), 0, len * 8, kRsrcWord3);
-            for (int b0 = sub; b0 < len; b0 += 64) {
-                double x[8];
+            for (int b0 = sub; b0 < len; b0 += 256) {
+                double x[16];
 #pragma unroll
-                for (int u = 0; u < 8; ++u)  // past len the descriptor returns 0
+                for (int u = 0; u < 16; ++u)  // past len the descriptor returns 0
                     x[u] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
-                                                          r, (uint32_t)(b0 + 8 * u) * 8u, 0, kCpolSC1));
+                                                          r, (uint32_t)(b0 + 16 * u) * 8u, 0, kCpolSC1));
 #pragma unroll
-                for (int u = 0; u < 8; ++u) s += x[u];
+                for (int u = 0; u < 16; ++u) s += x[u];
             }
         }
-        for (int off = 4; off > 0; off >>= 1) s += __shfl_down(s, off, 8);
+        for (int off = 8; off > 0; off >>= 1) s += __shfl_down(s, off, 16);
         if (sub == 0 && m < count) sums[m] = s;
     }
     __syncthreads();
 }
 
-// Block partials (count values, already in red[m * waves]) -> the tree.
-// Returns true in the one block that ends holding the totals in sums[].
+// Block partials (count values, already in red[m * waves]) -> the totals.
+// Returns true in the one block that ends holding them in sums[].
 struct Tree {
-    double* part;    // [count][nblk]
-    double* part2;   // [count][ngroups]
-    unsigned* tk;    // [1 + ngroups]: top ticket, then one per group
+    double* part;  // [count][nblk]
+    unsigned* tk;  // arrival ticket
 };
 __device__ __forceinline__ bool tree_sum(const Tree& t, const double* red, int count, double* sums) {
     const int nblk = gridDim.x, blk = blockIdx.x;
-    const int ngroups = (nblk + kGroup - 1) / kGroup, grp = blk / kGroup;
     if (threadIdx.x < count) put_partial(t.part + (size_t)threadIdx.x * nblk + blk, red[threadIdx.x * (kKB / 64)]);
-    const int gsize = min(kGroup, nblk - grp * kGroup);
-    if (!arrive_last(t.tk + 1 + grp, (unsigned)gsize)) return false;
-    sum_rows(t.part + (size_t)grp * kGroup, (size_t)nblk, gsize, count, sums);
-    if (threadIdx.x < count) put_partial(t.part2 + (size_t)threadIdx.x * ngroups + grp, sums[threadIdx.x]);
-    if (!arrive_last(t.tk, (unsigned)ngroups)) return false;
-    sum_rows(t.part2, (size_t)ngroups, ngroups, count, sums);
+    if (!arrive_last(t.tk, (unsigned)nblk)) return false;
+    sum_rows(t.part, (size_t)nblk, nblk, count, sums);
     return true;
 }
 
@@ -798,9 +793,8 @@ struct mjp_krylov {
     DevBuf Q;                    // kappa x n FP64, unnormalised basis
     DevBuf H;                    // kappa x kappa FP64
     DevBuf part;                 // (kKMax + 1) x nblk FP64 block partials
-    DevBuf part2;                // (kKMax + 1) x ngroups FP64 group partials
     DevBuf sc;                   // S_COUNT FP64 scalars
-    DevBuf ticket;               // 1 + ngroups arrival counters (zero between kernels)
+    DevBuf ticket;               // arrival counter (zero between kernels)
     // fused step (one cooperative launch per step), when it fits
     bool fused = false;
     int G = 0;                   // its workgroups (a multiple of 8)
@@ -879,16 +873,14 @@ mjp_status mjp_krylov_create(const mjp_csr* A, const mjp_krylov_opts* opts, mjp_
     k->m_theta = m_theta;
     k->n_slices = n_slices;
     const int64_t nblk = (n + kKB - 1) / kKB;
-    const int64_t ngroups = (nblk + kGroup - 1) / kGroup;
     if ((st = k->slice_off.reserve(sizeof(int32_t) * slice_off.size())) ||
         (st = k->col.reserve(sizeof(int32_t) * std::max<size_t>(total, 1))) ||
         (st = k->val.reserve(sizeof(double) * std::max<size_t>(total, 1))) ||
         (st = k->Q.reserve(sizeof(double) * (size_t)k->kappa * (size_t)n)) ||
         (st = k->H.reserve(sizeof(double) * kKMax * kKMax)) ||
         (st = k->part.reserve(sizeof(double) * (kKMax + 1) * (size_t)nblk)) ||
-        (st = k->part2.reserve(sizeof(double) * (kKMax + 1) * (size_t)ngroups)) ||
         (st = k->sc.reserve(sizeof(double) * S_COUNT)) ||
-        (st = k->ticket.reserve(sizeof(unsigned) * (size_t)(1 + ngroups))))
+        (st = k->ticket.reserve(sizeof(unsigned))))
         return bail(st);
     auto up = [&](DevBuf& b, const void* h, size_t bytes) -> mjp_status {
         if (bytes) MJP_HIP(hipMemcpy(b.ptr, h, bytes, hipMemcpyHostToDevice));
@@ -899,7 +891,7 @@ mjp_status mjp_krylov_create(const mjp_csr* A, const mjp_krylov_opts* opts, mjp_
         (st = up(k->val, hval.data(), sizeof(double) * total)))
         return bail(st);
     std::vector<double> zeros(kKMax * kKMax, 0.0);
-    std::vector<unsigned> z32((size_t)(1 + ngroups), 0u);
+    std::vector<unsigned> z32(1, 0u);
     if ((st = up(k->H, zeros.data(), sizeof(double) * kKMax * kKMax)) ||
         (st = up(k->ticket, z32.data(), sizeof(unsigned) * z32.size())))
         return bail(st);
@@ -945,7 +937,6 @@ void mjp_krylov_destroy(mjp_krylov* k) {
     k->Q.release();
     k->H.release();
     k->part.release();
-    k->part2.release();
     k->sc.release();
     k->ticket.release();
     k->spart.release();
@@ -975,7 +966,7 @@ mjp_status mjp_krylov_expv(mjp_krylov* k, const double* rho0_d, int32_t n_t, con
     const unsigned nblk = (unsigned)std::min<int64_t>((n + kKB - 1) / kKB, kMaxBlocks);
     double* Q = k->Q.as<double>();
     double* H = k->H.as<double>();
-    const Tree tree{k->part.as<double>(), k->part2.as<double>(), k->ticket.as<unsigned>()};
+    const Tree tree{k->part.as<double>(), k->ticket.as<unsigned>()};
     double* sc = k->sc.as<double>();
     KryOp op{k->slice_off.as<int32_t>(), k->col.as<int32_t>(), k->val.as<double>()};
 
