@@ -64,6 +64,8 @@ constexpr int kSlice = 64;  // rows per sliced-ELL slice (= one wavefront)
 
 // Generator checks shared by every CSR entry point (see runtime.hip).
 mjp_status check_generator_csr(const mjp_csr* A, int leaky, double* m_theta, std::vector<double>* diag);
+// Model description checks (model id, dims, finite non-negative rates).
+mjp_status check_model(const mjp_model* m);
 
 }  // namespace mjp
 

@@ -18,6 +18,11 @@
 // in LDS), writes the next stage's input and updates the weighted sum; the
 // fourth writes the new x.  Five N-vectors: x (two buffers), two stage
 // inputs, the weighted sum.
+//
+// Stencil form (birth-death and cascade models, Secs. 3.1.1 and 3.1.2): the
+// channels are the model's reactions in the order of its rates, and each
+// entry of A(t)^T is formed from the state's coordinates inside the stage
+// kernel, so a stage streams only the vectors.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -42,8 +47,21 @@ struct RkG {
     double g[kRkMaxChannels];
 };
 
-// k = xin A(t_s) for each row; FINAL: xout = x + h6 (acc + k); otherwise
-// xout = x + c_next k and acc = (first ? 0 : acc) + w k.
+// Row r of a stage once k = (xin A(t_s))_r is formed: FINAL: xout = x + h6
+// (acc + k); otherwise xout = x + c_next k and acc = (first ? 0 : acc) + w k.
+template <bool FINAL>
+__device__ __forceinline__ void rk_stage_row(int64_t r, double k, const double* __restrict__ x,
+                                             double* __restrict__ xout, double* __restrict__ acc, double c_next,
+                                             double w, int first, double h6) {
+    if constexpr (FINAL) {
+        xout[r] = x[r] + h6 * (acc[r] + k);
+    } else {
+        xout[r] = x[r] + c_next * k;
+        acc[r] = (first ? 0.0 : acc[r]) + w * k;
+    }
+}
+
+// k = xin A(t_s) for each row, then rk_stage_row.
 template <bool FINAL>
 __global__ __launch_bounds__(kRkB) void k_rk_stage(RkOp op, RkG gv, const double* __restrict__ xin,
                                                    const double* __restrict__ x, double* __restrict__ xout,
@@ -84,12 +102,38 @@ __global__ __launch_bounds__(kRkB) void k_rk_stage(RkOp op, RkG gv, const double
             const int32_t e = b + j * 64;
             k += gs[op.ch[e]] * op.val[e] * xin[op.col[e]];
         }
-        if constexpr (FINAL) {
-            xout[r] = x[r] + h6 * (acc[r] + k);
-        } else {
-            xout[r] = x[r] + c_next * k;
-            acc[r] = (first ? 0.0 : acc[r]) + w * k;
-        }
+        rk_stage_row<FINAL>(r, k, x, xout, acc, c_next, w, first, h6);
+    }
+}
+
+// Stencil operator: state r = x1 + S1 x2 (birth-death: S2 = 1), channels
+// 0..3 = birth of species 1 (th[0]), its death (th[1] x1), birth of species
+// 2 (th[2] x1), its death (th[3] x2); births off the grid are dropped, as in
+// the models' generators (conservative truncation).
+struct RkStencil {
+    int32_t S1, S2;
+    double th[4];  // 0 for channels the model lacks
+};
+
+// k_r = sum_n xin_n a_nr(t_s): the inflows from the four neighbours, minus
+// the exit rate of r; then rk_stage_row.
+template <bool FINAL>
+__global__ __launch_bounds__(kRkB) void k_rk_stage_stencil(RkStencil m, RkG gv, const double* __restrict__ xin,
+                                                           const double* __restrict__ x, double* __restrict__ xout,
+                                                           double* __restrict__ acc, int32_t n, double c_next,
+                                                           double w, int first, double h6) {
+    const double b1 = gv.g[0] * m.th[0], d1 = gv.g[1] * m.th[1], b2 = gv.g[2] * m.th[2], d2 = gv.g[3] * m.th[3];
+    const uint32_t S1 = (uint32_t)m.S1;
+    for (int32_t r = (int32_t)(blockIdx.x * kRkB + threadIdx.x); r < n; r += (int32_t)(gridDim.x * kRkB)) {
+        const uint32_t i2 = (uint32_t)r / S1, i1 = (uint32_t)r - i2 * S1;
+        const double f1 = (double)i1, f2 = (double)i2;
+        const bool up1 = i1 + 1 < S1, up2 = (int32_t)i2 + 1 < m.S2;
+        double k = -((up1 ? b1 : 0.0) + d1 * f1 + (up2 ? b2 * f1 : 0.0) + d2 * f2) * xin[r];
+        if (i1 > 0) k += b1 * xin[r - 1];
+        if (up1) k += d1 * (f1 + 1.0) * xin[r + 1];
+        if (i2 > 0) k += b2 * f1 * xin[r - (int32_t)S1];
+        if (up2) k += d2 * (f2 + 1.0) * xin[r + (int32_t)S1];
+        rk_stage_row<FINAL>(r, k, x, xout, acc, c_next, w, first, h6);
     }
 }
 
@@ -108,6 +152,8 @@ struct mjp_rk4 {
     double dt_factor = 1.0;
     std::vector<std::vector<double>> knot_t, knot_g;  // per channel
     std::vector<std::vector<double>> absdiag;         // per channel |a^c_nn|
+    bool stencil = false;                             // entries formed in the kernel (sten)
+    RkStencil sten{};
     DevBuf slice_off, col, val, ch;
     DevBuf x[2], s, t, acc;
 };
@@ -246,6 +292,58 @@ mjp_status mjp_rk4_create(int32_t n_channels, const mjp_csr* channels, const mjp
     return MJP_OK;
 }
 
+mjp_status mjp_rk4_create_stencil(const mjp_model* model, const mjp_rk4_opts* opts, mjp_rk4** out) {
+    clear_error();
+    MJP_CHECK(out, MJP_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    MJP_CHECK(opts, MJP_E_INVALID_ARG, "opts is NULL");
+    MJP_CHECK(std::isfinite(opts->dt_factor) && opts->dt_factor > 0.0, MJP_E_INVALID_ARG,
+              "dt_factor must be finite and > 0");
+    mjp_status st = check_model(model);
+    if (st) return st;
+    MJP_CHECK(model->model == MJP_MODEL_BD || model->model == MJP_MODEL_CASCADE2, MJP_E_UNSUPPORTED,
+              "the stencil form covers the birth-death and cascade models; give the others as channels to "
+              "mjp_rk4_create");
+    const bool bd = model->model == MJP_MODEL_BD;
+    const int32_t S1 = model->dims[0], S2 = model->dims[1];  // birth-death: S2 = 1
+    const int32_t n = S1 * S2;
+    const int C = bd ? 2 : 4;
+    // |a^c_nn| per channel: the rate of reaction c out of n, 0 where it would leave the grid
+    std::vector<std::vector<double>> absdiag((size_t)C, std::vector<double>((size_t)n));
+    for (int32_t r = 0; r < n; ++r) {
+        const int32_t i1 = r % S1, i2 = r / S1;
+        absdiag[0][(size_t)r] = i1 + 1 < S1 ? model->theta[0] : 0.0;
+        absdiag[1][(size_t)r] = model->theta[1] * (double)i1;
+        if (!bd) {
+            absdiag[2][(size_t)r] = i2 + 1 < S2 ? model->theta[2] * (double)i1 : 0.0;
+            absdiag[3][(size_t)r] = model->theta[3] * (double)i2;
+        }
+    }
+    mjp_rk4* k = new (std::nothrow) mjp_rk4();
+    MJP_CHECK(k, MJP_E_DEVICE, "out of host memory");
+    auto bail = [&](mjp_status s) {
+        mjp_rk4_destroy(k);
+        return s;
+    };
+    if (hipGetDevice(&k->device) != hipSuccess) return bail(fail(MJP_E_DEVICE, "no HIP device available"));
+    k->n = n;
+    k->C = C;
+    k->dt_factor = opts->dt_factor;
+    k->absdiag = std::move(absdiag);
+    k->knot_t.assign((size_t)C, std::vector<double>{0.0});
+    k->knot_g.assign((size_t)C, std::vector<double>{1.0});
+    k->stencil = true;
+    k->sten.S1 = S1;
+    k->sten.S2 = S2;
+    for (int c = 0; c < 4; ++c) k->sten.th[c] = c < C ? model->theta[c] : 0.0;
+    const size_t vec = sizeof(double) * (size_t)n;
+    if ((st = k->x[0].reserve(vec)) || (st = k->x[1].reserve(vec)) || (st = k->s.reserve(vec)) ||
+        (st = k->t.reserve(vec)) || (st = k->acc.reserve(vec)))
+        return bail(st);
+    *out = k;
+    return MJP_OK;
+}
+
 mjp_status mjp_rk4_set_schedule(mjp_rk4* k, int32_t channel, int32_t n_knots, const double* t_knots,
                                 const double* g_knots) {
     clear_error();
@@ -303,6 +401,26 @@ mjp_status mjp_rk4_expv(mjp_rk4* k, const double* rho0_d, int32_t n_t, const dou
         for (int c = 0; c < k->C; ++c) g.g[c] = sched(k->knot_t[(size_t)c], k->knot_g[(size_t)c], t);
         return g;
     };
+    // one stage: k from xin with the stage's g, then the row update
+    auto stage = [&](bool fin, const RkG& g, const double* xin, const double* x, double* xout, double c_next,
+                     double w, int first, double h6) {
+        double* ACCp = k->acc.as<double>();
+        if (k->stencil) {
+            const int32_t n32 = (int32_t)n;
+            if (fin)
+                hipLaunchKernelGGL(k_rk_stage_stencil<true>, dim3(grid), dim3(kRkB), 0, st, k->sten, g, xin, x, xout,
+                                   ACCp, n32, c_next, w, first, h6);
+            else
+                hipLaunchKernelGGL(k_rk_stage_stencil<false>, dim3(grid), dim3(kRkB), 0, st, k->sten, g, xin, x, xout,
+                                   ACCp, n32, c_next, w, first, h6);
+        } else if (fin) {
+            hipLaunchKernelGGL(k_rk_stage<true>, dim3(grid), dim3(kRkB), 0, st, op, g, xin, x, xout, ACCp, n, c_next, w,
+                               first, h6);
+        } else {
+            hipLaunchKernelGGL(k_rk_stage<false>, dim3(grid), dim3(kRkB), 0, st, op, g, xin, x, xout, ACCp, n, c_next,
+                               w, first, h6);
+        }
+    };
 
     std::vector<int> order((size_t)n_t);
     for (int j = 0; j < n_t; ++j) order[(size_t)j] = j;
@@ -311,7 +429,6 @@ mjp_status mjp_rk4_expv(mjp_rk4* k, const double* rho0_d, int32_t n_t, const dou
     double* X[2] = {k->x[0].as<double>(), k->x[1].as<double>()};
     double* S = k->s.as<double>();
     double* T = k->t.as<double>();
-    double* ACC = k->acc.as<double>();
     hipLaunchKernelGGL(k_rk_copy, dim3(grid), dim3(kRkB), 0, st, rho0_d, X[0], n);
     double tau = 0.0;
     int64_t steps = 0;
@@ -323,14 +440,10 @@ mjp_status mjp_rk4_expv(mjp_rk4* k, const double* rho0_d, int32_t n_t, const dou
             const double* x = X[cur];
             double* xn = X[cur ^ 1];
             const RkG g0 = gset(tau), gh = gset(tau + 0.5 * h), g1 = gset(tau + h);
-            hipLaunchKernelGGL(k_rk_stage<false>, dim3(grid), dim3(kRkB), 0, st, op, g0, x, x, S, ACC, n, 0.5 * h, 1.0,
-                               1, 0.0);
-            hipLaunchKernelGGL(k_rk_stage<false>, dim3(grid), dim3(kRkB), 0, st, op, gh, (const double*)S, x, T, ACC, n,
-                               0.5 * h, 2.0, 0, 0.0);
-            hipLaunchKernelGGL(k_rk_stage<false>, dim3(grid), dim3(kRkB), 0, st, op, gh, (const double*)T, x, S, ACC, n,
-                               h, 2.0, 0, 0.0);
-            hipLaunchKernelGGL(k_rk_stage<true>, dim3(grid), dim3(kRkB), 0, st, op, g1, (const double*)S, x, xn, ACC, n,
-                               0.0, 0.0, 0, h / 6.0);
+            stage(false, g0, x, x, S, 0.5 * h, 1.0, 1, 0.0);
+            stage(false, gh, S, x, T, 0.5 * h, 2.0, 0, 0.0);
+            stage(false, gh, T, x, S, h, 2.0, 0, 0.0);
+            stage(true, g1, S, x, xn, 0.0, 0.0, 0, h / 6.0);
             cur ^= 1;
             tau = lands ? te : tau + h;
             ++steps;

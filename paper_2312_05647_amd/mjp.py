@@ -154,6 +154,7 @@ _SIGS = [
     ("mjp_krylov_expv", ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, _P, _P]),
     ("mjp_rk4_opts_default", None, [_P]),
     ("mjp_rk4_create", ctypes.c_int, [ctypes.c_int32, _P, _P, _P]),
+    ("mjp_rk4_create_stencil", ctypes.c_int, [_P, _P, _P]),
     ("mjp_rk4_destroy", None, [_P]),
     ("mjp_rk4_n", ctypes.c_int32, [_P]),
     ("mjp_rk4_set_schedule", ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P, _P]),
@@ -343,6 +344,14 @@ def mjp_rk4_create(channels, opts: mjp_rk4_opts | None = None) -> int:
     opts = opts or mjp_rk4_opts_default()
     h = ctypes.c_void_p()
     _check(lib().mjp_rk4_create(len(keep), arr, ctypes.byref(opts), ctypes.byref(h)))
+    return h.value
+
+
+def mjp_rk4_create_stencil(model: mjp_model, opts: mjp_rk4_opts | None = None) -> int:
+    """Birth-death or cascade model given by its rates; channels = its reactions."""
+    opts = opts or mjp_rk4_opts_default()
+    h = ctypes.c_void_p()
+    _check(lib().mjp_rk4_create_stencil(ctypes.byref(model), ctypes.byref(opts), ctypes.byref(h)))
     return h.value
 
 

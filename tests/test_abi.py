@@ -328,6 +328,33 @@ def test_rk4_no_device_reports_device_error():
     if torch.cuda.is_available():
         pytest.skip("a GPU is present")
     assert status_of(mjp.mjp_rk4_create, [GOOD, GOOD]) == mjp.MJP_E_DEVICE
+    assert status_of(mjp.mjp_rk4_create_stencil, mjp.make_model(1, [1.0, 1.0, 1.0, 1.0], [4, 3])) == \
+        mjp.MJP_E_DEVICE
+
+
+@pytest.mark.parametrize("model,theta,dims,kw,expect", [
+    (2, [1.0] * 4, [5, 1], {}, mjp.MJP_E_UNSUPPORTED),             # two-state: give its channels
+    (3, [1.0] * 6, [5, 4], {}, mjp.MJP_E_UNSUPPORTED),             # autoregulatory
+    (0, [1.0, 1.0], [0, 1], {}, mjp.MJP_E_INVALID_ARG),            # empty grid
+    (0, [1.0, 1.0], [5, 2], {}, mjp.MJP_E_INVALID_ARG),            # birth-death needs dims[1] = 1
+    (1, [1.0, -1.0, 1.0, 1.0], [5, 4], {}, mjp.MJP_E_INVALID_ARG),  # negative rate
+    (1, [1.0, float("nan"), 1.0, 1.0], [5, 4], {}, mjp.MJP_E_INVALID_ARG),
+    (1, [1.0] * 4, [5, 4], dict(dt_factor=-1.0), mjp.MJP_E_INVALID_ARG),
+    (7, [1.0] * 4, [5, 4], {}, mjp.MJP_E_INVALID_ARG),             # unknown model
+])
+def test_rk4_create_stencil_validation(model, theta, dims, kw, expect):
+    assert status_of(mjp.mjp_rk4_create_stencil, mjp.make_model(model, theta, dims),
+                     mjp.mjp_rk4_opts_default(**kw)) == expect
+
+
+def test_rk4_create_stencil_null_arguments():
+    L = mjp.lib()
+    o = mjp.mjp_rk4_opts_default()
+    m = mjp.make_model(1, [1.0] * 4, [3, 3])
+    h = ctypes.c_void_p()
+    assert L.mjp_rk4_create_stencil(None, ctypes.byref(o), ctypes.byref(h)) == mjp.MJP_E_INVALID_ARG
+    assert L.mjp_rk4_create_stencil(ctypes.byref(m), None, ctypes.byref(h)) == mjp.MJP_E_INVALID_ARG
+    assert L.mjp_rk4_create_stencil(ctypes.byref(m), ctypes.byref(o), None) == mjp.MJP_E_INVALID_ARG
 
 
 @pytest.mark.parametrize("model,dims", [(2, [0, 1]), (2, [5, 2]), (3, [0, 4]), (3, [4, 0])])

@@ -63,6 +63,29 @@ def model_csr(model, theta, dims):
     return mjp.mjp_model_csr(mjp.make_model(model, theta, dims))
 
 
+def reaction_channels(model, theta, dims):
+    """The model's reactions as separate generators, in the order of theta
+    (each one the model's generator with every other rate 0)."""
+    k = 2 if model == 0 else 4
+    return [model_csr(model, [theta[c] if i == c else 0.0 for i in range(k)], dims) for c in range(k)]
+
+
+def gpu_rk4_stencil(model, theta, dims, schedules, rho0, times, dt_factor=1.0):
+    h = mjp.mjp_rk4_create_stencil(mjp.make_model(model, theta, dims), mjp.mjp_rk4_opts_default(dt_factor=dt_factor))
+    try:
+        for c, s in enumerate(schedules):
+            if s is not None:
+                mjp.mjp_rk4_set_schedule(h, c, *s)
+        n = mjp.mjp_rk4_n(h)
+        r0 = torch.as_tensor(np.asarray(rho0, np.float64), device="cuda")
+        out = torch.empty((len(times), n), dtype=torch.float64, device="cuda")
+        info = mjp.mjp_rk4_expv(h, r0, times, out)
+        torch.cuda.synchronize()
+        return out.cpu().numpy(), info
+    finally:
+        mjp.mjp_rk4_destroy(h)
+
+
 def compare(got, info, ref, rinfo, what):
     assert info["steps"] == rinfo["steps"], (info, rinfo)
     assert info["m"] == pytest.approx(rinfo["m"], rel=1e-15)
@@ -170,6 +193,41 @@ def test_deterministic():
     assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("model,theta,dims,seed", [
+    (1, [30.0, 1.0, 0.5, 0.7], [23, 17], 3),   # ragged against 64-row slices and 256-thread blocks
+    (1, [200.0, 1.0, 0.5, 0.5], [64, 65], 4),
+    (1, [5.0, 2.0, 0.0, 1.0], [1, 40], 5),     # one column: species-1 reactions only ever leave the grid
+    (0, [40.0, 1.0], [1], 6),                  # one state: every rate 0
+    (0, [40.0, 1.0], [63], 7),
+    (0, [40.0, 1.0], [257], 8),
+])
+def test_stencil_matches_reaction_channels(orc, model, theta, dims, seed):
+    """The stencil form against the oracle run on the model's reactions
+    given as channels, each with its own schedule (same steps, same bar), and
+    against the channel form on the GPU."""
+    ch = reaction_channels(model, theta, dims)
+    rng = np.random.default_rng(seed)
+    sch = [([0.0, 0.4, 1.1], list(rng.uniform(0.3, 2.0, 3))) if c % 2 == 0 else None for c in range(len(ch))]
+    n = int(np.prod(dims))
+    rho0 = synth.random_prob(n, seed)
+    times = [0.7, 0.0, 1.5]
+    say(f"[gpu] rk4 stencil model {model} dims {dims}")
+    got, info = gpu_rk4_stencil(model, theta, dims, sch, rho0, times, 0.5)
+    ref, rinfo = oracle_rk4(orc, ch, sch, rho0, times, 0.5)
+    compare(got, info, ref, rinfo, "stencil")
+    csr, cinfo = gpu_rk4(ch, sch, rho0, times, 0.5)
+    assert cinfo["steps"] == info["steps"]
+    for j in range(len(times)):
+        assert np.abs(got[j] - csr[j]).sum() <= BAR
+    assert np.array_equal(got[1], rho0)
+
+
+def test_stencil_zero_rates_copy():
+    rho0 = synth.random_prob(12, 2)
+    got, info = gpu_rk4_stencil(1, [0.0] * 4, [4, 3], [None] * 4, rho0, [2.0])
+    assert info["steps"] == 0 and np.array_equal(got[0], rho0)
+
+
 def test_full_size(orc):
     """Cascade 1000 x 1000 (N = 10^6), rates (200, 1, 0.5, 0.5): against the
     RK4 oracle to t = 0.05 (same steps), then to t = 1 with the paper's step
@@ -189,3 +247,8 @@ def test_full_size(orc):
     l1 = np.abs(got[0] - ex).sum()
     say(f"    steps {info['steps']}  L1 vs exact {l1:.3e}")
     assert l1 <= 1e-6 and abs(got[0].sum() - 1.0) < 1e-10
+    say("[gpu] rk4 stencil cascade 1000x1000 t=1")
+    sgot, sinfo = gpu_rk4_stencil(1, [200.0, 1.0, 0.5, 0.5], [1000, 1000], [None] * 4, rho0, [1.0])
+    assert sinfo["steps"] == info["steps"]
+    assert np.abs(sgot[0] - got[0]).sum() <= 1e-12
+    assert np.abs(sgot[0] - ex).sum() <= 1e-6
