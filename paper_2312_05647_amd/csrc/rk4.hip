@@ -47,6 +47,17 @@ struct RkG {
     double g[kRkMaxChannels];
 };
 
+// Block index for the grid-stride loops: workgroups are dispatched
+// round-robin over the 8 XCDs, so renumber them (when the grid is a multiple
+// of 8) to give each XCD one band of consecutive 256-row chunks per pass.  A
+// row's neighbours (a grid line away, the rows its product gathers) then
+// mostly lie in the same band and are served from that XCD's own L2 instead
+// of being fetched again by the XCDs of the blocks next to it.
+__device__ __forceinline__ int64_t rk_block() {
+    const unsigned b = blockIdx.x, G = gridDim.x;
+    return (G & 7u) ? (int64_t)b : (int64_t)((b & 7u) * (G >> 3) + (b >> 3));
+}
+
 // Row r of a stage once k = (xin A(t_s))_r is formed: FINAL: xout = x + h6
 // (acc + k); otherwise xout = x + c_next k and acc = (first ? 0 : acc) + w k.
 template <bool FINAL>
@@ -76,7 +87,7 @@ __global__ __launch_bounds__(kRkB) void k_rk_stage(RkOp op, RkG gv, const double
         gs[threadIdx.x] = v;
     }
     __syncthreads();
-    for (int64_t r = (int64_t)blockIdx.x * kRkB + threadIdx.x; r < n; r += (int64_t)gridDim.x * kRkB) {
+    for (int64_t r = rk_block() * kRkB + threadIdx.x; r < n; r += (int64_t)gridDim.x * kRkB) {
         const int64_t s = r >> 6;
         const int lane = (int)(r & 63);
         const int32_t b = op.slice_off[s] + lane;
@@ -124,7 +135,7 @@ __global__ __launch_bounds__(kRkB) void k_rk_stage_stencil(RkStencil m, RkG gv, 
                                                            double w, int first, double h6) {
     const double b1 = gv.g[0] * m.th[0], d1 = gv.g[1] * m.th[1], b2 = gv.g[2] * m.th[2], d2 = gv.g[3] * m.th[3];
     const uint32_t S1 = (uint32_t)m.S1;
-    for (int32_t r = (int32_t)(blockIdx.x * kRkB + threadIdx.x); r < n; r += (int32_t)(gridDim.x * kRkB)) {
+    for (int32_t r = (int32_t)(rk_block() * kRkB + threadIdx.x); r < n; r += (int32_t)(gridDim.x * kRkB)) {
         const uint32_t i2 = (uint32_t)r / S1, i1 = (uint32_t)r - i2 * S1;
         const double f1 = (double)i1, f2 = (double)i2;
         const bool up1 = i1 + 1 < S1, up2 = (int32_t)i2 + 1 < m.S2;
