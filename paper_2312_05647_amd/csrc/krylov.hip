@@ -156,6 +156,16 @@ __device__ __forceinline__ bool tree_sum(const Tree& t, const double* red, int c
 
 // ---- kernels
 
+// Block index of the product's grid-stride loop: workgroups are dispatched
+// round-robin over the 8 XCDs, so renumber them (when the grid is a multiple
+// of 8) to give each XCD one band of consecutive row chunks per pass; the
+// rows a product gathers (a grid line away) then mostly come from that XCD's
+// own L2.
+__device__ __forceinline__ int64_t kry_block() {
+    const unsigned b = blockIdx.x, G = gridDim.x;
+    return (G & 7u) ? (int64_t)b : (int64_t)((b & 7u) * (G >> 3) + (b >> 3));
+}
+
 // rho -> Qraw[0], ||rho||^2; last block: beta and scale[0].
 __global__ __launch_bounds__(kKB) void k_kry_start(const double* __restrict__ rho, double* __restrict__ q0, int64_t n,
                                                    Tree tree, double* __restrict__ sc) {
@@ -186,7 +196,7 @@ __global__ __launch_bounds__(kKB) void k_kry_spmv_dot(KryOp op, double* __restri
     for (int m = 0; m <= I; ++m) v[m] = 0.0;
     const double* __restrict__ x = Q + (size_t)(I - 1) * n;
     const double xs = sc[S_SCALE + I - 1];
-    for (int64_t r = (int64_t)blockIdx.x * kKB + threadIdx.x; r < n; r += (int64_t)gridDim.x * kKB) {
+    for (int64_t r = kry_block() * kKB + threadIdx.x; r < n; r += (int64_t)gridDim.x * kKB) {
         const int64_t s = r >> 6;
         const int lane = (int)(r & 63);
         const int32_t b = op.slice_off[s] + lane;
