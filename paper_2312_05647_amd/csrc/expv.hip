@@ -43,6 +43,32 @@ __device__ __forceinline__ float wave_sum(float v) {
     return v;
 }
 
+// Row block of a step kernel.  Workgroups are dispatched round-robin over
+// the 8 XCDs; the step launches are padded to a multiple of 8 blocks and
+// renumbered so that each XCD owns one band of consecutive row blocks, whose
+// gathers (a grid line away) then mostly hit that XCD's own L2.  Logical
+// block b covers the rows physical block b covered before, and writes its
+// partial to slot b, so every sum keeps its order.
+__device__ __forceinline__ int64_t step_block() {
+    const unsigned b = blockIdx.x, G = gridDim.x;
+    return (G & 7u) ? (int64_t)b : (int64_t)((b & 7u) * (G >> 3) + (b >> 3));
+}
+
+// Block-wide sum of v written by thread 0 to out[slot] (slot < nslots).
+__device__ __forceinline__ void block_partial_at(float v, float* out, int64_t slot, int64_t nslots) {
+    __shared__ float red[kBlock / 64];
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    if (threadIdx.x == 0 && slot < nslots) {
+        float s = 0.f;
+#pragma unroll
+        for (int i = 0; i < kBlock / 64; ++i) s += red[i];
+        out[slot] = s;
+    }
+}
+
 // Block-wide sum of v written by thread 0 to out[blockIdx.x].
 __device__ __forceinline__ void block_partial(float v, float* out) {
     __shared__ float red[kBlock / 64];
@@ -142,7 +168,8 @@ template <bool ACC>
 __global__ __launch_bounds__(kBlock) void k_sell_step(SellArgs a, int k, TimeSet ts, const double* __restrict__ wtab,
                                                       float* __restrict__ out, float* __restrict__ comp,
                                                       float* __restrict__ partials) {
-    const int64_t row = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t blk = step_block();
+    const int64_t row = blk * kBlock + threadIdx.x;
     float yv = 0.f;
     if (row < a.n) {
         const int32_t s = (int32_t)(row >> 6), l = (int32_t)(row & 63);
@@ -156,7 +183,7 @@ __global__ __launch_bounds__(kBlock) void k_sell_step(SellArgs a, int k, TimeSet
         a.y[row] = yv;
         if (ACC) accumulate_all(ts, k, wtab, yv, out, comp, (int)row, a.n);
     }
-    block_partial(yv, partials);
+    block_partial_at(yv, partials, blk, (a.n + kBlock - 1) / kBlock);
 }
 
 struct StencilArgs {
@@ -205,7 +232,8 @@ template <bool ACC>
 __global__ __launch_bounds__(kBlock) void k_stencil_step(StencilArgs a, int k, TimeSet ts,
                                                          const double* __restrict__ wtab, float* __restrict__ out,
                                                          float* __restrict__ comp, float* __restrict__ partials) {
-    const int64_t row = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t blk = step_block();
+    const int64_t row = blk * kBlock + threadIdx.x;
     float yv = 0.f;
     if (row < a.n) {
         const float acc = stencil_row(a.cf, a.x, row);
@@ -213,7 +241,7 @@ __global__ __launch_bounds__(kBlock) void k_stencil_step(StencilArgs a, int k, T
         a.y[row] = yv;
         if (ACC) accumulate_all(ts, k, wtab, yv, out, comp, (int)row, a.n);
     }
-    block_partial(yv, partials);
+    block_partial_at(yv, partials, blk, (a.n + kBlock - 1) / kBlock);
 }
 
 __global__ __launch_bounds__(kBlock) void k_accumulate(const float* __restrict__ y, int64_t n, int k, TimeSet ts,
@@ -290,6 +318,7 @@ static mjp_status run_sweep(mjp_plan* p, const float* rho0, const std::vector<Sw
     const int64_t n = p->n;
     const int nt = (int)times.size();
     const unsigned nblk = (unsigned)((n + kBlock - 1) / kBlock);
+    const unsigned nblk8 = (nblk + 7u) & ~7u;  // step launches: a multiple of 8 blocks (see step_block)
     AllTimes at{};
     at.n = nt;
     int64_t wtotal = 0;
@@ -425,15 +454,15 @@ static mjp_status run_sweep(mjp_plan* p, const float* rho0, const std::vector<Sw
             if (p->kind == PLAN_CSR) {
                 SellArgs a{p->slice_off.as<int32_t>(), p->col.as<int32_t>(), p->val.as<float>(), x, y, scale, n};
                 if (fused.n)
-                    hipLaunchKernelGGL(k_sell_step<true>, dim3(nblk), dim3(kBlock), 0, st, a, k, fused, wtab, out, comp, partials);
+                    hipLaunchKernelGGL(k_sell_step<true>, dim3(nblk8), dim3(kBlock), 0, st, a, k, fused, wtab, out, comp, partials);
                 else
-                    hipLaunchKernelGGL(k_sell_step<false>, dim3(nblk), dim3(kBlock), 0, st, a, k, fused, wtab, out, comp, partials);
+                    hipLaunchKernelGGL(k_sell_step<false>, dim3(nblk8), dim3(kBlock), 0, st, a, k, fused, wtab, out, comp, partials);
             } else {
                 StencilArgs a{p->coef, x, y, scale, n};
                 if (fused.n)
-                    hipLaunchKernelGGL(k_stencil_step<true>, dim3(nblk), dim3(kBlock), 0, st, a, k, fused, wtab, out, comp, partials);
+                    hipLaunchKernelGGL(k_stencil_step<true>, dim3(nblk8), dim3(kBlock), 0, st, a, k, fused, wtab, out, comp, partials);
                 else
-                    hipLaunchKernelGGL(k_stencil_step<false>, dim3(nblk), dim3(kBlock), 0, st, a, k, fused, wtab, out, comp, partials);
+                    hipLaunchKernelGGL(k_stencil_step<false>, dim3(nblk8), dim3(kBlock), 0, st, a, k, fused, wtab, out, comp, partials);
             }
             for (const TimeSet& e : extra)
                 hipLaunchKernelGGL(k_accumulate, dim3(nblk), dim3(kBlock), 0, st, y, n, k, e, wtab, out, comp);
