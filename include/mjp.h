@@ -514,18 +514,21 @@ void mjp_rk4_opts_default(mjp_rk4_opts* o);
  * (operator + five N-vectors) until mjp_rk4_destroy. */
 mjp_status mjp_rk4_create(int32_t n_channels, const mjp_csr* channels, const mjp_rk4_opts* opts, mjp_rk4** out);
 
-/* The same propagator for the birth-death (Sec. 3.1.1) and cascade models
- * given as rates (mjp_model, as for mjp_plan_create_stencil): the channels
- * are the model's reactions in the order of its theta -- birth-death: 0
- * birth (theta[0]), 1 death (theta[1] n); cascade at state (x, y): 0 birth
- * of x (theta[0]), 1 death of x (theta[1] x), 2 birth of y (theta[2] x),
- * 3 death of y (theta[3] y) -- each with its own schedule
- * (mjp_rk4_set_schedule).  Births off the grid are dropped, as in
- * mjp_model_csr.  The stage kernel forms A(t)'s entries from the state's
- * coordinates, so a stage streams only the N-vectors.  MJP_E_INVALID_ARG as
- * for mjp_model_csr; MJP_E_UNSUPPORTED for the other models (give their
- * reactions as channels to mjp_rk4_create).  The handle owns five FP64
- * N-vectors until mjp_rk4_destroy. */
+/* The same propagator for a built-in model given as rates (mjp_model, as
+ * for mjp_model_csr): the channels are the model's reactions in the order of
+ * its theta, each with its own schedule (mjp_rk4_set_schedule) --
+ *   birth-death: 0 birth (theta[0]), 1 death (theta[1] n);
+ *   cascade at (x, y): 0 birth of x (theta[0]), 1 death of x (theta[1] x),
+ *     2 birth of y (theta[2] x), 3 death of y (theta[3] y);
+ *   two-state (Sec. 3.1.2): 0 birth (theta[0], active gene), 1 death
+ *     (theta[1] n), 2 activation (theta[2]), 3 inactivation (theta[3]);
+ *   autoregulatory (Sec. 3.1.3): 0 R birth (theta[0], active), 1 P birth
+ *     (theta[1] n_R), 2 R death (theta[2] n_R), 3 P death (theta[3] n_P),
+ *     4 unbinding (theta[4]), 5 binding (theta[5] n_P).
+ * Births that would leave the grid are dropped, as in mjp_model_csr.  The
+ * stage kernel forms A(t)'s entries from the state's coordinates, so a stage
+ * streams only the N-vectors.  MJP_E_INVALID_ARG as for mjp_model_csr.  The
+ * handle owns five FP64 N-vectors until mjp_rk4_destroy. */
 mjp_status mjp_rk4_create_stencil(const mjp_model* model, const mjp_rk4_opts* opts, mjp_rk4** out);
 void       mjp_rk4_destroy(mjp_rk4* k);
 int32_t    mjp_rk4_n(const mjp_rk4* k);

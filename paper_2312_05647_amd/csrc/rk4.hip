@@ -19,8 +19,9 @@
 // fourth writes the new x.  Five N-vectors: x (two buffers), two stage
 // inputs, the weighted sum.
 //
-// Stencil form (birth-death and cascade models, Secs. 3.1.1 and 3.1.2): the
-// channels are the model's reactions in the order of its rates, and each
+// Stencil form (the birth-death, cascade, two-state and autoregulatory models
+// of Secs. 3.1.1-3.1.3): the channels are the model's reactions in the order
+// of its rates, and each
 // entry of A(t)^T is formed from the state's coordinates inside the stage
 // kernel, so a stage streams only the vectors.
 #include <algorithm>
@@ -117,35 +118,76 @@ __global__ __launch_bounds__(kRkB) void k_rk_stage(RkOp op, RkG gv, const double
     }
 }
 
-// Stencil operator: state r = x1 + S1 x2 (birth-death: S2 = 1), channels
-// 0..3 = birth of species 1 (th[0]), its death (th[1] x1), birth of species
-// 2 (th[2] x1), its death (th[3] x2); births off the grid are dropped, as in
-// the models' generators (conservative truncation).
+// Stencil operator: the channels are the model's reactions in the order of
+// its rates; births (and unbinding) that would leave the grid are dropped,
+// as in the models' generators (conservative truncation).
+//   birth-death / cascade, r = x1 + S1 x2 (birth-death: S2 = 1): 0 birth of
+//     x1 (th0), 1 its death (th1 x1), 2 birth of x2 (th2 x1), 3 its death
+//     (th3 x2);
+//   two-state, r = n + S1 g (g = 0 active): 0 birth (th0, active), 1 death
+//     (th1 n), 2 activation (th2, from inactive), 3 inactivation (th3);
+//   autoregulatory, r = n_R + S1 n_P + S1 S2 g (S2 = N_P): 0 R birth (th0,
+//     active), 1 P birth (th1 n_R), 2 R death (th2 n_R), 3 P death (th3 n_P),
+//     4 unbinding inactive -> active + P (th4), 5 binding active + P ->
+//     inactive (th5 n_P).
 struct RkStencil {
     int32_t S1, S2;
-    double th[4];  // 0 for channels the model lacks
+    double th[6];  // 0 for channels the model lacks
 };
 
-// k_r = sum_n xin_n a_nr(t_s): the inflows from the four neighbours, minus
-// the exit rate of r; then rk_stage_row.
-template <bool FINAL>
+// (xin A(t_s))_r for state r: the inflows from its neighbours, minus its
+// exit rate; c[i] = g_i th_i, the stage's effective rates.
+template <int MODEL>
+__device__ __forceinline__ double rk_stencil_row(const RkStencil& m, const double* c, const double* __restrict__ xin,
+                                                 int32_t r) {
+    const uint32_t S1 = (uint32_t)m.S1;
+    const uint32_t q = (uint32_t)r / S1, i1 = (uint32_t)r - q * S1;
+    const double f1 = (double)i1;
+    const bool up1 = i1 + 1 < S1;
+    if constexpr (MODEL == MJP_MODEL_BD || MODEL == MJP_MODEL_CASCADE2) {
+        const double f2 = (double)q;
+        const bool up2 = (int32_t)q + 1 < m.S2;
+        double k = -((up1 ? c[0] : 0.0) + c[1] * f1 + (up2 ? c[2] * f1 : 0.0) + c[3] * f2) * xin[r];
+        if (i1 > 0) k += c[0] * xin[r - 1];
+        if (up1) k += c[1] * (f1 + 1.0) * xin[r + 1];
+        if (q > 0) k += c[2] * f1 * xin[r - (int32_t)S1];
+        if (up2) k += c[3] * (f2 + 1.0) * xin[r + (int32_t)S1];
+        return k;
+    } else if constexpr (MODEL == MJP_MODEL_TWOSTATE) {
+        const bool act = q == 0;
+        double k = -((act && up1 ? c[0] : 0.0) + c[1] * f1 + (act ? c[3] : c[2])) * xin[r];
+        if (act && i1 > 0) k += c[0] * xin[r - 1];
+        if (up1) k += c[1] * (f1 + 1.0) * xin[r + 1];
+        k += act ? c[2] * xin[r + (int32_t)S1] : c[3] * xin[r - (int32_t)S1];
+        return k;
+    } else {  // MJP_MODEL_AUTOREG
+        const uint32_t NP = (uint32_t)m.S2, plane = S1 * NP;
+        const uint32_t g = q / NP, p = q - g * NP;
+        const bool act = g == 0, upp = p + 1 < NP;
+        const double fp = (double)p;
+        double k = -((act && up1 ? c[0] : 0.0) + (upp ? c[1] * f1 : 0.0) + c[2] * f1 + c[3] * fp +
+                     (act ? c[5] * fp : (upp ? c[4] : 0.0))) * xin[r];
+        if (act && i1 > 0) k += c[0] * xin[r - 1];                               // R birth
+        if (p > 0) k += c[1] * f1 * xin[r - (int32_t)S1];                         // P birth
+        if (up1) k += c[2] * (f1 + 1.0) * xin[r + 1];                             // R death
+        if (upp) k += c[3] * (fp + 1.0) * xin[r + (int32_t)S1];                   // P death
+        if (!act && upp) k += c[5] * (fp + 1.0) * xin[r - (int32_t)plane + (int32_t)S1];  // binding
+        if (act && p > 0) k += c[4] * xin[r + (int32_t)plane - (int32_t)S1];     // unbinding
+        return k;
+    }
+}
+
+// k = xin A(t_s) from the stencil for each row, then rk_stage_row.
+template <bool FINAL, int MODEL>
 __global__ __launch_bounds__(kRkB) void k_rk_stage_stencil(RkStencil m, RkG gv, const double* __restrict__ xin,
                                                            const double* __restrict__ x, double* __restrict__ xout,
                                                            double* __restrict__ acc, int32_t n, double c_next,
                                                            double w, int first, double h6) {
-    const double b1 = gv.g[0] * m.th[0], d1 = gv.g[1] * m.th[1], b2 = gv.g[2] * m.th[2], d2 = gv.g[3] * m.th[3];
-    const uint32_t S1 = (uint32_t)m.S1;
-    for (int32_t r = (int32_t)(rk_block() * kRkB + threadIdx.x); r < n; r += (int32_t)(gridDim.x * kRkB)) {
-        const uint32_t i2 = (uint32_t)r / S1, i1 = (uint32_t)r - i2 * S1;
-        const double f1 = (double)i1, f2 = (double)i2;
-        const bool up1 = i1 + 1 < S1, up2 = (int32_t)i2 + 1 < m.S2;
-        double k = -((up1 ? b1 : 0.0) + d1 * f1 + (up2 ? b2 * f1 : 0.0) + d2 * f2) * xin[r];
-        if (i1 > 0) k += b1 * xin[r - 1];
-        if (up1) k += d1 * (f1 + 1.0) * xin[r + 1];
-        if (i2 > 0) k += b2 * f1 * xin[r - (int32_t)S1];
-        if (up2) k += d2 * (f2 + 1.0) * xin[r + (int32_t)S1];
-        rk_stage_row<FINAL>(r, k, x, xout, acc, c_next, w, first, h6);
-    }
+    double c[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) c[i] = gv.g[i] * m.th[i];
+    for (int32_t r = (int32_t)(rk_block() * kRkB + threadIdx.x); r < n; r += (int32_t)(gridDim.x * kRkB))
+        rk_stage_row<FINAL>(r, rk_stencil_row<MODEL>(m, c, xin, r), x, xout, acc, c_next, w, first, h6);
 }
 
 __global__ void k_rk_copy(const double* __restrict__ a, double* __restrict__ b, int64_t n) {
@@ -163,7 +205,8 @@ struct mjp_rk4 {
     double dt_factor = 1.0;
     std::vector<std::vector<double>> knot_t, knot_g;  // per channel
     std::vector<std::vector<double>> absdiag;         // per channel |a^c_nn|
-    bool stencil = false;                             // entries formed in the kernel (sten)
+    bool stencil = false;                             // entries formed in the kernel (sten, model)
+    int32_t model = 0;
     RkStencil sten{};
     DevBuf slice_off, col, val, ch;
     DevBuf x[2], s, t, acc;
@@ -312,22 +355,38 @@ mjp_status mjp_rk4_create_stencil(const mjp_model* model, const mjp_rk4_opts* op
               "dt_factor must be finite and > 0");
     mjp_status st = check_model(model);
     if (st) return st;
-    MJP_CHECK(model->model == MJP_MODEL_BD || model->model == MJP_MODEL_CASCADE2, MJP_E_UNSUPPORTED,
-              "the stencil form covers the birth-death and cascade models; give the others as channels to "
-              "mjp_rk4_create");
-    const bool bd = model->model == MJP_MODEL_BD;
-    const int32_t S1 = model->dims[0], S2 = model->dims[1];  // birth-death: S2 = 1
-    const int32_t n = S1 * S2;
-    const int C = bd ? 2 : 4;
-    // |a^c_nn| per channel: the rate of reaction c out of n, 0 where it would leave the grid
-    std::vector<std::vector<double>> absdiag((size_t)C, std::vector<double>((size_t)n));
+    const int md = model->model;
+    const int32_t S1 = model->dims[0], S2 = model->dims[1];  // birth-death and two-state: S2 = 1
+    const int32_t n = md == MJP_MODEL_TWOSTATE ? 2 * S1 : md == MJP_MODEL_AUTOREG ? 2 * S1 * S2 : S1 * S2;
+    const int C = md == MJP_MODEL_BD ? 2 : md == MJP_MODEL_AUTOREG ? 6 : 4;
+    // |a^c_nn| per channel: the rate of reaction c out of state r, 0 where it would leave the grid
+    std::vector<std::vector<double>> absdiag((size_t)C, std::vector<double>((size_t)n, 0.0));
+    const double* th = model->theta;
     for (int32_t r = 0; r < n; ++r) {
-        const int32_t i1 = r % S1, i2 = r / S1;
-        absdiag[0][(size_t)r] = i1 + 1 < S1 ? model->theta[0] : 0.0;
-        absdiag[1][(size_t)r] = model->theta[1] * (double)i1;
-        if (!bd) {
-            absdiag[2][(size_t)r] = i2 + 1 < S2 ? model->theta[2] * (double)i1 : 0.0;
-            absdiag[3][(size_t)r] = model->theta[3] * (double)i2;
+        const int32_t i1 = r % S1, q = r / S1;
+        const double f1 = (double)i1;
+        if (md == MJP_MODEL_BD || md == MJP_MODEL_CASCADE2) {
+            absdiag[0][(size_t)r] = i1 + 1 < S1 ? th[0] : 0.0;
+            absdiag[1][(size_t)r] = th[1] * f1;
+            if (C == 4) {
+                absdiag[2][(size_t)r] = q + 1 < S2 ? th[2] * f1 : 0.0;
+                absdiag[3][(size_t)r] = th[3] * (double)q;
+            }
+        } else if (md == MJP_MODEL_TWOSTATE) {
+            const bool act = q == 0;
+            absdiag[0][(size_t)r] = act && i1 + 1 < S1 ? th[0] : 0.0;
+            absdiag[1][(size_t)r] = th[1] * f1;
+            absdiag[2][(size_t)r] = act ? 0.0 : th[2];
+            absdiag[3][(size_t)r] = act ? th[3] : 0.0;
+        } else {
+            const int32_t g = q / S2, p = q % S2;
+            const bool act = g == 0, upp = p + 1 < S2;
+            absdiag[0][(size_t)r] = act && i1 + 1 < S1 ? th[0] : 0.0;
+            absdiag[1][(size_t)r] = upp ? th[1] * f1 : 0.0;
+            absdiag[2][(size_t)r] = th[2] * f1;
+            absdiag[3][(size_t)r] = th[3] * (double)p;
+            absdiag[4][(size_t)r] = !act && upp ? th[4] : 0.0;
+            absdiag[5][(size_t)r] = act ? th[5] * (double)p : 0.0;
         }
     }
     mjp_rk4* k = new (std::nothrow) mjp_rk4();
@@ -344,9 +403,10 @@ mjp_status mjp_rk4_create_stencil(const mjp_model* model, const mjp_rk4_opts* op
     k->knot_t.assign((size_t)C, std::vector<double>{0.0});
     k->knot_g.assign((size_t)C, std::vector<double>{1.0});
     k->stencil = true;
+    k->model = md;
     k->sten.S1 = S1;
     k->sten.S2 = S2;
-    for (int c = 0; c < 4; ++c) k->sten.th[c] = c < C ? model->theta[c] : 0.0;
+    for (int c = 0; c < 6; ++c) k->sten.th[c] = c < C ? th[c] : 0.0;
     const size_t vec = sizeof(double) * (size_t)n;
     if ((st = k->x[0].reserve(vec)) || (st = k->x[1].reserve(vec)) || (st = k->s.reserve(vec)) ||
         (st = k->t.reserve(vec)) || (st = k->acc.reserve(vec)))
@@ -418,12 +478,25 @@ mjp_status mjp_rk4_expv(mjp_rk4* k, const double* rho0_d, int32_t n_t, const dou
         double* ACCp = k->acc.as<double>();
         if (k->stencil) {
             const int32_t n32 = (int32_t)n;
-            if (fin)
-                hipLaunchKernelGGL(k_rk_stage_stencil<true>, dim3(grid), dim3(kRkB), 0, st, k->sten, g, xin, x, xout,
-                                   ACCp, n32, c_next, w, first, h6);
-            else
-                hipLaunchKernelGGL(k_rk_stage_stencil<false>, dim3(grid), dim3(kRkB), 0, st, k->sten, g, xin, x, xout,
-                                   ACCp, n32, c_next, w, first, h6);
+#define MJP_RK_STENCIL(F, M)                                                                                    \
+    hipLaunchKernelGGL((k_rk_stage_stencil<F, M>), dim3(grid), dim3(kRkB), 0, st, k->sten, g, xin, x, xout, ACCp, n32, \
+                       c_next, w, first, h6)
+            switch (k->model) {
+                case MJP_MODEL_BD:
+                case MJP_MODEL_CASCADE2:
+                    if (fin) MJP_RK_STENCIL(true, MJP_MODEL_CASCADE2);
+                    else MJP_RK_STENCIL(false, MJP_MODEL_CASCADE2);
+                    break;
+                case MJP_MODEL_TWOSTATE:
+                    if (fin) MJP_RK_STENCIL(true, MJP_MODEL_TWOSTATE);
+                    else MJP_RK_STENCIL(false, MJP_MODEL_TWOSTATE);
+                    break;
+                default:
+                    if (fin) MJP_RK_STENCIL(true, MJP_MODEL_AUTOREG);
+                    else MJP_RK_STENCIL(false, MJP_MODEL_AUTOREG);
+                    break;
+            }
+#undef MJP_RK_STENCIL
         } else if (fin) {
             hipLaunchKernelGGL(k_rk_stage<true>, dim3(grid), dim3(kRkB), 0, st, op, g, xin, x, xout, ACCp, n, c_next, w,
                                first, h6);

@@ -333,8 +333,8 @@ def test_rk4_no_device_reports_device_error():
 
 
 @pytest.mark.parametrize("model,theta,dims,kw,expect", [
-    (2, [1.0] * 4, [5, 1], {}, mjp.MJP_E_UNSUPPORTED),             # two-state: give its channels
-    (3, [1.0] * 6, [5, 4], {}, mjp.MJP_E_UNSUPPORTED),             # autoregulatory
+    (2, [1.0] * 4, [5, 2], {}, mjp.MJP_E_INVALID_ARG),            # two-state needs dims[1] = 1
+    (3, [1.0, 1.0, 1.0, 1.0, 1.0, -2.0], [5, 4], {}, mjp.MJP_E_INVALID_ARG),  # negative binding rate
     (0, [1.0, 1.0], [0, 1], {}, mjp.MJP_E_INVALID_ARG),            # empty grid
     (0, [1.0, 1.0], [5, 2], {}, mjp.MJP_E_INVALID_ARG),            # birth-death needs dims[1] = 1
     (1, [1.0, -1.0, 1.0, 1.0], [5, 4], {}, mjp.MJP_E_INVALID_ARG),  # negative rate

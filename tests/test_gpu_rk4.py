@@ -66,7 +66,7 @@ def model_csr(model, theta, dims):
 def reaction_channels(model, theta, dims):
     """The model's reactions as separate generators, in the order of theta
     (each one the model's generator with every other rate 0)."""
-    k = 2 if model == 0 else 4
+    k = {0: 2, 1: 4, 2: 4, 3: 6}[model]
     return [model_csr(model, [theta[c] if i == c else 0.0 for i in range(k)], dims) for c in range(k)]
 
 
@@ -200,6 +200,10 @@ def test_deterministic():
     (0, [40.0, 1.0], [1], 6),                  # one state: every rate 0
     (0, [40.0, 1.0], [63], 7),
     (0, [40.0, 1.0], [257], 8),
+    (2, [40.0, 1.0, 2.0, 1.0], [70, 1], 9),                    # two-state: N = 140
+    (2, [40.0, 1.0, 2.0, 1.0], [1, 1], 10),                    # one count level, the gene switches
+    (3, [20.0, 2.0, 1.0, 0.5, 1.5, 0.7], [13, 11], 11),        # autoregulatory: N = 286
+    (3, [20.0, 2.0, 1.0, 0.5, 1.5, 0.7], [40, 1], 12),         # N_P = 1: no P moves, no (un)binding
 ])
 def test_stencil_matches_reaction_channels(orc, model, theta, dims, seed):
     """The stencil form against the oracle run on the model's reactions
@@ -208,7 +212,7 @@ def test_stencil_matches_reaction_channels(orc, model, theta, dims, seed):
     ch = reaction_channels(model, theta, dims)
     rng = np.random.default_rng(seed)
     sch = [([0.0, 0.4, 1.1], list(rng.uniform(0.3, 2.0, 3))) if c % 2 == 0 else None for c in range(len(ch))]
-    n = int(np.prod(dims))
+    n = {0: 1, 1: 1, 2: 2, 3: 2}[model] * int(np.prod(dims))
     rho0 = synth.random_prob(n, seed)
     times = [0.7, 0.0, 1.5]
     say(f"[gpu] rk4 stencil model {model} dims {dims}")
