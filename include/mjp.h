@@ -415,7 +415,7 @@ mjp_status mjp_surrogate_load(const char* path, mjp_surrogate** out);
 
 /* --------------------------------------- Krylov propagator (Method #5) */
 
-/* rho(0) exp(A t) by Krylov-subspace steps (Sec. 2.3, Algorithm
+/* rho(0) exp(A t) by Krylov-subspace steps (Sec. 2.2.5, Algorithm
  * ArnoldiKrylov and Eq. Krylov_expansion), in FP64: per step of length dt
  * an orthonormal basis q_1 = rho/||rho||, q_i from q_{i-1} A (kappa - 1
  * products, H kappa x kappa with a zero last column), and
@@ -482,7 +482,7 @@ mjp_status mjp_krylov_expv(mjp_krylov* k, const double* rho0_d, int32_t n_t, con
 /* ----------------------------- Runge-Kutta propagator (Method #4) */
 
 /* rho(0) propagated by the classical fourth-order Runge-Kutta step
- * (Sec. 2.3, Eqs. RKstep and RKintermediate), in FP64, with rates that may
+ * (Sec. 2.2.4, Eqs. RKstep and RKintermediate), in FP64, with rates that may
  * change in time: A(t) = sum_c g_c(t) A_c over 1..8 channels.  Each channel
  * A_c is a generator (checked like mjp_plan_create_csr, conservative rows)
  * and g_c(t) >= 0 is piecewise linear through the knots set with

@@ -17,9 +17,10 @@ What each function follows (Pessoa, Schweiger, Presse, arXiv 2312.05647):
   line.
 * ``loglik`` -- the snapshot likelihood p(s^i | theta) = rho(T^i)_{s^i}
   (Sec. 2.1.2), one independent solve per collection time.
-* ``mlp_*`` / ``adam_*`` -- an FP64 reference of the surrogate network, used
-  to check the GPU training kernels' gradients (the surrogate itself is not in
-  the paper).
+* ``oracle.mlp`` -- an FP64 reference of the surrogate network (forward,
+  backward, and the Adam update ``adam_step`` of Kingma and Ba, Algorithm 1,
+  with decoupled weight decay), used to check the GPU training kernels (the
+  surrogate itself is not in the paper).
 * ``oracle.krylov`` -- the Krylov-subspace propagator (Method #5, Algorithm
   ArnoldiKrylov, Eq. Krylov_expansion) in numpy FP64.
 * ``oracle.rk4`` -- the fourth-order Runge-Kutta propagator (Method #4, Eqs.

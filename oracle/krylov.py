@@ -1,5 +1,5 @@
 """FP64 CPU oracle of the Krylov-subspace propagator (Method #5 of Pessoa,
-Schweiger, Presse, arXiv 2312.05647, Sec. 2.3, Algorithm ArnoldiKrylov and
+Schweiger, Presse, arXiv 2312.05647, Sec. 2.2.5, Algorithm ArnoldiKrylov and
 Eq. Krylov_expansion): TEST INFRASTRUCTURE ONLY, like the rest of ``oracle/``.
 
 What is computed, in the paper's order and notation:

@@ -5,8 +5,12 @@ between Linear layers, mean-squared-error loss, and its gradient by the chain
 rule, written plainly in numpy float64.  Parameters use the packing of the C
 ABI: for each layer, the weight [out x in] row-major, then the bias [out].
 (The surrogate is not part of the paper; this only checks the GPU kernels.)
-Pinned by tests/test_oracle_mlp.py against central finite differences and a
-second GELU formula.
+``adam_step`` is the Adam update of Kingma and Ba (ICLR 2015, Algorithm 1)
+with decoupled weight decay (Loshchilov and Hutter, ICLR 2019) scaled by the
+step size, the form the training kernel applies.
+Pinned by tests/test_oracle_mlp.py against central finite differences, a
+second GELU formula, and closed forms of the Adam update (a constant
+gradient, a hand-derived two-step case, pure decay, the placement of eps).
 """
 from __future__ import annotations
 
@@ -75,3 +79,22 @@ def loss_and_grad(layers, X, t):
             dz = (dz @ W) * gelu_grad(zprev)
     flat = np.concatenate([np.concatenate([gW.ravel(), gb]) for gW, gb in grads])
     return loss, flat
+
+
+def adam_step(w, g, m, v, t: int, lr: float, beta1: float, beta2: float, eps: float, wd: float = 0.0):
+    """One Adam step at step number t >= 1 (Kingma and Ba, Algorithm 1):
+      m <- beta1 m + (1 - beta1) g           (first moment)
+      v <- beta2 v + (1 - beta2) g^2         (second raw moment)
+      m_hat = m / (1 - beta1^t),  v_hat = v / (1 - beta2^t)   (bias correction)
+      w <- w - lr (m_hat / (sqrt(v_hat) + eps) + wd w)
+    The last term is decoupled weight decay; eps is added outside the square
+    root.  Returns the new (w, m, v), all float64."""
+    assert t >= 1
+    w = np.asarray(w, np.float64)
+    g = np.asarray(g, np.float64)
+    m = beta1 * np.asarray(m, np.float64) + (1.0 - beta1) * g
+    v = beta2 * np.asarray(v, np.float64) + (1.0 - beta2) * g * g
+    m_hat = m / (1.0 - beta1 ** t)
+    v_hat = v / (1.0 - beta2 ** t)
+    w_new = w - lr * (m_hat / (np.sqrt(v_hat) + eps) + wd * w)
+    return w_new, m, v

@@ -1,5 +1,5 @@
 """FP64 CPU oracle of the fourth-order Runge-Kutta propagator (Method #4 of
-Pessoa, Schweiger, Presse, arXiv 2312.05647, Sec. 2.3, Eqs. RKstep and
+Pessoa, Schweiger, Presse, arXiv 2312.05647, Sec. 2.2.4, Eqs. RKstep and
 RKintermediate): TEST INFRASTRUCTURE ONLY, like the rest of ``oracle/``.
 
 The method integrates d rho / dt = rho A(t) with the classical RK4 step

@@ -1,4 +1,4 @@
-// Krylov-subspace propagator (Method #5, Sec. 2.3: Algorithm ArnoldiKrylov
+// Krylov-subspace propagator (Method #5, Sec. 2.2.5: Algorithm ArnoldiKrylov
 // and Eq. Krylov_expansion) on the GPU, in FP64.
 //
 // One step over [t, t + dt] from rho:

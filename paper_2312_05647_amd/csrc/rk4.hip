@@ -1,4 +1,4 @@
-// Fourth-order Runge-Kutta propagator (Method #4, Sec. 2.3, Eqs. RKstep
+// Fourth-order Runge-Kutta propagator (Method #4, Sec. 2.2.4, Eqs. RKstep
 // and RKintermediate) on the GPU, in FP64, with time-dependent rates.
 //
 // A(t) = sum_c g_c(t) A_c: every channel A_c is a generator (checked like a

@@ -13,7 +13,7 @@ Every state probability p(s^i | k^i, theta) comes from mjp_jump_probs (the
 paper's algorithm for J-MJP on the GPU: one sweep to max_i k^i per chain,
 reading the iterate at each observation's own k^i).  Marginalising the k^i
 gives back the exact posterior of theta, so J-MJP and the marginal samplers
-agree in distribution; the paper's point (Sec. 3.3) is that J-MJP mixes far
+agree in distribution; the paper's point (Sec. 3.2.2) is that J-MJP mixes far
 worse.  Chain bookkeeping uses torch tensors on the device; random numbers
 come from the caller's torch generator.
 """

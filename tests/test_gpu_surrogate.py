@@ -124,3 +124,41 @@ def test_bad_arguments(net):
     X = torch.zeros((10, IN), device="cuda")
     with pytest.raises(mjp.MjpError):
         mjp.mjp_surrogate_train(net, X, torch.zeros(10, device="cuda"), mjp.mjp_train_cfg_default(batch=100))
+
+
+def test_adam_update_matches_reference():
+    """Two training steps on one minibatch holding all rows; after each, the
+    FP32 master parameters are compared entry by entry with the FP64 Adam
+    update (oracle.mlp.adam_step, Kingma and Ba Algorithm 1 with decoupled
+    decay) applied to the gradient mjp_surrogate_grad returns at the same
+    parameters.  eps = 1e-3 keeps m_hat / (sqrt(v_hat) + eps) away from
+    sign(g), so the comparison sees the moments and the bias correction.
+    Bar: the training step sums the same rows in a shuffled order (FP32
+    sums, relative ~1e-6 of each gradient), and the update's derivative in g
+    is at most lr / eps = 1, so entries agree to 2e-6 + 1e-6 |w|."""
+    s = mjp.mjp_surrogate_create(IN, 64, 2, seed=1)
+    try:
+        g = synth.rng(21)
+        n = 300
+        p0 = mjp.mjp_surrogate_get_params(s)
+        x = torch.as_tensor(g.standard_normal((n, IN)), dtype=torch.float32, device="cuda").contiguous()
+        y = torch.as_tensor(g.standard_normal(n), dtype=torch.float32, device="cuda").contiguous()
+        lr, b1, b2, eps, wd = 1e-3, 0.9, 0.999, 1e-3, 0.01
+        cfg = mjp.mjp_train_cfg_default(epochs=1, batch=512, lr=lr, beta1=b1, beta2=b2, eps_adam=eps,
+                                        weight_decay=wd, seed=5)
+        m = np.zeros(p0.size)
+        v = np.zeros(p0.size)
+        w = p0.astype(np.float64)
+        for t in (1, 2):
+            _, grad = mjp.mjp_surrogate_grad(s, x, y)
+            mjp.mjp_surrogate_train(s, x, y, cfg)
+            got = mjp.mjp_surrogate_get_params(s).astype(np.float64)
+            ref, m, v = mlp.adam_step(w, grad, m, v, t, lr, b1, b2, eps, wd)
+            err = np.abs(got - ref)
+            bar = 2e-6 + 1e-6 * np.abs(ref)
+            say(f"[gpu] adam step {t}: max |w_gpu - w_ref| {err.max():.2e}, moved {np.abs(ref - w).max():.2e}")
+            assert (err <= bar).all(), (t, int(np.argmax(err - bar)), float(err.max()))
+            assert np.abs(ref - w).max() > 1e-4  # the step is not vacuous
+            w = got
+    finally:
+        mjp.mjp_surrogate_destroy(s)
