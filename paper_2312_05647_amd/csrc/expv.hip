@@ -158,6 +158,7 @@ struct SellArgs {
     const int32_t* __restrict__ slice_off;
     const int32_t* __restrict__ col;
     const float* __restrict__ val;
+    const float* __restrict__ dlo;   // lo part of each row's diagonal (entry 0 holds hi)
     const float* __restrict__ x;
     float* __restrict__ y;
     const double* __restrict__ scale;  // null -> 1
@@ -177,8 +178,10 @@ __global__ __launch_bounds__(kBlock) void k_sell_step(SellArgs a, int k, TimeSet
         const int32_t w = (a.slice_off[s + 1] - beg) >> 6;
         const int32_t* cp = a.col + beg + l;
         const float* vp = a.val + beg + l;
-        float acc = 0.f;
-        for (int32_t j = 0; j < w; ++j) acc = fmaf(vp[j * 64], a.x[cp[j * 64]], acc);
+        const float xs = a.x[row];
+        float acc = a.dlo[row] * xs;
+        acc = fmaf(vp[0], xs, acc);  // entry 0: the diagonal, column = row
+        for (int32_t j = 1; j < w; ++j) acc = fmaf(vp[j * 64], a.x[cp[j * 64]], acc);
         yv = a.scale ? (float)(*a.scale) * acc : acc;
         a.y[row] = yv;
         if (ACC) accumulate_all(ts, k, wtab, yv, out, comp, (int)row, a.n);
@@ -196,7 +199,8 @@ struct StencilArgs {
 
 // y_m = sum_n x_n b_nm for a built-in model.  The off-diagonal b_nm are the
 // FP32 products coef * count; the diagonal of a source state is 1 minus the
-// FP64 sum of exactly those FP32 numbers, so FP32 rows of B sum to 1.
+// FP64 sum of exactly those FP32 numbers, held as an FP32 pair hi + lo, so
+// rows of B sum to 1 to ~1e-16.
 __device__ __forceinline__ float stencil_row(const StencilCoef& cf, const float* __restrict__ x, int64_t m) {
     if (cf.model == MJP_MODEL_BD) {
         const int32_t N = cf.S1;
@@ -205,8 +209,10 @@ __device__ __forceinline__ float stencil_row(const StencilCoef& cf, const float*
         // exit coefficients of state i
         const float o_up = (i + 1 < N || cf.leaky) ? up : 0.f;
         const float o_dn = dn * (float)i;
-        const float diag = (float)(1.0 - ((double)o_up + (double)o_dn));
-        float y = diag * x[i];
+        float dh, dl;
+        diag_pair(1.0 - ((double)o_up + (double)o_dn), dh, dl);
+        float y = dl * x[i];
+        y = fmaf(dh, x[i], y);
         if (i > 0) y = fmaf(up, x[i - 1], y);
         if (i + 1 < N) y = fmaf(dn * (float)(i + 1), x[i + 1], y);
         return y;
@@ -219,8 +225,10 @@ __device__ __forceinline__ float stencil_row(const StencilCoef& cf, const float*
     const float o_d1 = d1 * f1;
     const float o_b2 = (i2 + 1 < S2 || cf.leaky) ? b2 * f1 : 0.f;
     const float o_d2 = d2 * f2;
-    const float diag = (float)(1.0 - (((double)o_b1 + (double)o_d1) + ((double)o_b2 + (double)o_d2)));
-    float y = diag * x[m];
+    float dh, dl;
+    diag_pair(1.0 - (((double)o_b1 + (double)o_d1) + ((double)o_b2 + (double)o_d2)), dh, dl);
+    float y = dl * x[m];
+    y = fmaf(dh, x[m], y);
     if (i1 > 0) y = fmaf(b1, x[m - 1], y);
     if (i1 + 1 < S1) y = fmaf(d1 * (f1 + 1.f), x[m + 1], y);
     if (i2 > 0) y = fmaf(b2 * f1, x[m - S1], y);
@@ -452,7 +460,8 @@ static mjp_status run_sweep(mjp_plan* p, const float* rho0, const std::vector<Sw
             if ((s = make_sets(k, fused, extra))) return s;
             const double* scale = (m > 0 && (k - 1) > 0 && (k - 1) % m == 0) ? scal + S_SCALE : nullptr;
             if (p->kind == PLAN_CSR) {
-                SellArgs a{p->slice_off.as<int32_t>(), p->col.as<int32_t>(), p->val.as<float>(), x, y, scale, n};
+                SellArgs a{p->slice_off.as<int32_t>(), p->col.as<int32_t>(), p->val.as<float>(), p->dlo.as<float>(), x, y,
+                           scale, n};
                 if (fused.n)
                     hipLaunchKernelGGL(k_sell_step<true>, dim3(nblk8), dim3(kBlock), 0, st, a, k, fused, wtab, out, comp, partials);
                 else

@@ -62,6 +62,17 @@ struct StencilCoef {
 
 constexpr int kSlice = 64;  // rows per sliced-ELL slice (= one wavefront)
 
+// A diagonal entry b_nn of B (FP64 value d) as an unevaluated pair of FP32
+// numbers hi + lo with hi = fl(d), lo = fl(d - hi): every FP32 row of B then
+// sums to its exact row sum to ~1e-16.  A row is formed as
+//   acc = lo x_m;  acc = fma(hi, x_m, acc);  acc = fma(b_nm, x_n, acc) ...
+// in every FP32 sweep, so all sweeps give the same bits.
+__host__ __device__ __forceinline__ void diag_pair(double d, float& hi, float& lo) {
+    hi = (float)d;
+    lo = (float)(d - (double)hi);
+}
+
+
 // Generator checks shared by every CSR entry point (see runtime.hip).
 mjp_status check_generator_csr(const mjp_csr* A, int leaky, double* m_theta, std::vector<double>* diag);
 // Model description checks (model id, dims, finite non-negative rates).
@@ -86,7 +97,8 @@ struct mjp_plan {
     std::vector<int32_t> slice_cmin, slice_cmax;  // column span of each slice (host)
     mjp::DevBuf slice_off;  // int32[n_slices+1]
     mjp::DevBuf col;        // int32[sell_entries]
-    mjp::DevBuf val;        // float[sell_entries]
+    mjp::DevBuf val;        // float[sell_entries]; entry 0 of each row is the diagonal's hi part
+    mjp::DevBuf dlo;        // float[n]: lo part of each row's diagonal (b_nn = hi + lo)
 
     // stencil plans
     mjp_model model{};

@@ -317,7 +317,8 @@ struct LLCoef {
 
 // New value of cell m = i1 + S1 i2 after one jump (pull form y_m = sum_n
 // rho_n b_nm).  The diagonal of B is 1 minus the FP64 sum of the state's
-// FP32 exit coefficients, the same numbers its neighbours pull.
+// FP32 exit coefficients, the same numbers its neighbours pull, held as an
+// FP32 pair hi + lo so the row sums to 1 to ~1e-16.
 template <int MODEL>
 __device__ __forceinline__ float ll_cell(const float* rho, int m, int i1, int i2, int S1, int S2, const LLCoef& k) {
     const float f1 = (float)i1;
@@ -326,8 +327,9 @@ __device__ __forceinline__ float ll_cell(const float* rho, int m, int i1, int i2
         const float f2 = (float)i2;
         const float o_b1 = (i1 + 1 < S1) ? b1 : 0.f;
         const float o_b2 = (i2 + 1 < S2) ? b2 * f1 : 0.f;
-        const float diag = (float)(1.0 - (((double)o_b1 + (double)(d1 * f1)) + ((double)o_b2 + (double)(d2 * f2))));
-        float y = diag * rho[m];
+        float dh, dl;
+        diag_pair(1.0 - (((double)o_b1 + (double)(d1 * f1)) + ((double)o_b2 + (double)(d2 * f2))), dh, dl);
+        float y = fmaf(dh, rho[m], dl * rho[m]);
         if (i1 > 0) y = fmaf(b1, rho[m - 1], y);
         if (i1 + 1 < S1) y = fmaf(d1 * (f1 + 1.f), rho[m + 1], y);
         if (i2 > 0) y = fmaf(b2 * f1, rho[m - S1], y);
@@ -339,8 +341,9 @@ __device__ __forceinline__ float ll_cell(const float* rho, int m, int i1, int i2
         const bool act = i2 == 0;
         const float o_b = (act && i1 + 1 < S1) ? be : 0.f;
         const float o_s = act ? li : la;
-        const float diag = (float)(1.0 - (((double)o_b + (double)(ga * f1)) + (double)o_s));
-        float y = diag * rho[m];
+        float dh, dl;
+        diag_pair(1.0 - (((double)o_b + (double)(ga * f1)) + (double)o_s), dh, dl);
+        float y = fmaf(dh, rho[m], dl * rho[m]);
         if (act && i1 > 0) y = fmaf(be, rho[m - 1], y);
         if (i1 + 1 < S1) y = fmaf(ga * (f1 + 1.f), rho[m + 1], y);
         y = act ? fmaf(la, rho[m + S1], y) : fmaf(li, rho[m - S1], y);
@@ -355,9 +358,11 @@ __device__ __forceinline__ float ll_cell(const float* rho, int m, int i1, int i2
         const float o_bR = (act && i1 + 1 < S1) ? k.c[0] : 0.f;
         const float o_bP = (p + 1 < NP) ? k.c[1] * f1 : 0.f;
         const float o_sw = act ? k.c[5] * fp : ((p + 1 < NP) ? k.c[4] : 0.f);
-        const float diag = (float)(1.0 - ((((double)o_bR + (double)o_bP) + ((double)(k.c[2] * f1) + (double)(k.c[3] * fp))) +
-                                          (double)o_sw));
-        float y = diag * rho[m];
+        float dh, dl;
+        diag_pair(1.0 - ((((double)o_bR + (double)o_bP) + ((double)(k.c[2] * f1) + (double)(k.c[3] * fp))) +
+                         (double)o_sw),
+                  dh, dl);
+        float y = fmaf(dh, rho[m], dl * rho[m]);
         if (act && i1 > 0) y = fmaf(k.c[0], rho[m - 1], y);               // R birth from n_R - 1
         if (p > 0) y = fmaf(k.c[1] * f1, rho[m - S1], y);                 // P birth from n_P - 1
         if (i1 + 1 < S1) y = fmaf(k.c[2] * (f1 + 1.f), rho[m + 1], y);    // R death from n_R + 1

@@ -56,6 +56,7 @@ struct PersistArgs {
     const int32_t* __restrict__ slice_off;
     const int32_t* __restrict__ col;
     const float* __restrict__ val;
+    const float* __restrict__ dlo;    // CSR: lo part of each row's diagonal (entry 0 holds hi)
     StencilCoef cf;
     const float* __restrict__ rho0;
     float* __restrict__ buf0;
@@ -199,9 +200,13 @@ __global__ __launch_bounds__(kPThreads) void k_persistent(PersistArgs a) {
 
     // ---- operator into registers
     // column of each entry, held as a 32-bit byte offset into the iterate so
-    // each gather is a 32-bit register offset on a uniform base (n < 2^30)
+    // each gather is a 32-bit register offset on a uniform base (n < 2^30).
+    // Entry 0 is the diagonal (hi part; lo in dlo): its column is the row
+    // itself, whose previous value the thread already holds, so coff[i][0]
+    // is never read.
     uint32_t coff[R][W];
     float cval[R][W];
+    float dlo[R];
     if (CSR) {
 #pragma unroll
         for (int i = 0; i < R; ++i) {
@@ -221,6 +226,7 @@ __global__ __launch_bounds__(kPThreads) void k_persistent(PersistArgs a) {
                     cval[i][j] = 0.f;
                 }
             }
+            dlo[i] = live(i) ? a.dlo[row(i)] : 0.f;
         }
     } else {
         // stencil: neighbour offsets and coefficients of each row (W == 5:
@@ -241,7 +247,9 @@ __global__ __launch_bounds__(kPThreads) void k_persistent(PersistArgs a) {
             const float o_d1 = d1 * f1;
             const float o_b2 = (i2 + 1 < S2 || cf.leaky) ? b2 * f1 : 0.f;
             const float o_d2 = d2 * f2;
-            float diag = (float)(1.0 - (((double)o_b1 + (double)o_d1) + ((double)o_b2 + (double)o_d2)));
+            float diag, dl;
+            diag_pair(1.0 - (((double)o_b1 + (double)o_d1) + ((double)o_b2 + (double)o_d2)), diag, dl);
+            dlo[i] = live(i) ? dl : 0.f;
             int32_t cc[5] = {(int32_t)m, (int32_t)m, (int32_t)m, (int32_t)m, (int32_t)m};
             float vv[5] = {diag, 0.f, 0.f, 0.f, 0.f};
             if (i1 > 0) { cc[1] = (int32_t)m - 1; vv[1] = b1; }
@@ -411,17 +419,19 @@ __global__ __launch_bounds__(kPThreads) void k_persistent(PersistArgs a) {
         for (int i = 0; i < R; ++i) {
             if ((lmask >> i) & 1u) {
 #pragma unroll
-                for (int j = 0; j < W; ++j) xv[i][j] = *reinterpret_cast<const float*>(xl + coff[i][j]);
+                for (int j = 1; j < W; ++j) xv[i][j] = *reinterpret_cast<const float*>(xl + coff[i][j]);
             } else {
 #pragma unroll
-                for (int j = 0; j < W; ++j) xv[i][j] = ld_iter<COH>(x, coff[i][j]);
+                for (int j = 1; j < W; ++j) xv[i][j] = ld_iter<COH>(x, coff[i][j]);
             }
         }
 #pragma unroll
         for (int i = 0; i < R; ++i) {
-            float acc = 0.f;
+            // the row's own previous value is yv[i]
+            float acc = dlo[i] * yv[i];
+            acc = fmaf(cval[i][0], yv[i], acc);
 #pragma unroll
-            for (int j = 0; j < W; ++j) acc = fmaf(cval[i][j], xv[i][j], acc);
+            for (int j = 1; j < W; ++j) acc = fmaf(cval[i][j], xv[i][j], acc);
             yv[i] = fs * acc;
             part += (double)yv[i];
         }
@@ -514,15 +524,18 @@ constexpr int kP2Slots = 2;                      // open windows held in registe
 
 template <int W>
 constexpr size_t p2_lds_bytes() {
-    return sizeof(float) * (kP2X2 + kP2X1) + sizeof(uint2) * (size_t)kP2Halo * W;
+    return sizeof(float) * (kP2X2 + kP2X1) + sizeof(uint2) * (size_t)kP2Halo * W + sizeof(float) * kP2Halo;
 }
 
 // Entries of pull row m (column, value) in the order the one-jump kernel
-// keeps them in registers; absent entries read row m with weight 0.
+// keeps them in registers (entry 0: the diagonal's hi part, column m) and
+// the diagonal's lo part; absent entries read row m with weight 0.
 template <int W, bool CSR>
-__device__ __forceinline__ void row_entries(const PersistArgs& a, int64_t m, int32_t (&cc)[W], float (&vv)[W]) {
+__device__ __forceinline__ void row_entries(const PersistArgs& a, int64_t m, int32_t (&cc)[W], float (&vv)[W],
+                                            float& lo) {
     if constexpr (CSR) {
         const int s = (int)(m >> 6), l = (int)(m & 63);
+        lo = a.dlo[m];
         int beg = 0, w = 0;
         if (s < a.n_slices) {
             beg = a.slice_off[s];
@@ -551,7 +564,8 @@ __device__ __forceinline__ void row_entries(const PersistArgs& a, int64_t m, int
         const float o_d1 = d1 * f1;
         const float o_b2 = (i2 + 1 < S2 || cf.leaky) ? b2 * f1 : 0.f;
         const float o_d2 = d2 * f2;
-        const float diag = (float)(1.0 - (((double)o_b1 + (double)o_d1) + ((double)o_b2 + (double)o_d2)));
+        float diag;
+        diag_pair(1.0 - (((double)o_b1 + (double)o_d1) + ((double)o_b2 + (double)o_d2)), diag, lo);
         int32_t c5[5] = {(int32_t)m, (int32_t)m, (int32_t)m, (int32_t)m, (int32_t)m};
         float v5[5] = {diag, 0.f, 0.f, 0.f, 0.f};
         if (i1 > 0) { c5[1] = (int32_t)m - 1; v5[1] = b1; }
@@ -576,6 +590,7 @@ __global__ __launch_bounds__(kPThreads) void k_persistent2(PersistArgs a) {
     // [j][h]: consecutive lanes (consecutive halo rows) read consecutive
     // 8-byte words, free of bank conflicts
     uint2* hent = reinterpret_cast<uint2*>(X1 + kP2X1);
+    float* hlo = reinterpret_cast<float*>(hent + (size_t)kP2Halo * W);  // halo rows' diagonal lo parts
     __shared__ double red[kPWaves + 1];
     const int G = a.G;
     const int g = logical_block(G);
@@ -590,29 +605,34 @@ __global__ __launch_bounds__(kPThreads) void k_persistent2(PersistArgs a) {
     auto row = [&](int i) { return row0 + 64 * i; };
     auto live = [&](int i) { return (int64_t)(row0 + 64 * i) < n; };
 
-    // own rows' operator in registers (byte offsets of absolute columns)
+    // own rows' operator in registers (byte offsets of absolute columns;
+    // entry 0 is the diagonal, whose column is the row itself: its value is
+    // the thread's own yv[i], so coff[i][0] is never read)
     uint32_t coff[R][W];
     float cval[R][W];
+    float dlo[R];
 #pragma unroll
     for (int i = 0; i < R; ++i) {
         int32_t cc[W];
-        float vv[W];
-        row_entries<W, CSR>(a, live(i) ? (int64_t)row(i) : 0, cc, vv);
+        float vv[W], lo;
+        row_entries<W, CSR>(a, live(i) ? (int64_t)row(i) : 0, cc, vv, lo);
 #pragma unroll
         for (int j = 0; j < W; ++j) {
             coff[i][j] = live(i) ? 4u * (uint32_t)cc[j] : 4u * (uint32_t)e1lo;
             cval[i][j] = live(i) ? vv[j] : 0.f;
         }
+        dlo[i] = live(i) ? lo : 0.f;
     }
     // halo rows' entries in LDS
     for (int h = tid; h < nh; h += kPThreads) {
         const int m = h < nlo ? e1lo + h : r1 + (h - nlo);
         int32_t cc[W];
-        float vv[W];
-        row_entries<W, CSR>(a, m, cc, vv);
+        float vv[W], lo;
+        row_entries<W, CSR>(a, m, cc, vv, lo);
 #pragma unroll
         for (int j = 0; j < W; ++j)
             hent[j * kP2Halo + h] = make_uint2(4u * (uint32_t)(cc[j] - e2lo), __builtin_bit_cast(uint32_t, vv[j]));
+        hlo[h] = lo;
     }
 
     // ---- k = 0
@@ -742,12 +762,13 @@ __global__ __launch_bounds__(kPThreads) void k_persistent2(PersistArgs a) {
 #pragma unroll
             for (int i = 0; i < R; ++i)
 #pragma unroll
-                for (int j = 0; j < W; ++j) xv[i][j] = *reinterpret_cast<const float*>(x2b + coff[i][j]);
+                for (int j = 1; j < W; ++j) xv[i][j] = *reinterpret_cast<const float*>(x2b + coff[i][j]);
 #pragma unroll
             for (int i = 0; i < R; ++i) {
-                float acc = 0.f;
+                float acc = dlo[i] * yv[i];  // yv[i]: the row's x_k
+                acc = fmaf(cval[i][0], yv[i], acc);
 #pragma unroll
-                for (int j = 0; j < W; ++j) acc = fmaf(cval[i][j], xv[i][j], acc);
+                for (int j = 1; j < W; ++j) acc = fmaf(cval[i][j], xv[i][j], acc);
                 yv[i] = fs * acc;
             }
             if (nh > 0) {
@@ -770,7 +791,7 @@ __global__ __launch_bounds__(kPThreads) void k_persistent2(PersistArgs a) {
 #pragma unroll
                     for (int u = 0; u < kB; ++u) {
                         const int h = tid + (u0 + u) * kPThreads;
-                        float acc = 0.f;
+                        float acc = hlo[min(h, nh - 1)] * hx[u][0];  // entry 0: the diagonal
 #pragma unroll
                         for (int j = 0; j < W; ++j) acc = fmaf(__builtin_bit_cast(float, e[u][j].y), hx[u][j], acc);
                         if (h < nh) X1[h < nlo ? h : (r1 - e1lo) + (h - nlo)] = fs * acc;
@@ -792,12 +813,13 @@ __global__ __launch_bounds__(kPThreads) void k_persistent2(PersistArgs a) {
 #pragma unroll
             for (int i = 0; i < R; ++i)
 #pragma unroll
-                for (int j = 0; j < W; ++j) xv[i][j] = *reinterpret_cast<const float*>(x1b + coff[i][j]);
+                for (int j = 1; j < W; ++j) xv[i][j] = *reinterpret_cast<const float*>(x1b + coff[i][j]);
 #pragma unroll
             for (int i = 0; i < R; ++i) {
-                float acc = 0.f;
+                float acc = dlo[i] * yv[i];  // yv[i]: the row's x_{k+1}
+                acc = fmaf(cval[i][0], yv[i], acc);
 #pragma unroll
-                for (int j = 0; j < W; ++j) acc = fmaf(cval[i][j], xv[i][j], acc);
+                for (int j = 1; j < W; ++j) acc = fmaf(cval[i][j], xv[i][j], acc);
                 yv[i] = 1.0f * acc;
                 part += (double)yv[i];
             }
@@ -1154,6 +1176,7 @@ mjp_status launch_persistent(mjp_plan* p, const PersistCfg& cfg, const float* rh
     a.slice_off = p->slice_off.as<int32_t>();
     a.col = p->col.as<int32_t>();
     a.val = p->val.as<float>();
+    a.dlo = p->dlo.as<float>();
     a.cf = p->coef;
     a.rho0 = rho0;
     a.buf0 = p->rho[0].as<float>();

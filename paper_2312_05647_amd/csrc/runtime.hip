@@ -395,6 +395,7 @@ void mjp_plan_destroy(mjp_plan* p) {
     p->slice_off.release();
     p->col.release();
     p->val.release();
+    p->dlo.release();
     for (auto& b : p->rho) b.release();
     p->comp.release();
     p->wait.release();
@@ -490,13 +491,19 @@ mjp_status mjp_plan_create_csr(const mjp_csr* A, const mjp_opts* opts, mjp_plan*
     }
 
     // B = I + A/Omega in FP32, pull form (row m of B^T lists b_nm over n).
-    // b_nn = (exact row sum of B) - (FP64 sum of the row's FP32 off-diagonals),
-    // so each FP32 row of B has the row sum of the exact B up to the rounding
-    // of b_nn: 1 under conservative truncation, 1 - (leaked rate)/Omega under
-    // the leaky reading.
+    // The diagonal is held as an unevaluated pair of FP32 numbers hi + lo:
+    // b_nn = (exact row sum of B) - (FP64 sum of the row's FP32
+    // off-diagonals), hi = fl(b_nn), lo = fl(b_nn - hi).  Each row of B then
+    // sums to the exact row sum (1 under conservative truncation,
+    // 1 - leaked rate/Omega under the leaky reading) to ~1e-16.  A single
+    // FP32 diagonal leaves up to 2^-25 per row, a state-dependent gain or
+    // loss of mass that the same state repeats at every jump; over thousands
+    // of jumps it distorts the result far more than the rounding of the
+    // off-diagonal rates, which conserves mass.  Entry 0 of every pull row is
+    // the diagonal (column = the row itself); lo is stored per row.
     const double omega = p->omega > 0.0 ? p->omega : 1.0;
     std::vector<int32_t> cnt((size_t)n + 1, 0);
-    std::vector<float> bdiag((size_t)n);
+    std::vector<float> bdiag((size_t)n), bdlo((size_t)n);
     for (int32_t r = 0; r < n; ++r) {
         double off = 0.0;
         for (int32_t i = A->row_ptr[r]; i < A->row_ptr[r + 1]; ++i) {
@@ -512,7 +519,9 @@ mjp_status mjp_plan_create_csr(const mjp_csr* A, const mjp_opts* opts, mjp_plan*
                 if (A->col_idx[i] != r) exact_off += A->val[i];
             target = 1.0 + (exact_off + diag[(size_t)r]) / omega;
         }
-        bdiag[(size_t)r] = (float)(target - off);
+        const double dex = target - off;
+        bdiag[(size_t)r] = (float)dex;
+        bdlo[(size_t)r] = (float)(dex - (double)bdiag[(size_t)r]);
         cnt[(size_t)r]++;  // the diagonal is always present in B
     }
     const int32_t n_slices = (n + kSlice - 1) / kSlice;
@@ -546,14 +555,12 @@ mjp_status mjp_plan_create_csr(const mjp_csr* A, const mjp_opts* opts, mjp_plan*
         hval[at] = v;
         fill[(size_t)m]++;
     };
+    for (int32_t r = 0; r < n; ++r) put(r, r, bdiag[(size_t)r]);  // entry 0: the diagonal
     for (int32_t r = 0; r < n; ++r) {  // r = source state n; entries go to output row m = col
-        bool diag_done = false;
         for (int32_t i = A->row_ptr[r]; i < A->row_ptr[r + 1]; ++i) {
             const int32_t c = A->col_idx[i];
-            if (c == r) { put(r, r, bdiag[(size_t)r]); diag_done = true; }
-            else put(c, r, (float)(A->val[i] / omega));
+            if (c != r) put(c, r, (float)(A->val[i] / omega));
         }
-        if (!diag_done) put(r, r, bdiag[(size_t)r]);
     }
     p->slice_cmin.assign((size_t)n_slices, INT32_MAX);
     p->slice_cmax.assign((size_t)n_slices, -1);
@@ -567,7 +574,8 @@ mjp_status mjp_plan_create_csr(const mjp_csr* A, const mjp_opts* opts, mjp_plan*
     p->max_width = max_w;
     if ((st = p->slice_off.reserve(sizeof(int32_t) * slice_off.size())) ||
         (st = p->col.reserve(sizeof(int32_t) * (size_t)std::max<int64_t>(total, 1))) ||
-        (st = p->val.reserve(sizeof(float) * (size_t)std::max<int64_t>(total, 1)))) {
+        (st = p->val.reserve(sizeof(float) * (size_t)std::max<int64_t>(total, 1))) ||
+        (st = p->dlo.reserve(sizeof(float) * (size_t)std::max<int32_t>(n, 1)))) {
         mjp_plan_destroy(p);
         return st;
     }
@@ -577,7 +585,8 @@ mjp_status mjp_plan_create_csr(const mjp_csr* A, const mjp_opts* opts, mjp_plan*
                           : hipSuccess;
     hipError_t e3 = total ? hipMemcpy(p->val.ptr, hval.data(), sizeof(float) * (size_t)total, hipMemcpyHostToDevice)
                           : hipSuccess;
-    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+    hipError_t e4 = hipMemcpy(p->dlo.ptr, bdlo.data(), sizeof(float) * (size_t)n, hipMemcpyHostToDevice);
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess) {
         mjp_plan_destroy(p);
         return fail(MJP_E_DEVICE, "upload of the operator failed");
     }

@@ -2,12 +2,12 @@
 Sec. 3.1.2; autoregulatory gene network, Sec. 3.1.3) through the C ABI.
 
 * Propagation through CSR plans (mjp_model_csr -> mjp_plan_create_csr ->
-  mjp_expv) against the FP64 oracle, persistent and stepwise.  Bar from the
-  FP32 arithmetic: each jump forms every entry from at most five rounded
-  products and sums (relative error <= 3u, u = 2^-24, with the corrected
-  diagonal keeping the mass), and these errors accumulate like a random walk
-  over the K jumps, so L1 <= max(1e-6, 4 u sqrt(K)); entrywise relative
-  <= 1e-4 where p > 1e-7.  (The headline workload keeps its fixed 1e-6.)
+  mjp_expv) against the FP64 oracle, persistent and stepwise, at the fixed
+  bar L1 <= 1e-6 of every FP32 result, and entrywise relative <= 1e-4 where
+  p > 1e-7.  The two-state case is the sensitive one: with B's diagonal as
+  a single FP32 number each row sums to 1 only to 2^-25, a per-state gain or
+  loss of mass repeated at every one of the ~4000 jumps, which left L1 at
+  1.4e-6 (t = 10); the diagonal is now an FP32 pair hi + lo.
 * Batched log-likelihoods with the gene state hidden (mjp_loglik sums a
   record's probability over it) against the oracle's marginal definition:
   |l_gpu - l_oracle| <= sum_i c_i (2e-6 + 2e-9 / p_i), the log-likelihood bar.
@@ -49,7 +49,7 @@ def check(got, ref, what, K):
     l1 = np.abs(got - ref).sum()
     big = ref > 1e-7
     rel = (np.abs(got - ref)[big] / ref[big]).max()
-    bar = max(1e-6, 4 * 2.0 ** -24 * np.sqrt(K))
+    bar = 1e-6
     say(f"    {what}: K {K}  L1 {l1:.3e} (bar {bar:.2e})  rel {rel:.2e}")
     assert l1 <= bar and rel <= 1e-4, (what, l1, bar, rel)
     return l1
