@@ -275,11 +275,22 @@ typedef struct {
  *   loglik_d [B] FP64 device
  *   info_d   [B] device or NULL (omega, W of the last time, K, L of the last
  *            time, flags, mass_out = final mass of the iterate)
- * Asynchronous.  The first call with new observations uploads them
- * (synchronously) and a larger B grows per-device work buffers; a call after
- * one with the same observations and at least this B only enqueues kernels,
- * so it may be captured in a hipGraph.  A later call that grows the buffers
- * invalidates such a graph. */
+ * Asynchronous on `stream`.  Buffers (library-owned, per device):
+ *   - each distinct observation set (records and times) is uploaded once, by
+ *     copies enqueued on the stream of the first call that uses it, into
+ *     device buffers that are never rewritten, so kernels still in flight and
+ *     captured graphs keep the records they were given; the 256 most recently
+ *     used sets are kept (an older one is freed after a device
+ *     synchronisation);
+ *   - the work tables (windows, costs, order, queue counters) are kept per
+ *     stream (64 streams; an older stream's are freed likewise), so calls on
+ *     different streams never share them; a call with more items than its
+ *     stream had before grows them (hipMalloc/hipFree).
+ * A call on a stream that already ran one with at least this B and the same
+ * observation set only enqueues kernels, so it may be captured in a hipGraph.
+ * The graph uses that stream's work tables: it is invalidated by a later call
+ * on the stream that grows them, and must not be replayed while another call
+ * on that stream runs. */
 mjp_status mjp_loglik(int32_t model, int32_t B, const double* theta_d, const int32_t* dims_d,
                       const mjp_obs* obs, const mjp_opts* opts, double* loglik_d,
                       mjp_info* info_d, mjp_stream_t stream);

@@ -28,6 +28,7 @@
 #include <array>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <utility>
 #include <vector>
@@ -638,12 +639,49 @@ inline bool ll_eligible(int shape, int cls, int n_rec) {
            n_rec <= kLLRecPerThread * kLLShapes[shape].T;
 }
 
+// ---------------------------------------------------------------- host state
+//
+// Per device, kept until the process ends:
+//  * kernel attributes, occupancies and the chosen shape per (model, class);
+//  * every observation set seen so far, in its own device buffers, written
+//    once by a copy on the stream of the first call that used it and never
+//    rewritten: work already enqueued, and a graph captured from a call, keep
+//    reading the records they were enqueued with;
+//  * the work tables (windows, costs, order, queue counters, class offsets)
+//    per stream, so calls on different streams never share them.
+constexpr int kLLMaxObsSets = 256;  // kept per device; the least recently used is freed beyond that
+constexpr int kLLMaxStreams = 64;   // work tables per device; likewise
+constexpr int kLLMaxDevices = 64;
+
+static_assert(sizeof(LLRecord) == 4 * sizeof(int32_t), "records are the caller's (t, x1, x2, count) rows");
+
+struct LLObsSet {
+    std::vector<LLRecord> rec;
+    std::vector<double> T;
+    DevBuf rec_d, T_d;
+};
+
+struct LLWork {
+    hipStream_t stream = nullptr;
+    DevBuf win, cost, order, queue, cls_off;
+};
+
+// Device tables of one call.
+struct LLBufs {
+    const LLRecord* rec = nullptr;
+    const double* T = nullptr;
+    LLWin* win = nullptr;
+    float* cost = nullptr;
+    int32_t* order = nullptr;
+    unsigned* queue = nullptr;
+    int32_t* cls_off = nullptr;
+};
+
 struct LLContext {
     std::mutex mu;
-    int device = -1;
-    DevBuf rec, T, win, cost, order, queue, cls_off;
-    std::vector<LLRecord> rec_host;
-    std::vector<double> T_host;
+    int device = -1, ncu = 0;
+    std::vector<std::unique_ptr<LLObsSet>> obs;  // most recently used first
+    std::vector<std::unique_ptr<LLWork>> work;
     bool attr_set = false;
     int occ[4][kLLNumShapes] = {};  // resident workgroups per CU (0 = not queried)
     int occ_jp[4][kLLClasses] = {};  // the same for the jump-mode kernels
@@ -655,8 +693,8 @@ struct LLContext {
 };
 
 static LLContext& ctx_for(int dev) {
-    static LLContext ctxs[64];
-    return ctxs[dev & 63];
+    static LLContext ctxs[kLLMaxDevices];
+    return ctxs[dev];
 }
 
 }  // namespace mjp
@@ -665,48 +703,123 @@ using namespace mjp;
 
 namespace mjp {
 
-// per-call buffers, kernel attributes and the argument block
-static mjp_status ll_setup(LLContext& C, int model, int B, const mjp_obs* obs, const mjp_opts* opts,
-                           const double* theta_d, const int32_t* dims_d, double* loglik_d, mjp_info* info_d,
-                           LLArgs& a) {
-    mjp_status st;
-    if ((st = C.win.reserve(sizeof(LLWin) * (size_t)B * obs->n_t)) || (st = C.cost.reserve(sizeof(float) * B)) ||
-        (st = C.order.reserve(sizeof(int32_t) * B)) || (st = C.queue.reserve(64)) ||
-        (st = C.cls_off.reserve(sizeof(int32_t) * (kLLClasses + 1))))
-        return st;
-    if (!C.attr_set) {
-        for (int m = 0; m < 4; ++m)
-            for (int sid = 0; sid < kLLNumShapes; ++sid) {
-                MJP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kLLMains[m][sid]),
-                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)ll_lds(sid)));
-                int nb = 0;
-                MJP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kLLMains[m][sid], kLLShapes[sid].T,
-                                                                     ll_lds(sid)));
-                C.occ[m][sid] = std::max(nb, 1);
-            }
-        for (int m = 0; m < 4; ++m)
-            for (int c = 0; c < kLLClasses; ++c) {
-                const int sid = kLLDefaultShape[c];
-                MJP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kJpMains[m][c]),
-                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)ll_lds(sid)));
-                int nb = 0;
-                MJP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kJpMains[m][c], kLLShapes[sid].T, ll_lds(sid)));
-                C.occ_jp[m][c] = std::max(nb, 1);
-            }
-        MJP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_ll_order), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)(sizeof(unsigned long long) * kLLMaxSort)));
-        C.attr_set = true;
+// kernel attributes and occupancies, once per device
+static mjp_status ll_attrs(LLContext& C, int dev) {
+    if (C.attr_set) return MJP_OK;
+    for (int m = 0; m < 4; ++m)
+        for (int sid = 0; sid < kLLNumShapes; ++sid) {
+            MJP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kLLMains[m][sid]),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)ll_lds(sid)));
+            int nb = 0;
+            MJP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kLLMains[m][sid], kLLShapes[sid].T, ll_lds(sid)));
+            C.occ[m][sid] = std::max(nb, 1);
+        }
+    for (int m = 0; m < 4; ++m)
+        for (int c = 0; c < kLLClasses; ++c) {
+            const int sid = kLLDefaultShape[c];
+            MJP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kJpMains[m][c]),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)ll_lds(sid)));
+            int nb = 0;
+            MJP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kJpMains[m][c], kLLShapes[sid].T, ll_lds(sid)));
+            C.occ_jp[m][c] = std::max(nb, 1);
+        }
+    MJP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_ll_order), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)(sizeof(unsigned long long) * kLLMaxSort)));
+    MJP_HIP(hipDeviceGetAttribute(&C.ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    C.device = dev;
+    C.attr_set = true;
+    return MJP_OK;
+}
+
+// The device copy of an observation set: found among the sets seen before,
+// or uploaded once with a copy on stream s (from host vectors the set keeps).
+static mjp_status ll_obs(LLContext& C, const std::vector<LLRecord>& recs, const mjp_obs* obs, hipStream_t s,
+                         LLBufs& bf) {
+    const size_t nrec = recs.size(), nt = (size_t)obs->n_t;
+    for (size_t i = 0; i < C.obs.size(); ++i) {
+        LLObsSet& o = *C.obs[i];
+        if (o.rec.size() != nrec || o.T.size() != nt) continue;
+        if (nrec && std::memcmp(o.rec.data(), recs.data(), sizeof(LLRecord) * nrec) != 0) continue;
+        if (std::memcmp(o.T.data(), obs->T_h, sizeof(double) * nt) != 0) continue;
+        if (i > 0) std::rotate(C.obs.begin(), C.obs.begin() + i, C.obs.begin() + i + 1);
+        bf.rec = C.obs[0]->rec_d.as<LLRecord>();
+        bf.T = C.obs[0]->T_d.as<double>();
+        return MJP_OK;
     }
-    a = LLArgs{};
+    if ((int)C.obs.size() >= kLLMaxObsSets) {  // free the least recently used set once nothing reads it
+        MJP_HIP(hipDeviceSynchronize());
+        C.obs.back()->rec_d.release();
+        C.obs.back()->T_d.release();
+        C.obs.pop_back();
+    }
+    std::unique_ptr<LLObsSet> o(new (std::nothrow) LLObsSet());
+    MJP_CHECK(o, MJP_E_DEVICE, "out of host memory");
+    o->rec = recs;
+    o->T.assign(obs->T_h, obs->T_h + nt);
+    mjp_status st;
+    if ((st = o->rec_d.reserve(sizeof(LLRecord) * std::max<size_t>(nrec, 1))) ||
+        (st = o->T_d.reserve(sizeof(double) * nt)))
+        return st;
+    if (nrec) MJP_HIP(hipMemcpyAsync(o->rec_d.ptr, o->rec.data(), sizeof(LLRecord) * nrec, hipMemcpyHostToDevice, s));
+    MJP_HIP(hipMemcpyAsync(o->T_d.ptr, o->T.data(), sizeof(double) * nt, hipMemcpyHostToDevice, s));
+    bf.rec = o->rec_d.as<LLRecord>();
+    bf.T = o->T_d.as<double>();
+    C.obs.insert(C.obs.begin(), std::move(o));
+    return MJP_OK;
+}
+
+// The work tables of stream s, grown to B items of n_t times.
+static mjp_status ll_work(LLContext& C, hipStream_t s, int B, int n_t, LLBufs& bf) {
+    LLWork* w = nullptr;
+    for (size_t i = 0; i < C.work.size(); ++i)  // most recently used first
+        if (C.work[i]->stream == s) {
+            if (i > 0) std::rotate(C.work.begin(), C.work.begin() + i, C.work.begin() + i + 1);
+            w = C.work[0].get();
+            break;
+        }
+    if (!w) {
+        if ((int)C.work.size() >= kLLMaxStreams) {  // free the least recently used stream's tables
+            MJP_HIP(hipDeviceSynchronize());
+            LLWork& old = *C.work.back();
+            old.win.release();
+            old.cost.release();
+            old.order.release();
+            old.queue.release();
+            old.cls_off.release();
+            C.work.pop_back();
+        }
+        std::unique_ptr<LLWork> nw(new (std::nothrow) LLWork());
+        MJP_CHECK(nw, MJP_E_DEVICE, "out of host memory");
+        nw->stream = s;
+        C.work.insert(C.work.begin(), std::move(nw));
+        w = C.work[0].get();
+    }
+    mjp_status st;
+    if ((st = w->win.reserve(sizeof(LLWin) * (size_t)B * n_t)) || (st = w->cost.reserve(sizeof(float) * B)) ||
+        (st = w->order.reserve(sizeof(int32_t) * B)) || (st = w->queue.reserve(64)) ||
+        (st = w->cls_off.reserve(sizeof(int32_t) * (kLLClasses + 1))))
+        return st;
+    bf.win = w->win.as<LLWin>();
+    bf.cost = w->cost.as<float>();
+    bf.order = w->order.as<int32_t>();
+    bf.queue = w->queue.as<unsigned>();
+    bf.cls_off = w->cls_off.as<int32_t>();
+    return MJP_OK;
+}
+
+// the argument block of a call
+static LLArgs ll_args(int model, int B, const mjp_obs* obs, const mjp_opts* opts, const double* theta_d,
+                      const int32_t* dims_d, double* loglik_d, mjp_info* info_d, const LLBufs& bf) {
+    LLArgs a{};
     a.theta = theta_d;
     a.dims = dims_d;
-    a.T = C.T.as<double>();
-    a.rec = C.rec.as<LLRecord>();
-    a.win = C.win.as<LLWin>();
-    a.cost = C.cost.as<float>();
-    a.order = C.order.as<int32_t>();
-    a.queue = C.queue.as<unsigned>();
-    a.cls_off = C.cls_off.as<int32_t>();
+    a.T = bf.T;
+    a.rec = bf.rec;
+    a.win = bf.win;
+    a.cost = bf.cost;
+    a.order = bf.order;
+    a.queue = bf.queue;
+    a.cls_off = bf.cls_off;
     a.loglik = loglik_d;
     a.info = info_d;
     a.B = B;
@@ -721,7 +834,7 @@ static mjp_status ll_setup(LLContext& C, int model, int B, const mjp_obs* obs, c
     a.lump = opts->lump;
     a.renorm_every = opts->truncation == MJP_CONSERVATIVE ? opts->renorm_every : 0;
     a.k_cap = opts->k_cap;
-    return MJP_OK;
+    return a;
 }
 
 // windows, costs, classes and the order (also zeroes the class queues)
@@ -736,9 +849,7 @@ static void ll_prepare(const LLArgs& a, hipStream_t s) {
 
 // the items of class c with shape sid: as many workgroups as fit on the chip
 static void ll_launch(const LLContext& C, const LLArgs& a, int cls, int sid, hipStream_t s) {
-    int ncu = 0;
-    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, C.device);
-    const int grid = std::max(1, std::min(a.B, std::max(ncu, 1) * C.occ[a.model][sid]));
+    const int grid = std::max(1, std::min(a.B, std::max(C.ncu, 1) * C.occ[a.model][sid]));
     hipLaunchKernelGGL(kLLMains[a.model][sid], dim3(grid), dim3(kLLShapes[sid].T), ll_lds(sid), s, a, cls);
 }
 
@@ -750,9 +861,10 @@ extern "C" int32_t mjp_loglik_max_states(void) { return kLLMaxStates; }
 
 namespace mjp {
 
-// host checks of a log-likelihood call; the records in kernel form
+// host checks of a log-likelihood call; the records in kernel form (recs may
+// be null: check only)
 static mjp_status ll_check(int32_t model, int32_t B, const mjp_obs* obs, const mjp_opts* opts,
-                           std::vector<LLRecord>& recs) {
+                           std::vector<LLRecord>* recs) {
     MJP_CHECK(model >= MJP_MODEL_BD && model <= MJP_MODEL_AUTOREG, MJP_E_INVALID_ARG, "unknown model %d", model);
     MJP_CHECK(B >= 0, MJP_E_INVALID_ARG, "B must be >= 0");
     mjp_status st = check_opts(opts);
@@ -768,7 +880,7 @@ static mjp_status ll_check(int32_t model, int32_t B, const mjp_obs* obs, const m
               MJP_E_INVALID_ARG, "bad initial state");
     for (int j = 0; j < obs->n_t; ++j)
         MJP_CHECK(std::isfinite(obs->T_h[j]) && obs->T_h[j] >= 0.0, MJP_E_INVALID_ARG, "T[%d] must be finite, >= 0", j);
-    recs.resize((size_t)obs->n_obs);
+    if (recs) recs->resize((size_t)obs->n_obs);
     for (int i = 0; i < obs->n_obs; ++i) {
         const int32_t* r = obs->obs_h + 4 * (size_t)i;
         MJP_CHECK(r[0] >= 0 && r[0] < obs->n_t, MJP_E_INVALID_ARG, "record %d: time index out of range", i);
@@ -776,36 +888,21 @@ static mjp_status ll_check(int32_t model, int32_t B, const mjp_obs* obs, const m
         MJP_CHECK((model != MJP_MODEL_BD && model != MJP_MODEL_TWOSTATE) || r[2] == 0, MJP_E_INVALID_ARG,
                   "record %d: x2 must be 0 for a one-count model", i);
         MJP_CHECK(r[3] >= 1, MJP_E_INVALID_ARG, "record %d: count must be >= 1", i);
-        recs[(size_t)i] = {r[0], r[1], r[2], r[3]};
+        if (recs) (*recs)[(size_t)i] = {r[0], r[1], r[2], r[3]};
     }
-    return MJP_OK;
-}
-
-// observation tables are uploaded only when they change, so repeated calls
-// with the same data enqueue kernels only (graph-capturable)
-static mjp_status ll_upload(LLContext& C, int dev, const std::vector<LLRecord>& recs, const mjp_obs* obs) {
-    mjp_status st;
-    const bool same_rec = C.device == dev && C.rec_host.size() == recs.size() &&
-                          (recs.empty() || std::memcmp(C.rec_host.data(), recs.data(), sizeof(LLRecord) * recs.size()) == 0);
-    const bool same_T = C.device == dev && C.T_host.size() == (size_t)obs->n_t &&
-                        std::memcmp(C.T_host.data(), obs->T_h, sizeof(double) * obs->n_t) == 0;
-    if (!same_rec) {
-        if ((st = C.rec.reserve(sizeof(LLRecord) * std::max<size_t>(recs.size(), 1)))) return st;
-        if (!recs.empty()) MJP_HIP(hipMemcpy(C.rec.ptr, recs.data(), sizeof(LLRecord) * recs.size(), hipMemcpyHostToDevice));
-        C.rec_host = recs;
-    }
-    if (!same_T) {
-        if ((st = C.T.reserve(sizeof(double) * obs->n_t))) return st;
-        MJP_HIP(hipMemcpy(C.T.ptr, obs->T_h, sizeof(double) * obs->n_t, hipMemcpyHostToDevice));
-        C.T_host.assign(obs->T_h, obs->T_h + obs->n_t);
-    }
-    C.device = dev;
     return MJP_OK;
 }
 
 inline int ll_effective(const LLContext& C, int model, int cls, int n_rec) {
     const int sid = C.shape[model][cls];
     return (sid < 0 || !ll_eligible(sid, cls, n_rec)) ? kLLDefaultShape[cls] : sid;
+}
+
+// current device, checked against the table size
+static mjp_status ll_device(int& dev) {
+    MJP_HIP(hipGetDevice(&dev));
+    MJP_CHECK(dev >= 0 && dev < kLLMaxDevices, MJP_E_UNSUPPORTED, "device %d: at most %d devices", dev, kLLMaxDevices);
+    return MJP_OK;
 }
 
 }  // namespace mjp
@@ -815,18 +912,19 @@ extern "C" mjp_status mjp_loglik(int32_t model, int32_t B, const double* theta_d
                                  mjp_stream_t stream) {
     clear_error();
     std::vector<LLRecord> recs;
-    mjp_status st = ll_check(model, B, obs, opts, recs);
+    mjp_status st = ll_check(model, B, obs, opts, &recs);
     if (st) return st;
     if (B == 0) return MJP_OK;
     MJP_CHECK(theta_d && dims_d && loglik_d, MJP_E_INVALID_ARG, "null device array");
     int dev = 0;
-    MJP_HIP(hipGetDevice(&dev));
+    if ((st = ll_device(dev))) return st;
     LLContext& C = ctx_for(dev);
     std::lock_guard<std::mutex> lock(C.mu);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    LLArgs a;
-    if ((st = ll_upload(C, dev, recs, obs)) || (st = ll_setup(C, model, B, obs, opts, theta_d, dims_d, loglik_d, info_d, a)))
+    LLBufs bf;
+    if ((st = ll_attrs(C, dev)) || (st = ll_obs(C, recs, obs, s, bf)) || (st = ll_work(C, s, B, obs->n_t, bf)))
         return st;
+    const LLArgs a = ll_args(model, B, obs, opts, theta_d, dims_d, loglik_d, info_d, bf);
     ll_prepare(a, s);
     for (int c = 0; c < kLLClasses; ++c) ll_launch(C, a, c, ll_effective(C, model, c, a.n_rec), s);
     MJP_HIP(hipGetLastError());
@@ -861,7 +959,8 @@ extern "C" mjp_status mjp_loglik_set_shapes(int32_t model, const int32_t* ids) {
                   "class %d: shape %d holds fewer than %d states", c, ids[c], kLLClassCap[c]);
     }
     int dev = 0;
-    MJP_HIP(hipGetDevice(&dev));
+    mjp_status st = ll_device(dev);
+    if (st) return st;
     LLContext& C = ctx_for(dev);
     std::lock_guard<std::mutex> lock(C.mu);
     for (int c = 0; c < kLLClasses; ++c) C.shape[model][c] = ids[c];
@@ -874,7 +973,8 @@ extern "C" mjp_status mjp_loglik_get_shapes(int32_t model, int32_t n_rec, int32_
     MJP_CHECK(ids, MJP_E_INVALID_ARG, "ids is NULL");
     MJP_CHECK(n_rec >= 0 && n_rec <= kLLMaxRecords, MJP_E_INVALID_ARG, "n_rec must be in [0, %d]", kLLMaxRecords);
     int dev = 0;
-    MJP_HIP(hipGetDevice(&dev));
+    mjp_status st = ll_device(dev);
+    if (st) return st;
     LLContext& C = ctx_for(dev);
     std::lock_guard<std::mutex> lock(C.mu);
     for (int c = 0; c < kLLClasses; ++c) ids[c] = ll_effective(C, model, c, n_rec);
@@ -886,19 +986,20 @@ extern "C" mjp_status mjp_loglik_tune(int32_t model, int32_t B, const double* th
                                       int32_t reps, mjp_ll_tune_report* report, mjp_stream_t stream) {
     clear_error();
     std::vector<LLRecord> recs;
-    mjp_status st = ll_check(model, B, obs, opts, recs);
+    mjp_status st = ll_check(model, B, obs, opts, &recs);
     if (st) return st;
     MJP_CHECK(reps >= 1 && reps <= 100, MJP_E_INVALID_ARG, "reps must be in [1, 100]");
     MJP_CHECK(B >= 1, MJP_E_INVALID_ARG, "tuning needs B >= 1");
     MJP_CHECK(theta_d && dims_d && loglik_d, MJP_E_INVALID_ARG, "null device array");
     int dev = 0;
-    MJP_HIP(hipGetDevice(&dev));
+    if ((st = ll_device(dev))) return st;
     LLContext& C = ctx_for(dev);
     std::lock_guard<std::mutex> lock(C.mu);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    LLArgs a;
-    if ((st = ll_upload(C, dev, recs, obs)) || (st = ll_setup(C, model, B, obs, opts, theta_d, dims_d, loglik_d, info_d, a)))
+    LLBufs bf;
+    if ((st = ll_attrs(C, dev)) || (st = ll_obs(C, recs, obs, s, bf)) || (st = ll_work(C, s, B, obs->n_t, bf)))
         return st;
+    const LLArgs a = ll_args(model, B, obs, opts, theta_d, dims_d, loglik_d, info_d, bf);
     ll_prepare(a, s);
     int32_t off[kLLClasses + 1];
     MJP_HIP(hipMemcpyAsync(off, a.cls_off, sizeof(off), hipMemcpyDeviceToHost, s));
@@ -966,7 +1067,7 @@ extern "C" mjp_status mjp_jump_probs(int32_t model, int32_t B, const double* the
                                      double* omega_d, mjp_stream_t stream) {
     clear_error();
     std::vector<LLRecord> recs;
-    mjp_status st = ll_check(model, B, obs, opts, recs);
+    mjp_status st = ll_check(model, B, obs, opts, &recs);
     if (st) return st;
     for (size_t i = 0; i < recs.size(); ++i)
         MJP_CHECK(recs[i].count == 1, MJP_E_INVALID_ARG, "record %zu: each observation has its own jump count (count 1)",
@@ -974,13 +1075,14 @@ extern "C" mjp_status mjp_jump_probs(int32_t model, int32_t B, const double* the
     if (B == 0 || recs.empty()) return MJP_OK;
     MJP_CHECK(theta_d && dims_d && k_d && logphi_d, MJP_E_INVALID_ARG, "null device array");
     int dev = 0;
-    MJP_HIP(hipGetDevice(&dev));
+    if ((st = ll_device(dev))) return st;
     LLContext& C = ctx_for(dev);
     std::lock_guard<std::mutex> lock(C.mu);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    LLArgs a;
-    if ((st = ll_upload(C, dev, recs, obs)) || (st = ll_setup(C, model, B, obs, opts, theta_d, dims_d, nullptr, nullptr, a)))
+    LLBufs bf;
+    if ((st = ll_attrs(C, dev)) || (st = ll_obs(C, recs, obs, s, bf)) || (st = ll_work(C, s, B, obs->n_t, bf)))
         return st;
+    LLArgs a = ll_args(model, B, obs, opts, theta_d, dims_d, nullptr, nullptr, bf);
     a.n_t = 1;  // one window per item: [0, max_i k_i]
     a.kobs = k_d;
     a.phi = logphi_d;
@@ -990,11 +1092,9 @@ extern "C" mjp_status mjp_jump_probs(int32_t model, int32_t B, const double* the
     while (P < B) P <<= 1;
     const size_t sort_lds = P <= kLLMaxSort ? sizeof(unsigned long long) * P : 0;
     hipLaunchKernelGGL(k_ll_order, dim3(1), dim3(1024), sort_lds, s, a);
-    int ncu = 0;
-    MJP_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     for (int c = 0; c < kLLClasses; ++c) {
         const int sid = kLLDefaultShape[c];
-        const int grid = std::max(1, std::min(B, std::max(ncu, 1) * C.occ_jp[model][c]));
+        const int grid = std::max(1, std::min(B, std::max(C.ncu, 1) * C.occ_jp[model][c]));
         hipLaunchKernelGGL(kJpMains[model][c], dim3(grid), dim3(kLLShapes[sid].T), ll_lds(sid), s, a, c);
     }
     MJP_HIP(hipGetLastError());

@@ -366,3 +366,4 @@ def test_new_model_dims_validation(model, dims):
 def test_stencil_plans_refuse_gene_state_models():
     for model, dims in ((2, [10]), (3, [4, 5])):
         assert status_of(mjp.mjp_plan_create_stencil, mjp.make_model(model, [1.0] * 6, dims)) == mjp.MJP_E_UNSUPPORTED
+

@@ -203,3 +203,75 @@ def test_graph_capture_replay(small_case):
         g.replay()
         torch.cuda.synchronize()
         assert np.array_equal(out.cpu().numpy(), eager), rep
+
+
+def _second_case():
+    """Another observation set with the small case's batch shape: other
+    rates, times and snapshots."""
+    theta_star = [9.0, 0.8, 0.5, 0.7]
+    T = synth.even_times(3, 0.6)
+    data = synth.gillespie_cascade2(theta_star, T, 17, seed=synth.SEED_DATA + 7)
+    recs = synth.cascade_records(data)
+    return T, recs
+
+
+def test_graph_keeps_its_observations(small_case):
+    """A graph captured from a call keeps the records it was captured with:
+    an eager call with another observation set between replays (the same
+    number of items, so nothing grows) changes neither the replays nor its
+    own result.  The replays run on the capturing stream, ordered after the
+    eager call: a graph shares that stream's work tables, so it must not run
+    concurrently with another call on the stream."""
+    theta, dims, T, recs = small_case
+    T2, recs2 = _second_case()
+    eager_a = run_loglik(1, theta, dims, T, recs)
+    eager_b = run_loglik(1, theta, dims, T2, recs2)
+    assert not np.array_equal(eager_a, eager_b)
+    B = len(theta)
+    th = torch.as_tensor(theta, device="cuda")
+    dm = torch.as_tensor(np.asarray(dims, np.int32), device="cuda")
+    out = torch.zeros(B, dtype=torch.float64, device="cuda")
+    out_b = torch.zeros(B, dtype=torch.float64, device="cuda")
+    obs_a, obs_b = mjp.make_obs(T, recs, (0, 0)), mjp.make_obs(T2, recs2, (0, 0))
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        mjp.mjp_loglik(1, th, dm, obs_a, out)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        mjp.mjp_loglik(1, th, dm, obs_a, out, stream=s)
+    for rep in range(3):
+        out.zero_()
+        out_b.zero_()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            mjp.mjp_loglik(1, th, dm, obs_b, out_b, stream=s)   # other records, same stream
+            g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), eager_a), rep
+        assert np.array_equal(out_b.cpu().numpy(), eager_b), rep
+
+
+def test_two_streams_do_not_share_tables(small_case):
+    """Calls on two streams, enqueued back to back without a
+    synchronisation between them, each with its own observation set, give
+    what each gives alone."""
+    theta, dims, T, recs = small_case
+    T2, recs2 = _second_case()
+    eager_a = run_loglik(1, theta, dims, T, recs)
+    eager_b = run_loglik(1, theta, dims, T2, recs2)
+    B = len(theta)
+    th = torch.as_tensor(theta, device="cuda")
+    dm = torch.as_tensor(np.asarray(dims, np.int32), device="cuda")
+    obs_a, obs_b = mjp.make_obs(T, recs, (0, 0)), mjp.make_obs(T2, recs2, (0, 0))
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    for rep in range(3):
+        out_a = torch.zeros(B, dtype=torch.float64, device="cuda")
+        out_b = torch.zeros(B, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        mjp.mjp_loglik(1, th, dm, obs_a, out_a, stream=s1)
+        mjp.mjp_loglik(1, th, dm, obs_b, out_b, stream=s2)
+        torch.cuda.synchronize()
+        assert np.array_equal(out_a.cpu().numpy(), eager_a), rep
+        assert np.array_equal(out_b.cpu().numpy(), eager_b), rep
