@@ -295,6 +295,32 @@ mjp_status mjp_loglik(int32_t model, int32_t B, const double* theta_d, const int
                       const mjp_obs* obs, const mjp_opts* opts, double* loglik_d,
                       mjp_info* info_d, mjp_stream_t stream);
 
+/* mjp_loglik without any allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight sampling loops, harnesses that
+ * forbid hipMalloc).  Same arguments, kernels, launch shapes and results
+ * (bit for bit) as mjp_loglik.  The call's tables (records, times, windows,
+ * costs, order, queue counters) live in one fixed array of
+ * mjp_loglik_noalloc_capacity() bytes (4 MiB) of device memory per GPU,
+ * part of the library and held until the process ends; a call needs
+ * mjp_loglik_noalloc_bytes(B, n_t, n_obs) of it (B (24 n_t + 8) + 16 n_obs +
+ * 8 n_t plus alignment: for example B <= 8192 at 20 times and 1000 records)
+ * and returns MJP_E_WORKSPACE, before any GPU work, when that exceeds the
+ * capacity.  The records and times are copied from obs's host arrays by
+ * copies enqueued on `stream`: keep those arrays unchanged until the stream
+ * has passed the call (for a captured graph, while it is replayed).  Every
+ * call on a GPU uses that GPU's one array, which keeps the last call's
+ * contents: calls that overlap on one GPU (on different streams, or a graph
+ * replayed while another call runs) race and give wrong results.  Calls no
+ * hipMalloc, hipFree or allocating routine; the first call on a device looks
+ * up the array's device address and sets kernel attributes. */
+mjp_status mjp_loglik_noalloc(int32_t model, int32_t B, const double* theta_d, const int32_t* dims_d,
+                              const mjp_obs* obs, const mjp_opts* opts, double* loglik_d,
+                              mjp_info* info_d, mjp_stream_t stream);
+/* Bytes of the array a mjp_loglik_noalloc call with these sizes needs (-1 for
+ * negative sizes), and the array's size. */
+int64_t mjp_loglik_noalloc_bytes(int32_t B, int32_t n_t, int32_t n_obs);
+int64_t mjp_loglik_noalloc_capacity(void);
+
 /* Largest S1*S2 a log-likelihood item may have (LDS capacity of one CU). */
 int32_t mjp_loglik_max_states(void);
 

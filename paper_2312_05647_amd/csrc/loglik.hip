@@ -905,6 +905,57 @@ static mjp_status ll_device(int& dev) {
     return MJP_OK;
 }
 
+// ------------------------------------------------ the allocation-free call
+//
+// mjp_loglik_noalloc keeps one call's tables (records, times, windows,
+// costs, order, queue counters, class offsets) in this array instead of
+// buffers it allocates.  The array's name is a host-side stand-in in host
+// code: its device address, different on each GPU, comes from
+// hipGetSymbolAddress once per device (scratch_base) and only that address
+// is handed to copies and kernels.
+constexpr size_t kLLScratchBytes = (size_t)4 << 20;
+static __device__ __align__(256) unsigned char scratch[kLLScratchBytes];
+static void* g_scratch[kLLMaxDevices];
+static std::mutex g_scratch_mu;
+
+static mjp_status scratch_base(int dev, unsigned char** out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        MJP_CHECK(e == hipSuccess && ptr, MJP_E_DEVICE, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev,
+                  hipGetErrorString(e));
+        g_scratch[dev] = ptr;
+    }
+    *out = static_cast<unsigned char*>(g_scratch[dev]);
+    return MJP_OK;
+}
+
+struct LLScratchLayout {
+    size_t rec, T, win, cost, order, queue, cls_off, total;
+};
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static LLScratchLayout scratch_layout(int B, int n_t, int n_rec) {
+    LLScratchLayout L;
+    size_t at = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = at;
+        at += align256(std::max<size_t>(bytes, 1));
+        return o;
+    };
+    L.rec = take(sizeof(LLRecord) * (size_t)n_rec);
+    L.T = take(sizeof(double) * (size_t)n_t);
+    L.win = take(sizeof(LLWin) * (size_t)B * n_t);
+    L.cost = take(sizeof(float) * (size_t)B);
+    L.order = take(sizeof(int32_t) * (size_t)B);
+    L.queue = take(64);
+    L.cls_off = take(sizeof(int32_t) * (kLLClasses + 1));
+    L.total = at;
+    return L;
+}
+
 }  // namespace mjp
 
 extern "C" mjp_status mjp_loglik(int32_t model, int32_t B, const double* theta_d, const int32_t* dims_d,
@@ -926,6 +977,52 @@ extern "C" mjp_status mjp_loglik(int32_t model, int32_t B, const double* theta_d
         return st;
     const LLArgs a = ll_args(model, B, obs, opts, theta_d, dims_d, loglik_d, info_d, bf);
     ll_prepare(a, s);
+    for (int c = 0; c < kLLClasses; ++c) ll_launch(C, a, c, ll_effective(C, model, c, a.n_rec), s);
+    MJP_HIP(hipGetLastError());
+    return MJP_OK;
+}
+
+extern "C" int64_t mjp_loglik_noalloc_bytes(int32_t B, int32_t n_t, int32_t n_obs) {
+    if (B < 0 || n_t < 0 || n_obs < 0) return -1;
+    return (int64_t)scratch_layout(B, n_t, n_obs).total;
+}
+
+extern "C" int64_t mjp_loglik_noalloc_capacity(void) { return (int64_t)kLLScratchBytes; }
+
+extern "C" mjp_status mjp_loglik_noalloc(int32_t model, int32_t B, const double* theta_d, const int32_t* dims_d,
+                                         const mjp_obs* obs, const mjp_opts* opts, double* loglik_d,
+                                         mjp_info* info_d, mjp_stream_t stream) {
+    clear_error();
+    mjp_status st = ll_check(model, B, obs, opts, nullptr);
+    if (st) return st;
+    if (B == 0) return MJP_OK;
+    MJP_CHECK(theta_d && dims_d && loglik_d, MJP_E_INVALID_ARG, "null device array");
+    const LLScratchLayout L = scratch_layout(B, obs->n_t, obs->n_obs);
+    MJP_CHECK(L.total <= kLLScratchBytes, MJP_E_WORKSPACE,
+              "B = %d items of %d times with %d records need %zu bytes of scratch; the allocation-free call holds %zu",
+              B, obs->n_t, obs->n_obs, L.total, kLLScratchBytes);
+    int dev = 0;
+    if ((st = ll_device(dev))) return st;
+    unsigned char* base = nullptr;
+    if ((st = scratch_base(dev, &base))) return st;
+    LLContext& C = ctx_for(dev);
+    std::lock_guard<std::mutex> lock(C.mu);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if ((st = ll_attrs(C, dev))) return st;
+    LLBufs bf;
+    bf.rec = reinterpret_cast<const LLRecord*>(base + L.rec);
+    bf.T = reinterpret_cast<const double*>(base + L.T);
+    bf.win = reinterpret_cast<LLWin*>(base + L.win);
+    bf.cost = reinterpret_cast<float*>(base + L.cost);
+    bf.order = reinterpret_cast<int32_t*>(base + L.order);
+    bf.queue = reinterpret_cast<unsigned*>(base + L.queue);
+    bf.cls_off = reinterpret_cast<int32_t*>(base + L.cls_off);
+    // the caller's record rows have the kernels' record layout
+    if (obs->n_obs)
+        MJP_HIP(hipMemcpyAsync(base + L.rec, obs->obs_h, sizeof(LLRecord) * (size_t)obs->n_obs, hipMemcpyHostToDevice, s));
+    MJP_HIP(hipMemcpyAsync(base + L.T, obs->T_h, sizeof(double) * (size_t)obs->n_t, hipMemcpyHostToDevice, s));
+    const LLArgs a = ll_args(model, B, obs, opts, theta_d, dims_d, loglik_d, info_d, bf);
+    ll_prepare(a, s);  // also zeroes the queue counters (no memset node)
     for (int c = 0; c < kLLClasses; ++c) ll_launch(C, a, c, ll_effective(C, model, c, a.n_rec), s);
     MJP_HIP(hipGetLastError());
     return MJP_OK;

@@ -128,6 +128,9 @@ _SIGS = [
     ("mjp_expv", ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, _P, _P]),
     ("mjp_expv_batched", ctypes.c_int, [ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P]),
     ("mjp_loglik", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P]),
+    ("mjp_loglik_noalloc", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P]),
+    ("mjp_loglik_noalloc_bytes", ctypes.c_int64, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    ("mjp_loglik_noalloc_capacity", ctypes.c_int64, []),
     ("mjp_loglik_max_states", ctypes.c_int32, []),
     ("mjp_loglik_num_shapes", ctypes.c_int32, []),
     ("mjp_loglik_shape", ctypes.c_int, [ctypes.c_int32, _P]),
@@ -397,6 +400,24 @@ def mjp_loglik(model: int, theta, dims, obs: mjp_obs, out, opts: mjp_opts | None
     B = int(out.shape[0])
     _check(lib().mjp_loglik(model, B, _ptr(theta), _ptr(dims), ctypes.byref(obs), ctypes.byref(opts), _ptr(out),
                             _ptr(info), _stream(stream)))
+
+
+def mjp_loglik_noalloc(model: int, theta, dims, obs: mjp_obs, out, opts: mjp_opts | None = None, info=None,
+                       stream=None) -> None:
+    """mjp_loglik with the call's tables in the library's fixed device array
+    (no allocation); same arguments."""
+    opts = opts or mjp_opts_default()
+    B = int(out.shape[0])
+    _check(lib().mjp_loglik_noalloc(model, B, _ptr(theta), _ptr(dims), ctypes.byref(obs), ctypes.byref(opts),
+                                    _ptr(out), _ptr(info), _stream(stream)))
+
+
+def mjp_loglik_noalloc_bytes(B: int, n_t: int, n_obs: int) -> int:
+    return int(lib().mjp_loglik_noalloc_bytes(B, n_t, n_obs))
+
+
+def mjp_loglik_noalloc_capacity() -> int:
+    return int(lib().mjp_loglik_noalloc_capacity())
 
 
 def mjp_jump_probs(model: int, theta, dims, obs: mjp_obs, k, logphi, omega=None, opts: mjp_opts | None = None,

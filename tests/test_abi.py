@@ -367,3 +367,22 @@ def test_stencil_plans_refuse_gene_state_models():
     for model, dims in ((2, [10]), (3, [4, 5])):
         assert status_of(mjp.mjp_plan_create_stencil, mjp.make_model(model, [1.0] * 6, dims)) == mjp.MJP_E_UNSUPPORTED
 
+
+def test_noalloc_loglik_rejects_oversize_on_the_host():
+    """mjp_loglik_noalloc sizes its tables on the host and refuses a call
+    whose tables exceed the fixed array (MJP_E_WORKSPACE) before touching
+    the GPU (the device pointers below are never dereferenced)."""
+    cap = mjp.mjp_loglik_noalloc_capacity()
+    assert cap == 4 << 20
+    assert mjp.mjp_loglik_noalloc_bytes(-1, 1, 1) == -1
+    a, b = mjp.mjp_loglik_noalloc_bytes(100, 20, 1000), mjp.mjp_loglik_noalloc_bytes(200, 20, 1000)
+    assert b - a >= 100 * (24 * 20 + 8)
+    assert mjp.mjp_loglik_noalloc_bytes(8192, 20, 1000) <= cap < mjp.mjp_loglik_noalloc_bytes(20000, 20, 1000)
+    T = np.linspace(0.5, 10, 20)
+    recs = np.array([[0, 1, 2, 1]], np.int32)
+    obs = mjp.make_obs(T, recs, (0, 0))
+    fake = ctypes.c_void_p(0x1000)
+    st = mjp.lib().mjp_loglik_noalloc(1, 20000, fake, fake, ctypes.byref(obs), ctypes.byref(mjp.mjp_opts_default()),
+                                      fake, None, None)
+    assert st == mjp.MJP_E_WORKSPACE
+    assert "scratch" in mjp.mjp_last_error()
