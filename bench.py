@@ -8,8 +8,17 @@ The operator and rho(0) are resident in HBM before timing starts.
 
 Prints ONE JSON line (rank 0, N = 1):
   value      solves/s of the timed variant (default: CSR operator)
-  roofline   algorithmic bytes of one solve / solve time (HIP events on the
-             library's stream), against the 8 TB/s HBM3E peak
+  roofline   the solve kernel against the bound that sets its time.  It keeps
+             the operator in registers for all K jumps and exchanges only the
+             iterate between neighbouring workgroups, two jumps per
+             synchronisation, so the bound is that exchange ("sync"):
+             achieved = jumps/s of the solve (HIP events on the stream the
+             kernel runs on), peak = jumps/s if every two-jump round took only
+             the measured exchange floor (mjp_probe_exchange: the same loads,
+             stores, flags and waits with no arithmetic).  The survey's
+             streaming byte count (52 B per row and jump for CSR) divided by
+             the solve time is reported beside it as algorithmic_GBps; it
+             exceeds the HBM peak because the operator is not re-read.
   cpu_baseline  the FP64 oracle on the host on the same workload
 """
 from __future__ import annotations
@@ -35,6 +44,16 @@ T_SOLVE = 1.0
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def algorithmic_bytes(kind: str, n: int, nnz: int, K: int, L: int) -> float:
@@ -66,7 +85,7 @@ def measured_traffic(kind: str):
     return {"bytes_per_launch": rec["hbm_bytes_per_launch"], "source": os.path.relpath(path, ROOT)}
 
 
-def bench_small(torch, mjp, reps: int = 20):
+def bench_small(torch, mjp, reps: int = 20, orc=None):
     """The two smaller expv workloads.
     C1: immigration-death on states 0..999, lambda = 500, mu = 1, t = 1,
         rho(0) at 0 (latency-bound: one short sweep of ~1900 jumps); its
@@ -74,7 +93,8 @@ def bench_small(torch, mjp, reps: int = 20):
     C2: cascade 300 x 300 (N = 90,000), rates (200, 1, 0.5, 0.5), rho(0) at
         (0, 0), 16 log-spaced times 0.1..10 in one sweep with 16 full-vector
         outputs (K up to ~9400); its bytes are served from cache (the vector
-        pair is 0.7 MB)."""
+        pair is 0.7 MB).  With the oracle (orc) each time's L1 error against
+        its independent FP64 solve is reported."""
     from scipy.stats import poisson
     from paper_2312_05647_amd import synth
     res = {}
@@ -122,6 +142,13 @@ def bench_small(torch, mjp, reps: int = 20):
     ab = Kmax * (8 * len(ci) + 12 * 90000) + acc * 16 * 90000
     res["C2_cascade_300x300_16_times"] = {"ms_per_sweep": sec * 1e3, "K_max": Kmax, "jumps_per_s": Kmax / sec,
                                           "algorithmic_GBps_cache_served": ab / sec / 1e9}
+    if orc is not None:
+        A2 = orc.model_generator(orc.MODEL_CASCADE2, [200.0, 1.0, 0.5, 0.5], [300, 300])
+        ref = orc.expv_times(A2, synth.delta(90000), times)
+        l1 = np.abs(out.double().cpu().numpy() - ref).sum(axis=1)
+        res["C2_cascade_300x300_16_times"]["l1_vs_fp64_oracle_per_time"] = [float(v) for v in l1]
+        res["C2_cascade_300x300_16_times"]["times"] = [float(t) for t in times]
+        log(f"[bench] C2 L1 vs FP64 per time: max {l1.max():.2e}")
     log(f"[bench] C2: {sec * 1e3:.2f} ms per 16-time sweep, K_max={Kmax}")
     return res
 
@@ -331,7 +358,21 @@ def bench_loglik(torch, mjp, reps: int = 3):
     sec = ev0.elapsed_time(ev1) / 1e3 / reps
     raw = info.cpu().numpy().tobytes()
     sz = ctypes.sizeof(mjp.mjp_info)
-    K = np.array([mjp.mjp_info.from_buffer_copy(raw[i * sz:(i + 1) * sz]).K for i in range(B)], np.float64)
+    infos = [mjp.mjp_info.from_buffer_copy(raw[i * sz:(i + 1) * sz]) for i in range(B)]
+    K = np.array([i.K for i in infos], np.float64)
+    vals = out.cpu().numpy()
+    reasons = {"out_of_grid": 0, "fp32_underflow_at_observed_state": 0, "k_cap": 0, "other": 0}
+    for v, i in zip(vals, infos):
+        if np.isfinite(v):
+            continue
+        if i.flags & mjp.MJP_FLAG_K_LIMIT:
+            reasons["k_cap"] += 1
+        elif i.flags & mjp.MJP_FLAG_OUT_OF_GRID:
+            reasons["out_of_grid"] += 1
+        elif i.flags & mjp.MJP_FLAG_UNDERFLOW_OBS:
+            reasons["fp32_underflow_at_observed_state"] += 1
+        else:
+            reasons["other"] += 1
     cells = float(np.sum((K + 1) * dims[:, 0] * dims[:, 1]))
     default_shapes = mjp.mjp_loglik_get_shapes(1, len(recs))
     log(f"[bench] loglik batch: {sec * 1e3:.1f} ms for {B} draws, {B / sec:.0f} loglik/s (default shapes)")
@@ -350,7 +391,8 @@ def bench_loglik(torch, mjp, reps: int = 3):
             "loglik_per_s": B / sec_t, "ms_per_batch": sec_t * 1e3,
             "cell_updates_per_s": cells / sec_t,
             "lds_equiv_GBps": 8 * cells / sec_t / 1e9,
-            "finite_fraction": float(np.isfinite(out.cpu().numpy()).mean()),
+            "finite_fraction": float(np.isfinite(vals).mean()),
+            "minus_inf_reasons": reasons,
             "ms_per_batch_default_shapes": sec * 1e3,
             "tuner": {"items_per_class": rep["items"],
                       "default": [f"{shapes[i]['threads']}x{shapes[i]['cells']}" for i in default_shapes],
@@ -511,10 +553,20 @@ def main():
         wall = time.perf_counter() - t0
         return info, ev0.elapsed_time(ev1) / 1e3 / steps, wall
 
+    def exchange_floor(plan, K):
+        """(rounds per solve, measured us per round, floor us per round) of
+        the two-jump sweep; None where the plan's sweep is another kernel."""
+        if info.get("path") != mjp.MJP_PATH_PERSISTENT_TWOJUMP:
+            return None
+        rounds = (K + 1) // 2
+        floor = mjp.mjp_probe_exchange(plan, rounds, stream=stream)
+        return rounds, floor
+
     log(f"[bench] plan {args.kind} N={n} nnz={nnz}")
     plan = make_plan(args.kind)
     info, dev_s, wall = time_solves(plan, args.steps, args.warmup)
     got = out[0].double().cpu().numpy()
+    xfloor = exchange_floor(plan, info["K"])
     mjp.mjp_plan_destroy(plan)
     K, L = info["K"], info["L"]
     ab = algorithmic_bytes(args.kind, n, nnz, K, L)
@@ -523,6 +575,26 @@ def main():
         f"K={K} L={L}, {achieved:.0f} GB/s algorithmic")
 
     traffic = measured_traffic(args.kind)
+    if xfloor is not None:
+        rounds, floor_us = xfloor
+        meas_us = dev_s * 1e6 / rounds
+        roof = {"bound": "sync", "achieved": K / dev_s, "peak": 2.0 / (floor_us * 1e-6), "unit": "jumps/s",
+                "frac": (K / dev_s) / (2.0 / (floor_us * 1e-6)),
+                "kernel": "one solve (all K jumps, weighted accumulation, lumping), two jumps per neighbour exchange",
+                "rounds_per_solve": rounds, "us_per_round_measured": meas_us,
+                "us_per_round_exchange_floor": floor_us,
+                "floor_source": "mjp_probe_exchange: the same device-scope halo loads, own-row stores, drain, "
+                                "flags and waits on the same launch, no arithmetic"}
+        log(f"[bench] {args.kind}: {meas_us:.2f} us per two-jump round, exchange floor {floor_us:.2f} us "
+            f"({roof['frac']:.2f})")
+    else:
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "kernel": "one solve, stepwise launches"}
+    roof.update({"traffic": traffic["bytes_per_launch"] if traffic else None,
+                 "traffic_source": traffic["source"] if traffic else "no counter record for the current kernel source",
+                 "traffic_frac_of_hbm_peak": (traffic["bytes_per_launch"] / dev_s / 1e9 / HBM_PEAK_GBS) if traffic else None,
+                 "algorithmic_bytes_per_solve": ab, "algorithmic_GBps": achieved,
+                 "ms_per_solve_device": dev_s * 1e3})
     result = {
         "metric": METRIC,
         "value": 1.0 / (wall / args.steps),
@@ -540,23 +612,25 @@ def main():
                                f"t={T_SOLVE}, tol=1e-9, {args.kind.upper()} FP32 operator",
                    "operator": args.kind, "variant": args.variant, "K": K, "L": L,
                    "omega": info["omega"], "global_batch": 1, "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic["bytes_per_launch"] if traffic else None,
-                     "traffic_source": traffic["source"] if traffic else "no counter record for the current kernel source",
-                     "kernel": "one solve (all K jumps, weighted accumulation, lumping)",
-                     "algorithmic_bytes_per_solve": ab, "ms_per_solve_device": dev_s * 1e3},
+        "roofline": roof,
     }
 
     if not args.no_extra:
         other = "stencil" if args.kind == "csr" else "csr"
         plan = make_plan(other)
         info2, dev2, wall2 = time_solves(plan, max(3, args.steps // 2), 1)
+        xf2 = exchange_floor(plan, info2["K"])
         mjp.mjp_plan_destroy(plan)
         ab2 = algorithmic_bytes(other, n, nnz, info2["K"], info2["L"])
         result[f"{other}_variant"] = {"solves_per_s": 1.0 / (wall2 / max(3, args.steps // 2)),
                                       "ms_per_solve_device": dev2 * 1e3,
-                                      "algorithmic_GBps": ab2 / dev2 / 1e9}
+                                      "algorithmic_GBps": ab2 / dev2 / 1e9,
+                                      "algorithmic_frac_of_hbm_peak": ab2 / dev2 / 1e9 / HBM_PEAK_GBS}
+        if xf2 is not None:
+            r2, f2 = xf2
+            result[f"{other}_variant"].update({"us_per_round_measured": dev2 * 1e6 / r2,
+                                               "us_per_round_exchange_floor": f2,
+                                               "sync_frac": (info2["K"] / dev2) / (2.0 / (f2 * 1e-6))})
         log(f"[bench] {other}: {dev2 * 1e3:.3f} ms/solve")
 
     kry = None
@@ -568,7 +642,11 @@ def main():
         rk = bench_rk4(torch, mjp, rp, ci, va, n)
         result["rk4_method4"] = {k: v for k, v in rk.items() if k != "result"}
         result["rk4_method4"]["l1_vs_rmjp_gpu"] = float(np.abs(rk["result"] - got).sum())
-        result["small_configs"] = bench_small(torch, mjp)
+        orc = None
+        if not args.no_cpu:
+            import oracle as orc
+            orc.build(force=False)
+        result["small_configs"] = bench_small(torch, mjp, orc=orc)
         result["loglik_batch"] = bench_loglik(torch, mjp)
         result["da_mcmc"] = bench_da(torch, mjp)
         result["jmjp_method2"] = bench_jmjp(torch, mjp)
@@ -592,7 +670,7 @@ def main():
                 break
         cpu_s = (time.perf_counter() - t0) / solves
         result["cpu_baseline"] = {"value": 1.0 / cpu_s, "unit": "solves/s", "cores": oracle.num_threads(),
-                                  "kind": "oracle",
+                                  "cpu_model": cpu_model(), "kind": "oracle",
                                   "sample": f"{solves} full FP64 solve(s) of the same workload (K={oinfo['K']}, "
                                             f"right tail {eps_r:g}), OpenMP over rows"}
         l1 = float(np.abs(got - ref).sum())

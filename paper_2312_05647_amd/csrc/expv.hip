@@ -572,6 +572,18 @@ extern "C" mjp_status mjp_expv(mjp_plan* p, const float* rho0_d, int32_t n_t, co
     return MJP_OK;
 }
 
+extern "C" mjp_status mjp_probe_exchange(mjp_plan* p, int32_t rounds, double* us_per_round_h, mjp_stream_t stream) {
+    clear_error();
+    MJP_CHECK(p && us_per_round_h, MJP_E_INVALID_ARG, "null argument");
+    MJP_CHECK(rounds >= 1 && rounds <= 1000000, MJP_E_INVALID_ARG, "rounds must be in [1, 10^6]");
+    DeviceGuard guard(p->device);
+    float ms = 0.f;
+    const mjp_status s = probe_exchange(p, rounds, reinterpret_cast<hipStream_t>(stream), &ms);
+    if (s) return s;
+    *us_per_round_h = 1e3 * (double)ms / rounds;
+    return MJP_OK;
+}
+
 extern "C" mjp_status mjp_expv_batched(int32_t B, mjp_plan* const* plans, const float* const* rho0_d,
                                        const int32_t* n_t, const double* const* t_h, float* const* out_d,
                                        mjp_info* info_h, mjp_stream_t stream) {

@@ -859,6 +859,61 @@ __global__ __launch_bounds__(kPThreads) void k_persistent2(PersistArgs a) {
     }
 }
 
+// Exchange floor of the two-jump sweep (a measurement aid, not part of the
+// method): `rounds` rounds of exactly its per-round communication with no
+// arithmetic.  Each round: load the iterate on E2 outside the own rows from
+// global memory into LDS (device scope, the same coalesced pass as phase A),
+// a workgroup barrier, store the own rows from LDS (device scope, as phase C
+// does), then the same neighbour synchronisation (drain, flag, wait for the
+// neighbour interval).  The iterate is copied unchanged between the two
+// buffers, so every load reads what a neighbour stored the round before.
+template <bool FORCE = false>
+__global__ __launch_bounds__(kPThreads) void k_exchange_probe(PersistArgs a, int rounds) {
+    extern __shared__ __align__(16) char p2lds[];
+    float* X2 = reinterpret_cast<float*>(p2lds);
+    const int G = a.G;
+    const int g = logical_block(G);
+    const int tid = threadIdx.x;
+    const int64_t n = a.n;
+    const int32_t* tb = a.p2 + kP2Tab * g;
+    const int r0 = tb[0], r1 = tb[1], e2lo = tb[4], e2hi = tb[5];
+    const int wlo = tb[6], whi = tb[7];
+    const int nl2 = r0 - e2lo, nt2 = nl2 + (e2hi - r1);
+    for (int r = r0 + tid; r < r1; r += kPThreads) X2[r - e2lo] = a.rho0[r];
+    const __amdgpu_buffer_rsrc_t r_buf0 = iter_rsrc(a.buf0, n), r_buf1 = iter_rsrc(a.buf1, n);
+    __syncthreads();
+    {  // round 0 stores the own rows so the first loads read defined values
+        for (int r = r0 + tid; r < r1; r += kPThreads) st_iter<true>(r_buf0, 4u * (uint32_t)r, X2[r - e2lo]);
+        if (!neighbour_sync<true, FORCE>(a.wflag, wlo, whi, 1u, g, a.flags, a.timeout_ticks)) return;
+    }
+    for (int q = 1; q <= rounds; ++q) {
+        const __amdgpu_buffer_rsrc_t src = (q & 1) ? r_buf0 : r_buf1;
+        const __amdgpu_buffer_rsrc_t dst = (q & 1) ? r_buf1 : r_buf0;
+        {
+            constexpr int kU = kP2X2 / kPThreads - kP2R;
+            float t[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int i = tid + u * kPThreads;
+                const int rr = i < nl2 ? e2lo + i : r1 + (i - nl2);
+                t[u] = ld_iter<true>(src, 4u * (uint32_t)rr);
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int i = tid + u * kPThreads;
+                if (i < nt2) X2[i < nl2 ? i : (r1 - e2lo) + (i - nl2)] = t[u];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kP2R; ++i) {
+            const int r = r0 + tid + i * kPThreads;
+            st_iter<true>(dst, 4u * (uint32_t)r, r < r1 ? X2[r - e2lo] : 0.f);  // rows >= n fall outside the range
+        }
+        if (!neighbour_sync<true, FORCE>(a.wflag, wlo, whi, (unsigned)(q + 1), g, a.flags, a.timeout_ticks)) return;
+    }
+}
+
 using PersistFn = void (*)(PersistArgs);
 
 template <bool CSR, bool COH>
@@ -1211,6 +1266,64 @@ mjp_status launch_persistent(mjp_plan* p, const PersistCfg& cfg, const float* rh
     void* args[] = {&a};
     const size_t lds = cfg.jumps == 2 ? p2_lds_for(cfg.W) : 0;
     MJP_HIP(hipLaunchCooperativeKernel(cfg.fn, dim3(cfg.G), dim3(kPThreads), args, lds, st));
+    return MJP_OK;
+}
+
+// Times `rounds` exchange-only rounds on the two-jump sweep's launch
+// configuration for this plan (HIP events on st); false if the plan's sweep
+// does not run the two-jump kernel.
+mjp_status probe_exchange(mjp_plan* p, int rounds, hipStream_t st, float* ms_out) {
+    PersistCfg cfg;
+    MJP_CHECK(persistent2_fits(p, 1, cfg), MJP_E_UNSUPPORTED, "the plan's sweep does not use the two-jump kernel");
+    const int64_t n = p->n;
+    mjp_status s;
+    if ((s = p->rho[0].reserve(sizeof(float) * n)) || (s = p->rho[1].reserve(sizeof(float) * n)) ||
+        (s = p->sync.reserve(sizeof(unsigned) * (kBarWords + 32 * (size_t)cfg.G) + sizeof(double) * 3 * (size_t)cfg.G)) ||
+        (s = p->scal.reserve(sizeof(double) * S_COUNT)))
+        return s;
+    unsigned* bar = p->sync.as<unsigned>();
+    PersistArgs a{};
+    a.rho0 = p->rho[1].as<float>();  // any defined vector: the probe only copies it around
+    a.buf0 = p->rho[0].as<float>();
+    a.buf1 = p->rho[1].as<float>();
+    a.bar = bar;
+    a.wflag = bar + kBarWords;
+    a.p2 = p->p2tab.as<int32_t>();
+    a.flags = reinterpret_cast<unsigned*>(p->scal.as<double>() + S_FLAGS);
+    a.n = n;
+    a.G = cfg.G;
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, p->device) != hipSuccess || khz <= 0) khz = 100000;
+    a.timeout_ticks = (uint64_t)khz * 1000ull * 2ull;
+    const void* fn = reinterpret_cast<const void*>(k_exchange_probe<false>);
+    const size_t lds = sizeof(float) * kP2X2;
+    MJP_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    const int nzero = kBarWords + 32 * cfg.G;
+    hipEvent_t e0, e1;
+    MJP_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(MJP_E_DEVICE, "hipEventCreate failed");
+    }
+    hipError_t he = hipSuccess;
+    float ms = 0.f;
+    for (int rep = 0; rep < 2 && he == hipSuccess; ++rep) {  // the first run warms up
+        hipLaunchKernelGGL(k_zero_u32, dim3((nzero + 255) / 256), dim3(256), 0, st, bar, nzero);
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, reinterpret_cast<unsigned*>(a.flags), 2);
+        he = hipEventRecord(e0, st);
+        void* args[] = {&a, &rounds};
+        if (he == hipSuccess) he = hipLaunchCooperativeKernel(fn, dim3(cfg.G), dim3(kPThreads), args, lds, st);
+        if (he == hipSuccess) he = hipEventRecord(e1, st);
+        if (he == hipSuccess) he = hipEventSynchronize(e1);
+        if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+    }
+    unsigned fl = 0;
+    if (he == hipSuccess) he = hipMemcpy(&fl, a.flags, sizeof(unsigned), hipMemcpyDeviceToHost);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    MJP_CHECK(he == hipSuccess, MJP_E_DEVICE, "exchange probe failed: %s", hipGetErrorString(he));
+    MJP_CHECK(!(fl & kFlagBarrierTimeout), MJP_E_DEVICE, "exchange probe: a wait missed its deadline");
+    *ms_out = ms;
     return MJP_OK;
 }
 

@@ -38,6 +38,7 @@ struct PersistCfg {
 bool persistent_fits(const mjp_plan* p, int max_open, bool coh, PersistCfg& cfg);
 // the two-jump kernel (device-scope protocol only); builds its tables
 bool persistent2_fits(mjp_plan* p, int max_open, PersistCfg& cfg);
+mjp_status probe_exchange(mjp_plan* p, int rounds, hipStream_t st, float* ms_out);
 mjp_status launch_persistent(mjp_plan* p, const PersistCfg& cfg, const float* rho0, const AllTimes& at,
                              const std::vector<int>& slot, float* out, hipStream_t st);
 

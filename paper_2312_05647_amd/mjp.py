@@ -127,6 +127,7 @@ _SIGS = [
     ("mjp_plan_n", ctypes.c_int32, [_P]),
     ("mjp_expv", ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, _P, _P]),
     ("mjp_expv_batched", ctypes.c_int, [ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P]),
+    ("mjp_probe_exchange", ctypes.c_int, [_P, ctypes.c_int32, _P, _P]),
     ("mjp_loglik", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P]),
     ("mjp_loglik_noalloc", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P]),
     ("mjp_loglik_noalloc_bytes", ctypes.c_int64, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
@@ -273,6 +274,14 @@ def mjp_expv(plan: int, rho0, times, out, info: bool = False, stream=None):
     _check(lib().mjp_expv(plan, _ptr(rho0), len(t), _ptr(t), _ptr(out),
                           ctypes.cast(inf, ctypes.c_void_p) if info else None, _stream(stream)))
     return [i.as_dict() for i in inf] if info else None
+
+
+def mjp_probe_exchange(plan: int, rounds: int, stream=None) -> float:
+    """Microseconds per round of the two-jump sweep's communication alone on
+    this plan's launch configuration (a measurement aid)."""
+    us = ctypes.c_double()
+    _check(lib().mjp_probe_exchange(plan, rounds, ctypes.byref(us), _stream(stream)))
+    return us.value
 
 
 def mjp_expv_batched(plans, rho0s, times_list, outs, info: bool = False, stream=None):

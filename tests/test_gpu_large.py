@@ -91,3 +91,28 @@ def test_full_size_protocols_bit_identical(kind):
             mjp.mjp_plan_destroy(plan)
     for r in res[1:]:
         assert np.array_equal(res[0], r)
+
+
+def test_exchange_probe_is_a_floor():
+    """mjp_probe_exchange times the two-jump sweep's communication alone on
+    the plan's own launch: it must take less per round than a solve's
+    rounds do (which add two jumps of arithmetic to the same exchange)."""
+    model = mjp.make_model(mjp.MJP_MODEL_CASCADE2, [200.0, 1.0, 0.5, 0.5], [1000, 1000])
+    plan = mjp.mjp_plan_create_stencil(model)
+    try:
+        r0 = torch.zeros(10 ** 6, device="cuda")
+        r0[0] = 1.0
+        out = torch.empty((1, 10 ** 6), device="cuda")
+        info = mjp.mjp_expv(plan, r0, [1.0], out, info=True)[0]
+        assert info["path"] == mjp.MJP_PATH_PERSISTENT_TWOJUMP
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        mjp.mjp_expv(plan, r0, [1.0], out)
+        ev1.record()
+        torch.cuda.synchronize()
+        per_round = ev0.elapsed_time(ev1) * 1e3 / ((info["K"] + 1) // 2)
+        floor = mjp.mjp_probe_exchange(plan, (info["K"] + 1) // 2)
+        print(f"[gpu] exchange floor {floor:.2f} us per round, solve {per_round:.2f} us per round", file=sys.stderr)
+        assert 0.2 < floor < per_round
+    finally:
+        mjp.mjp_plan_destroy(plan)
