@@ -347,15 +347,20 @@ def bench_loglik(torch, mjp, reps: int = 3):
     info = torch.zeros(B * ctypes.sizeof(mjp.mjp_info), dtype=torch.uint8, device="cuda")
     obs = mjp.make_obs(T, recs, (0, 0))
     stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed():
+        ev0.record(stream)
+        for _ in range(reps):
+            mjp.mjp_loglik(1, th, dm, obs, out, stream=stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / 1e3 / reps
+
+    # default launch shapes
     mjp.mjp_loglik(1, th, dm, obs, out, info=info, stream=stream)
     torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    for _ in range(reps):
-        mjp.mjp_loglik(1, th, dm, obs, out, stream=stream)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    sec = ev0.elapsed_time(ev1) / 1e3 / reps
+    sec = timed()
     raw = info.cpu().numpy().tobytes()
     sz = ctypes.sizeof(mjp.mjp_info)
     infos = [mjp.mjp_info.from_buffer_copy(raw[i * sz:(i + 1) * sz]) for i in range(B)]
@@ -387,7 +392,7 @@ def bench_loglik(torch, mjp, reps: int = 3):
     sec_t = ev0.elapsed_time(ev1) / 1e3 / reps
     shapes = mjp.mjp_loglik_shapes()
     log(f"[bench] loglik batch tuned: {sec_t * 1e3:.1f} ms, shapes {rep['chosen']} (items per class {rep['items']})")
-    return {"workload": "4096 cascade draws, grids 50..200 per side, 20 times x 50 snapshots",
+    return {"workload": "4096 cascade draws, grids 148..200 per side, 20 times x 50 snapshots",
             "loglik_per_s": B / sec_t, "ms_per_batch": sec_t * 1e3,
             "cell_updates_per_s": cells / sec_t,
             "lds_equiv_GBps": 8 * cells / sec_t / 1e9,

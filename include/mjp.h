@@ -334,6 +334,22 @@ mjp_status mjp_loglik_noalloc(int32_t model, int32_t B, const double* theta_d, c
 int64_t mjp_loglik_noalloc_bytes(int32_t B, int32_t n_t, int32_t n_obs);
 int64_t mjp_loglik_noalloc_capacity(void);
 
+/* Which kernel computes the items of a model in mjp_loglik (and its tuner,
+ * and mjp_loglik_noalloc) on the current device:
+ *   MJP_LL_KERNEL_AUTO  (default) cascade items whose grid fits the column
+ *       kernel -- S1 <= 992 columns, the S2 rows cut into at most 992 / S1
+ *       segments of at most 64 rows, a column-major LDS mirror of at most
+ *       40,256 floats -- would run in it (each lane keeps one column segment
+ *       in registers; left and right neighbours by cross-lane moves).  That
+ *       kernel is switched off in this build (its first GPU run did not
+ *       finish and the cause has not been found), so AUTO runs every item in
+ *       the cell kernel;
+ *   MJP_LL_KERNEL_CELLS every item in the cell kernel, whose launch shapes
+ *       mjp_loglik_set_shapes and mjp_loglik_tune choose.
+ * The other models always use the cell kernel. */
+enum { MJP_LL_KERNEL_AUTO = 0, MJP_LL_KERNEL_CELLS = 1 };
+mjp_status mjp_loglik_set_kernel(int32_t model, int32_t kernel);
+
 /* Largest S1*S2 a log-likelihood item may have (LDS capacity of one CU). */
 int32_t mjp_loglik_max_states(void);
 

@@ -15,11 +15,16 @@ namespace mjp {
 mjp_status fail(mjp_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 void clear_error();
 
+// A failed HIP call is reported through the library's status and message;
+// HIP's per-thread last-error slot is cleared so the caller's next HIP call
+// does not report it again.
 #define MJP_HIP(expr)                                                                     \
     do {                                                                                  \
         hipError_t e_ = (expr);                                                           \
-        if (e_ != hipSuccess)                                                             \
+        if (e_ != hipSuccess) {                                                           \
+            (void)hipGetLastError();                                                      \
             return ::mjp::fail(MJP_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+        }                                                                                 \
     } while (0)
 
 #define MJP_CHECK(cond, status, ...)                 \

@@ -129,6 +129,7 @@ _SIGS = [
     ("mjp_expv_batched", ctypes.c_int, [ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P]),
     ("mjp_probe_exchange", ctypes.c_int, [_P, ctypes.c_int32, _P, _P]),
     ("mjp_loglik", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P]),
+    ("mjp_loglik_set_kernel", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32]),
     ("mjp_loglik_noalloc", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P]),
     ("mjp_loglik_noalloc_bytes", ctypes.c_int64, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     ("mjp_loglik_noalloc_capacity", ctypes.c_int64, []),
@@ -409,6 +410,13 @@ def mjp_loglik(model: int, theta, dims, obs: mjp_obs, out, opts: mjp_opts | None
     B = int(out.shape[0])
     _check(lib().mjp_loglik(model, B, _ptr(theta), _ptr(dims), ctypes.byref(obs), ctypes.byref(opts), _ptr(out),
                             _ptr(info), _stream(stream)))
+
+
+MJP_LL_KERNEL_AUTO, MJP_LL_KERNEL_CELLS = 0, 1
+
+
+def mjp_loglik_set_kernel(model: int, kernel: int) -> None:
+    _check(lib().mjp_loglik_set_kernel(model, kernel))
 
 
 def mjp_loglik_noalloc(model: int, theta, dims, obs: mjp_obs, out, opts: mjp_opts | None = None, info=None,

@@ -35,9 +35,12 @@ def shape_class(n):
 
 @pytest.fixture(autouse=True)
 def default_shapes():
+    """The cell kernel (whose shapes these tests cover) for every cascade item."""
+    mjp.mjp_loglik_set_kernel(1, mjp.MJP_LL_KERNEL_CELLS)
     mjp.mjp_loglik_set_shapes(1, [-1] * 4)
     yield
     mjp.mjp_loglik_set_shapes(1, [-1] * 4)
+    mjp.mjp_loglik_set_kernel(1, mjp.MJP_LL_KERNEL_AUTO)
 
 
 @pytest.fixture(scope="module")
