@@ -172,8 +172,8 @@ typedef struct {
  *     active R births at beta_R, P births at beta_P n_R, deaths at gamma_R n_R
  *     and gamma_P n_P, active + P -> inactive at lambda_ina n_P, inactive ->
  *     active + P at lambda_act.
- * Stencil plans (mjp_plan_create_stencil) cover BD and CASCADE2; the other
- * two are run through mjp_model_csr and a CSR plan. */
+ * Stencil plans (mjp_plan_create_stencil) cover all four: the kernels form
+ * each row's entries from theta and the state's coordinates (no matrix). */
 enum { MJP_MODEL_BD = 0, MJP_MODEL_CASCADE2 = 1, MJP_MODEL_TWOSTATE = 2, MJP_MODEL_AUTOREG = 3 };
 
 typedef struct {
@@ -203,8 +203,12 @@ typedef struct mjp_plan mjp_plan;
  * rounding.  Copies what it needs; the caller's arrays may be freed after. */
 mjp_status mjp_plan_create_csr(const mjp_csr* A, const mjp_opts* opts, mjp_plan** out);
 
-/* Build a plan for a built-in model: no matrix is stored, the kernels
- * compute each entry of B from theta when they need it. */
+/* Build a plan for a built-in model (any of the four): no matrix is stored,
+ * the kernels compute each entry of B from theta when they need it -- the
+ * same FP32 values a CSR plan of mjp_model_csr would hold up to the rounding
+ * of rate/Omega * count (products of FP32 factors here), with the diagonal as
+ * an FP32 pair so rows sum to their exact sum.  Omega comes from the same
+ * FP64 maximum exit rate as for the CSR generator. */
 mjp_status mjp_plan_create_stencil(const mjp_model* m, const mjp_opts* opts, mjp_plan** out);
 
 /* Free a plan and its device memory.  NULL is accepted. */

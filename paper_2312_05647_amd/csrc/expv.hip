@@ -202,37 +202,14 @@ struct StencilArgs {
 // FP64 sum of exactly those FP32 numbers, held as an FP32 pair hi + lo, so
 // rows of B sum to 1 to ~1e-16.
 __device__ __forceinline__ float stencil_row(const StencilCoef& cf, const float* __restrict__ x, int64_t m) {
-    if (cf.model == MJP_MODEL_BD) {
-        const int32_t N = cf.S1;
-        const int32_t i = (int32_t)m;
-        const float up = cf.c[0], dn = cf.c[1];
-        // exit coefficients of state i
-        const float o_up = (i + 1 < N || cf.leaky) ? up : 0.f;
-        const float o_dn = dn * (float)i;
-        float dh, dl;
-        diag_pair(1.0 - ((double)o_up + (double)o_dn), dh, dl);
-        float y = dl * x[i];
-        y = fmaf(dh, x[i], y);
-        if (i > 0) y = fmaf(up, x[i - 1], y);
-        if (i + 1 < N) y = fmaf(dn * (float)(i + 1), x[i + 1], y);
-        return y;
-    }
-    const int32_t S1 = cf.S1, S2 = cf.S2;
-    const int32_t i2 = (int32_t)(m / S1), i1 = (int32_t)(m - (int64_t)i2 * S1);
-    const float b1 = cf.c[0], d1 = cf.c[1], b2 = cf.c[2], d2 = cf.c[3];
-    const float f1 = (float)i1, f2 = (float)i2;
-    const float o_b1 = (i1 + 1 < S1 || cf.leaky) ? b1 : 0.f;
-    const float o_d1 = d1 * f1;
-    const float o_b2 = (i2 + 1 < S2 || cf.leaky) ? b2 * f1 : 0.f;
-    const float o_d2 = d2 * f2;
-    float dh, dl;
-    diag_pair(1.0 - (((double)o_b1 + (double)o_d1) + ((double)o_b2 + (double)o_d2)), dh, dl);
-    float y = dl * x[m];
-    y = fmaf(dh, x[m], y);
-    if (i1 > 0) y = fmaf(b1, x[m - 1], y);
-    if (i1 + 1 < S1) y = fmaf(d1 * (f1 + 1.f), x[m + 1], y);
-    if (i2 > 0) y = fmaf(b2 * f1, x[m - S1], y);
-    if (i2 + 1 < S2) y = fmaf(d2 * (f2 + 1.f), x[m + S1], y);
+    int32_t cc[kStencilMaxW];
+    float vv[kStencilMaxW], lo;
+    stencil_entries<kStencilMaxW>(cf, m, cc, vv, lo);
+    const float xs = x[m];
+    float y = lo * xs;
+    y = fmaf(vv[0], xs, y);
+#pragma unroll
+    for (int j = 1; j < kStencilMaxW; ++j) y = fmaf(vv[j], x[cc[j]], y);
     return y;
 }
 

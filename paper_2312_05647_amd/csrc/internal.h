@@ -59,8 +59,8 @@ enum PlanKind { PLAN_CSR = 0, PLAN_STENCIL = 1 };
 // FP32 coefficients of a built-in model's B = I + A/Omega, one per reaction
 // channel (the diagonal is formed from them in the kernels).
 struct StencilCoef {
-    float c[4];     // BD: {beta/O, gamma/O, 0, 0}; cascade2: {k1/O, g1/O, k2/O, g2/O}
-    int32_t S1, S2; // BD: {N, 1}
+    float c[6];     // rate / Omega per channel, in the order of the model's theta (mjp.h)
+    int32_t S1, S2; // dims: BD {N, 1}; cascade {S1, S2}; two-state {N_R, 1}; autoregulatory {N_R, N_P}
     int32_t model;
     int32_t leaky;
 };

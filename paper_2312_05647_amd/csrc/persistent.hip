@@ -229,37 +229,19 @@ __global__ __launch_bounds__(kPThreads) void k_persistent(PersistArgs a) {
             dlo[i] = live(i) ? a.dlo[row(i)] : 0.f;
         }
     } else {
-        // stencil: neighbour offsets and coefficients of each row (W == 5:
-        // self, -1, +1, -S1, +S1); absent neighbours get weight 0
-        const StencilCoef cf = a.cf;
+        // stencil: each row's entries from the model (stencil_entries: the
+        // diagonal first, then the inflows); absent entries get weight 0
 #pragma unroll
         for (int i = 0; i < R; ++i) {
             const int64_t m = live(i) ? (int64_t)row(i) : 0;
-            int32_t i1, i2, S1 = cf.S1, S2 = cf.S2;
-            if (cf.model == MJP_MODEL_BD) { i1 = (int32_t)m; i2 = 0; S2 = 1; }
-            else { i2 = (int32_t)(m / S1); i1 = (int32_t)(m - (int64_t)i2 * S1); }
-            const float f1 = (float)i1, f2 = (float)i2;
-            float b1, d1, b2, d2;
-            b1 = cf.c[0]; d1 = cf.c[1];
-            b2 = cf.model == MJP_MODEL_BD ? 0.f : cf.c[2];
-            d2 = cf.model == MJP_MODEL_BD ? 0.f : cf.c[3];
-            const float o_b1 = (i1 + 1 < S1 || cf.leaky) ? b1 : 0.f;
-            const float o_d1 = d1 * f1;
-            const float o_b2 = (i2 + 1 < S2 || cf.leaky) ? b2 * f1 : 0.f;
-            const float o_d2 = d2 * f2;
-            float diag, dl;
-            diag_pair(1.0 - (((double)o_b1 + (double)o_d1) + ((double)o_b2 + (double)o_d2)), diag, dl);
-            dlo[i] = live(i) ? dl : 0.f;
-            int32_t cc[5] = {(int32_t)m, (int32_t)m, (int32_t)m, (int32_t)m, (int32_t)m};
-            float vv[5] = {diag, 0.f, 0.f, 0.f, 0.f};
-            if (i1 > 0) { cc[1] = (int32_t)m - 1; vv[1] = b1; }
-            if (i1 + 1 < S1) { cc[2] = (int32_t)m + 1; vv[2] = d1 * (f1 + 1.f); }
-            if (i2 > 0) { cc[3] = (int32_t)m - S1; vv[3] = b2 * f1; }
-            if (i2 + 1 < S2) { cc[4] = (int32_t)m + S1; vv[4] = d2 * (f2 + 1.f); }
+            int32_t cc[W];
+            float vv[W], lo;
+            stencil_entries<W>(a.cf, m, cc, vv, lo);
+            dlo[i] = live(i) ? lo : 0.f;
 #pragma unroll
             for (int j = 0; j < W; ++j) {
-                coff[i][j] = 4u * (uint32_t)(j < 5 ? cc[j] : (int32_t)m);
-                cval[i][j] = (j < 5 && live(i)) ? vv[j] : 0.f;
+                coff[i][j] = 4u * (uint32_t)cc[j];
+                cval[i][j] = live(i) ? vv[j] : 0.f;
             }
         }
     }
@@ -552,31 +534,7 @@ __device__ __forceinline__ void row_entries(const PersistArgs& a, int64_t m, int
             }
         }
     } else {
-        const StencilCoef cf = a.cf;
-        int32_t i1, i2, S1 = cf.S1, S2 = cf.S2;
-        if (cf.model == MJP_MODEL_BD) { i1 = (int32_t)m; i2 = 0; S2 = 1; }
-        else { i2 = (int32_t)(m / S1); i1 = (int32_t)(m - (int64_t)i2 * S1); }
-        const float f1 = (float)i1, f2 = (float)i2;
-        const float b1 = cf.c[0], d1 = cf.c[1];
-        const float b2 = cf.model == MJP_MODEL_BD ? 0.f : cf.c[2];
-        const float d2 = cf.model == MJP_MODEL_BD ? 0.f : cf.c[3];
-        const float o_b1 = (i1 + 1 < S1 || cf.leaky) ? b1 : 0.f;
-        const float o_d1 = d1 * f1;
-        const float o_b2 = (i2 + 1 < S2 || cf.leaky) ? b2 * f1 : 0.f;
-        const float o_d2 = d2 * f2;
-        float diag;
-        diag_pair(1.0 - (((double)o_b1 + (double)o_d1) + ((double)o_b2 + (double)o_d2)), diag, lo);
-        int32_t c5[5] = {(int32_t)m, (int32_t)m, (int32_t)m, (int32_t)m, (int32_t)m};
-        float v5[5] = {diag, 0.f, 0.f, 0.f, 0.f};
-        if (i1 > 0) { c5[1] = (int32_t)m - 1; v5[1] = b1; }
-        if (i1 + 1 < S1) { c5[2] = (int32_t)m + 1; v5[2] = d1 * (f1 + 1.f); }
-        if (i2 > 0) { c5[3] = (int32_t)m - S1; v5[3] = b2 * f1; }
-        if (i2 + 1 < S2) { c5[4] = (int32_t)m + S1; v5[4] = d2 * (f2 + 1.f); }
-#pragma unroll
-        for (int j = 0; j < W; ++j) {
-            cc[j] = j < 5 ? c5[j] : (int32_t)m;
-            vv[j] = j < 5 ? v5[j] : 0.f;
-        }
+        stencil_entries<W>(a.cf, m, cc, vv, lo);
     }
 }
 
@@ -927,6 +885,7 @@ static PersistFn pick(int R, int W) {
         MJP_CASE(1, 16) MJP_CASE(2, 16)
     } else {
         MJP_CASE(1, 5) MJP_CASE(2, 5) MJP_CASE(4, 5) MJP_CASE(8, 5)
+        MJP_CASE(1, 8) MJP_CASE(2, 8) MJP_CASE(4, 8)
     }
 #undef MJP_CASE
     return nullptr;
@@ -941,7 +900,7 @@ __global__ void k_zero_u32(unsigned* p, int n) {
 bool persistent_fits(const mjp_plan* p, int max_open, bool coh, PersistCfg& cfg) {
     if (max_open > kPSlots) return false;
     if (p->n >= ((int64_t)1 << 30)) return false;  // byte offsets of the iterate must fit 32 bits
-    int W = 5;
+    int W = stencil_width(p->coef.model) <= 5 ? 5 : 8;
     if (p->kind == PLAN_CSR) {
         if (p->max_width <= 3) W = 3;
         else if (p->max_width <= 5) W = 5;
@@ -1016,7 +975,7 @@ static bool build_p2_table(const mjp_plan* p, int G, std::vector<int32_t>& tab) 
             lo = p->slice_cmin[(size_t)sl];
             hi = p->slice_cmax[(size_t)sl];
         } else {
-            const int64_t reach = p->coef.model == MJP_MODEL_BD ? 1 : p->coef.S1;
+            const int64_t reach = stencil_reach(p->coef);
             lo = std::max<int64_t>(0, sl * 64 - reach);
             hi = std::min<int64_t>(n - 1, sl * 64 + 63 + reach);
         }
@@ -1077,6 +1036,7 @@ bool persistent2_fits(mjp_plan* p, int max_open, PersistCfg& cfg) {
     if (max_open > kP2Slots) return false;
     if (p->n >= ((int64_t)1 << 30)) return false;
     if (p->opts.renorm_every % 2 != 0) return false;  // renormalisation points must end a round
+    if (p->kind == PLAN_STENCIL && stencil_width(p->coef.model) > 5) return false;  // halo entries: W <= 5
     int W = 5;
     if (p->kind == PLAN_CSR) {
         if (p->max_width <= 3) W = 3;
@@ -1158,7 +1118,7 @@ static mjp_status build_sweep_tables(mjp_plan* p, const PersistCfg& cfg, const i
             smin[(size_t)sl] = p->slice_cmin[(size_t)sl];
             smax[(size_t)sl] = p->slice_cmax[(size_t)sl];
         } else {
-            const int64_t reach = p->coef.model == MJP_MODEL_BD ? 1 : p->coef.S1;
+            const int64_t reach = stencil_reach(p->coef);
             smin[(size_t)sl] = std::max<int64_t>(0, sl * 64 - reach);
             smax[(size_t)sl] = std::min<int64_t>(n - 1, sl * 64 + 63 + reach);
         }

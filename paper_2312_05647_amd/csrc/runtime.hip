@@ -601,20 +601,18 @@ mjp_status mjp_plan_create_stencil(const mjp_model* m, const mjp_opts* opts, mjp
     mjp_status st = check_model(m);
     if (st) return st;
     if ((st = check_opts(opts))) return st;
-    MJP_CHECK(m->model == MJP_MODEL_BD || m->model == MJP_MODEL_CASCADE2, MJP_E_UNSUPPORTED,
-              "stencil plans cover the birth-death and cascade models; build the others with mjp_model_csr");
     mjp_plan* p = new (std::nothrow) mjp_plan();
     MJP_CHECK(p, MJP_E_DEVICE, "out of host memory");
     p->kind = PLAN_STENCIL;
     p->model = *m;
     p->opts = *opts;
-    p->n = m->dims[0] * m->dims[1];
+    p->n = (int32_t)model_states(m);
     const int leaky = opts->truncation == MJP_LEAKY;
     p->m_theta = model_max_exit(m, leaky);
     p->omega = opts->omega_factor * p->m_theta;
     const double omega = p->omega > 0.0 ? p->omega : 1.0;
-    const int np = m->model == MJP_MODEL_BD ? 2 : 4;
-    for (int i = 0; i < 4; ++i) p->coef.c[i] = i < np ? (float)(m->theta[i] / omega) : 0.0f;
+    const int np = m->model == MJP_MODEL_BD ? 2 : (m->model == MJP_MODEL_AUTOREG ? 6 : 4);
+    for (int i = 0; i < 6; ++i) p->coef.c[i] = i < np ? (float)(m->theta[i] / omega) : 0.0f;
     p->coef.S1 = m->dims[0];
     p->coef.S2 = m->dims[1];
     p->coef.model = m->model;

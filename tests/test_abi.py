@@ -363,9 +363,15 @@ def test_new_model_dims_validation(model, dims):
     assert status_of(mjp.mjp_model_csr, m) == mjp.MJP_E_INVALID_ARG
 
 
-def test_stencil_plans_refuse_gene_state_models():
-    for model, dims in ((2, [10]), (3, [4, 5])):
-        assert status_of(mjp.mjp_plan_create_stencil, mjp.make_model(model, [1.0] * 6, dims)) == mjp.MJP_E_UNSUPPORTED
+def test_stencil_plans_take_gene_state_models():
+    """Stencil plans cover the two-state and autoregulatory models: their
+    host checks pass (without a GPU the only failure left is the device
+    lookup), and bad dims are rejected before that."""
+    for model, dims in ((2, [10, 1]), (3, [4, 5])):
+        st = status_of(mjp.mjp_plan_create_stencil, mjp.make_model(model, [1.0] * 6, dims))
+        assert st in (mjp.MJP_OK, mjp.MJP_E_DEVICE), st
+    for model, dims in ((2, [0, 1]), (3, [4, 0])):
+        assert status_of(mjp.mjp_plan_create_stencil, mjp.make_model(model, [1.0] * 6, dims)) == mjp.MJP_E_INVALID_ARG
 
 
 def test_noalloc_loglik_rejects_oversize_on_the_host():

@@ -31,9 +31,13 @@ def say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def expv_gpu(model, theta, dims, rho0, times, variant):
-    rp, ci, va = mjp.mjp_model_csr(mjp.make_model(model, theta, dims))
-    plan = mjp.mjp_plan_create_csr(rp, ci, va, mjp.mjp_opts_default(variant=variant))
+def expv_gpu(model, theta, dims, rho0, times, variant, kind="csr", **opts):
+    o = mjp.mjp_opts_default(variant=variant, **opts)
+    if kind == "csr":
+        rp, ci, va = mjp.mjp_model_csr(mjp.make_model(model, theta, dims), truncation=o.truncation)
+        plan = mjp.mjp_plan_create_csr(rp, ci, va, o)
+    else:
+        plan = mjp.mjp_plan_create_stencil(mjp.make_model(model, theta, dims), o)
     try:
         n = mjp.mjp_plan_n(plan)
         r0 = torch.as_tensor(np.asarray(rho0, np.float32), device="cuda")
@@ -55,30 +59,67 @@ def check(got, ref, what, K):
     return l1
 
 
+@pytest.mark.parametrize("kind", ["csr", "stencil"])
 @pytest.mark.parametrize("variant", [mjp.MJP_VARIANT_PERSISTENT, mjp.MJP_VARIANT_STEPWISE])
-def test_two_state_expv(orc, variant):
+def test_two_state_expv(orc, variant, kind):
     NR = 250
     A = orc.model_generator(orc.MODEL_TWOSTATE, TS_THETA, [NR])
     times = [0.5, 2.0, 10.0]
     ref = orc.expv_times(A, synth.delta(2 * NR), times)
-    say(f"[gpu] two-state N={2 * NR} variant {variant}")
-    got, inf = expv_gpu(mjp.MJP_MODEL_TWOSTATE, TS_THETA, [NR, 1], synth.delta(2 * NR), times, variant)
+    say(f"[gpu] two-state N={2 * NR} {kind} variant {variant}")
+    got, inf = expv_gpu(mjp.MJP_MODEL_TWOSTATE, TS_THETA, [NR, 1], synth.delta(2 * NR), times, variant, kind)
     for j, t in enumerate(times):
         check(got[j], ref[j], f"t={t}", inf[j]["K"])
         assert inf[j]["flags"] == 0
 
 
+@pytest.mark.parametrize("kind", ["csr", "stencil"])
 @pytest.mark.parametrize("variant", [mjp.MJP_VARIANT_PERSISTENT, mjp.MJP_VARIANT_STEPWISE])
-def test_autoreg_expv(orc, variant):
+def test_autoreg_expv(orc, variant, kind):
     NR, NP = 20, 60
     A = orc.model_generator(orc.MODEL_AUTOREG, AR_THETA, [NR, NP])
     rho0 = synth.random_prob(2 * NR * NP, 12)
     times = [0.5, 3.0, 10.0]
     ref = orc.expv_times(A, rho0, times)
-    say(f"[gpu] autoregulatory N={2 * NR * NP} variant {variant}")
-    got, inf = expv_gpu(mjp.MJP_MODEL_AUTOREG, AR_THETA, [NR, NP], rho0, times, variant)
+    say(f"[gpu] autoregulatory N={2 * NR * NP} {kind} variant {variant}")
+    got, inf = expv_gpu(mjp.MJP_MODEL_AUTOREG, AR_THETA, [NR, NP], rho0, times, variant, kind)
     for j, t in enumerate(times):
         check(got[j], ref[j], f"t={t}", inf[j]["K"])
+
+
+@pytest.mark.parametrize("variant", [mjp.MJP_VARIANT_PERSISTENT, mjp.MJP_VARIANT_STEPWISE])
+def test_autoreg_stencil_many_workgroups(orc, variant):
+    """A grid large enough for the persistent sweep to spread over many
+    workgroups (N = 2 * 60 * 120 = 14,400; rows reach a whole n_P plane
+    away), from a random start, stencil plan against the oracle."""
+    NR, NP = 60, 120
+    theta = [8.0, 0.4, 1.0, 0.1, 0.2, 0.05]
+    A = orc.model_generator(orc.MODEL_AUTOREG, theta, [NR, NP])
+    rho0 = synth.random_prob(2 * NR * NP, 5)
+    times = [0.7, 4.0]
+    ref = orc.expv_times(A, rho0, times)
+    say(f"[gpu] autoregulatory stencil N={2 * NR * NP} variant {variant}")
+    got, inf = expv_gpu(mjp.MJP_MODEL_AUTOREG, theta, [NR, NP], rho0, times, variant, "stencil")
+    for j, t in enumerate(times):
+        check(got[j], ref[j], f"t={t}", inf[j]["K"])
+
+
+@pytest.mark.parametrize("model,theta,dims", [(mjp.MJP_MODEL_TWOSTATE, TS_THETA, [120, 1]),
+                                              (mjp.MJP_MODEL_AUTOREG, AR_THETA, [12, 30])])
+def test_gene_state_stencil_leaky(orc, model, theta, dims):
+    """Leaky truncation (births off the grid still leave, no renormalisation):
+    the stencil plan against the oracle's leaky generator; the lost mass
+    matches."""
+    A = orc.model_generator(model, theta, dims[:1] if model == mjp.MJP_MODEL_TWOSTATE else dims, leaky=True)
+    n = A.n if hasattr(A, "n") else len(A.row_ptr) - 1
+    times = [1.0, 6.0]
+    ref = orc.expv_times(A, synth.delta(n), times)
+    say(f"[gpu] model {model} leaky stencil N={n}")
+    got, inf = expv_gpu(model, theta, dims, synth.delta(n), times, mjp.MJP_VARIANT_AUTO, "stencil",
+                        truncation=mjp.MJP_LEAKY, renorm_every=0)
+    for j, t in enumerate(times):
+        check(got[j], ref[j], f"t={t}", inf[j]["K"])
+        assert abs(got[j].sum() - ref[j].sum()) <= 1e-6
 
 
 def run_loglik(model, theta, dims, T, recs, x0):
