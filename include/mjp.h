@@ -354,6 +354,19 @@ int64_t mjp_loglik_noalloc_capacity(void);
 enum { MJP_LL_KERNEL_AUTO = 0, MJP_LL_KERNEL_CELLS = 1 };
 mjp_status mjp_loglik_set_kernel(int32_t model, int32_t kernel);
 
+/* Items of the cascade and birth-death models with more states than one
+ * workgroup's LDS holds (S1*S2 > mjp_loglik_max_states()) run in clusters
+ * of *group_h workgroups of one cooperative launch (each workgroup owns a
+ * contiguous range of states, the boundary rows are exchanged every jump),
+ * up to *max_states_h states and, for the cascade, S1 <= 1024; larger items
+ * (and any large item of the other models, or in mjp_loglik_noalloc) get
+ * -inf with MJP_FLAG_OUT_OF_GRID.  Reports, for the current device, the
+ * clusters that run co-resident (0: none, large items then get -inf), the
+ * cluster workgroups that fit one CU and whether cooperative launches are
+ * supported.  Any pointer may be NULL. */
+mjp_status mjp_loglik_cluster_config(int32_t* clusters_h, int32_t* per_cu_h, int32_t* coop_h, int32_t* group_h,
+                                     int32_t* max_states_h);
+
 /* Largest S1*S2 a log-likelihood item may have (LDS capacity of one CU). */
 int32_t mjp_loglik_max_states(void);
 

@@ -90,8 +90,8 @@ __device__ __forceinline__ void block_sums(double (&v)[M], P red) {
 // kMaxBlocks blocks, so one level suffices: the last block to arrive sums
 // every partial, with all of its loads issued together (a second level of
 // group sums would add a ticket and a round of loads to the kernel's tail).
-constexpr int kCpolSC1 = 16;            // device-scope cache policy of a buffer access
-constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, 32-bit elements, no swizzle
+// (kCpolSC1 and kRsrcWord3, the device-scope cache policy of a buffer
+// access and the raw-buffer descriptor word, come from gridsync.h)
 
 __device__ __forceinline__ void put_partial(double* p, double v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

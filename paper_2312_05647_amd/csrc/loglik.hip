@@ -33,6 +33,7 @@
 #include <utility>
 #include <vector>
 
+#include "gridsync.h"
 #include "internal.h"
 
 namespace mjp {
@@ -74,8 +75,21 @@ constexpr int kColReal = 62;
 constexpr int kColLanes = kColReal * (kColT / 64);
 constexpr int kColClasses = 8;
 constexpr int kColCs[kColClasses] = {8, 16, 24, 32, 40, 48, 56, 64};
-constexpr int kAllClasses = kColClasses + kLLClasses;
 constexpr bool kColEnabled = false;
+
+// Items above one workgroup's LDS (cascade and birth-death, S1*S2 >
+// kLLMaxStates) run in clusters of kClG workgroups (k_ll_cluster below):
+// each owns a contiguous range of at most kClOwn states and exchanges the
+// kClReach-row boundary with its neighbours every jump.  Their queue class
+// follows the cell kernel's.
+constexpr int kClT = 1024;
+constexpr int kClC = 32;
+constexpr int kClOwn = kClT * kClC;        // states one workgroup owns at most
+constexpr int kClG = 4;                    // workgroups per item
+constexpr int kClReachMax = 1024;          // S1 of a cascade item at most
+constexpr int kClMaxStates = kClG * kClOwn;
+constexpr int kClClass = kColClasses + kLLClasses;
+constexpr int kAllClasses = kClClass + 1;
 
 // Segments of an item (S1 columns, S2 rows) for the column kernel: nseg
 // segments of len = kColCs[class] consecutive rows (the register template,
@@ -129,7 +143,8 @@ struct LLArgs {
     double* __restrict__ phi;           // jump mode: [B][n_rec] log p(s_i | k_i, theta)
     double* __restrict__ omega_out;     // jump mode: [B] Omega_theta, or null
     int32_t B, n_t, n_rec, model, x0_1, x0_2;
-    int32_t use_col;                    // cascade/birth-death items that fit go to the column kernel
+    int32_t use_col;                    // cascade items that fit go to the column kernel
+    int32_t use_cluster;                // cascade/birth-death items above kLLMaxStates go to clusters
     double omega_factor, tol;
     int32_t k_rule, lump, renorm_every;
     int64_t k_cap;
@@ -278,6 +293,10 @@ __global__ void k_jp_prep(LLArgs a) {
 // else kColClasses + its size class
 __device__ inline int ll_item_class(const LLArgs& a, int S1, int S2) {
     // (a.use_col is set only for cascade items with at most kColT records)
+    const int64_t n = (int64_t)S1 * S2;
+    if (a.use_cluster && n > kLLMaxStates && n <= kClMaxStates &&
+        (a.model == MJP_MODEL_BD || (a.model == MJP_MODEL_CASCADE2 && S1 <= kClReachMax)))
+        return kClClass;
     int cc, ns, len, S2p;
     if (a.use_col && col_geom(S1, S2, cc, ns, len, S2p) && (int64_t)S1 * S2p <= col_cap(cc)) return cc;
     return kColClasses + ll_class((int64_t)S1 * S2);
@@ -303,6 +322,7 @@ __global__ void k_ll_order(LLArgs a) {
             int S1, S2;
             ll_grid(a.model, a.dims + 2 * b, S1, S2);
             const int cls = ll_item_class(a, S1, S2);
+            if (cls == kClClass && a.loglik) a.loglik[b] = NAN;  // until its cluster finishes it
             atomicAdd(&cnt[cls], 1);
             const float c = fmaxf((float)(kmax + 1) * (float)S1 * (float)S2, 0.f);
             a.cost[b] = c;
@@ -906,6 +926,335 @@ __global__ __launch_bounds__(kColT) void k_ll_col(LLArgs a, int cls) {
     }
 }
 
+// ------------------------------------------------------- cluster kernel
+//
+// The cell kernel's sweep (k_ll_main: the same cell update, weights,
+// renormalisation and record accumulation) for an item too large for one
+// workgroup's LDS, run by a cluster of kClG workgroups of one cooperative
+// launch.  Cluster c takes the items c, c + nclust, ... of the class (cost
+// order), so every workgroup of a cluster knows the item without a
+// broadcast.  Workgroup r of a cluster owns the states [lo, hi) =
+// [r len, (r + 1) len), len = ceil(N / kClG), and keeps them in LDS with a
+// halo of reach = S1 states (the pull rows' farthest column) on each side.
+// A jump: the new values of the own states into registers, a barrier, into
+// LDS; the reach states at each end of the own range written to the
+// cluster's exchange buffer (device-scope stores, the slot of the jump's
+// parity); every wave drains its stores; the workgroup publishes the number
+// of jumps done on its flag and waits for its neighbours' (all of the
+// cluster's at a renormalisation, whose block sums travel the same way); it
+// then reads its halo from the neighbours' slots (device-scope loads).  Every
+// wait has the 2 s deadline of the persistent sweeps: on a miss the abort
+// word is raised and every workgroup leaves, the items not finished keep
+// the NaN k_ll_order wrote.  At the end of an item each workgroup's FP64 sum
+// of count log p over the records of its own states meets the others' in
+// the same way and rank 0 adds them in rank order.
+struct ClArgs {
+    LLArgs a;
+    float* __restrict__ xbuf;      // [nclust][2][kClG][2][kClReachMax] boundary states
+    double* __restrict__ part;     // [nclust][4][kClG] block sums: renormalisation masses (two
+                                   // slots, alternating), an item's log-lik and mass
+    double* __restrict__ ninf;     // [nclust][kClG] count of records with no probability
+    unsigned* __restrict__ wflag;  // [nclust][kClG][32] jumps (exchange rounds) done
+    unsigned* __restrict__ abort_word;
+    uint64_t timeout_ticks;
+    int32_t nclust;
+};
+
+// Publish `round` on my flag and wait until the workgroups of my cluster in
+// [rlo, rhi] have published it (bounded); false if the sweep aborted.
+__device__ __forceinline__ bool cl_sync(unsigned* wf, int r, int rlo, int rhi, unsigned round, unsigned* abort_word,
+                                        uint64_t timeout_ticks) {
+    __shared__ int aborted;
+    drain_wave<true>();
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        if (lane == 0) {
+            aborted = 0;
+            __hip_atomic_store(&wf[r * 32], round, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        const int h = rlo + lane;
+        bool bad = false;
+        if (h <= rhi && h != r) {
+            const uint64_t t0 = wall_clock64();
+            unsigned spins = 0;
+            while (__hip_atomic_load(&wf[h * 32], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < round) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins % kAbortCheckEvery != 0) continue;
+                if (__hip_atomic_load(abort_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                    bad = true;
+                    break;
+                }
+                if (wall_clock64() - t0 > timeout_ticks) {
+                    __hip_atomic_store(abort_word, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    bad = true;
+                    break;
+                }
+            }
+        }
+        if (bad) aborted = 1;
+    }
+    __syncthreads();
+    return aborted == 0;
+}
+
+template <int MODEL>
+__global__ __launch_bounds__(kClT) void k_ll_cluster(ClArgs ca) {
+    constexpr int T = kClT, C = kClC;
+    constexpr int CAP = kClOwn + 2 * kClReachMax;  // own states and both halos
+    const LLArgs& a = ca.a;
+    extern __shared__ __align__(16) char lds[];
+    float* lx = reinterpret_cast<float*>(lds);                             // [CAP]
+    double* wbuf = reinterpret_cast<double*>(lds + sizeof(float) * CAP);   // [2][kLLMaxTimes]
+    double* scratch = wbuf + 2 * kLLMaxTimes;                              // [16]
+    LLWin* win = reinterpret_cast<LLWin*>(scratch + 16);                   // [kLLMaxTimes]
+    __shared__ unsigned flag_sh;
+    const int tid = threadIdx.x;
+    const int cl = blockIdx.x / kClG, r = blockIdx.x - cl * kClG;
+    const int first = a.cls_off[kClClass], last = a.cls_off[kClClass + 1];
+    unsigned* wf = ca.wflag + (size_t)cl * kClG * 32;
+    float* xb = ca.xbuf + (size_t)cl * 2 * kClG * 2 * kClReachMax;
+    double* pt = ca.part + (size_t)cl * 4 * kClG;
+    unsigned round = 0;  // exchange rounds done (the same in every workgroup of the cluster)
+    for (int slot = first + cl; slot < last; slot += ca.nclust) {
+        const int b = a.order[slot];
+        const double* th = a.theta + ll_stride(MODEL) * (int64_t)b;
+        int S1, S2;
+        ll_grid(MODEL, a.dims + 2 * b, S1, S2);
+        if (tid < a.n_t) win[tid] = a.win[(int64_t)b * a.n_t + tid];
+        if (tid == 0) flag_sh = 0u;
+        __syncthreads();
+        unsigned flags = 0;
+        int32_t Kmax = 0, Lmin = INT32_MAX;
+        bool over = false;
+        for (int j = 0; j < a.n_t; ++j) {
+            const int Kj = win[j].K;
+            if (Kj < 0) over = true;
+            Kmax = max(Kmax, Kj);
+            Lmin = min(Lmin, win[j].L);
+        }
+        const int64_t N64 = (int64_t)S1 * S2;
+        const double omega = a.omega_factor * ll_max_exit(MODEL, th, a.dims + 2 * b);
+        const int reach = MODEL == MJP_MODEL_BD ? 1 : S1;
+        if (over || S1 < 1 || S2 < 1 || N64 > kClMaxStates || reach > kClReachMax) {
+            if (r == 0 && tid == 0) {
+                a.loglik[b] = -INFINITY;
+                if (a.info) {
+                    mjp_info inf{};
+                    inf.omega = omega;
+                    inf.flags = over ? MJP_FLAG_K_LIMIT : MJP_FLAG_OUT_OF_GRID;
+                    a.info[b] = inf;
+                }
+            }
+            continue;
+        }
+        const int N = (int)N64;
+        const int len = (N + kClG - 1) / kClG;
+        const int lo = min(N, r * len), hi = min(N, lo + len);
+        const int hlo = max(0, lo - reach), hhi = min(N, hi + reach);
+        float* rho = lx - hlo;  // rho[m] for m in [hlo, hhi)
+        const double om = omega > 0.0 ? omega : 1.0;
+        LLCoef kc;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) kc.c[i] = i < ll_params(MODEL) ? (float)(th[i] / om) : 0.f;
+        kc.NP = 1;
+        const int x0lim2 = S2;
+        const int x0 = (a.x0_1 < S1 && a.x0_2 < x0lim2) ? a.x0_1 + S1 * a.x0_2 : -1;
+        for (int m = hlo + tid; m < hhi; m += T) rho[m] = (m == x0) ? 1.f : 0.f;
+
+        // the records whose state this workgroup owns
+        int rm[kLLRecPerThread], rt[kLLRecPerThread];
+        float rs[kLLRecPerThread], rc[kLLRecPerThread];
+        bool any_off = false;
+#pragma unroll
+        for (int u = 0; u < kLLRecPerThread; ++u) {
+            const int rr = tid + u * T;
+            rm[u] = -2;
+            rt[u] = 0;
+            rs[u] = 0.f;
+            rc[u] = 0.f;
+            if (rr < a.n_rec) {
+                const LLRecord R = a.rec[rr];
+                const int m = (R.x1 < S1 && R.x2 < S2) ? R.x1 + S1 * R.x2 : -1;
+                if (m < 0) {
+                    any_off = true;  // every workgroup sees it; rank 0 reports it
+                } else if (m >= lo && m < hi) {
+                    rm[u] = m;
+                    rt[u] = R.t;
+                }
+            }
+        }
+        if (any_off && r == 0) flags |= MJP_FLAG_OUT_OF_GRID;
+        if (tid < a.n_t) wbuf[tid] = 0.0;
+        __syncthreads();
+        if (x0 < 0 && r == 0) flags |= MJP_FLAG_OUT_OF_GRID;
+
+        const int qT = T / S1, rT = T - qT * S1;
+        const int s0 = lo + tid;
+        const int i1_0 = s0 % S1, i2_0 = s0 / S1;
+        double scale = 1.0;
+        const int m_renorm = a.renorm_every;
+        int rpar = 0;
+        double lw = 0.0, logW = 0.0;
+        if (tid < a.n_t) {
+            const double W = win[tid].W;
+            logW = W > 0.0 ? log(W) : 0.0;
+            lw = W > 0.0 ? -W : 0.0;
+        }
+        const __amdgpu_buffer_rsrc_t xr = iter_rsrc(xb, (int64_t)2 * kClG * 2 * kClReachMax);
+        bool ok = true;
+        for (int k = 0; k <= Kmax && ok; ++k) {
+            if (tid < a.n_t) {
+                if (k > 0) lw += logW - log((double)k);
+                const double W = win[tid].W;
+                wbuf[(k & 1) * kLLMaxTimes + tid] = W > 0.0 ? exp(lw) : (k == 0 ? 1.0 : 0.0);
+            }
+            if (k > 0) {
+                float nv[C];
+                int i1 = i1_0, i2 = i2_0, mb = s0;
+                asm volatile("" : "+v"(i1), "+v"(i2), "+v"(mb));
+                const float fs = (float)scale;
+                float part = 0.f;
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const int m = mb + c * T;
+                    float y = 0.f;
+                    if (m < hi) y = fs * ll_cell<MODEL>(rho, m, i1, i2, S1, S2, kc);
+                    nv[c] = y;
+                    part += y;
+                    i1 += rT;
+                    i2 += qT;
+                    if (i1 >= S1) { i1 -= S1; i2 += 1; }
+                }
+                __syncthreads();  // every read of the old values is done
+                // own states into LDS; the boundary states into this jump's slot:
+                // [parity][r][0] the first reach states, [parity][r][1] the last reach
+                const uint32_t sbase = (uint32_t)((((k & 1) * kClG + r) * 2) * kClReachMax);
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const int m = s0 + c * T;
+                    if (m < hi) {
+                        rho[m] = nv[c];
+                        if (m - lo < reach) st_iter<true>(xr, 4u * (sbase + (uint32_t)(m - lo)), nv[c]);
+                        if (hi - m <= reach)
+                            st_iter<true>(xr, 4u * (sbase + kClReachMax + (uint32_t)(m - (hi - reach))), nv[c]);
+                    }
+                }
+                const bool renorm = m_renorm > 0 && k % m_renorm == 0 && k < Kmax;
+                if (renorm) {
+                    const double s = ll_block_sum<T>((double)part, scratch);
+                    if (tid == 0)
+                        __hip_atomic_store(pt + rpar * kClG + r, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                ++round;
+                ok = renorm ? cl_sync(wf, r, 0, kClG - 1, round, ca.abort_word, ca.timeout_ticks)
+                            : cl_sync(wf, r, max(0, r - 1), min(kClG - 1, r + 1), round, ca.abort_word,
+                                      ca.timeout_ticks);
+                if (!ok) break;
+                // the halo from the neighbours' slots of this jump
+                for (int m = hlo + tid; m < lo; m += T) {  // rank r - 1's last reach states
+                    const uint32_t o = (uint32_t)((((k & 1) * kClG + (r - 1)) * 2 + 1) * kClReachMax) +
+                                       (uint32_t)(m - (lo - reach));
+                    rho[m] = ld_iter<true>(xr, 4u * o);
+                }
+                for (int m = hi + tid; m < hhi; m += T) {  // rank r + 1's first reach states
+                    const uint32_t o = (uint32_t)((((k & 1) * kClG + (r + 1)) * 2) * kClReachMax) + (uint32_t)(m - hi);
+                    rho[m] = ld_iter<true>(xr, 4u * o);
+                }
+                if (renorm) {
+                    double tot = 0.0;
+                    for (int q = 0; q < kClG; ++q)
+                        tot += __hip_atomic_load(pt + rpar * kClG + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    scale = tot > 0.0 ? 1.0 / tot : 1.0;  // rho(0) has unit mass
+                    rpar ^= 1;
+                } else {
+                    scale = 1.0;
+                }
+                __syncthreads();
+            } else {
+                __syncthreads();
+            }
+#pragma unroll
+            for (int u = 0; u < kLLRecPerThread; ++u) {
+                if (rm[u] < 0) continue;
+                const LLWin& w = win[rt[u]];
+                if (k < w.L || k > w.K) continue;
+                const float wt = (k == w.K) ? (float)w.lastw : (float)wbuf[(k & 1) * kLLMaxTimes + rt[u]];
+                const float v = rho[rm[u]];
+                if (k == w.L) {
+                    rs[u] = wt * v;
+                    rc[u] = 0.f;
+                } else {
+                    const float yk = fmaf(wt, v, -rc[u]);
+                    const float t = rs[u] + yk;
+                    rc[u] = (t - rs[u]) - yk;
+                    rs[u] = t;
+                }
+            }
+        }
+        if (!ok) return;  // aborted: every workgroup leaves
+        double ll = 0.0, nneg = 0.0;
+#pragma unroll
+        for (int u = 0; u < kLLRecPerThread; ++u) {
+            if (rm[u] < 0) continue;
+            const float p = rs[u] - rc[u];
+            if (!(p > 0.f)) {
+                nneg += 1.0;
+                flags |= MJP_FLAG_UNDERFLOW_OBS;
+                continue;
+            }
+            ll += (double)a.rec[tid + u * T].count * log((double)p);
+        }
+        const double tot = ll_block_sum<T>(ll, scratch);
+        const double bad = ll_block_sum<T>(nneg, scratch);
+        float mpart = 0.f;
+        for (int m = lo + tid; m < hi; m += T) mpart += rho[m];
+        const double mass = ll_block_sum<T>((double)mpart, scratch);
+        if (flags) atomicOr(&flag_sh, flags);
+        __syncthreads();
+        // the workgroups' sums meet in slots of their own (a workgroup that
+        // is not my neighbour may still read the renormalisation slots)
+        if (tid == 0) {
+            __hip_atomic_store(pt + 2 * kClG + r, tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(pt + 3 * kClG + r, mass, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(ca.ninf + (size_t)cl * kClG + r, bad + (double)(flag_sh & MJP_FLAG_OUT_OF_GRID ? 1 : 0),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        ++round;
+        if (!cl_sync(wf, r, 0, kClG - 1, round, ca.abort_word, ca.timeout_ticks)) return;
+        if (r == 0 && tid == 0) {
+            double sll = 0.0, smass = 0.0, sbad = 0.0;
+            for (int q = 0; q < kClG; ++q) {
+                sll += __hip_atomic_load(pt + 2 * kClG + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                smass += __hip_atomic_load(pt + 3 * kClG + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                sbad += __hip_atomic_load(ca.ninf + (size_t)cl * kClG + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            a.loglik[b] = sbad > 0.0 ? -INFINITY : sll;
+            if (a.info) {
+                mjp_info inf{};
+                inf.omega = omega;
+                inf.W = win[a.n_t - 1].W;
+                inf.mass_in = x0 >= 0 ? 1.0 : 0.0;
+                inf.mass_out = smass;
+                inf.K = Kmax;
+                inf.L = Lmin;
+                inf.flags = (int32_t)flag_sh;  // rank 0's flags: out-of-grid; its own underflows
+                a.info[b] = inf;
+            }
+        }
+        // the end-of-item slots are reused by the next item only after
+        // another cluster-wide round: nobody overwrites them before rank 0
+        // read them (and the renormalisation slots of this item are free)
+        ++round;
+        if (!cl_sync(wf, r, 0, kClG - 1, round, ca.abort_word, ca.timeout_ticks)) return;
+    }
+}
+
+__global__ void k_ll_zero_u32(unsigned* p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
 // ---------------------------------------------------------------- host
 
 using MainFn = void (*)(LLArgs, int);
@@ -946,6 +1295,9 @@ constexpr size_t kColExtra = sizeof(double) * (2 * kLLMaxTimes + 16) + sizeof(LL
 static_assert(sizeof(float) * kColMirror + kColExtra + 64 <= 160 * 1024, "column kernel LDS exceeds a CU");
 inline size_t col_lds(int cc) { return sizeof(float) * (size_t)col_cap(cc) + kColExtra; }
 inline bool col_model(int model) { return model == MJP_MODEL_CASCADE2; }
+// LDS of a cluster workgroup: own states and halos, then the weights,
+// block-sum scratch and windows (as the column kernel's extras)
+inline size_t cl_lds() { return sizeof(float) * (size_t)(kClOwn + 2 * kClReachMax) + kColExtra; }
 
 inline size_t ll_lds(int shape) {
     return sizeof(float) * (size_t)ll_cap(kLLShapes[shape].T, kLLShapes[shape].C) + kLLExtraLds;
@@ -982,6 +1334,7 @@ struct LLObsSet {
 struct LLWork {
     hipStream_t stream = nullptr;
     DevBuf win, cost, order, queue, cls_off;
+    DevBuf cl_x, cl_part, cl_ninf, cl_flag;  // clusters: exchange slots, sums, flags + abort word
 };
 
 // Device tables of one call.
@@ -993,6 +1346,10 @@ struct LLBufs {
     int32_t* order = nullptr;
     unsigned* queue = nullptr;
     int32_t* cls_off = nullptr;
+    float* cl_x = nullptr;  // null: no clusters (items above kLLMaxStates get -inf)
+    double* cl_part = nullptr;
+    double* cl_ninf = nullptr;
+    unsigned* cl_flag = nullptr;
 };
 
 struct LLContext {
@@ -1004,6 +1361,9 @@ struct LLContext {
     int occ[4][kLLNumShapes] = {};  // resident workgroups per CU (0 = not queried)
     int occ_jp[4][kLLClasses] = {};  // the same for the jump-mode kernels
     int occ_col[kColClasses] = {};  // the same for the column kernels (cascade)
+    int nclust = 0;                 // clusters of the cluster kernel that fit co-resident (0: none)
+    int cl_occ = 0, cl_coop = 0;    // its workgroups per CU, cooperative launch support
+    int wall_khz = 0;
     int shape[4][kLLClasses];       // chosen shape per (model, class); -1 = default
     int kernel[4] = {MJP_LL_KERNEL_AUTO, MJP_LL_KERNEL_AUTO, MJP_LL_KERNEL_AUTO, MJP_LL_KERNEL_AUTO};
     LLContext() {
@@ -1053,6 +1413,26 @@ static mjp_status ll_attrs(LLContext& C, int dev) {
     MJP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_ll_order), hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)(sizeof(unsigned long long) * kLLMaxSort)));
     MJP_HIP(hipDeviceGetAttribute(&C.ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    {  // clusters: one cooperative launch, every workgroup co-resident
+        int coop = 0, occ = 0;
+        MJP_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+        // the wall-clock rate of the wait deadlines (100 MHz where not reported, as
+        // in the persistent sweep)
+        if (hipDeviceGetAttribute(&C.wall_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || C.wall_khz <= 0) {
+            (void)hipGetLastError();
+            C.wall_khz = 100000;
+        }
+        for (const void* f : {reinterpret_cast<const void*>(k_ll_cluster<MJP_MODEL_BD>),
+                              reinterpret_cast<const void*>(k_ll_cluster<MJP_MODEL_CASCADE2>)}) {
+            MJP_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)cl_lds()));
+            int nb = 0;
+            MJP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kClT, cl_lds()));
+            occ = occ == 0 ? nb : std::min(occ, nb);
+        }
+        C.cl_occ = occ;
+        C.cl_coop = coop;
+        C.nclust = (coop && occ >= 1) ? C.ncu * occ / kClG : 0;
+    }
     C.device = dev;
     C.attr_set = true;
     return MJP_OK;
@@ -1113,6 +1493,10 @@ static mjp_status ll_work(LLContext& C, hipStream_t s, int B, int n_t, LLBufs& b
             old.order.release();
             old.queue.release();
             old.cls_off.release();
+            old.cl_x.release();
+            old.cl_part.release();
+            old.cl_ninf.release();
+            old.cl_flag.release();
             C.work.pop_back();
         }
         std::unique_ptr<LLWork> nw(new (std::nothrow) LLWork());
@@ -1126,6 +1510,17 @@ static mjp_status ll_work(LLContext& C, hipStream_t s, int B, int n_t, LLBufs& b
         (st = w->order.reserve(sizeof(int32_t) * B)) || (st = w->queue.reserve(64)) ||
         (st = w->cls_off.reserve(sizeof(int32_t) * (kAllClasses + 1))))
         return st;
+    if (C.nclust > 0) {
+        const size_t nc = (size_t)C.nclust;
+        if ((st = w->cl_x.reserve(sizeof(float) * nc * 2 * kClG * 2 * kClReachMax)) ||
+            (st = w->cl_part.reserve(sizeof(double) * nc * 4 * kClG)) || (st = w->cl_ninf.reserve(sizeof(double) * nc * kClG)) ||
+            (st = w->cl_flag.reserve(sizeof(unsigned) * (nc * kClG * 32 + 32))))
+            return st;
+        bf.cl_x = w->cl_x.as<float>();
+        bf.cl_part = w->cl_part.as<double>();
+        bf.cl_ninf = w->cl_ninf.as<double>();
+        bf.cl_flag = w->cl_flag.as<unsigned>();
+    }
     bf.win = w->win.as<LLWin>();
     bf.cost = w->cost.as<float>();
     bf.order = w->order.as<int32_t>();
@@ -1140,6 +1535,7 @@ static LLArgs ll_args(const LLContext& C, int model, int B, const mjp_obs* obs, 
                       const LLBufs& bf) {
     LLArgs a{};
     a.use_col = kColEnabled && col_model(model) && C.kernel[model] == MJP_LL_KERNEL_AUTO && obs->n_obs <= kColT;
+    a.use_cluster = (model == MJP_MODEL_BD || model == MJP_MODEL_CASCADE2) && bf.cl_x && C.nclust > 0;
     a.theta = theta_d;
     a.dims = dims_d;
     a.T = bf.T;
@@ -1182,6 +1578,28 @@ static void ll_launch(const LLContext& C, const LLArgs& a, int cls, int sid, hip
     const int grid = std::max(1, std::min(a.B, std::max(C.ncu, 1) * C.occ[a.model][sid]));
     hipLaunchKernelGGL(kLLMains[a.model][sid], dim3(grid), dim3(kLLShapes[sid].T), ll_lds(sid), s, a,
                        kColClasses + cls);
+}
+
+// the items of the cluster class (above one workgroup's LDS): zero the
+// flags and the abort word, then one cooperative launch of every cluster
+static mjp_status cluster_launch(const LLContext& C, const LLArgs& a, const LLBufs& bf, hipStream_t s) {
+    if (!a.use_cluster) return MJP_OK;
+    const int nflag = C.nclust * kClG * 32 + 32;
+    hipLaunchKernelGGL(k_ll_zero_u32, dim3((nflag + 255) / 256), dim3(256), 0, s, bf.cl_flag, nflag);
+    ClArgs ca{};
+    ca.a = a;
+    ca.xbuf = bf.cl_x;
+    ca.part = bf.cl_part;
+    ca.ninf = bf.cl_ninf;
+    ca.wflag = bf.cl_flag;
+    ca.abort_word = bf.cl_flag + (size_t)C.nclust * kClG * 32;
+    ca.timeout_ticks = (uint64_t)C.wall_khz * 1000ull * 2ull;  // 2 s per wait
+    ca.nclust = C.nclust;
+    const void* fn = a.model == MJP_MODEL_BD ? reinterpret_cast<const void*>(k_ll_cluster<MJP_MODEL_BD>)
+                                             : reinterpret_cast<const void*>(k_ll_cluster<MJP_MODEL_CASCADE2>);
+    void* args[] = {&ca};
+    MJP_HIP(hipLaunchCooperativeKernel(fn, dim3(C.nclust * kClG), dim3(kClT), args, cl_lds(), s));
+    return MJP_OK;
 }
 
 // the items of every column class (nothing when the column kernel is off)
@@ -1319,6 +1737,7 @@ extern "C" mjp_status mjp_loglik(int32_t model, int32_t B, const double* theta_d
     ll_prepare(a, s);
     col_launch(C, a, s);
     for (int c = 0; c < kLLClasses; ++c) ll_launch(C, a, c, ll_effective(C, model, c, a.n_rec), s);
+    if ((st = cluster_launch(C, a, bf, s))) return st;
     MJP_HIP(hipGetLastError());
     return MJP_OK;
 }
@@ -1334,6 +1753,23 @@ extern "C" mjp_status mjp_loglik_set_kernel(int32_t model, int32_t kernel) {
     LLContext& C = ctx_for(dev);
     std::lock_guard<std::mutex> lock(C.mu);
     C.kernel[model] = kernel;
+    return MJP_OK;
+}
+
+extern "C" mjp_status mjp_loglik_cluster_config(int32_t* clusters_h, int32_t* per_cu_h, int32_t* coop_h,
+                                                int32_t* group_h, int32_t* max_states_h) {
+    clear_error();
+    int dev = 0;
+    mjp_status st = ll_device(dev);
+    if (st) return st;
+    LLContext& C = ctx_for(dev);
+    std::lock_guard<std::mutex> lock(C.mu);
+    if ((st = ll_attrs(C, dev))) return st;
+    if (clusters_h) *clusters_h = C.nclust;
+    if (per_cu_h) *per_cu_h = C.cl_occ;
+    if (coop_h) *coop_h = C.cl_coop;
+    if (group_h) *group_h = kClG;
+    if (max_states_h) *max_states_h = kClMaxStates;
     return MJP_OK;
 }
 
@@ -1454,7 +1890,8 @@ extern "C" mjp_status mjp_loglik_tune(int32_t model, int32_t B, const double* th
         return st;
     const LLArgs a = ll_args(C, model, B, obs, opts, theta_d, dims_d, loglik_d, info_d, bf);
     ll_prepare(a, s);
-    col_launch(C, a, s);  // items the column kernel takes are not tuned
+    col_launch(C, a, s);  // items the column kernel or the clusters take are not tuned
+    if ((st = cluster_launch(C, a, bf, s))) return st;
     int32_t off[kAllClasses + 1];
     MJP_HIP(hipMemcpyAsync(off, a.cls_off, sizeof(off), hipMemcpyDeviceToHost, s));
     MJP_HIP(hipStreamSynchronize(s));

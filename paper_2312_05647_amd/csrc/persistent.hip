@@ -81,29 +81,6 @@ struct PersistArgs {
     int32_t slot[kMaxTimes];
 };
 
-// Iterate accesses under either protocol: raw buffer loads and stores at a
-// 32-bit byte offset from a uniform descriptor (one offset register per
-// gather instead of a 64-bit address pair).  The descriptor's range is the
-// vector's n*4 bytes, so an access past the end reads 0 or is dropped.  COH
-// sets the device-scope cache policy (the SC1 bit of the instruction's
-// cache-policy operand on this architecture family), which is what the
-// compiler emits for an agent-scope relaxed atomic load or store.
-constexpr int kCpolSC1 = 16;
-constexpr int kRsrcWord3 = 0x00020000;  // raw 32-bit buffer, no swizzle
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t iter_rsrc(const float* p, int64_t n) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(p), 0, (int)(uint32_t)(4 * n), kRsrcWord3);
-}
-// (the b32 builtins move 32-bit integers: the float travels as its bits)
-template <bool COH>
-__device__ __forceinline__ float ld_iter(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, COH ? kCpolSC1 : 0));
-}
-template <bool COH>
-__device__ __forceinline__ void st_iter(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, COH ? kCpolSC1 : 0);
-}
-
 // Neighbour synchronisation after jump k: publish "my rows of step k are
 // written" (publishing step + relaxed store of k to my flag line), then wait
 // until every workgroup in my interval [lo, hi] has published k.  The

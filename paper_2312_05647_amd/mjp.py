@@ -130,6 +130,7 @@ _SIGS = [
     ("mjp_probe_exchange", ctypes.c_int, [_P, ctypes.c_int32, _P, _P]),
     ("mjp_loglik", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P]),
     ("mjp_loglik_set_kernel", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32]),
+    ("mjp_loglik_cluster_config", ctypes.c_int, [_P, _P, _P, _P, _P]),
     ("mjp_loglik_noalloc", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P]),
     ("mjp_loglik_noalloc_bytes", ctypes.c_int64, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     ("mjp_loglik_noalloc_capacity", ctypes.c_int64, []),
@@ -413,6 +414,12 @@ def mjp_loglik(model: int, theta, dims, obs: mjp_obs, out, opts: mjp_opts | None
 
 
 MJP_LL_KERNEL_AUTO, MJP_LL_KERNEL_CELLS = 0, 1
+
+
+def mjp_loglik_cluster_config() -> dict:
+    v = [ctypes.c_int32() for _ in range(5)]
+    _check(lib().mjp_loglik_cluster_config(*[ctypes.byref(x) for x in v]))
+    return dict(zip(("clusters", "per_cu", "cooperative", "group", "max_states"), (x.value for x in v)))
 
 
 def mjp_loglik_set_kernel(model: int, kernel: int) -> None:
