@@ -407,63 +407,82 @@ def bench_loglik(torch, mjp, reps: int = 3):
                                              for c in range(mjp.MJP_LL_CLASSES) if rep["items"][c] > 0}}}
 
 
-def bench_da(torch, mjp, chains: int = 2048, steps: int = 100, burn: int = 20, n_train: int = 16384):
-    """Delayed-acceptance vs plain Metropolis-Hastings on the cascade
-    posterior: data = 20 times 0.5..10 x 50 snapshots from rates
-    (50, 1, 0.5, 0.5), fixed grid from the data (twice the largest count or
-    the stationary mean + 8 sd).  The proposal covariance is adapted on 256
-    chains (SI scheme) and frozen at the 2.38^2/d random-walk scaling; both
-    samplers then start from the same burnt-in states of `chains` chains and
-    use the same covariance."""
+def bench_da(torch, mjp, chains: int = 256, steps: int = 60, n_train: int = 8192, pilot_chains: int = 128,
+             pilot_steps: int = 30):
+    """Delayed-acceptance vs plain Metropolis-Hastings on the posterior of
+    the cascade's four log-rates with config-2 truth (200, 1, 0.5, 0.5) on
+    the 300 x 300 grid (N = 90,000 states: every exact log-likelihood runs
+    in a cluster of workgroups): data 20 times 0.5..10 x 50 snapshots.
+    A pilot MH run (pilot_chains from independent starts near the truth,
+    the SI's small initial covariance, then one covariance estimate) gives
+    the proposal covariance (pooled covariance x 2.38^2/4) and a Gaussian
+    approximation of the posterior; both samplers then run `chains` chains
+    from the same independent draws of that Gaussian with the same
+    covariance.  The surrogate is trained on n_train exact evaluations at
+    draws from the Gaussian with 3x the pilot's standard deviations."""
     from paper_2312_05647_amd import sampler, synth
-    theta_star = np.array([50.0, 1.0, 0.5, 0.5])
+    theta_star = np.array([200.0, 1.0, 0.5, 0.5])
     T = synth.even_times(20, 0.5)
     data = synth.gillespie_cascade2(theta_star, T, 50, seed=synth.SEED_DATA)
     recs = synth.cascade_records(data)
-    dims = synth.grid_dims(theta_star[None, :], (int(data[:, 1].max()), int(data[:, 2].max())))[0]
+    dims = (300, 300)
     post = sampler.Posterior(mjp.MJP_MODEL_CASCADE2, T, recs, dims)
     gen = torch.Generator(device="cuda").manual_seed(synth.SEED_MCMC)
-    psi0 = torch.log(torch.as_tensor(np.tile(theta_star, (256, 1)), device="cuda"))
+    g = synth.rng(synth.SEED_MCMC)
     t0 = time.perf_counter()
-    Z, psi = sampler.adapt_covariance(post, psi0, gen, rounds=4, steps=30, final_scale="optimal")
-    psi = psi.repeat(chains // 256, 1)
-    _, _ = sampler.run_mh(post, psi, Z, 1, gen)  # warm the batch size
-    smp, _ = sampler.run_mh(post, psi, Z, burn, gen)
-    psi = torch.as_tensor(smp[-1], device="cuda")
-    t_adapt = time.perf_counter() - t0
-    pilot_m = psi.mean(0).cpu().numpy()
-    cov = np.cov(smp.reshape(-1, 4).T)
-    g = synth.rng(synth.SEED_MLP)
-    pts = g.multivariate_normal(pilot_m, 9.0 * cov, size=n_train)
+    psi0 = torch.as_tensor(np.log(theta_star) + 0.01 * g.standard_normal((pilot_chains, 4)), device="cuda")
+    Z0 = 2e-5 * np.eye(4)
+    smp, _ = sampler.run_mh(post, psi0, Z0, pilot_steps, gen, progress=lambda h: log(f"[bench] DA pilot 1: {h}"))
+    half = pilot_steps // 2
+    smp2, _ = sampler.run_mh(post, torch.as_tensor(smp[-1], device="cuda"),
+                             2.38 ** 2 / 4 * np.cov(smp[half:].reshape(-1, 4).T), pilot_steps, gen,
+                             progress=lambda h: log(f"[bench] DA pilot 2: {h}"))
+    pilot = smp2[half:].reshape(-1, 4)
+    pm, pc = pilot.mean(0), np.cov(pilot.T)
+    Z = 2.38 ** 2 / 4 * pc
+    t_pilot = time.perf_counter() - t0
+    starts = torch.as_tensor(g.multivariate_normal(pm, pc, size=chains), device="cuda")
+    pts = g.multivariate_normal(pm, 9.0 * pc, size=n_train)
     t0 = time.perf_counter()
-    ll = torch.cat([post.loglik(torch.as_tensor(pts[i:i + 4096], device="cuda"))
-                    for i in range(0, n_train, 4096)]).cpu().numpy()
+    parts = []
+    for i in range(0, n_train, 4096):
+        parts.append(post.loglik(torch.as_tensor(pts[i:i + 4096], device="cuda")).cpu())
+        log(f"[bench] DA leg: {i + len(parts[-1])}/{n_train} training evaluations, {time.perf_counter() - t0:.1f} s")
+    ll = torch.cat(parts).numpy()
     t_data = time.perf_counter() - t0
     ok = np.isfinite(ll)
     screen, losses, t_train = sampler.train_surrogate(pts[ok], ll[ok], epochs=60, batch=1024, seed=synth.SEED_MLP)
     res = {}
     try:
-        for name, run in (("plain_mh", lambda: sampler.run_mh(post, psi, Z, steps, gen)),
-                          ("delayed_acceptance", lambda: sampler.run_da(post, screen, psi, Z, steps, gen))):
+        def prog(name):
+            return lambda h: log(f"[bench] DA leg {name}: step {h}/{steps}")
+        for name, run in (("plain_mh", lambda: sampler.run_mh(post, starts, Z, steps, gen, progress=prog("mh"))),
+                          ("delayed_acceptance",
+                           lambda: sampler.run_da(post, screen, starts, Z, steps, gen, progress=prog("da")))):
             smp, st = run()
             e = sampler.ess(smp)
             flat = smp.reshape(-1, smp.shape[2])
+            var = flat.var(0)
             res[name] = {"ess_min": float(e.min()), "ess_per_s": float(e.min() / st.seconds),
                          "seconds": st.seconds, "exact_evals": st.exact_evals,
                          "accept_rate": st.accepted / (steps * chains),
                          "stage1_accept_rate": (st.stage1_accepted / (steps * chains)) if name != "plain_mh" else None,
-                         "mean_log_theta": flat.mean(0).tolist(), "var_log_theta": flat.var(0).tolist(),
-                         "mcse_mean": np.sqrt(flat.var(0) / e).tolist()}
-            log(f"[bench] {name}: ESS/s {res[name]['ess_per_s']:.1f}, {st.seconds:.2f} s, exact {st.exact_evals}")
+                         "mean_log_theta": flat.mean(0).tolist(), "var_log_theta": var.tolist(),
+                         "mcse_mean": np.sqrt(var / e).tolist(),
+                         # the variance estimate's standard error: var sqrt(2 / ESS) (Gaussian fourth moment)
+                         "mcse_var": (var * np.sqrt(2.0 / e)).tolist()}
+            log(f"[bench] DA leg {name}: ESS/s {res[name]['ess_per_s']:.1f}, {st.seconds:.2f} s, exact {st.exact_evals}")
     finally:
         mjp.mjp_surrogate_destroy(screen.h)
     mh, da = res["plain_mh"], res["delayed_acceptance"]
-    z = np.abs(np.array(mh["mean_log_theta"]) - np.array(da["mean_log_theta"])) / np.hypot(mh["mcse_mean"], da["mcse_mean"])
-    return {"workload": f"cascade posterior, grid {int(dims[0])}x{int(dims[1])}, {len(recs)} records, "
-                        f"{chains} chains x {steps} steps per sampler, surrogate 4-256-256-256-1 on {int(ok.sum())} exact evaluations",
+    zm = np.abs(np.array(mh["mean_log_theta"]) - np.array(da["mean_log_theta"])) / np.hypot(mh["mcse_mean"], da["mcse_mean"])
+    zv = np.abs(np.array(mh["var_log_theta"]) - np.array(da["var_log_theta"])) / np.hypot(mh["mcse_var"], da["mcse_var"])
+    return {"workload": f"cascade posterior, truth (200, 1, 0.5, 0.5), grid 300x300 (N=90,000), {len(recs)} records, "
+                        f"{chains} chains x {steps} steps per sampler from independent starts, surrogate "
+                        f"4-256-256-256-1 on {int(ok.sum())} exact evaluations",
             "ess_per_s_ratio_da_over_mh": da["ess_per_s"] / mh["ess_per_s"],
-            "mean_diff_in_mcse_max": float(z.max()),
-            "adapt_s": t_adapt, "train_data_s": t_data, "train_s": t_train,
+            "mean_diff_in_mcse_max": float(zm.max()), "var_diff_in_mcse_max": float(zv.max()),
+            "pilot_s": t_pilot, "train_data_s": t_data, "train_s": t_train,
             "train_loss_first_last": [float(losses[0]), float(losses[-1])],
             "ess_per_s_da_incl_training": da["ess_min"] / (da["seconds"] + t_data + t_train),
             **res}
@@ -480,6 +499,9 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the secondary measurements")
     ap.add_argument("--part", choices=["all", "loglik", "da", "small", "krylov", "rk4", "jmjp", "surrogate"], default="all",
                     help="run only one secondary leg (for profiling)")
+    ap.add_argument("--da-chains", type=int, default=256)
+    ap.add_argument("--da-steps", type=int, default=60)
+    ap.add_argument("--da-train", type=int, default=8192)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the byte counters)")
     args = ap.parse_args()
@@ -502,7 +524,7 @@ def main():
         print(json.dumps({"loglik_batch": bench_loglik(torch, mjp)}))
         return
     if args.part == "da":
-        print(json.dumps({"da_mcmc": bench_da(torch, mjp)}))
+        print(json.dumps({"da_mcmc": bench_da(torch, mjp, args.da_chains, args.da_steps, args.da_train)}))
         return
     if args.part == "small":
         print(json.dumps({"small_configs": bench_small(torch, mjp)}))
@@ -653,7 +675,7 @@ def main():
             orc.build(force=False)
         result["small_configs"] = bench_small(torch, mjp, orc=orc)
         result["loglik_batch"] = bench_loglik(torch, mjp)
-        result["da_mcmc"] = bench_da(torch, mjp)
+        result["da_mcmc"] = bench_da(torch, mjp, args.da_chains, args.da_steps, args.da_train)
         result["jmjp_method2"] = bench_jmjp(torch, mjp)
         result["surrogate_training"] = bench_surrogate(torch, mjp)
 

@@ -132,8 +132,9 @@ def _draws(gen, steps, C, d):
     return z, u
 
 
-def run_mh(post: Posterior, psi0, Z, steps: int, gen, draws=None):
-    """Plain Metropolis-Hastings; returns (samples [steps, C, d] on the host, stats)."""
+def run_mh(post: Posterior, psi0, Z, steps: int, gen, draws=None, progress=None):
+    """Plain Metropolis-Hastings; returns (samples [steps, C, d] on the host, stats).
+    progress, if given, is called with the step number after every 10th step."""
     import torch
     psi = psi0.clone()
     C, d = psi.shape
@@ -153,15 +154,18 @@ def run_mh(post: Posterior, psi0, Z, steps: int, gen, draws=None):
         lp = torch.where(acc, lpp, lp)
         out[h] = psi
         acc_total += int(acc.sum().item())
+        if progress is not None and (h + 1) % 10 == 0:
+            progress(h + 1)
     torch.cuda.synchronize()
     st = ChainStats(steps=steps, accepted=acc_total, exact_evals=post.n_exact - n0,
                     seconds=time.perf_counter() - t0)
     return out.cpu().numpy(), st
 
 
-def run_da(post: Posterior, screen, psi0, Z, steps: int, gen, draws=None):
+def run_da(post: Posterior, screen, psi0, Z, steps: int, gen, draws=None, progress=None):
     """Delayed-acceptance Metropolis-Hastings with `screen` (a callable
-    returning a screened log-posterior) as the first stage."""
+    returning a screened log-posterior) as the first stage.  progress as in
+    run_mh."""
     import torch
     psi = psi0.clone()
     C, d = psi.shape
@@ -190,6 +194,8 @@ def run_da(post: Posterior, screen, psi0, Z, steps: int, gen, draws=None):
             sc[take] = scp[take]
             acc_total += int(take.numel())
         out[h] = psi
+        if progress is not None and (h + 1) % 10 == 0:
+            progress(h + 1)
     torch.cuda.synchronize()
     st = ChainStats(steps=steps, accepted=acc_total, stage1_accepted=s1_total,
                     exact_evals=post.n_exact - n0, screen_evals=scr, seconds=time.perf_counter() - t0)
