@@ -119,7 +119,10 @@ enum { MJP_FLAG_NAN = 1,           /* a NaN/Inf appeared in rho(0) or in the ite
        MJP_FLAG_NEG = 2,           /* rho(0) had a negative entry */
        MJP_FLAG_UNDERFLOW_OBS = 4, /* an observed state had probability <= 0 in FP32 */
        MJP_FLAG_OUT_OF_GRID = 8,   /* an observation lies outside the state space */
-       MJP_FLAG_K_LIMIT = 16 };    /* (log-likelihood) an item needed K > k_cap; its value is -inf */
+       MJP_FLAG_K_LIMIT = 16,      /* (log-likelihood) an item needed K > k_cap; its value is -inf */
+       MJP_FLAG_SUBNORMAL_OBS = 32 };/* (log-likelihood) an observed state's FP32 probability lay below
+                                        FP32's normal range (1.18e-38): that log term has fewer than
+                                        24 significant bits */
 
 typedef struct {
     double  omega;          /* Omega */
@@ -132,13 +135,14 @@ typedef struct {
     int32_t K;              /* number of products rho <- rho B */
     int32_t L;              /* first accumulated jump index */
     int32_t flags;          /* MJP_FLAG_* */
-    int32_t path;           /* mjp_expv: the sweep that ran (MJP_PATH_*); 0 elsewhere */
+    int32_t path;           /* mjp_expv(_batched): the sweep that ran (MJP_PATH_*); 0 elsewhere */
 } mjp_info;
 
 enum { MJP_PATH_STEPWISE = 1,            /* one launch per jump */
        MJP_PATH_PERSISTENT = 2,          /* one launch, one jump per synchronisation */
        MJP_PATH_PERSISTENT_FENCED = 3,   /* the same, fenced protocol */
-       MJP_PATH_PERSISTENT_TWOJUMP = 4 };/* one launch, two jumps per synchronisation */
+       MJP_PATH_PERSISTENT_TWOJUMP = 4,  /* one launch, two jumps per synchronisation */
+       MJP_PATH_BATCHED_ITEM = 5 };      /* mjp_expv_batched: one workgroup ran the item */
 
 /* ------------------------------------------------------------ operators */
 
@@ -237,10 +241,23 @@ int32_t mjp_plan_n(const mjp_plan* p);
 mjp_status mjp_expv(mjp_plan* p, const float* rho0_d, int32_t n_t, const double* t_h,
                     float* out_d, mjp_info* info_h, mjp_stream_t stream);
 
-/* B independent solves, item b: plans[b], rho0_d[b], n_t[b] times t_h[b],
- * outputs out_d[b] ([n_t[b] x N_b]).  info_h, if not NULL, holds
- * sum_b n_t[b] entries in item order and makes the call synchronous.
- * Plans may repeat (the same operator with several initial vectors). */
+/* B independent solves of Algorithm 2, item b: plans[b], rho0_d[b], n_t[b]
+ * times t_h[b], outputs out_d[b] ([n_t[b] x N_b], the layout of mjp_expv).
+ * info_h, if not NULL, holds sum_b n_t[b] entries in item order (path
+ * MJP_PATH_BATCHED_ITEM for items of the batched sweep) and makes the call
+ * synchronous, with mjp_expv's error rules.  Plans may repeat (the same
+ * operator with several initial vectors).
+ * Items whose vector one workgroup holds (N up to 512 R rows, R = 1..8 by
+ * the row width; at most 48 times and 4 windows open at once) on the first
+ * item's device, with opts.variant AUTO, PERSISTENT or PERSISTENT_ONEJUMP,
+ * run in one launch per operator class (kind, rows per thread, entries per
+ * row) after one launch that forms every item's Poisson weights: each
+ * workgroup takes every grid-th item of the longest-first order and sweeps it with its
+ * vector in LDS.  Such an item's output equals its own mjp_expv call's bit
+ * for bit.  Every other item runs its own sweep (mjp_expv), in item order.
+ * The batched sweep's workspace belongs to the library, one per (device,
+ * stream); concurrent calls on one stream from several host threads are
+ * not allowed. */
 mjp_status mjp_expv_batched(int32_t B, mjp_plan* const* plans, const float* const* rho0_d,
                             const int32_t* n_t, const double* const* t_h, float* const* out_d,
                             mjp_info* info_h, mjp_stream_t stream);
@@ -343,11 +360,9 @@ int64_t mjp_loglik_noalloc_capacity(void);
  *   MJP_LL_KERNEL_AUTO  (default) cascade items whose grid fits the column
  *       kernel -- S1 <= 992 columns, the S2 rows cut into at most 992 / S1
  *       segments of at most 64 rows, a column-major LDS mirror of at most
- *       40,256 floats -- would run in it (each lane keeps one column segment
- *       in registers; left and right neighbours by cross-lane moves).  That
- *       kernel is switched off in this build (its first GPU run did not
- *       finish and the cause has not been found), so AUTO runs every item in
- *       the cell kernel;
+ *       40,256 floats -- run in it (each lane keeps one column segment in
+ *       registers; left and right neighbours by cross-lane moves); every
+ *       other item in the cell kernel;
  *   MJP_LL_KERNEL_CELLS every item in the cell kernel, whose launch shapes
  *       mjp_loglik_set_shapes and mjp_loglik_tune choose.
  * The other models always use the cell kernel. */

@@ -13,6 +13,11 @@ import os
 import subprocess
 import sys
 
+try:
+    from . import asmcheck
+except ImportError:  # run as a script
+    import asmcheck
+
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
@@ -30,11 +35,25 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=o
 
 
 def _compile(src: str) -> str:
+    """Compiles one source, keeping the device assembly the object is
+    assembled from, and refuses kernels with a loop that holds a barrier
+    and exits lane by lane (asmcheck)."""
     obj = os.path.join(OBJ, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+    base = os.path.splitext(os.path.basename(src))[0]
+    cmd = [HIPCC, *FLAGS, "-save-temps=obj", "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}\n{r.stderr}")
+    temps = [os.path.join(OBJ, f) for f in os.listdir(OBJ)
+             if f.startswith(base + "-hip-") or f.startswith(base + "-host-") or f.startswith(base + ".hip-hip-")]
+    try:
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}\n{r.stderr}")
+        asm = os.path.join(OBJ, f"{base}-hip-amdgcn-amd-amdhsa-gfx950.s")
+        bad = asmcheck.check_file(asm)
+        if bad:
+            raise RuntimeError(f"{src}: loops holding a barrier that exit lane by lane: {bad}")
+    finally:
+        for f in temps:
+            os.remove(f)
     return obj
 
 

@@ -15,6 +15,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <memory>
+#include <mutex>
 #include <numeric>
 #include <vector>
 
@@ -127,11 +129,7 @@ __global__ void k_weights(AllTimes at, double* __restrict__ wtab) {
     const TimeParam tp = at.tp[j];
     const int cnt = tp.K - tp.L + 1;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x) {
-        const int k = tp.L + i;
-        double w;
-        if (tp.W > 0.0) w = exp(-tp.W + (double)k * log(tp.W) - lgamma((double)k + 1.0));
-        else w = (k == 0) ? 1.0 : 0.0;
-        wtab[tp.woff + i] = w;
+        wtab[tp.woff + i] = poisson_weight(tp.W, tp.L + i);
     }
 }
 
@@ -297,17 +295,13 @@ struct SweepTime {
     int32_t out;  // caller's index
 };
 
-// One sweep over up to kMaxTimes times sorted by t.
-static mjp_status run_sweep(mjp_plan* p, const float* rho0, const std::vector<SweepTime>& times, float* out,
-                            hipStream_t st, std::vector<double>* out_mass) {
-    const int64_t n = p->n;
+// Parameters of the times (sorted by t) in at; returns the number of
+// Poisson weights of all their windows.
+static int64_t build_times(const mjp_plan* p, const std::vector<SweepTime>& times, AllTimes& at) {
     const int nt = (int)times.size();
-    const unsigned nblk = (unsigned)((n + kBlock - 1) / kBlock);
-    const unsigned nblk8 = (nblk + 7u) & ~7u;  // step launches: a multiple of 8 blocks (see step_block)
-    AllTimes at{};
+    at = AllTimes{};
     at.n = nt;
     int64_t wtotal = 0;
-    int32_t Kmax = 0;
     for (int j = 0; j < nt; ++j) {
         const Window& w = times[j].win;
         TimeParam& tp = at.tp[j];
@@ -322,16 +316,51 @@ static mjp_status run_sweep(mjp_plan* p, const float* rho0, const std::vector<Sw
         else wK = 1.0;
         tp.lastw = wK + (p->opts.lump ? w.residual : 0.0);
         wtotal += w.K - w.L + 1;
-        Kmax = std::max(Kmax, tp.K);
     }
-    // largest number of windows open at the same jump = compensation rows needed
+    return wtotal;
+}
+
+// Largest number of windows open at the same jump (= compensation rows or
+// register slots needed).
+static int max_open_windows(const AllTimes& at) {
     int max_open = 0;
-    for (int j = 0; j < nt; ++j) {
+    for (int j = 0; j < at.n; ++j) {
         int open = 0;
-        for (int i = 0; i < nt; ++i)
+        for (int i = 0; i < at.n; ++i)
             if (at.tp[i].L <= at.tp[j].L && at.tp[j].L <= at.tp[i].K) ++open;
         max_open = std::max(max_open, open);
     }
+    return max_open;
+}
+
+// Colours the windows (sorted by start) onto register slots: a slot is
+// reused once its previous window has closed.
+static std::vector<int> colour_slots(const AllTimes& at) {
+    std::vector<int> slot(at.n, -1);
+    std::vector<int32_t> busy_until;  // last jump of each slot's current window
+    for (int j = 0; j < at.n; ++j) {
+        int q = -1;
+        for (size_t i = 0; i < busy_until.size(); ++i)
+            if (busy_until[i] < at.tp[j].L) { q = (int)i; break; }
+        if (q < 0) { q = (int)busy_until.size(); busy_until.push_back(0); }
+        busy_until[(size_t)q] = at.tp[j].K;
+        slot[(size_t)j] = q;
+    }
+    return slot;
+}
+
+// One sweep over up to kMaxTimes times sorted by t.
+static mjp_status run_sweep(mjp_plan* p, const float* rho0, const std::vector<SweepTime>& times, float* out,
+                            hipStream_t st, std::vector<double>* out_mass) {
+    const int64_t n = p->n;
+    const int nt = (int)times.size();
+    const unsigned nblk = (unsigned)((n + kBlock - 1) / kBlock);
+    const unsigned nblk8 = (nblk + 7u) & ~7u;  // step launches: a multiple of 8 blocks (see step_block)
+    AllTimes at;
+    const int64_t wtotal = build_times(p, times, at);
+    int32_t Kmax = 0;
+    for (int j = 0; j < nt; ++j) Kmax = std::max(Kmax, at.tp[j].K);
+    const int max_open = max_open_windows(at);
     mjp_status s;
     if ((s = p->rho[0].reserve(sizeof(float) * n)) || (s = p->rho[1].reserve(sizeof(float) * n)) ||
         (s = p->comp.reserve(sizeof(float) * n * (size_t)std::max(max_open, 1))) ||
@@ -360,17 +389,7 @@ static mjp_status run_sweep(mjp_plan* p, const float* rho0, const std::vector<Sw
     bool fits = (var == MJP_VARIANT_AUTO || var == MJP_VARIANT_PERSISTENT) && persistent2_fits(p, max_open, cfg);
     if (!fits && var != MJP_VARIANT_STEPWISE) fits = persistent_fits(p, max_open, coh, cfg);
     if (fits) {
-        // colour the windows (sorted by start) onto the register slots
-        std::vector<int> slot(nt, -1);
-        std::vector<int32_t> busy_until;  // last jump of each slot's current window
-        for (int j = 0; j < nt; ++j) {
-            int q = -1;
-            for (size_t i = 0; i < busy_until.size(); ++i)
-                if (busy_until[i] < at.tp[j].L) { q = (int)i; break; }
-            if (q < 0) { q = (int)busy_until.size(); busy_until.push_back(0); }
-            busy_until[(size_t)q] = at.tp[j].K;
-            slot[(size_t)j] = q;
-        }
+        const std::vector<int> slot = colour_slots(at);
         p->last_path = cfg.jumps == 2 ? MJP_PATH_PERSISTENT_TWOJUMP
                                       : (coh ? MJP_PATH_PERSISTENT : MJP_PATH_PERSISTENT_FENCED);
         if ((s = launch_persistent(p, cfg, rho0, at, slot, out, st))) return s;
@@ -483,6 +502,60 @@ static mjp_status run_sweep(mjp_plan* p, const float* rho0, const std::vector<Sw
     return MJP_OK;
 }
 
+// The times' windows (checked against k_cap), sorted by t; out = caller's index.
+static mjp_status prepare_times(const mjp_plan* p, int32_t n_t, const double* t_h, std::vector<SweepTime>& all) {
+    all.clear();
+    all.reserve(n_t);
+    for (int32_t j = 0; j < n_t; ++j) {
+        const double t = t_h[j];
+        MJP_CHECK(std::isfinite(t) && t >= 0.0, MJP_E_INVALID_ARG, "t[%d] = %g must be finite and >= 0", j, t);
+        SweepTime s;
+        s.t = t;
+        s.out = j;
+        s.win = poisson_window(p->omega * t, p->opts);  // W = 0 gives K = L = 0
+        MJP_CHECK(s.win.K <= p->opts.k_cap, MJP_E_K_LIMIT, "t[%d] needs K = %lld > k_cap = %lld", j,
+                  (long long)s.win.K, (long long)p->opts.k_cap);
+        MJP_CHECK(s.win.K < INT32_MAX / 2, MJP_E_K_LIMIT, "K too large");
+        all.push_back(s);
+    }
+    std::stable_sort(all.begin(), all.end(), [](const SweepTime& a, const SweepTime& b) { return a.t < b.t; });
+    return MJP_OK;
+}
+
+// Workspaces of the batched sweep per (device, stream), most recently used
+// first; the least recently used is freed beyond kItemStreams streams.
+constexpr int kItemDevices = 64;
+constexpr int kItemStreams = 16;
+struct ItemCtx {
+    std::mutex mu;
+    std::vector<std::unique_ptr<ItemWork>> work;
+};
+
+static ItemCtx& item_ctx(int dev) {
+    static ItemCtx ctxs[kItemDevices];
+    return ctxs[dev];
+}
+
+static mjp_status item_work(ItemCtx& C, hipStream_t st, ItemWork*& out) {
+    for (size_t i = 0; i < C.work.size(); ++i)
+        if (C.work[i]->stream == st) {
+            if (i > 0) std::rotate(C.work.begin(), C.work.begin() + i, C.work.begin() + i + 1);
+            out = C.work[0].get();
+            return MJP_OK;
+        }
+    if ((int)C.work.size() >= kItemStreams) {
+        MJP_HIP(hipDeviceSynchronize());
+        C.work.back()->release();
+        C.work.pop_back();
+    }
+    std::unique_ptr<ItemWork> w(new (std::nothrow) ItemWork());
+    MJP_CHECK(w, MJP_E_DEVICE, "out of host memory");
+    w->stream = st;
+    C.work.insert(C.work.begin(), std::move(w));
+    out = C.work[0].get();
+    return MJP_OK;
+}
+
 }  // namespace mjp
 
 using namespace mjp;
@@ -501,20 +574,7 @@ extern "C" mjp_status mjp_expv(mjp_plan* p, const float* rho0_d, int32_t n_t, co
                   "out_d overlaps rho0_d");
     }
     std::vector<SweepTime> all;
-    all.reserve(n_t);
-    for (int32_t j = 0; j < n_t; ++j) {
-        const double t = t_h[j];
-        MJP_CHECK(std::isfinite(t) && t >= 0.0, MJP_E_INVALID_ARG, "t[%d] = %g must be finite and >= 0", j, t);
-        SweepTime s;
-        s.t = t;
-        s.out = j;
-        s.win = poisson_window(p->omega * t, p->opts);  // W = 0 gives K = L = 0
-        MJP_CHECK(s.win.K <= p->opts.k_cap, MJP_E_K_LIMIT, "t[%d] needs K = %lld > k_cap = %lld", j,
-                  (long long)s.win.K, (long long)p->opts.k_cap);
-        MJP_CHECK(s.win.K < INT32_MAX / 2, MJP_E_K_LIMIT, "K too large");
-        all.push_back(s);
-    }
-    std::stable_sort(all.begin(), all.end(), [](const SweepTime& a, const SweepTime& b) { return a.t < b.t; });
+    if (mjp_status s = prepare_times(p, n_t, t_h, all)) return s;
     DeviceGuard g(p->device);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     std::vector<double> mass;
@@ -568,17 +628,95 @@ extern "C" mjp_status mjp_expv_batched(int32_t B, mjp_plan* const* plans, const 
     MJP_CHECK(B >= 0, MJP_E_INVALID_ARG, "B must be >= 0");
     if (B == 0) return MJP_OK;
     MJP_CHECK(plans && rho0_d && n_t && t_h && out_d, MJP_E_INVALID_ARG, "null array");
+    std::vector<int64_t> ioff((size_t)B + 1, 0);  // first mjp_info entry of each item
     for (int32_t b = 0; b < B; ++b) {
         MJP_CHECK(plans[b] && rho0_d[b] && out_d[b] && t_h[b] && n_t[b] >= 1, MJP_E_INVALID_ARG,
                   "item %d: null or empty argument", b);
         for (int32_t j = 0; j < n_t[b]; ++j)
             MJP_CHECK(std::isfinite(t_h[b][j]) && t_h[b][j] >= 0.0, MJP_E_INVALID_ARG, "item %d: bad time", b);
+        const int64_t n = plans[b]->n;
+        const char* x = reinterpret_cast<const char*>(rho0_d[b]);
+        const char* y = reinterpret_cast<const char*>(out_d[b]);
+        MJP_CHECK(x + sizeof(float) * n <= y || y + sizeof(float) * n * n_t[b] <= x, MJP_E_INVALID_ARG,
+                  "item %d: out_d overlaps rho0_d", b);
+        ioff[(size_t)b + 1] = ioff[(size_t)b] + n_t[b];
     }
-    int64_t off = 0;
+    // Items that one workgroup holds (on the first item's device, with the
+    // device-scope persistent sweep allowed) go through the batched sweep;
+    // the others through their own sweep, one after another.
+    const int dev = plans[0]->device;
+    std::vector<ItemSweep> items;
+    std::vector<int32_t> item_of, single;
+    std::vector<std::vector<SweepTime>> times((size_t)B);
     for (int32_t b = 0; b < B; ++b) {
-        mjp_status s = mjp_expv(plans[b], rho0_d[b], n_t[b], t_h[b], out_d[b], info_h ? info_h + off : nullptr, stream);
+        const mjp_plan* p = plans[b];
+        if (mjp_status s = prepare_times(p, n_t[b], t_h[b], times[(size_t)b])) return s;
+        const int var = p->opts.variant;
+        bool ok = p->device == dev && n_t[b] <= kMaxTimes &&
+                  (var == MJP_VARIANT_AUTO || var == MJP_VARIANT_PERSISTENT || var == MJP_VARIANT_PERSISTENT_ONEJUMP);
+        if (ok) {
+            ItemSweep it;
+            it.p = p;
+            it.rho0 = rho0_d[b];
+            it.out = out_d[b];
+            it.wtotal = build_times(p, times[(size_t)b], it.at);
+            ok = item_fits(p, max_open_windows(it.at), it.R, it.W);
+            if (ok) {
+                const std::vector<int> slot = colour_slots(it.at);
+                for (int j = 0; j < it.at.n; ++j) it.slot[j] = slot[(size_t)j];
+                items.push_back(it);
+                item_of.push_back(b);
+            }
+        }
+        if (!ok) single.push_back(b);
+    }
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (!items.empty()) {
+        MJP_CHECK(dev >= 0 && dev < kItemDevices, MJP_E_UNSUPPORTED, "device %d beyond the supported count", dev);
+        DeviceGuard g(dev);
+        ItemCtx& C = item_ctx(dev);
+        std::lock_guard<std::mutex> lock(C.mu);
+        ItemWork* ws = nullptr;
+        std::vector<int64_t> roff;
+        mjp_status s;
+        if ((s = item_work(C, st, ws)) || (s = launch_items(items, info_h != nullptr, *ws, st, roff))) return s;
+        if (info_h) {
+            const size_t bytes = ws->info.bytes;
+            std::vector<double> rep(bytes / sizeof(double));
+            MJP_HIP(hipMemcpyAsync(rep.data(), ws->info.ptr, bytes, hipMemcpyDeviceToHost, st));
+            MJP_HIP(hipStreamSynchronize(st));
+            unsigned bad = 0;
+            for (size_t i = 0; i < items.size(); ++i) {
+                const int32_t b = item_of[i];
+                const mjp_plan* p = plans[b];
+                const double* r = rep.data() + roff[i];
+                unsigned fl = 0;
+                std::memcpy(&fl, r, sizeof fl);
+                bad |= fl;
+                for (const SweepTime& tt : times[(size_t)b]) {
+                    mjp_info& inf = info_h[ioff[(size_t)b] + tt.out];
+                    std::memset(&inf, 0, sizeof inf);
+                    inf.omega = p->omega;
+                    inf.W = tt.win.W;
+                    inf.eps_left = tt.win.eps_left;
+                    inf.eps_right = tt.win.eps_right;
+                    inf.residual = tt.win.residual;
+                    inf.mass_in = r[1];
+                    inf.mass_out = r[6 + tt.out];
+                    inf.K = (int32_t)tt.win.K;
+                    inf.L = (int32_t)tt.win.L;
+                    inf.flags = (int32_t)fl;
+                    inf.path = MJP_PATH_BATCHED_ITEM;
+                }
+            }
+            if (bad & (MJP_FLAG_NAN | MJP_FLAG_NEG))
+                return fail(MJP_E_NUMERIC, "numeric flags 0x%x (NaN/Inf or negative entry)", bad);
+        }
+    }
+    for (int32_t b : single) {
+        mjp_status s = mjp_expv(plans[b], rho0_d[b], n_t[b], t_h[b], out_d[b],
+                                info_h ? info_h + ioff[(size_t)b] : nullptr, stream);
         if (s) return s;
-        off += n_t[b];
     }
     return MJP_OK;
 }

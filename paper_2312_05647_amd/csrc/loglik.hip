@@ -25,6 +25,7 @@
 //               the per-time weights are formed in FP64 log space by one
 //               thread per time.  The final sum of count * log p is FP64.
 #include <algorithm>
+#include <cfloat>
 #include <array>
 #include <cmath>
 #include <cstring>
@@ -62,10 +63,10 @@ static_assert(kLLNumShapes <= MJP_LL_MAX_SHAPES, "shape table larger than the re
 constexpr int kLLDefaultShape[kLLClasses] = {8, 5, 2, 0};  // T = 1024, tightest C
 constexpr int ll_cap(int T, int C) { return T * C < kLLMaxStates ? T * C : kLLMaxStates; }
 
-// Column kernel (cascade items; k_ll_col below) -- SWITCHED OFF: its first
-// GPU run did not finish (a test call never returned) and no cause has been
-// found in its code, so no call launches it (kColEnabled); it stays here,
-// with its tests skipped, until a cause is shown.  1024
+// Column kernel (cascade items; k_ll_col below).  Its item loop once
+// popped the queue under "if (tid == 0)", which the compiler folded into
+// the loop's back edge so that the workgroup repeated an item for ever (see
+// queue_pop); kColEnabled switches it off again if needed.  1024
 // threads, 62 real lanes per wave (lanes 0 and 63 are ghost lanes), so 992
 // column segments per workgroup; an item's class is the register template C
 // that holds its segment length.  Queue and class-offset entries: the
@@ -75,7 +76,7 @@ constexpr int kColReal = 62;
 constexpr int kColLanes = kColReal * (kColT / 64);
 constexpr int kColClasses = 8;
 constexpr int kColCs[kColClasses] = {8, 16, 24, 32, 40, 48, 56, 64};
-constexpr bool kColEnabled = false;
+constexpr bool kColEnabled = true;
 
 // Items above one workgroup's LDS (cascade and birth-death, S1*S2 >
 // kLLMaxStates) run in clusters of kClG workgroups (k_ll_cluster below):
@@ -449,6 +450,24 @@ __device__ __forceinline__ float ll_cell(const float* rho, int m, int i1, int i2
 // JUMP: the J-MJP state probabilities (Method #2's algorithm): no weights;
 // observation i records log rho_{k_i} at its state when the sweep reaches its
 // own jump count k_i (one window per item, n_t = 1).
+// Next slot of a work queue for the whole workgroup, with no branch: every
+// thread adds (tid == 0) to the counter and each wave stores its first
+// lane's old value in its own LDS word; wave 0's word is thread 0's slot.
+// A pop written as "if (tid == 0) slot = atomicAdd(...)" at the top of an
+// item loop lets the compiler fold that loop-invariant branch into the
+// loop's back edge: the loop becomes a nest in which thread 0 alone goes
+// round the pop while the other lanes of wave 0 go straight back to the
+// barrier, so the workgroup passes the barrier without the pop and repeats
+// its last item for ever.
+__device__ __forceinline__ int queue_pop(unsigned* q, int* wslot) {
+    const unsigned v = atomicAdd(q, threadIdx.x == 0 ? 1u : 0u);
+    wslot[threadIdx.x >> 6] = (int)__builtin_amdgcn_readfirstlane(v);
+    __syncthreads();
+    const int r = __builtin_amdgcn_readfirstlane(wslot[0]);
+    __syncthreads();
+    return r;
+}
+
 template <int MODEL, int T, int C, bool JUMP = false>
 __global__ __launch_bounds__(T) void k_ll_main(LLArgs a, int cls) {
     constexpr int CAP = ll_cap(T, C);  // states this shape holds (a multiple of 2)
@@ -457,16 +476,13 @@ __global__ __launch_bounds__(T) void k_ll_main(LLArgs a, int cls) {
     double* wbuf = reinterpret_cast<double*>(lds + sizeof(float) * CAP);  // [2][kLLMaxTimes]
     double* scratch = wbuf + 2 * kLLMaxTimes;                                      // [16]
     LLWin* win = reinterpret_cast<LLWin*>(scratch + 16);                           // [kLLMaxTimes]
-    __shared__ int item_sh;
+    __shared__ int pop_sh[T / 64];
     __shared__ unsigned flag_sh;
     const int tid = threadIdx.x;
 
     const int first = a.cls_off[cls], last = a.cls_off[cls + 1];
     while (true) {
-        if (tid == 0) item_sh = first + (int)atomicAdd(a.queue + cls, 1u);
-        __syncthreads();
-        const int slot = item_sh;
-        __syncthreads();
+        const int slot = first + queue_pop(a.queue + cls, pop_sh);
         if (slot >= last) break;
         const int b = a.order[slot];
         const double* th = a.theta + ll_stride(MODEL) * (int64_t)b;
@@ -603,6 +619,7 @@ __global__ __launch_bounds__(T) void k_ll_main(LLArgs a, int cls) {
                     if (rm[u] < 0 || rt[u] != k) continue;
                     const float v = kHidden ? rho[rm[u]] + rho[rm[u] + hid] : rho[rm[u]];
                     if (!(v > 0.f)) flags |= MJP_FLAG_UNDERFLOW_OBS;
+                    else if (v < FLT_MIN) flags |= MJP_FLAG_SUBNORMAL_OBS;
                     a.phi[(int64_t)b * a.n_rec + tid + u * T] = v > 0.f ? log((double)v) : -INFINITY;
                 }
                 continue;
@@ -642,6 +659,7 @@ __global__ __launch_bounds__(T) void k_ll_main(LLArgs a, int cls) {
                     flags |= MJP_FLAG_UNDERFLOW_OBS;
                     continue;
                 }
+                if (p < FLT_MIN) flags |= MJP_FLAG_SUBNORMAL_OBS;
                 ll += (double)a.rec[r].count * log((double)p);
             }
             tot = ll_block_sum<T>(ll, scratch);
@@ -711,7 +729,7 @@ __global__ __launch_bounds__(kColT) void k_ll_col(LLArgs a, int cls) {
     double* wbuf = reinterpret_cast<double*>(lds + sizeof(float) * CAP);   // [2][kLLMaxTimes]
     double* scratch = wbuf + 2 * kLLMaxTimes;                              // [16]
     LLWin* win = reinterpret_cast<LLWin*>(scratch + 16);                   // [kLLMaxTimes]
-    __shared__ int item_sh;
+    __shared__ int pop_sh[kColT / 64];
     __shared__ unsigned flag_sh;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lam = kColReal * wave + lane - 1;  // column segment of this lane
@@ -719,10 +737,7 @@ __global__ __launch_bounds__(kColT) void k_ll_col(LLArgs a, int cls) {
 
     const int first = a.cls_off[cls], last = a.cls_off[cls + 1];
     while (true) {
-        if (tid == 0) item_sh = first + (int)atomicAdd(a.queue + cls, 1u);
-        __syncthreads();
-        const int slot = item_sh;
-        __syncthreads();
+        const int slot = first + queue_pop(a.queue + cls, pop_sh);
         if (slot >= last) break;
         const int b = a.order[slot];
         const double* th = a.theta + ll_stride(MODEL) * (int64_t)b;
@@ -900,6 +915,7 @@ __global__ __launch_bounds__(kColT) void k_ll_col(LLArgs a, int cls) {
                 neg_inf = true;
                 flags |= MJP_FLAG_UNDERFLOW_OBS;
             } else {
+                if (pr < FLT_MIN) flags |= MJP_FLAG_SUBNORMAL_OBS;
                 ll = (double)a.rec[tid].count * log((double)pr);
             }
         }
@@ -953,7 +969,7 @@ struct ClArgs {
     float* __restrict__ xbuf;      // [nclust][2][kClG][2][kClReachMax] boundary states
     double* __restrict__ part;     // [nclust][4][kClG] block sums: renormalisation masses (two
                                    // slots, alternating), an item's log-lik and mass
-    double* __restrict__ ninf;     // [nclust][kClG] count of records with no probability
+    double* __restrict__ ninf;     // [nclust][2][kClG] count of records with no probability; flags (as a double)
     unsigned* __restrict__ wflag;  // [nclust][kClG][32] jumps (exchange rounds) done
     unsigned* __restrict__ abort_word;
     uint64_t timeout_ticks;
@@ -1203,6 +1219,7 @@ __global__ __launch_bounds__(kClT) void k_ll_cluster(ClArgs ca) {
                 flags |= MJP_FLAG_UNDERFLOW_OBS;
                 continue;
             }
+            if (p < FLT_MIN) flags |= MJP_FLAG_SUBNORMAL_OBS;
             ll += (double)a.rec[tid + u * T].count * log((double)p);
         }
         const double tot = ll_block_sum<T>(ll, scratch);
@@ -1217,17 +1234,22 @@ __global__ __launch_bounds__(kClT) void k_ll_cluster(ClArgs ca) {
         if (tid == 0) {
             __hip_atomic_store(pt + 2 * kClG + r, tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(pt + 3 * kClG + r, mass, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(ca.ninf + (size_t)cl * kClG + r, bad + (double)(flag_sh & MJP_FLAG_OUT_OF_GRID ? 1 : 0),
+            __hip_atomic_store(ca.ninf + (size_t)cl * 2 * kClG + r, bad + (double)(flag_sh & MJP_FLAG_OUT_OF_GRID ? 1 : 0),
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(ca.ninf + (size_t)cl * 2 * kClG + kClG + r, (double)flag_sh, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
         }
         ++round;
         if (!cl_sync(wf, r, 0, kClG - 1, round, ca.abort_word, ca.timeout_ticks)) return;
         if (r == 0 && tid == 0) {
             double sll = 0.0, smass = 0.0, sbad = 0.0;
+            unsigned sflags = 0u;
             for (int q = 0; q < kClG; ++q) {
                 sll += __hip_atomic_load(pt + 2 * kClG + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 smass += __hip_atomic_load(pt + 3 * kClG + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                sbad += __hip_atomic_load(ca.ninf + (size_t)cl * kClG + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                sbad += __hip_atomic_load(ca.ninf + (size_t)cl * 2 * kClG + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                sflags |= (unsigned)__hip_atomic_load(ca.ninf + (size_t)cl * 2 * kClG + kClG + q, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
             }
             a.loglik[b] = sbad > 0.0 ? -INFINITY : sll;
             if (a.info) {
@@ -1238,7 +1260,7 @@ __global__ __launch_bounds__(kClT) void k_ll_cluster(ClArgs ca) {
                 inf.mass_out = smass;
                 inf.K = Kmax;
                 inf.L = Lmin;
-                inf.flags = (int32_t)flag_sh;  // rank 0's flags: out-of-grid; its own underflows
+                inf.flags = (int32_t)sflags;  // every workgroup's flags
                 a.info[b] = inf;
             }
         }
@@ -1513,7 +1535,7 @@ static mjp_status ll_work(LLContext& C, hipStream_t s, int B, int n_t, LLBufs& b
     if (C.nclust > 0) {
         const size_t nc = (size_t)C.nclust;
         if ((st = w->cl_x.reserve(sizeof(float) * nc * 2 * kClG * 2 * kClReachMax)) ||
-            (st = w->cl_part.reserve(sizeof(double) * nc * 4 * kClG)) || (st = w->cl_ninf.reserve(sizeof(double) * nc * kClG)) ||
+            (st = w->cl_part.reserve(sizeof(double) * nc * 4 * kClG)) || (st = w->cl_ninf.reserve(sizeof(double) * nc * 2 * kClG)) ||
             (st = w->cl_flag.reserve(sizeof(unsigned) * (nc * kClG * 32 + 32))))
             return st;
         bf.cl_x = w->cl_x.as<float>();

@@ -71,6 +71,7 @@ struct PersistArgs {
     const int32_t* __restrict__ p2;    // two-jump kernel: [G][kP2Tab] regions and neighbour interval
     unsigned* __restrict__ flags;
     double* __restrict__ mass_out;  // [2]: initial mass, last measured mass
+    double* __restrict__ out_mass;  // item sweep only: FP64 mass of each output row, or null
     uint64_t timeout_ticks;         // per-barrier wait limit in wall-clock ticks
     int64_t n;
     int32_t n_slices;
@@ -160,11 +161,14 @@ __device__ __forceinline__ double sum_partials(const double* p, int G, double* r
     return s;
 }
 
-template <int R, int W, bool CSR, bool COH>
-__global__ __launch_bounds__(kPThreads) void k_persistent(PersistArgs a) {
+// The sweep of one workgroup's rows.  ITEMS: the single-workgroup form run
+// once per item of a batch (G = 1; the whole vector is in LDS, so every
+// gather is local and no slice table is read).
+template <int R, int W, bool CSR, bool COH, bool ITEMS>
+__device__ __forceinline__ void persistent_body(const PersistArgs& a) {
     __shared__ double red[kPWaves + 1];
-    const int G = a.G;
-    const int g = logical_block(G);
+    const int G = ITEMS ? 1 : a.G;
+    const int g = ITEMS ? 0 : logical_block(G);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int slice0 = (g * kPWaves + wave) * R;
     const int64_t n = a.n;
@@ -241,9 +245,13 @@ __global__ __launch_bounds__(kPThreads) void k_persistent(PersistArgs a) {
 #pragma unroll
             for (int j = 0; j < W; ++j) coff[i][j] = lbase;  // padding lanes read a local row, weight 0
         }
-        const int sl = slice0 + i;
-        const uint8_t f = sl < a.n_slices ? a.sflag[sl] : kSliceLocal;
-        if (f & kSliceLocal) lmask |= 1u << i;
+        if constexpr (ITEMS) {
+            lmask |= 1u << i;
+        } else {
+            const int sl = slice0 + i;
+            const uint8_t f = sl < a.n_slices ? a.sflag[sl] : kSliceLocal;
+            if (f & kSliceLocal) lmask |= 1u << i;
+        }
     }
     lmask = __builtin_amdgcn_readfirstlane(lmask);
     const int lrow0 = wave * R * 64 + lane;  // this thread's row i sits at lrow0 + 64 i
@@ -337,6 +345,16 @@ __global__ __launch_bounds__(kPThreads) void k_persistent(PersistArgs a) {
                     sacc[qq][i] = t;
                 }
                 if (k == jK[qq] && live(i)) a.out[(int64_t)jO[qq] * n + row(i)] = sacc[qq][i] - cacc[qq][i];
+            }
+            if constexpr (ITEMS) {
+                if (k == jK[qq] && a.out_mass) {  // uniform: the row's mass for the item's report
+                    double ms = 0.0;
+#pragma unroll
+                    for (int i = 0; i < R; ++i)
+                        if (live(i)) ms += (double)(sacc[qq][i] - cacc[qq][i]);
+                    ms = block_sum_f64(ms, red);
+                    if (threadIdx.x == 0) a.out_mass[jO[qq]] = ms;
+                }
             }
         }
     };
@@ -448,6 +466,35 @@ __global__ __launch_bounds__(kPThreads) void k_persistent(PersistArgs a) {
     if (g == 0 && threadIdx.x == 0) {
         a.mass_out[0] = mass0;
         a.mass_out[1] = last_mass;
+    }
+}
+
+template <int R, int W, bool CSR, bool COH>
+__global__ __launch_bounds__(kPThreads) void k_persistent(PersistArgs a) {
+    persistent_body<R, W, CSR, COH, false>(a);
+}
+
+// Batched sweep: workgroup g runs items g, g + grid, g + 2 grid, ... of its
+// class (ordered longest first by the host, so each round of the grid takes
+// the next-longest items).  The assignment is static: a queue counter popped
+// by one thread puts a divergent branch in front of the loop's barrier,
+// which the compiler may rotate into a nested loop whose other lanes pass
+// the barrier without the pop.
+template <int R, int W, bool CSR>
+__global__ __launch_bounds__(kPThreads) void k_expv_items(const PersistArgs* __restrict__ items, int B) {
+    for (int b = blockIdx.x; b < B; b += gridDim.x) persistent_body<R, W, CSR, true, true>(items[b]);
+}
+
+// Before the batched sweep: the Poisson weights of every item's windows (the
+// single sweep's formula) and each item's flags word cleared.
+__global__ __launch_bounds__(256) void k_item_weights(const PersistArgs* __restrict__ items) {
+    const PersistArgs& a = items[blockIdx.x];
+    if (threadIdx.x == 0) *a.flags = 0u;
+    double* wt = const_cast<double*>(a.wtab);
+    for (int j = 0; j < a.at.n; ++j) {
+        const TimeParam& tp = a.at.tp[j];
+        const int cnt = tp.K - tp.L + 1;
+        for (int i = threadIdx.x; i < cnt; i += blockDim.x) wt[tp.woff + i] = poisson_weight(tp.W, tp.L + i);
     }
 }
 
@@ -868,6 +915,37 @@ static PersistFn pick(int R, int W) {
     return nullptr;
 }
 
+using ItemFn = void (*)(const PersistArgs*, int);
+
+// the item kernel for (R, W): the same shapes as the one-jump kernel
+template <bool CSR>
+static ItemFn pick_items(int R, int W) {
+#define MJP_CASE(r, w) if (R == r && W == w) return k_expv_items<r, w, CSR>;
+    if constexpr (CSR) {
+        MJP_CASE(1, 3) MJP_CASE(2, 3) MJP_CASE(4, 3) MJP_CASE(8, 3)
+        MJP_CASE(1, 5) MJP_CASE(2, 5) MJP_CASE(4, 5) MJP_CASE(8, 5)
+        MJP_CASE(1, 8) MJP_CASE(2, 8) MJP_CASE(4, 8)
+        MJP_CASE(1, 12) MJP_CASE(2, 12) MJP_CASE(4, 12)
+        MJP_CASE(1, 16) MJP_CASE(2, 16)
+    } else {
+        MJP_CASE(1, 5) MJP_CASE(2, 5) MJP_CASE(4, 5) MJP_CASE(8, 5)
+        MJP_CASE(1, 8) MJP_CASE(2, 8) MJP_CASE(4, 8)
+    }
+#undef MJP_CASE
+    return nullptr;
+}
+
+// Entries per row of the one-jump kernel for this plan (0: too wide).
+static int sweep_width(const mjp_plan* p) {
+    if (p->kind != PLAN_CSR) return stencil_width(p->coef.model) <= 5 ? 5 : 8;
+    if (p->max_width <= 3) return 3;
+    if (p->max_width <= 5) return 5;
+    if (p->max_width <= 8) return 8;
+    if (p->max_width <= 12) return 12;
+    if (p->max_width <= 16) return 16;
+    return 0;
+}
+
 __global__ void k_zero_u32(unsigned* p, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0u;
@@ -877,15 +955,8 @@ __global__ void k_zero_u32(unsigned* p, int n) {
 bool persistent_fits(const mjp_plan* p, int max_open, bool coh, PersistCfg& cfg) {
     if (max_open > kPSlots) return false;
     if (p->n >= ((int64_t)1 << 30)) return false;  // byte offsets of the iterate must fit 32 bits
-    int W = stencil_width(p->coef.model) <= 5 ? 5 : 8;
-    if (p->kind == PLAN_CSR) {
-        if (p->max_width <= 3) W = 3;
-        else if (p->max_width <= 5) W = 5;
-        else if (p->max_width <= 8) W = 8;
-        else if (p->max_width <= 12) W = 12;
-        else if (p->max_width <= 16) W = 16;
-        else return false;
-    }
+    const int W = sweep_width(p);
+    if (W == 0) return false;
     int dev = 0, ncu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return false;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return false;
@@ -928,6 +999,136 @@ bool persistent_fits(const mjp_plan* p, int max_open, bool coh, PersistCfg& cfg)
     return false;
 }
 
+// ---- the batched sweep
+bool item_fits(const mjp_plan* p, int max_open, int& R, int& W) {
+    if (max_open > kPSlots || p->n >= ((int64_t)1 << 30)) return false;
+    W = sweep_width(p);
+    if (W == 0) return false;
+    const int64_t slices = (p->n + 63) / 64;
+    for (int r : {1, 2, 4, 8}) {
+        const ItemFn f = p->kind == PLAN_CSR ? pick_items<true>(r, W) : pick_items<false>(r, W);
+        if (f && slices <= (int64_t)kPWaves * r) {
+            R = r;
+            return true;
+        }
+    }
+    return false;
+}
+
+void ItemWork::release() {
+    args.release();
+    wtab.release();
+    info.release();
+    if (staged) (void)hipEventDestroy(staged);
+    if (stage) (void)hipHostFree(stage);
+    staged = nullptr;
+    stage = nullptr;
+    stage_bytes = 0;
+}
+
+mjp_status launch_items(const std::vector<ItemSweep>& items, bool out_mass, ItemWork& ws, hipStream_t st,
+                        std::vector<int64_t>& info_off) {
+    const int B = (int)items.size();
+    info_off.assign(B, 0);
+    if (B == 0) return MJP_OK;
+    // classes by (kind, R, W); longest first inside a class
+    auto cls_key = [&](int i) {
+        const ItemSweep& it = items[(size_t)i];
+        return (it.p->kind == PLAN_CSR ? 0 : 1000) + it.R * 32 + it.W;
+    };
+    std::vector<double> work((size_t)B);  // n K_max: the item's cell updates
+    for (int i = 0; i < B; ++i) {
+        const ItemSweep& it = items[(size_t)i];
+        int32_t k = 0;
+        for (int j = 0; j < it.at.n; ++j) k = std::max(k, it.at.tp[j].K);
+        work[(size_t)i] = (double)it.p->n * (double)k;
+    }
+    std::vector<int> order((size_t)B);
+    for (int i = 0; i < B; ++i) order[(size_t)i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        const int kx = cls_key(x), ky = cls_key(y);
+        return kx != ky ? kx < ky : work[(size_t)x] > work[(size_t)y];
+    });
+    std::vector<int64_t> woff((size_t)B);
+    int64_t wt = 0, inf = 0;
+    for (int i : order) {
+        woff[(size_t)i] = wt;
+        wt += (std::max<int64_t>(items[(size_t)i].wtotal, 1) + 31) / 32 * 32;  // 256-byte aligned regions
+        info_off[(size_t)i] = inf;
+        inf += (6 + items[(size_t)i].at.n + 7) / 8 * 8;
+    }
+    const size_t abytes = sizeof(PersistArgs) * (size_t)B;
+    mjp_status s;
+    if ((s = ws.args.reserve(abytes)) || (s = ws.wtab.reserve(sizeof(double) * (size_t)wt)) ||
+        (s = ws.info.reserve(sizeof(double) * (size_t)inf)))
+        return s;
+    if (!ws.staged) MJP_HIP(hipEventCreateWithFlags(&ws.staged, hipEventDisableTiming));
+    else MJP_HIP(hipEventSynchronize(ws.staged));  // the last upload from the stage has completed
+    if (ws.stage_bytes < abytes) {
+        if (ws.stage) MJP_HIP(hipHostFree(ws.stage));
+        ws.stage = nullptr;
+        ws.stage_bytes = 0;
+        MJP_HIP(hipHostMalloc(&ws.stage, abytes, hipHostMallocDefault));
+        ws.stage_bytes = abytes;
+    }
+    PersistArgs* A = static_cast<PersistArgs*>(ws.stage);
+    double* info = ws.info.as<double>();
+    struct Cls { int key, beg, cnt; const ItemSweep* first; };
+    std::vector<Cls> cls;
+    for (int pos = 0; pos < B; ++pos) {
+        const int i = order[(size_t)pos];
+        const ItemSweep& it = items[(size_t)i];
+        const mjp_plan* p = it.p;
+        PersistArgs a{};
+        a.slice_off = p->slice_off.as<int32_t>();
+        a.col = p->col.as<int32_t>();
+        a.val = p->val.as<float>();
+        a.dlo = p->dlo.as<float>();
+        a.cf = p->coef;
+        a.rho0 = it.rho0;
+        a.out = it.out;
+        a.wtab = ws.wtab.as<double>() + woff[(size_t)i];
+        double* rep = info + info_off[(size_t)i];
+        a.flags = reinterpret_cast<unsigned*>(rep);
+        a.mass_out = rep + 1;
+        a.pmass = rep + 3;
+        a.out_mass = out_mass ? rep + 6 : nullptr;
+        a.n = p->n;
+        a.n_slices = (int32_t)((p->n + 63) / 64);
+        a.Kmax = 0;
+        for (int j = 0; j < it.at.n; ++j) a.Kmax = std::max(a.Kmax, it.at.tp[j].K);
+        a.renorm_every = p->opts.renorm_every;
+        a.G = 1;
+        a.at = it.at;
+        for (int j = 0; j < it.at.n; ++j) a.slot[j] = it.slot[j];
+        A[pos] = a;
+        const int key = cls_key(i);
+        if (cls.empty() || cls.back().key != key) cls.push_back(Cls{key, pos, 0, &it});
+        cls.back().cnt++;
+    }
+    MJP_HIP(hipMemcpyAsync(ws.args.ptr, ws.stage, abytes, hipMemcpyHostToDevice, st));
+    MJP_HIP(hipEventRecord(ws.staged, st));
+    const PersistArgs* args_d = ws.args.as<PersistArgs>();
+    hipLaunchKernelGGL(k_item_weights, dim3((unsigned)B), dim3(256), 0, st, args_d);
+    int dev = 0, ncu = 0;
+    MJP_HIP(hipGetDevice(&dev));
+    MJP_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    for (size_t c = 0; c < cls.size(); ++c) {
+        const ItemSweep& it = *cls[c].first;
+        const ItemFn f = it.p->kind == PLAN_CSR ? pick_items<true>(it.R, it.W) : pick_items<false>(it.R, it.W);
+        MJP_CHECK(f, MJP_E_UNSUPPORTED, "no item kernel for R=%d W=%d", it.R, it.W);
+        int per_cu = 0;
+        MJP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(f), kPThreads, 0));
+        const int grid = std::max(1, std::min(cls[c].cnt, ncu * std::max(per_cu, 1)));
+        const PersistArgs* first = args_d + cls[c].beg;
+        int cnt = cls[c].cnt;
+        void* kargs[] = {&first, &cnt};
+        MJP_HIP(hipLaunchKernel(reinterpret_cast<const void*>(f), dim3((unsigned)grid), dim3(kPThreads), kargs, 0, st));
+    }
+    MJP_HIP(hipGetLastError());
+    return MJP_OK;
+}
+
 // ---- the two-jump kernel: table and fit
 template <bool CSR>
 static PersistFn pick2(int W, bool force) {
@@ -946,7 +1147,7 @@ static size_t p2_lds_for(int W) { return W == 3 ? p2_lds_bytes<3>() : p2_lds_byt
 // column hulls (conservative); false if some region exceeds the LDS
 // buffers or a neighbour interval spans more than 64 workgroups.
 static bool build_p2_table(const mjp_plan* p, int G, std::vector<int32_t>& tab) {
-    const int64_t n = p->n, n_slices = (n + 63) / 64;
+    const int64_t n = p->n;
     auto hull = [&](int64_t sl, int64_t& lo, int64_t& hi) {
         if (p->kind == PLAN_CSR) {
             lo = p->slice_cmin[(size_t)sl];

@@ -24,6 +24,13 @@ struct AllTimes {
     TimeParam tp[kMaxTimes];
 };
 
+// Poisson weight w_k = exp(-W + k log W - lgamma(k + 1)) in log space
+// (Algorithm 2's P(k | Omega t)); W = 0 is the point mass at k = 0.
+__device__ __forceinline__ double poisson_weight(double W, int k) {
+    if (W > 0.0) return exp(-W + (double)k * log(W) - lgamma((double)k + 1.0));
+    return k == 0 ? 1.0 : 0.0;
+}
+
 // scalar slots in plan->scal (doubles)
 enum { S_MASS0 = 0, S_MASSK = 1, S_FLAGS = 2, S_SCALE = 3, S_COUNT = 8 };
 
@@ -137,6 +144,40 @@ struct PersistCfg {
 };
 
 bool persistent_fits(const mjp_plan* p, int max_open, bool coh, PersistCfg& cfg);
+
+// ---- batched sweep of operators that one workgroup holds
+// One item: an operator, an initial vector and up to kMaxTimes collection
+// times, run by one workgroup with the whole vector in LDS (the
+// single-workgroup form of the persistent sweep, so its result equals the
+// item's own sweep bit for bit).
+struct ItemSweep {
+    const mjp_plan* p = nullptr;
+    const float* rho0 = nullptr;
+    float* out = nullptr;
+    AllTimes at{};
+    int32_t slot[kMaxTimes] = {};
+    int R = 0, W = 0;     // rows per thread and entries per row of the kernel that runs it
+    int64_t wtotal = 0;   // Poisson weights of all its windows
+};
+// Workspace of the batched sweep, one per (device, stream).
+struct ItemWork {
+    hipStream_t stream = nullptr;
+    DevBuf args, wtab, info;
+    void* stage = nullptr;        // pinned host copy of the argument block
+    size_t stage_bytes = 0;
+    hipEvent_t staged = nullptr;  // recorded after the last upload from stage
+    void release();
+};
+// Kernel shape (R, W) for an item of plan p with max_open windows open at
+// once; false if one workgroup cannot hold it.
+bool item_fits(const mjp_plan* p, int max_open, int& R, int& W);
+// Launches every item on st: one weights pass, then one launch per kernel
+// shape present (items of one operator class: one launch).  info_off[i]:
+// offset in doubles of item i's report in ws.info: [0] flags word,
+// [1] initial mass, [2] last measured mass, [6 + j] FP64 mass of output row
+// j (written only when out_mass).
+mjp_status launch_items(const std::vector<ItemSweep>& items, bool out_mass, ItemWork& ws, hipStream_t st,
+                        std::vector<int64_t>& info_off);
 // the two-jump kernel (device-scope protocol only); builds its tables
 bool persistent2_fits(mjp_plan* p, int max_open, PersistCfg& cfg);
 mjp_status probe_exchange(mjp_plan* p, int rounds, hipStream_t st, float* ms_out);

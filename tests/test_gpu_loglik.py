@@ -5,8 +5,9 @@ Bar: |l_gpu - l_oracle| <= sum_i c_i (2e-6 + 2e-9 / p_i) for every item:
 FP32 products and accumulation give a relative error of a few 1e-7 per
 probability, and the left and right Poisson cuts of 2.5e-10 each move at
 most 1e-9 of absolute probability (lumped).  Items whose smallest oracle
-probability is below 1e-12 are excluded from the numeric comparison
-(checked for -inf handling separately)."""
+probability is below 1e-12 are excluded from that comparison (checked for
+-inf handling separately); test_cell_kernel_small_probabilities compares
+items down to 1e-30 with identical truncation on both sides."""
 import ctypes
 import sys
 
@@ -142,6 +143,40 @@ def test_paper_rule(orc, small_case):
         if np.isfinite(ll) and pmin > 1e-12:
             # the paper cutoff leaves a tail up to ~1e-6 on each side; both sides lump it the same way
             assert abs(got[b] - ll) <= tol + 1e-3, (b, got[b], ll)
+
+
+def test_cell_kernel_small_probabilities(orc):
+    """Items whose smallest observed probability lies in (1e-30, 1e-12),
+    down to where FP32 still has its full precision: the paper's jump count
+    K = floor(W + 6 sqrt W) + 1 and L = 0 on both sides, so the truncation is
+    identical and only FP32 arithmetic differs.  Each entry of an iterate is
+    formed from about nine rounded operations; the diagonal enters as
+    x - (exit terms) x, which can amplify a rounding by (1 + e) / (1 - e) <= 21
+    (e <= 1/1.1 the exit probability), and the K jumps' errors add like a
+    random walk, so each observed probability carries a relative error
+    <= 21 * 9 u sqrt(K) ~ 1e-5 at K ~ 1500: bar sum_i c_i 5e-5."""
+    theta_star = [12.0, 1.0, 0.6, 0.5]
+    T = np.array([0.5, 1.5, 3.0])
+    d = synth.gillespie_cascade2(theta_star, T, 20, seed=synth.SEED_DATA)
+    recs = synth.cascade_records(d)
+    g = synth.rng(79)
+    theta = np.array([np.asarray(theta_star) * np.exp(g.uniform(-1.2, 1.2, size=4)) for _ in range(24)])
+    dims = np.array([(40 + 4 * (i % 5), 40 + 3 * (i % 7)) for i in range(len(theta))], np.int32)
+    mjp.mjp_loglik_set_kernel(1, mjp.MJP_LL_KERNEL_CELLS)
+    try:
+        got = run_loglik(1, theta, dims, T, recs, k_rule=mjp.MJP_K_PAPER)
+    finally:
+        mjp.mjp_loglik_set_kernel(1, mjp.MJP_LL_KERNEL_AUTO)
+    bar = 5e-5 * recs[:, 3].sum()
+    small = 0
+    for b in range(len(theta)):
+        ll, _, pmin = oracle_cascade(orc, theta[b], dims[b], T, recs, k_rule=orc.K_PAPER)
+        if not np.isfinite(ll) or pmin <= 1e-30:
+            continue
+        small += pmin < 1e-12
+        assert abs(got[b] - ll) <= bar, (b, dims[b], got[b], ll, pmin)
+    say(f"[gpu] cell kernel: {small} items compared with p_min in (1e-30, 1e-12)")
+    assert small >= 3
 
 
 @pytest.fixture(scope="module")

@@ -18,6 +18,7 @@ moves) through the C ABI.
 * Against the cell kernel (mjp_loglik_set_kernel) on the same inputs, with
   twice that bar.
 """
+import ctypes
 import sys
 
 import numpy as np
@@ -27,9 +28,7 @@ import torch
 from paper_2312_05647_amd import mjp, synth
 
 pytestmark = [pytest.mark.gpu,
-              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU"),
-              pytest.mark.skip(reason="the column kernel is switched off: its first GPU run (this file's first "
-                                      "test) did not finish and no cause has been found in its code")]
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
 
 THETA_STAR = [12.0, 1.0, 0.6, 0.5]
 # (S1, S2): column templates 8 (several with wave-crossing segment wraps),
@@ -52,16 +51,22 @@ def data():
     return T, recs
 
 
-def run(theta, dims, T, recs, kernel, **opts):
+def run(theta, dims, T, recs, kernel, flags=False, **opts):
     mjp.mjp_loglik_set_kernel(1, kernel)
     try:
         B = len(theta)
         th = torch.as_tensor(np.asarray(theta, np.float64), device="cuda").contiguous()
         dm = torch.as_tensor(np.asarray(dims, np.int32), device="cuda").contiguous()
         out = torch.empty(B, dtype=torch.float64, device="cuda")
-        mjp.mjp_loglik(1, th, dm, mjp.make_obs(T, recs, (0, 0)), out, mjp.mjp_opts_default(**opts))
+        sz = ctypes.sizeof(mjp.mjp_info)
+        info = torch.zeros(B * sz, dtype=torch.uint8, device="cuda") if flags else None
+        mjp.mjp_loglik(1, th, dm, mjp.make_obs(T, recs, (0, 0)), out, mjp.mjp_opts_default(**opts), info=info)
         torch.cuda.synchronize()
-        return out.cpu().numpy()
+        if not flags:
+            return out.cpu().numpy()
+        raw = info.cpu().numpy().tobytes()
+        fl = np.array([mjp.mjp_info.from_buffer_copy(raw[i * sz:(i + 1) * sz]).flags for i in range(B)])
+        return out.cpu().numpy(), fl
     finally:
         mjp.mjp_loglik_set_kernel(1, mjp.MJP_LL_KERNEL_AUTO)
 
@@ -115,19 +120,27 @@ def test_column_kernel_vs_cell_kernel(data):
 
 def test_full_batch_column_vs_cells():
     """The 4096-draw batched workload (grids 148..200 per side): the column
-    kernel and the cell kernel give the same finite/-inf pattern and values
-    within the bar above."""
+    kernel and the cell kernel give the same finite/-inf pattern (up to
+    items at the edge of FP32's range) and values within the bar above for
+    every item whose observed probabilities all lie in FP32's normal range
+    (neither kernel raises MJP_FLAG_SUBNORMAL_OBS).  Below 1.18e-38 a
+    probability keeps fewer than 24 significant bits, so two kernels that
+    round differently may differ there by more than the bar."""
     theta_star = [50.0, 1.0, 0.5, 0.5]
     T = synth.even_times(20, 0.5)
     d = synth.gillespie_cascade2(theta_star, T, 50, seed=synth.SEED_DATA)
     recs = synth.cascade_records(d)
     theta = synth.theta_draws(4096, theta_star, seed=synth.SEED_THETA)
     dims = synth.grid_dims(theta, (int(d[:, 1].max()), int(d[:, 2].max())))
-    a = run(theta, dims, T, recs, mjp.MJP_LL_KERNEL_AUTO)
-    b = run(theta, dims, T, recs, mjp.MJP_LL_KERNEL_CELLS)
+    a, fla = run(theta, dims, T, recs, mjp.MJP_LL_KERNEL_AUTO, flags=True)
+    b, flb = run(theta, dims, T, recs, mjp.MJP_LL_KERNEL_CELLS, flags=True)
     fa, fb = np.isfinite(a), np.isfinite(b)
+    normal = ((fla | flb) & mjp.MJP_FLAG_SUBNORMAL_OBS) == 0
+    both = fa & fb & normal
     say(f"[gpu] full batch: finite {fa.mean():.3f} (column) {fb.mean():.3f} (cells); "
-        f"max |diff| {np.abs(a[fa & fb] - b[fa & fb]).max():.2e}")
+        f"{(fa & fb & ~normal).sum()} finite items read a subnormal probability; "
+        f"max |diff| over the other {both.sum()}: {np.abs(a[both] - b[both]).max():.2e}")
     assert (fa == fb).mean() > 0.99
+    assert both.sum() > 0.6 * len(theta)
     bar = 2 * 5e-5 * recs[:, 3].sum()
-    assert (np.abs(a[fa & fb] - b[fa & fb]) <= bar).all()
+    assert (np.abs(a[both] - b[both]) <= bar).all()
