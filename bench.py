@@ -119,12 +119,34 @@ def bench_small(torch, mjp, reps: int = 20, orc=None):
     out = torch.empty((1, 1000), device="cuda")
     try:
         inf, sec = run(plan, r0, [1.0], out)
+        exact = poisson.pmf(np.arange(1000), 500.0 * (1 - math.exp(-1.0)))
+        res["C1_birth_death_N1000"] = {"us_per_solve": sec * 1e6, "jumps_per_s": inf[0]["K"] / sec, "K": inf[0]["K"],
+                                       "l1_vs_closed_form": float(np.abs(out[0].double().cpu().numpy() - exact).sum())}
+        log(f"[bench] C1: {sec * 1e6:.1f} us/solve, K={inf[0]['K']}")
+        # the same solve for a batch of initial states delta(i) (i = 0..B-1
+        # mod 1000) in one mjp_expv_batched call: one workgroup per item
+        B = 4096
+        r0s = torch.zeros((B, 1000), device="cuda")
+        r0s[torch.arange(B), torch.arange(B) % 1000] = 1.0
+        outs = torch.empty((B, 1, 1000), device="cuda")
+        rl, ol = [r0s[b] for b in range(B)], [outs[b] for b in range(B)]
+        bi = mjp.mjp_expv_batched([plan] * B, rl, [[1.0]] * B, ol, info=True)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        for _ in range(3):
+            mjp.mjp_expv_batched([plan] * B, rl, [[1.0]] * B, ol, stream=stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        bwall = (time.perf_counter() - t0) / 3
+        bsec = ev0.elapsed_time(ev1) / 1e3 / 3
+        same = bool(torch.equal(outs[0, 0], out[0]))
+        res["C1_batched_4096_initial_states"] = {
+            "solves_per_s": B / bsec, "solves_per_s_wall": B / bwall, "us_per_solve": bsec * 1e6 / B,
+            "speedup_vs_single_calls": sec / (bsec / B), "path": bi[0]["path"], "item0_bit_equal_single": same}
+        log(f"[bench] C1 batched: {B / bsec:.0f} solves/s ({sec / (bsec / B):.0f}x single calls), item 0 equal {same}")
     finally:
         mjp.mjp_plan_destroy(plan)
-    exact = poisson.pmf(np.arange(1000), 500.0 * (1 - math.exp(-1.0)))
-    res["C1_birth_death_N1000"] = {"us_per_solve": sec * 1e6, "jumps_per_s": inf[0]["K"] / sec, "K": inf[0]["K"],
-                                   "l1_vs_closed_form": float(np.abs(out[0].double().cpu().numpy() - exact).sum())}
-    log(f"[bench] C1: {sec * 1e6:.1f} us/solve, K={inf[0]['K']}")
 
     m2 = mjp.make_model(mjp.MJP_MODEL_CASCADE2, [200.0, 1.0, 0.5, 0.5], [300, 300])
     rp, ci, va = mjp.mjp_model_csr(m2)
