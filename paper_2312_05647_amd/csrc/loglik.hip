@@ -74,8 +74,10 @@ constexpr int ll_cap(int T, int C) { return T * C < kLLMaxStates ? T * C : kLLMa
 constexpr int kColT = 1024;
 constexpr int kColReal = 62;
 constexpr int kColLanes = kColReal * (kColT / 64);
-constexpr int kColClasses = 8;
-constexpr int kColCs[kColClasses] = {8, 16, 24, 32, 40, 48, 56, 64};
+constexpr int kColClasses = 9;
+// (50: a 200-row column in four segments fits the mirror at stride 201,
+// where 56-row segments would pad it to 225)
+constexpr int kColCs[kColClasses] = {8, 16, 24, 32, 40, 48, 50, 56, 64};
 constexpr bool kColEnabled = true;
 
 // Items above one workgroup's LDS (cascade and birth-death, S1*S2 >

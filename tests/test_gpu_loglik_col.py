@@ -32,10 +32,11 @@ pytestmark = [pytest.mark.gpu,
 
 THETA_STAR = [12.0, 1.0, 0.6, 0.5]
 # (S1, S2): column templates 8 (several with wave-crossing segment wraps),
-# 24, 40, 56, and grids whose mirror exceeds the column kernel's LDS (cell
-# kernel fallback)
+# 24, 40, 50 (the 200-row columns of the batched workload's largest grids),
+# 56 and 64 (one segment per column), and grids whose mirror exceeds the
+# column kernel's LDS (cell kernel fallback)
 GRIDS = [(40, 40), (41, 47), (63, 63), (45, 130), (60, 90), (110, 150), (160, 200), (200, 200),
-         (130, 300), (170, 235)]
+         (199, 197), (700, 55), (500, 60), (130, 300), (170, 235)]
 
 
 def say(*a):
