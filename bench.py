@@ -129,13 +129,13 @@ def bench_small(torch, mjp, reps: int = 20, orc=None):
         r0s = torch.zeros((B, 1000), device="cuda")
         r0s[torch.arange(B), torch.arange(B) % 1000] = 1.0
         outs = torch.empty((B, 1, 1000), device="cuda")
-        rl, ol = [r0s[b] for b in range(B)], [outs[b] for b in range(B)]
-        bi = mjp.mjp_expv_batched([plan] * B, rl, [[1.0]] * B, ol, info=True)
+        plans, tl = [plan] * B, [[1.0]] * B
+        bi = mjp.mjp_expv_batched(plans, r0s, tl, outs, info=True)
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
         ev0.record(stream)
         for _ in range(3):
-            mjp.mjp_expv_batched([plan] * B, rl, [[1.0]] * B, ol, stream=stream)
+            mjp.mjp_expv_batched(plans, r0s, tl, outs, stream=stream)
         ev1.record(stream)
         torch.cuda.synchronize()
         bwall = (time.perf_counter() - t0) / 3
@@ -524,6 +524,8 @@ def main():
     ap.add_argument("--da-chains", type=int, default=256)
     ap.add_argument("--da-steps", type=int, default=60)
     ap.add_argument("--da-train", type=int, default=8192)
+    ap.add_argument("--log-maps", metavar="FILE",
+                    help="write this process's memory map to FILE at exit (to place a crash address in a library)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the byte counters)")
     args = ap.parse_args()
@@ -533,6 +535,14 @@ def main():
 
     import torch
     from paper_2312_05647_amd import mjp
+
+    if args.log_maps:
+        import atexit
+
+        def write_maps(path=args.log_maps):
+            with open("/proc/self/maps") as f, open(path, "w") as g:
+                g.write(f.read())
+        atexit.register(write_maps)
 
     if args.calibrate_copy:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB

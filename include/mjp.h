@@ -652,6 +652,16 @@ const char* mjp_last_error(void);
 /* Library version string. */
 const char* mjp_version(void);
 
+/* Waits for every device the library used and frees the device memory,
+ * pinned host memory and events the library itself owns (the
+ * log-likelihood's observation sets and work tables, the batched sweep's
+ * workspaces); later calls rebuild them.  Handles the caller owns (plans,
+ * Krylov, RK4 and surrogate handles) are not touched, and the fixed array
+ * of mjp_loglik_noalloc stays.  For a clean process exit (the Python
+ * binding calls it at interpreter exit); not thread-safe with other calls.
+ * MJP_E_DEVICE if a device call fails. */
+mjp_status mjp_shutdown(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -15,9 +15,11 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <numeric>
+#include <tuple>
 #include <vector>
 
 #include "internal.h"
@@ -502,8 +504,21 @@ static mjp_status run_sweep(mjp_plan* p, const float* rho0, const std::vector<Sw
     return MJP_OK;
 }
 
+// Windows already formed in one call, keyed by (W, tol, k_rule): a batch
+// of items on one operator and one set of times forms each window once.
+struct WindowCache {
+    std::map<std::tuple<double, double, int32_t>, Window> m;
+    const Window& get(double W, const mjp_opts& o) {
+        const auto key = std::make_tuple(W, o.tol, (int32_t)o.k_rule);
+        auto it = m.find(key);
+        if (it == m.end()) it = m.emplace(key, poisson_window(W, o)).first;
+        return it->second;
+    }
+};
+
 // The times' windows (checked against k_cap), sorted by t; out = caller's index.
-static mjp_status prepare_times(const mjp_plan* p, int32_t n_t, const double* t_h, std::vector<SweepTime>& all) {
+static mjp_status prepare_times(const mjp_plan* p, int32_t n_t, const double* t_h, std::vector<SweepTime>& all,
+                                WindowCache* cache = nullptr) {
     all.clear();
     all.reserve(n_t);
     for (int32_t j = 0; j < n_t; ++j) {
@@ -512,7 +527,8 @@ static mjp_status prepare_times(const mjp_plan* p, int32_t n_t, const double* t_
         SweepTime s;
         s.t = t;
         s.out = j;
-        s.win = poisson_window(p->omega * t, p->opts);  // W = 0 gives K = L = 0
+        // W = 0 gives K = L = 0
+        s.win = cache ? cache->get(p->omega * t, p->opts) : poisson_window(p->omega * t, p->opts);
         MJP_CHECK(s.win.K <= p->opts.k_cap, MJP_E_K_LIMIT, "t[%d] needs K = %lld > k_cap = %lld", j,
                   (long long)s.win.K, (long long)p->opts.k_cap);
         MJP_CHECK(s.win.K < INT32_MAX / 2, MJP_E_K_LIMIT, "K too large");
@@ -534,6 +550,20 @@ struct ItemCtx {
 static ItemCtx& item_ctx(int dev) {
     static ItemCtx ctxs[kItemDevices];
     return ctxs[dev];
+}
+
+// Frees every batched-sweep workspace on every device.
+mjp_status items_release_all() {
+    for (int dev = 0; dev < kItemDevices; ++dev) {
+        ItemCtx& C = item_ctx(dev);
+        std::lock_guard<std::mutex> lock(C.mu);
+        if (C.work.empty()) continue;
+        MJP_HIP(hipSetDevice(dev));
+        MJP_HIP(hipDeviceSynchronize());
+        for (auto& w : C.work) w->release();
+        C.work.clear();
+    }
+    return MJP_OK;
 }
 
 static mjp_status item_work(ItemCtx& C, hipStream_t st, ItemWork*& out) {
@@ -647,10 +677,13 @@ extern "C" mjp_status mjp_expv_batched(int32_t B, mjp_plan* const* plans, const 
     const int dev = plans[0]->device;
     std::vector<ItemSweep> items;
     std::vector<int32_t> item_of, single;
+    items.reserve((size_t)B);
+    item_of.reserve((size_t)B);
     std::vector<std::vector<SweepTime>> times((size_t)B);
+    WindowCache wcache;
     for (int32_t b = 0; b < B; ++b) {
         const mjp_plan* p = plans[b];
-        if (mjp_status s = prepare_times(p, n_t[b], t_h[b], times[(size_t)b])) return s;
+        if (mjp_status s = prepare_times(p, n_t[b], t_h[b], times[(size_t)b], &wcache)) return s;
         const int var = p->opts.variant;
         bool ok = p->device == dev && n_t[b] <= kMaxTimes &&
                   (var == MJP_VARIANT_AUTO || var == MJP_VARIANT_PERSISTENT || var == MJP_VARIANT_PERSISTENT_ONEJUMP);

@@ -78,6 +78,10 @@ __host__ __device__ __forceinline__ void diag_pair(double d, float& hi, float& l
 }
 
 
+// Library-owned device state, freed by mjp_shutdown (loglik.hip, expv.hip).
+mjp_status ll_release_all();
+mjp_status items_release_all();
+
 // Generator checks shared by every CSR entry point (see runtime.hip).
 mjp_status check_generator_csr(const mjp_csr* A, int leaky, double* m_theta, std::vector<double>* diag);
 // Model description checks (model id, dims, finite non-negative rates).

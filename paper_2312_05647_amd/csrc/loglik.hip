@@ -1396,9 +1396,34 @@ struct LLContext {
     }
 };
 
-static LLContext& ctx_for(int dev) {
+static LLContext* ll_contexts() {
     static LLContext ctxs[kLLMaxDevices];
-    return ctxs[dev];
+    return ctxs;
+}
+static LLContext& ctx_for(int dev) { return ll_contexts()[dev]; }
+
+// Frees every device table the log-likelihood calls keep (observation sets,
+// per-stream work tables) on every device; the next call rebuilds them.
+mjp_status ll_release_all() {
+    for (int dev = 0; dev < kLLMaxDevices; ++dev) {
+        LLContext& C = ll_contexts()[dev];
+        std::lock_guard<std::mutex> lock(C.mu);
+        if (C.obs.empty() && C.work.empty()) continue;
+        MJP_HIP(hipSetDevice(dev));
+        MJP_HIP(hipDeviceSynchronize());
+        for (auto& o : C.obs) {
+            o->rec_d.release();
+            o->T_d.release();
+        }
+        for (auto& w : C.work) {
+            for (DevBuf* d : {&w->win, &w->cost, &w->order, &w->queue, &w->cls_off, &w->cl_x, &w->cl_part,
+                              &w->cl_ninf, &w->cl_flag})
+                d->release();
+        }
+        C.obs.clear();
+        C.work.clear();
+    }
+    return MJP_OK;
 }
 
 }  // namespace mjp

@@ -38,6 +38,7 @@
 //    protocol; both protocols give bit-identical results.
 #include <algorithm>
 #include <climits>
+#include <cstring>
 #include <cmath>
 #include <vector>
 
@@ -1079,7 +1080,9 @@ mjp_status launch_items(const std::vector<ItemSweep>& items, bool out_mass, Item
         const int i = order[(size_t)pos];
         const ItemSweep& it = items[(size_t)i];
         const mjp_plan* p = it.p;
-        PersistArgs a{};
+        // every field the single-workgroup sweep reads is written; of the
+        // time table only the item's own entries (the struct is 2 KB)
+        PersistArgs& a = A[pos];
         a.slice_off = p->slice_off.as<int32_t>();
         a.col = p->col.as<int32_t>();
         a.val = p->val.as<float>();
@@ -1099,9 +1102,14 @@ mjp_status launch_items(const std::vector<ItemSweep>& items, bool out_mass, Item
         for (int j = 0; j < it.at.n; ++j) a.Kmax = std::max(a.Kmax, it.at.tp[j].K);
         a.renorm_every = p->opts.renorm_every;
         a.G = 1;
-        a.at = it.at;
-        for (int j = 0; j < it.at.n; ++j) a.slot[j] = it.slot[j];
-        A[pos] = a;
+        a.buf0 = a.buf1 = nullptr;
+        a.bar = a.wflag = nullptr;
+        a.wait = a.p2 = nullptr;
+        a.sflag = nullptr;
+        a.timeout_ticks = 0;
+        a.at.n = it.at.n;
+        std::memcpy(a.at.tp, it.at.tp, sizeof(TimeParam) * (size_t)it.at.n);
+        std::memcpy(a.slot, it.slot, sizeof(int32_t) * (size_t)it.at.n);
         const int key = cls_key(i);
         if (cls.empty() || cls.back().key != key) cls.push_back(Cls{key, pos, 0, &it});
         cls.back().cnt++;

@@ -108,6 +108,16 @@ const char* mjp_last_error(void) { return g_last_error.c_str(); }
 
 const char* mjp_version(void) { return "libmjp 0.1 (gfx950)"; }
 
+mjp_status mjp_shutdown(void) {
+    clear_error();
+    int cur = -1;
+    const bool have = hipGetDevice(&cur) == hipSuccess;
+    mjp_status s = ll_release_all();
+    if (s == MJP_OK) s = items_release_all();
+    if (have) (void)hipSetDevice(cur);
+    return s;
+}
+
 void mjp_opts_default(mjp_opts* o) {
     if (!o) return;
     std::memset(o, 0, sizeof *o);

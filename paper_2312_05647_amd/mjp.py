@@ -8,6 +8,7 @@ every call raises.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 
@@ -169,7 +170,14 @@ _SIGS = [
     ("mjp_rk4_expv", ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, _P, _P]),
     ("mjp_last_error", ctypes.c_char_p, []),
     ("mjp_version", ctypes.c_char_p, []),
+    ("mjp_shutdown", ctypes.c_int, []),
 ]
+
+
+def _shutdown_at_exit():
+    # free the library's own device tables while the HIP runtime is still up
+    if _lib is not None:
+        _lib.mjp_shutdown()
 
 
 def lib():
@@ -184,7 +192,12 @@ def lib():
             f.restype = res
             f.argtypes = args
         _lib = L
+        atexit.register(_shutdown_at_exit)
     return _lib
+
+
+def mjp_shutdown() -> None:
+    _check(lib().mjp_shutdown())
 
 
 def _check(status: int):
@@ -288,15 +301,36 @@ def mjp_probe_exchange(plan: int, rounds: int, stream=None) -> float:
     return us.value
 
 
+def _row_ptrs(x, B):
+    """Per-item device pointers: a list of tensors, or one contiguous tensor
+    whose leading dimension is the item (rows of [B, ...])."""
+    if hasattr(x, "data_ptr") and hasattr(x, "is_contiguous"):
+        assert x.is_contiguous() and x.shape[0] == B, "a batched tensor must be contiguous with B rows"
+        base, step = x.data_ptr(), x[0].numel() * x.element_size()
+        return [base + b * step for b in range(B)]
+    return [_ptr(r) for r in x]
+
+
 def mjp_expv_batched(plans, rho0s, times_list, outs, info: bool = False, stream=None):
+    """rho0s: list of [N_b] tensors or one contiguous [B, N] tensor; outs:
+    list of [n_t_b, N_b] tensors or one contiguous [B, n_t, N] tensor."""
     B = len(plans)
     P = (ctypes.c_void_p * B)(*plans)
-    R = (ctypes.c_void_p * B)(*[_ptr(r) for r in rho0s])
-    O = (ctypes.c_void_p * B)(*[_ptr(o) for o in outs])
-    ts = [np.ascontiguousarray(t, dtype=np.float64).reshape(-1) for t in times_list]
-    NT = (ctypes.c_int32 * B)(*[len(t) for t in ts])
-    TP = (ctypes.c_void_p * B)(*[_ptr(t) for t in ts])
-    total = sum(len(t) for t in ts)
+    R = (ctypes.c_void_p * B)(*_row_ptrs(rho0s, B))
+    O = (ctypes.c_void_p * B)(*_row_ptrs(outs, B))
+    conv = {}  # (array, length, pointer) per distinct times object: a batch often repeats one list
+    keep, nts, tps = [], [], []
+    for t in times_list:
+        c = conv.get(id(t))
+        if c is None:
+            a = np.ascontiguousarray(t, dtype=np.float64).reshape(-1)
+            keep.append(a)
+            c = conv[id(t)] = (len(a), a.ctypes.data)
+        nts.append(c[0])
+        tps.append(c[1])
+    NT = (ctypes.c_int32 * B)(*nts)
+    TP = (ctypes.c_void_p * B)(*tps)
+    total = sum(nts)
     inf = (mjp_info * total)() if info else None
     _check(lib().mjp_expv_batched(B, P, R, NT, TP, O, ctypes.cast(inf, ctypes.c_void_p) if info else None,
                                   _stream(stream)))

@@ -30,6 +30,12 @@ def test_every_declared_symbol_is_exported():
     assert set(names) == bound, set(names) ^ bound
 
 
+def test_shutdown_without_device_work_is_a_no_op():
+    # nothing was allocated by the library: no device call is made
+    assert mjp.lib().mjp_shutdown() == mjp.MJP_OK
+    assert mjp.lib().mjp_shutdown() == mjp.MJP_OK
+
+
 def test_version_and_defaults():
     assert "gfx950" in mjp.mjp_version()
     o = mjp.mjp_opts_default()
