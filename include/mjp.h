@@ -511,6 +511,81 @@ mjp_status mjp_surrogate_set_params(mjp_surrogate* s, const float* params_h, int
 mjp_status mjp_surrogate_save(const mjp_surrogate* s, const char* path);
 mjp_status mjp_surrogate_load(const char* path, mjp_surrogate** out);
 
+/* ------------------------------------------------------ device samplers */
+
+/* Metropolis-Hastings and delayed-acceptance chains on the GPU (SI:
+ * sampling scheme and prior; Christen and Fox 2005 for delayed acceptance).
+ * C chains random-walk in log-rates psi = log(theta), proposal psi' = psi +
+ * L z with z ~ Normal(0, I) (L: lower Cholesky factor of the proposal
+ * covariance), prior Normal(prior_mu, prior_sigma) on every log-rate.  Each
+ * scored proposal's log-likelihood is mjp_loglik's (model, grid, obs, opts).
+ *   Plain MH:  accept with min(1, exp(post(psi') - post(psi))).
+ *   Delayed acceptance (a screen is set): stage 1 accepts with min(1,
+ *     exp(s(psi') - s(psi))), s = the surrogate's log-likelihood (its
+ *     standardised output times ll_std plus ll_mean, inputs (psi - mean) /
+ *     std) plus the exact log-prior; only stage-1 survivors are scored
+ *     exactly, and stage 2 accepts with min(1, exp((post(psi') - post(psi))
+ *     - (s(psi') - s(psi)))), so the exact posterior stays invariant.
+ * Random numbers: Philox4x32-10 (Salmon et al., SC 2011) keyed by cfg.seed
+ * with counter (chain, step mod 2^32, step / 2^32, block): blocks 0-2 give
+ * the normals (Box-Muller on 53-bit uniforms), block 3 the uniforms u1
+ * (stage 1) and u2 (MH test, stage 2).  The same seed, covariance and start
+ * give the same chains on every run, and plain MH equals delayed acceptance
+ * whose screen is constant.
+ * A step is a fixed sequence of kernel launches on the stream with no host
+ * read (the masked likelihood skips stage-1 rejects on the device), so a
+ * step may be captured in a graph once the same call has run eagerly on
+ * the same stream (which sizes the likelihood's tables). */
+typedef struct mjp_sampler mjp_sampler;
+
+typedef struct {
+    int32_t  model;        /* MJP_MODEL_*: the chains sample its 2, 4 or 6 log-rates */
+    int32_t  dims[2];      /* the grid of every likelihood (mjp_loglik's dims; dims[1] unused for BD) */
+    int32_t  chains;       /* C, 1 .. 2^24 */
+    uint64_t seed;         /* Philox key */
+    double   prior_mu;     /* Normal prior on every log-rate */
+    double   prior_sigma;
+} mjp_sampler_cfg;
+
+void       mjp_sampler_cfg_default(mjp_sampler_cfg* cfg);  /* cascade, 256 chains, seed 1, prior (1, 1e5) */
+/* Copies obs (host arrays) and opts; device buffers for cfg->chains chains
+ * on the current device.  MJP_E_INVALID_ARG on a bad model, grid, chain
+ * count, prior or empty observations. */
+mjp_status mjp_sampler_create(const mjp_sampler_cfg* cfg, const mjp_obs* obs, const mjp_opts* opts,
+                              mjp_sampler** out);
+void       mjp_sampler_destroy(mjp_sampler* s);
+/* chol_h [d x d] row-major, lower triangular, finite (d = the model's
+ * log-rate count). */
+mjp_status mjp_sampler_set_proposal(mjp_sampler* s, const double* chol_h);
+/* screen NULL: plain MH.  Otherwise delayed acceptance with this surrogate
+ * (borrowed, must outlive the runs) and its standardisation: psi_mean_h,
+ * psi_std_h [d] (std > 0), output scale ll_mean, ll_std > 0.  Takes effect
+ * at the next mjp_sampler_init. */
+mjp_status mjp_sampler_set_screen(mjp_sampler* s, const mjp_surrogate* screen, const double* psi_mean_h,
+                                  const double* psi_std_h, double ll_mean, double ll_std);
+/* psi0_d [C x d] device: the chains' states; scores them (and screens them)
+ * and zeroes the step and the counters. */
+mjp_status mjp_sampler_init(mjp_sampler* s, const double* psi0_d, mjp_stream_t stream);
+/* steps steps; samples_d [ring_rows x C x d] device or NULL: after step h
+ * the states go to row h mod ring_rows (h counts from 0 since init). */
+mjp_status mjp_sampler_run(mjp_sampler* s, int32_t steps, double* samples_d, int32_t ring_rows,
+                           mjp_stream_t stream);
+/* Checkpoint: states psi_h [C x d], log-posteriors lp_h [C], screened
+ * log-posteriors sc_h [C] and counters_h [4] = (steps, accepted, stage-1
+ * accepted, exact evaluations), host, synchronous.  set_state restores them
+ * (same cfg, proposal and screen): the continued chains equal the
+ * uninterrupted ones. */
+mjp_status mjp_sampler_get_state(const mjp_sampler* s, double* psi_h, double* lp_h, double* sc_h,
+                                 uint64_t* counters_h, mjp_stream_t stream);
+mjp_status mjp_sampler_set_state(mjp_sampler* s, const double* psi_h, const double* lp_h, const double* sc_h,
+                                 const uint64_t* counters_h, mjp_stream_t stream);
+/* The generator itself: out4 = Philox4x32-10(ctr4, key2) on the host, and
+ * out_d[4i .. 4i+3] = Philox4x32-10((i, c1, c2, c3), key) on the device for
+ * i < n. */
+void       mjp_philox4x32_10(const uint32_t* ctr4, const uint32_t* key2, uint32_t* out4);
+mjp_status mjp_philox_fill(uint64_t key, uint32_t c1, uint32_t c2, uint32_t c3, int32_t n, uint32_t* out_d,
+                           mjp_stream_t stream);
+
 /* --------------------------------------- Krylov propagator (Method #5) */
 
 /* rho(0) exp(A t) by Krylov-subspace steps (Sec. 2.2.5, Algorithm

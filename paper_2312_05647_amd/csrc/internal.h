@@ -78,6 +78,12 @@ __host__ __device__ __forceinline__ void diag_pair(double d, float& hi, float& l
 }
 
 
+// mjp_loglik with an optional device mask [B] of the items to compute
+// (0: skipped, outputs untouched); no host synchronisation (loglik.hip).
+mjp_status loglik_run(int32_t model, int32_t B, const double* theta_d, const int32_t* dims_d, const mjp_obs* obs,
+                      const mjp_opts* opts, const uint8_t* active_d, double* loglik_d, mjp_info* info_d,
+                      hipStream_t s);
+
 // Library-owned device state, freed by mjp_shutdown (loglik.hip, expv.hip).
 mjp_status ll_release_all();
 mjp_status items_release_all();

@@ -145,6 +145,7 @@ struct LLArgs {
     const int32_t* __restrict__ kobs;   // jump mode: [B][n_rec] jump count of each observation
     double* __restrict__ phi;           // jump mode: [B][n_rec] log p(s_i | k_i, theta)
     double* __restrict__ omega_out;     // jump mode: [B] Omega_theta, or null
+    const uint8_t* __restrict__ active; // [B] or null: items with 0 are skipped (outputs untouched)
     int32_t B, n_t, n_rec, model, x0_1, x0_2;
     int32_t use_col;                    // cascade items that fit go to the column kernel
     int32_t use_cluster;                // cascade/birth-death items above kLLMaxStates go to clusters
@@ -204,6 +205,7 @@ __global__ void k_ll_prep(LLArgs a) {
     if (idx < kAllClasses) a.queue[idx] = 0u;
     if (idx >= a.B * a.n_t) return;
     const int b = idx / a.n_t, j = idx - b * a.n_t;
+    if (a.active && !a.active[b]) return;
     const double* th = a.theta + ll_stride(a.model) * (int64_t)b;
     bool bad_theta = false;
     for (int i = 0; i < ll_params(a.model); ++i) bad_theta |= !(th[i] >= 0.0) || isinf(th[i]);
@@ -318,8 +320,8 @@ __global__ void k_ll_order(LLArgs a) {
     if (threadIdx.x < kAllClasses) cnt[threadIdx.x] = 0;
     __syncthreads();
     for (int b = threadIdx.x; b < (sort ? P : B); b += blockDim.x) {
-        unsigned long long key = ~0ull;
-        if (b < B) {
+        unsigned long long key = ~0ull;  // padding and skipped items sort last, outside every class
+        if (b < B && (!a.active || a.active[b])) {
             int32_t kmax = 0;
             for (int j = 0; j < a.n_t; ++j) kmax = max(kmax, a.win[(int64_t)b * a.n_t + j].K);
             int S1, S2;
@@ -349,6 +351,7 @@ __global__ void k_ll_order(LLArgs a) {
     __syncthreads();
     if (!sort) {  // too many items to sort in LDS: grouped by class only
         for (int b = threadIdx.x; b < B; b += blockDim.x) {
+            if (a.active && !a.active[b]) continue;
             int S1, S2;
             ll_grid(a.model, a.dims + 2 * b, S1, S2);
             a.order[atomicAdd(&cur[ll_item_class(a, S1, S2)], 1)] = b;
@@ -1769,6 +1772,17 @@ extern "C" mjp_status mjp_loglik(int32_t model, int32_t B, const double* theta_d
                                  const mjp_obs* obs, const mjp_opts* opts, double* loglik_d, mjp_info* info_d,
                                  mjp_stream_t stream) {
     clear_error();
+    return loglik_run(model, B, theta_d, dims_d, obs, opts, nullptr, loglik_d, info_d,
+                      reinterpret_cast<hipStream_t>(stream));
+}
+
+namespace mjp {
+
+// mjp_loglik with an optional device mask of the items to compute (the
+// sampler's second stage: only proposals that passed the screen).
+mjp_status loglik_run(int32_t model, int32_t B, const double* theta_d, const int32_t* dims_d, const mjp_obs* obs,
+                      const mjp_opts* opts, const uint8_t* active_d, double* loglik_d, mjp_info* info_d,
+                      hipStream_t s) {
     std::vector<LLRecord> recs;
     mjp_status st = ll_check(model, B, obs, opts, &recs);
     if (st) return st;
@@ -1778,11 +1792,11 @@ extern "C" mjp_status mjp_loglik(int32_t model, int32_t B, const double* theta_d
     if ((st = ll_device(dev))) return st;
     LLContext& C = ctx_for(dev);
     std::lock_guard<std::mutex> lock(C.mu);
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     LLBufs bf;
     if ((st = ll_attrs(C, dev)) || (st = ll_obs(C, recs, obs, s, bf)) || (st = ll_work(C, s, B, obs->n_t, bf)))
         return st;
-    const LLArgs a = ll_args(C, model, B, obs, opts, theta_d, dims_d, loglik_d, info_d, bf);
+    LLArgs a = ll_args(C, model, B, obs, opts, theta_d, dims_d, loglik_d, info_d, bf);
+    a.active = active_d;
     ll_prepare(a, s);
     col_launch(C, a, s);
     for (int c = 0; c < kLLClasses; ++c) ll_launch(C, a, c, ll_effective(C, model, c, a.n_rec), s);
@@ -1790,6 +1804,8 @@ extern "C" mjp_status mjp_loglik(int32_t model, int32_t B, const double* theta_d
     MJP_HIP(hipGetLastError());
     return MJP_OK;
 }
+
+}  // namespace mjp
 
 extern "C" mjp_status mjp_loglik_set_kernel(int32_t model, int32_t kernel) {
     clear_error();

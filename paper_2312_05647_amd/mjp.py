@@ -71,6 +71,11 @@ class mjp_obs(ctypes.Structure):
                 ("obs_h", ctypes.c_void_p), ("x0", ctypes.c_int32 * 2)]
 
 
+class mjp_sampler_cfg(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_int32), ("dims", ctypes.c_int32 * 2), ("chains", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("prior_mu", ctypes.c_double), ("prior_sigma", ctypes.c_double)]
+
+
 class mjp_mlp_cfg(ctypes.Structure):
     _fields_ = [("in_dim", ctypes.c_int32), ("width", ctypes.c_int32), ("depth", ctypes.c_int32)]
 
@@ -171,6 +176,18 @@ _SIGS = [
     ("mjp_last_error", ctypes.c_char_p, []),
     ("mjp_version", ctypes.c_char_p, []),
     ("mjp_shutdown", ctypes.c_int, []),
+    ("mjp_sampler_cfg_default", None, [_P]),
+    ("mjp_sampler_create", ctypes.c_int, [_P, _P, _P, _P]),
+    ("mjp_sampler_destroy", None, [_P]),
+    ("mjp_sampler_set_proposal", ctypes.c_int, [_P, _P]),
+    ("mjp_sampler_set_screen", ctypes.c_int, [_P, _P, _P, _P, ctypes.c_double, ctypes.c_double]),
+    ("mjp_sampler_init", ctypes.c_int, [_P, _P, _P]),
+    ("mjp_sampler_run", ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int32, _P]),
+    ("mjp_sampler_get_state", ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    ("mjp_sampler_set_state", ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    ("mjp_philox4x32_10", None, [_P, _P, _P]),
+    ("mjp_philox_fill", ctypes.c_int, [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                       ctypes.c_int32, _P, _P]),
 ]
 
 
@@ -605,3 +622,79 @@ def mjp_last_error() -> str:
 
 def mjp_version() -> str:
     return lib().mjp_version().decode()
+
+
+# ------------------------------------------------------- device samplers
+
+def mjp_sampler_cfg_default(**kw) -> mjp_sampler_cfg:
+    c = mjp_sampler_cfg()
+    lib().mjp_sampler_cfg_default(ctypes.byref(c))
+    for k, v in kw.items():
+        if k == "dims":
+            c.dims = (ctypes.c_int32 * 2)(*v)
+        else:
+            setattr(c, k, v)
+    return c
+
+
+def mjp_sampler_create(cfg: mjp_sampler_cfg, obs: mjp_obs, opts: mjp_opts | None = None) -> int:
+    h = ctypes.c_void_p()
+    _check(lib().mjp_sampler_create(ctypes.byref(cfg), ctypes.byref(obs), ctypes.byref(opts or mjp_opts_default()),
+                                    ctypes.byref(h)))
+    return h.value
+
+
+def mjp_sampler_destroy(h) -> None:
+    lib().mjp_sampler_destroy(h)
+
+
+def mjp_sampler_set_proposal(h, chol) -> None:
+    L = np.ascontiguousarray(chol, dtype=np.float64)
+    _check(lib().mjp_sampler_set_proposal(h, _ptr(L)))
+
+
+def mjp_sampler_set_screen(h, screen, psi_mean=None, psi_std=None, ll_mean=0.0, ll_std=1.0) -> None:
+    if screen is None:
+        _check(lib().mjp_sampler_set_screen(h, None, None, None, 0.0, 1.0))
+        return
+    m = np.ascontiguousarray(psi_mean, dtype=np.float64)
+    sd = np.ascontiguousarray(psi_std, dtype=np.float64)
+    _check(lib().mjp_sampler_set_screen(h, screen, _ptr(m), _ptr(sd), float(ll_mean), float(ll_std)))
+
+
+def mjp_sampler_init(h, psi0, stream=None) -> None:
+    _check(lib().mjp_sampler_init(h, _ptr(psi0), _stream(stream)))
+
+
+def mjp_sampler_run(h, steps: int, samples=None, stream=None) -> None:
+    """samples: None or a device float64 tensor [ring, C, d]."""
+    ring = int(samples.shape[0]) if samples is not None else 0
+    _check(lib().mjp_sampler_run(h, int(steps), _ptr(samples), ring, _stream(stream)))
+
+
+def mjp_sampler_get_state(h, C: int, d: int, stream=None):
+    psi = np.empty((C, d)); lp = np.empty(C); sc = np.empty(C); ctr = np.zeros(4, np.uint64)
+    _check(lib().mjp_sampler_get_state(h, _ptr(psi), _ptr(lp), _ptr(sc), _ptr(ctr), _stream(stream)))
+    return {"psi": psi, "lp": lp, "sc": sc, "counters": ctr}
+
+
+def mjp_sampler_set_state(h, state, stream=None) -> None:
+    psi = np.ascontiguousarray(state["psi"], dtype=np.float64)
+    lp = np.ascontiguousarray(state["lp"], dtype=np.float64)
+    sc = np.ascontiguousarray(state["sc"], dtype=np.float64)
+    ctr = np.ascontiguousarray(state["counters"], dtype=np.uint64)
+    _check(lib().mjp_sampler_set_state(h, _ptr(psi), _ptr(lp), _ptr(sc), _ptr(ctr), _stream(stream)))
+
+
+def mjp_philox4x32_10(ctr, key) -> np.ndarray:
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, np.uint32)
+    lib().mjp_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def mjp_philox_fill(key: int, c1: int, c2: int, c3: int, out, stream=None) -> None:
+    """out: device uint32-sized tensor of 4 n words (torch int32 works)."""
+    n = out.numel() // 4
+    _check(lib().mjp_philox_fill(int(key), c1, c2, c3, n, _ptr(out), _stream(stream)))

@@ -202,6 +202,77 @@ def run_da(post: Posterior, screen, psi0, Z, steps: int, gen, draws=None, progre
     return out.cpu().numpy(), st
 
 
+class DeviceChains:
+    """Chains whose every step runs on the device (mjp_sampler_*): Philox
+    draws keyed by `seed`, stage 1, the masked exact likelihood and the
+    accept step as one fixed sequence of launches with no host read.  With a
+    screen the chains use delayed acceptance, else plain MH; the same seed,
+    start and covariance give the same chains, and plain MH equals delayed
+    acceptance under a constant screen."""
+
+    def __init__(self, post: Posterior, chains: int, seed: int, Z, screen: SurrogateScreen | None = None):
+        import torch
+        self.torch = torch
+        npar = 2 if post.model == mjp.MJP_MODEL_BD else (6 if post.model == mjp.MJP_MODEL_AUTOREG else 4)
+        assert post.n_par == npar, "the device sampler samples all of the model's log-rates"
+        self.C, self.d = int(chains), npar
+        cfg = mjp.mjp_sampler_cfg_default(model=post.model, dims=post.dims, chains=self.C, seed=int(seed),
+                                          prior_mu=PRIOR_MU, prior_sigma=PRIOR_SIGMA)
+        self.h = mjp.mjp_sampler_create(cfg, post.obs, post.opts)
+        mjp.mjp_sampler_set_proposal(self.h, np.linalg.cholesky(np.asarray(Z, np.float64)))
+        if screen is not None:
+            mjp.mjp_sampler_set_screen(self.h, screen.h, screen.psi_mean.cpu().numpy(), screen.psi_std.cpu().numpy(),
+                                       screen.ll_mean, screen.ll_std)
+
+    def init(self, psi0, stream=None):
+        psi0 = self.torch.as_tensor(psi0, dtype=self.torch.float64, device="cuda").contiguous()
+        mjp.mjp_sampler_init(self.h, psi0, stream=stream)
+
+    def run(self, steps: int, samples=None, stream=None):
+        mjp.mjp_sampler_run(self.h, steps, samples, stream=stream)
+
+    def state(self):
+        return mjp.mjp_sampler_get_state(self.h, self.C, self.d)
+
+    def set_state(self, st):
+        mjp.mjp_sampler_set_state(self.h, st)
+
+    def close(self):
+        if self.h:
+            mjp.mjp_sampler_destroy(self.h)
+            self.h = None
+
+
+def run_device(post: Posterior, psi0, Z, steps: int, seed: int, screen: SurrogateScreen | None = None,
+               progress=None):
+    """run_mh (screen None) or run_da on the device; returns (samples
+    [steps, C, d] on the host, stats).  progress as in run_mh."""
+    import torch
+    ch = DeviceChains(post, psi0.shape[0], seed, Z, screen)
+    try:
+        samples = torch.empty((steps, ch.C, ch.d), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ch.init(psi0)
+        done = 0
+        while done < steps:
+            n = min(10, steps - done)
+            ch.run(n, samples)  # the ring is the whole array: row h after step h
+            done += n
+            if progress is not None and done % 10 == 0:
+                torch.cuda.synchronize()
+                progress(done)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        ctr = ch.state()["counters"]
+    finally:
+        ch.close()
+    st = ChainStats(steps=steps, accepted=int(ctr[1]), stage1_accepted=int(ctr[2]),
+                    exact_evals=int(ctr[3]) + psi0.shape[0], screen_evals=(steps + 1) * psi0.shape[0] if screen else 0,
+                    seconds=sec)
+    return samples.cpu().numpy(), st
+
+
 def adapt_covariance(post: Posterior, psi0, gen, rounds: int = 6, steps: int = 40, z0: float = 1e-4,
                      eps: float = 1e-12, final_scale: str = "si"):
     """SI adaptive scheme: Z = (2.38 / eta)^2 [cov(recent samples) + eps I],

@@ -52,7 +52,8 @@ def test_struct_layouts_match_header(tmp_path):
                "mjp_train_cfg": mjp.mjp_train_cfg, "mjp_krylov_opts": mjp.mjp_krylov_opts,
                "mjp_krylov_info": mjp.mjp_krylov_info,
                "mjp_rk4_opts": mjp.mjp_rk4_opts, "mjp_rk4_info": mjp.mjp_rk4_info,
-               "mjp_ll_shape": mjp.mjp_ll_shape, "mjp_ll_tune_report": mjp.mjp_ll_tune_report}
+               "mjp_ll_shape": mjp.mjp_ll_shape, "mjp_ll_tune_report": mjp.mjp_ll_tune_report,
+               "mjp_sampler_cfg": mjp.mjp_sampler_cfg}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mjp.h"', "int main(void) {"]
     for name, cls in structs.items():
         lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
@@ -398,3 +399,23 @@ def test_noalloc_loglik_rejects_oversize_on_the_host():
                                       fake, None, None)
     assert st == mjp.MJP_E_WORKSPACE
     assert "scratch" in mjp.mjp_last_error()
+
+
+def test_sampler_rejects_bad_configuration_on_the_host():
+    L = mjp.lib()
+    obs = mjp.make_obs([1.0], [[0, 3, 0, 1]])
+    opts = mjp.mjp_opts_default()
+    h = ctypes.c_void_p()
+    cfg = mjp.mjp_sampler_cfg_default(model=mjp.MJP_MODEL_BD, dims=(50, 1), chains=8)
+    assert L.mjp_sampler_create(None, ctypes.byref(obs), ctypes.byref(opts), ctypes.byref(h)) == mjp.MJP_E_INVALID_ARG
+    for bad in (dict(model=7), dict(chains=0), dict(dims=(0, 1)), dict(prior_sigma=0.0),
+                dict(prior_mu=float("nan"))):
+        c = mjp.mjp_sampler_cfg_default(**{**dict(model=mjp.MJP_MODEL_BD, dims=(50, 1), chains=8), **bad})
+        assert L.mjp_sampler_create(ctypes.byref(c), ctypes.byref(obs), ctypes.byref(opts),
+                                    ctypes.byref(h)) == mjp.MJP_E_INVALID_ARG, bad
+    empty = mjp.make_obs([1.0], np.zeros((0, 4), np.int32))
+    assert L.mjp_sampler_create(ctypes.byref(cfg), ctypes.byref(empty), ctypes.byref(opts),
+                                ctypes.byref(h)) == mjp.MJP_E_INVALID_ARG
+    assert L.mjp_sampler_set_proposal(None, None) == mjp.MJP_E_INVALID_ARG
+    assert L.mjp_sampler_run(None, 1, None, 0, None) == mjp.MJP_E_INVALID_ARG
+    assert L.mjp_philox_fill(1, 0, 0, 0, -1, None, None) == mjp.MJP_E_INVALID_ARG
