@@ -277,7 +277,8 @@ def bench_jmjp(torch, mjp, chains: int = 512, steps: int = 300):
     on the marginal likelihood (R-MJP) for the birth-death posterior of
     (log beta, log gamma): data 10 times 0.5..5 x 30 snapshots from
     (50, 1); both start from the same draws near the posterior and share the
-    random-walk covariance (posterior covariance x 2.38^2/2)."""
+    random-walk covariance (posterior covariance x 2.38^2/2).  Both run every
+    step on the device (mjp_sampler_*, mjp_jmjp_*)."""
     from paper_2312_05647_amd import jmjp, sampler, synth
     beta, gamma = 50.0, 1.0
     T = np.linspace(0.5, 5.0, 10)
@@ -289,14 +290,13 @@ def bench_jmjp(torch, mjp, chains: int = 512, steps: int = 300):
     cov = np.diag([0.004, 0.004])
     psi0 = torch.as_tensor(g.multivariate_normal(center, cov, size=chains), device="cuda")
     mh_post = sampler.Posterior(mjp.MJP_MODEL_BD, T, recs, (N, 1), n_par=2)
-    gen = torch.Generator(device="cuda").manual_seed(13)
     # posterior covariance from a short MH pilot, shared by both samplers
-    pilot, _ = sampler.run_mh(mh_post, psi0, cov * 2.38 ** 2 / 2, 200, gen)
+    pilot, _ = sampler.run_device(mh_post, psi0, cov * 2.38 ** 2 / 2, 200, seed=13)
     Z = np.cov(pilot[100:].reshape(-1, 2).T) * 2.38 ** 2 / 2
     psi1 = torch.as_tensor(pilot[-1], device="cuda")
-    s_mh, st_mh = sampler.run_mh(mh_post, psi1, Z, steps, gen)
+    s_mh, st_mh = sampler.run_device(mh_post, psi1, Z, steps, seed=14)
     post = jmjp.JumpPosterior(mjp.MJP_MODEL_BD, T, recs, (N, 1), n_par=2)
-    s_j, st_j = jmjp.run_jmjp(post, psi1, Z, steps, gen)
+    s_j, st_j = jmjp.run_jmjp_device(post, psi1, Z, steps, seed=15)
     e_mh, e_j = sampler.ess(s_mh), sampler.ess(s_j)
     res = {"workload": f"birth-death posterior, {post.I} snapshots, {chains} chains x {steps} steps per sampler",
            "ess_per_s_mh_rmjp": float(e_mh.min() / st_mh.seconds), "ess_per_s_jmjp": float(e_j.min() / st_j.seconds),
@@ -441,7 +441,9 @@ def bench_da(torch, mjp, chains: int = 256, steps: int = 60, n_train: int = 8192
     approximation of the posterior; both samplers then run `chains` chains
     from the same independent draws of that Gaussian with the same
     covariance.  The surrogate is trained on n_train exact evaluations at
-    draws from the Gaussian with 3x the pilot's standard deviations."""
+    draws from the Gaussian with 3x the pilot's standard deviations.  Every
+    step of every chain runs on the device (mjp_sampler_*: Philox draws,
+    the screen, the masked exact likelihood, the accept step)."""
     from paper_2312_05647_amd import sampler, synth
     theta_star = np.array([200.0, 1.0, 0.5, 0.5])
     T = synth.even_times(20, 0.5)
@@ -449,16 +451,16 @@ def bench_da(torch, mjp, chains: int = 256, steps: int = 60, n_train: int = 8192
     recs = synth.cascade_records(data)
     dims = (300, 300)
     post = sampler.Posterior(mjp.MJP_MODEL_CASCADE2, T, recs, dims)
-    gen = torch.Generator(device="cuda").manual_seed(synth.SEED_MCMC)
     g = synth.rng(synth.SEED_MCMC)
     t0 = time.perf_counter()
     psi0 = torch.as_tensor(np.log(theta_star) + 0.01 * g.standard_normal((pilot_chains, 4)), device="cuda")
     Z0 = 2e-5 * np.eye(4)
-    smp, _ = sampler.run_mh(post, psi0, Z0, pilot_steps, gen, progress=lambda h: log(f"[bench] DA pilot 1: {h}"))
+    smp, _ = sampler.run_device(post, psi0, Z0, pilot_steps, seed=synth.SEED_MCMC + 1,
+                                progress=lambda h: log(f"[bench] DA pilot 1: {h}"))
     half = pilot_steps // 2
-    smp2, _ = sampler.run_mh(post, torch.as_tensor(smp[-1], device="cuda"),
-                             2.38 ** 2 / 4 * np.cov(smp[half:].reshape(-1, 4).T), pilot_steps, gen,
-                             progress=lambda h: log(f"[bench] DA pilot 2: {h}"))
+    smp2, _ = sampler.run_device(post, torch.as_tensor(smp[-1], device="cuda"),
+                                 2.38 ** 2 / 4 * np.cov(smp[half:].reshape(-1, 4).T), pilot_steps,
+                                 seed=synth.SEED_MCMC + 2, progress=lambda h: log(f"[bench] DA pilot 2: {h}"))
     pilot = smp2[half:].reshape(-1, 4)
     pm, pc = pilot.mean(0), np.cov(pilot.T)
     Z = 2.38 ** 2 / 4 * pc
@@ -478,9 +480,12 @@ def bench_da(torch, mjp, chains: int = 256, steps: int = 60, n_train: int = 8192
     try:
         def prog(name):
             return lambda h: log(f"[bench] DA leg {name}: step {h}/{steps}")
-        for name, run in (("plain_mh", lambda: sampler.run_mh(post, starts, Z, steps, gen, progress=prog("mh"))),
+        # every step on the device (Philox draws, screen, masked exact likelihood, accept)
+        for name, run in (("plain_mh", lambda: sampler.run_device(post, starts, Z, steps, seed=synth.SEED_MCMC + 3,
+                                                                  progress=prog("mh"))),
                           ("delayed_acceptance",
-                           lambda: sampler.run_da(post, screen, starts, Z, steps, gen, progress=prog("da")))):
+                           lambda: sampler.run_device(post, starts, Z, steps, seed=synth.SEED_MCMC + 4, screen=screen,
+                                                      progress=prog("da")))):
             smp, st = run()
             e = sampler.ess(smp)
             flat = smp.reshape(-1, smp.shape[2])

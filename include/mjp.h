@@ -586,6 +586,34 @@ void       mjp_philox4x32_10(const uint32_t* ctr4, const uint32_t* key2, uint32_
 mjp_status mjp_philox_fill(uint64_t key, uint32_t c1, uint32_t c2, uint32_t c3, int32_t n, uint32_t* out_d,
                            mjp_stream_t stream);
 
+/* Device Poisson draws: out_d[i] ~ Poisson(lam_d[i]) from the generator
+ * keyed by key with counter (i, c1, 0, attempt): inversion below mean 10,
+ * the transformed rejection method of Hoermann (1993) above. */
+mjp_status mjp_poisson_fill(uint64_t key, uint32_t c1, const double* lam_d, int32_t n, int32_t* out_d,
+                            mjp_stream_t stream);
+
+/* J-MJP Gibbs chains on the device (Method #2, Sec. 2.2.2, Eq.
+ * sample_J-MJP): per step every jump count k_i is proposed from
+ * Poisson(Omega_theta T_i) (its prior, the SI's proposal) and accepted with
+ * min(1, phi(k') / phi(k)), phi = mjp_jump_probs; then theta takes a
+ * Gaussian random-walk step in log space (mjp_sampler's proposal and prior)
+ * with target p(theta) prod_i Poisson(k_i | Omega_theta T_i) phi_i.  Every
+ * record's count must be 1 (one jump count per observation).  Random
+ * numbers: the sampler's Philox generator keyed by cfg.seed (counters
+ * (chain, observation, step, attempt) for the counts, (chain, 2^32 - 1,
+ * step, block) for theta).  No host read inside a step. */
+typedef struct mjp_jmjp mjp_jmjp;
+mjp_status mjp_jmjp_create(const mjp_sampler_cfg* cfg, const mjp_obs* obs, const mjp_opts* opts, mjp_jmjp** out);
+void       mjp_jmjp_destroy(mjp_jmjp* s);
+mjp_status mjp_jmjp_set_proposal(mjp_jmjp* s, const double* chol_h);
+/* psi0_d [C x d] device; the jump counts start from their prior at psi0 and
+ * take k_burn sweeps at fixed psi0; the step and the counters restart. */
+mjp_status mjp_jmjp_init(mjp_jmjp* s, const double* psi0_d, int32_t k_burn, mjp_stream_t stream);
+/* as mjp_sampler_run */
+mjp_status mjp_jmjp_run(mjp_jmjp* s, int32_t steps, double* samples_d, int32_t ring_rows, mjp_stream_t stream);
+/* counters_h [4]: steps, theta accepted, jump counts accepted, jump counts proposed (synchronous) */
+mjp_status mjp_jmjp_counters(const mjp_jmjp* s, uint64_t* counters_h, mjp_stream_t stream);
+
 /* --------------------------------------- Krylov propagator (Method #5) */
 
 /* rho(0) exp(A t) by Krylov-subspace steps (Sec. 2.2.5, Algorithm

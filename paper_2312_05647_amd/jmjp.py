@@ -144,3 +144,30 @@ def run_jmjp(post: JumpPosterior, psi0, Z, steps: int, gen, k_burn: int = 20):
     st = JumpStats(steps=steps, theta_accepted=acc_theta, k_accept_rate=acc_k / max(steps, 1),
                    jump_prob_calls=post.n_calls - n0, seconds=time.perf_counter() - t0)
     return out.cpu().numpy(), st
+
+
+def run_jmjp_device(post: JumpPosterior, psi0, Z, steps: int, seed: int, k_burn: int = 20):
+    """run_jmjp with every step on the device (mjp_jmjp_*: Philox draws, the
+    jump-count proposals and their prior, the theta step); returns (psi
+    samples [steps, C, d] on the host, stats)."""
+    import torch
+    C, d = psi0.shape
+    cfg = mjp.mjp_sampler_cfg_default(model=post.model, dims=post.dims, chains=C, seed=int(seed),
+                                      prior_mu=PRIOR_MU, prior_sigma=PRIOR_SIGMA)
+    h = mjp.mjp_jmjp_create(cfg, post.obs, post.opts)
+    try:
+        mjp.mjp_jmjp_set_proposal(h, np.linalg.cholesky(np.asarray(Z, np.float64)))
+        psi0 = torch.as_tensor(psi0, dtype=torch.float64, device="cuda").contiguous()
+        out = torch.empty((steps, C, d), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mjp.mjp_jmjp_init(h, psi0, k_burn)
+        mjp.mjp_jmjp_run(h, steps, out)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        ctr = mjp.mjp_jmjp_counters(h)
+    finally:
+        mjp.mjp_jmjp_destroy(h)
+    st = JumpStats(steps=steps, theta_accepted=int(ctr[1]), k_accept_rate=float(ctr[2]) / max(float(ctr[3]), 1.0),
+                   jump_prob_calls=2 * steps + 3 + k_burn, seconds=sec)
+    return out.cpu().numpy(), st

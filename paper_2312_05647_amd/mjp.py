@@ -186,6 +186,13 @@ _SIGS = [
     ("mjp_sampler_get_state", ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     ("mjp_sampler_set_state", ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     ("mjp_philox4x32_10", None, [_P, _P, _P]),
+    ("mjp_poisson_fill", ctypes.c_int, [ctypes.c_uint64, ctypes.c_uint32, _P, ctypes.c_int32, _P, _P]),
+    ("mjp_jmjp_create", ctypes.c_int, [_P, _P, _P, _P]),
+    ("mjp_jmjp_destroy", None, [_P]),
+    ("mjp_jmjp_set_proposal", ctypes.c_int, [_P, _P]),
+    ("mjp_jmjp_init", ctypes.c_int, [_P, _P, ctypes.c_int32, _P]),
+    ("mjp_jmjp_run", ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int32, _P]),
+    ("mjp_jmjp_counters", ctypes.c_int, [_P, _P, _P]),
     ("mjp_philox_fill", ctypes.c_int, [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
                                        ctypes.c_int32, _P, _P]),
 ]
@@ -698,3 +705,39 @@ def mjp_philox_fill(key: int, c1: int, c2: int, c3: int, out, stream=None) -> No
     """out: device uint32-sized tensor of 4 n words (torch int32 works)."""
     n = out.numel() // 4
     _check(lib().mjp_philox_fill(int(key), c1, c2, c3, n, _ptr(out), _stream(stream)))
+
+
+def mjp_poisson_fill(key: int, c1: int, lam, out, stream=None) -> None:
+    """lam: device float64 tensor [n]; out: device int32 tensor [n]."""
+    _check(lib().mjp_poisson_fill(int(key), int(c1), _ptr(lam), int(lam.numel()), _ptr(out), _stream(stream)))
+
+
+def mjp_jmjp_create(cfg: mjp_sampler_cfg, obs: mjp_obs, opts: mjp_opts | None = None) -> int:
+    h = ctypes.c_void_p()
+    _check(lib().mjp_jmjp_create(ctypes.byref(cfg), ctypes.byref(obs), ctypes.byref(opts or mjp_opts_default()),
+                                 ctypes.byref(h)))
+    return h.value
+
+
+def mjp_jmjp_destroy(h) -> None:
+    lib().mjp_jmjp_destroy(h)
+
+
+def mjp_jmjp_set_proposal(h, chol) -> None:
+    L = np.ascontiguousarray(chol, dtype=np.float64)
+    _check(lib().mjp_jmjp_set_proposal(h, _ptr(L)))
+
+
+def mjp_jmjp_init(h, psi0, k_burn: int = 20, stream=None) -> None:
+    _check(lib().mjp_jmjp_init(h, _ptr(psi0), int(k_burn), _stream(stream)))
+
+
+def mjp_jmjp_run(h, steps: int, samples=None, stream=None) -> None:
+    ring = int(samples.shape[0]) if samples is not None else 0
+    _check(lib().mjp_jmjp_run(h, int(steps), _ptr(samples), ring, _stream(stream)))
+
+
+def mjp_jmjp_counters(h, stream=None) -> np.ndarray:
+    ctr = np.zeros(4, np.uint64)
+    _check(lib().mjp_jmjp_counters(h, _ptr(ctr), _stream(stream)))
+    return ctr

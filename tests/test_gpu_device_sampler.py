@@ -192,3 +192,53 @@ def test_checkpoint_resume_continues_the_chains(bd):
                 part.close()
     finally:
         mjp.mjp_surrogate_destroy(screen.h)
+
+
+def test_device_poisson_draws_follow_the_law():
+    """Chi-square of 200,000 device draws against the Poisson pmf, for means
+    on both sides of the inversion / transformed-rejection switch."""
+    from scipy.stats import chi2
+    n = 200000
+    for lam in (0.3, 3.0, 9.99, 10.0, 37.5, 500.0, 4000.0):
+        lt = torch.full((n,), lam, dtype=torch.float64, device="cuda")
+        out = torch.empty(n, dtype=torch.int32, device="cuda")
+        mjp.mjp_poisson_fill(99, int(lam * 100), lt, out)
+        x = out.cpu().numpy()
+        lo, hi = int(poisson.ppf(1e-4, lam)), int(poisson.ppf(1 - 1e-4, lam))
+        edges = np.unique(np.linspace(lo, hi + 1, 40).astype(int))
+        obs, _ = np.histogram(x, bins=np.concatenate([[-np.inf], edges[1:-1], [np.inf]]))
+        cdf = poisson.cdf(edges[1:-1] - 1, lam)
+        p = np.diff(np.concatenate([[0.0], cdf, [1.0]]))
+        keep = p * n > 5
+        stat = ((obs[keep] - n * p[keep]) ** 2 / (n * p[keep])).sum()
+        dof = keep.sum() - 1
+        say(f"    Poisson({lam}): mean {x.mean():.4f} var {x.var():.4f} chi2 {stat:.1f} dof {dof}")
+        assert stat < chi2.ppf(1 - 1e-4, dof), lam
+        assert abs(x.mean() - lam) < 6 * np.sqrt(lam / n)
+
+
+def test_device_jmjp_matches_quadrature():
+    """J-MJP Gibbs with every step on the device: the theta marginal of the
+    birth-death posterior (10 times x 30 snapshots) against quadrature."""
+    from paper_2312_05647_amd import jmjp
+    beta, gamma = 50.0, 1.0
+    T = np.linspace(0.5, 5.0, 10)
+    data = synth.gillespie_bd(beta, gamma, T, 30, seed=synth.SEED_DATA)
+    recs = np.array([[j, n, 0, c] for j, n, c in synth.tally(data)], np.int32)
+    N = max(2 * int(data[:, 1].max()), 120)
+    mq, vq = quadrature(T, recs, np.log([beta, gamma]))
+    C, S = 256, 600
+    g = synth.rng(12)
+    psi0 = torch.as_tensor(g.multivariate_normal(mq, np.diag(vq), size=C), device="cuda")
+    Z = np.diag(vq) * 2.38 ** 2 / 2
+    post = jmjp.JumpPosterior(0, T, recs, (N, 1), n_par=2)
+    s, st = jmjp.run_jmjp_device(post, psi0, Z, S, seed=31)
+    e = sampler.ess(s)
+    flat = s.reshape(-1, 2)
+    m, v = flat.mean(0), flat.var(0)
+    mcse = np.sqrt(v / e)
+    say(f"    device jmjp: mean {m} (quad {mq}) mcse {mcse}, var {v} (quad {vq}), ess {e}, "
+        f"theta acc {st.theta_accepted / (S * C):.3f}, k acc {st.k_accept_rate:.3f}, {st.seconds:.1f} s")
+    assert np.all(np.abs(m - mq) < 4 * mcse + 1e-4 * np.abs(mq))
+    assert np.all(np.abs(v - vq) < 0.3 * vq)
+    assert 0.05 < st.k_accept_rate < 0.99  # the host Gibbs sampler measures 0.951 here
