@@ -72,22 +72,31 @@ enum { MJP_VARIANT_AUTO = 0,       /* the plan picks the launch strategy */
        MJP_VARIANT_STEPWISE = 1,   /* one kernel per jump, launched in a loop */
        MJP_VARIANT_PERSISTENT = 2, /* all K jumps in one cooperative launch; the
                                       iterate moves between XCDs through
-                                      device-scope loads and stores; where the
-                                      operator's reach is short (at most 2048
-                                      rows of halo per 4096-row block, width
-                                      <= 5) and renorm_every is even, each
-                                      workgroup computes two jumps per
-                                      synchronisation, recomputing its
-                                      neighbours' boundary rows
-                                      (bit-identical) */
+                                      device-scope loads and stores.  Where
+                                      the operator is a grid (every column of
+                                      row m in {m, m +- 1, m +- S1}, width <=
+                                      5, at least 128 workgroups of 4096 rows)
+                                      and renorm_every is a multiple of 4,
+                                      each workgroup owns a 2-D tile and
+                                      computes four jumps per synchronisation,
+                                      recomputing the rings of cells around
+                                      its tile; else, where the reach is short
+                                      (at most 2048 rows of halo per 4096-row
+                                      block, width <= 5) and renorm_every is
+                                      even, two jumps per synchronisation;
+                                      both bit-identical to one jump per
+                                      synchronisation */
        MJP_VARIANT_PERSISTENT_FENCED = 3, /* one jump per synchronisation,
                                       synchronised with agent-scope
                                       release/acquire fences (L2 write-back and
                                       invalidate per workgroup and jump):
                                       slower, bit-identical; kept as the
                                       reference protocol */
-       MJP_VARIANT_PERSISTENT_ONEJUMP = 4 /* one jump per synchronisation,
-                                      device-scope protocol: bit-identical */ };
+       MJP_VARIANT_PERSISTENT_ONEJUMP = 4, /* one jump per synchronisation,
+                                      device-scope protocol: bit-identical */
+       MJP_VARIANT_PERSISTENT_TWOJUMP = 5 /* two jumps per synchronisation on
+                                      row blocks where they fit, else one:
+                                      bit-identical */ };
 
 typedef struct {
     double  omega_factor;  /* Omega = omega_factor * max|a_nn|; must be > 1 (Eq. B_def: 1.1) */
@@ -142,7 +151,8 @@ enum { MJP_PATH_STEPWISE = 1,            /* one launch per jump */
        MJP_PATH_PERSISTENT = 2,          /* one launch, one jump per synchronisation */
        MJP_PATH_PERSISTENT_FENCED = 3,   /* the same, fenced protocol */
        MJP_PATH_PERSISTENT_TWOJUMP = 4,  /* one launch, two jumps per synchronisation */
-       MJP_PATH_BATCHED_ITEM = 5 };      /* mjp_expv_batched: one workgroup ran the item */
+       MJP_PATH_BATCHED_ITEM = 5,        /* mjp_expv_batched: one workgroup ran the item */
+       MJP_PATH_PERSISTENT_MULTIJUMP = 6 };/* one launch, four jumps per synchronisation on tiles */
 
 /* ------------------------------------------------------------ operators */
 

@@ -14,8 +14,8 @@ barrier, the item) lanes 1..63 of wave 0 re-enter without thread 0's pop.
 The check reads the device assembly that the build keeps (clang's loop
 comments name each block's innermost loop header) and reports every loop
 that contains ``s_barrier`` and also either masks lanes out of the loop
-(``s_andn2_b64 exec, exec, ...``) or branches back to its header on the exec
-mask.
+(``s_andn2_b64 exec, exec, ...``) or branches back to its header while some
+lanes are active (``s_cbranch_execnz``).
 """
 from __future__ import annotations
 
@@ -46,8 +46,11 @@ def divergent_barrier_loops(asm: str) -> list[tuple[str, str]]:
                 continue
             if "s_barrier" in line:
                 barrier.add(loop)
+            # lanes masked out of the loop, or a back edge taken while some
+            # lanes remain (an execz branch to the header is taken only when
+            # no lane is active: not a lane-by-lane exit)
             if re.search(r"s_andn2_b64\s+exec,\s*exec", line) or \
-                    re.search(r"s_cbranch_exec(n)?z\s+\.L" + loop + r"\b", line):
+                    re.search(r"s_cbranch_execnz\s+\.L" + loop + r"\b", line):
                 divergent.add(loop)
         found += [(name, h) for h in sorted(barrier & divergent)]
     return found

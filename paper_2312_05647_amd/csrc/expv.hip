@@ -388,15 +388,22 @@ static mjp_status run_sweep(mjp_plan* p, const float* rho0, const std::vector<Sw
     const bool coh = var != MJP_VARIANT_PERSISTENT_FENCED;
     // two jumps per synchronisation where the operator's reach allows it,
     // else one
-    bool fits = (var == MJP_VARIANT_AUTO || var == MJP_VARIANT_PERSISTENT) && persistent2_fits(p, max_open, cfg);
-    if (!fits && var != MJP_VARIANT_STEPWISE) fits = persistent_fits(p, max_open, coh, cfg);
+    // four jumps per synchronisation on tiles where the operator is a grid,
+    // else two on row blocks where its reach allows, else one
+    const bool multi = var == MJP_VARIANT_AUTO || var == MJP_VARIANT_PERSISTENT;
+    bool fits = multi && persistent_mj_fits(p, max_open, cfg);
+    if (!fits && (multi || var == MJP_VARIANT_PERSISTENT_TWOJUMP)) fits = persistent2_fits(p, max_open, cfg);
+    if (!fits && var != MJP_VARIANT_STEPWISE && var != MJP_VARIANT_PERSISTENT_TWOJUMP)
+        fits = persistent_fits(p, max_open, coh, cfg);
     if (fits) {
         const std::vector<int> slot = colour_slots(at);
-        p->last_path = cfg.jumps == 2 ? MJP_PATH_PERSISTENT_TWOJUMP
-                                      : (coh ? MJP_PATH_PERSISTENT : MJP_PATH_PERSISTENT_FENCED);
+        p->last_path = cfg.jumps >= 4 ? MJP_PATH_PERSISTENT_MULTIJUMP
+                       : cfg.jumps == 2         ? MJP_PATH_PERSISTENT_TWOJUMP
+                                                : (coh ? MJP_PATH_PERSISTENT : MJP_PATH_PERSISTENT_FENCED);
         if ((s = launch_persistent(p, cfg, rho0, at, slot, out, st))) return s;
     } else {
-        if (var == MJP_VARIANT_PERSISTENT || var == MJP_VARIANT_PERSISTENT_FENCED || var == MJP_VARIANT_PERSISTENT_ONEJUMP)
+        if (var == MJP_VARIANT_PERSISTENT || var == MJP_VARIANT_PERSISTENT_FENCED || var == MJP_VARIANT_PERSISTENT_ONEJUMP ||
+            var == MJP_VARIANT_PERSISTENT_TWOJUMP)
             return fail(MJP_E_UNSUPPORTED, "the persistent kernel cannot hold this operator (width %d, %d open windows)",
                         p->max_width, max_open);
         p->last_path = MJP_PATH_STEPWISE;

@@ -135,7 +135,7 @@ __device__ __forceinline__ bool grid_barrier(unsigned* w, unsigned epoch, int g,
         acquire_agent<COH>();
     }
     __syncthreads();
-    return aborted == 0;
+    return __builtin_amdgcn_readfirstlane(aborted) == 0;  // uniform: every thread read the same word
 }
 
 }  // namespace mjp

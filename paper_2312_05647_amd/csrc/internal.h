@@ -132,6 +132,9 @@ struct mjp_plan {
     int wait_key[3] = {0, 0, 0};  // (G, R, valid) the two tables were built for
     mjp::DevBuf p2tab;      // two-jump persistent kernel: per-workgroup regions and neighbour interval
     int p2_key[2] = {0, 0};       // (G, state) the table was built for: 1 fits, 2 does not
+    mjp::DevBuf mjtab;      // tiled multi-jump kernel: per-workgroup rings, entry maps, exchange positions
+    int mj_key[3] = {0, 0, 0};    // (capacity, W, state) the table was built for: 1 fits, 2 does not
+    int mj_G = 0;                 // its workgroups
     int last_path = 0;            // MJP_PATH_* of the last sweep
     std::vector<char> host_stage;
 };

@@ -1016,7 +1016,7 @@ __device__ __forceinline__ bool cl_sync(unsigned* wf, int r, int rlo, int rhi, u
         if (bad) aborted = 1;
     }
     __syncthreads();
-    return aborted == 0;
+    return __builtin_amdgcn_readfirstlane(aborted) == 0;  // uniform: every thread read the same word
 }
 
 template <int MODEL>

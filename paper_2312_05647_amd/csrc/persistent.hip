@@ -37,6 +37,8 @@
 //    acquire fence (L2 write-back / invalidate).  Kept as the reference
 //    protocol; both protocols give bit-identical results.
 #include <algorithm>
+#include <unordered_map>
+#include <array>
 #include <climits>
 #include <cstring>
 #include <cmath>
@@ -134,7 +136,7 @@ __device__ __forceinline__ bool neighbour_sync(unsigned* wflag, int lo, int hi, 
         if (bad) aborted = 1;
     }
     __syncthreads();
-    return aborted == 0;
+    return __builtin_amdgcn_readfirstlane(aborted) == 0;  // uniform: every thread read the same word
 }
 
 __device__ __forceinline__ double block_sum_f64(double v, double* red) {
@@ -842,6 +844,303 @@ __global__ __launch_bounds__(kPThreads) void k_persistent2(PersistArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// S jumps per synchronisation on tiles (the matrix-powers form of the sweep).
+// Workgroup g owns up to kMJOwn rows (for a grid operator: a 2-D tile of
+// cells; otherwise a block of consecutive rows).  With E_0 the own rows and
+// E_{j+1} the columns that the rows of E_j read, a round advances x_k to
+// x_{k+S}: the values of x_k on E_S outside the own rows come from the
+// exchange buffer, then jump j (1..S) computes x_{k+j} on E_{S-j} from
+// x_{k+j-1} on E_{S-j+1}, all in LDS; the own rows of x_{k+S} go to the
+// exchange buffer and one synchronisation (neighbour flags, or the grid
+// barrier at a renormalisation point, which must end a round) follows.
+// Local numbering: own rows first (tile order), then ring 1 = E_1 \ E_0,
+// ring 2, ..., ring S, so every E_j is a prefix.  Own rows keep their
+// operator in registers, ring rows 1..S-1 as (LDS offset, value) pairs in
+// LDS, formed from the same row entries in the same order, so every value
+// equals the one-jump kernel's bit for bit.  The exchange buffer holds the
+// own rows of workgroup g at [g kMJOwn, g kMJOwn + n_0) (tile order); a
+// host-built table gives each ring row's position there.
+constexpr int kMJR = 8;                         // own rows per thread
+constexpr int kMJOwn = kPWaves * kMJR * 64;     // own rows of a workgroup (4096)
+constexpr int kMJHdr = 16;                      // per-workgroup header words
+// header: n_0 .. n_S, wlo, whi, own (gid, lcol), ring (gid, lcol), positions
+// rows of rings 1..S-1 and of rings 1..S a workgroup holds, at most (63 x 63
+// tiles: 792 / 1072 for S = 4, 1960 / 2272 for S = 8)
+constexpr int mj_halo_cap(int S) { return S == 4 ? 1024 : 2048; }
+constexpr int mj_load_cap(int S) { return S == 4 ? 1536 : 2304; }
+constexpr int mj_x_cap(int S) { return kMJOwn + mj_load_cap(S); }
+
+template <int W, int S>
+constexpr size_t mj_lds_bytes() {
+    return sizeof(float) * 2 * mj_x_cap(S) + sizeof(uint2) * (size_t)mj_halo_cap(S) * W +
+           sizeof(float) * mj_halo_cap(S) + sizeof(int32_t) * mj_load_cap(S);
+}
+
+template <int W, bool CSR, int S>
+__global__ __launch_bounds__(kPThreads) void k_persistent_mj(PersistArgs a) {
+    constexpr int R = kMJR;
+    constexpr int kMJHalo = mj_halo_cap(S), kMJLoad = mj_load_cap(S), kMJX = mj_x_cap(S);
+    extern __shared__ __align__(16) char mjlds[];
+    float* X0 = reinterpret_cast<float*>(mjlds);            // x_{k+j} for even j (E_S at j = 0)
+    float* X1 = X0 + kMJX;                                   // x_{k+j} for odd j
+    uint2* hent = reinterpret_cast<uint2*>(X1 + kMJX);      // ring rows' entries, entry j of row h at [j][h]
+    float* hlo = reinterpret_cast<float*>(hent + (size_t)kMJHalo * W);
+    int32_t* lpos = reinterpret_cast<int32_t*>(hlo + kMJHalo);  // exchange positions of rings 1..S
+    __shared__ double red[kPWaves + 1];
+    const int G = a.G;
+    const int g = logical_block(G);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t n = a.n;
+    const int32_t* hd = a.p2 + (size_t)kMJHdr * g;
+    int nS[S + 1];
+#pragma unroll
+    for (int j = 0; j <= S; ++j) nS[j] = hd[j];
+    const int n0 = nS[0], nh = nS[S - 1] - n0, nl = nS[S] - n0;
+    const int wlo = hd[S + 1], whi = hd[S + 2];
+    const int32_t* own_gid = a.p2 + hd[S + 3];
+    const int32_t* own_lcol = own_gid + n0;
+    const int32_t* ring_gid = a.p2 + hd[S + 4];
+    const int32_t* ring_lcol = ring_gid + nh;
+    const int32_t* pos = a.p2 + hd[S + 5];
+    auto li = [&](int i) { return (wave * R + i) * 64 + lane; };
+    auto live = [&](int i) { return li(i) < n0; };
+
+    uint32_t coff[R][W];
+    float cval[R][W];
+    float dlo[R];
+    int32_t gid[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        gid[i] = live(i) ? own_gid[li(i)] : 0;
+        int32_t cc[W];
+        float vv[W], lo;
+        row_entries<W, CSR>(a, (int64_t)gid[i], cc, vv, lo);
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+            coff[i][j] = live(i) ? 4u * (uint32_t)own_lcol[(size_t)li(i) * W + j] : 0u;
+            cval[i][j] = live(i) ? vv[j] : 0.f;
+        }
+        dlo[i] = live(i) ? lo : 0.f;
+    }
+    for (int h = tid; h < nh; h += kPThreads) {
+        int32_t cc[W];
+        float vv[W], lo;
+        row_entries<W, CSR>(a, (int64_t)ring_gid[h], cc, vv, lo);
+#pragma unroll
+        for (int j = 0; j < W; ++j)
+            hent[j * kMJHalo + h] = make_uint2(4u * (uint32_t)ring_lcol[(size_t)h * W + j], __builtin_bit_cast(uint32_t, vv[j]));
+        hlo[h] = lo;
+    }
+    for (int h = tid; h < kMJLoad; h += kPThreads) lpos[h] = h < nl ? pos[h] : 0;
+
+    // ---- k = 0: own rows of x_0 into LDS and into the exchange buffer the
+    // first round reads (buf1), then the initial mass
+    float sacc[kP2Slots][R], cacc[kP2Slots][R];
+#pragma unroll
+    for (int q = 0; q < kP2Slots; ++q)
+#pragma unroll
+        for (int i = 0; i < R; ++i) { sacc[q][i] = 0.f; cacc[q][i] = 0.f; }
+    float yv[R];
+    double mloc = 0.0;
+    const __amdgpu_buffer_rsrc_t r_buf0 = iter_rsrc(a.buf0, (int64_t)G * kMJOwn),
+                                 r_buf1 = iter_rsrc(a.buf1, (int64_t)G * kMJOwn);
+    const uint32_t pbase = 4u * (uint32_t)(g * kMJOwn);
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        yv[i] = live(i) ? a.rho0[gid[i]] : 0.f;
+        if (live(i)) {
+            if (!(yv[i] >= 0.f)) atomicOr(a.flags, (yv[i] != yv[i]) ? (unsigned)MJP_FLAG_NAN : (unsigned)MJP_FLAG_NEG);
+            else if (isinf(yv[i])) atomicOr(a.flags, (unsigned)MJP_FLAG_NAN);
+            X0[li(i)] = yv[i];
+            st_iter<true>(r_buf1, pbase + 4u * (uint32_t)li(i), yv[i]);
+        }
+        mloc += (double)yv[i];
+    }
+    int jq[kP2Slots], jL[kP2Slots], jK[kP2Slots], jO[kP2Slots];  // as in the one-jump kernel
+    int knext = 0;
+    float wvec[kP2Slots];
+    int wbase = 0;
+    auto fetch = [&](int k) {
+        if (k >= knext) {
+            knext = INT_MAX;
+#pragma unroll
+            for (int qq = 0; qq < kP2Slots; ++qq) {
+                jq[qq] = -1;
+                jL[qq] = jK[qq] = jO[qq] = 0;
+            }
+            for (int j = 0; j < a.at.n; ++j) {
+                const TimeParam& tp = a.at.tp[j];
+                const int L = tp.L, K = tp.K;
+                if (k < L) {
+                    knext = min(knext, L);
+                    continue;
+                }
+                if (k > K) continue;
+                knext = min(knext, K + 1);
+                const int o = tp.out, sj = a.slot[j];
+#pragma unroll
+                for (int qq = 0; qq < kP2Slots; ++qq)
+                    if (qq == sj) { jq[qq] = j; jL[qq] = L; jK[qq] = K; jO[qq] = o; }
+            }
+        }
+        if ((k & 63) == 0) {
+            wbase = k;
+            const int kk = k + lane;
+#pragma unroll
+            for (int qq = 0; qq < kP2Slots; ++qq) wvec[qq] = 0.f;
+            for (int j = 0; j < a.at.n; ++j) {
+                const TimeParam& tp = a.at.tp[j];
+                if (kk < tp.L || kk > tp.K) continue;
+                const float w = (kk == tp.K) ? (float)tp.lastw : (float)a.wtab[tp.woff + (kk - tp.L)];
+#pragma unroll
+                for (int qq = 0; qq < kP2Slots; ++qq)
+                    if (qq == a.slot[j]) wvec[qq] = w;
+            }
+        }
+    };
+    auto accumulate = [&](int k) {
+#pragma unroll
+        for (int qq = 0; qq < kP2Slots; ++qq) {
+            if (jq[qq] < 0) continue;
+            const float w = __builtin_bit_cast(
+                float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, wvec[qq]), k - wbase));
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                if (k == jL[qq]) {
+                    sacc[qq][i] = w * yv[i];
+                    cacc[qq][i] = 0.f;
+                } else {
+                    const float yk = fmaf(w, yv[i], -cacc[qq][i]);
+                    const float t = sacc[qq][i] + yk;
+                    cacc[qq][i] = (t - sacc[qq][i]) - yk;
+                    sacc[qq][i] = t;
+                }
+                if (k == jK[qq] && live(i)) a.out[(int64_t)jO[qq] * n + gid[i]] = sacc[qq][i] - cacc[qq][i];
+            }
+        }
+    };
+    fetch(0);
+    accumulate(0);
+    {
+        const double s = block_sum_f64(mloc, red);
+        if (tid == 0) __hip_atomic_store(a.pmass + g, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    unsigned epoch = 1;
+    if (!grid_barrier<true>(a.bar, epoch, g, G, a.flags, a.timeout_ticks)) return;
+    const double mass0 = sum_partials(a.pmass, G, red);
+    double scale = 1.0;
+    double last_mass = mass0;
+    const int m = a.renorm_every;  // a multiple of S, or 0
+    int rc = m, rpar = 0;
+    for (int k = 0; k < a.Kmax; k += S) {
+        const int q = k / S;
+        const __amdgpu_buffer_rsrc_t src = (q & 1) ? r_buf0 : r_buf1;
+        const __amdgpu_buffer_rsrc_t dst = (q & 1) ? r_buf1 : r_buf0;
+        // x_k on rings 1..S from the exchange buffer
+        {
+            constexpr int kU = (kMJLoad + kPThreads - 1) / kPThreads;  // passes covering every ring row
+            float t[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int h = tid + u * kPThreads;
+                t[u] = ld_iter<true>(src, 4u * (uint32_t)lpos[min(h, kMJLoad - 1)]);
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int h = tid + u * kPThreads;
+                if (h < nl) X0[n0 + h] = t[u];
+            }
+        }
+        __syncthreads();
+        double part = 0.0;
+#pragma unroll
+        for (int jj = 1; jj <= S; ++jj) {
+            const float* Xr = (jj & 1) ? X0 : X1;
+            float* Xw = (jj & 1) ? X1 : X0;
+            const char* __restrict__ xrb = reinterpret_cast<const char*>(Xr);
+            const float fs = jj == 1 ? (float)scale : 1.0f;
+            fetch(k + jj);
+            {
+                float xv[R][W];
+#pragma unroll
+                for (int i = 0; i < R; ++i)
+#pragma unroll
+                    for (int j = 1; j < W; ++j) xv[i][j] = *reinterpret_cast<const float*>(xrb + coff[i][j]);
+#pragma unroll
+                for (int i = 0; i < R; ++i) {
+                    float acc = dlo[i] * yv[i];
+                    acc = fmaf(cval[i][0], yv[i], acc);
+#pragma unroll
+                    for (int j = 1; j < W; ++j) acc = fmaf(cval[i][j], xv[i][j], acc);
+                    yv[i] = fs * acc;
+                }
+            }
+            const int nring = nS[S - jj] - n0;  // ring rows this jump computes
+            if (nring > 0) {
+                constexpr int kB = 2;
+                for (int u0 = 0; u0 * kPThreads < nring; u0 += kB) {
+                    uint2 e[kB][W];
+                    float hx[kB][W];
+#pragma unroll
+                    for (int u = 0; u < kB; ++u) {
+                        const int h = min(tid + (u0 + u) * kPThreads, nring - 1);
+#pragma unroll
+                        for (int j = 0; j < W; ++j) e[u][j] = hent[j * kMJHalo + h];
+                    }
+#pragma unroll
+                    for (int u = 0; u < kB; ++u)
+#pragma unroll
+                        for (int j = 0; j < W; ++j) hx[u][j] = *reinterpret_cast<const float*>(xrb + e[u][j].x);
+#pragma unroll
+                    for (int u = 0; u < kB; ++u) {
+                        const int h = tid + (u0 + u) * kPThreads;
+                        float acc = hlo[min(h, nring - 1)] * hx[u][0];
+#pragma unroll
+                        for (int j = 0; j < W; ++j) acc = fmaf(__builtin_bit_cast(float, e[u][j].y), hx[u][j], acc);
+                        if (h < nring) Xw[n0 + h] = fs * acc;
+                    }
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < R; ++i)
+                if (live(i)) Xw[li(i)] = yv[i];
+            accumulate(k + jj);
+            if (k + jj == a.Kmax) break;
+            if (jj < S) __syncthreads();
+        }
+        if (k + S >= a.Kmax) break;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            part += (double)yv[i];
+            if (live(i)) st_iter<true>(dst, pbase + 4u * (uint32_t)li(i), yv[i]);
+        }
+        bool renorm = false;
+        if (m > 0 && (rc -= S) == 0) {
+            rc = m;
+            rpar ^= 1;
+            renorm = true;
+        }
+        double* pm = a.pmass + (size_t)G * (1 + rpar);
+        if (renorm) {
+            const double s = block_sum_f64(part, red);
+            if (tid == 0) __hip_atomic_store(pm + g, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ++epoch;
+            if (!grid_barrier<true>(a.bar, epoch, g, G, a.flags, a.timeout_ticks)) return;
+            if (tid == 0) __hip_atomic_store(&a.wflag[g * 32], (unsigned)(k + S), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            last_mass = sum_partials(pm, G, red);
+            scale = (last_mass > 0.0 && mass0 > 0.0) ? mass0 / last_mass : 1.0;
+        } else {
+            if (!neighbour_sync<true>(a.wflag, wlo, whi, (unsigned)(k + S), g, a.flags, a.timeout_ticks)) return;
+            scale = 1.0;
+        }
+    }
+    if (g == 0 && tid == 0) {
+        a.mass_out[0] = mass0;
+        a.mass_out[1] = last_mass;
+    }
+}
+
 // Exchange floor of the two-jump sweep (a measurement aid, not part of the
 // method): `rounds` rounds of exactly its per-round communication with no
 // arithmetic.  Each round: load the iterate on E2 outside the own rows from
@@ -1218,6 +1517,279 @@ static bool build_p2_table(const mjp_plan* p, int G, std::vector<int32_t>& tab) 
     return true;
 }
 
+// ---- the tiled multi-jump kernel: tables and fit
+static PersistFn pick_mj(int W, bool csr, int S) {
+    if (S == 8) {
+        if (csr) {
+            if (W == 3) return k_persistent_mj<3, true, 8>;
+            if (W == 5) return k_persistent_mj<5, true, 8>;
+        } else if (W == 5) {
+            return k_persistent_mj<5, false, 8>;
+        }
+    } else if (S == 4) {
+        if (csr) {
+            if (W == 3) return k_persistent_mj<3, true, 4>;
+            if (W == 5) return k_persistent_mj<5, true, 4>;
+        } else if (W == 5) {
+            return k_persistent_mj<5, false, 4>;
+        }
+    }
+    return nullptr;
+}
+static size_t mj_lds_for(int W, int S) {
+    if (S == 8) return W == 3 ? mj_lds_bytes<3, 8>() : mj_lds_bytes<5, 8>();
+    return W == 3 ? mj_lds_bytes<3, 4>() : mj_lds_bytes<5, 4>();
+}
+
+// Columns of row m in the order the kernels hold its entries (entry 0 the
+// row itself; absent entries the row itself).
+struct HostRows {
+    const mjp_plan* p;
+    std::vector<int32_t> off, col;  // CSR plans: the sliced ELL's offsets and columns
+    int W;
+    void cols(int64_t m, int32_t* out) const {
+        if (p->kind == PLAN_CSR) {
+            const int64_t s = m >> 6, l = m & 63;
+            const int beg = off[(size_t)s], w = (off[(size_t)s + 1] - beg) >> 6;
+            for (int j = 0; j < W; ++j) out[j] = j < w ? col[(size_t)beg + 64 * (size_t)j + (size_t)l] : (int32_t)m;
+        } else {
+            int32_t cc[kStencilMaxW];
+            float vv[kStencilMaxW], lo;
+            stencil_entries<kStencilMaxW>(p->coef, m, cc, vv, lo);
+            for (int j = 0; j < W; ++j) out[j] = j < kStencilMaxW ? cc[j] : (int32_t)m;
+        }
+    }
+};
+
+// Builds the table for tiles of at most kMJOwn rows and at most `cap`
+// workgroups; false if the operator has no grid structure, or a ring or
+// neighbour interval exceeds the kernel's buffers.
+static bool build_mj_table(mjp_plan* p, int W, int S, int cap, std::vector<int32_t>& tab, int& G_out) {
+    const int64_t n = p->n;
+    HostRows hr{p, {}, {}, W};
+    if (p->kind == PLAN_CSR) {
+        hr.off.resize((size_t)p->n_slices + 1);
+        hr.col.resize((size_t)p->sell_entries);
+        if (hipMemcpy(hr.off.data(), p->slice_off.ptr, sizeof(int32_t) * hr.off.size(), hipMemcpyDeviceToHost) !=
+                hipSuccess ||
+            hipMemcpy(hr.col.data(), p->col.ptr, sizeof(int32_t) * hr.col.size(), hipMemcpyDeviceToHost) != hipSuccess)
+            return false;
+    }
+    // grid: every column of row m in {m, m +- 1, m +- S1}
+    int64_t S1 = 0;
+    {
+        std::vector<int32_t> c(W);
+        for (int64_t m = 0; m < n; ++m) {
+            hr.cols(m, c.data());
+            for (int j = 0; j < W; ++j) {
+                const int64_t d = std::llabs((int64_t)c[j] - m);
+                if (d <= 1) continue;
+                if (S1 == 0) S1 = d;
+                else if (d != S1) return false;
+            }
+        }
+    }
+    const bool one_d = S1 == 0;
+    if (one_d) S1 = n;
+    const int64_t S2 = (n + S1 - 1) / S1;
+    // tiles: tw x th cells, Tx x Ty of them, fewest halo cells per tile (a
+    // band operator: blocks of kMJOwn consecutive rows)
+    int64_t best = -1, Tx = 0, Ty = 0, tw = 0, th = 0;
+    if (one_d) {
+        Tx = (n + kMJOwn - 1) / kMJOwn;
+        Ty = 1;
+        tw = kMJOwn;
+        th = 1;
+        best = Tx <= cap ? 0 : -1;
+    }
+    for (int64_t tx = 1; !one_d && tx <= std::min<int64_t>(S1, 30); ++tx) {
+        const int64_t w = (S1 + tx - 1) / tx;
+        if (w > kMJOwn) continue;
+        const int64_t hmax = kMJOwn / w;
+        const int64_t ty = (S2 + hmax - 1) / hmax;
+        const int64_t h = (S2 + ty - 1) / ty;
+        if (tx * ty > cap) continue;
+        const int64_t cost = (one_d ? 0 : 2 * w) + (S2 > 1 ? 2 * h : 0);
+        if (best < 0 || cost < best || (cost == best && tx * ty < Tx * Ty)) {
+            best = cost;
+            Tx = tx;
+            Ty = ty;
+            tw = w;
+            th = h;
+        }
+    }
+    if (best < 0) return false;
+    const int nt = (int)(Tx * Ty);
+    const int G = (nt + 7) / 8 * 8;
+    if (G > cap) return false;
+    auto owner_of = [&](int64_t m, int64_t& li) {
+        const int64_t i1 = m % S1, i2 = m / S1;
+        const int64_t tx = i1 / tw, ty = i2 / th;
+        const int64_t x0 = tx * tw, y0 = ty * th;
+        const int64_t w = std::min(tw, S1 - x0);
+        li = (i1 - x0) + w * (i2 - y0);
+        return (int)(tx + Tx * ty);
+    };
+    tab.assign((size_t)kMJHdr * G, 0);
+    std::vector<std::vector<int32_t>> ring_owner(G);  // owners of each workgroup's ring rows
+    std::vector<std::vector<int32_t>> lists(G);
+    std::vector<std::array<int32_t, 9>> sizes(G);
+    std::vector<int32_t> cbuf(W);
+    for (int g = 0; g < G; ++g) {
+        std::vector<int32_t>& L = lists[g];
+        std::unordered_map<int32_t, int32_t> loc;
+        if (g < nt) {
+            const int64_t tx = g % Tx, ty = g / Tx, x0 = tx * tw, y0 = ty * th;
+            const int64_t w = std::min(tw, S1 - x0), h = std::min(th, S2 - y0);
+            for (int64_t iy = 0; iy < h; ++iy)
+                for (int64_t ix = 0; ix < w; ++ix) {
+                    const int64_t m = x0 + ix + S1 * (y0 + iy);
+                    if (m < n) L.push_back((int32_t)m);
+                }
+        }
+        for (size_t i = 0; i < L.size(); ++i) loc.emplace(L[i], (int32_t)i);
+        sizes[g][0] = (int32_t)L.size();
+        size_t prev = 0;
+        for (int j = 1; j <= S; ++j) {
+            const size_t end = L.size();
+            std::vector<int32_t> fresh;
+            // E_j = columns of E_{j-1}; those of E_{j-2} are in E_{j-1} already
+            for (size_t r = prev; r < end; ++r) {
+                hr.cols(L[r], cbuf.data());
+                for (int e = 0; e < W; ++e)
+                    if (!loc.count(cbuf[e])) {
+                        loc.emplace(cbuf[e], -1);
+                        fresh.push_back(cbuf[e]);
+                    }
+            }
+            // ring j in exchange-buffer order
+            std::sort(fresh.begin(), fresh.end(), [&](int32_t x, int32_t y) {
+                int64_t lx, ly;
+                const int ox = owner_of(x, lx), oy = owner_of(y, ly);
+                return ox != oy ? ox < oy : lx < ly;
+            });
+            for (int32_t c : fresh) {
+                loc[c] = (int32_t)L.size();
+                L.push_back(c);
+            }
+            prev = j == 1 ? (size_t)sizes[g][0] : (size_t)sizes[g][j - 1];
+            sizes[g][j] = (int32_t)L.size();
+        }
+        const int n0 = sizes[g][0];
+        if (sizes[g][S] - n0 > mj_load_cap(S) || sizes[g][S - 1] - n0 > mj_halo_cap(S)) return false;
+        for (int32_t i = n0; i < sizes[g][S]; ++i) {
+            int64_t li;
+            ring_owner[g].push_back(owner_of(L[(size_t)i], li));
+        }
+        // own rows: gid, local columns; ring rows 1..S-1: gid, local columns;
+        // rings 1..S: exchange positions
+        int32_t* hd = tab.data() + (size_t)kMJHdr * g;
+        for (int j = 0; j <= S; ++j) hd[j] = sizes[g][j];
+        hd[S + 3] = (int32_t)tab.size();
+        for (int i = 0; i < n0; ++i) tab.push_back(L[(size_t)i]);
+        for (int i = 0; i < n0; ++i) {
+            hr.cols(L[(size_t)i], cbuf.data());
+            for (int e = 0; e < W; ++e) tab.push_back(loc.at(cbuf[e]));
+        }
+        hd = tab.data() + (size_t)kMJHdr * g;
+        hd[S + 4] = (int32_t)tab.size();
+        const int nh = sizes[g][S - 1] - n0;
+        for (int h = 0; h < nh; ++h) tab.push_back(L[(size_t)(n0 + h)]);
+        for (int h = 0; h < nh; ++h) {
+            hr.cols(L[(size_t)(n0 + h)], cbuf.data());
+            for (int e = 0; e < W; ++e) tab.push_back(loc.at(cbuf[e]));
+        }
+        hd = tab.data() + (size_t)kMJHdr * g;
+        hd[S + 5] = (int32_t)tab.size();
+        for (int32_t i = n0; i < sizes[g][S]; ++i) {
+            int64_t li;
+            const int o = owner_of(L[(size_t)i], li);
+            tab.push_back((int32_t)((int64_t)o * kMJOwn + li));
+        }
+        if (tab.size() >= (size_t)INT32_MAX) return false;
+    }
+    // neighbour intervals: whom I read and who reads me
+    std::vector<int> lo(G), hi(G);
+    for (int g = 0; g < G; ++g) lo[g] = hi[g] = g;
+    for (int g = 0; g < G; ++g)
+        for (int o : ring_owner[g]) {
+            lo[g] = std::min(lo[g], o);
+            hi[g] = std::max(hi[g], o);
+            lo[o] = std::min(lo[o], g);
+            hi[o] = std::max(hi[o], g);
+        }
+    for (int g = 0; g < G; ++g) {
+        if (hi[g] - lo[g] > 63) return false;
+        tab[(size_t)kMJHdr * g + S + 1] = lo[g];
+        tab[(size_t)kMJHdr * g + S + 2] = hi[g];
+    }
+    G_out = G;
+    return true;
+}
+
+static bool persistent_mj_fits_s(mjp_plan* p, int max_open, int S, PersistCfg& cfg);
+
+bool persistent_mj_fits(mjp_plan* p, int max_open, PersistCfg& cfg) {
+    for (int S : {8, 4})
+        if (persistent_mj_fits_s(p, max_open, S, cfg)) return true;
+    return false;
+}
+
+static bool persistent_mj_fits_s(mjp_plan* p, int max_open, int S, PersistCfg& cfg) {
+    if (max_open > kP2Slots) return false;
+    if (p->n >= ((int64_t)1 << 30)) return false;
+    if (p->opts.renorm_every % S != 0) return false;  // renormalisation points must end a round
+    if (p->opts.barrier_timeout_us < 0) return false;  // the abort-path test uses the two-jump kernel
+    if (p->kind == PLAN_STENCIL && stencil_width(p->coef.model) > 5) return false;
+    int W = 5;
+    if (p->kind == PLAN_CSR) {
+        if (p->max_width <= 3) W = 3;
+        else if (p->max_width <= 5) W = 5;
+        else return false;
+    }
+    int dev = 0, ncu = 0, coop = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return false;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return false;
+    if (p->n < (int64_t)kMJOwn * (ncu / 2)) return false;  // too few workgroups: the one-jump kernel spreads wider
+    PersistFn f = pick_mj(W, p->kind == PLAN_CSR, S);
+    if (!f) return false;
+    const size_t lds = mj_lds_for(W, S);
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(f), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+        hipSuccess)
+        return false;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(f), kPThreads, lds) !=
+            hipSuccess || per_cu < 1)
+        return false;
+    const int cap = ncu * per_cu;
+    const int key1 = W * 16 + S;
+    if (p->mj_key[0] != cap || p->mj_key[1] != key1 || p->mj_key[2] == 0) {
+        std::vector<int32_t> tab;
+        int G = 0;
+        const bool ok = build_mj_table(p, W, S, cap, tab, G);
+        p->mj_key[0] = cap;
+        p->mj_key[1] = key1;
+        p->mj_key[2] = ok ? 1 : 2;
+        p->mj_G = G;
+        if (ok) {
+            if (p->mjtab.reserve(sizeof(int32_t) * tab.size()) != MJP_OK ||
+                hipMemcpy(p->mjtab.ptr, tab.data(), sizeof(int32_t) * tab.size(), hipMemcpyHostToDevice) != hipSuccess) {
+                p->mj_key[2] = 0;
+                return false;
+            }
+        }
+    }
+    if (p->mj_key[2] != 1) return false;
+    cfg.R = kMJR;
+    cfg.W = W;
+    cfg.G = p->mj_G;
+    cfg.coh = true;
+    cfg.jumps = S;
+    cfg.fn = reinterpret_cast<const void*>(f);
+    return true;
+}
+
 bool persistent2_fits(mjp_plan* p, int max_open, PersistCfg& cfg) {
     if (max_open > kP2Slots) return false;
     if (p->n >= ((int64_t)1 << 30)) return false;
@@ -1362,8 +1934,10 @@ static mjp_status build_sweep_tables(mjp_plan* p, const PersistCfg& cfg, const i
 mjp_status launch_persistent(mjp_plan* p, const PersistCfg& cfg, const float* rho0, const AllTimes& at,
                              const std::vector<int>& slot, float* out, hipStream_t st) {
     const int64_t n = p->n;
+    // the multi-jump kernel's exchange buffers hold kMJOwn rows per workgroup
+    const int64_t nbuf = cfg.jumps >= 4 ? std::max<int64_t>(n, (int64_t)cfg.G * kMJOwn) : n;
     mjp_status s;
-    if ((s = p->rho[0].reserve(sizeof(float) * n)) || (s = p->rho[1].reserve(sizeof(float) * n)) ||
+    if ((s = p->rho[0].reserve(sizeof(float) * nbuf)) || (s = p->rho[1].reserve(sizeof(float) * nbuf)) ||
         (s = p->sync.reserve(sizeof(unsigned) * (kBarWords + 32 * (size_t)cfg.G) + sizeof(double) * 3 * (size_t)cfg.G)))
         return s;
     unsigned* bar = p->sync.as<unsigned>();
@@ -1389,7 +1963,7 @@ mjp_status launch_persistent(mjp_plan* p, const PersistCfg& cfg, const float* rh
     a.wflag = wflag;
     a.wait = wait;
     a.sflag = sflag;
-    a.p2 = cfg.jumps == 2 ? p->p2tab.as<int32_t>() : nullptr;
+    a.p2 = cfg.jumps == 2 ? p->p2tab.as<int32_t>() : (cfg.jumps >= 4 ? p->mjtab.as<int32_t>() : nullptr);
     a.flags = reinterpret_cast<unsigned*>(p->scal.as<double>() + S_FLAGS);
     a.mass_out = mass_out;
     a.n = n;
@@ -1410,7 +1984,7 @@ mjp_status launch_persistent(mjp_plan* p, const PersistCfg& cfg, const float* rh
     const int nzero = kBarWords + 32 * cfg.G;
     hipLaunchKernelGGL(k_zero_u32, dim3((nzero + 255) / 256), dim3(256), 0, st, bar, nzero);
     void* args[] = {&a};
-    const size_t lds = cfg.jumps == 2 ? p2_lds_for(cfg.W) : 0;
+    const size_t lds = cfg.jumps == 2 ? p2_lds_for(cfg.W) : (cfg.jumps >= 4 ? mj_lds_for(cfg.W, cfg.jumps) : 0);
     MJP_HIP(hipLaunchCooperativeKernel(cfg.fn, dim3(cfg.G), dim3(kPThreads), args, lds, st));
     return MJP_OK;
 }
@@ -1422,8 +1996,10 @@ mjp_status probe_exchange(mjp_plan* p, int rounds, hipStream_t st, float* ms_out
     PersistCfg cfg;
     MJP_CHECK(persistent2_fits(p, 1, cfg), MJP_E_UNSUPPORTED, "the plan's sweep does not use the two-jump kernel");
     const int64_t n = p->n;
+    // the multi-jump kernel's exchange buffers hold kMJOwn rows per workgroup
+    const int64_t nbuf = cfg.jumps >= 4 ? std::max<int64_t>(n, (int64_t)cfg.G * kMJOwn) : n;
     mjp_status s;
-    if ((s = p->rho[0].reserve(sizeof(float) * n)) || (s = p->rho[1].reserve(sizeof(float) * n)) ||
+    if ((s = p->rho[0].reserve(sizeof(float) * nbuf)) || (s = p->rho[1].reserve(sizeof(float) * nbuf)) ||
         (s = p->sync.reserve(sizeof(unsigned) * (kBarWords + 32 * (size_t)cfg.G) + sizeof(double) * 3 * (size_t)cfg.G)) ||
         (s = p->scal.reserve(sizeof(double) * S_COUNT)))
         return s;

@@ -150,7 +150,7 @@ mjp_status check_opts(const mjp_opts* o) {
               "mass renormalisation is only valid under conservative truncation");
     MJP_CHECK(o->lump == 0 || o->lump == 1, MJP_E_INVALID_ARG, "lump must be 0 or 1");
     MJP_CHECK(o->k_cap >= 1 && o->k_cap <= (int64_t)1 << 30, MJP_E_INVALID_ARG, "k_cap out of range");
-    MJP_CHECK(o->variant >= MJP_VARIANT_AUTO && o->variant <= MJP_VARIANT_PERSISTENT_ONEJUMP, MJP_E_INVALID_ARG,
+    MJP_CHECK(o->variant >= MJP_VARIANT_AUTO && o->variant <= MJP_VARIANT_PERSISTENT_TWOJUMP, MJP_E_INVALID_ARG,
               "bad variant %d", o->variant);
     for (int i = 0; i < 6; ++i) MJP_CHECK(o->reserved[i] == 0, MJP_E_INVALID_ARG, "reserved fields must be 0");
     return MJP_OK;

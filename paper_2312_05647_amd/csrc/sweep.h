@@ -68,7 +68,7 @@ __host__ __device__ inline int64_t stencil_reach(const StencilCoef& cf) {
     return cf.S1;
 }
 template <int W>
-__device__ __forceinline__ void stencil_entries(const StencilCoef& cf, int64_t m, int32_t (&cc)[W], float (&vv)[W],
+__host__ __device__ __forceinline__ void stencil_entries(const StencilCoef& cf, int64_t m, int32_t (&cc)[W], float (&vv)[W],
                                                 float& lo) {
     static_assert(W >= 3, "entries");
     const int32_t mi = (int32_t)m;
@@ -180,6 +180,9 @@ mjp_status launch_items(const std::vector<ItemSweep>& items, bool out_mass, Item
                         std::vector<int64_t>& info_off);
 // the two-jump kernel (device-scope protocol only); builds its tables
 bool persistent2_fits(mjp_plan* p, int max_open, PersistCfg& cfg);
+// the tiled kernel with eight (else four) jumps per synchronisation
+// (grid-structured operators of width <= 5); builds and caches its tables
+bool persistent_mj_fits(mjp_plan* p, int max_open, PersistCfg& cfg);
 mjp_status probe_exchange(mjp_plan* p, int rounds, hipStream_t st, float* ms_out);
 mjp_status launch_persistent(mjp_plan* p, const PersistCfg& cfg, const float* rho0, const AllTimes& at,
                              const std::vector<int>& slot, float* out, hipStream_t st);

@@ -25,8 +25,10 @@ MJP_K_TOL, MJP_K_PAPER = 0, 1
 MJP_CONSERVATIVE, MJP_LEAKY = 0, 1
 MJP_VARIANT_AUTO, MJP_VARIANT_STEPWISE, MJP_VARIANT_PERSISTENT, MJP_VARIANT_PERSISTENT_FENCED = 0, 1, 2, 3
 MJP_VARIANT_PERSISTENT_ONEJUMP = 4
+MJP_VARIANT_PERSISTENT_TWOJUMP = 5
 MJP_PATH_STEPWISE, MJP_PATH_PERSISTENT, MJP_PATH_PERSISTENT_FENCED, MJP_PATH_PERSISTENT_TWOJUMP = 1, 2, 3, 4
 MJP_PATH_BATCHED_ITEM = 5
+MJP_PATH_PERSISTENT_MULTIJUMP = 6
 MJP_KRYLOV_AUTO, MJP_KRYLOV_PASSES, MJP_KRYLOV_FUSED = 0, 1, 2
 MJP_MODEL_BD, MJP_MODEL_CASCADE2, MJP_MODEL_TWOSTATE, MJP_MODEL_AUTOREG = 0, 1, 2, 3
 MJP_FLAG_NAN, MJP_FLAG_NEG, MJP_FLAG_UNDERFLOW_OBS, MJP_FLAG_OUT_OF_GRID, MJP_FLAG_K_LIMIT = 1, 2, 4, 8, 16

@@ -415,7 +415,7 @@ def test_twojump_bit_identical(case, renorm):
     make, rho0, times, fits = _twojump_case(case)
     say(f"[gpu] two-jump {case} renorm_every={renorm}")
     res, paths = [], []
-    for variant in (mjp.MJP_VARIANT_PERSISTENT, mjp.MJP_VARIANT_PERSISTENT_ONEJUMP,
+    for variant in (mjp.MJP_VARIANT_PERSISTENT_TWOJUMP, mjp.MJP_VARIANT_PERSISTENT_ONEJUMP,
                     mjp.MJP_VARIANT_PERSISTENT_FENCED):
         plan = make(variant=variant, renorm_every=renorm)
         try:
@@ -439,7 +439,7 @@ def test_wait_deadline_abort_path(dims):
     workgroup leaves the kernel; the call with info reports MJP_E_DEVICE.
     A solve with the default deadline afterwards is bit-identical to one
     before (nothing is left behind)."""
-    variant = mjp.MJP_VARIANT_AUTO
+    variant = mjp.MJP_VARIANT_PERSISTENT_TWOJUMP
     S1, S2 = dims
     n = S1 * S2
     rp, ci, va = mjp.mjp_model_csr(mjp.make_model(mjp.MJP_MODEL_CASCADE2, [200.0, 1.0, 0.5, 0.5], [S1, S2]))

@@ -42,8 +42,9 @@ def run(plan):
 
 
 @pytest.mark.parametrize("kind", ["csr", "stencil"])
-@pytest.mark.parametrize("variant", [mjp.MJP_VARIANT_PERSISTENT, mjp.MJP_VARIANT_PERSISTENT_FENCED,
-                                     mjp.MJP_VARIANT_PERSISTENT_ONEJUMP, mjp.MJP_VARIANT_STEPWISE])
+@pytest.mark.parametrize("variant", [mjp.MJP_VARIANT_PERSISTENT, mjp.MJP_VARIANT_PERSISTENT_TWOJUMP,
+                                     mjp.MJP_VARIANT_PERSISTENT_FENCED, mjp.MJP_VARIANT_PERSISTENT_ONEJUMP,
+                                     mjp.MJP_VARIANT_STEPWISE])
 def test_full_size_parity(ref, kind, variant):
     say(f"[gpu] cascade {S}x{S} t=1 via {kind}, variant {variant}")
     m = mjp.make_model(1, THETA, [S, S])
@@ -74,23 +75,81 @@ def test_full_size_parity(ref, kind, variant):
 
 @pytest.mark.parametrize("kind", ["csr", "stencil"])
 def test_full_size_protocols_bit_identical(kind):
-    """The persistent kernel's forms (two jumps per synchronisation, one jump
-    with device-scope accesses, one jump with fences) agree bit for bit at
-    full size (248 workgroups, every XCD)."""
+    """The persistent kernel's forms (four jumps per synchronisation on
+    tiles, two on row blocks, one jump with device-scope accesses, one jump
+    with fences) agree bit for bit at full size (every XCD)."""
     say(f"[gpu] cascade {S}x{S} protocols via {kind}")
     m = mjp.make_model(1, THETA, [S, S])
-    res = []
-    for variant in (mjp.MJP_VARIANT_PERSISTENT, mjp.MJP_VARIANT_PERSISTENT_FENCED,
-                    mjp.MJP_VARIANT_PERSISTENT_ONEJUMP):
+    res, paths = [], []
+    for variant in (mjp.MJP_VARIANT_PERSISTENT, mjp.MJP_VARIANT_PERSISTENT_TWOJUMP,
+                    mjp.MJP_VARIANT_PERSISTENT_FENCED, mjp.MJP_VARIANT_PERSISTENT_ONEJUMP):
         opts = mjp.mjp_opts_default(variant=variant)
         plan = mjp.mjp_plan_create_csr(*mjp.mjp_model_csr(m), opts) if kind == "csr" else \
             mjp.mjp_plan_create_stencil(m, opts)
         try:
-            res.append(run(plan)[0])
+            out, inf = run(plan)
+            res.append(out)
+            paths.append(inf["path"])
         finally:
             mjp.mjp_plan_destroy(plan)
+    assert paths == [mjp.MJP_PATH_PERSISTENT_MULTIJUMP, mjp.MJP_PATH_PERSISTENT_TWOJUMP,
+                     mjp.MJP_PATH_PERSISTENT_FENCED, mjp.MJP_PATH_PERSISTENT]
     for r in res[1:]:
         assert np.array_equal(res[0], r)
+
+
+def _mj_case(name):
+    """(plan factory, rho0, times) of grids large enough for the tiled kernel."""
+    if name == "cascade-csr-1000x1000-2open":
+        m = mjp.make_model(1, THETA, [S, S])
+        rp, ci, va = mjp.mjp_model_csr(m)
+        return (lambda **o: mjp.mjp_plan_create_csr(rp, ci, va, mjp.mjp_opts_default(**o)),
+                synth.delta(S * S), [0.3, 0.31])
+    if name == "cascade-stencil-750x750-random":
+        m = mjp.make_model(1, [30.0, 1.0, 0.7, 0.4], [750, 750])
+        return (lambda **o: mjp.mjp_plan_create_stencil(m, mjp.mjp_opts_default(**o)),
+                synth.random_prob(750 * 750, 72), [0.21])
+    if name == "cascade-csr-600x1500":
+        m = mjp.make_model(1, [40.0, 1.0, 0.6, 0.5], [600, 1500])
+        rp, ci, va = mjp.mjp_model_csr(m)
+        return (lambda **o: mjp.mjp_plan_create_csr(rp, ci, va, mjp.mjp_opts_default(**o)),
+                synth.random_prob(600 * 1500, 73), [0.05, 0.4])
+    if name == "bd-stencil-700001":
+        m = mjp.make_model(0, [50000.0, 0.01], [700001])
+        return (lambda **o: mjp.mjp_plan_create_stencil(m, mjp.mjp_opts_default(**o)),
+                synth.delta(700001), [0.01, 0.013])
+    raise KeyError(name)
+
+
+@pytest.mark.parametrize("renorm", [32, 0, 4, 8, 2])
+@pytest.mark.parametrize("case", ["cascade-csr-1000x1000-2open", "cascade-stencil-750x750-random",
+                                  "cascade-csr-600x1500", "bd-stencil-700001"])
+def test_multijump_bit_identical(case, renorm):
+    """Four jumps per synchronisation on tiles (rings of cells around each
+    tile recomputed from the same inputs with the same operations) against
+    the one-jump kernel, bit for bit: square and oblong grids, CSR and
+    stencil plans, a band operator (1-D blocks), jump counts of every
+    residue mod 4, two windows open together, renormalisation every 4, 8 or
+    32 jumps or never.  renorm_every = 2 cannot end a four-jump round: the
+    sweep then takes the two-jump kernel."""
+    make, rho0, times = _mj_case(case)
+    say(f"[gpu] multi-jump {case} renorm_every={renorm}")
+    res, paths = [], []
+    for variant in (mjp.MJP_VARIANT_PERSISTENT, mjp.MJP_VARIANT_PERSISTENT_ONEJUMP):
+        plan = make(variant=variant, renorm_every=renorm)
+        try:
+            r0 = torch.as_tensor(np.asarray(rho0, np.float32), device="cuda")
+            out = torch.empty((len(times), mjp.mjp_plan_n(plan)), device="cuda")
+            inf = mjp.mjp_expv(plan, r0, times, out, info=True)
+            torch.cuda.synchronize()
+        finally:
+            mjp.mjp_plan_destroy(plan)
+        res.append(out.cpu().numpy())
+        paths.append(inf[0]["path"])
+        say(f"    variant {variant}: path {inf[0]['path']}, K {[i['K'] for i in inf]}")
+    want = mjp.MJP_PATH_PERSISTENT_MULTIJUMP if renorm % 4 == 0 else mjp.MJP_PATH_PERSISTENT_TWOJUMP
+    assert paths == [want, mjp.MJP_PATH_PERSISTENT]
+    assert np.array_equal(res[0], res[1])
 
 
 def test_exchange_probe_is_a_floor():
@@ -98,7 +157,7 @@ def test_exchange_probe_is_a_floor():
     the plan's own launch: it must take less per round than a solve's
     rounds do (which add two jumps of arithmetic to the same exchange)."""
     model = mjp.make_model(mjp.MJP_MODEL_CASCADE2, [200.0, 1.0, 0.5, 0.5], [1000, 1000])
-    plan = mjp.mjp_plan_create_stencil(model)
+    plan = mjp.mjp_plan_create_stencil(model, mjp.mjp_opts_default(variant=mjp.MJP_VARIANT_PERSISTENT_TWOJUMP))
     try:
         r0 = torch.zeros(10 ** 6, device="cuda")
         r0[0] = 1.0
