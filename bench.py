@@ -617,20 +617,22 @@ def main():
         wall = time.perf_counter() - t0
         return info, ev0.elapsed_time(ev1) / 1e3 / steps, wall
 
-    def exchange_floor(plan, K):
-        """(rounds per solve, measured us per round, floor us per round) of
-        the two-jump sweep; None where the plan's sweep is another kernel."""
-        if info.get("path") != mjp.MJP_PATH_PERSISTENT_TWOJUMP:
+    def exchange_floor(plan, K, path):
+        """(rounds per solve, floor us per round, jumps per round) of a sweep
+        with several jumps per synchronisation (the tiled or the two-jump
+        kernel); None where the plan's sweep synchronises every jump."""
+        if path not in (mjp.MJP_PATH_PERSISTENT_TWOJUMP, mjp.MJP_PATH_PERSISTENT_MULTIJUMP):
             return None
-        rounds = (K + 1) // 2
-        floor = mjp.mjp_probe_exchange(plan, rounds, stream=stream)
-        return rounds, floor
+        _, jumps = mjp.mjp_probe_exchange2(plan, 50, stream=stream)
+        rounds = -(-K // jumps)
+        floor, _ = mjp.mjp_probe_exchange2(plan, rounds, stream=stream)
+        return rounds, floor, jumps
 
     log(f"[bench] plan {args.kind} N={n} nnz={nnz}")
     plan = make_plan(args.kind)
     info, dev_s, wall = time_solves(plan, args.steps, args.warmup)
     got = out[0].double().cpu().numpy()
-    xfloor = exchange_floor(plan, info["K"])
+    xfloor = exchange_floor(plan, info["K"], info.get("path"))
     mjp.mjp_plan_destroy(plan)
     K, L = info["K"], info["L"]
     ab = algorithmic_bytes(args.kind, n, nnz, K, L)
@@ -640,16 +642,19 @@ def main():
 
     traffic = measured_traffic(args.kind)
     if xfloor is not None:
-        rounds, floor_us = xfloor
+        rounds, floor_us, jumps = xfloor
         meas_us = dev_s * 1e6 / rounds
-        roof = {"bound": "sync", "achieved": K / dev_s, "peak": 2.0 / (floor_us * 1e-6), "unit": "jumps/s",
-                "frac": (K / dev_s) / (2.0 / (floor_us * 1e-6)),
-                "kernel": "one solve (all K jumps, weighted accumulation, lumping), two jumps per neighbour exchange",
-                "rounds_per_solve": rounds, "us_per_round_measured": meas_us,
+        peak = jumps / (floor_us * 1e-6)  # the jump rate if the arithmetic took no time
+        roof = {"bound": "sync", "achieved": K / dev_s, "peak": peak, "unit": "jumps/s",
+                "frac": (K / dev_s) / peak,
+                "kernel": f"one solve (all K jumps, weighted accumulation, lumping), {jumps} jumps per "
+                          f"neighbour exchange" + (" on 2-D tiles" if jumps > 2 else ""),
+                "jumps_per_sync": jumps, "rounds_per_solve": rounds, "us_per_round_measured": meas_us,
                 "us_per_round_exchange_floor": floor_us,
-                "floor_source": "mjp_probe_exchange: the same device-scope halo loads, own-row stores, drain, "
-                                "flags and waits on the same launch, no arithmetic"}
-        log(f"[bench] {args.kind}: {meas_us:.2f} us per two-jump round, exchange floor {floor_us:.2f} us "
+                "us_per_round_arithmetic": meas_us - floor_us,
+                "floor_source": "mjp_probe_exchange2: the same device-scope halo loads, own-row stores, drain, "
+                                "flags and waits on the same launch and tables, no arithmetic"}
+        log(f"[bench] {args.kind}: {meas_us:.2f} us per {jumps}-jump round, exchange floor {floor_us:.2f} us "
             f"({roof['frac']:.2f})")
     else:
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -683,7 +688,7 @@ def main():
         other = "stencil" if args.kind == "csr" else "csr"
         plan = make_plan(other)
         info2, dev2, wall2 = time_solves(plan, max(3, args.steps // 2), 1)
-        xf2 = exchange_floor(plan, info2["K"])
+        xf2 = exchange_floor(plan, info2["K"], info2.get("path"))
         mjp.mjp_plan_destroy(plan)
         ab2 = algorithmic_bytes(other, n, nnz, info2["K"], info2["L"])
         result[f"{other}_variant"] = {"solves_per_s": 1.0 / (wall2 / max(3, args.steps // 2)),
@@ -691,10 +696,10 @@ def main():
                                       "algorithmic_GBps": ab2 / dev2 / 1e9,
                                       "algorithmic_frac_of_hbm_peak": ab2 / dev2 / 1e9 / HBM_PEAK_GBS}
         if xf2 is not None:
-            r2, f2 = xf2
-            result[f"{other}_variant"].update({"us_per_round_measured": dev2 * 1e6 / r2,
+            r2, f2, j2 = xf2
+            result[f"{other}_variant"].update({"jumps_per_sync": j2, "us_per_round_measured": dev2 * 1e6 / r2,
                                                "us_per_round_exchange_floor": f2,
-                                               "sync_frac": (info2["K"] / dev2) / (2.0 / (f2 * 1e-6))})
+                                               "sync_frac": (info2["K"] / dev2) / (j2 / (f2 * 1e-6))})
         log(f"[bench] {other}: {dev2 * 1e3:.3f} ms/solve")
 
     kry = None

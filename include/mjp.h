@@ -273,17 +273,22 @@ mjp_status mjp_expv_batched(int32_t B, mjp_plan* const* plans, const float* cons
                             mjp_info* info_h, mjp_stream_t stream);
 
 /* Measurement aid, not a computation of the method: the floor that the
- * two-jump sweep's synchronisation sets.  Runs `rounds` rounds of exactly its
- * per-round communication on this plan's launch configuration -- each
- * workgroup loads its halo rows of the iterate from global memory into LDS
- * with device-scope loads, stores its own rows with device-scope stores,
- * drains them, publishes its flag and waits for its neighbours' -- without
- * the arithmetic, and returns the mean time per round (HIP events on
- * `stream`, after one warm-up run) in *us_per_round_h.  Synchronous.
- * MJP_E_UNSUPPORTED when the plan's sweep does not use the two-jump kernel;
- * MJP_E_INVALID_ARG for rounds outside [1, 10^6]; MJP_E_DEVICE if a wait
- * missed its 2 s deadline.  Overwrites the plan's iterate buffers. */
+ * synchronisation of the plan's sweep sets (the tiled sweep with several
+ * jumps per synchronisation where the plan's variant allows it, else the
+ * two-jump sweep).  Runs `rounds` rounds of exactly its per-round
+ * communication on this plan's launch configuration -- each workgroup loads
+ * its halo rows of the iterate from global memory into LDS with
+ * device-scope loads, stores its own rows with device-scope stores, drains
+ * them, publishes its flag and waits for its neighbours' -- without the
+ * arithmetic, and returns the mean time per round (HIP events on `stream`,
+ * after one warm-up run) in *us_per_round_h, and (probe_exchange2) the
+ * sweep's jumps per round in *jumps_h.  Synchronous.  MJP_E_UNSUPPORTED
+ * when the plan's sweep synchronises every jump; MJP_E_INVALID_ARG for
+ * rounds outside [1, 10^6]; MJP_E_DEVICE if a wait missed its 2 s deadline.
+ * Overwrites the plan's iterate buffers. */
 mjp_status mjp_probe_exchange(mjp_plan* p, int32_t rounds, double* us_per_round_h, mjp_stream_t stream);
+mjp_status mjp_probe_exchange2(mjp_plan* p, int32_t rounds, double* us_per_round_h, int32_t* jumps_h,
+                               mjp_stream_t stream);
 
 /* Snapshot observations shared by every item of a log-likelihood batch
  * (Sec. 2.1.2): each observation is one system observed at one collection

@@ -647,14 +647,22 @@ extern "C" mjp_status mjp_expv(mjp_plan* p, const float* rho0_d, int32_t n_t, co
 }
 
 extern "C" mjp_status mjp_probe_exchange(mjp_plan* p, int32_t rounds, double* us_per_round_h, mjp_stream_t stream) {
+    int32_t jumps = 0;
+    return mjp_probe_exchange2(p, rounds, us_per_round_h, &jumps, stream);
+}
+
+extern "C" mjp_status mjp_probe_exchange2(mjp_plan* p, int32_t rounds, double* us_per_round_h, int32_t* jumps_h,
+                                          mjp_stream_t stream) {
     clear_error();
-    MJP_CHECK(p && us_per_round_h, MJP_E_INVALID_ARG, "null argument");
+    MJP_CHECK(p && us_per_round_h && jumps_h, MJP_E_INVALID_ARG, "null argument");
     MJP_CHECK(rounds >= 1 && rounds <= 1000000, MJP_E_INVALID_ARG, "rounds must be in [1, 10^6]");
     DeviceGuard guard(p->device);
     float ms = 0.f;
-    const mjp_status s = probe_exchange(p, rounds, reinterpret_cast<hipStream_t>(stream), &ms);
+    int jumps = 0;
+    const mjp_status s = probe_exchange(p, rounds, reinterpret_cast<hipStream_t>(stream), &ms, &jumps);
     if (s) return s;
     *us_per_round_h = 1e3 * (double)ms / rounds;
+    *jumps_h = jumps;
     return MJP_OK;
 }
 

@@ -1141,6 +1141,52 @@ __global__ __launch_bounds__(kPThreads) void k_persistent_mj(PersistArgs a) {
     }
 }
 
+// Exchange floor of the tiled sweep (a measurement aid): `rounds` rounds of
+// exactly its per-round communication with no arithmetic -- the ring loads
+// from the exchange buffer into LDS, a workgroup barrier, the own rows'
+// stores, the neighbour synchronisation -- on the same table and launch.
+template <int S>
+__global__ __launch_bounds__(kPThreads) void k_exchange_probe_mj(PersistArgs a, int rounds) {
+    constexpr int R = kMJR;
+    constexpr int kMJLoad = mj_load_cap(S), kMJX = mj_x_cap(S);
+    extern __shared__ __align__(16) char mjlds[];
+    float* X0 = reinterpret_cast<float*>(mjlds);
+    int32_t* lpos = reinterpret_cast<int32_t*>(X0 + kMJX);
+    const int G = a.G;
+    const int g = logical_block(G);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int32_t* hd = a.p2 + (size_t)kMJHdr * g;
+    const int n0 = hd[0], nl = hd[S] - n0;
+    const int wlo = hd[S + 1], whi = hd[S + 2];
+    const int32_t* pos = a.p2 + hd[S + 5];
+    for (int h = tid; h < kMJLoad; h += kPThreads) lpos[h] = h < nl ? pos[h] : 0;
+    for (int i = tid; i < kMJX; i += kPThreads) X0[i] = 0.f;
+    __syncthreads();
+    const __amdgpu_buffer_rsrc_t r_buf0 = iter_rsrc(a.buf0, (int64_t)G * kMJOwn),
+                                 r_buf1 = iter_rsrc(a.buf1, (int64_t)G * kMJOwn);
+    const uint32_t pbase = 4u * (uint32_t)(g * kMJOwn);
+    for (int q = 0; q < rounds; ++q) {
+        const __amdgpu_buffer_rsrc_t src = (q & 1) ? r_buf0 : r_buf1;
+        const __amdgpu_buffer_rsrc_t dst = (q & 1) ? r_buf1 : r_buf0;
+        constexpr int kU = (kMJLoad + kPThreads - 1) / kPThreads;
+        float t[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) t[u] = ld_iter<true>(src, 4u * (uint32_t)lpos[min(tid + u * kPThreads, kMJLoad - 1)]);
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int h = tid + u * kPThreads;
+            if (h < nl) X0[n0 + h] = t[u];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const int li = (wave * R + i) * 64 + lane;
+            if (li < n0) st_iter<true>(dst, pbase + 4u * (uint32_t)li, X0[li]);
+        }
+        if (!neighbour_sync<true>(a.wflag, wlo, whi, (unsigned)((q + 1) * S), g, a.flags, a.timeout_ticks)) return;
+    }
+}
+
 // Exchange floor of the two-jump sweep (a measurement aid, not part of the
 // method): `rounds` rounds of exactly its per-round communication with no
 // arithmetic.  Each round: load the iterate on E2 outside the own rows from
@@ -1992,9 +2038,13 @@ mjp_status launch_persistent(mjp_plan* p, const PersistCfg& cfg, const float* rh
 // Times `rounds` exchange-only rounds on the two-jump sweep's launch
 // configuration for this plan (HIP events on st); false if the plan's sweep
 // does not run the two-jump kernel.
-mjp_status probe_exchange(mjp_plan* p, int rounds, hipStream_t st, float* ms_out) {
+mjp_status probe_exchange(mjp_plan* p, int rounds, hipStream_t st, float* ms_out, int* jumps_out) {
     PersistCfg cfg;
-    MJP_CHECK(persistent2_fits(p, 1, cfg), MJP_E_UNSUPPORTED, "the plan's sweep does not use the two-jump kernel");
+    const bool multi = (p->opts.variant == MJP_VARIANT_AUTO || p->opts.variant == MJP_VARIANT_PERSISTENT) &&
+                       persistent_mj_fits(p, 1, cfg);
+    MJP_CHECK(multi || persistent2_fits(p, 1, cfg), MJP_E_UNSUPPORTED,
+              "the plan's sweep synchronises every jump (no two-jump or tiled kernel)");
+    *jumps_out = cfg.jumps;
     const int64_t n = p->n;
     // the multi-jump kernel's exchange buffers hold kMJOwn rows per workgroup
     const int64_t nbuf = cfg.jumps >= 4 ? std::max<int64_t>(n, (int64_t)cfg.G * kMJOwn) : n;
@@ -2010,15 +2060,18 @@ mjp_status probe_exchange(mjp_plan* p, int rounds, hipStream_t st, float* ms_out
     a.buf1 = p->rho[1].as<float>();
     a.bar = bar;
     a.wflag = bar + kBarWords;
-    a.p2 = p->p2tab.as<int32_t>();
+    a.p2 = multi ? p->mjtab.as<int32_t>() : p->p2tab.as<int32_t>();
     a.flags = reinterpret_cast<unsigned*>(p->scal.as<double>() + S_FLAGS);
     a.n = n;
     a.G = cfg.G;
     int khz = 0;
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, p->device) != hipSuccess || khz <= 0) khz = 100000;
     a.timeout_ticks = (uint64_t)khz * 1000ull * 2ull;
-    const void* fn = reinterpret_cast<const void*>(k_exchange_probe<false>);
-    const size_t lds = sizeof(float) * kP2X2;
+    const void* fn = !multi ? reinterpret_cast<const void*>(k_exchange_probe<false>)
+                     : cfg.jumps == 8 ? reinterpret_cast<const void*>(k_exchange_probe_mj<8>)
+                                      : reinterpret_cast<const void*>(k_exchange_probe_mj<4>);
+    const size_t lds = !multi ? sizeof(float) * kP2X2
+                              : sizeof(float) * (size_t)mj_x_cap(cfg.jumps) + sizeof(int32_t) * (size_t)mj_load_cap(cfg.jumps);
     MJP_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     const int nzero = kBarWords + 32 * cfg.G;
     hipEvent_t e0, e1;

@@ -183,7 +183,9 @@ bool persistent2_fits(mjp_plan* p, int max_open, PersistCfg& cfg);
 // the tiled kernel with eight (else four) jumps per synchronisation
 // (grid-structured operators of width <= 5); builds and caches its tables
 bool persistent_mj_fits(mjp_plan* p, int max_open, PersistCfg& cfg);
-mjp_status probe_exchange(mjp_plan* p, int rounds, hipStream_t st, float* ms_out);
+// times `rounds` exchange-only rounds of the plan's two-jump or tiled sweep;
+// *jumps_out: the jumps per synchronisation of that sweep
+mjp_status probe_exchange(mjp_plan* p, int rounds, hipStream_t st, float* ms_out, int* jumps_out);
 mjp_status launch_persistent(mjp_plan* p, const PersistCfg& cfg, const float* rho0, const AllTimes& at,
                              const std::vector<int>& slot, float* out, hipStream_t st);
 

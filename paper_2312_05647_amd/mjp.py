@@ -138,6 +138,7 @@ _SIGS = [
     ("mjp_expv", ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, _P, _P]),
     ("mjp_expv_batched", ctypes.c_int, [ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P]),
     ("mjp_probe_exchange", ctypes.c_int, [_P, ctypes.c_int32, _P, _P]),
+    ("mjp_probe_exchange2", ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P]),
     ("mjp_loglik", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P]),
     ("mjp_loglik_set_kernel", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32]),
     ("mjp_loglik_cluster_config", ctypes.c_int, [_P, _P, _P, _P, _P]),
@@ -325,6 +326,14 @@ def mjp_probe_exchange(plan: int, rounds: int, stream=None) -> float:
     us = ctypes.c_double()
     _check(lib().mjp_probe_exchange(plan, rounds, ctypes.byref(us), _stream(stream)))
     return us.value
+
+
+def mjp_probe_exchange2(plan, rounds: int, stream=None):
+    """(microseconds per round, jumps per round) of the plan's sweep's exchange floor."""
+    us = ctypes.c_double()
+    j = ctypes.c_int32()
+    _check(lib().mjp_probe_exchange2(plan, rounds, ctypes.byref(us), ctypes.byref(j), _stream(stream)))
+    return us.value, j.value
 
 
 def _row_ptrs(x, B):

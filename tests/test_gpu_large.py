@@ -175,3 +175,32 @@ def test_exchange_probe_is_a_floor():
         assert 0.2 < floor < per_round
     finally:
         mjp.mjp_plan_destroy(plan)
+
+
+def test_tiled_exchange_probe_is_a_floor():
+    """mjp_probe_exchange2 on the tiled sweep's launch and tables (eight jumps
+    per round at this size): the exchange alone must take less per round
+    than a solve's rounds do."""
+    model = mjp.make_model(mjp.MJP_MODEL_CASCADE2, [200.0, 1.0, 0.5, 0.5], [1000, 1000])
+    plan = mjp.mjp_plan_create_stencil(model)
+    try:
+        r0 = torch.zeros(10 ** 6, device="cuda")
+        r0[0] = 1.0
+        out = torch.empty((1, 10 ** 6), device="cuda")
+        info = mjp.mjp_expv(plan, r0, [1.0], out, info=True)[0]
+        assert info["path"] == mjp.MJP_PATH_PERSISTENT_MULTIJUMP
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        mjp.mjp_expv(plan, r0, [1.0], out)
+        ev1.record()
+        torch.cuda.synchronize()
+        _, jumps = mjp.mjp_probe_exchange2(plan, 10)
+        assert jumps == 8
+        rounds = -(-info["K"] // jumps)
+        per_round = ev0.elapsed_time(ev1) * 1e3 / rounds
+        floor, _ = mjp.mjp_probe_exchange2(plan, rounds)
+        print(f"[gpu] tiled exchange floor {floor:.2f} us per round, solve {per_round:.2f} us per round",
+              file=sys.stderr)
+        assert 0.2 < floor < per_round
+    finally:
+        mjp.mjp_plan_destroy(plan)
