@@ -139,6 +139,45 @@ __device__ __forceinline__ bool neighbour_sync(unsigned* wflag, int lo, int hi, 
     return __builtin_amdgcn_readfirstlane(aborted) == 0;  // uniform: every thread read the same word
 }
 
+// neighbour_sync over an explicit set: lane l < nn of wave 0 waits for
+// workgroup nb[l] (the tiled sweep: the workgroups whose rows I read and
+// those that read mine, eight for an interior tile).
+__device__ __forceinline__ bool neighbour_sync_set(unsigned* wflag, const int32_t* nb, int nn, unsigned k, int g,
+                                                   unsigned* flags, uint64_t timeout_ticks) {
+    __shared__ int aborted;
+    drain_wave<true>();
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    if (threadIdx.x < 64) {
+        if (lane == 0) {
+            aborted = 0;
+            __hip_atomic_store(&wflag[g * 32], k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        bool bad = false;
+        if (lane < nn) {
+            const int h = nb[lane];
+            const uint64_t t0 = wall_clock64();
+            unsigned spins = 0;
+            while (__hip_atomic_load(&wflag[h * 32], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < k) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins % kAbortCheckEvery != 0) continue;
+                if (__hip_atomic_load(flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kFlagBarrierTimeout) {
+                    bad = true;
+                    break;
+                }
+                if (wall_clock64() - t0 > timeout_ticks) {
+                    __hip_atomic_fetch_or(flags, kFlagBarrierTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    bad = true;
+                    break;
+                }
+            }
+        }
+        if (bad) aborted = 1;
+    }
+    __syncthreads();
+    return __builtin_amdgcn_readfirstlane(aborted) == 0;  // uniform: every thread read the same word
+}
+
 __device__ __forceinline__ double block_sum_f64(double v, double* red) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -863,8 +902,11 @@ __global__ __launch_bounds__(kPThreads) void k_persistent2(PersistArgs a) {
 // host-built table gives each ring row's position there.
 constexpr int kMJR = 8;                         // own rows per thread
 constexpr int kMJOwn = kPWaves * kMJR * 64;     // own rows of a workgroup (4096)
-constexpr int kMJHdr = 16;                      // per-workgroup header words
-// header: n_0 .. n_S, wlo, whi, own (gid, lcol), ring (gid, lcol), positions
+constexpr int kMJHdr = 32;                      // per-workgroup header words
+constexpr int kMJNb = 16;                       // neighbours a workgroup waits for, at most
+// header: [0..S] n_0 .. n_S, [9] neighbour count, [10] own block (gid, lcol),
+// [11] ring block (gid, lcol), [12] positions, [16..31] neighbours
+enum { kMJHCount = 9, kMJHOwn = 10, kMJHRing = 11, kMJHPos = 12, kMJHNb = 16 };
 // rows of rings 1..S-1 and of rings 1..S a workgroup holds, at most (63 x 63
 // tiles: 792 / 1072 for S = 4, 1960 / 2272 for S = 8)
 constexpr int mj_halo_cap(int S) { return S == 4 ? 1024 : 2048; }
@@ -897,12 +939,12 @@ __global__ __launch_bounds__(kPThreads) void k_persistent_mj(PersistArgs a) {
 #pragma unroll
     for (int j = 0; j <= S; ++j) nS[j] = hd[j];
     const int n0 = nS[0], nh = nS[S - 1] - n0, nl = nS[S] - n0;
-    const int wlo = hd[S + 1], whi = hd[S + 2];
-    const int32_t* own_gid = a.p2 + hd[S + 3];
+    const int nn = hd[kMJHCount];
+    const int32_t* own_gid = a.p2 + hd[kMJHOwn];
     const int32_t* own_lcol = own_gid + n0;
-    const int32_t* ring_gid = a.p2 + hd[S + 4];
+    const int32_t* ring_gid = a.p2 + hd[kMJHRing];
     const int32_t* ring_lcol = ring_gid + nh;
-    const int32_t* pos = a.p2 + hd[S + 5];
+    const int32_t* pos = a.p2 + hd[kMJHPos];
     auto li = [&](int i) { return (wave * R + i) * 64 + lane; };
     auto live = [&](int i) { return li(i) < n0; };
 
@@ -1131,7 +1173,7 @@ __global__ __launch_bounds__(kPThreads) void k_persistent_mj(PersistArgs a) {
             last_mass = sum_partials(pm, G, red);
             scale = (last_mass > 0.0 && mass0 > 0.0) ? mass0 / last_mass : 1.0;
         } else {
-            if (!neighbour_sync<true>(a.wflag, wlo, whi, (unsigned)(k + S), g, a.flags, a.timeout_ticks)) return;
+            if (!neighbour_sync_set(a.wflag, hd + kMJHNb, nn, (unsigned)(k + S), g, a.flags, a.timeout_ticks)) return;
             scale = 1.0;
         }
     }
@@ -1157,8 +1199,8 @@ __global__ __launch_bounds__(kPThreads) void k_exchange_probe_mj(PersistArgs a, 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int32_t* hd = a.p2 + (size_t)kMJHdr * g;
     const int n0 = hd[0], nl = hd[S] - n0;
-    const int wlo = hd[S + 1], whi = hd[S + 2];
-    const int32_t* pos = a.p2 + hd[S + 5];
+    const int nn = hd[kMJHCount];
+    const int32_t* pos = a.p2 + hd[kMJHPos];
     for (int h = tid; h < kMJLoad; h += kPThreads) lpos[h] = h < nl ? pos[h] : 0;
     for (int i = tid; i < kMJX; i += kPThreads) X0[i] = 0.f;
     __syncthreads();
@@ -1183,7 +1225,7 @@ __global__ __launch_bounds__(kPThreads) void k_exchange_probe_mj(PersistArgs a, 
             const int li = (wave * R + i) * 64 + lane;
             if (li < n0) st_iter<true>(dst, pbase + 4u * (uint32_t)li, X0[li]);
         }
-        if (!neighbour_sync<true>(a.wflag, wlo, whi, (unsigned)((q + 1) * S), g, a.flags, a.timeout_ticks)) return;
+        if (!neighbour_sync_set(a.wflag, hd + kMJHNb, nn, (unsigned)((q + 1) * S), g, a.flags, a.timeout_ticks)) return;
     }
 }
 
@@ -1731,14 +1773,14 @@ static bool build_mj_table(mjp_plan* p, int W, int S, int cap, std::vector<int32
         // rings 1..S: exchange positions
         int32_t* hd = tab.data() + (size_t)kMJHdr * g;
         for (int j = 0; j <= S; ++j) hd[j] = sizes[g][j];
-        hd[S + 3] = (int32_t)tab.size();
+        hd[kMJHOwn] = (int32_t)tab.size();
         for (int i = 0; i < n0; ++i) tab.push_back(L[(size_t)i]);
         for (int i = 0; i < n0; ++i) {
             hr.cols(L[(size_t)i], cbuf.data());
             for (int e = 0; e < W; ++e) tab.push_back(loc.at(cbuf[e]));
         }
         hd = tab.data() + (size_t)kMJHdr * g;
-        hd[S + 4] = (int32_t)tab.size();
+        hd[kMJHRing] = (int32_t)tab.size();
         const int nh = sizes[g][S - 1] - n0;
         for (int h = 0; h < nh; ++h) tab.push_back(L[(size_t)(n0 + h)]);
         for (int h = 0; h < nh; ++h) {
@@ -1746,7 +1788,7 @@ static bool build_mj_table(mjp_plan* p, int W, int S, int cap, std::vector<int32
             for (int e = 0; e < W; ++e) tab.push_back(loc.at(cbuf[e]));
         }
         hd = tab.data() + (size_t)kMJHdr * g;
-        hd[S + 5] = (int32_t)tab.size();
+        hd[kMJHPos] = (int32_t)tab.size();
         for (int32_t i = n0; i < sizes[g][S]; ++i) {
             int64_t li;
             const int o = owner_of(L[(size_t)i], li);
@@ -1754,20 +1796,21 @@ static bool build_mj_table(mjp_plan* p, int W, int S, int cap, std::vector<int32
         }
         if (tab.size() >= (size_t)INT32_MAX) return false;
     }
-    // neighbour intervals: whom I read and who reads me
-    std::vector<int> lo(G), hi(G);
-    for (int g = 0; g < G; ++g) lo[g] = hi[g] = g;
+    // neighbour sets: whom I read and who reads me
+    std::vector<std::vector<int32_t>> nb(G);
     for (int g = 0; g < G; ++g)
-        for (int o : ring_owner[g]) {
-            lo[g] = std::min(lo[g], o);
-            hi[g] = std::max(hi[g], o);
-            lo[o] = std::min(lo[o], g);
-            hi[o] = std::max(hi[o], g);
-        }
+        for (int o : ring_owner[g])
+            if (o != g) {
+                nb[g].push_back(o);
+                nb[o].push_back(g);
+            }
     for (int g = 0; g < G; ++g) {
-        if (hi[g] - lo[g] > 63) return false;
-        tab[(size_t)kMJHdr * g + S + 1] = lo[g];
-        tab[(size_t)kMJHdr * g + S + 2] = hi[g];
+        std::sort(nb[g].begin(), nb[g].end());
+        nb[g].erase(std::unique(nb[g].begin(), nb[g].end()), nb[g].end());
+        if ((int)nb[g].size() > kMJNb) return false;
+        int32_t* hd = tab.data() + (size_t)kMJHdr * g;
+        hd[kMJHCount] = (int32_t)nb[g].size();
+        for (size_t i = 0; i < nb[g].size(); ++i) hd[kMJHNb + i] = nb[g][i];
     }
     G_out = G;
     return true;
