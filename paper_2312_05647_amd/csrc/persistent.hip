@@ -916,7 +916,11 @@ constexpr int mj_x_cap(int S) { return kMJOwn + mj_load_cap(S); }
 template <int W, int S>
 constexpr size_t mj_lds_bytes() {
     return sizeof(float) * 2 * mj_x_cap(S) + sizeof(uint2) * (size_t)mj_halo_cap(S) * W +
-           sizeof(float) * mj_halo_cap(S) + sizeof(int32_t) * mj_load_cap(S);
+           sizeof(float) * mj_halo_cap(S) + (sizeof(int32_t) + sizeof(uint16_t)) * mj_load_cap(S);
+}
+// the exchange probe's LDS: E_S's values and the load lists
+constexpr size_t mj_probe_lds_bytes(int S) {
+    return sizeof(float) * (size_t)mj_x_cap(S) + (sizeof(int32_t) + sizeof(uint16_t)) * (size_t)mj_load_cap(S);
 }
 
 template <int W, bool CSR, int S>
@@ -928,7 +932,10 @@ __global__ __launch_bounds__(kPThreads) void k_persistent_mj(PersistArgs a) {
     float* X1 = X0 + kMJX;                                   // x_{k+j} for odd j
     uint2* hent = reinterpret_cast<uint2*>(X1 + kMJX);      // ring rows' entries, entry j of row h at [j][h]
     float* hlo = reinterpret_cast<float*>(hent + (size_t)kMJHalo * W);
-    int32_t* lpos = reinterpret_cast<int32_t*>(hlo + kMJHalo);  // exchange positions of rings 1..S
+    // rings 1..S in exchange-buffer order (coalesced loads): position, and
+    // the row's place after the own rows
+    int32_t* lpos = reinterpret_cast<int32_t*>(hlo + kMJHalo);
+    uint16_t* lloc = reinterpret_cast<uint16_t*>(lpos + kMJLoad);
     __shared__ double red[kPWaves + 1];
     const int G = a.G;
     const int g = logical_block(G);
@@ -974,7 +981,10 @@ __global__ __launch_bounds__(kPThreads) void k_persistent_mj(PersistArgs a) {
             hent[j * kMJHalo + h] = make_uint2(4u * (uint32_t)ring_lcol[(size_t)h * W + j], __builtin_bit_cast(uint32_t, vv[j]));
         hlo[h] = lo;
     }
-    for (int h = tid; h < kMJLoad; h += kPThreads) lpos[h] = h < nl ? pos[h] : 0;
+    for (int h = tid; h < kMJLoad; h += kPThreads) {
+        lpos[h] = h < nl ? pos[h] : 0;
+        lloc[h] = h < nl ? (uint16_t)pos[nl + h] : (uint16_t)0;
+    }
 
     // ---- k = 0: own rows of x_0 into LDS and into the exchange buffer the
     // first round reads (buf1), then the initial mass
@@ -1091,7 +1101,7 @@ __global__ __launch_bounds__(kPThreads) void k_persistent_mj(PersistArgs a) {
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
                 const int h = tid + u * kPThreads;
-                if (h < nl) X0[n0 + h] = t[u];
+                if (h < nl) X0[n0 + lloc[h]] = t[u];
             }
         }
         __syncthreads();
@@ -1194,6 +1204,7 @@ __global__ __launch_bounds__(kPThreads) void k_exchange_probe_mj(PersistArgs a, 
     extern __shared__ __align__(16) char mjlds[];
     float* X0 = reinterpret_cast<float*>(mjlds);
     int32_t* lpos = reinterpret_cast<int32_t*>(X0 + kMJX);
+    uint16_t* lloc = reinterpret_cast<uint16_t*>(lpos + kMJLoad);
     const int G = a.G;
     const int g = logical_block(G);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -1201,7 +1212,10 @@ __global__ __launch_bounds__(kPThreads) void k_exchange_probe_mj(PersistArgs a, 
     const int n0 = hd[0], nl = hd[S] - n0;
     const int nn = hd[kMJHCount];
     const int32_t* pos = a.p2 + hd[kMJHPos];
-    for (int h = tid; h < kMJLoad; h += kPThreads) lpos[h] = h < nl ? pos[h] : 0;
+    for (int h = tid; h < kMJLoad; h += kPThreads) {
+        lpos[h] = h < nl ? pos[h] : 0;
+        lloc[h] = h < nl ? (uint16_t)pos[nl + h] : (uint16_t)0;
+    }
     for (int i = tid; i < kMJX; i += kPThreads) X0[i] = 0.f;
     __syncthreads();
     const __amdgpu_buffer_rsrc_t r_buf0 = iter_rsrc(a.buf0, (int64_t)G * kMJOwn),
@@ -1217,7 +1231,7 @@ __global__ __launch_bounds__(kPThreads) void k_exchange_probe_mj(PersistArgs a, 
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
             const int h = tid + u * kPThreads;
-            if (h < nl) X0[n0 + h] = t[u];
+            if (h < nl) X0[n0 + lloc[h]] = t[u];
         }
         __syncthreads();
 #pragma unroll
@@ -1789,10 +1803,16 @@ static bool build_mj_table(mjp_plan* p, int W, int S, int cap, std::vector<int32
         }
         hd = tab.data() + (size_t)kMJHdr * g;
         hd[kMJHPos] = (int32_t)tab.size();
-        for (int32_t i = n0; i < sizes[g][S]; ++i) {
-            int64_t li;
-            const int o = owner_of(L[(size_t)i], li);
-            tab.push_back((int32_t)((int64_t)o * kMJOwn + li));
+        {  // rings 1..S by exchange position: positions, then their places after the own rows
+            std::vector<std::pair<int32_t, int32_t>> pl;
+            for (int32_t i = n0; i < sizes[g][S]; ++i) {
+                int64_t li;
+                const int o = owner_of(L[(size_t)i], li);
+                pl.emplace_back((int32_t)((int64_t)o * kMJOwn + li), i - n0);
+            }
+            std::sort(pl.begin(), pl.end());
+            for (const auto& e : pl) tab.push_back(e.first);
+            for (const auto& e : pl) tab.push_back(e.second);
         }
         if (tab.size() >= (size_t)INT32_MAX) return false;
     }
@@ -2113,8 +2133,7 @@ mjp_status probe_exchange(mjp_plan* p, int rounds, hipStream_t st, float* ms_out
     const void* fn = !multi ? reinterpret_cast<const void*>(k_exchange_probe<false>)
                      : cfg.jumps == 8 ? reinterpret_cast<const void*>(k_exchange_probe_mj<8>)
                                       : reinterpret_cast<const void*>(k_exchange_probe_mj<4>);
-    const size_t lds = !multi ? sizeof(float) * kP2X2
-                              : sizeof(float) * (size_t)mj_x_cap(cfg.jumps) + sizeof(int32_t) * (size_t)mj_load_cap(cfg.jumps);
+    const size_t lds = !multi ? sizeof(float) * kP2X2 : mj_probe_lds_bytes(cfg.jumps);
     MJP_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     const int nzero = kBarWords + 32 * cfg.G;
     hipEvent_t e0, e1;
