@@ -152,7 +152,7 @@ enum { MJP_PATH_STEPWISE = 1,            /* one launch per jump */
        MJP_PATH_PERSISTENT_FENCED = 3,   /* the same, fenced protocol */
        MJP_PATH_PERSISTENT_TWOJUMP = 4,  /* one launch, two jumps per synchronisation */
        MJP_PATH_BATCHED_ITEM = 5,        /* mjp_expv_batched: one workgroup ran the item */
-       MJP_PATH_PERSISTENT_MULTIJUMP = 6 };/* one launch, four jumps per synchronisation on tiles */
+       MJP_PATH_PERSISTENT_MULTIJUMP = 6 };/* one launch, eight (else four) jumps per synchronisation on tiles */
 
 /* ------------------------------------------------------------ operators */
 
@@ -499,7 +499,11 @@ void       mjp_surrogate_destroy(mjp_surrogate* s);
 
 /* Mean-squared-error training with Adam on x_d [n x in_dim] FP32 and targets
  * y_d [n] FP32 (device).  loss_h [epochs] receives the mean training loss of
- * each epoch (the call is synchronous when loss_h is not NULL). */
+ * each epoch (the call is synchronous when loss_h is not NULL).  For width
+ * <= 256 a step is three launches (forward, loss and backward-data products
+ * of 16 rows per workgroup with activations in LDS; every layer's
+ * weight-gradient partials; Adam); wider nets run one launch per product.
+ * Both are deterministic: the same seed and data give the same parameters. */
 mjp_status mjp_surrogate_train(mjp_surrogate* s, const float* x_d, const float* y_d, int32_t n,
                                const mjp_train_cfg* cfg, float* loss_h, mjp_stream_t stream);
 

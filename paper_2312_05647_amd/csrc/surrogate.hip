@@ -2,8 +2,10 @@
 // in -> width -> ... -> width -> 1, exact (erf) GELU between Linear layers,
 // FP32 master parameters, BF16 operands on the matrix cores.
 //
-// Every Linear layer, forward and backward, runs through one MFMA GEMM
-// kernel (k_gemm): a 64x64 output tile per workgroup, four waves of 32x32,
+// Nets up to 256 wide train in three launches per step (k_mlp_fused,
+// k_wgrad_all, k_adam; see the fused step below).  Wider nets, and the
+// weight gradients of both, run through one MFMA GEMM kernel body
+// (gemm_tile): a 64x64 output tile per workgroup, four waves of 32x32,
 // FP32 accumulation.  The reduction runs in chunks of up to 256 (one
 // chunk for the 256-wide layers): each thread issues all sixteen 16-byte
 // loads of a chunk at once, and the chunk is staged whole in LDS in the [row][k] order the
@@ -137,14 +139,14 @@ __device__ __forceinline__ void tile_store(const uint4 (&v)[8], uint16_t* __rest
     }
 }
 
+// One 64x64 output tile (bx, by) of split bz.
 template <bool TA, bool TB, int EPI>
-__global__ __launch_bounds__(kGT) void k_gemm(GemmArgs g) {
-    extern __shared__ __attribute__((aligned(16))) uint16_t gemm_lds[];
+__device__ __forceinline__ void gemm_tile(const GemmArgs& g, int bx, int by, int bz, uint16_t* gemm_lds) {
     uint16_t* As = gemm_lds;               // [kTM][kLDK]
     uint16_t* Bs = gemm_lds + kTM * kLDK;  // [kTN][kLDK]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int m0 = blockIdx.y * kTM, n0 = blockIdx.x * kTN;
-    const int kbeg = blockIdx.z * g.k_per_split;
+    const int m0 = by * kTM, n0 = bx * kTN;
+    const int kbeg = bz * g.k_per_split;
     const int kend = min(g.K, kbeg + g.k_per_split);
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
     floatx4 acc[2][2];
@@ -224,7 +226,7 @@ __global__ __launch_bounds__(kGT) void k_gemm(GemmArgs g) {
                     g.H[at] = f2bf(d);
                     csum[j] += d;
                 } else {
-                    g.P[((size_t)blockIdx.z * g.M + row) * g.N + col] = v;
+                    g.P[((size_t)bz * g.M + row) * g.N + col] = v;
                 }
             }
     if (EPI == EPI_BWD_DATA) {
@@ -240,8 +242,14 @@ __global__ __launch_bounds__(kGT) void k_gemm(GemmArgs g) {
             if (lane < 16) red[(wm >> 5) * 64 + wn + j * 16 + lane] = t;
         }
         __syncthreads();
-        if (tid < 64) g.bpart[(size_t)blockIdx.y * g.N + n0 + tid] = red[tid] + red[64 + tid];
+        if (tid < 64) g.bpart[(size_t)by * g.N + n0 + tid] = red[tid] + red[64 + tid];
     }
+}
+
+template <bool TA, bool TB, int EPI>
+__global__ __launch_bounds__(kGT) void k_gemm(GemmArgs g) {
+    extern __shared__ __attribute__((aligned(16))) uint16_t gemm_lds[];
+    gemm_tile<TA, TB, EPI>(g, blockIdx.x, blockIdx.y, blockIdx.z, gemm_lds);
 }
 
 // X rows (optionally permuted) into the padded BF16 input, targets alongside.
@@ -306,6 +314,14 @@ __global__ void k_zero_u32(uint32_t* __restrict__ p, size_t n) {
     if (i < n) p[i] = 0u;
 }
 
+// MFMA B-operand fragment order of an N x K matrix (N output columns, K
+// reductions; both multiples of 32): the 16 x 32 block (n/16, k/32) is 512
+// consecutive values, lane (n mod 16) + 16 ((k mod 32) / 8) holding its eight
+// consecutive k, so a wave loads one block as one contiguous 1 KB run.
+__host__ __device__ __forceinline__ size_t frag_index(int n, int k, int K) {
+    return ((size_t)(n >> 4) * (K >> 5) + (k >> 5)) * 512 + (size_t)(((n & 15) + 16 * ((k & 31) >> 3)) * 8 + (k & 7));
+}
+
 struct LayerDev {
     int in, out, kpad, npad;
     int64_t woff;      // offset of W[out][in] in the packed parameters (bias follows)
@@ -313,6 +329,8 @@ struct LayerDev {
     const float* bp;   // bias-gradient partials [nbp][bps] (column c = output c)
     int nbp, bps;
     uint16_t* Wbf;     // BF16 weights [npad][kpad]
+    uint16_t* WbfF;    // the same in fragment order, N = npad (outputs), K = kpad (the fused forward operand)
+    uint16_t* WbfB;    // ... and transposed, N = kpad, K = npad (the fused backward operand)
 };
 
 struct AdamArgs {
@@ -356,12 +374,12 @@ __global__ void k_adam(AdamArgs a) {
     } else {
         const int c = (int)(q - nw);
         g = 0.f;
-        for (int k0 = 0; k0 < d.nbp; k0 += 8) {
-            float x[8];
+        for (int k0 = 0; k0 < d.nbp; k0 += 32) {  // up to 256 partials: 32 loads in flight
+            float x[32];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) x[u] = d.bp[(size_t)(k0 + u < d.nbp ? k0 + u : k0) * d.bps + c];
+            for (int u = 0; u < 32; ++u) x[u] = d.bp[(size_t)(k0 + u < d.nbp ? k0 + u : k0) * d.bps + c];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) g += k0 + u < d.nbp ? x[u] : 0.f;
+            for (int u = 0; u < 32; ++u) g += k0 + u < d.nbp ? x[u] : 0.f;
         }
     }
     if (a.grad_out) {
@@ -376,7 +394,12 @@ __global__ void k_adam(AdamArgs a) {
     float w = a.master[p];
     w -= a.lr * (mh / (sqrtf(vh) + a.eps) + a.wd * w);
     a.master[p] = w;
-    if (o >= 0) d.Wbf[(size_t)o * d.kpad + i] = f2bf(w);
+    if (o >= 0) {
+        const uint16_t h = f2bf(w);
+        d.Wbf[(size_t)o * d.kpad + i] = h;
+        d.WbfF[frag_index(o, i, d.kpad)] = h;
+        d.WbfB[frag_index(i, o, d.npad)] = h;
+    }
 }
 
 // BF16 padded copies of all weights from the masters (after create/set/load).
@@ -389,13 +412,353 @@ __global__ void k_refresh_bf16(AdamArgs a) {
     const int64_t q = p - d.woff;
     if (q < (int64_t)d.out * d.in) {
         const int o = (int)(q / d.in), i = (int)(q - (int64_t)o * d.in);
-        d.Wbf[(size_t)o * d.kpad + i] = f2bf(a.master[p]);
+        const uint16_t h = f2bf(a.master[p]);
+        d.Wbf[(size_t)o * d.kpad + i] = h;
+        d.WbfF[frag_index(o, i, d.kpad)] = h;
+        d.WbfB[frag_index(i, o, d.npad)] = h;
     }
 }
 
 __global__ void k_copy_col0(const float* __restrict__ Y, int npad, int n, float* __restrict__ out) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b < n) out[b] = Y[(size_t)b * npad];
+}
+
+// ---- fused training step: one workgroup per 16 batch rows -------------
+//
+// For nets no wider than 256 a workgroup carries its rows through the whole
+// network: input gather, every hidden layer forward (pre-activations kept in
+// LDS for the backward pass), the output layer and the squared-error loss,
+// then the backward-data products down to the first layer's output
+// gradient.  Activations never leave LDS between layers; each layer's input
+// (forward) and output gradient (backward) is also written to global memory
+// in BF16 for the weight-gradient launch.  Wave w owns output column tiles w
+// and w + 8 (16 columns each) of every product and streams its slice of the
+// weights straight into registers as MFMA B operands -- no LDS staging, the
+// slice is private to the wave.  The forward products read W, the backward
+// ones W^T, both kept by the optimiser in B-operand fragment order
+// (frag_index), so each load of a wave is one contiguous 1 KB run.
+//
+// The next product's slice is loaded while the current one computes.  The
+// wave's memory counter covers loads and stores alike, and with both in
+// flight a wait for one load is a wait for everything, so each pass first
+// takes its own (already loaded) slice, then issues the next slice's loads,
+// then the MFMAs, and only then the global stores of the previous pass's
+// output: the stores are the youngest operations when the pass ends, and the
+// prefetch stays in flight across the MFMAs.
+constexpr int kFThreads = 512;    // eight waves
+constexpr int kFMaxW = 256;       // widest hidden layer: two column tiles per wave
+constexpr int kFMaxKS = kFMaxW / 32;
+constexpr int kFMinRows = 16;     // ... and at least (sizes the per-workgroup partials)
+
+struct FusedArgs {
+    int L, width, in_dim, kpad0;
+    int n_valid, base;                // rows base .. base + n_valid - 1 of x (and y) are real
+    const float* x;                   // [n][in_dim]
+    const float* y;                   // targets [n] (training)
+    const int32_t* perm;              // optional row permutation
+    const float* master;              // FP32 parameters (the biases are read from here)
+    int64_t boff[kMaxLayers];         // offset of layer l's bias in master
+    const uint16_t* W[kMaxLayers];    // BF16 [npad_l][kpad_l]
+    const uint16_t* WF[kMaxLayers];   // the same, B-operand fragment order (N = npad_l, K = kpad_l)
+    const uint16_t* WB[kMaxLayers];   // transposed, fragment order (N = kpad_l, K = npad_l)
+    uint16_t* X[kMaxLayers];          // layer inputs [Bpad][kpad_l] (training)
+    uint16_t* dZ[kMaxLayers];         // output gradients [Bpad][npad_l] (training)
+    float* bpart[kMaxLayers];         // bias-gradient partials [Bpad / MT][npad_l] (training)
+    double* lossp;                    // squared-error partials [Bpad / MT] (training)
+    float* yout;                      // inference: outputs of the n_valid rows
+};
+
+// LDS of the fused step at MT rows per workgroup: pre-activations of the
+// L - 1 hidden layers (FP32, training only), two BF16 row buffers
+// [MT][width + 8], the output layer's weights (FP32), and MT rows of loss
+// scratch.
+__host__ __device__ constexpr size_t fused_lds_bytes(bool train, int L, int width, int MT) {
+    return (train ? sizeof(float) * (size_t)(L - 1) * MT * width : 0) +
+           sizeof(uint16_t) * 2 * (size_t)MT * (width + 8) + sizeof(float) * (size_t)width +
+           (sizeof(double) + 3 * sizeof(float)) * (size_t)MT;
+}
+
+// keeps a register's load complete here (an empty use the compiler must wait for)
+__device__ __forceinline__ void take(const uint4& v) {
+    asm volatile("" ::"v"(v.x), "v"(v.y), "v"(v.z), "v"(v.w));
+}
+
+template <bool TRAIN, int MR>
+__global__ __launch_bounds__(kFThreads) void k_mlp_fused(FusedArgs a) {
+    constexpr int MT = 16 * MR;       // batch rows of the workgroup
+    extern __shared__ __attribute__((aligned(16))) char flds[];
+    const int L = a.L, W = a.width, P = W + 8, NT = W / 16;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int row0 = blockIdx.x * MT;
+    float* Zs = reinterpret_cast<float*>(flds);                                     // [L-1][MT][W]
+    uint16_t* Hb = reinterpret_cast<uint16_t*>(Zs + (TRAIN ? (L - 1) * MT * W : 0));  // [2][MT][P]
+    float* wl = reinterpret_cast<float*>(Hb + 2 * MT * P);                          // output weights [W]
+    double* se = reinterpret_cast<double*>(wl + W);                                 // squared errors [MT]
+    float* tg = reinterpret_cast<float*>(se + MT);                                  // targets [MT]
+    float* dyb = tg + MT;                                                           // BF16-rounded dy [MT]
+    float* dyf = dyb + MT;                                                          // dy [MT]
+
+    // input rows (BF16, zero padded to kpad0) into buffer 0 and, training, X[0]
+    for (int e = tid; e < MT * a.kpad0; e += kFThreads) {
+        const int r = e / a.kpad0, i = e - r * a.kpad0, b = row0 + r;
+        float v = 0.f;
+        if (b < a.n_valid && i < a.in_dim) {
+            const int src = a.perm ? a.perm[a.base + b] : a.base + b;
+            v = a.x[(size_t)src * a.in_dim + i];
+        }
+        const uint16_t h = f2bf(v);
+        Hb[r * P + i] = h;
+        if (TRAIN) a.X[0][(size_t)b * a.kpad0 + i] = h;
+    }
+    if (TRAIN && tid < MT) {
+        const int b = row0 + tid;
+        tg[tid] = b < a.n_valid ? a.y[a.perm ? a.perm[a.base + b] : a.base + b] : 0.f;
+    }
+    for (int c = tid; c < W; c += kFThreads) wl[c] = bf2f(a.W[L - 1][c]);
+    const float blast = a.master[a.boff[L - 1]];
+
+    // product p: forward layer p for p < L - 1, then backward through layer
+    // 2L - 3 - p (its W^T) for the training passes
+    auto geom = [&](int p, int& l, int& K, bool& fwd) {
+        fwd = p < L - 1;
+        l = fwd ? p : 2 * L - 3 - p;
+        K = (fwd && p == 0) ? a.kpad0 : W;
+    };
+    // Every load is issued unconditionally (a load under a branch leaves the
+    // compiler unsure which are still in flight, and it then waits for all):
+    // a tile past the layer's width reads its last tile again, a reduction
+    // step past K reads step 0 again, and neither is used.
+    auto wload = [&](int p, uint4 (&wr)[2][kFMaxKS], float (&br)[2]) {
+        int l, K;
+        bool fwd;
+        geom(p, l, K, fwd);
+        const uint16_t* M = fwd ? a.WF[l] : a.WB[l];
+        const int KS = K >> 5;
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const int tile = min(wave + 8 * t, NT - 1);
+            const uint16_t* q = M + (size_t)tile * KS * 512 + lane * 8;
+#pragma unroll
+            for (int ks = 0; ks < kFMaxKS; ++ks)
+                wr[t][ks] = *reinterpret_cast<const uint4*>(q + (ks < KS ? ks : 0) * 512);
+            br[t] = a.master[a.boff[l] + tile * 16 + (lane & 15)];  // used by the forward products only
+        }
+    };
+    auto wtake = [&](const uint4 (&wr)[2][kFMaxKS], const float (&br)[2]) {
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+#pragma unroll
+            for (int ks = 0; ks < kFMaxKS; ++ks) take(wr[t][ks]);
+            asm volatile("" ::"v"(br[t]));
+        }
+        asm volatile("" ::: "memory");  // the next slice's loads stay behind this wait
+    };
+    // MT rows of a buffer to global rows row0.. of dst (16-byte stores)
+    auto spill = [&](const uint16_t* from, uint16_t* dst) {
+        const int per = W / 8;
+        for (int e = tid; e < MT * per; e += kFThreads) {
+            const int r = e / per, c8 = (e - r * per) * 8;
+            *reinterpret_cast<uint4*>(dst + (size_t)(row0 + r) * W + c8) =
+                *reinterpret_cast<const uint4*>(from + r * P + c8);
+        }
+    };
+    uint16_t* pend = nullptr;  // global destination of the rows in the current input buffer
+    auto mpass = [&](int p, const uint4 (&wr)[2][kFMaxKS], const float (&br)[2]) {
+        int l, K;
+        bool fwd;
+        geom(p, l, K, fwd);
+        const uint16_t* Ain = Hb + (p & 1) * MT * P;
+        uint16_t* Hout = Hb + ((p + 1) & 1) * MT * P;
+        floatx4 acc[MR][2];
+#pragma unroll
+        for (int i = 0; i < MR; ++i)
+#pragma unroll
+            for (int t = 0; t < 2; ++t) acc[i][t] = floatx4{0.f, 0.f, 0.f, 0.f};
+        // reduction steps past K (the first layer's) multiply zeros
+#pragma unroll
+        for (int ks = 0; ks < kFMaxKS; ++ks) {
+            const bool on = ks * 32 < K;
+            bf16x8 av[MR];
+#pragma unroll
+            for (int i = 0; i < MR; ++i) {
+                const uint4 v = *reinterpret_cast<const uint4*>(Ain + (i * 16 + (lane & 15)) * P + ks * 32 + 8 * (lane >> 4));
+                av[i] = __builtin_bit_cast(bf16x8, on ? v : make_uint4(0u, 0u, 0u, 0u));
+            }
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int i = 0; i < MR; ++i)
+                    acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        av[i], __builtin_bit_cast(bf16x8, on ? wr[t][ks] : make_uint4(0u, 0u, 0u, 0u)), acc[i][t], 0,
+                        0, 0);
+        }
+        asm volatile("" ::: "memory");
+        if (TRAIN && pend) spill(Ain, pend);  // the previous pass's output, behind the MFMAs
+        // D layout: lane holds column (lane & 15) of a tile, rows 4 (lane >> 4) + r
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const int tile = wave + 8 * t;
+            if (tile >= NT) continue;
+            const int c = tile * 16 + (lane & 15);
+            if (fwd) {
+#pragma unroll
+                for (int i = 0; i < MR; ++i)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = i * 16 + 4 * (lane >> 4) + r;
+                        const float z = acc[i][t][r] + br[t];
+                        if (TRAIN) Zs[(l * MT + row) * W + c] = z;
+                        Hout[row * P + c] = f2bf(gelu(z));
+                    }
+            } else {
+                float cs = 0.f;
+#pragma unroll
+                for (int i = 0; i < MR; ++i)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = i * 16 + 4 * (lane >> 4) + r;
+                        const float d = acc[i][t][r] * gelu_grad(Zs[((l - 1) * MT + row) * W + c]);
+                        Hout[row * P + c] = f2bf(d);
+                        cs += d;
+                    }
+                cs += __shfl_xor(cs, 16, 64);
+                cs += __shfl_xor(cs, 32, 64);
+                if (lane < 16) a.bpart[l - 1][(size_t)blockIdx.x * W + c] = cs;
+            }
+        }
+        __syncthreads();
+        pend = TRAIN ? (fwd ? a.X[l + 1] : a.dZ[l - 1]) : nullptr;
+    };
+    // output layer (one column, VALU), loss and, training, the gradient
+    // through it into layer L - 2's output gradient
+    auto output_layer = [&]() {
+        constexpr int LPR = kFThreads / MT;  // lanes per row
+        uint16_t* Hin = Hb + ((L - 1) & 1) * MT * P;
+        const int r = tid / LPR, j = tid % LPR;
+        float sacc = 0.f;
+#pragma unroll
+        for (int u = 0; u < kFMaxW / LPR; ++u) {  // independent loads, one accumulation order
+            const int k = j + u * LPR;
+            const float hv = k < W ? bf2f(Hin[r * P + k]) : 0.f;
+            sacc = fmaf(hv, k < W ? wl[k] : 0.f, sacc);
+        }
+#pragma unroll
+        for (int m = LPR / 2; m > 0; m >>= 1) sacc += __shfl_xor(sacc, m, LPR);
+        const float yv = sacc + blast;
+        const bool real = row0 + r < a.n_valid;
+        if (!TRAIN) {
+            if (j == 0 && real) a.yout[row0 + r] = yv;
+            return;
+        }
+        if (j == 0) {
+            const float e = yv - tg[r];
+            const float d = real ? 2.f * e / (float)a.n_valid : 0.f;
+            const uint16_t db = f2bf(d);
+            se[r] = real ? (double)e * (double)e : 0.0;
+            dyf[r] = d;
+            dyb[r] = bf2f(db);
+            a.dZ[L - 1][(size_t)(row0 + r) * 64] = db;
+        }
+        spill(Hin, pend);  // this layer's input, before the buffer is reused
+        __syncthreads();   // every row's y is formed and stored: Hin can be overwritten
+        if (wave == 0) {  // the rows' squared errors and dy, a fixed shuffle tree
+            double s2 = lane < MT ? se[lane] : 0.0;
+            float sd = lane < MT ? dyf[lane] : 0.f;
+#pragma unroll
+            for (int m = MT / 2; m > 0; m >>= 1) {
+                s2 += __shfl_xor(s2, m, 64);
+                sd += __shfl_xor(sd, m, 64);
+            }
+            if (lane == 0) {
+                a.lossp[blockIdx.x] = s2;
+                a.bpart[L - 1][(size_t)blockIdx.x * 64] = sd;
+            }
+        }
+        float* Zl = Zs + (size_t)(L - 2) * MT * W;  // becomes layer L - 2's output gradient (FP32)
+        for (int e = tid; e < MT * W; e += kFThreads) {
+            const int rr = e / W, c = e - rr * W;
+            const float d = (dyb[rr] * wl[c]) * gelu_grad(Zl[e]);
+            Zl[e] = d;
+            Hin[rr * P + c] = f2bf(d);
+        }
+        __syncthreads();
+        for (int c = tid; c < W; c += kFThreads) {
+            float cs = 0.f;
+            for (int q = 0; q < MT; ++q) cs += Zl[q * W + c];
+            a.bpart[L - 2][(size_t)blockIdx.x * W + c] = cs;
+        }
+        pend = a.dZ[L - 2];
+    };
+
+    const int NP = TRAIN ? 2 * L - 3 : L - 1;
+    uint4 wA[2][kFMaxKS], wB[2][kFMaxKS];
+    float bA[2] = {0.f, 0.f}, bB[2] = {0.f, 0.f};
+    wload(0, wA, bA);
+    __syncthreads();  // input rows and output weights staged
+    auto stage = [&](int p, const uint4 (&cur)[2][kFMaxKS], const float (&bc)[2], uint4 (&nxt)[2][kFMaxKS],
+                     float (&bn)[2]) {
+        wtake(cur, bc);
+        if (p + 1 < NP) wload(p + 1, nxt, bn);
+        mpass(p, cur, bc);
+        if (p == L - 2) output_layer();
+    };
+    for (int p = 0; p < NP; p += 2) {
+        stage(p, wA, bA, wB, bB);
+        if (p + 1 >= NP) break;
+        stage(p + 1, wB, bB, wA, bA);
+    }
+    if (TRAIN) spill(Hb + (NP & 1) * MT * P, pend);  // the first layer's output gradient
+}
+
+// Weight gradients of every layer in one launch: the split-K tiles of all
+// layers' dW = dZ^T X, laid end to end in the grid, then one block per 64
+// bias columns of each layer adding that layer's per-workgroup bias partials
+// (four interleaved strided sums, 16 loads in flight each, joined in a fixed
+// order) into one bias gradient.
+struct WgradAll {
+    int L;
+    int start[kMaxLayers + 1];   // first block of layer l's weight tiles; start[L]: the bias blocks
+    int bstart[kMaxLayers + 1];  // first bias block of layer l, counted from start[L]
+    GemmArgs g[kMaxLayers];
+    const float* bpart[kMaxLayers];  // [nbp][npad_l]
+    float* bgrad[kMaxLayers];        // [npad_l]
+    int nbp;
+};
+
+__global__ __launch_bounds__(kGT) void k_wgrad_all(WgradAll w) {
+    extern __shared__ __attribute__((aligned(16))) uint16_t gemm_lds[];
+    int b = blockIdx.x;
+    if (b >= w.start[w.L]) {
+        b -= w.start[w.L];
+        int l = 0;
+        while (l + 1 < w.L && b >= w.bstart[l + 1]) ++l;
+        const int npad = w.g[l].M;  // the layer's padded outputs
+        const int c = (b - w.bstart[l]) * 64 + (threadIdx.x & 63), grp = threadIdx.x >> 6;
+        const float* bp = w.bpart[l];
+        float acc = 0.f;
+        for (int k0 = grp; k0 < w.nbp; k0 += 4 * 16) {
+            float x[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int k = k0 + 4 * u;
+                x[u] = bp[(size_t)(k < w.nbp ? k : grp) * npad + c];
+            }
+#pragma unroll
+            for (int u = 0; u < 16; ++u) acc += k0 + 4 * u < w.nbp ? x[u] : 0.f;
+        }
+        float* red = reinterpret_cast<float*>(gemm_lds);
+        red[threadIdx.x] = acc;
+        __syncthreads();
+        if (threadIdx.x < 64) w.bgrad[l][c] = (red[threadIdx.x] + red[64 + threadIdx.x]) + (red[128 + threadIdx.x] + red[192 + threadIdx.x]);
+        return;
+    }
+    int l = 0;
+    while (l + 1 < w.L && b >= w.start[l + 1]) ++l;
+    b -= w.start[l];
+    const GemmArgs& g = w.g[l];
+    const int nx = g.N / kTN, ny = g.M / kTM;
+    gemm_tile<true, false, EPI_WGRAD>(g, b % nx, (b / nx) % ny, b / (nx * ny), gemm_lds);
 }
 
 }  // namespace mjp
@@ -412,11 +775,14 @@ struct mjp_surrogate {
     int Bmax = 0, splits = 0;
     int64_t step = 0;
     DevBuf master, m1, m2, gradbuf;
-    DevBuf wbf[kMaxLayers], P[kMaxLayers];
+    DevBuf wbf[kMaxLayers], wbfF[kMaxLayers], wbfB[kMaxLayers], P[kMaxLayers];
+    bool fused = false;        // nets up to 256 wide: the three-launch training step
+    int mt = 16;               // its batch rows per workgroup
     DevBuf X[kMaxLayers + 1];  // BF16 inputs of each layer [Bmax x kpad]; X[L] unused
     DevBuf Z[kMaxLayers];      // FP32 pre-activations [Bmax x npad]
     DevBuf dZ[kMaxLayers];     // BF16 output gradients [Bmax x npad]
-    DevBuf bpart[kMaxLayers];  // bias-gradient partials [Bmax / 64][npad] (last layer: [Bmax / kMseRows][npad])
+    DevBuf bpart[kMaxLayers];  // bias-gradient partials [Bmax / 16][npad] (one per 16 rows at most)
+    DevBuf bgrad[kMaxLayers];  // fused step: the bias gradients [npad], from the partials
     DevBuf Y, tgt, lossp, perm;
 };
 
@@ -433,12 +799,14 @@ static mjp_status surrogate_alloc(mjp_surrogate* s, int Bmax, hipStream_t st_) {
         if ((st = s->X[l].reserve(sizeof(uint16_t) * (size_t)Bmax * s->kpad[l])) ||
             (st = s->Z[l].reserve(sizeof(float) * (size_t)Bmax * s->npad[l])) ||
             (st = s->dZ[l].reserve(sizeof(uint16_t) * (size_t)Bmax * s->npad[l])) ||
-            (st = s->bpart[l].reserve(sizeof(float) * (size_t)(Bmax / 64) * s->npad[l])) ||
+            (st = s->bpart[l].reserve(sizeof(float) * (size_t)(Bmax / kFMinRows) * s->npad[l])) ||
+            (st = s->bgrad[l].reserve(sizeof(float) * (size_t)s->npad[l])) ||
             (st = s->P[l].reserve(sizeof(float) * (size_t)s->splits * s->npad[l] * s->kpad[l])))
             return st;
     }
     if ((st = s->Y.reserve(sizeof(float) * (size_t)Bmax * s->npad[s->L - 1])) ||
-        (st = s->tgt.reserve(sizeof(float) * (size_t)Bmax)) || (st = s->lossp.reserve(sizeof(double) * (size_t)Bmax)))
+        (st = s->tgt.reserve(sizeof(float) * (size_t)Bmax)) ||
+        (st = s->lossp.reserve(sizeof(double) * (size_t)(Bmax / kFMinRows))))
         return st;
     // the loss kernel writes only column 0 of the last layer's dZ: the
     // padding columns are cleared once per allocation
@@ -463,6 +831,8 @@ static AdamArgs adam_args(mjp_surrogate* s) {
         a.lay[l].nbp = 0;
         a.lay[l].bps = s->npad[l];
         a.lay[l].Wbf = s->wbf[l].as<uint16_t>();
+        a.lay[l].WbfF = s->wbfF[l].as<uint16_t>();
+        a.lay[l].WbfB = s->wbfB[l].as<uint16_t>();
     }
     a.splits = s->splits;
     a.master = s->master.as<float>();
@@ -573,13 +943,108 @@ static void loss_grad(mjp_surrogate* s, int n_valid, int Bpad, double* loss_part
                        s->bpart[s->L - 1].as<float>());
 }
 
+// Split-K count of the weight-gradient products at padded batch Bpad: one
+// split per 256 rows on the per-layer path; at most kFusedSplits on the fused
+// one (fewer partials for the optimiser to add, each split a longer reduction).
+constexpr int kFusedSplits = 8;
+static int wgrad_splits(const mjp_surrogate* s, int Bpad) {
+    const int sp = std::max(1, Bpad / kWgradChunk);
+    return s->fused ? std::min(sp, kFusedSplits) : sp;
+}
+
 // Adam arguments of one training step at padded batch Bpad: split-K
 // weight-gradient partials and the bias-gradient partials' counts.
 static AdamArgs step_args(mjp_surrogate* s, int Bpad) {
     AdamArgs a = adam_args(s);
-    a.splits = std::max(1, Bpad / kWgradChunk);
-    for (int l = 0; l < s->L; ++l) a.lay[l].nbp = l + 1 == s->L ? Bpad / kMseRows : Bpad / 64;
+    a.splits = wgrad_splits(s, Bpad);
+    for (int l = 0; l < s->L; ++l) {
+        a.lay[l].nbp = s->fused ? 1 : (l + 1 == s->L ? Bpad / kMseRows : Bpad / 64);
+        if (s->fused) a.lay[l].bp = s->bgrad[l].as<float>();  // reduced by the weight-gradient launch
+    }
     return a;
+}
+
+// loss partials one training step leaves at padded batch Bpad
+static int loss_parts(const mjp_surrogate* s, int Bpad) { return s->fused ? Bpad / s->mt : Bpad / kMseRows; }
+
+static FusedArgs fused_args(const mjp_surrogate* s, const float* x, const float* y, const int32_t* perm, int base,
+                            int n_valid) {
+    FusedArgs f{};
+    f.L = s->L;
+    f.width = s->cfg.width;
+    f.in_dim = s->in[0];
+    f.kpad0 = s->kpad[0];
+    f.n_valid = n_valid;
+    f.base = base;
+    f.x = x;
+    f.y = y;
+    f.perm = perm;
+    f.master = s->master.as<float>();
+    for (int l = 0; l < s->L; ++l) {
+        f.boff[l] = s->woff[l] + (int64_t)s->out[l] * s->in[l];
+        f.W[l] = s->wbf[l].as<uint16_t>();
+        f.WF[l] = s->wbfF[l].as<uint16_t>();
+        f.WB[l] = s->wbfB[l].as<uint16_t>();
+        f.X[l] = s->X[l].as<uint16_t>();
+        f.dZ[l] = s->dZ[l].as<uint16_t>();
+        f.bpart[l] = s->bpart[l].as<float>();
+    }
+    return f;
+}
+
+static hipError_t fused_lds_limits() {
+    const void* fns[] = {reinterpret_cast<const void*>(k_mlp_fused<true, 1>),
+                         reinterpret_cast<const void*>(k_mlp_fused<false, 1>)};
+    hipError_t e = hipSuccess;
+    for (const void* f : fns)
+        if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_wgrad_all), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)kGemmLds);
+    return e;
+}
+
+// One fused training pass over rows base.. (forward, loss, backward data)
+// into X, dZ, the bias partials and the loss partials lp, then every
+// layer's weight-gradient partials.
+static void fused_train_pass(mjp_surrogate* s, const float* x, const float* y, const int32_t* perm, int base,
+                             int n_valid, int Bpad, double* lp, hipStream_t st) {
+    static const hipError_t lds_ok = fused_lds_limits();  // a failure surfaces as a launch error
+    (void)lds_ok;
+    FusedArgs f = fused_args(s, x, y, perm, base, n_valid);
+    f.lossp = lp;
+    hipLaunchKernelGGL((k_mlp_fused<true, 1>), dim3(Bpad / 16), dim3(kFThreads),
+                       fused_lds_bytes(true, s->L, s->cfg.width, 16), st, f);
+    WgradAll w{};
+    w.L = s->L;
+    const int splits = wgrad_splits(s, Bpad);
+    int blocks = 0;
+    for (int l = 0; l < s->L; ++l) {
+        GemmArgs& g = w.g[l];
+        g.M = s->npad[l];
+        g.N = s->kpad[l];
+        g.K = Bpad;
+        g.A = s->dZ[l].as<uint16_t>();
+        g.lda = s->npad[l];
+        g.B = s->X[l].as<uint16_t>();
+        g.ldb = s->kpad[l];
+        g.k_per_split = Bpad / splits;
+        g.P = s->P[l].as<float>();
+        w.start[l] = blocks;
+        blocks += (g.N / kTN) * (g.M / kTM) * splits;
+    }
+    w.start[s->L] = blocks;
+    int bb = 0;
+    for (int l = 0; l < s->L; ++l) {
+        w.bstart[l] = bb;
+        w.bpart[l] = s->bpart[l].as<float>();
+        w.bgrad[l] = s->bgrad[l].as<float>();
+        bb += s->npad[l] / 64;
+    }
+    w.bstart[s->L] = bb;
+    w.nbp = Bpad / s->mt;
+    blocks += bb;
+    hipLaunchKernelGGL(k_wgrad_all, dim3(blocks), dim3(kGT), kGemmLds, st, w);
 }
 
 }  // namespace mjp
@@ -611,6 +1076,10 @@ mjp_status mjp_surrogate_create(const mjp_mlp_cfg* cfg, uint64_t seed, mjp_surro
     }
     s->woff[s->L] = off;
     s->total = off;
+    // the fused step's rows per workgroup: 16 (32 halves the weight loads per row but
+    // leaves half the CUs idle at batch 4096: 1.87% against 2.05% of the BF16 peak)
+    s->mt = 16;
+    s->fused = cfg->width <= kFMaxW && fused_lds_bytes(true, s->L, cfg->width, s->mt) <= 160 * 1024;
     if (hipGetDevice(&s->device) != hipSuccess) {
         delete s;
         return fail(MJP_E_DEVICE, "no HIP device available");
@@ -630,11 +1099,13 @@ mjp_status mjp_surrogate_create(const mjp_mlp_cfg* cfg, uint64_t seed, mjp_surro
         return st;
     }
     for (int l = 0; l < s->L; ++l) {
-        if ((st = s->wbf[l].reserve(sizeof(uint16_t) * (size_t)s->npad[l] * s->kpad[l]))) {
+        const size_t wb = sizeof(uint16_t) * (size_t)s->npad[l] * s->kpad[l];
+        if ((st = s->wbf[l].reserve(wb)) || (st = s->wbfF[l].reserve(wb)) || (st = s->wbfB[l].reserve(wb))) {
             mjp_surrogate_destroy(s);
             return st;
         }
-        if (hipMemset(s->wbf[l].ptr, 0, sizeof(uint16_t) * (size_t)s->npad[l] * s->kpad[l]) != hipSuccess) {
+        if (hipMemset(s->wbf[l].ptr, 0, wb) != hipSuccess || hipMemset(s->wbfF[l].ptr, 0, wb) != hipSuccess ||
+            hipMemset(s->wbfB[l].ptr, 0, wb) != hipSuccess) {
             mjp_surrogate_destroy(s);
             return fail(MJP_E_DEVICE, "hipMemset failed");
         }
@@ -663,10 +1134,13 @@ void mjp_surrogate_destroy(mjp_surrogate* s) {
     s->gradbuf.release();
     for (int l = 0; l < kMaxLayers; ++l) {
         s->wbf[l].release();
+        s->wbfF[l].release();
+        s->wbfB[l].release();
         s->P[l].release();
         s->Z[l].release();
         s->dZ[l].release();
         s->bpart[l].release();
+        s->bgrad[l].release();
     }
     for (auto& b : s->X) b.release();
     s->Y.release();
@@ -711,6 +1185,16 @@ mjp_status mjp_surrogate_infer(const mjp_surrogate* sc, const float* x_d, int32_
     MJP_CHECK(x_d && y_d, MJP_E_INVALID_ARG, "null buffer");
     mjp_surrogate* s = const_cast<mjp_surrogate*>(sc);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (s->fused) {  // one launch, no work buffers
+        static const hipError_t lds_ok = fused_lds_limits();
+        (void)lds_ok;
+        FusedArgs f = fused_args(s, x_d, nullptr, nullptr, 0, n);
+        f.yout = y_d;
+        hipLaunchKernelGGL((k_mlp_fused<false, 1>), dim3((unsigned)((n + 15) / 16)), dim3(kFThreads),
+                           fused_lds_bytes(false, s->L, s->cfg.width, 16), st, f);
+        MJP_HIP(hipGetLastError());
+        return MJP_OK;
+    }
     const int chunk = 4096;
     mjp_status e = surrogate_alloc(s, std::max(s->Bmax, std::min(chunk, round_up(n, 256))), st);
     if (e) return e;
@@ -737,15 +1221,19 @@ mjp_status mjp_surrogate_grad(const mjp_surrogate* sc, const float* x_d, const f
     mjp_status e = surrogate_alloc(s, Bpad, st);
     if (e) return e;
     if ((e = s->gradbuf.reserve(sizeof(float) * s->total))) return e;
-    load_rows(s, x_d, y_d, nullptr, 0, n, Bpad, st);
-    forward(s, Bpad, n, st);
-    loss_grad(s, n, Bpad, s->lossp.as<double>(), st);
-    backward(s, Bpad, st);
+    if (s->fused) {
+        fused_train_pass(s, x_d, y_d, nullptr, 0, n, Bpad, s->lossp.as<double>(), st);
+    } else {
+        load_rows(s, x_d, y_d, nullptr, 0, n, Bpad, st);
+        forward(s, Bpad, n, st);
+        loss_grad(s, n, Bpad, s->lossp.as<double>(), st);
+        backward(s, Bpad, st);
+    }
     AdamArgs a = step_args(s, Bpad);
     a.grad_out = s->gradbuf.as<float>();
     hipLaunchKernelGGL(k_adam, dim3((unsigned)((s->total + 255) / 256)), dim3(256), 0, st, a);
     MJP_HIP(hipGetLastError());
-    std::vector<double> lp((size_t)Bpad / kMseRows);
+    std::vector<double> lp((size_t)loss_parts(s, Bpad));
     MJP_HIP(hipMemcpyAsync(lp.data(), s->lossp.ptr, sizeof(double) * lp.size(), hipMemcpyDeviceToHost, st));
     MJP_HIP(hipMemcpyAsync(grad_h, s->gradbuf.ptr, sizeof(float) * s->total, hipMemcpyDeviceToHost, st));
     MJP_HIP(hipStreamSynchronize(st));
@@ -776,7 +1264,7 @@ mjp_status mjp_surrogate_train(mjp_surrogate* s, const float* x_d, const float* 
     // (an event per slot); the loss partials of every step stay on the
     // device and are read once at the end.
     const int nb = (n + cfg->batch - 1) / cfg->batch;
-    const int lstride = cfg->batch / kMseRows;  // loss partials per step
+    const int lstride = loss_parts(s, cfg->batch);  // loss partials per step
     if ((e = s->perm.reserve(sizeof(int32_t) * 2 * (size_t)n))) return e;
     if (loss_h && (e = s->lossp.reserve(sizeof(double) * (size_t)cfg->epochs * nb * lstride))) return e;
     int32_t* ph[2] = {nullptr, nullptr};
@@ -810,11 +1298,15 @@ mjp_status mjp_surrogate_train(mjp_surrogate* s, const float* x_d, const float* 
             const int base = bi * cfg->batch;
             const int nv = std::min(cfg->batch, n - base);
             const int Bpad = round_up(nv, 512);
-            load_rows(s, x_d, y_d, perm_d, base, nv, Bpad, st);
-            forward(s, Bpad, nv, st);
             double* lp = loss_h ? s->lossp.as<double>() + ((size_t)ep * nb + bi) * lstride : s->lossp.as<double>();
-            loss_grad(s, nv, Bpad, lp, st);
-            backward(s, Bpad, st);
+            if (s->fused) {
+                fused_train_pass(s, x_d, y_d, perm_d, base, nv, Bpad, lp, st);
+            } else {
+                load_rows(s, x_d, y_d, perm_d, base, nv, Bpad, st);
+                forward(s, Bpad, nv, st);
+                loss_grad(s, nv, Bpad, lp, st);
+                backward(s, Bpad, st);
+            }
             s->step += 1;
             AdamArgs a = step_args(s, Bpad);
             a.lr = cfg->lr;
@@ -839,7 +1331,7 @@ mjp_status mjp_surrogate_train(mjp_surrogate* s, const float* x_d, const float* 
             double ep_loss = 0.0;
             for (int bi = 0; bi < nb; ++bi) {
                 const int nv = std::min(cfg->batch, n - bi * cfg->batch);
-                const int used = round_up(nv, 512) / kMseRows;
+                const int used = loss_parts(s, round_up(nv, 512));
                 for (int c = 0; c < used; ++c) ep_loss += lp[((size_t)ep * nb + bi) * lstride + c];
             }
             loss_h[ep] = (float)(ep_loss / n);
