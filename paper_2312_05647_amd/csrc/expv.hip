@@ -386,15 +386,13 @@ static mjp_status run_sweep(mjp_plan* p, const float* rho0, const std::vector<Sw
     PersistCfg cfg;
     const int var = p->opts.variant;
     const bool coh = var != MJP_VARIANT_PERSISTENT_FENCED;
-    // two jumps per synchronisation where the operator's reach allows it,
-    // else one
-    // four jumps per synchronisation on tiles where the operator is a grid,
-    // else two on row blocks where its reach allows, else one
+    // eight (else four) jumps per synchronisation on tiles where the operator
+    // is a grid, else two on row blocks where its reach allows, else one
+    // (MJP_VARIANT_PERSISTENT_TWOJUMP starts at two)
     const bool multi = var == MJP_VARIANT_AUTO || var == MJP_VARIANT_PERSISTENT;
     bool fits = multi && persistent_mj_fits(p, max_open, cfg);
     if (!fits && (multi || var == MJP_VARIANT_PERSISTENT_TWOJUMP)) fits = persistent2_fits(p, max_open, cfg);
-    if (!fits && var != MJP_VARIANT_STEPWISE && var != MJP_VARIANT_PERSISTENT_TWOJUMP)
-        fits = persistent_fits(p, max_open, coh, cfg);
+    if (!fits && var != MJP_VARIANT_STEPWISE) fits = persistent_fits(p, max_open, coh, cfg);
     if (fits) {
         const std::vector<int> slot = colour_slots(at);
         p->last_path = cfg.jumps >= 4 ? MJP_PATH_PERSISTENT_MULTIJUMP
