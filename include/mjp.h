@@ -436,6 +436,20 @@ mjp_status mjp_loglik_set_shapes(int32_t model, const int32_t* ids_h);
 /* The shapes a call with n_rec records would use now (defaults resolved). */
 mjp_status mjp_loglik_get_shapes(int32_t model, int32_t n_rec, int32_t* ids_h);
 
+/* On-disk cache of the autotuner's choices (a build aid, not in the paper):
+ * mjp_loglik_save_shapes writes the shape chosen for every (model, size
+ * class) on the current device -- by mjp_loglik_tune, mjp_loglik_set_shapes
+ * or the defaults (-1) -- to the text file `path`, keyed by the device's
+ * architecture, compute-unit count and product name and by this library's
+ * shape table (number of shapes, class limits).  mjp_loglik_load_shapes reads
+ * such a file and applies it to the current device; the whole file is
+ * checked first and nothing changes on an error: MJP_E_INVALID_ARG if it
+ * cannot be read or is not a complete, valid cache; MJP_E_UNSUPPORTED if it
+ * was written on another GPU or by a build with another shape table (tune
+ * again there); MJP_E_DEVICE if no device can be queried. */
+mjp_status mjp_loglik_save_shapes(const char* path);
+mjp_status mjp_loglik_load_shapes(const char* path);
+
 /* Autotuner: runs the batch of mjp_loglik (same arguments) once per
  * eligible shape and size class (after one warm-up run each, reps timed
  * runs, HIP events on `stream`), keeps the fastest shape per class for this

@@ -28,7 +28,9 @@
 #include <cfloat>
 #include <array>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <string>
 #include <memory>
 #include <mutex>
 #include <utility>
@@ -1932,6 +1934,115 @@ extern "C" mjp_status mjp_loglik_get_shapes(int32_t model, int32_t n_rec, int32_
     LLContext& C = ctx_for(dev);
     std::lock_guard<std::mutex> lock(C.mu);
     for (int c = 0; c < kLLClasses; ++c) ids[c] = ll_effective(C, model, c, n_rec);
+    return MJP_OK;
+}
+
+// ---- on-disk cache of the shape choices, keyed by GPU ------------------
+//
+// Text, one record per line:
+//   mjp-loglik-shapes 1
+//   gpu <architecture> <compute units> <product name, spaces as '_'>
+//   table <number of shapes> <class limit 0> .. <class limit MJP_LL_CLASSES-1>
+//   model <m> <shape of class 0> .. <shape of class MJP_LL_CLASSES-1>   (four lines, -1 = default)
+// The gpu and table lines are the key: a file from another GPU, or from a
+// build with another shape table, is refused.
+
+static mjp_status ll_gpu_key(std::string& key) {
+    int dev = 0;
+    MJP_HIP(hipGetDevice(&dev));
+    hipDeviceProp_t pr;
+    MJP_HIP(hipGetDeviceProperties(&pr, dev));
+    std::string name(pr.name), arch(pr.gcnArchName);
+    for (char& ch : name)
+        if (ch == ' ' || ch == '\t' || ch == '\n') ch = '_';
+    for (char& ch : arch)
+        if (ch == ' ' || ch == '\t' || ch == '\n') ch = '_';
+    if (name.empty()) name = "unnamed";
+    char buf[96];
+    std::snprintf(buf, sizeof buf, " %d ", pr.multiProcessorCount);
+    key = arch + buf + name;
+    return MJP_OK;
+}
+
+static std::string ll_table_key() {
+    std::string t = std::to_string(kLLNumShapes);
+    for (int c = 0; c < kLLClasses; ++c) t += " " + std::to_string(kLLClassCap[c]);
+    return t;
+}
+
+extern "C" mjp_status mjp_loglik_save_shapes(const char* path) {
+    clear_error();
+    MJP_CHECK(path && *path, MJP_E_INVALID_ARG, "path is NULL or empty");
+    std::string key;
+    mjp_status st = ll_gpu_key(key);
+    if (st) return st;
+    int dev = 0;
+    if ((st = ll_device(dev))) return st;
+    int shape[4][kLLClasses];
+    {
+        LLContext& C = ctx_for(dev);
+        std::lock_guard<std::mutex> lock(C.mu);
+        std::memcpy(shape, C.shape, sizeof shape);
+    }
+    FILE* f = std::fopen(path, "w");
+    MJP_CHECK(f, MJP_E_INVALID_ARG, "cannot open %s for writing", path);
+    bool ok = std::fprintf(f, "mjp-loglik-shapes 1\ngpu %s\ntable %s\n", key.c_str(), ll_table_key().c_str()) > 0;
+    for (int m = 0; m < 4 && ok; ++m) {
+        ok = std::fprintf(f, "model %d", m) > 0;
+        for (int c = 0; c < kLLClasses && ok; ++c) ok = std::fprintf(f, " %d", shape[m][c]) > 0;
+        ok = ok && std::fputc('\n', f) != EOF;
+    }
+    ok = (std::fclose(f) == 0) && ok;
+    MJP_CHECK(ok, MJP_E_INVALID_ARG, "write to %s failed", path);
+    return MJP_OK;
+}
+
+extern "C" mjp_status mjp_loglik_load_shapes(const char* path) {
+    clear_error();
+    MJP_CHECK(path && *path, MJP_E_INVALID_ARG, "path is NULL or empty");
+    FILE* f = std::fopen(path, "r");
+    MJP_CHECK(f, MJP_E_INVALID_ARG, "cannot open %s", path);
+    // parse the whole file first: nothing changes unless it is complete and valid
+    std::vector<std::string> lines;
+    {
+        char buf[512];
+        while (std::fgets(buf, sizeof buf, f)) {
+            std::string l(buf);
+            while (!l.empty() && (l.back() == '\n' || l.back() == '\r')) l.pop_back();
+            lines.push_back(l);
+        }
+        std::fclose(f);
+    }
+    MJP_CHECK(lines.size() == 7 && lines[0] == "mjp-loglik-shapes 1" && lines[1].rfind("gpu ", 0) == 0 &&
+                  lines[2].rfind("table ", 0) == 0,
+              MJP_E_INVALID_ARG, "%s is not a shape cache", path);
+    int shape[4][kLLClasses];
+    for (int m = 0; m < 4; ++m) {
+        int mm = -1, used = 0;
+        int v[kLLClasses];
+        static_assert(kLLClasses == 4, "the record below reads four classes");
+        const int got = std::sscanf(lines[3 + m].c_str(), "model %d %d %d %d %d%n", &mm, &v[0], &v[1], &v[2], &v[3], &used);
+        MJP_CHECK(got == 5 && mm == m && used == (int)lines[3 + m].size(), MJP_E_INVALID_ARG, "%s: bad model record %d",
+                  path, m);
+        for (int c = 0; c < kLLClasses; ++c) {
+            MJP_CHECK(v[c] >= -1 && v[c] < kLLNumShapes &&
+                          (v[c] < 0 || ll_cap(kLLShapes[v[c]].T, kLLShapes[v[c]].C) >= kLLClassCap[c]),
+                      MJP_E_INVALID_ARG, "%s: model %d class %d: shape %d cannot hold the class", path, m, c, v[c]);
+            shape[m][c] = v[c];
+        }
+    }
+    MJP_CHECK(lines[2].substr(6) == ll_table_key(), MJP_E_UNSUPPORTED,
+              "%s was written by a library with another shape table", path);
+    std::string key;
+    mjp_status st = ll_gpu_key(key);
+    if (st) return st;
+    MJP_CHECK(lines[1].substr(4) == key, MJP_E_UNSUPPORTED, "%s was tuned on another GPU (%s, this is %s)", path,
+              lines[1].c_str() + 4, key.c_str());
+    int dev = 0;
+    if ((st = ll_device(dev))) return st;
+    LLContext& C = ctx_for(dev);
+    std::lock_guard<std::mutex> lock(C.mu);
+    std::memcpy(C.shape, shape, sizeof shape);
     return MJP_OK;
 }
 

@@ -151,6 +151,8 @@ _SIGS = [
     ("mjp_loglik_class_limit", ctypes.c_int32, [ctypes.c_int32]),
     ("mjp_loglik_set_shapes", ctypes.c_int, [ctypes.c_int32, _P]),
     ("mjp_loglik_get_shapes", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _P]),
+    ("mjp_loglik_save_shapes", ctypes.c_int, [ctypes.c_char_p]),
+    ("mjp_loglik_load_shapes", ctypes.c_int, [ctypes.c_char_p]),
     ("mjp_loglik_tune", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P, _P, ctypes.c_int32, _P,
                                        _P]),
     ("mjp_jump_probs", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P, _P]),
@@ -555,6 +557,14 @@ def mjp_loglik_get_shapes(model: int, n_rec: int = 0) -> list:
     a = (ctypes.c_int32 * MJP_LL_CLASSES)()
     _check(lib().mjp_loglik_get_shapes(model, n_rec, a))
     return list(a)
+
+
+def mjp_loglik_save_shapes(path: str) -> None:
+    _check(lib().mjp_loglik_save_shapes(os.fsencode(path)))
+
+
+def mjp_loglik_load_shapes(path: str) -> None:
+    _check(lib().mjp_loglik_load_shapes(os.fsencode(path)))
 
 
 def mjp_loglik_tune(model: int, theta, dims, obs: mjp_obs, out, opts: mjp_opts | None = None, info=None,

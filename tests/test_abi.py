@@ -419,3 +419,46 @@ def test_sampler_rejects_bad_configuration_on_the_host():
     assert L.mjp_sampler_set_proposal(None, None) == mjp.MJP_E_INVALID_ARG
     assert L.mjp_sampler_run(None, 1, None, 0, None) == mjp.MJP_E_INVALID_ARG
     assert L.mjp_philox_fill(1, 0, 0, 0, -1, None, None) == mjp.MJP_E_INVALID_ARG
+
+
+def _cache_file(tmp_path, gpu="gfx950 256 AMD_Instinct_MI355X", table=None, models=None):
+    """A shape-cache file in the library's text format (the format is stated
+    in include/mjp.h beside mjp_loglik_save_shapes)."""
+    if table is None:
+        table = " ".join([str(len(mjp.mjp_loglik_shapes()))] + [str(c) for c in mjp.mjp_loglik_class_limits()])
+    models = models or [[-1, -1, -1, -1]] * 4
+    lines = ["mjp-loglik-shapes 1", f"gpu {gpu}", f"table {table}"]
+    lines += [f"model {m} " + " ".join(str(v) for v in ids) for m, ids in enumerate(models)]
+    p = tmp_path / "shapes.txt"
+    p.write_text("\n".join(lines) + "\n")
+    return str(p)
+
+
+def test_shape_cache_rejects_bad_files_on_the_host(tmp_path):
+    L = mjp.lib()
+    assert L.mjp_loglik_save_shapes(None) == mjp.MJP_E_INVALID_ARG
+    assert L.mjp_loglik_load_shapes(None) == mjp.MJP_E_INVALID_ARG
+    assert L.mjp_loglik_load_shapes(str(tmp_path / "missing").encode()) == mjp.MJP_E_INVALID_ARG
+    junk = tmp_path / "junk"
+    junk.write_text("not a cache\n")
+    assert L.mjp_loglik_load_shapes(str(junk).encode()) == mjp.MJP_E_INVALID_ARG
+    # a shape that cannot hold its class, a shape id out of range, a truncated file
+    assert status_of(mjp.mjp_loglik_load_shapes, _cache_file(tmp_path, models=[[0, 0, 0, 8]] * 4)) == \
+        mjp.MJP_E_INVALID_ARG
+    assert status_of(mjp.mjp_loglik_load_shapes, _cache_file(tmp_path, models=[[99, -1, -1, -1]] * 4)) == \
+        mjp.MJP_E_INVALID_ARG
+    p = _cache_file(tmp_path)
+    with open(p) as f:
+        head = f.readlines()[:5]
+    open(p, "w").writelines(head)
+    assert status_of(mjp.mjp_loglik_load_shapes, p) == mjp.MJP_E_INVALID_ARG
+    # written by a build with another shape table: refused before any device query
+    assert status_of(mjp.mjp_loglik_load_shapes, _cache_file(tmp_path, table="3 1 2 3 4")) == mjp.MJP_E_UNSUPPORTED
+
+
+def test_shape_cache_needs_a_device_for_its_key(tmp_path):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    assert status_of(mjp.mjp_loglik_load_shapes, _cache_file(tmp_path)) == mjp.MJP_E_DEVICE
+    assert status_of(mjp.mjp_loglik_save_shapes, str(tmp_path / "out.txt")) == mjp.MJP_E_DEVICE

@@ -177,3 +177,33 @@ def test_unsorted_batch_groups_classes(mixed):
     sub = np.r_[slots, np.arange(100, 140)]
     ref = run(th[sub], dm[sub], T, recs_small)
     assert np.array_equal(np.nan_to_num(big[sub], neginf=-1e300), np.nan_to_num(ref, neginf=-1e300))
+
+
+def test_shape_cache_round_trip(tmp_path):
+    """The autotuner's on-disk cache: choices saved on this GPU load back
+    exactly; a file keyed to another GPU is refused and changes nothing."""
+    path = str(tmp_path / "shapes.txt")
+    chosen = [10, 7, 4, -1]
+    mjp.mjp_loglik_set_shapes(1, chosen)
+    mjp.mjp_loglik_set_shapes(3, [-1, -1, 4, -1])
+    want1, want3 = mjp.mjp_loglik_get_shapes(1), mjp.mjp_loglik_get_shapes(3)
+    mjp.mjp_loglik_save_shapes(path)
+    lines = open(path).read().splitlines()
+    say("shape cache key:", lines[1])
+    assert lines[0] == "mjp-loglik-shapes 1" and lines[1].startswith("gpu ") and len(lines) == 7
+    assert lines[4] == "model 1 10 7 4 -1"
+    mjp.mjp_loglik_set_shapes(1, [-1] * 4)
+    mjp.mjp_loglik_set_shapes(3, [-1] * 4)
+    mjp.mjp_loglik_load_shapes(path)
+    assert mjp.mjp_loglik_get_shapes(1) == want1 and mjp.mjp_loglik_get_shapes(3) == want3
+    other = list(lines)
+    other[1] = "gpu gfx000 7 Another_GPU"
+    other[4] = "model 1 -1 -1 -1 -1"
+    p2 = str(tmp_path / "other.txt")
+    open(p2, "w").write("\n".join(other) + "\n")
+    with pytest.raises(mjp.MjpError) as e:
+        mjp.mjp_loglik_load_shapes(p2)
+    assert e.value.status == mjp.MJP_E_UNSUPPORTED
+    assert mjp.mjp_loglik_get_shapes(1) == want1
+    mjp.mjp_loglik_set_shapes(1, [-1] * 4)
+    mjp.mjp_loglik_set_shapes(3, [-1] * 4)
