@@ -349,9 +349,9 @@ mjp_status mjp_loglik(int32_t model, int32_t B, const double* theta_d, const int
  * forbid hipMalloc).  Same arguments, kernels, launch shapes and results
  * (bit for bit) as mjp_loglik.  The call's tables (records, times, windows,
  * costs, order, queue counters) live in one fixed array of
- * mjp_loglik_noalloc_capacity() bytes (4 MiB) of device memory per GPU,
+ * mjp_loglik_noalloc_capacity() bytes (6 MiB) of device memory per GPU,
  * part of the library and held until the process ends; a call needs
- * mjp_loglik_noalloc_bytes(B, n_t, n_obs) of it (B (24 n_t + 8) + 16 n_obs +
+ * mjp_loglik_noalloc_bytes(B, n_t, n_obs) of it (B (32 n_t + 8) + 16 n_obs +
  * 8 n_t plus alignment: for example B <= 8192 at 20 times and 1000 records)
  * and returns MJP_E_WORKSPACE, before any GPU work, when that exceeds the
  * capacity.  The records and times are copied from obs's host arrays by

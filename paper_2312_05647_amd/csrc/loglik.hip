@@ -125,8 +125,29 @@ constexpr int col_cap(int cc) {
 struct LLWin {     // per (item, time)
     double W;
     double lastw;  // w_K + residual (lumping) or w_K
+    double aw;     // w_L: the anchor of the sweep's weight recurrence
     int32_t L, K;
 };
+// Weights in the sweeps: w_L = aw from the window (formed by k_ll_prep's
+// walk from the mode), then w_k = w_{k-1} W / k in FP64 -- one division per
+// jump instead of a log and an exp.  The recurrence's relative rounding grows
+// by about 2.2e-16 per jump, below 1e-11 over any window here.  Under the
+// paper's K rule (L = 0) at W > 667 the weights of the first jumps are below
+// FP64's range; the window then starts at the first k whose weight is at
+// least kWeightFloor (every weight skipped is below 1e-290).
+constexpr double kWeightFloor = 1e-290;
+// the part of a window every thread of a sweep reads, kept in LDS (the
+// anchor stays in the register of the thread that forms the time's weights)
+struct LLWinL {
+    double W, lastw;
+    int32_t L, K;
+};
+__device__ __forceinline__ LLWinL ll_win_lds(const LLWin& w) { return LLWinL{w.W, w.lastw, w.L, w.K}; }
+// a time's weight at jump k, from the previous jump's (cur)
+__device__ __forceinline__ double ll_weight_step(int k, double W, int L, double aw, double cur) {
+    if (k == L) return aw;
+    return k > L ? cur * (W / (double)k) : 0.0;
+}
 
 struct LLRecord {  // per observation record
     int32_t t, x1, x2, count;
@@ -215,9 +236,11 @@ __global__ void k_ll_prep(LLArgs a) {
     const double W = bad_theta ? NAN : omega * a.T[j];
     LLWin w;
     w.W = W;
+    w.aw = 0.0;
     if (W == 0.0) {
         w.L = w.K = 0;
         w.lastw = 1.0;
+        w.aw = 1.0;  // w_0 = 1, later weights W^k / k! = 0
     } else if (!(W > 0.0) || !(W < 1e9) || W > (double)a.k_cap) {
         // non-finite or enormous rates: K >= floor(W) already exceeds the cap
         w.L = 0;
@@ -247,13 +270,19 @@ __global__ void k_ll_prep(LLArgs a) {
             K = (int64_t)k;
         }
         const double wK = wk;
-        // left end
+        // left end; the window starts at the smallest k walked whose weight
+        // is at least kWeightFloor (the tolerance rule's L always qualifies)
         int64_t L;
         k = mode;
         wk = wm;
+        double ka = mode, wa = wm;
         if (a.k_rule == MJP_K_PAPER) {
-            while (k > 0.0) { wk = wk * k / W; k -= 1.0; sum += wk; }
-            L = 0;
+            while (k > 0.0) {
+                wk = wk * k / W;
+                k -= 1.0;
+                sum += wk;
+                if (wk >= kWeightFloor) { ka = k; wa = wk; }
+            }
         } else {
             while (k > 0.0) {
                 const double wp = wk * k / W;
@@ -262,9 +291,11 @@ __global__ void k_ll_prep(LLArgs a) {
                 wk = wp;
                 k -= 1.0;
                 sum += wk;
+                if (wk >= kWeightFloor) { ka = k; wa = wk; }
             }
-            L = (int64_t)k;
         }
+        L = (int64_t)ka;
+        w.aw = wa;
         const double resid = 1.0 - sum;
         w.K = (int32_t)min<int64_t>(K, (int64_t)INT32_MAX / 2);
         w.L = (int32_t)L;
@@ -291,6 +322,7 @@ __global__ void k_jp_prep(LLArgs a) {
     LLWin w;
     w.W = 0.0;
     w.lastw = 0.0;
+    w.aw = 0.0;
     w.L = 0;
     w.K = bad ? -1 : (int32_t)kmax;
     a.win[b] = w;
@@ -482,7 +514,7 @@ __global__ __launch_bounds__(T) void k_ll_main(LLArgs a, int cls) {
     float* rho = reinterpret_cast<float*>(lds);                          // [CAP]
     double* wbuf = reinterpret_cast<double*>(lds + sizeof(float) * CAP);  // [2][kLLMaxTimes]
     double* scratch = wbuf + 2 * kLLMaxTimes;                                      // [16]
-    LLWin* win = reinterpret_cast<LLWin*>(scratch + 16);                           // [kLLMaxTimes]
+    LLWinL* win = reinterpret_cast<LLWinL*>(scratch + 16);                         // [kLLMaxTimes]
     __shared__ int pop_sh[T / 64];
     __shared__ unsigned flag_sh;
     const int tid = threadIdx.x;
@@ -495,7 +527,12 @@ __global__ __launch_bounds__(T) void k_ll_main(LLArgs a, int cls) {
         const double* th = a.theta + ll_stride(MODEL) * (int64_t)b;
         int S1, S2;
         ll_grid(MODEL, a.dims + 2 * b, S1, S2);
-        if (tid < a.n_t) win[tid] = a.win[(int64_t)b * a.n_t + tid];
+        double w_aw = 0.0;  // the anchor weight of this thread's time (threads tid < n_t)
+        if (tid < a.n_t) {
+            const LLWin wg = a.win[(int64_t)b * a.n_t + tid];
+            win[tid] = ll_win_lds(wg);
+            w_aw = wg.aw;
+        }
         if (tid == 0) flag_sh = 0u;
         __syncthreads();
         unsigned flags = 0;
@@ -572,18 +609,12 @@ __global__ __launch_bounds__(T) void k_ll_main(LLArgs a, int cls) {
         const int i1_0 = tid % S1, i2_0 = tid / S1;
         double scale = 1.0;
         const int m_renorm = a.renorm_every;
-        double lw = 0.0, logW = 0.0;
-        if (!JUMP && tid < a.n_t) {
-            const double W = win[tid].W;
-            logW = W > 0.0 ? log(W) : 0.0;
-            lw = W > 0.0 ? -W : 0.0;  // log w_0
-        }
+        double wcur = 0.0;  // this time's weight at the current jump (threads tid < n_t)
         for (int k = 0; k <= Kmax; ++k) {
-            // weight of jump k for each time (FP64 log space, running form)
+            // weight of jump k for each time (FP64, the recurrence from w_L)
             if (!JUMP && tid < a.n_t) {
-                if (k > 0) lw += logW - log((double)k);
-                const double W = win[tid].W;
-                wbuf[(k & 1) * kLLMaxTimes + tid] = W > 0.0 ? exp(lw) : (k == 0 ? 1.0 : 0.0);
+                wcur = ll_weight_step(k, win[tid].W, win[tid].L, w_aw, wcur);
+                wbuf[(k & 1) * kLLMaxTimes + tid] = wcur;
             }
             if (k > 0) {
                 float nv[C];
@@ -635,7 +666,7 @@ __global__ __launch_bounds__(T) void k_ll_main(LLArgs a, int cls) {
 #pragma unroll
             for (int u = 0; u < kLLRecPerThread; ++u) {
                 if (rm[u] < 0) continue;
-                const LLWin& w = win[rt[u]];
+                const LLWinL& w = win[rt[u]];
                 if (k < w.L || k > w.K) continue;
                 const float wt = (k == w.K) ? (float)w.lastw : (float)wbuf[(k & 1) * kLLMaxTimes + rt[u]];
                 const float v = kHidden ? rho[rm[u]] + rho[rm[u] + hid] : rho[rm[u]];
@@ -735,7 +766,7 @@ __global__ __launch_bounds__(kColT) void k_ll_col(LLArgs a, int cls) {
     float* rho = reinterpret_cast<float*>(lds);                            // [CAP] the vector's mirror
     double* wbuf = reinterpret_cast<double*>(lds + sizeof(float) * CAP);   // [2][kLLMaxTimes]
     double* scratch = wbuf + 2 * kLLMaxTimes;                              // [16]
-    LLWin* win = reinterpret_cast<LLWin*>(scratch + 16);                   // [kLLMaxTimes]
+    LLWinL* win = reinterpret_cast<LLWinL*>(scratch + 16);                 // [kLLMaxTimes]
     __shared__ int pop_sh[kColT / 64];
     __shared__ unsigned flag_sh;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -750,7 +781,12 @@ __global__ __launch_bounds__(kColT) void k_ll_col(LLArgs a, int cls) {
         const double* th = a.theta + ll_stride(MODEL) * (int64_t)b;
         int S1, S2;
         ll_grid(MODEL, a.dims + 2 * b, S1, S2);
-        if (tid < a.n_t) win[tid] = a.win[(int64_t)b * a.n_t + tid];
+        double w_aw = 0.0;  // the anchor weight of this thread's time (threads tid < n_t)
+        if (tid < a.n_t) {
+            const LLWin wg = a.win[(int64_t)b * a.n_t + tid];
+            win[tid] = ll_win_lds(wg);
+            w_aw = wg.aw;
+        }
         if (tid == 0) flag_sh = 0u;
         __syncthreads();
         unsigned flags = 0;
@@ -821,17 +857,12 @@ __global__ __launch_bounds__(kColT) void k_ll_col(LLArgs a, int cls) {
         if (x0 < 0) flags |= MJP_FLAG_OUT_OF_GRID;
 
         const int m_renorm = a.renorm_every;
-        double lw = 0.0, logW = 0.0;
-        if (tid < a.n_t) {
-            const double W = win[tid].W;
-            logW = W > 0.0 ? log(W) : 0.0;
-            lw = W > 0.0 ? -W : 0.0;  // log w_0
-        }
+        double wcur = 0.0;  // this time's weight at the current jump (threads tid < n_t)
         for (int k = 0; k <= Kmax; ++k) {
+            // weight of jump k for each time (FP64, the recurrence from w_L)
             if (tid < a.n_t) {
-                if (k > 0) lw += logW - log((double)k);
-                const double W = win[tid].W;
-                wbuf[(k & 1) * kLLMaxTimes + tid] = W > 0.0 ? exp(lw) : (k == 0 ? 1.0 : 0.0);
+                wcur = ll_weight_step(k, win[tid].W, win[tid].L, w_aw, wcur);
+                wbuf[(k & 1) * kLLMaxTimes + tid] = wcur;
             }
             if (k > 0) {
                 // old values a lane does not hold: ghost columns (rows past
@@ -896,7 +927,7 @@ __global__ __launch_bounds__(kColT) void k_ll_col(LLArgs a, int cls) {
                 __syncthreads();
             }
             if (rm >= 0) {
-                const LLWin& w = win[rt];
+                const LLWinL& w = win[rt];
                 if (k >= w.L && k <= w.K) {
                     const float wt = (k == w.K) ? (float)w.lastw : (float)wbuf[(k & 1) * kLLMaxTimes + rt];
                     const float v = rho[rm];
@@ -1030,7 +1061,7 @@ __global__ __launch_bounds__(kClT) void k_ll_cluster(ClArgs ca) {
     float* lx = reinterpret_cast<float*>(lds);                             // [CAP]
     double* wbuf = reinterpret_cast<double*>(lds + sizeof(float) * CAP);   // [2][kLLMaxTimes]
     double* scratch = wbuf + 2 * kLLMaxTimes;                              // [16]
-    LLWin* win = reinterpret_cast<LLWin*>(scratch + 16);                   // [kLLMaxTimes]
+    LLWinL* win = reinterpret_cast<LLWinL*>(scratch + 16);                 // [kLLMaxTimes]
     __shared__ unsigned flag_sh;
     const int tid = threadIdx.x;
     const int cl = blockIdx.x / kClG, r = blockIdx.x - cl * kClG;
@@ -1044,7 +1075,12 @@ __global__ __launch_bounds__(kClT) void k_ll_cluster(ClArgs ca) {
         const double* th = a.theta + ll_stride(MODEL) * (int64_t)b;
         int S1, S2;
         ll_grid(MODEL, a.dims + 2 * b, S1, S2);
-        if (tid < a.n_t) win[tid] = a.win[(int64_t)b * a.n_t + tid];
+        double w_aw = 0.0;  // the anchor weight of this thread's time (threads tid < n_t)
+        if (tid < a.n_t) {
+            const LLWin wg = a.win[(int64_t)b * a.n_t + tid];
+            win[tid] = ll_win_lds(wg);
+            w_aw = wg.aw;
+        }
         if (tid == 0) flag_sh = 0u;
         __syncthreads();
         unsigned flags = 0;
@@ -1118,19 +1154,14 @@ __global__ __launch_bounds__(kClT) void k_ll_cluster(ClArgs ca) {
         double scale = 1.0;
         const int m_renorm = a.renorm_every;
         int rpar = 0;
-        double lw = 0.0, logW = 0.0;
-        if (tid < a.n_t) {
-            const double W = win[tid].W;
-            logW = W > 0.0 ? log(W) : 0.0;
-            lw = W > 0.0 ? -W : 0.0;
-        }
+        double wcur = 0.0;  // this time's weight at the current jump (threads tid < n_t)
         const __amdgpu_buffer_rsrc_t xr = iter_rsrc(xb, (int64_t)2 * kClG * 2 * kClReachMax);
         bool ok = true;
         for (int k = 0; k <= Kmax && ok; ++k) {
+            // weight of jump k for each time (FP64, the recurrence from w_L)
             if (tid < a.n_t) {
-                if (k > 0) lw += logW - log((double)k);
-                const double W = win[tid].W;
-                wbuf[(k & 1) * kLLMaxTimes + tid] = W > 0.0 ? exp(lw) : (k == 0 ? 1.0 : 0.0);
+                wcur = ll_weight_step(k, win[tid].W, win[tid].L, w_aw, wcur);
+                wbuf[(k & 1) * kLLMaxTimes + tid] = wcur;
             }
             if (k > 0) {
                 float nv[C];
@@ -1200,7 +1231,7 @@ __global__ __launch_bounds__(kClT) void k_ll_cluster(ClArgs ca) {
 #pragma unroll
             for (int u = 0; u < kLLRecPerThread; ++u) {
                 if (rm[u] < 0) continue;
-                const LLWin& w = win[rt[u]];
+                const LLWinL& w = win[rt[u]];
                 if (k < w.L || k > w.K) continue;
                 const float wt = (k == w.K) ? (float)w.lastw : (float)wbuf[(k & 1) * kLLMaxTimes + rt[u]];
                 const float v = rho[rm[u]];
@@ -1320,7 +1351,7 @@ static const std::array<MainFn, kColClasses> kColMains =
 // LDS after the column kernel's mirror: weights [2][kLLMaxTimes], block-sum
 // scratch [16] (FP64), windows [kLLMaxTimes]; with the mirror at most
 // kColMirror floats the block stays within one CU's 160 KB
-constexpr size_t kColExtra = sizeof(double) * (2 * kLLMaxTimes + 16) + sizeof(LLWin) * kLLMaxTimes;
+constexpr size_t kColExtra = sizeof(double) * (2 * kLLMaxTimes + 16) + sizeof(LLWinL) * kLLMaxTimes;
 static_assert(sizeof(float) * kColMirror + kColExtra + 64 <= 160 * 1024, "column kernel LDS exceeds a CU");
 inline size_t col_lds(int cc) { return sizeof(float) * (size_t)col_cap(cc) + kColExtra; }
 inline bool col_model(int model) { return model == MJP_MODEL_CASCADE2; }
@@ -1725,7 +1756,7 @@ static mjp_status ll_device(int& dev) {
 // code: its device address, different on each GPU, comes from
 // hipGetSymbolAddress once per device (scratch_base) and only that address
 // is handed to copies and kernels.
-constexpr size_t kLLScratchBytes = (size_t)4 << 20;
+constexpr size_t kLLScratchBytes = (size_t)6 << 20;
 static __device__ __align__(256) unsigned char scratch[kLLScratchBytes];
 static void* g_scratch[kLLMaxDevices];
 static std::mutex g_scratch_mu;

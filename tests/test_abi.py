@@ -386,7 +386,7 @@ def test_noalloc_loglik_rejects_oversize_on_the_host():
     whose tables exceed the fixed array (MJP_E_WORKSPACE) before touching
     the GPU (the device pointers below are never dereferenced)."""
     cap = mjp.mjp_loglik_noalloc_capacity()
-    assert cap == 4 << 20
+    assert cap == 6 << 20
     assert mjp.mjp_loglik_noalloc_bytes(-1, 1, 1) == -1
     a, b = mjp.mjp_loglik_noalloc_bytes(100, 20, 1000), mjp.mjp_loglik_noalloc_bytes(200, 20, 1000)
     assert b - a >= 100 * (24 * 20 + 8)
