@@ -75,12 +75,14 @@ enum { MJP_VARIANT_AUTO = 0,       /* the plan picks the launch strategy */
                                       device-scope loads and stores.  Where
                                       the operator is a grid (every column of
                                       row m in {m, m +- 1, m +- S1}, width <=
-                                      5, at least 128 workgroups of 4096 rows)
-                                      and renorm_every is a multiple of 4,
+                                      5, at least 128 workgroups of 4096 rows,
+                                      at most 2 windows open at once) and
+                                      renorm_every is a multiple of 8 (else 4),
                                       each workgroup owns a 2-D tile and
-                                      computes four jumps per synchronisation,
-                                      recomputing the rings of cells around
-                                      its tile; else, where the reach is short
+                                      computes eight (else four) jumps per
+                                      synchronisation where the rings of cells
+                                      around its tile fit its LDS, recomputing
+                                      those rings; else, where the reach is short
                                       (at most 2048 rows of halo per 4096-row
                                       block, width <= 5) and renorm_every is
                                       even, two jumps per synchronisation;

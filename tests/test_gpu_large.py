@@ -75,7 +75,7 @@ def test_full_size_parity(ref, kind, variant):
 
 @pytest.mark.parametrize("kind", ["csr", "stencil"])
 def test_full_size_protocols_bit_identical(kind):
-    """The persistent kernel's forms (four jumps per synchronisation on
+    """The persistent kernel's forms (eight jumps per synchronisation on
     tiles, two on row blocks, one jump with device-scope accesses, one jump
     with fences) agree bit for bit at full size (every XCD)."""
     say(f"[gpu] cascade {S}x{S} protocols via {kind}")
