@@ -1391,10 +1391,31 @@ struct LLObsSet {
     DevBuf rec_d, T_d;
 };
 
+// A call's size classes are launched round-robin on the caller's stream and
+// kLLAux streams forked from it (and joined back before the call returns),
+// so the tail of one class -- a few long items while most CUs idle -- runs
+// beside the next class's items.  Each caller stream has its own forked
+// streams (default priority), so a graph captured on one stream forks and
+// joins only its own.
+constexpr int kLLAux = 3;
+
 struct LLWork {
     hipStream_t stream = nullptr;
     DevBuf win, cost, order, queue, cls_off;
     DevBuf cl_x, cl_part, cl_ninf, cl_flag;  // clusters: exchange slots, sums, flags + abort word
+    hipStream_t aux[kLLAux] = {};
+    hipEvent_t fork = nullptr, join[kLLAux] = {};
+    void release() {
+        for (DevBuf* d : {&win, &cost, &order, &queue, &cls_off, &cl_x, &cl_part, &cl_ninf, &cl_flag}) d->release();
+        for (int i = 0; i < kLLAux; ++i) {
+            if (aux[i]) (void)hipStreamDestroy(aux[i]);
+            if (join[i]) (void)hipEventDestroy(join[i]);
+            aux[i] = nullptr;
+            join[i] = nullptr;
+        }
+        if (fork) (void)hipEventDestroy(fork);
+        fork = nullptr;
+    }
 };
 
 // Device tables of one call.
@@ -1451,11 +1472,7 @@ mjp_status ll_release_all() {
             o->rec_d.release();
             o->T_d.release();
         }
-        for (auto& w : C.work) {
-            for (DevBuf* d : {&w->win, &w->cost, &w->order, &w->queue, &w->cls_off, &w->cl_x, &w->cl_part,
-                              &w->cl_ninf, &w->cl_flag})
-                d->release();
-        }
+        for (auto& w : C.work) w->release();
         C.obs.clear();
         C.work.clear();
     }
@@ -1561,7 +1578,7 @@ static mjp_status ll_obs(LLContext& C, const std::vector<LLRecord>& recs, const 
 }
 
 // The work tables of stream s, grown to B items of n_t times.
-static mjp_status ll_work(LLContext& C, hipStream_t s, int B, int n_t, LLBufs& bf) {
+static mjp_status ll_work(LLContext& C, hipStream_t s, int B, int n_t, LLBufs& bf, LLWork** wout = nullptr) {
     LLWork* w = nullptr;
     for (size_t i = 0; i < C.work.size(); ++i)  // most recently used first
         if (C.work[i]->stream == s) {
@@ -1572,24 +1589,27 @@ static mjp_status ll_work(LLContext& C, hipStream_t s, int B, int n_t, LLBufs& b
     if (!w) {
         if ((int)C.work.size() >= kLLMaxStreams) {  // free the least recently used stream's tables
             MJP_HIP(hipDeviceSynchronize());
-            LLWork& old = *C.work.back();
-            old.win.release();
-            old.cost.release();
-            old.order.release();
-            old.queue.release();
-            old.cls_off.release();
-            old.cl_x.release();
-            old.cl_part.release();
-            old.cl_ninf.release();
-            old.cl_flag.release();
+            C.work.back()->release();
             C.work.pop_back();
         }
         std::unique_ptr<LLWork> nw(new (std::nothrow) LLWork());
         MJP_CHECK(nw, MJP_E_DEVICE, "out of host memory");
         nw->stream = s;
+        for (int i = 0; i < kLLAux; ++i) {
+            if (hipStreamCreateWithFlags(&nw->aux[i], hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&nw->join[i], hipEventDisableTiming) != hipSuccess) {
+                nw->release();
+                return fail(MJP_E_DEVICE, "could not create the forked streams of a likelihood call");
+            }
+        }
+        if (hipEventCreateWithFlags(&nw->fork, hipEventDisableTiming) != hipSuccess) {
+            nw->release();
+            return fail(MJP_E_DEVICE, "could not create the forked streams of a likelihood call");
+        }
         C.work.insert(C.work.begin(), std::move(nw));
         w = C.work[0].get();
     }
+    if (wout) *wout = w;
     mjp_status st;
     if ((st = w->win.reserve(sizeof(LLWin) * (size_t)B * n_t)) || (st = w->cost.reserve(sizeof(float) * B)) ||
         (st = w->order.reserve(sizeof(int32_t) * B)) || (st = w->queue.reserve(64)) ||
@@ -1687,13 +1707,15 @@ static mjp_status cluster_launch(const LLContext& C, const LLArgs& a, const LLBu
     return MJP_OK;
 }
 
+// the items of column class cc
+static void col_launch_one(const LLContext& C, const LLArgs& a, int cc, hipStream_t s) {
+    const int grid = std::max(1, std::min(a.B, std::max(C.ncu, 1) * C.occ_col[cc]));
+    hipLaunchKernelGGL(kColMains[cc], dim3(grid), dim3(kColT), col_lds(cc), s, a, cc);
+}
 // the items of every column class (nothing when the column kernel is off)
 static void col_launch(const LLContext& C, const LLArgs& a, hipStream_t s) {
     if (!kColEnabled || !a.use_col) return;
-    for (int cc = 0; cc < kColClasses; ++cc) {
-        const int grid = std::max(1, std::min(a.B, std::max(C.ncu, 1) * C.occ_col[cc]));
-        hipLaunchKernelGGL(kColMains[cc], dim3(grid), dim3(kColT), col_lds(cc), s, a, cc);
-    }
+    for (int cc = 0; cc < kColClasses; ++cc) col_launch_one(C, a, cc, s);
 }
 
 __global__ void k_ll_queue_reset(unsigned* q, int cls) { q[cls] = 0u; }
@@ -1826,13 +1848,28 @@ mjp_status loglik_run(int32_t model, int32_t B, const double* theta_d, const int
     LLContext& C = ctx_for(dev);
     std::lock_guard<std::mutex> lock(C.mu);
     LLBufs bf;
-    if ((st = ll_attrs(C, dev)) || (st = ll_obs(C, recs, obs, s, bf)) || (st = ll_work(C, s, B, obs->n_t, bf)))
+    LLWork* w = nullptr;
+    if ((st = ll_attrs(C, dev)) || (st = ll_obs(C, recs, obs, s, bf)) || (st = ll_work(C, s, B, obs->n_t, bf, &w)))
         return st;
     LLArgs a = ll_args(C, model, B, obs, opts, theta_d, dims_d, loglik_d, info_d, bf);
     a.active = active_d;
     ll_prepare(a, s);
-    col_launch(C, a, s);
-    for (int c = 0; c < kLLClasses; ++c) ll_launch(C, a, c, ll_effective(C, model, c, a.n_rec), s);
+    // the size classes round-robin on the caller's stream and its forked ones
+    MJP_HIP(hipEventRecord(w->fork, s));
+    for (int i = 0; i < kLLAux; ++i) MJP_HIP(hipStreamWaitEvent(w->aux[i], w->fork, 0));
+    int rr = 0;
+    auto next_stream = [&]() {
+        hipStream_t t = rr == 0 ? s : w->aux[rr - 1];
+        rr = (rr + 1) % (kLLAux + 1);
+        return t;
+    };
+    if (kColEnabled && a.use_col)
+        for (int cc = 0; cc < kColClasses; ++cc) col_launch_one(C, a, cc, next_stream());
+    for (int c = 0; c < kLLClasses; ++c) ll_launch(C, a, c, ll_effective(C, model, c, a.n_rec), next_stream());
+    for (int i = 0; i < kLLAux; ++i) {
+        MJP_HIP(hipEventRecord(w->join[i], w->aux[i]));
+        MJP_HIP(hipStreamWaitEvent(s, w->join[i], 0));
+    }
     if ((st = cluster_launch(C, a, bf, s))) return st;
     MJP_HIP(hipGetLastError());
     return MJP_OK;
