@@ -336,7 +336,12 @@ typedef struct {
  *   - the work tables (windows, costs, order, queue counters) are kept per
  *     stream (64 streams; an older stream's are freed likewise), so calls on
  *     different streams never share them; a call with more items than its
- *     stream had before grows them (hipMalloc/hipFree).
+ *     stream had before grows them (hipMalloc/hipFree);
+ *   - with them, three streams of default priority per caller stream: the
+ *     call forks its size classes onto them after the preparation kernels
+ *     and joins them back into `stream` before it returns (events), so the
+ *     call stays ordered on `stream` and a capture on it records the fork
+ *     and the join.
  * A call on a stream that already ran one with at least this B and the same
  * observation set only enqueues kernels, so it may be captured in a hipGraph.
  * The graph uses that stream's work tables: it is invalidated by a later call
