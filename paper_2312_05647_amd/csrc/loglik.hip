@@ -1863,9 +1863,12 @@ mjp_status loglik_run(int32_t model, int32_t B, const double* theta_d, const int
         rr = (rr + 1) % (kLLAux + 1);
         return t;
     };
+    // widest classes first: a class the batch leaves empty then exits at once
+    // on a free chip instead of waiting, in front of a full class on its
+    // stream, for CUs that an earlier class holds
     if (kColEnabled && a.use_col)
-        for (int cc = 0; cc < kColClasses; ++cc) col_launch_one(C, a, cc, next_stream());
-    for (int c = 0; c < kLLClasses; ++c) ll_launch(C, a, c, ll_effective(C, model, c, a.n_rec), next_stream());
+        for (int cc = kColClasses - 1; cc >= 0; --cc) col_launch_one(C, a, cc, next_stream());
+    for (int c = kLLClasses - 1; c >= 0; --c) ll_launch(C, a, c, ll_effective(C, model, c, a.n_rec), next_stream());
     for (int i = 0; i < kLLAux; ++i) {
         MJP_HIP(hipEventRecord(w->join[i], w->aux[i]));
         MJP_HIP(hipStreamWaitEvent(s, w->join[i], 0));
