@@ -182,7 +182,11 @@ def krylov_bytes_per_step(kappa: int, n: int, nnz: int, fused: bool) -> float:
     reorthogonalisation, norm); the new vector is written by the product and
     read/written by the two later passes in the per-pass launches (8 B x 6 per
     state with the gather), but kept in LDS and written once by the fused
-    step (8 B x 2); then the combination reads kappa vectors and writes one."""
+    step (8 B x 2); then the combination reads kappa vectors and writes one.
+    The paper's modified Gram-Schmidt streams the same 24 B per state per
+    earlier vector (i dependent passes, each reading q_j and reading and
+    writing w), so this is also the method's own traffic, not only the
+    implementation's (classical Gram-Schmidt with one reorthogonalisation)."""
     own = 2 if fused else 6
     per_i = sum(12 * nnz + 8 * n * (3 * i + own) for i in range(1, kappa))
     return per_i + 8 * n * (kappa + 1)
