@@ -114,6 +114,13 @@ def _mj_case(name):
         rp, ci, va = mjp.mjp_model_csr(m)
         return (lambda **o: mjp.mjp_plan_create_csr(rp, ci, va, mjp.mjp_opts_default(**o)),
                 synth.random_prob(600 * 1500, 73), [0.05, 0.4])
+    if name == "birth-csr-1000x1000":
+        # death rates 0: the builder drops the zero entries, so every row reads
+        # only the states below it and a tile's reads across a side go one way
+        m = mjp.make_model(1, [30.0, 0.0, 0.7, 0.0], [S, S])
+        rp, ci, va = mjp.mjp_model_csr(m)
+        return (lambda **o: mjp.mjp_plan_create_csr(rp, ci, va, mjp.mjp_opts_default(**o)),
+                synth.random_prob(S * S, 74), [0.2, 0.35])
     if name == "bd-stencil-700001":
         m = mjp.make_model(0, [50000.0, 0.01], [700001])
         return (lambda **o: mjp.mjp_plan_create_stencil(m, mjp.mjp_opts_default(**o)),
@@ -123,14 +130,15 @@ def _mj_case(name):
 
 @pytest.mark.parametrize("renorm", [32, 0, 4, 8, 2])
 @pytest.mark.parametrize("case", ["cascade-csr-1000x1000-2open", "cascade-stencil-750x750-random",
-                                  "cascade-csr-600x1500", "bd-stencil-700001"])
+                                  "cascade-csr-600x1500", "bd-stencil-700001", "birth-csr-1000x1000"])
 def test_multijump_bit_identical(case, renorm):
     """Four jumps per synchronisation on tiles (rings of cells around each
     tile recomputed from the same inputs with the same operations) against
     the one-jump kernel, bit for bit: square and oblong grids, CSR and
-    stencil plans, a band operator (1-D blocks), jump counts of every
-    residue mod 4, two windows open together, renormalisation every 4, 8 or
-    32 jumps or never.  renorm_every = 2 cannot end a four-jump round: the
+    stencil plans, a band operator (1-D blocks), an operator whose rows
+    read only lower states (a tile waits for the tiles it reads and for those
+    that read it), jump counts of every residue mod 4, two windows open
+    together, renormalisation every 4, 8 or 32 jumps or never.  renorm_every = 2 cannot end a four-jump round: the
     sweep then takes the two-jump kernel."""
     make, rho0, times = _mj_case(case)
     say(f"[gpu] multi-jump {case} renorm_every={renorm}")
