@@ -2073,11 +2073,12 @@ extern "C" mjp_status mjp_loglik_load_shapes(const char* path) {
     MJP_CHECK(path && *path, MJP_E_INVALID_ARG, "path is NULL or empty");
     FILE* f = std::fopen(path, "r");
     MJP_CHECK(f, MJP_E_INVALID_ARG, "cannot open %s", path);
-    // parse the whole file first: nothing changes unless it is complete and valid
+    // parse the whole file first: nothing changes unless it is complete and
+    // valid (an eighth line already makes it invalid, so reading stops there)
     std::vector<std::string> lines;
     {
         char buf[512];
-        while (std::fgets(buf, sizeof buf, f)) {
+        while (lines.size() < 8 && std::fgets(buf, sizeof buf, f)) {
             std::string l(buf);
             while (!l.empty() && (l.back() == '\n' || l.back() == '\r')) l.pop_back();
             lines.push_back(l);

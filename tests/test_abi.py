@@ -452,6 +452,11 @@ def test_shape_cache_rejects_bad_files_on_the_host(tmp_path):
         head = f.readlines()[:5]
     open(p, "w").writelines(head)
     assert status_of(mjp.mjp_loglik_load_shapes, p) == mjp.MJP_E_INVALID_ARG
+    # a valid cache with a long tail of extra lines (reading stops at the eighth)
+    p = _cache_file(tmp_path)
+    with open(p, "a") as f:
+        f.write("x\n" * 100000)
+    assert status_of(mjp.mjp_loglik_load_shapes, p) == mjp.MJP_E_INVALID_ARG
     # written by a build with another shape table: refused before any device query
     assert status_of(mjp.mjp_loglik_load_shapes, _cache_file(tmp_path, table="3 1 2 3 4")) == mjp.MJP_E_UNSUPPORTED
 
