@@ -394,8 +394,12 @@ mjp_status mjp_loglik_set_kernel(int32_t model, int32_t kernel);
 /* Items of the cascade and birth-death models with more states than one
  * workgroup's LDS holds (S1*S2 > mjp_loglik_max_states()) run in clusters
  * of *group_h workgroups of one cooperative launch (each workgroup owns a
- * contiguous range of states, the boundary rows are exchanged every jump),
- * up to *max_states_h states and, for the cascade, S1 <= 1024; larger items
+ * contiguous range of states and recomputes a halo three boundary rows
+ * deep, so the boundary rows are exchanged every four jumps where the item
+ * allows -- renorm_every a multiple of 4, S1 <= 512, at least four rows per
+ * workgroup -- and every jump otherwise or when opts->variant is
+ * MJP_VARIANT_PERSISTENT_ONEJUMP; the results are bit-identical either
+ * way), up to *max_states_h states and, for the cascade, S1 <= 1024; larger items
  * (and any large item of the other models, or in mjp_loglik_noalloc) get
  * -inf with MJP_FLAG_OUT_OF_GRID.  Reports, for the current device, the
  * clusters that run co-resident (0: none, large items then get -inf), the

@@ -84,14 +84,17 @@ constexpr bool kColEnabled = true;
 
 // Items above one workgroup's LDS (cascade and birth-death, S1*S2 >
 // kLLMaxStates) run in clusters of kClG workgroups (k_ll_cluster below):
-// each owns a contiguous range of at most kClOwn states and exchanges the
-// kClReach-row boundary with its neighbours every jump.  Their queue class
-// follows the cell kernel's.
+// each owns a contiguous range of at most kClOwn states and exchanges its
+// boundary rows with its neighbours every kClJumps jumps (every jump where
+// the item does not allow that).  Their queue class follows the cell
+// kernel's.
 constexpr int kClT = 1024;
 constexpr int kClC = 32;
 constexpr int kClOwn = kClT * kClC;        // states one workgroup owns at most
 constexpr int kClG = 4;                    // workgroups per item
 constexpr int kClReachMax = 1024;          // S1 of a cascade item at most
+constexpr int kClJumps = 4;                // jumps per exchange where an item allows (else 1)
+constexpr int kClSlot = 2048;              // states per exchange slot: reach, or kClJumps x reach
 constexpr int kClMaxStates = kClG * kClOwn;
 constexpr int kClClass = kColClasses + kLLClasses;
 constexpr int kAllClasses = kClClass + 1;
@@ -174,6 +177,7 @@ struct LLArgs {
     int32_t use_cluster;                // cascade/birth-death items above kLLMaxStates go to clusters
     double omega_factor, tol;
     int32_t k_rule, lump, renorm_every;
+    int32_t one_jump;                   // clusters exchange every jump (opts->variant MJP_VARIANT_PERSISTENT_ONEJUMP)
     int64_t k_cap;
 };
 
@@ -989,14 +993,18 @@ __global__ __launch_bounds__(kColT) void k_ll_col(LLArgs a, int cls) {
 // order), so every workgroup of a cluster knows the item without a
 // broadcast.  Workgroup r of a cluster owns the states [lo, hi) =
 // [r len, (r + 1) len), len = ceil(N / kClG), and keeps them in LDS with a
-// halo of reach = S1 states (the pull rows' farthest column) on each side.
-// A jump: the new values of the own states into registers, a barrier, into
-// LDS; the reach states at each end of the own range written to the
-// cluster's exchange buffer (device-scope stores, the slot of the jump's
-// parity); every wave drains its stores; the workgroup publishes the number
-// of jumps done on its flag and waits for its neighbours' (all of the
-// cluster's at a renormalisation, whose block sums travel the same way); it
-// then reads its halo from the neighbours' slots (device-scope loads).  Every
+// halo of SJ reaches on each side (reach = S1 states, the pull rows'
+// farthest column; SJ = kClJumps where the item allows, else 1).  A round
+// is SJ jumps; jump j of a round updates the own states and the halo states
+// still (SJ - j) reaches deep (the same cell update the halo's owner makes,
+// so the same bits): the new values into registers, a barrier, into LDS.
+// At a round's end the SJ reach states at each end of the own range go to
+// the cluster's exchange buffer (device-scope stores, the slot of the
+// round's parity); every wave drains its stores; the workgroup publishes the
+// number of rounds done on its flag and waits for its neighbours' (all of
+// the cluster's at a renormalisation, which falls on a round's end and whose
+// block sums travel the same way); it then reads its halo from the
+// neighbours' slots (device-scope loads).  Every
 // wait has the 2 s deadline of the persistent sweeps: on a miss the abort
 // word is raised and every workgroup leaves, the items not finished keep
 // the NaN k_ll_order wrote.  At the end of an item each workgroup's FP64 sum
@@ -1004,7 +1012,7 @@ __global__ __launch_bounds__(kColT) void k_ll_col(LLArgs a, int cls) {
 // the same way and rank 0 adds them in rank order.
 struct ClArgs {
     LLArgs a;
-    float* __restrict__ xbuf;      // [nclust][2][kClG][2][kClReachMax] boundary states
+    float* __restrict__ xbuf;      // [nclust][2][kClG][2][kClSlot] boundary states
     double* __restrict__ part;     // [nclust][4][kClG] block sums: renormalisation masses (two
                                    // slots, alternating), an item's log-lik and mass
     double* __restrict__ ninf;     // [nclust][2][kClG] count of records with no probability; flags (as a double)
@@ -1055,7 +1063,7 @@ __device__ __forceinline__ bool cl_sync(unsigned* wf, int r, int rlo, int rhi, u
 template <int MODEL>
 __global__ __launch_bounds__(kClT) void k_ll_cluster(ClArgs ca) {
     constexpr int T = kClT, C = kClC;
-    constexpr int CAP = kClOwn + 2 * kClReachMax;  // own states and both halos
+    constexpr int CAP = kClOwn + 2 * kClSlot;  // own states and both halos
     const LLArgs& a = ca.a;
     extern __shared__ __align__(16) char lds[];
     float* lx = reinterpret_cast<float*>(lds);                             // [CAP]
@@ -1067,7 +1075,7 @@ __global__ __launch_bounds__(kClT) void k_ll_cluster(ClArgs ca) {
     const int cl = blockIdx.x / kClG, r = blockIdx.x - cl * kClG;
     const int first = a.cls_off[kClClass], last = a.cls_off[kClClass + 1];
     unsigned* wf = ca.wflag + (size_t)cl * kClG * 32;
-    float* xb = ca.xbuf + (size_t)cl * 2 * kClG * 2 * kClReachMax;
+    float* xb = ca.xbuf + (size_t)cl * 2 * kClG * 2 * kClSlot;
     double* pt = ca.part + (size_t)cl * 4 * kClG;
     unsigned round = 0;  // exchange rounds done (the same in every workgroup of the cluster)
     for (int slot = first + cl; slot < last; slot += ca.nclust) {
@@ -1110,7 +1118,16 @@ __global__ __launch_bounds__(kClT) void k_ll_cluster(ClArgs ca) {
         const int N = (int)N64;
         const int len = (N + kClG - 1) / kClG;
         const int lo = min(N, r * len), hi = min(N, lo + len);
-        const int hlo = max(0, lo - reach), hhi = min(N, hi + reach);
+        // jumps per exchange: kClJumps where the renormalisation points end a
+        // round, the deeper halo fits its slot and LDS, and every jump's
+        // cells fit the threads' registers (unless the caller asked for one);
+        // else one
+        const int SJ = (!a.one_jump && a.renorm_every % kClJumps == 0 && kClJumps * reach <= kClSlot &&
+                        len >= kClJumps * reach && len + 2 * (kClJumps - 1) * reach <= kClOwn)
+                           ? kClJumps
+                           : 1;
+        const int ext = SJ * reach;  // halo depth
+        const int hlo = max(0, lo - ext), hhi = min(N, hi + ext);
         float* rho = lx - hlo;  // rho[m] for m in [hlo, hhi)
         const double om = omega > 0.0 ? omega : 1.0;
         LLCoef kc;
@@ -1149,13 +1166,11 @@ __global__ __launch_bounds__(kClT) void k_ll_cluster(ClArgs ca) {
         if (x0 < 0 && r == 0) flags |= MJP_FLAG_OUT_OF_GRID;
 
         const int qT = T / S1, rT = T - qT * S1;
-        const int s0 = lo + tid;
-        const int i1_0 = s0 % S1, i2_0 = s0 / S1;
         double scale = 1.0;
         const int m_renorm = a.renorm_every;
         int rpar = 0;
         double wcur = 0.0;  // this time's weight at the current jump (threads tid < n_t)
-        const __amdgpu_buffer_rsrc_t xr = iter_rsrc(xb, (int64_t)2 * kClG * 2 * kClReachMax);
+        const __amdgpu_buffer_rsrc_t xr = iter_rsrc(xb, (int64_t)2 * kClG * 2 * kClSlot);
         bool ok = true;
         for (int k = 0; k <= Kmax && ok; ++k) {
             // weight of jump k for each time (FP64, the recurrence from w_L)
@@ -1164,65 +1179,77 @@ __global__ __launch_bounds__(kClT) void k_ll_cluster(ClArgs ca) {
                 wbuf[(k & 1) * kLLMaxTimes + tid] = wcur;
             }
             if (k > 0) {
+                // jump j of its round: the own states and the halo states still
+                // (SJ - j) reaches deep, from values one reach deeper (the
+                // same cell update the halo's owner makes, so the same bits)
+                const int j = (k - 1) % SJ + 1;
+                const int e = (SJ - j) * reach;
+                const int clo = max(0, lo - e), chi = min(N, hi + e);
+                const int s0 = clo + tid;
                 float nv[C];
-                int i1 = i1_0, i2 = i2_0, mb = s0;
+                int i1 = s0 % S1, i2 = s0 / S1, mb = s0;
                 asm volatile("" : "+v"(i1), "+v"(i2), "+v"(mb));
                 const float fs = (float)scale;
+                scale = 1.0;
                 float part = 0.f;
 #pragma unroll
                 for (int c = 0; c < C; ++c) {
                     const int m = mb + c * T;
                     float y = 0.f;
-                    if (m < hi) y = fs * ll_cell<MODEL>(rho, m, i1, i2, S1, S2, kc);
+                    if (m < chi) y = fs * ll_cell<MODEL>(rho, m, i1, i2, S1, S2, kc);
                     nv[c] = y;
-                    part += y;
+                    if (m >= lo && m < hi) part += y;
                     i1 += rT;
                     i2 += qT;
                     if (i1 >= S1) { i1 -= S1; i2 += 1; }
                 }
                 __syncthreads();  // every read of the old values is done
-                // own states into LDS; the boundary states into this jump's slot:
-                // [parity][r][0] the first reach states, [parity][r][1] the last reach
-                const uint32_t sbase = (uint32_t)((((k & 1) * kClG + r) * 2) * kClReachMax);
 #pragma unroll
                 for (int c = 0; c < C; ++c) {
                     const int m = s0 + c * T;
-                    if (m < hi) {
-                        rho[m] = nv[c];
-                        if (m - lo < reach) st_iter<true>(xr, 4u * (sbase + (uint32_t)(m - lo)), nv[c]);
-                        if (hi - m <= reach)
-                            st_iter<true>(xr, 4u * (sbase + kClReachMax + (uint32_t)(m - (hi - reach))), nv[c]);
+                    if (m < chi) rho[m] = nv[c];
+                }
+                if (j == SJ) {
+                    // round end: the first and last ext own states into this
+                    // round's slot ([parity][r][0], [parity][r][1])
+                    const uint32_t sbase = (uint32_t)(((((k / SJ) & 1) * kClG + r) * 2) * kClSlot);
+#pragma unroll
+                    for (int c = 0; c < C; ++c) {
+                        const int m = s0 + c * T;
+                        if (m >= lo && m < hi) {
+                            if (m - lo < ext) st_iter<true>(xr, 4u * (sbase + (uint32_t)(m - lo)), nv[c]);
+                            if (hi - m <= ext)
+                                st_iter<true>(xr, 4u * (sbase + kClSlot + (uint32_t)(m - (hi - ext))), nv[c]);
+                        }
                     }
-                }
-                const bool renorm = m_renorm > 0 && k % m_renorm == 0 && k < Kmax;
-                if (renorm) {
-                    const double s = ll_block_sum<T>((double)part, scratch);
-                    if (tid == 0)
-                        __hip_atomic_store(pt + rpar * kClG + r, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                }
-                ++round;
-                ok = renorm ? cl_sync(wf, r, 0, kClG - 1, round, ca.abort_word, ca.timeout_ticks)
-                            : cl_sync(wf, r, max(0, r - 1), min(kClG - 1, r + 1), round, ca.abort_word,
-                                      ca.timeout_ticks);
-                if (!ok) break;
-                // the halo from the neighbours' slots of this jump
-                for (int m = hlo + tid; m < lo; m += T) {  // rank r - 1's last reach states
-                    const uint32_t o = (uint32_t)((((k & 1) * kClG + (r - 1)) * 2 + 1) * kClReachMax) +
-                                       (uint32_t)(m - (lo - reach));
-                    rho[m] = ld_iter<true>(xr, 4u * o);
-                }
-                for (int m = hi + tid; m < hhi; m += T) {  // rank r + 1's first reach states
-                    const uint32_t o = (uint32_t)((((k & 1) * kClG + (r + 1)) * 2) * kClReachMax) + (uint32_t)(m - hi);
-                    rho[m] = ld_iter<true>(xr, 4u * o);
-                }
-                if (renorm) {
-                    double tot = 0.0;
-                    for (int q = 0; q < kClG; ++q)
-                        tot += __hip_atomic_load(pt + rpar * kClG + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    scale = tot > 0.0 ? 1.0 / tot : 1.0;  // rho(0) has unit mass
-                    rpar ^= 1;
-                } else {
-                    scale = 1.0;
+                    const bool renorm = m_renorm > 0 && k % m_renorm == 0 && k < Kmax;
+                    if (renorm) {
+                        const double s = ll_block_sum<T>((double)part, scratch);
+                        if (tid == 0)
+                            __hip_atomic_store(pt + rpar * kClG + r, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                    ++round;
+                    ok = renorm ? cl_sync(wf, r, 0, kClG - 1, round, ca.abort_word, ca.timeout_ticks)
+                                : cl_sync(wf, r, max(0, r - 1), min(kClG - 1, r + 1), round, ca.abort_word,
+                                          ca.timeout_ticks);
+                    if (!ok) break;
+                    // the halo from the neighbours' slots of this round
+                    const uint32_t pb = (uint32_t)(((k / SJ) & 1) * kClG);
+                    for (int m = hlo + tid; m < lo; m += T) {  // rank r - 1's last ext states
+                        const uint32_t o = (uint32_t)(((pb + (r - 1)) * 2 + 1) * kClSlot) + (uint32_t)(m - (lo - ext));
+                        rho[m] = ld_iter<true>(xr, 4u * o);
+                    }
+                    for (int m = hi + tid; m < hhi; m += T) {  // rank r + 1's first ext states
+                        const uint32_t o = (uint32_t)(((pb + (r + 1)) * 2) * kClSlot) + (uint32_t)(m - hi);
+                        rho[m] = ld_iter<true>(xr, 4u * o);
+                    }
+                    if (renorm) {
+                        double tot = 0.0;
+                        for (int q = 0; q < kClG; ++q)
+                            tot += __hip_atomic_load(pt + rpar * kClG + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        scale = tot > 0.0 ? 1.0 / tot : 1.0;  // rho(0) has unit mass
+                        rpar ^= 1;
+                    }
                 }
                 __syncthreads();
             } else {
@@ -1357,7 +1384,7 @@ inline size_t col_lds(int cc) { return sizeof(float) * (size_t)col_cap(cc) + kCo
 inline bool col_model(int model) { return model == MJP_MODEL_CASCADE2; }
 // LDS of a cluster workgroup: own states and halos, then the weights,
 // block-sum scratch and windows (as the column kernel's extras)
-inline size_t cl_lds() { return sizeof(float) * (size_t)(kClOwn + 2 * kClReachMax) + kColExtra; }
+inline size_t cl_lds() { return sizeof(float) * (size_t)(kClOwn + 2 * kClSlot) + kColExtra; }
 
 inline size_t ll_lds(int shape) {
     return sizeof(float) * (size_t)ll_cap(kLLShapes[shape].T, kLLShapes[shape].C) + kLLExtraLds;
@@ -1617,7 +1644,7 @@ static mjp_status ll_work(LLContext& C, hipStream_t s, int B, int n_t, LLBufs& b
         return st;
     if (C.nclust > 0) {
         const size_t nc = (size_t)C.nclust;
-        if ((st = w->cl_x.reserve(sizeof(float) * nc * 2 * kClG * 2 * kClReachMax)) ||
+        if ((st = w->cl_x.reserve(sizeof(float) * nc * 2 * kClG * 2 * kClSlot)) ||
             (st = w->cl_part.reserve(sizeof(double) * nc * 4 * kClG)) || (st = w->cl_ninf.reserve(sizeof(double) * nc * 2 * kClG)) ||
             (st = w->cl_flag.reserve(sizeof(unsigned) * (nc * kClG * 32 + 32))))
             return st;
@@ -1663,6 +1690,7 @@ static LLArgs ll_args(const LLContext& C, int model, int B, const mjp_obs* obs, 
     a.k_rule = opts->k_rule;
     a.lump = opts->lump;
     a.renorm_every = opts->truncation == MJP_CONSERVATIVE ? opts->renorm_every : 0;
+    a.one_jump = opts->variant == MJP_VARIANT_PERSISTENT_ONEJUMP;
     a.k_cap = opts->k_cap;
     return a;
 }

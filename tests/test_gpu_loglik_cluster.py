@@ -1,7 +1,8 @@
 """Log-likelihoods of items too large for one workgroup's LDS (S1*S2 above
 40,000 states): clusters of workgroups of one cooperative launch, each
 owning a contiguous range of states and exchanging the boundary rows with
-its neighbours every jump, through the C ABI.
+its neighbours every four jumps (a halo three rows deep recomputed by each
+workgroup), or every jump, through the C ABI.
 
 Against the FP64 oracle's independent per-time solves (Sec. 2.1.2) with the
 log-likelihood bar of the batched path, |l_gpu - l_oracle| <=
@@ -28,13 +29,13 @@ def say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run(model, theta, dims, T, recs, x0=(0, 0)):
+def run(model, theta, dims, T, recs, x0=(0, 0), opts=None):
     B = len(theta)
     th = torch.as_tensor(np.asarray(theta, np.float64), device="cuda").contiguous()
     dm = torch.as_tensor(np.asarray(dims, np.int32), device="cuda").contiguous()
     out = torch.empty(B, dtype=torch.float64, device="cuda")
     info = torch.zeros(B * ctypes.sizeof(mjp.mjp_info), dtype=torch.uint8, device="cuda")
-    mjp.mjp_loglik(model, th, dm, mjp.make_obs(T, recs, x0), out, info=info)
+    mjp.mjp_loglik(model, th, dm, mjp.make_obs(T, recs, x0), out, opts=opts, info=info)
     torch.cuda.synchronize()
     raw = info.cpu().numpy().tobytes()
     sz = ctypes.sizeof(mjp.mjp_info)
@@ -115,3 +116,28 @@ def test_cluster_batch_repeatable():
     for i in (0, 77, 149):
         one, _ = run(mjp.MJP_MODEL_CASCADE2, theta[i:i + 1], dims[i:i + 1], T, recs)
         assert one[0] == a[i], (i, one[0], a[i])
+
+
+@pytest.mark.parametrize("renorm", [32, 0])
+def test_cluster_four_jumps_bit_identical(renorm):
+    """Four jumps per exchange (the halo states recomputed with the owner's
+    cell update) against one jump per exchange (opts.variant
+    MJP_VARIANT_PERSISTENT_ONEJUMP), bit for bit: cascade items from just
+    above one workgroup's capacity to 300 x 300 and a wide one (S1 = 500),
+    each with its own jump count (a last round of 1 to 4 jumps), with and
+    without renormalisation."""
+    theta_star = [60.0, 1.0, 0.5, 0.5]
+    T = np.array([0.37, 1.0, 1.91])
+    data = synth.gillespie_cascade2(theta_star, T, 12, seed=synth.SEED_DATA)
+    recs = synth.cascade_records(data)
+    g = synth.rng(93)
+    grids = np.array([(210, 200), (300, 300), (500, 120), (256, 260), (233, 190)], np.int32)
+    theta = np.asarray(theta_star) * np.exp(g.uniform(-0.15, 0.15, size=(len(grids), 4)))
+    res = []
+    for var in (mjp.MJP_VARIANT_AUTO, mjp.MJP_VARIANT_PERSISTENT_ONEJUMP):
+        got, info = run(mjp.MJP_MODEL_CASCADE2, theta, grids, T, recs,
+                        opts=mjp.mjp_opts_default(variant=var, renorm_every=renorm))
+        res.append((got, [i.K for i in info], [i.mass_out for i in info]))
+    say(f"    renorm {renorm}: K {res[0][1]} l {res[0][0]}")
+    assert np.isfinite(res[0][0]).all()
+    assert np.array_equal(res[0][0], res[1][0]) and res[0][2] == res[1][2]
