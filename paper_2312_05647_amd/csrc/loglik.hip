@@ -986,8 +986,8 @@ __global__ __launch_bounds__(kColT) void k_ll_col(LLArgs a, int cls) {
 
 // ------------------------------------------------------- cluster kernel
 //
-// The cell kernel's sweep (k_ll_main: the same cell update, weights,
-// renormalisation and record accumulation) for an item too large for one
+// The cell kernel's sweep (k_ll_main: the same weights, renormalisation and
+// record accumulation; the column kernel's cell update) for an item too large for one
 // workgroup's LDS, run by a cluster of kClG workgroups of one cooperative
 // launch.  Cluster c takes the items c, c + nclust, ... of the class (cost
 // order), so every workgroup of a cluster knows the item without a
@@ -1021,6 +1021,40 @@ struct ClArgs {
     uint64_t timeout_ticks;
     int32_t nclust;
 };
+
+// The column kernel's cell update for the cluster kernel's models (birth-
+// death and cascade), neighbours read from LDS: y = x + (inflows - exits x)
+// with each exit rate a separate FP32 product (the numbers its neighbours
+// pull), no FP64 diagonal.
+template <int MODEL>
+__device__ __forceinline__ float cl_cell(const float* rho, int m, int i1, int i2, int S1, int S2, const LLCoef& k) {
+    static_assert(MODEL == MJP_MODEL_BD || MODEL == MJP_MODEL_CASCADE2, "birth-death and cascade only");
+    const float b1 = k.c[0], d1 = k.c[1], b2 = k.c[2], d2 = k.c[3];
+    const float f1 = (float)i1, f2 = (float)i2;
+    const bool left = i1 > 0, right = i1 + 1 < S1, up = i2 > 0, down = i2 + 1 < S2;
+    const float xc = rho[m];
+    const float xl = left ? rho[m - 1] : 0.f;
+    const float xr = right ? rho[m + 1] : 0.f;
+    const float xu = up ? rho[m - S1] : 0.f;
+    const float xd = down ? rho[m + S1] : 0.f;
+    const float cl = left ? b1 : 0.f;                 // inflow from (i1 - 1, i2): k1
+    const float cr = right ? d1 * (f1 + 1.f) : 0.f;   // from (i1 + 1, i2): g1 (i1 + 1)
+    const float cu = b2 * f1;                         // from (i1, i2 - 1): k2 i1
+    const float cd = d2 * (f2 + 1.f);                 // from (i1, i2 + 1): g2 (i2 + 1)
+    const float q = down ? cu : 0.f;                  // exits: birth 2 (blocked in the last row),
+    const float p = d2 * f2;                          //   death 2,
+    const float od1 = d1 * f1;                        //   death 1,
+    const float ob1 = right ? b1 : 0.f;               //   birth 1 (blocked at the cap)
+    float acc = cl * xl;
+    acc = fmaf(cr, xr, acc);
+    acc = fmaf(cu, xu, acc);
+    acc = fmaf(cd, xd, acc);
+    acc = fmaf(-q, xc, acc);
+    acc = fmaf(-p, xc, acc);
+    acc = fmaf(-od1, xc, acc);
+    acc = fmaf(-ob1, xc, acc);
+    return xc + acc;
+}
 
 // Publish `round` on my flag and wait until the workgroups of my cluster in
 // [rlo, rhi] have published it (bounded); false if the sweep aborted.
@@ -1196,7 +1230,7 @@ __global__ __launch_bounds__(kClT) void k_ll_cluster(ClArgs ca) {
                 for (int c = 0; c < C; ++c) {
                     const int m = mb + c * T;
                     float y = 0.f;
-                    if (m < chi) y = fs * ll_cell<MODEL>(rho, m, i1, i2, S1, S2, kc);
+                    if (m < chi) y = fs * cl_cell<MODEL>(rho, m, i1, i2, S1, S2, kc);
                     nv[c] = y;
                     if (m >= lo && m < hi) part += y;
                     i1 += rT;
