@@ -514,7 +514,7 @@ typedef struct {
     uint64_t seed;        /* minibatch shuffling */
 } mjp_train_cfg;
 
-/* Create an MLP in->width->...->width->1 with exact (erf) GELU between the
+/* Create an MLP in->width->...->width->1 with GELU z*Phi(z) between the
  * Linear layers, FP32 master weights initialised from seed (uniform in
  * +-1/sqrt(fan_in)), BF16 copies used by the matrix-core kernels.  Not part
  * of the paper: a learned stand-in for the log-likelihood over log-rates,

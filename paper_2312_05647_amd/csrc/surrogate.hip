@@ -1,5 +1,5 @@
 // MLP surrogate of the log-likelihood (an addition to the paper's method):
-// in -> width -> ... -> width -> 1, exact (erf) GELU between Linear layers,
+// in -> width -> ... -> width -> 1, GELU z Phi(z) between Linear layers (Phi from a rational erf form, |error| <= 1.5e-7),
 // FP32 master parameters, BF16 operands on the matrix cores.
 //
 // Nets up to 256 wide train in three launches per step (k_mlp_fused,
@@ -54,10 +54,35 @@ __device__ __forceinline__ uint16_t f2bf(float f) {  // round to nearest even
 
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+// Standard normal CDF Phi(z) = (1 + erf(z / sqrt 2)) / 2 and density phi(z), sharing one exponential:
+// erf(x) = 1 - t (a1 + a2 t + ... + a5 t^4) e^{-x^2} with t = 1 / (1 + p x) for x >= 0 (Abramowitz &
+// Stegun 7.1.26, Hastings' rational form, |error| <= 1.5e-7), and e^{-x^2} at x = |z| / sqrt 2 is
+// e^{-z^2/2}, the density's own factor.  Branch-free; the error is far below the BF16 rounding of the
+// activations it feeds.
+__device__ __forceinline__ void normal_cdf_pdf(float z, float& cdf, float& pdf) {
+    const float x = fabsf(z) * 0.70710678118654752f;
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, x, 1.0f));
+    const float e = exp2f(-0.72134752044448170f * z * z);  // e^{-z^2/2} = 2^{-z^2 log2(e) / 2}
+    float q = fmaf(1.061405429f, t, -1.453152027f);
+    q = fmaf(q, t, 1.421413741f);
+    q = fmaf(q, t, -0.284496736f);
+    q = fmaf(q, t, 0.254829592f);
+    const float half_erf = fmaf(-0.5f * q * t, e, 0.5f);  // erf(x) / 2
+    cdf = 0.5f + copysignf(half_erf, z);
+    pdf = 0.39894228040143268f * e;
+}
+
+// GELU(z) = z Phi(z) and its derivative Phi(z) + z phi(z).
+__device__ __forceinline__ float gelu(float z) {
+    float c, d;
+    normal_cdf_pdf(z, c, d);
+    return z * c;
+}
 
 __device__ __forceinline__ float gelu_grad(float z) {
-    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
+    float c, d;
+    normal_cdf_pdf(z, c, d);
+    return fmaf(z, d, c);
 }
 
 enum { EPI_FWD_GELU = 0, EPI_FWD_LINEAR = 1, EPI_BWD_DATA = 2, EPI_WGRAD = 3 };
