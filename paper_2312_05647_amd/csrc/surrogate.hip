@@ -339,6 +339,14 @@ __global__ void k_zero_u32(uint32_t* __restrict__ p, size_t n) {
     if (i < n) p[i] = 0u;
 }
 
+// Device copy of an epoch's permutation from mapped, coherent pinned host
+// memory: an ordinary launch on the training stream, so the stream never
+// hands over to the copy engine and back between epochs.
+__global__ void k_copy_perm(const int32_t* __restrict__ src, int32_t* __restrict__ dst, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
 // MFMA B-operand fragment order of an N x K matrix (N output columns, K
 // reductions; both multiples of 32): the 16 x 32 block (n/16, k/32) is 512
 // consecutive values, lane (n mod 16) + 16 ((k mod 32) / 8) holding its eight
@@ -1285,14 +1293,16 @@ mjp_status mjp_surrogate_train(mjp_surrogate* s, const float* x_d, const float* 
     if (e) return e;
     // The host runs ahead of the device: no step waits for the previous one.
     // Each epoch's permutation goes to one of two device slots from one of
-    // two pinned host buffers, reused once the epoch two back has finished
-    // (an event per slot); the loss partials of every step stay on the
+    // two pinned host buffers (copied by a kernel on the stream), reused once
+    // the epoch two back has finished (an event per slot, recorded after the
+    // epoch's last step); the loss partials of every step stay on the
     // device and are read once at the end.
     const int nb = (n + cfg->batch - 1) / cfg->batch;
     const int lstride = loss_parts(s, cfg->batch);  // loss partials per step
     if ((e = s->perm.reserve(sizeof(int32_t) * 2 * (size_t)n))) return e;
     if (loss_h && (e = s->lossp.reserve(sizeof(double) * (size_t)cfg->epochs * nb * lstride))) return e;
     int32_t* ph[2] = {nullptr, nullptr};
+    int32_t* ph_d[2] = {nullptr, nullptr};  // device addresses of the pinned slots
     hipEvent_t ev[2] = {nullptr, nullptr};
     auto cleanup = [&]() {
         for (int q = 0; q < 2; ++q) {
@@ -1301,8 +1311,9 @@ mjp_status mjp_surrogate_train(mjp_surrogate* s, const float* x_d, const float* 
         }
     };
     for (int q = 0; q < 2; ++q) {
-        if (hipHostMalloc(reinterpret_cast<void**>(&ph[q]), sizeof(int32_t) * (size_t)n, hipHostMallocDefault) !=
-                hipSuccess ||
+        if (hipHostMalloc(reinterpret_cast<void**>(&ph[q]), sizeof(int32_t) * (size_t)n,
+                          hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+            hipHostGetDevicePointer(reinterpret_cast<void**>(&ph_d[q]), ph[q], 0) != hipSuccess ||
             hipEventCreateWithFlags(&ev[q], hipEventDisableTiming) != hipSuccess) {
             cleanup();
             return fail(MJP_E_DEVICE, "pinned permutation buffers or events could not be created");
@@ -1317,8 +1328,7 @@ mjp_status mjp_surrogate_train(mjp_surrogate* s, const float* x_d, const float* 
         for (int i = 0; i < n; ++i) perm[i] = i;
         std::shuffle(perm, perm + n, rng);
         int32_t* perm_d = s->perm.as<int32_t>() + (size_t)slot * n;
-        if ((he = hipMemcpyAsync(perm_d, perm, sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, st)) != hipSuccess)
-            break;
+        hipLaunchKernelGGL(k_copy_perm, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ph_d[slot], perm_d, n);
         for (int bi = 0; bi < nb; ++bi) {
             const int base = bi * cfg->batch;
             const int nv = std::min(cfg->batch, n - base);
