@@ -378,21 +378,32 @@ struct AdamArgs {
     int64_t total;
 };
 
+// The layer that packed parameter p belongs to (the last whose offset is <= p;
+// offsets increase with the layer).  Every layer's record is read at a fixed
+// index, so the loads are uniform and issue together, and the lane's record is
+// picked by selects: no lane-dependent chain of loads from the argument block.
+__device__ __forceinline__ LayerDev layer_of(const AdamArgs& a, int64_t p) {
+    LayerDev d = a.lay[0];
+#pragma unroll
+    for (int j = 1; j < kMaxLayers; ++j)
+        if (j < a.L && p >= a.lay[j].woff) d = a.lay[j];
+    return d;
+}
+
 __global__ void k_adam(AdamArgs a) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= a.total) return;
-    int l = 0;
-    while (l + 1 < a.L && p >= a.lay[l + 1].woff) ++l;
-    const LayerDev& d = a.lay[l];
-    const int64_t q = p - d.woff;
-    const int64_t nw = (int64_t)d.out * d.in;
+    const LayerDev d = layer_of(a, p);
+    // a layer holds fewer than 2^31 parameters (width <= 512, depth <= 8)
+    const uint32_t q = (uint32_t)(p - d.woff);
+    const uint32_t nw = (uint32_t)d.out * (uint32_t)d.in;
     float g;
     int o = -1, i = -1;
     // the partials are added in index order; eight loads are in flight at a
     // time (an out-of-range slot loads the group's first partial and adds 0)
     if (q < nw) {
-        o = (int)(q / d.in);
-        i = (int)(q - (int64_t)o * d.in);
+        o = (int)(q / (uint32_t)d.in);
+        i = (int)(q - (uint32_t)o * (uint32_t)d.in);
         g = 0.f;
         for (int s0 = 0; s0 < a.splits; s0 += 8) {
             float x[8];
@@ -439,9 +450,7 @@ __global__ void k_adam(AdamArgs a) {
 __global__ void k_refresh_bf16(AdamArgs a) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= a.total) return;
-    int l = 0;
-    while (l + 1 < a.L && p >= a.lay[l + 1].woff) ++l;
-    const LayerDev& d = a.lay[l];
+    const LayerDev d = layer_of(a, p);
     const int64_t q = p - d.woff;
     if (q < (int64_t)d.out * d.in) {
         const int o = (int)(q / d.in), i = (int)(q - (int64_t)o * d.in);
