@@ -433,7 +433,7 @@ def bench_loglik(torch, mjp, reps: int = 3):
                                              for c in range(mjp.MJP_LL_CLASSES) if rep["items"][c] > 0}}}
 
 
-def bench_da(torch, mjp, chains: int = 256, steps: int = 60, n_train: int = 8192, pilot_chains: int = 128,
+def bench_da(torch, mjp, chains: int = 256, steps: int = 60, n_train: int = 4096, pilot_chains: int = 128,
              pilot_steps: int = 30):
     """Delayed-acceptance vs plain Metropolis-Hastings on the posterior of
     the cascade's four log-rates with config-2 truth (200, 1, 0.5, 0.5) on
@@ -532,7 +532,7 @@ def main():
                     help="run only one secondary leg (for profiling)")
     ap.add_argument("--da-chains", type=int, default=256)
     ap.add_argument("--da-steps", type=int, default=60)
-    ap.add_argument("--da-train", type=int, default=8192)
+    ap.add_argument("--da-train", type=int, default=4096)
     ap.add_argument("--log-maps", metavar="FILE",
                     help="write this process's memory map to FILE at exit (to place a crash address in a library)")
     ap.add_argument("--calibrate-copy", action="store_true",
