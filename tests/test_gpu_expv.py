@@ -461,3 +461,29 @@ def test_wait_deadline_abort_path(dims):
     assert e.value.status == mjp.MJP_E_DEVICE and "timed out" in str(e.value)
     after, _ = solve()
     assert np.array_equal(before, after)
+
+
+@pytest.mark.parametrize("kind", ["csr", "stencil"])
+def test_tiled_sweep_mid_size(orc, kind):
+    """A 300 x 300 cascade (N = 90,000, 22 tiles of the grid) at one time
+    runs the tiled sweep (eight jumps per neighbour exchange): it meets the
+    parity bar against the FP64 oracle and equals the one-jump kernel bit
+    for bit."""
+    theta = [200.0, 1.0, 0.5, 0.5]
+    A = orc.model_generator(1, theta, [300, 300])
+    say(f"[oracle] cascade 300x300, t=10")
+    ref, _ = orc.expv(A, synth.delta(90000), 10.0)
+    outs, paths = [], []
+    for variant in (mjp.MJP_VARIANT_AUTO, mjp.MJP_VARIANT_PERSISTENT_ONEJUMP):
+        say(f"[gpu] cascade 300x300 t=10 via {kind}, variant {variant}")
+        plan = (csr_plan_from_model if kind == "csr" else stencil_plan)(1, theta, [300, 300], variant=variant)
+        try:
+            got, inf = gpu_expv(plan, synth.delta(90000), [10.0])
+        finally:
+            mjp.mjp_plan_destroy(plan)
+        outs.append(got)
+        paths.append(inf[0]["path"])
+        assert inf[0]["flags"] == 0
+    assert paths == [mjp.MJP_PATH_PERSISTENT_MULTIJUMP, mjp.MJP_PATH_PERSISTENT]
+    say(f"    L1 {check_close(outs[0][0], ref, kind):.3e}")
+    assert np.array_equal(outs[0], outs[1])
